@@ -1,0 +1,937 @@
+"""Plain FP64 CPU oracle of the MCD hot path (Matsuda & Ii, arXiv 2404.17542).
+
+TEST INFRASTRUCTURE.  Only the tests, the smoke check and the CPU-baseline
+leg of the benchmark may import this module.  It shares no code with the
+HIP library; the only common module is the seeded input generator
+(`paper_2404_17542_amd.inputs`), which holds no method arithmetic.
+
+Everything is float64 numpy, vectorised over discrete points (DPs) with
+loops over stencil slots in a fixed order, written to be checked by eye
+against the paper:
+
+* roles ........ Sec. 2.2 (mask equation), Sec. 2.4, Sec. 2.5 (nearest SDF)
+* update_dps ... Sec. 2.3 procedures (ii)-(v): Eqs. (gov_eq_mcd) ..
+                 (1st_intermed_position), (2nd_intermed_position), mesh
+                 constraint (Fig. mesh_constraint); Sec. 2.4 band of 5 l0
+* mls_build .... Sec. 3.2, Eqs. (intrp_chi_1), (p_ic), (obj_func), (set)
+                 and the cos^2 weight, with chi_c = 1
+* remap ........ Sec. 3.3 Eq. (ale_vel) with p = 2; Appendix A Eqs. (A.1),
+                 (A.2) with the shifted support of Sec. 3.4
+* moc/visc/rhs . Sec. 3.3 Eqs. (intermed_vel), (pressure_poisson),
+                 (projection); Neumann datum Eq. (neumann_moving_boundary)
+* bicgstab ..... Sec. 3.3 (Bi-CGSTAB, van der Vorst's unpreconditioned form)
+
+Readings where the paper is silent (3D mask rule, wall DPs, periodic pin,
+relaxation stopping rule, the MOC reading, ...) are listed with the design
+notes; each function states the reading it uses.
+
+Array conventions: cell c = i + n0*(j + n1*k) (x fastest); per-DP vectors
+are (dim, Nc); role is int8 (-1 inner, 0 void, >= 1 boundary id).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field
+
+import numpy as np
+import scipy.sparse as sp
+
+INNER = -1
+VOID = 0
+DIRICHLET = 0
+NEUMANN = 1
+
+# transition classes (void, inner, boundary); code = 3*cls(old) + cls(new)
+CLS_VOID, CLS_INNER, CLS_BOUNDARY = 0, 1, 2
+
+
+# ---------------------------------------------------------------------------
+# Mesh geometry
+# ---------------------------------------------------------------------------
+
+class Mesh:
+    """Uniform Cartesian background mesh, one DP per cell (Sec. 2.2)."""
+
+    def __init__(self, dim, n, origin, l0, periodic=None, walls=False, wall_id=1):
+        self.dim = int(dim)
+        self.n = tuple(int(v) for v in n)
+        self.origin = tuple(float(v) for v in origin)
+        self.l0 = float(l0)
+        self.periodic = tuple(bool(p) for p in (periodic or (False,) * dim))
+        self.walls = bool(walls)
+        self.wall_id = int(wall_id)
+        self.Nc = int(np.prod(self.n))
+        self.length = tuple(self.n[a] * self.l0 for a in range(self.dim))
+        # stencil slots: the 3^dim block in lexicographic order, x fastest
+        offs = []
+        for s in range(3 ** self.dim):
+            o, r = [], s
+            for _ in range(self.dim):
+                o.append(r % 3 - 1)
+                r //= 3
+            offs.append(tuple(o))
+        self.offsets = offs
+        self.S = len(offs)
+        self.centre = (self.S - 1) // 2
+
+    @classmethod
+    def from_case(cls, case):
+        return cls(case.dim, case.n, case.origin, case.l0, case.periodic, case.walls)
+
+    def ijk(self, idx):
+        out = np.empty((self.dim, len(idx)), dtype=np.int64)
+        rem = np.asarray(idx, dtype=np.int64)
+        for a in range(self.dim):
+            out[a] = rem % self.n[a]
+            rem = rem // self.n[a]
+        return out
+
+    def neighbour(self, ijk, off):
+        """Cell index of ijk+off (-1 if outside a non-periodic mesh) and the
+        periodic wrap (-1, 0, +1) per axis, so that the neighbour's image
+        position is x_j + wrap*L."""
+        K = ijk.shape[1]
+        j = np.zeros(K, dtype=np.int64)
+        ok = np.ones(K, dtype=bool)
+        wrap = np.zeros((self.dim, K), dtype=np.int64)
+        stride = 1
+        for a in range(self.dim):
+            ii = ijk[a] + off[a]
+            if self.periodic[a]:
+                wrap[a] = np.where(ii >= self.n[a], 1, np.where(ii < 0, -1, 0))
+                ii = ii - wrap[a] * self.n[a]
+            else:
+                ok &= (ii >= 0) & (ii < self.n[a])
+            j += np.clip(ii, 0, self.n[a] - 1) * stride
+            stride *= self.n[a]
+        return np.where(ok, j, -1), wrap
+
+    def is_wall_cell(self, ijk):
+        w = np.zeros(ijk.shape[1], dtype=bool)
+        if self.walls:
+            for a in range(self.dim):
+                w |= (ijk[a] == 0) | (ijk[a] == self.n[a] - 1)
+        return w
+
+
+@dataclass
+class BodyState:
+    """Circle/sphere at a given time: centre, radius R, R^2 (host value), id."""
+    centre: tuple
+    radius: float
+    body_id: int
+    velocity: tuple = ()
+
+    @property
+    def r2(self):
+        return self.radius * self.radius
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.2 / 2.4 / 2.5: masks (roles) from vertex SDF signs
+# ---------------------------------------------------------------------------
+
+def roles(mesh, bodies, idx=None):
+    """Mask of each cell by the number n of its vertices with psi >= 0.
+
+    2D (mask equation): n = 4 -> inner (-1); n = 2, 3 -> boundary id;
+    n = 0, 1 -> void (0).  3D reading: 8 -> inner, 4..7 -> boundary,
+    <= 3 -> void (at least half the vertices in fluid -> boundary).
+    psi >= 0 of a circle/sphere is tested as |v - c|^2 >= R^2 (no sqrt).
+    Several bodies: a vertex is fluid when it lies outside every body, which
+    is the sign of the smallest-|psi| SDF for non-overlapping bodies
+    (Sec. 2.5); the boundary id is the body of smallest |psi| at the
+    centroid, ties to the lower id.  The outer ring/shell of cells is the
+    wall boundary when the mesh has walls.
+    """
+    if idx is None:
+        idx = np.arange(mesh.Nc)
+    ijk = mesh.ijk(idx)
+    dim, l0 = mesh.dim, mesh.l0
+    K = len(idx)
+    count = np.zeros(K, dtype=np.int64)
+    for v in range(2 ** dim):
+        corner = [(v >> a) & 1 for a in range(dim)]
+        vx = [mesh.origin[a] + (ijk[a] + corner[a]).astype(np.float64) * l0 for a in range(dim)]
+        fluid = np.ones(K, dtype=bool)
+        for b in bodies:
+            d2 = np.zeros(K)
+            for a in range(dim):
+                da = vx[a] - b.centre[a]
+                d2 = d2 + da * da
+            fluid &= d2 >= b.r2
+        count += fluid
+    full = 2 ** dim
+    half = full // 2
+    role = np.where(count == full, INNER, np.where(count >= half, 1, VOID)).astype(np.int8)
+    bnd = role == 1
+    if bodies:
+        cen = [mesh.origin[a] + (ijk[a].astype(np.float64) + 0.5) * l0 for a in range(dim)]
+        best = np.full(K, np.inf)
+        best_id = np.zeros(K, dtype=np.int8)
+        for b in sorted(bodies, key=lambda q: q.body_id):
+            d2 = np.zeros(K)
+            for a in range(dim):
+                da = cen[a] - b.centre[a]
+                d2 = d2 + da * da
+            apsi = np.abs(np.sqrt(d2) - b.radius)
+            better = apsi < best
+            best = np.where(better, apsi, best)
+            best_id = np.where(better, b.body_id, best_id).astype(np.int8)
+        role = np.where(bnd, best_id, role).astype(np.int8)
+    role = np.where(mesh.is_wall_cell(ijk), mesh.wall_id, role).astype(np.int8)
+    return role
+
+
+def transition_codes(role_prev, role_new):
+    def cls(r):
+        return np.where(r == VOID, CLS_VOID, np.where(r == INNER, CLS_INNER, CLS_BOUNDARY))
+    return (3 * cls(role_prev) + cls(role_new)).astype(np.uint8)
+
+
+def band_cells(mesh, bodies, role, band_l0):
+    """Sec. 2.4: DPs re-positioned each step are those within band_l0 of a body.
+
+    Reading: min_b |psi_b| at the cell centroid < band_l0 (strict), void and
+    wall cells excluded.  Returns sorted cell indices.
+    """
+    if not bodies:
+        return np.zeros(0, dtype=np.int64)
+    idx = np.arange(mesh.Nc)
+    ijk = mesh.ijk(idx)
+    cen = [mesh.origin[a] + (ijk[a].astype(np.float64) + 0.5) * mesh.l0 for a in range(mesh.dim)]
+    best = np.full(mesh.Nc, np.inf)
+    for b in bodies:
+        d2 = np.zeros(mesh.Nc)
+        for a in range(mesh.dim):
+            da = cen[a] - b.centre[a]
+            d2 = d2 + da * da
+        best = np.minimum(best, np.abs(np.sqrt(d2) - b.radius))
+    sel = (best < band_l0) & (role != VOID)
+    if mesh.walls:
+        sel &= role != mesh.wall_id
+    return idx[sel]
+
+
+def project_walls(mesh, pos):
+    """Wall DPs sit on the wall: wall-normal coordinate := wall coordinate."""
+    if not mesh.walls:
+        return pos
+    pos = pos.copy()
+    ijk = mesh.ijk(np.arange(mesh.Nc))
+    for a in range(mesh.dim):
+        lo = ijk[a] == 0
+        hi = ijk[a] == mesh.n[a] - 1
+        pos[a] = np.where(lo, mesh.origin[a], pos[a])
+        pos[a] = np.where(hi, mesh.origin[a] + mesh.n[a] * mesh.l0, pos[a])
+    return pos
+
+
+# ---------------------------------------------------------------------------
+# Sec. 2.3: relaxation (ii), SDF projection (iii), mesh constraint (iv)
+# ---------------------------------------------------------------------------
+
+@dataclass
+class RelaxConsts:
+    """Host-computed constants used identically by every implementation."""
+    kl0: float            # kappa * l0   (kappa = 1/5)
+    spring: tuple         # natural lengths by number of nonzero offset axes
+    eps_l0: float         # stopping threshold eps_relax * l0
+    band_l0: float        # 5 l0
+
+    @classmethod
+    def make(cls, l0, kappa=0.2, eps_relax=1e-6, band_over_l0=5.0):
+        return cls(kl0=kappa * l0,
+                   spring=(0.0, l0, math.sqrt(2.0) * l0, math.sqrt(3.0) * l0),
+                   eps_l0=eps_relax * l0, band_l0=band_over_l0 * l0)
+
+
+def relax_sweep(mesh, consts, bodies, role, band, pos):
+    """One Jacobi sweep over the band cells; returns (new positions, max |dx|).
+
+    (ii) Spring forces: for every non-void neighbour j in the 3x3(x3) block,
+    F += G(r') x_ij/|x_ij| with G = 1 - |x_ij|/l_spring, l_spring = l0 for an
+    edge, sqrt(2) l0 for a diagonal (sqrt(3) l0 for a 3D corner: reading);
+    explicit Euler x* = x - (kappa l0) F (dimensionless form times l0).
+    (iii) Boundary DPs: x** = x* + psi d, d = -grad psi/|grad psi|, i.e.
+    x** = x* - (psi/r) (x* - c) for a circle/sphere of centre c.
+    (iv) Clamp every coordinate to the DP's own cell.
+    Slots are visited in lexicographic order; sums are left to right.
+    """
+    dim = mesh.dim
+    if len(band) == 0:
+        return pos.copy(), 0.0
+    ijk = mesh.ijk(band)
+    x = pos[:, band]
+    F = [np.zeros(len(band)) for _ in range(dim)]
+    with np.errstate(divide="ignore", invalid="ignore"):
+        for s, off in enumerate(mesh.offsets):
+            if s == mesh.centre:
+                continue
+            j, wrap = mesh.neighbour(ijk, off)
+            ok = j >= 0
+            jj = np.where(ok, j, 0)
+            ok &= role[jj] != VOID
+            d = [(pos[a, jj] + wrap[a] * mesh.length[a]) - x[a] for a in range(dim)]
+            d2 = d[0] * d[0]
+            for a in range(1, dim):
+                d2 = d2 + d[a] * d[a]
+            dist = np.sqrt(d2)
+            L = consts.spring[sum(1 for v in off if v != 0)]
+            g = 1.0 - dist / L
+            for a in range(dim):
+                F[a] = np.where(ok, F[a] + g * (d[a] / dist), F[a])
+        xs = [x[a] - consts.kl0 * F[a] for a in range(dim)]
+        rb = role[band]
+        for b in bodies:
+            sel = rb == b.body_id
+            if not sel.any():
+                continue
+            dd = [xs[a] - b.centre[a] for a in range(dim)]
+            r2 = dd[0] * dd[0]
+            for a in range(1, dim):
+                r2 = r2 + dd[a] * dd[a]
+            r = np.sqrt(r2)
+            psi = r - b.radius
+            t = psi / r
+            for a in range(dim):
+                xs[a] = np.where(sel, xs[a] - t * dd[a], xs[a])
+    out = pos.copy()
+    mx = 0.0
+    for a in range(dim):
+        lo = mesh.origin[a] + ijk[a].astype(np.float64) * mesh.l0
+        hi = mesh.origin[a] + (ijk[a] + 1).astype(np.float64) * mesh.l0
+        xn = np.minimum(np.maximum(xs[a], lo), hi)
+        out[a, band] = xn
+        mx = max(mx, float(np.max(np.abs(xn - x[a]))))
+    return out, mx
+
+
+def normals(mesh, bodies, role, pos):
+    """Unit normal of boundary DPs pointing into the fluid (grad psi).
+
+    Body DPs: (x - c)/|x - c|.  Wall DPs: the axis normals of the walls the
+    cell touches, summed and normalised (corners get the diagonal).
+    """
+    dim = mesh.dim
+    nrm = np.zeros((dim, mesh.Nc))
+    for b in bodies:
+        sel = np.nonzero(role == b.body_id)[0]
+        if len(sel) == 0:
+            continue
+        dd = [pos[a, sel] - b.centre[a] for a in range(dim)]
+        r2 = dd[0] * dd[0]
+        for a in range(1, dim):
+            r2 = r2 + dd[a] * dd[a]
+        r = np.sqrt(r2)
+        for a in range(dim):
+            nrm[a, sel] = dd[a] / r
+    if mesh.walls:
+        sel = np.nonzero(role == mesh.wall_id)[0]
+        ijk = mesh.ijk(sel)
+        sv = [np.where(ijk[a] == 0, 1.0, np.where(ijk[a] == mesh.n[a] - 1, -1.0, 0.0)) for a in range(dim)]
+        s2 = sv[0] * sv[0]
+        for a in range(1, dim):
+            s2 = s2 + sv[a] * sv[a]
+        nn = np.sqrt(s2)
+        for a in range(dim):
+            nrm[a, sel] = sv[a] / nn
+    return nrm
+
+
+@dataclass
+class UpdateResult:
+    pos: np.ndarray
+    role: np.ndarray
+    trans: np.ndarray
+    normal: np.ndarray
+    sweeps: int
+    band: np.ndarray
+
+
+def update_dps(mesh, consts, bodies, pos, role_prev, max_sweeps):
+    """Per-step DP rearrangement and role reassignment (Sec. 2.3, 2.4).
+
+    Reading of the iteration index: each time step starts from x^k and
+    sweeps (ii)-(iv) until max |dx| <= eps_relax l0 or max_sweeps sweeps.
+    """
+    role = roles(mesh, bodies)
+    trans = transition_codes(role_prev, role)
+    pos = project_walls(mesh, pos)
+    band = band_cells(mesh, bodies, role, consts.band_l0)
+    sweeps = 0
+    for _ in range(max_sweeps):
+        pos, mx = relax_sweep(mesh, consts, bodies, role, band, pos)
+        sweeps += 1
+        if mx <= consts.eps_l0:
+            break
+    nrm = normals(mesh, bodies, role, pos)
+    return UpdateResult(pos, role, trans, nrm, sweeps, band)
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.2: MLS approximation with chi_c = 1
+# ---------------------------------------------------------------------------
+
+def n_basis(dim):
+    return 5 if dim == 2 else 9
+
+
+def second_diag(dim):
+    return (2, 4) if dim == 2 else (3, 4, 5)
+
+
+def basis(X):
+    """Quadratic basis p(X), Eq. (p_ic); 3D order reading (X,Y,Z,X2/2,Y2/2,Z2/2,XY,YZ,ZX)."""
+    if len(X) == 2:
+        x, y = X
+        return [x, y, 0.5 * x * x, x * y, 0.5 * y * y]
+    x, y, z = X
+    return [x, y, z, 0.5 * x * x, 0.5 * y * y, 0.5 * z * z, x * y, y * z, z * x]
+
+
+def basis_normal(X, nv):
+    """p^N(X) = n . grad_X p(X)."""
+    if len(X) == 2:
+        x, y = X
+        nx, ny = nv
+        return [nx + 0 * x, ny + 0 * x, nx * x, nx * y + ny * x, ny * y]
+    x, y, z = X
+    nx, ny, nz = nv
+    return [nx + 0 * x, ny + 0 * x, nz + 0 * x, nx * x, ny * y, nz * z,
+            nx * y + ny * x, ny * z + nz * y, nz * x + nx * z]
+
+
+def weight(r, re, kind):
+    """cos^2(pi r / (2 re)) for r <= re, else 0 (Sec. 3.2).  'gauss' is the
+    truncated Gaussian exp(-4 r^2/re^2) used by the manufactured case."""
+    if kind == "cos2":
+        t = np.cos(np.pi * r / (2.0 * re))
+        w = t * t
+    elif kind == "gauss":
+        w = np.exp(-4.0 * r * r / (re * re))
+    else:
+        raise ValueError(kind)
+    return np.where(r <= re, w, 0.0)
+
+
+def _row_kind(role_j, bc):
+    """0 none, 1 value row (inner or Dirichlet id), 2 Neumann row."""
+    kind = np.where(role_j == INNER, 1, 0)
+    for bid, t in bc.items():
+        kind = np.where(role_j == bid, 2 if t == NEUMANN else 1, kind)
+    # boundary ids missing from the table default to Dirichlet
+    known = np.isin(role_j, list(bc.keys())) if bc else np.zeros(len(role_j), bool)
+    kind = np.where((role_j >= 1) & ~known, 1, kind)
+    return kind
+
+
+@dataclass
+class StencilSet:
+    """Per-DP MLS weights in slot form.
+
+    phi[b, s, k]: for a value slot s, W_s[b] (coefficient of phi_j - phi_c);
+    for a Neumann slot, the coefficient of f_j (W_s[b] times r_s); slot
+    `centre` holds -sum of value W; slot S holds the DP's own Neumann row.
+    """
+    idx: np.ndarray
+    phi: np.ndarray
+    kind: np.ndarray        # (S, K): 0 none, 1 value, 2 Neumann  (centre: own Neumann row)
+    nbr: np.ndarray         # (S, K) neighbour cell index (-1 outside)
+    singular: np.ndarray
+    rs: float
+    dim: int
+    extra: dict = field(default_factory=dict)
+
+
+def mls_build(mesh, pos, role, normal, bc, re, rs, kind="cos2", idx=None, chunk=1 << 17):
+    """Weights of the chi_c = 1 quadratic MLS fit at each DP (Sec. 3.2).
+
+    Minimising J of Eq. (obj_func) with phi_c fixed (chi_c = 1) gives
+    M Phi = sum_{Lambda_c} w_j p_j (phi_j - phi_c) + sum_{Lambda^N_c} w_j p^N_j r_s f_j,
+    M = sum_{Lambda_c} w_j p_j p_j^T + sum_{Lambda^N_c} w_j p^N_j p^N_j^T,
+    with Lambda_c the inner and Dirichlet DPs of the block and Lambda^N_c its
+    Neumann DPs (Eq. set), the DP itself included when it is Neumann.  M is
+    factored by textbook Cholesky; a pivot <= 1e-14 trace(M)/m flags the DP
+    singular (its weights are set to zero).
+    """
+    if idx is None:
+        idx = np.arange(mesh.Nc)
+    idx = np.asarray(idx, dtype=np.int64)
+    dim, S = mesh.dim, mesh.S
+    m = n_basis(dim)
+    K = len(idx)
+    phi = np.zeros((m, S + 1, K))
+    kindv = np.zeros((S, K), dtype=np.int8)
+    nbr = np.full((S, K), -1, dtype=np.int64)
+    singular = np.zeros(K, dtype=bool)
+    for c0 in range(0, K, chunk):
+        sl = slice(c0, min(K, c0 + chunk))
+        ph, kd, nb, sg = _mls_chunk(mesh, pos, role, normal, bc, re, rs, kind, idx[sl])
+        phi[:, :, sl], kindv[:, sl], nbr[:, sl], singular[sl] = ph, kd, nb, sg
+    return StencilSet(idx, phi, kindv, nbr, singular, rs, dim)
+
+
+def _mls_chunk(mesh, pos, role, normal, bc, re, rs, wkind, idx):
+    dim, S, m = mesh.dim, mesh.S, n_basis(mesh.dim)
+    K = len(idx)
+    ijk = mesh.ijk(idx)
+    xc = pos[:, idx]
+    role_c = role[idx]
+    active = role_c != VOID
+    rows = []        # (slot, kind, w, a)
+    kinds = np.zeros((S, K), dtype=np.int8)
+    nbrs = np.full((S, K), -1, dtype=np.int64)
+    for s, off in enumerate(mesh.offsets):
+        j, wrap = mesh.neighbour(ijk, off)
+        ok = (j >= 0) & active
+        jj = np.where(j >= 0, j, 0)
+        rk = np.where(ok, _row_kind(role[jj], bc), 0)
+        if s == mesh.centre:
+            rk = np.where(rk == 2, 2, 0)      # the DP itself: only its Neumann row
+        d = [(pos[a, jj] + wrap[a] * mesh.length[a]) - xc[a] for a in range(dim)]
+        r2 = d[0] * d[0]
+        for a in range(1, dim):
+            r2 = r2 + d[a] * d[a]
+        w = weight(np.sqrt(r2), re, wkind)
+        X = [d[a] / rs for a in range(dim)]
+        nv = [normal[a, jj] for a in range(dim)]
+        pv = np.array(basis(X))
+        pn = np.array(basis_normal(X, nv))
+        a_row = np.where(rk == 2, pn, pv)
+        w = np.where(rk > 0, w, 0.0)
+        rows.append((s, rk, w, a_row))
+        kinds[s] = rk
+        nbrs[s] = np.where(j >= 0, j, -1)
+    # moment matrix, slots in order
+    M = np.zeros((m, m, K))
+    for s, rk, w, a_row in rows:
+        M += w[None, None, :] * a_row[:, None, :] * a_row[None, :, :]
+    # textbook Cholesky M = L L^T
+    L = np.zeros_like(M)
+    tr = np.zeros(K)
+    for i in range(m):
+        tr = tr + M[i, i]
+    singular = np.zeros(K, dtype=bool)
+    for jcol in range(m):
+        dsum = M[jcol, jcol].copy()
+        for k in range(jcol):
+            dsum = dsum - L[jcol, k] * L[jcol, k]
+        bad = dsum <= 1e-14 * tr / m
+        singular |= bad
+        ljj = np.sqrt(np.where(bad, 1.0, dsum))
+        L[jcol, jcol] = ljj
+        for i in range(jcol + 1, m):
+            acc = M[i, jcol].copy()
+            for k in range(jcol):
+                acc = acc - L[i, k] * L[jcol, k]
+            L[i, jcol] = acc / ljj
+    singular &= active
+
+    def solve(rhs):
+        z = np.zeros_like(rhs)
+        for i in range(m):
+            acc = rhs[i].copy()
+            for k in range(i):
+                acc = acc - L[i, k] * z[k]
+            z[i] = acc / L[i, i]
+        y = np.zeros_like(rhs)
+        for i in reversed(range(m)):
+            acc = z[i].copy()
+            for k in range(i + 1, m):
+                acc = acc - L[k, i] * y[k]
+            y[i] = acc / L[i, i]
+        return y
+
+    phi = np.zeros((m, S + 1, K))
+    centre_sum = np.zeros((m, K))
+    for s, rk, w, a_row in rows:
+        if not (rk > 0).any():
+            continue
+        y = solve(w[None, :] * a_row)
+        y = np.where((rk > 0)[None, :], y, 0.0)
+        if s == mesh.centre:
+            phi[:, S] = np.where((rk == 2)[None, :], y * rs, 0.0)
+        else:
+            phi[:, s] = np.where((rk == 2)[None, :], y * rs, y)
+            centre_sum = centre_sum + np.where((rk == 1)[None, :], y, 0.0)
+    phi[:, mesh.centre] = -centre_sum
+    phi[:, :, singular] = 0.0
+    return phi, kinds, nbrs, singular
+
+
+# ---------------------------------------------------------------------------
+# Applying the weights (Eq. intrp_chi_1 and derivative readings)
+# ---------------------------------------------------------------------------
+
+def poly_coeffs(mesh, st, fld, f_neu=None):
+    """Phi at the stencil set's DPs for scalar field fld (Nc,).
+
+    Phi = sum_value W_j (phi_j - phi_c) + sum_Neumann (W_j r_s) f_j.
+    """
+    m = st.phi.shape[0]
+    K = len(st.idx)
+    acc = np.zeros((m, K))
+    fc = fld[st.idx]
+    for s in range(mesh.S):
+        kd = st.kind[s]
+        jj = np.where(st.nbr[s] >= 0, st.nbr[s], 0)
+        if s == mesh.centre:
+            continue
+        val = np.where(kd == 1, fld[jj] - fc, 0.0)
+        if f_neu is not None:
+            val = np.where(kd == 2, f_neu[jj], val)
+        acc = acc + st.phi[:, s] * val[None, :]
+    if f_neu is not None:
+        acc = acc + st.phi[:, mesh.S] * np.where(st.kind[mesh.centre] == 2, f_neu[st.idx], 0.0)[None, :]
+    return acc
+
+
+def grad_from_phi(Phi, rs, dim):
+    return np.stack([Phi[a] / rs for a in range(dim)])
+
+
+def lap_from_phi(Phi, rs, dim):
+    acc = 0.0
+    for b in second_diag(dim):
+        acc = acc + Phi[b]
+    return acc / (rs * rs)
+
+
+def taylor_shift(fc, Phi, shift, rs):
+    """phi(x_c + shift) = phi_c + p(shift / r_s) . Phi   (Eq. intrp_chi_1)."""
+    dim = shift.shape[0]
+    pv = basis([shift[a] / rs for a in range(dim)])
+    acc = fc.copy()
+    for b in range(len(pv)):
+        acc = acc + pv[b] * Phi[b]
+    return acc
+
+
+def lap_coefficients(mesh, st):
+    """Laplacian weights per slot: (S+1, K)."""
+    acc = 0.0
+    for b in second_diag(mesh.dim):
+        acc = acc + st.phi[b]
+    return acc / (st.rs * st.rs)
+
+
+# ---------------------------------------------------------------------------
+# PPE (Eq. pressure_poisson) and Bi-CGSTAB
+# ---------------------------------------------------------------------------
+
+def unknown_mask(role, bc, pin_first=False):
+    """Unknown rows: inner DPs and Neumann boundary DPs (collocated); Dirichlet
+    DPs are known.  Periodic problems pin DP 0 to P = 0."""
+    unk = role == INNER
+    for bid, t in bc.items():
+        if t == NEUMANN:
+            unk |= role == bid
+    if pin_first:
+        unk = unk.copy()
+        unk[0] = False
+    return unk
+
+
+def ppe_system(mesh, st, role, bc, rhs, g, f_neu, pin_first=False):
+    """Sparse A over unknown rows/columns and the effective right-hand side.
+
+    Row c: sum_value L_j (P_j - P_c) + sum_Neumann L^N_j f_j = b_c.  Columns of
+    known (Dirichlet / pinned) DPs move to the right-hand side with their
+    values g; Neumann data move there as well.
+    """
+    assert len(st.idx) == mesh.Nc
+    unk = unknown_mask(role, bc, pin_first)
+    uidx = np.nonzero(unk)[0]
+    col_of = -np.ones(mesh.Nc, dtype=np.int64)
+    col_of[uidx] = np.arange(len(uidx))
+    lc = lap_coefficients(mesh, st)
+    beff = rhs[uidx].astype(np.float64).copy()
+    rows, cols, vals = [], [], []
+    diag = np.zeros(len(uidx))
+    for s in range(mesh.S):
+        if s == mesh.centre:
+            continue
+        kd = st.kind[s][uidx]
+        j = st.nbr[s][uidx]
+        jj = np.where(j >= 0, j, 0)
+        cj = lc[s][uidx]
+        isval = kd == 1
+        diag = diag - np.where(isval, cj, 0.0)
+        jun = isval & unk[jj]
+        rows.append(np.nonzero(jun)[0])
+        cols.append(col_of[jj[jun]])
+        vals.append(cj[jun])
+        known = isval & ~unk[jj]
+        beff = beff - np.where(known, cj * g[jj], 0.0)
+        if f_neu is not None:
+            beff = beff - np.where(kd == 2, cj * f_neu[jj], 0.0)
+    if f_neu is not None:
+        beff = beff - np.where(st.kind[mesh.centre][uidx] == 2, lc[mesh.S][uidx] * f_neu[uidx], 0.0)
+    rows.append(np.arange(len(uidx)))
+    cols.append(np.arange(len(uidx)))
+    vals.append(diag)
+    A = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))),
+                      shape=(len(uidx), len(uidx)))
+    return A, beff, uidx
+
+
+@dataclass
+class SolveInfo:
+    iterations: int = 0
+    restarts: int = 0
+    true_rel_residual: float = np.nan
+    converged: bool = False
+
+
+def bicgstab(A, b, x0, tol, max_iter=20000, breakdown=1e-30):
+    """Unpreconditioned Bi-CGSTAB (van der Vorst, 1992), as named in Sec. 3.3.
+
+    Stopping (reading): recurrence ||r|| <= tol ||b||, then confirmed by the
+    true residual b - A x; if that fails, restart from the true residual.
+    A restart with r_hat = r also follows a (near-)breakdown of rho or
+    r_hat.v.
+    """
+    info = SolveInfo()
+    x = x0.astype(np.float64).copy()
+    nb = float(np.linalg.norm(b))
+    if nb == 0.0:
+        info.true_rel_residual, info.converged = 0.0, True
+        return np.zeros_like(x), info
+    r = b - A @ x
+    while info.iterations < max_iter:
+        if np.linalg.norm(r) <= tol * nb:
+            break
+        rhat = r.copy()
+        rho = alpha = omega = 1.0
+        v = np.zeros_like(x)
+        p = np.zeros_like(x)
+        restart = False
+        while info.iterations < max_iter:
+            rho_new = float(rhat @ r)
+            if abs(rho_new) < breakdown * float(rhat @ rhat):
+                restart = True
+                break
+            beta = (rho_new / rho) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+            v = A @ p
+            rv = float(rhat @ v)
+            if abs(rv) < breakdown * float(np.linalg.norm(rhat) * np.linalg.norm(v)):
+                restart = True
+                break
+            alpha = rho_new / rv
+            s = r - alpha * v
+            t = A @ s
+            tt = float(t @ t)
+            omega = float(t @ s) / tt if tt > 0 else 0.0
+            x = x + alpha * p + omega * s
+            r = s - omega * t
+            rho = rho_new
+            info.iterations += 1
+            if np.linalg.norm(r) <= tol * nb:
+                break
+            if omega == 0.0:
+                restart = True
+                break
+        r = b - A @ x          # confirm with the true residual
+        if restart:
+            info.restarts += 1
+        elif np.linalg.norm(r) > tol * nb:
+            info.restarts += 1
+    info.true_rel_residual = float(np.linalg.norm(b - A @ x)) / nb
+    info.converged = info.true_rel_residual <= tol
+    return x, info
+
+
+def solve_ppe(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess="zero", max_iter=20000):
+    """Solve the PPE; p_in carries Dirichlet values (and the guess for 'caller')."""
+    A, beff, uidx = ppe_system(mesh, st, role, bc, rhs, p_in, f_neu, pin_first)
+    x0 = p_in[uidx] if guess == "caller" else np.zeros(len(uidx))
+    x, info = bicgstab(A, beff, x0, tol, max_iter)
+    p = p_in.copy()
+    p[uidx] = x
+    return p, info, (A, beff, uidx)
+
+
+def solve_ppe_mixed(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess="zero",
+                    inner_tol=1e-4, max_outer=30, max_iter=20000):
+    """FP32-operator Bi-CGSTAB inside FP64 iterative refinement.
+
+    A32 = FP64 weights rounded to FP32, FP32 vectors, FP64 dot products;
+    the residual b - A64 x and the update x += d are FP64.
+    """
+    A, beff, uidx = ppe_system(mesh, st, role, bc, rhs, p_in, f_neu, pin_first)
+    A32 = A.astype(np.float32)
+    x = p_in[uidx].astype(np.float64) if guess == "caller" else np.zeros(len(uidx))
+    nb = float(np.linalg.norm(beff))
+    info = SolveInfo()
+    outer = 0
+    while nb > 0:
+        r = beff - A @ x
+        nr = float(np.linalg.norm(r))
+        if nr <= tol * nb or outer >= max_outer:
+            break
+        scale = 1.0 / nr
+        d, inf = _bicgstab32(A32, (r * scale).astype(np.float32), inner_tol, max_iter)
+        x = x + d.astype(np.float64) / scale
+        info.iterations += inf
+        outer += 1
+    info.restarts = outer
+    info.true_rel_residual = float(np.linalg.norm(beff - A @ x)) / nb if nb > 0 else 0.0
+    info.converged = info.true_rel_residual <= tol
+    p = p_in.copy()
+    p[uidx] = x
+    return p, info
+
+
+def _bicgstab32(A32, b32, tol, max_iter):
+    x = np.zeros_like(b32)
+    r = b32.copy()
+    nb = float(np.linalg.norm(b32.astype(np.float64)))
+    rhat = r.copy()
+    rho = alpha = omega = 1.0
+    v = np.zeros_like(b32)
+    p = np.zeros_like(b32)
+    it = 0
+
+    def dot(a, b):
+        return float(np.dot(a.astype(np.float64), b.astype(np.float64)))
+    while it < max_iter:
+        rho_new = dot(rhat, r)
+        if rho_new == 0.0:
+            break
+        beta = (rho_new / rho) * (alpha / omega)
+        p = (r + np.float32(beta) * (p - np.float32(omega) * v)).astype(np.float32)
+        v = A32 @ p
+        rv = dot(rhat, v)
+        if rv == 0.0:
+            break
+        alpha = rho_new / rv
+        s = (r - np.float32(alpha) * v).astype(np.float32)
+        t = A32 @ s
+        tt = dot(t, t)
+        omega = dot(t, s) / tt if tt > 0 else 0.0
+        x = (x + np.float32(alpha) * p + np.float32(omega) * s).astype(np.float32)
+        r = (s - np.float32(omega) * t).astype(np.float32)
+        rho = rho_new
+        it += 1
+        if math.sqrt(dot(r, r)) <= tol * nb or omega == 0.0:
+            break
+    return x, it
+
+
+# ---------------------------------------------------------------------------
+# Sec. 3.3 fractional step, Appendix A remap
+# ---------------------------------------------------------------------------
+
+def remap_velocity(mesh, st_prev, u, pos_prev, pos_new, role_prev, role_new, bodies_prev, bodies_new,
+                   f_vel_prev=None):
+    """u~ = u^k(x^{k+1}) by the chi_c = 1 quadratic Taylor shift (Eq. ale_vel, p = 2).
+
+    inner -> inner: Eq. (A.1) with the DP's own step-k stencil.
+    boundary/void -> inner: Eq. (A.2) with the support shifted one cell per
+    axis by sign(d psi / d x_a) at x^k (into the fluid, Sec. 3.4); the shifted
+    block is the step-k support of the neighbour c' it is centred on.  When
+    c' was not inner at step k the DP's own step-k stencil is used instead
+    (reading) and the event is counted.
+    -> body boundary: the body velocity (no slip).  -> wall or void: 0.
+    """
+    dim = mesh.dim
+    out = np.zeros_like(u)
+    stats = {"shifted": 0, "fallback": 0}
+    body_of = {b.body_id: b for b in bodies_new}
+    prev_of = {b.body_id: b for b in bodies_prev}
+    inner_new = role_new == INNER
+    # Phi^k for every component at every cell (st_prev covers all cells)
+    Phis = [poly_coeffs(mesh, st_prev, u[a], f_vel_prev[a] if f_vel_prev is not None else None)
+            for a in range(dim)]
+    centre = np.arange(mesh.Nc)
+    # default: own stencil
+    src = centre.copy()
+    newly = inner_new & (role_prev != INNER)
+    idxs = np.nonzero(newly)[0]
+    if len(idxs):
+        ijk = mesh.ijk(idxs)
+        off = np.zeros((dim, len(idxs)), dtype=np.int64)
+        rp = role_prev[idxs]
+        for b in bodies_prev:
+            sel = rp == b.body_id
+            for a in range(dim):
+                gcomp = pos_prev[a, idxs] - b.centre[a]
+                off[a] = np.where(sel, np.sign(gcomp).astype(np.int64), off[a])
+        cp = np.zeros(len(idxs), dtype=np.int64)
+        okc = np.ones(len(idxs), dtype=bool)
+        stride = 1
+        for a in range(dim):
+            ii = ijk[a] + off[a]
+            okc &= (ii >= 0) & (ii < mesh.n[a])
+            cp += np.clip(ii, 0, mesh.n[a] - 1) * stride
+            stride *= mesh.n[a]
+        good = okc & (role_prev[np.where(okc, cp, 0)] == INNER)
+        src[idxs] = np.where(good, cp, idxs)
+        stats["shifted"] = int(good.sum())
+        stats["fallback"] = int((~good).sum())
+    dx = pos_new - pos_prev[:, src]
+    for a in range(dim):
+        val = taylor_shift(u[a, src], Phis[a][:, src], dx, st_prev.rs)
+        out[a] = np.where(inner_new, val, 0.0)
+    for bid, b in body_of.items():
+        sel = role_new == bid
+        for a in range(dim):
+            out[a] = np.where(sel, b.velocity[a], out[a])
+    return out, stats
+
+
+def moc_viscous(mesh, st_vel, ut, dt, nu, role, bodies, f_vel=None):
+    """u* = F_MOC + nu dt lap(u~) at inner DPs (Eq. intermed_vel).
+
+    F_MOC reading: the chi_c = 1 Taylor value of u~ at x - u~ dt with the
+    step-(k+1) velocity weights.  Body DPs take the body velocity; walls and
+    void take 0 (never used as value data).
+    """
+    dim = mesh.dim
+    out = np.zeros_like(ut)
+    shift = -ut * dt
+    for a in range(dim):
+        Phi = poly_coeffs(mesh, st_vel, ut[a], f_vel[a] if f_vel is not None else None)
+        val = taylor_shift(ut[a], Phi, shift, st_vel.rs) + nu * dt * lap_from_phi(Phi, st_vel.rs, dim)
+        out[a] = np.where(role == INNER, val, 0.0)
+    for b in bodies:
+        sel = role == b.body_id
+        for a in range(dim):
+            out[a] = np.where(sel, b.velocity[a], out[a])
+    return out
+
+
+def divergence(mesh, st_vel, uvec, f_vel=None):
+    dim = mesh.dim
+    acc = 0.0
+    for a in range(dim):
+        Phi = poly_coeffs(mesh, st_vel, uvec[a], f_vel[a] if f_vel is not None else None)
+        acc = acc + Phi[a] / st_vel.rs
+    return acc
+
+
+def project(mesh, st_p, P, f_p, ustar, dt, role, bodies):
+    """u^{k+1} = u* - dt grad P at inner DPs (Eq. projection)."""
+    dim = mesh.dim
+    Phi = poly_coeffs(mesh, st_p, P, f_p)
+    g = grad_from_phi(Phi, st_p.rs, dim)
+    out = np.where((role == INNER)[None, :], ustar - dt * g, 0.0)
+    for b in bodies:
+        sel = role == b.body_id
+        for a in range(dim):
+            out[a] = np.where(sel, b.velocity[a], out[a])
+    return out
+
+
+def neumann_pressure_data(mesh, role, normal, bodies, dvdt):
+    """f_j = -dV/dt . n_j at body DPs (Eq. neumann_moving_boundary)."""
+    f = np.zeros(mesh.Nc)
+    for b in bodies:
+        sel = role == b.body_id
+        acc = 0.0
+        for a in range(mesh.dim):
+            acc = acc + dvdt[b.body_id][a] * normal[a]
+        f = np.where(sel, -acc, f)
+    return f

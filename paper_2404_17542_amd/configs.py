@@ -1,0 +1,109 @@
+"""Workload definitions (data only): mesh, DP jitter seed, bodies, physics constants.
+
+Role ids: the outer ring (2D) / shell (3D) of cells is the wall boundary with
+id WALL_ID; the moving rigid body has id BODY_ID.  Per-field boundary
+conditions are given per id (Dirichlet or Neumann) for the pressure set and
+the velocity set.
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass, field, replace
+from typing import Optional
+
+from .inputs import Oscillation
+
+WALL_ID = 1
+BODY_ID = 2
+
+DIRICHLET = 0
+NEUMANN = 1
+
+
+@dataclass(frozen=True)
+class Body:
+    """A rigid circle (2D) or sphere (3D) with prescribed translation."""
+    radius: float
+    motion: Oscillation
+    body_id: int = BODY_ID
+
+
+@dataclass(frozen=True)
+class Case:
+    name: str
+    dim: int
+    n: tuple
+    origin: tuple
+    l0: float
+    periodic: tuple
+    walls: bool
+    jitter_seed: int
+    weight: str = "cos2"          # "cos2" (paper) or "gauss"
+    re_over_l0: float = 2.5
+    rs_over_l0: float = 1.0
+    kappa: float = 0.2
+    band_over_l0: float = 5.0
+    n_relax: int = 20
+    n_relax_init: int = 500
+    eps_relax: float = 1e-6
+    body: Optional[Body] = None
+    nu: float = 0.0
+    dt: float = 0.0
+    steps: int = 1
+    tol: float = 1e-8
+    # boundary condition per role id for the pressure and the velocity sets
+    bc_pressure: dict = field(default_factory=dict)
+    bc_velocity: dict = field(default_factory=dict)
+    pin_first: bool = False
+
+    @property
+    def n_cells(self):
+        out = 1
+        for m in self.n:
+            out *= m
+        return out
+
+    def scaled(self, n, **kw):
+        """Same case on a different mesh size (domain kept, l0 rescaled)."""
+        length = self.n[0] * self.l0
+        return replace(self, n=tuple(n), l0=length / n[0], **kw)
+
+
+def c0_manufactured(n=32):
+    """Unit square, n x n mesh, Dirichlet ring, Gaussian weight, one solve."""
+    return Case(name=f"C0-manufactured-{n}", dim=2, n=(n, n), origin=(0.0, 0.0), l0=1.0 / n,
+                periodic=(False, False), walls=True, jitter_seed=0, weight="gauss",
+                bc_pressure={1: DIRICHLET}, bc_velocity={1: DIRICHLET})
+
+
+def c1_taylor_green(n=512, steps=100):
+    """Periodic [0, 2pi]^2 Taylor-Green vortex, nu = 0.01, dt = 0.2 l0."""
+    l0 = 2 * math.pi / n
+    return Case(name=f"C1-taylor-green-{n}", dim=2, n=(n, n), origin=(0.0, 0.0), l0=l0,
+                periodic=(True, True), walls=False, jitter_seed=1, weight="cos2",
+                nu=0.01, dt=0.2 * l0, steps=steps, pin_first=True)
+
+
+def c2_oscillating_cylinder(n=1024, steps=50):
+    """[-4, 4]^2, cylinder D = 1 with x(t) = 0.2 sin(2 pi t), Re = 100."""
+    amp, freq, diam = 0.2, 1.0, 1.0
+    u_max = 2 * math.pi * freq * amp
+    l0 = 8.0 / n
+    return Case(name=f"C2-oscillating-cylinder-{n}", dim=2, n=(n, n), origin=(-4.0, -4.0), l0=l0,
+                periodic=(False, False), walls=True, jitter_seed=2, weight="cos2",
+                body=Body(radius=0.5 * diam, motion=Oscillation((0.0, 0.0), amp, freq, 0)),
+                nu=u_max * diam / 100.0, dt=(1.0 / 800.0) * (1024.0 / n), steps=steps,
+                bc_pressure={1: DIRICHLET, 2: NEUMANN}, bc_velocity={1: NEUMANN, 2: DIRICHLET})
+
+
+def c4_moving_sphere(n=128, steps=20):
+    """[0, 1]^3, sphere D = 0.25 at the centre with x(t) = 0.05 sin(2 pi t), Re = 100."""
+    diam = 0.25
+    amp, freq = 0.2 * diam, 1.0
+    u_max = 2 * math.pi * freq * amp
+    l0 = 1.0 / n
+    return Case(name=f"C4-moving-sphere-{n}", dim=3, n=(n, n, n), origin=(0.0, 0.0, 0.0), l0=l0,
+                periodic=(False, False, False), walls=True, jitter_seed=4, weight="cos2",
+                body=Body(radius=0.5 * diam, motion=Oscillation((0.5, 0.5, 0.5), amp, freq, 0)),
+                nu=u_max * diam / 100.0, dt=(1.0 / 200.0) * (128.0 / n), steps=steps,
+                bc_pressure={1: DIRICHLET, 2: NEUMANN}, bc_velocity={1: NEUMANN, 2: DIRICHLET})

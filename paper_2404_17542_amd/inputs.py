@@ -1,0 +1,108 @@
+"""Seeded synthetic inputs shared by the HIP path, the tests and the oracle.
+
+This module holds *data generation only*: cell geometry of the background
+mesh, seeded jitter of the discrete points (DPs), analytic fields of the test
+problems (manufactured Poisson solution, Taylor-Green vortex) and prescribed
+rigid-body trajectories.  None of the MCD method's arithmetic (masking,
+relaxation, MLS, Krylov) lives here, so importing it does not couple the
+oracle to the GPU path.
+
+Cell ordering everywhere: c = i + n0 * (j + n1 * k) (x fastest).
+Per-DP vectors are structure-of-arrays, shape (dim, Nc).
+"""
+from __future__ import annotations
+
+import math
+from dataclasses import dataclass
+
+import numpy as np
+
+
+def n_cells(n) -> int:
+    return int(np.prod(np.asarray(n, dtype=np.int64)))
+
+
+def cell_index_grid(n):
+    """Integer cell coordinates (dim, Nc), x fastest."""
+    dim = len(n)
+    grids = np.meshgrid(*[np.arange(m, dtype=np.int64) for m in n], indexing="ij")
+    # meshgrid(ij) gives axis-0 slowest; we want x (axis 0 of n) fastest.
+    out = np.empty((dim, n_cells(n)), dtype=np.int64)
+    for a in range(dim):
+        out[a] = np.transpose(grids[a]).reshape(-1)
+    return out
+
+
+def cell_centroids(n, origin, l0):
+    """Centroid of every background-mesh cell, (dim, Nc) float64."""
+    ijk = cell_index_grid(n)
+    dim = len(n)
+    out = np.empty((dim, ijk.shape[1]), dtype=np.float64)
+    for a in range(dim):
+        out[a] = origin[a] + (ijk[a].astype(np.float64) + 0.5) * l0
+    return out
+
+
+def jittered_positions(n, origin, l0, seed, amp=0.2):
+    """One DP per cell at the centroid plus uniform jitter of +-amp*l0 per axis.
+
+    numpy PCG64(seed) draws U(-amp, amp) of shape (dim, Nc) in one call.
+    """
+    rng = np.random.Generator(np.random.PCG64(seed))
+    u = rng.uniform(-amp, amp, size=(len(n), n_cells(n)))
+    return cell_centroids(n, origin, l0) + l0 * u
+
+
+# --------------------------------------------------------------------------
+# Analytic fields of the synthetic workloads
+# --------------------------------------------------------------------------
+
+def manufactured_pressure(pos):
+    """p = sin(2 pi x) sin(2 pi y) on the unit square."""
+    return np.sin(2 * np.pi * pos[0]) * np.sin(2 * np.pi * pos[1])
+
+
+def manufactured_rhs(pos):
+    """Laplacian of manufactured_pressure: -8 pi^2 sin(2 pi x) sin(2 pi y)."""
+    return -8.0 * np.pi ** 2 * manufactured_pressure(pos)
+
+
+def tgv_velocity(pos, t, nu):
+    """2D Taylor-Green vortex on [0, 2pi]^2: (sin x cos y, -cos x sin y) e^{-2 nu t}."""
+    e = math.exp(-2.0 * nu * t)
+    return np.stack([np.sin(pos[0]) * np.cos(pos[1]) * e,
+                     -np.cos(pos[0]) * np.sin(pos[1]) * e])
+
+
+def tgv_pressure(pos, t, nu):
+    """p = (cos 2x + cos 2y) e^{-4 nu t} / 4."""
+    return 0.25 * (np.cos(2 * pos[0]) + np.cos(2 * pos[1])) * math.exp(-4.0 * nu * t)
+
+
+# --------------------------------------------------------------------------
+# Prescribed rigid-body motion (translation only)
+# --------------------------------------------------------------------------
+
+@dataclass(frozen=True)
+class Oscillation:
+    """Body centre c(t) = c0 + A sin(2 pi f t) e_axis; velocity is its derivative."""
+    c0: tuple
+    amplitude: float
+    freq: float
+    axis: int = 0
+
+    def centre(self, t):
+        c = list(self.c0)
+        c[self.axis] = self.c0[self.axis] + self.amplitude * math.sin(2 * math.pi * self.freq * t)
+        return tuple(float(v) for v in c)
+
+    def velocity(self, t):
+        v = [0.0] * len(self.c0)
+        v[self.axis] = 2 * math.pi * self.freq * self.amplitude * math.cos(2 * math.pi * self.freq * t)
+        return tuple(v)
+
+
+def random_unet_batch(rng_seed, shape, dtype=np.float32):
+    """Seeded normal tensor for network tests (no method arithmetic)."""
+    rng = np.random.Generator(np.random.PCG64(rng_seed))
+    return rng.standard_normal(shape).astype(dtype)

@@ -1,0 +1,149 @@
+"""Pins of the oracle's masking and DP arrangement (Sec. 2.2-2.4)."""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from hypothesis import given, settings, strategies as st
+
+from oracle import mcd_oracle as O
+from paper_2404_17542_amd import inputs
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _brute_roles(n, origin, l0, centre, radius, walls):
+    """Pure-Python vertex counting with psi = hypot(v - c) - R >= 0."""
+    dim = len(n)
+    out = []
+    for c in range(int(np.prod(n))):
+        ijk, r = [], c
+        for a in range(dim):
+            ijk.append(r % n[a])
+            r //= n[a]
+        cnt = 0
+        for v in range(2 ** dim):
+            vx = [origin[a] + (ijk[a] + ((v >> a) & 1)) * l0 for a in range(dim)]
+            psi = math.sqrt(sum((vx[a] - centre[a]) ** 2 for a in range(dim))) - radius
+            cnt += psi >= 0
+        full = 2 ** dim
+        role = -1 if cnt == full else (2 if cnt >= full // 2 else 0)
+        if walls and any(ijk[a] in (0, n[a] - 1) for a in range(dim)):
+            role = 1
+        out.append(role)
+    return np.array(out, dtype=np.int8)
+
+
+@settings(max_examples=25, deadline=None)
+@given(n=st.integers(4, 12), cx=st.floats(0.2, 0.8), cy=st.floats(0.2, 0.8), rad=st.floats(0.05, 0.4),
+       walls=st.booleans())
+def test_roles_brute_force_2d(n, cx, cy, rad, walls):
+    l0 = 1.0 / n
+    m = O.Mesh(2, (n, n), (0.0, 0.0), l0, walls=walls)
+    got = O.roles(m, [O.BodyState((cx, cy), rad, 2)])
+    want = _brute_roles((n, n), (0.0, 0.0), l0, (cx, cy), rad, walls)
+    # |v-c|^2 >= R^2 and hypot(v-c) - R >= 0 can differ only on exact ties
+    assert np.mean(got == want) == 1.0
+
+
+@settings(max_examples=8, deadline=None)
+@given(n=st.integers(4, 7), rad=st.floats(0.1, 0.4))
+def test_roles_brute_force_3d(n, rad):
+    l0 = 1.0 / n
+    m = O.Mesh(3, (n, n, n), (0.0,) * 3, l0, walls=True)
+    got = O.roles(m, [O.BodyState((0.47, 0.52, 0.5), rad, 2)])
+    want = _brute_roles((n, n, n), (0.0,) * 3, l0, (0.47, 0.52, 0.5), rad, True)
+    assert np.array_equal(got, want)
+
+
+@pytest.mark.parametrize("key", ["cylinder_1024", "sphere_128"])
+def test_role_counts_at_t0(key):
+    g = json.load(open(os.path.join(GOLD, "role_counts_t0.json")))[key]
+    dim = len(g["n"])
+    m = O.Mesh(dim, g["n"], g["origin"], g["l0"], walls=True)
+    r = O.roles(m, [O.BodyState(tuple(g["centre"]), g["radius"], 2)])
+    assert int((r == O.INNER).sum()) == g["inner"]
+    assert int((r == 2).sum()) == g["body"]
+    assert int((r == O.VOID).sum()) == g["void"]
+    assert int((r == 1).sum()) == g["wall"]
+
+
+def test_no_edge_adjacent_inner_void():
+    """An inner cell shares two vertices with psi >= 0 with each edge
+    neighbour, so no edge neighbour of an inner cell can be void."""
+    n = 64
+    m = O.Mesh(2, (n, n), (0.0, 0.0), 1.0 / n)
+    r = O.roles(m, [O.BodyState((0.51, 0.43), 0.27, 2)]).reshape(n, n)
+    inner, void = r == O.INNER, r == O.VOID
+    assert not (inner[:, 1:] & void[:, :-1]).any() and not (inner[:, :-1] & void[:, 1:]).any()
+    assert not (inner[1:, :] & void[:-1, :]).any() and not (inner[:-1, :] & void[1:, :]).any()
+
+
+def test_spring_hand_example():
+    """One edge neighbour at 0.8 l0: the spring is compressed by 0.2 and the
+    DP moves by kappa l0 (1 - 0.8) = 0.04 l0 away from it (Eqs.
+    dimensionless_force_function, 1st_intermed_position)."""
+    l0 = 1.0
+    m = O.Mesh(2, (3, 3), (0.0, 0.0), l0)
+    role = np.zeros(9, np.int8)
+    role[4] = O.INNER
+    role[5] = O.INNER
+    pos = inputs.cell_centroids(m.n, m.origin, l0)
+    pos[0, 4] = 1.6
+    pos[0, 5] = 2.4          # distance 0.8
+    consts = O.RelaxConsts.make(l0)
+    out, mx = O.relax_sweep(m, consts, [], role, np.array([4]), pos)
+    assert out[0, 4] == pytest.approx(1.6 - 0.04, abs=1e-15)
+    assert out[1, 4] == pos[1, 4]
+    assert mx == pytest.approx(0.04, abs=1e-15)
+
+
+def test_regular_grid_is_a_fixed_point():
+    n = 10
+    m = O.Mesh(2, (n, n), (0.0, 0.0), 0.1, (True, True))
+    pos = inputs.cell_centroids(m.n, m.origin, m.l0)
+    role = np.full(m.Nc, O.INNER, np.int8)
+    out, mx = O.relax_sweep(m, O.RelaxConsts.make(0.1), [], role, np.arange(m.Nc), pos)
+    assert mx < 1e-15
+
+
+def test_update_invariants_cylinder():
+    """Every DP ends inside its closed cell; band boundary DPs end on the
+    circle unless the mesh constraint clamped them; the clamp is idempotent."""
+    n = 96
+    l0 = 8.0 / n
+    m = O.Mesh(2, (n, n), (-4.0, -4.0), l0, walls=True)
+    body = O.BodyState((0.13, -0.07), 0.5, 2)
+    pos = inputs.jittered_positions(m.n, m.origin, l0, seed=2)
+    role0 = O.roles(m, [body])
+    consts = O.RelaxConsts.make(l0)
+    up = O.update_dps(m, consts, [body], pos, role0, 300)
+    ijk = m.ijk(np.arange(m.Nc))
+    for a in range(2):
+        lo = m.origin[a] + ijk[a] * l0
+        hi = m.origin[a] + (ijk[a] + 1) * l0
+        assert np.all(up.pos[a] >= lo) and np.all(up.pos[a] <= hi)
+    bnd = np.nonzero(up.role == 2)[0]
+    psi = np.hypot(up.pos[0, bnd] - body.centre[0], up.pos[1, bnd] - body.centre[1]) - body.radius
+    on_edge = np.zeros(len(bnd), bool)
+    for a in range(2):
+        lo = m.origin[a] + ijk[a, bnd] * l0
+        hi = m.origin[a] + (ijk[a, bnd] + 1) * l0
+        on_edge |= (up.pos[a, bnd] == lo) | (up.pos[a, bnd] == hi)
+    assert np.all(np.abs(psi[~on_edge]) <= 1e-12 * l0 * 10)
+    assert on_edge.mean() < 0.5
+    # wall DPs on the walls
+    w = np.nonzero(up.role == 1)[0]
+    wi = m.ijk(w)
+    assert np.all(up.pos[0, w][wi[0] == 0] == -4.0)
+    # a second update at the same body position moves nothing already converged
+    again = O.update_dps(m, consts, [body], up.pos, up.role, 1)
+    assert np.array_equal(again.role, up.role)
+    assert np.abs(again.pos - up.pos).max() < 0.05 * l0
+
+
+def test_transition_codes():
+    prev = np.array([0, 0, -1, -1, 2, 2, 0, -1, 2], np.int8)
+    new = np.array([0, -1, 0, -1, 0, -1, 2, 2, 2], np.int8)
+    assert list(O.transition_codes(prev, new)) == [0, 1, 3, 4, 6, 7, 2, 5, 8]

@@ -1,0 +1,110 @@
+"""Pins of the oracle's PPE solve and time step (Sec. 3.3): dense direct
+solves, the manufactured solution's convergence order, the Taylor-Green
+decay, and the remap's exactness on quadratics."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mcd_oracle as O
+from oracle.sim import OracleSim
+from paper_2404_17542_amd import configs, inputs
+
+
+def _c0(n):
+    case = configs.c0_manufactured(n)
+    m = O.Mesh.from_case(case)
+    pos = O.project_walls(m, inputs.jittered_positions(case.n, case.origin, case.l0, case.jitter_seed))
+    role = O.roles(m, [])
+    st = O.mls_build(m, pos, role, np.zeros_like(pos), case.bc_pressure, case.re_over_l0 * case.l0,
+                     case.l0, case.weight)
+    return case, m, pos, role, st
+
+
+@pytest.mark.parametrize("n", [16, 32])
+def test_bicgstab_matches_dense_solve(n):
+    case, m, pos, role, st = _c0(n)
+    rhs = inputs.manufactured_rhs(pos)
+    g = np.where(role == O.INNER, 0.0, inputs.manufactured_pressure(pos))
+    p, info, (A, b, uidx) = O.solve_ppe(m, st, role, case.bc_pressure, rhs, g, None, 1e-12)
+    dense = np.linalg.solve(A.toarray(), b)
+    assert info.converged and info.true_rel_residual <= 1e-12
+    np.testing.assert_allclose(p[uidx], dense, rtol=0, atol=1e-10 * np.abs(dense).max())
+    # the operator applied through the weights equals the assembled matrix
+    Phi = O.poly_coeffs(m, st, p)
+    lap = O.lap_from_phi(Phi, st.rs, 2)
+    np.testing.assert_allclose(lap[uidx], rhs[uidx], rtol=0, atol=1e-9 * np.abs(rhs).max())
+
+
+def test_manufactured_convergence_order():
+    """p = sin 2 pi x sin 2 pi y: the RMS error of the jittered quadratic MLS
+    Poisson solve falls at order >= 1.5 between the two finest meshes."""
+    errs = []
+    for n in (16, 32, 64):
+        case, m, pos, role, st = _c0(n)
+        rhs = inputs.manufactured_rhs(pos)
+        g = np.where(role == O.INNER, 0.0, inputs.manufactured_pressure(pos))
+        p, info, _ = O.solve_ppe(m, st, role, case.bc_pressure, rhs, g, None, 1e-10)
+        assert info.converged
+        err = p - inputs.manufactured_pressure(pos)
+        errs.append(math.sqrt(np.mean(err[role == O.INNER] ** 2)))
+    orders = [math.log2(errs[i] / errs[i + 1]) for i in range(2)]
+    assert orders[-1] >= 1.5, orders
+
+
+def test_mixed_refinement_reaches_fp64_tolerance():
+    case, m, pos, role, st = _c0(32)
+    rhs = inputs.manufactured_rhs(pos)
+    g = np.where(role == O.INNER, 0.0, inputs.manufactured_pressure(pos))
+    p64, i64, _ = O.solve_ppe(m, st, role, case.bc_pressure, rhs, g, None, 1e-8)
+    pm, im = O.solve_ppe_mixed(m, st, role, case.bc_pressure, rhs, g, None, 1e-8)
+    assert im.converged and im.true_rel_residual <= 1e-8 and im.restarts >= 2
+    assert np.linalg.norm(pm - p64) / np.linalg.norm(p64) < 1e-7
+
+
+def test_remap_identity_and_quadratic_exactness():
+    n, l0 = 12, 0.1
+    m = O.Mesh(2, (n, n), (0.0, 0.0), l0, (True, True))
+    pos = inputs.jittered_positions(m.n, m.origin, l0, seed=3)
+    role = np.full(m.Nc, O.INNER, np.int8)
+    st = O.mls_build(m, pos, role, np.zeros_like(pos), {}, 2.5 * l0, l0)
+    rng = np.random.default_rng(0)
+    u = rng.standard_normal((2, m.Nc))
+    out, _ = O.remap_velocity(m, st, u, pos, pos, role, role, [], [])
+    assert np.array_equal(out, u)
+    # a quadratic field (away from the periodic seam) is shifted exactly
+    cf = rng.standard_normal(6)
+
+    def q(p):
+        return cf[0] + cf[1] * p[0] + cf[2] * p[1] + cf[3] * p[0] ** 2 + cf[4] * p[0] * p[1] + cf[5] * p[1] ** 2
+    mnp = O.Mesh(2, (n, n), (0.0, 0.0), l0)
+    stq = O.mls_build(mnp, pos, role, np.zeros_like(pos), {}, 2.5 * l0, l0)
+    shift = 0.3 * l0 * rng.uniform(-1, 1, (2, m.Nc))
+    ijk = m.ijk(np.arange(m.Nc))
+    ins = np.all((ijk > 0) & (ijk < n - 1), axis=0)
+    uq = np.stack([q(pos), q(pos)])
+    out, _ = O.remap_velocity(mnp, stq, uq, pos, pos + shift, role, role, [], [])
+    np.testing.assert_allclose(out[0, ins], q(pos + shift)[ins], rtol=0, atol=1e-12)
+
+
+def _tgv_decay_ratio(n, t_end):
+    case = configs.c1_taylor_green(n, steps=1)
+    steps = int(round(t_end / case.dt))
+    sim = OracleSim(case)
+    ke0 = sim.kinetic_energy()
+    for _ in range(steps):
+        rec = sim.step()
+        assert rec["converged"]
+    ana = math.exp(-4 * case.nu * steps * case.dt)
+    return (1 - sim.kinetic_energy() / ke0) / (1 - ana)
+
+
+def test_taylor_green_decay_converges_first_order():
+    """KE(t)/KE(0) of the Taylor-Green vortex decays as exp(-4 nu t); the
+    scheme's excess dissipation (first-order MOC, Sec. 3.3) must shrink about
+    linearly with the mesh spacing at fixed time."""
+    t_end = 20 * configs.c1_taylor_green(64).dt
+    r64 = _tgv_decay_ratio(64, t_end)
+    r128 = _tgv_decay_ratio(128, t_end)
+    assert 1.0 < r128 < r64 < 1.5
+    assert (r128 - 1.0) < 0.65 * (r64 - 1.0)
