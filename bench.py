@@ -1,0 +1,134 @@
+"""Benchmark: DP-steps/s of the MCD hot path on one MI355X.
+
+A step is one projection step of the 512x512 periodic Taylor-Green vortex
+(262,144 DPs): DP update and role pass, remap, MLS weights for every DP,
+u* and the PPE right-hand side, Bi-CGSTAB to a true relative residual of
+1e-8 (FP64), projection.  Inputs are resident in HBM before the timed
+region starts.  Prints one JSON line.
+
+--gpus N with N > 1 exits: this build runs on one GPU.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import platform
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DP-steps/s (MLS build + PPE to rel-res 1e-8), plain FP64 vs learned+mixed"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def stage_bytes(n_unknown, dim, value_bytes):
+    """Algorithmic bytes of one S-stage launch (s = r - alpha v; t = A s):
+    A (3^dim planes) + r, v, rhat read once + s, t written once."""
+    slots = 3 ** dim
+    return n_unknown * (slots + 5) * value_bytes
+
+
+def cpu_baseline(case, steps):
+    from threadpoolctl import threadpool_limits
+
+    from oracle.sim import OracleSim
+    with threadpool_limits(limits=1):
+        sim = OracleSim(case)
+        n_active = int((sim.role != 0).sum())
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            sim.step()
+        dt = time.perf_counter() - t0
+    return {"value": n_active * steps / dt, "unit": "DP-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{steps} projection steps of the same {case.n[0]}x{case.n[1]} workload "
+                      f"(after its initial arrangement and weights), numpy/scipy FP64, 1 thread, "
+                      f"{dt:.1f} s; host {platform.processor() or platform.machine()}, "
+                      f"{os.cpu_count()} logical CPUs"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-kernel-timing", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is not built.",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+
+    from paper_2404_17542_amd import configs, mcd
+    from paper_2404_17542_amd.sim import GpuSim
+
+    torch.cuda.set_device(0)
+    mcd.load()
+    case = configs.c1_taylor_green(n=args.n, steps=args.steps)
+    prec = mcd.PREC_FP64 if args.precision == "fp64" else mcd.PREC_FP32_REFINE
+    log(f"setting up {case.name}")
+    sim = GpuSim(case, precision=prec, update_info=False)
+    n_active = sim.n_active()
+    for _ in range(args.warmup):
+        sim.step()
+    torch.cuda.synchronize()
+    log(f"warm-up done ({args.warmup} steps)")
+    if not args.no_kernel_timing:
+        sim.ctx.profile(True)
+        sim.ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for k in range(args.steps):
+        sim.step()
+        if (k + 1) % 25 == 0:
+            log(f"step {k + 1}/{args.steps}")
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    timed = sim.log[-args.steps:]
+    iters = [r["iters"] for r in timed]
+    worst = max(r["rel_res"] for r in timed)
+    assert all(r["converged"] for r in timed), "a PPE solve did not converge"
+    value = n_active * args.steps / elapsed
+    roofline = None
+    if not args.no_kernel_timing:
+        prof = sim.ctx.profile_read(reset=True)
+        sim.ctx.profile(False)
+        n_unknown = n_active - (1 if case.pin_first else 0)
+        vb = 8 if args.precision == "fp64" else 4
+        bytes_per = stage_bytes(n_unknown, case.dim, vb)
+        avg_s = prof["s_ms"] / max(prof["s_n"], 1) * 1e-3
+        achieved = bytes_per / avg_s / 1e9 if avg_s > 0 else None
+        roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                    "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                    "kernel": "k_kS (Bi-CGSTAB S-stage: s = r - alpha v, t = A s, 4 dots)",
+                    "avg_us": avg_s * 1e6, "launches": prof["s_n"], "bytes_per_launch": bytes_per,
+                    "p_stage_avg_us": prof["p_ms"] / max(prof["p_n"], 1) * 1e3}
+    out = {"metric": METRIC, "value": value, "unit": "DP-steps/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
+           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+           "data": "synthetic",
+           "config": {"workload": f"periodic Taylor-Green vortex {case.n[0]}x{case.n[1]}, {n_active} DPs "
+                                  f"(one per cell, +-0.2 l0 jitter), Re=100, dt=0.2 l0, quadratic MLS 3x3, "
+                                  f"PPE Bi-CGSTAB to 1e-8 ({args.precision})",
+                      "dps": n_active, "ppe_iters_per_step": sum(iters) / len(iters), "max_true_rel_res": worst},
+           "roofline": roofline}
+    if not args.no_cpu_baseline and args.cpu_steps > 0:
+        log(f"timing the CPU oracle on {args.cpu_steps} steps")
+        out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

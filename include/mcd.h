@@ -1,0 +1,278 @@
+/*
+ * mcd.h - C ABI of libmcd, the MI355X (gfx950) hot path of the
+ * mesh-constrained discrete point (MCD) method for incompressible flow with
+ * moving boundaries (Matsuda & Ii, arXiv 2404.17542).
+ *
+ * Conventions shared by every call
+ * --------------------------------
+ * - One discrete point (DP) per background-mesh cell (Sec. 2.2).  Cell
+ *   c = i + n0*(j + n1*k) (x fastest); Nc = n0*n1*(n2).
+ * - Per-DP vectors are structure-of-arrays: a "[d][Nc]" argument is d
+ *   consecutive planes of Nc values.
+ * - Every pointer argument is a DEVICE pointer owned by the caller unless its
+ *   comment says "host".  The library never frees caller memory.
+ * - role is int8: -1 inner (Omega_I), 0 void, >= 1 boundary id (mask
+ *   equation of Sec. 2.2).  When the mesh has walls, the outer ring (2D) or
+ *   shell (3D) of cells carries the role mesh.wall_id.
+ * - All work is enqueued on the context's HIP stream and is asynchronous
+ *   unless a call says it synchronises.  Errors detected on the device
+ *   (singular moment matrix, forbidden role transition) are latched in the
+ *   context and returned by the next mcd_sync().
+ * - No call throws; every call returns an mcd_status.  mcd_last_error()
+ *   returns a human-readable message of the last failure.
+ * - The context allocates all workspaces in mcd_create(); later calls do not
+ *   allocate device memory.
+ */
+#ifndef MCD_H
+#define MCD_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    MCD_OK = 0,
+    MCD_ERR_ARG = 1,           /* invalid argument (null pointer, bad size, NaN input ...) */
+    MCD_ERR_SINGULAR = 2,      /* an inner DP's MLS moment matrix is singular */
+    MCD_ERR_NOT_CONVERGED = 3, /* PPE not converged in max_iter; p holds the last iterate */
+    MCD_ERR_BREAKDOWN = 4,     /* Bi-CGSTAB breakdown that restarts could not cure */
+    MCD_ERR_ROLE = 5,          /* forbidden role transition (void <-> inner in one step) */
+    MCD_ERR_HIP = 6,           /* a HIP runtime call failed */
+    MCD_ERR_OOM = 7            /* device allocation failed in mcd_create */
+} mcd_status;
+
+enum { MCD_ROLE_INNER = -1, MCD_ROLE_VOID = 0 };
+enum { MCD_BC_DIRICHLET = 0, MCD_BC_NEUMANN = 1 };
+enum { MCD_WEIGHT_COS2 = 0, MCD_WEIGHT_GAUSS = 1 };
+enum { MCD_PREC_FP64 = 0, MCD_PREC_FP32_REFINE = 1 };
+enum { MCD_GUESS_ZERO = 0, MCD_GUESS_CALLER = 1 };
+
+#define MCD_MAX_IDS 16      /* boundary ids 1 .. 15 */
+#define MCD_MAX_BODIES 8
+#define MCD_MAX_SETS 4      /* stencil-set slots held by a context */
+
+/* Background mesh (Sec. 2.2): uniform spacing l0, dim in {2, 3}. */
+typedef struct {
+    int dim;
+    int n[3];            /* cells per axis (n[2] ignored in 2D) */
+    double origin[3];    /* coordinates of vertex (0,0,0) */
+    double l0;           /* mesh spacing */
+    int periodic[3];     /* 1: axis is periodic */
+    int walls;           /* 1: outer ring/shell of cells are wall DPs */
+    int wall_id;         /* role id of wall DPs (1 .. 15) */
+} mcd_mesh_desc;
+
+/* Method constants (Sec. 2.3, 2.4, 3.2).  Paper values in brackets. */
+typedef struct {
+    int weight_kind;       /* MCD_WEIGHT_COS2 [paper] or MCD_WEIGHT_GAUSS (exp(-4 r^2/re^2)) */
+    double re_over_l0;     /* MLS influence radius r_e / l0 [2.5] */
+    double rs_over_l0;     /* MLS scaling length r_s / l0 [1] */
+    double kappa;          /* relaxation coefficient [1/5] */
+    double band_over_l0;   /* DPs re-positioned within this distance of a body [5] */
+    double eps_relax;      /* relaxation stops when max |dx| <= eps_relax * l0 */
+} mcd_params;
+
+/* Rigid circle (2D) / sphere (3D) at one time level; host memory.
+ * psi = |x - centre| - radius (> 0 in the fluid, Sec. 2.5). */
+typedef struct {
+    int id;              /* role id of its boundary DPs (1 .. 15), != wall_id */
+    double centre[3];
+    double radius;
+    double velocity[3];  /* V of Eq. (velocity_moving_boundary) (translation) */
+    double dvdt[3];      /* dV/dt of Eq. (dvdt_moving_boundary) */
+} mcd_body;
+
+/* Boundary condition of one field per role id (Eq. set: Dirichlet DPs are
+ * value rows, Neumann DPs are normal-derivative rows of the MLS fit). */
+typedef struct {
+    int type[MCD_MAX_IDS];   /* index = role id; MCD_BC_DIRICHLET / MCD_BC_NEUMANN */
+    int pin_first;           /* 1: DP 0 is a known value (periodic PPE) */
+} mcd_bc_table;
+
+typedef struct mcd_ctx mcd_ctx;
+
+/* ---------------------------------------------------------------------
+ * Context
+ * ------------------------------------------------------------------- */
+
+/* Creates a context for one mesh on the current HIP device.  hip_stream is a
+ * hipStream_t (NULL = default stream).  Allocates all workspaces: stencil
+ * storage for MCD_MAX_SETS sets, Krylov vectors and reduction scratch.
+ * Errors: MCD_ERR_ARG for an invalid mesh/params, MCD_ERR_OOM. */
+mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hip_stream,
+                      mcd_ctx** out);
+void mcd_destroy(mcd_ctx* ctx);
+mcd_status mcd_set_stream(mcd_ctx* ctx, void* hip_stream);
+/* Waits for the context's stream and returns latched device errors
+ * (MCD_ERR_SINGULAR, MCD_ERR_ROLE), clearing them. */
+mcd_status mcd_sync(mcd_ctx* ctx);
+const char* mcd_last_error(const mcd_ctx* ctx);
+
+/* ---------------------------------------------------------------------
+ * DP rearrangement and role reassignment (Sec. 2.2 - 2.4)
+ * ------------------------------------------------------------------- */
+
+typedef struct {
+    int sweeps;             /* relaxation sweeps executed */
+    int band_cells;         /* cells in the re-positioned band */
+    int counts[9];          /* transition codes: 3*cls(old)+cls(new), cls: void 0, inner 1, boundary 2 */
+    int role_errors;        /* void->inner plus inner->void transitions */
+} mcd_update_info;
+
+/* One rearrangement at the bodies' new state t^{k+1}:
+ *  1. pos_prev := pos, role_prev := role;
+ *  2. role := mask of each cell from the number of its vertices with
+ *     psi >= 0 (2D: 4 inner, 2-3 boundary, 0-1 void; 3D: 8 / 4-7 / <= 3),
+ *     the boundary id being the body of smallest |psi| at the centroid;
+ *     wall DPs are moved onto the walls; trans := transition code;
+ *  3. up to max_sweeps Jacobi sweeps over the band (non-void, non-wall cells
+ *     whose centroid has min |psi| < band): spring relaxation (Eqs.
+ *     resultant_force .. 1st_intermed_position), SDF projection of body DPs
+ *     (Eq. 2nd_intermed_position) and the mesh-constraint clamp; stops after
+ *     the first sweep whose max |dx| <= eps_relax l0;
+ *  4. normal := unit normal pointing into the fluid at boundary DPs, 0
+ *     elsewhere.
+ * Arrays: pos, pos_prev, normal [dim][Nc] f64; role, role_prev [Nc] i8;
+ * trans [Nc] u8.  bodies: host array of n_bodies (<= MCD_MAX_BODIES).
+ * Bit-exact contract: only + - * / sqrt min max, no contraction.
+ * info (host, nullable): when given the call synchronises and fills it;
+ * role errors are then returned directly as MCD_ERR_ROLE. */
+mcd_status mcd_update_dps(mcd_ctx* ctx, const mcd_body* bodies, int n_bodies, int max_sweeps,
+                          double* pos, int8_t* role, double* pos_prev, int8_t* role_prev,
+                          uint8_t* trans, double* normal, mcd_update_info* info);
+
+/* ---------------------------------------------------------------------
+ * MLS stencils (Sec. 3.2, chi_c = 1)
+ * ------------------------------------------------------------------- */
+
+/* Builds the quadratic MLS weights of every non-void DP into context slot
+ * `set` (0 .. MCD_MAX_SETS-1), minimising J of Eq. (obj_func) with
+ * phi_c fixed: value rows from inner and Dirichlet neighbours of the 3x3
+ * (3x3x3) block, normal-derivative rows from Neumann neighbours (and the DP
+ * itself when it is Neumann), weight cos^2(pi r / 2 r_e) (r <= r_e).
+ * Also builds the PPE matrix of the set (Laplacian weights over unknown
+ * rows/columns: inner and Neumann DPs minus the pinned DP) in FP64 and FP32.
+ * normal: [dim][Nc] (read at Neumann DPs).  bc: host.
+ * Singular inner DPs latch MCD_ERR_SINGULAR (weights set to 0); singular
+ * boundary DPs are counted only. */
+mcd_status mcd_build_stencils(mcd_ctx* ctx, int set, const double* pos, const int8_t* role,
+                              const double* normal, const mcd_bc_table* bc);
+
+/* Copies the weights of a set into caller memory (for inspection / tests):
+ * phi [nb][S+1][Nc] f64 with nb = 5 (2D) / 9 (3D), S = 9 / 27 slots in
+ * lexicographic order (x fastest), slot (S-1)/2 = -sum of value weights,
+ * slot S = the DP's own Neumann row; masks [2][Nc] u32 (bit s of masks[0]:
+ * slot s is a value row; bit s of masks[1]: slot s is a Neumann row, bit S:
+ * own Neumann row); amat [S][Nc] f64 PPE matrix (nullable). */
+mcd_status mcd_get_stencils(mcd_ctx* ctx, int set, double* phi, uint32_t* masks, double* amat);
+
+typedef enum {
+    MCD_OP_PHI = 0,    /* out[nb][Nc]: polynomial coefficients Phi (ncomp must be 1) */
+    MCD_OP_GRAD = 1,   /* out[dim][Nc] = grad in (ncomp 1) */
+    MCD_OP_LAP = 2,    /* out[ncomp][Nc] = laplacian of each component */
+    MCD_OP_DIV = 3,    /* out[1][Nc] = div in (ncomp = dim) */
+    MCD_OP_SHIFT = 4   /* out[ncomp][Nc] = in_c + p(shift/r_s) . Phi (Eq. intrp_chi_1) */
+} mcd_op;
+
+/* Applies set weights to a field: Phi = sum_value W_j (in_j - in_c) +
+ * sum_Neumann W^N_j f_j; derivatives d/dx_a = Phi_a / r_s, laplacian =
+ * sum of the pure second-derivative components / r_s^2.
+ * in [ncomp][Nc]; neumann_f [ncomp][Nc] Neumann data (NULL = 0);
+ * shift [dim][Nc] (MCD_OP_SHIFT only); out as listed per op.
+ * Void DPs get 0. */
+mcd_status mcd_apply(mcd_ctx* ctx, int set, int op, const double* in, int ncomp,
+                     const double* neumann_f, const double* shift, double* out);
+
+/* ---------------------------------------------------------------------
+ * Fractional-step glue (Sec. 3.3, Appendix A)
+ * ------------------------------------------------------------------- */
+
+/* u~ = u^k(x^{k+1}) (Eq. ale_vel, second order = chi_c = 1 Taylor shift)
+ * with the step-k weights of set_prev:
+ *  inner->inner: Eq. (A.1) at the DP itself;
+ *  boundary/void->inner: Eq. (A.2) centred on c' = cell(c + s), s_a =
+ *   sign of (x^k_c - centre^k)_a of its step-k body (support shifted into
+ *   the fluid, Sec. 3.4); if c' was not inner at step k the DP's own step-k
+ *   weights are used;
+ *  -> body boundary: the body's velocity; -> wall or void: 0.
+ * u, out [dim][Nc]; bodies_prev / bodies_new: host arrays (same order). */
+mcd_status mcd_remap(mcd_ctx* ctx, int set_prev, const double* u, const double* pos_prev,
+                     const double* pos, const int8_t* role_prev, const int8_t* role,
+                     const mcd_body* bodies_prev, const mcd_body* bodies_new, int n_bodies,
+                     double* out);
+
+/* u* = F_MOC + nu dt lap u~ at inner DPs (Eq. intermed_vel); F_MOC is the
+ * chi_c = 1 Taylor value of u~ at x - u~ dt with the weights of `set`.
+ * Body DPs take the body velocity, walls and void 0.  ut, ustar [dim][Nc].
+ * rhs [Nc] (nullable) := div u* / dt with the same set (Eq. pressure_poisson);
+ * it is computed in a second pass after u* is complete. */
+mcd_status mcd_advect_diffuse(mcd_ctx* ctx, int set, const double* ut, double dt, double nu,
+                              const int8_t* role, const mcd_body* bodies, int n_bodies,
+                              double* ustar, double* rhs);
+
+/* f = -dV/dt . n at body DPs (Eq. neumann_moving_boundary), 0 elsewhere. */
+mcd_status mcd_neumann_pressure(mcd_ctx* ctx, const int8_t* role, const double* normal,
+                                const mcd_body* bodies, int n_bodies, double* f);
+
+/* u^{k+1} = u* - dt grad P at inner DPs (Eq. projection) with the weights of
+ * pressure set `set` and Neumann data f; body DPs take the body velocity. */
+mcd_status mcd_project(mcd_ctx* ctx, int set, const double* P, const double* f,
+                       const double* ustar, double dt, const int8_t* role,
+                       const mcd_body* bodies, int n_bodies, double* u);
+
+/* ---------------------------------------------------------------------
+ * Pressure Poisson solve (Eq. pressure_poisson, Bi-CGSTAB)
+ * ------------------------------------------------------------------- */
+
+typedef struct {
+    double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2 over unknown rows */
+    int max_iter;        /* total Bi-CGSTAB iterations (all restarts/refinements) */
+    int precision;       /* MCD_PREC_FP64 or MCD_PREC_FP32_REFINE */
+    int guess;           /* MCD_GUESS_ZERO or MCD_GUESS_CALLER (p on entry) */
+    double inner_tol;    /* FP32 inner solve tolerance (FP32_REFINE) */
+    int max_outer;       /* refinement steps (FP32_REFINE) */
+    int check_every;     /* iterations between host convergence checks */
+} mcd_solve_opts;
+
+typedef struct {
+    int iterations;           /* Bi-CGSTAB iterations executed */
+    int restarts;             /* restarts (true-residual check failed or breakdown) */
+    int refinements;          /* FP64 refinement steps (FP32_REFINE) */
+    int converged;
+    double true_rel_residual; /* ||b - A64 x|| / ||b|| in FP64 at exit */
+    double rhs_norm;          /* ||b|| of the effective right-hand side */
+} mcd_solve_info;
+
+/* Solves the PPE of set `set`: unknown rows are inner DPs and Neumann DPs
+ * (collocated with their own Neumann row), Dirichlet DPs (and the pinned DP)
+ * are known.  rhs [Nc]: right-hand side at unknown rows; neumann_f [Nc]:
+ * Neumann data (NULL = 0); p [Nc]: on entry the known values at known DPs
+ * (and the initial guess at unknown DPs for MCD_GUESS_CALLER); on exit the
+ * solution at unknown DPs (known DPs unchanged).  Synchronises; info is host
+ * memory.  Returns MCD_ERR_NOT_CONVERGED if the tolerance was not met. */
+mcd_status mcd_solve_ppe(mcd_ctx* ctx, int set, const double* rhs, const double* neumann_f,
+                         double* p, const mcd_solve_opts* opts, mcd_solve_info* info);
+
+/* ---------------------------------------------------------------------
+ * Kernel timing (measurement aid)
+ * ------------------------------------------------------------------- */
+
+/* enable = 1: every P-stage and S-stage kernel launch of later
+ * mcd_solve_ppe calls is bracketed by HIP events on the context's stream
+ * (the events are created on the first enable; at most 4096 iterations are
+ * timed per restart cycle).  Launches that only observed convergence and
+ * returned are excluded.  enable = 0 stops recording. */
+mcd_status mcd_profile(mcd_ctx* ctx, int enable);
+/* Accumulated milliseconds and launch counts of the working P- and S-stage
+ * launches since the last reset (all host pointers). */
+mcd_status mcd_profile_read(mcd_ctx* ctx, double* ms_p, long long* n_p, double* ms_s, long long* n_s,
+                            int reset);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MCD_H */

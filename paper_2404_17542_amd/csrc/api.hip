@@ -1,0 +1,474 @@
+// C ABI of libmcd: argument validation, context state, launches.
+#include <math.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <algorithm>
+#include <string>
+
+#include "common.h"
+
+using namespace mcd;
+
+namespace {
+
+enum {
+    CNT_TRANS = 0,       // [0..8] transition histogram, [9] band cells, [10] role errors
+    CNT_MLS = 16,        // [16] singular inner, [17] singular other, [18] first singular inner DP
+    CNT_LATCH_ROLE = 32,
+    CNT_LATCH_SING = 33,
+    CNT_REMAP = 40,      // [40] shifted, [41] fallback
+    CNT_BAD = 48,        // non-finite PPE right-hand side
+    CNT_N = 64
+};
+
+struct SetStore {
+    SetDev dev{};
+    int built = 0;
+};
+
+}  // namespace
+
+struct mcd_ctx {
+    mcd_mesh_desc desc{};
+    mcd_params prm{};
+    MeshDev m{};
+    hipStream_t stream = nullptr;
+    int dim = 2, NB = 5, S = 9;
+    size_t Nc = 0;
+    SetStore sets[MCD_MAX_SETS];
+    double* pos_tmp = nullptr;
+    uint8_t* band = nullptr;
+    unsigned long long* dmax = nullptr;
+    int max_sweeps_alloc = 0;
+    int* relax_state = nullptr;
+    int* cnt = nullptr;
+    int* cnt_host = nullptr;    // pinned
+    KrylovWork* kw = nullptr;
+    // host constants of the arrangement (computed once, used identically by every call)
+    double kl0 = 0, spring[4] = {0, 0, 0, 0}, eps_l0 = 0, band_l0 = 0, re = 0, rs = 0;
+    std::string err;
+};
+
+static mcd_status fail(mcd_ctx* c, mcd_status s, const char* fmt, const char* detail = "") {
+    if (c) {
+        char buf[512];
+        snprintf(buf, sizeof(buf), fmt, detail);
+        c->err = buf;
+    }
+    return s;
+}
+
+static mcd_status hipfail(mcd_ctx* c, hipError_t e, const char* where) {
+    if (c) c->err = std::string(where) + ": " + hipGetErrorString(e);
+    return MCD_ERR_HIP;
+}
+
+#define HIPCHK(ctx, expr, where)                    \
+    do {                                            \
+        hipError_t _e = (expr);                     \
+        if (_e != hipSuccess) return hipfail(ctx, _e, where); \
+    } while (0)
+
+static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* out) {
+    *out = BodiesDev{};
+    if (n < 0 || n > MCD_MAX_BODIES || (n > 0 && !bodies)) return false;
+    // ascending id order: ties of the nearest-body rule go to the lower id
+    int order[MCD_MAX_BODIES];
+    for (int i = 0; i < n; ++i) order[i] = i;
+    std::sort(order, order + n, [&](int a, int b) { return bodies[a].id < bodies[b].id; });
+    out->n = n;
+    for (int k = 0; k < n; ++k) {
+        const mcd_body& b = bodies[order[k]];
+        if (b.id < 1 || b.id >= MCD_MAX_IDS || (c->desc.walls && b.id == c->desc.wall_id)) return false;
+        if (!(b.radius > 0) || !isfinite(b.radius)) return false;
+        out->id[k] = b.id;
+        for (int a = 0; a < 3; ++a) {
+            if (!isfinite(b.centre[a]) || !isfinite(b.velocity[a]) || !isfinite(b.dvdt[a])) return false;
+            out->c[k][a] = b.centre[a];
+            out->vel[k][a] = b.velocity[a];
+            out->dvdt[k][a] = b.dvdt[a];
+        }
+        out->R[k] = b.radius;
+        out->R2[k] = b.radius * b.radius;
+    }
+    return true;
+}
+
+static bool make_bc(const mcd_bc_table* bc, BcDev* out) {
+    *out = BcDev{};
+    if (!bc) return false;
+    for (int i = 0; i < MCD_MAX_IDS; ++i) {
+        if (bc->type[i] != MCD_BC_DIRICHLET && bc->type[i] != MCD_BC_NEUMANN) return false;
+        out->type[i] = bc->type[i];
+    }
+    out->pin_first = bc->pin_first ? 1 : 0;
+    return true;
+}
+
+static bool valid_set(mcd_ctx* c, int set, bool need_built) {
+    return c && set >= 0 && set < MCD_MAX_SETS && (!need_built || c->sets[set].built);
+}
+
+extern "C" {
+
+mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hip_stream, mcd_ctx** out) {
+    if (!mesh || !prm || !out) return MCD_ERR_ARG;
+    *out = nullptr;
+    const int dim = mesh->dim;
+    if (dim != 2 && dim != 3) return MCD_ERR_ARG;
+    long long Nc = 1;
+    for (int a = 0; a < dim; ++a) {
+        if (mesh->n[a] < 3 || mesh->n[a] > (1 << 16)) return MCD_ERR_ARG;
+        Nc *= mesh->n[a];
+    }
+    if (Nc > (1LL << 30)) return MCD_ERR_ARG;
+    if (!(mesh->l0 > 0) || !isfinite(mesh->l0)) return MCD_ERR_ARG;
+    if (mesh->walls && (mesh->wall_id < 1 || mesh->wall_id >= MCD_MAX_IDS)) return MCD_ERR_ARG;
+    if (!(prm->re_over_l0 > 0) || !(prm->rs_over_l0 > 0) || !(prm->kappa > 0) || !(prm->band_over_l0 >= 0) ||
+        !(prm->eps_relax >= 0) || (prm->weight_kind != MCD_WEIGHT_COS2 && prm->weight_kind != MCD_WEIGHT_GAUSS))
+        return MCD_ERR_ARG;
+    mcd_ctx* c = new mcd_ctx();
+    c->desc = *mesh;
+    c->prm = *prm;
+    c->stream = (hipStream_t)hip_stream;
+    c->dim = dim;
+    c->NB = dim == 2 ? 5 : 9;
+    c->S = dim == 2 ? 9 : 27;
+    c->Nc = (size_t)Nc;
+    MeshDev& m = c->m;
+    m.dim = dim;
+    m.Nc = (int)Nc;
+    m.l0 = mesh->l0;
+    for (int a = 0; a < 3; ++a) {
+        m.n[a] = a < dim ? mesh->n[a] : 1;
+        m.origin[a] = a < dim ? mesh->origin[a] : 0.0;
+        m.periodic[a] = a < dim ? (mesh->periodic[a] ? 1 : 0) : 0;
+        m.length[a] = (double)m.n[a] * mesh->l0;
+    }
+    m.walls = mesh->walls ? 1 : 0;
+    m.wall_id = mesh->wall_id;
+    const double l0 = mesh->l0;
+    c->kl0 = prm->kappa * l0;
+    c->spring[0] = 0.0;
+    c->spring[1] = l0;
+    c->spring[2] = sqrt(2.0) * l0;
+    c->spring[3] = sqrt(3.0) * l0;
+    c->eps_l0 = prm->eps_relax * l0;
+    c->band_l0 = prm->band_over_l0 * l0;
+    c->re = prm->re_over_l0 * l0;
+    c->rs = prm->rs_over_l0 * l0;
+
+    auto alloc = [&](void** p, size_t bytes) {
+        hipError_t e = hipMalloc(p, bytes);
+        if (e == hipSuccess) e = hipMemset(*p, 0, bytes);
+        return e;
+    };
+    hipError_t e = hipSuccess;
+    const size_t N = c->Nc;
+    for (int s = 0; s < MCD_MAX_SETS && e == hipSuccess; ++s) {
+        SetDev& d = c->sets[s].dev;
+        d.rs = c->rs;
+        e = alloc((void**)&d.phi, (size_t)c->NB * (c->S + 1) * N * sizeof(double));
+        if (e == hipSuccess) e = alloc((void**)&d.vmask, N * sizeof(uint32_t));
+        if (e == hipSuccess) e = alloc((void**)&d.nmask, N * sizeof(uint32_t));
+        if (e == hipSuccess) e = alloc((void**)&d.amat, (size_t)c->S * N * sizeof(double));
+        if (e == hipSuccess) e = alloc((void**)&d.amat32, (size_t)c->S * N * sizeof(float));
+        if (e == hipSuccess) e = alloc((void**)&d.unknown, N);
+    }
+    c->max_sweeps_alloc = 4096;
+    if (e == hipSuccess) e = alloc((void**)&c->pos_tmp, (size_t)dim * N * sizeof(double));
+    if (e == hipSuccess) e = alloc((void**)&c->band, N);
+    if (e == hipSuccess) e = alloc((void**)&c->dmax, (size_t)c->max_sweeps_alloc * sizeof(unsigned long long));
+    if (e == hipSuccess) e = alloc((void**)&c->relax_state, 4 * sizeof(int));
+    if (e == hipSuccess) e = alloc((void**)&c->cnt, CNT_N * sizeof(int));
+    if (e == hipSuccess) e = hipHostMalloc((void**)&c->cnt_host, CNT_N * sizeof(int), hipHostMallocDefault);
+    if (e == hipSuccess) e = krylov_alloc((int)N, &c->kw);
+    if (e == hipSuccess) e = hipDeviceSynchronize();
+    if (e != hipSuccess) {
+        mcd_destroy(c);
+        return e == hipErrorOutOfMemory ? MCD_ERR_OOM : MCD_ERR_HIP;
+    }
+    *out = c;
+    return MCD_OK;
+}
+
+void mcd_destroy(mcd_ctx* c) {
+    if (!c) return;
+    (void)hipStreamSynchronize(c->stream);
+    for (int s = 0; s < MCD_MAX_SETS; ++s) {
+        SetDev& d = c->sets[s].dev;
+        void* ptrs[6] = {d.phi, d.vmask, d.nmask, d.amat, d.amat32, d.unknown};
+        for (void* p : ptrs)
+            if (p) (void)hipFree(p);
+    }
+    void* ptrs[5] = {c->pos_tmp, c->band, c->dmax, c->relax_state, c->cnt};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (c->cnt_host) (void)hipHostFree(c->cnt_host);
+    krylov_free(c->kw);
+    delete c;
+}
+
+mcd_status mcd_set_stream(mcd_ctx* c, void* hip_stream) {
+    if (!c) return MCD_ERR_ARG;
+    c->stream = (hipStream_t)hip_stream;
+    return MCD_OK;
+}
+
+const char* mcd_last_error(const mcd_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+mcd_status mcd_sync(mcd_ctx* c) {
+    if (!c) return MCD_ERR_ARG;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "mcd_sync");
+    HIPCHK(c, hipMemcpy(c->cnt_host, c->cnt, CNT_N * sizeof(int), hipMemcpyDeviceToHost), "mcd_sync copy");
+    const int role_err = c->cnt_host[CNT_LATCH_ROLE], sing = c->cnt_host[CNT_LATCH_SING];
+    HIPCHK(c, launch_fill_i32(c->cnt + CNT_LATCH_ROLE, 2, 0, c->stream), "mcd_sync clear");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "mcd_sync clear");
+    if (sing) {
+        char buf[64];
+        snprintf(buf, sizeof(buf), "%d", sing);
+        return fail(c, MCD_ERR_SINGULAR, "singular MLS moment matrix at %s inner DPs", buf);
+    }
+    if (role_err) {
+        char buf[64];
+        snprintf(buf, sizeof(buf), "%d", role_err);
+        return fail(c, MCD_ERR_ROLE, "%s void<->inner role transitions", buf);
+    }
+    return MCD_OK;
+}
+
+mcd_status mcd_update_dps(mcd_ctx* c, const mcd_body* bodies, int n_bodies, int max_sweeps, double* pos,
+                          int8_t* role, double* pos_prev, int8_t* role_prev, uint8_t* trans, double* normal,
+                          mcd_update_info* info) {
+    if (!c) return MCD_ERR_ARG;
+    if (!pos || !role || !pos_prev || !role_prev || !trans || !normal)
+        return fail(c, MCD_ERR_ARG, "mcd_update_dps: null array%s");
+    if (max_sweeps < 0 || max_sweeps > c->max_sweeps_alloc)
+        return fail(c, MCD_ERR_ARG, "mcd_update_dps: max_sweeps out of range%s");
+    BodiesDev B;
+    if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_update_dps: invalid bodies%s");
+    const MeshDev& m = c->m;
+    hipStream_t st = c->stream;
+    const size_t N = c->Nc;
+    HIPCHK(c, launch_fill_i32(c->cnt + CNT_TRANS, 11, 0, st), "fill");
+    HIPCHK(c, launch_roles(m, B, c->band_l0, role, role_prev, pos, pos_prev, trans, c->band, c->cnt + CNT_TRANS,
+                           c->cnt + CNT_LATCH_ROLE, st),
+           "roles");
+    // bounding box of the band: cells whose centroid lies within R + band of a body
+    int lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0}, bn[3] = {1, 1, 1};
+    bool any = false;
+    for (int b = 0; b < B.n; ++b) {
+        int l[3] = {0, 0, 0}, h[3] = {0, 0, 0};
+        for (int a = 0; a < c->dim; ++a) {
+            const double ext = B.R[b] + c->band_l0 + m.l0;
+            l[a] = (int)floor((B.c[b][a] - ext - m.origin[a]) / m.l0) - 1;
+            h[a] = (int)floor((B.c[b][a] + ext - m.origin[a]) / m.l0) + 1;
+            l[a] = std::max(l[a], 0);
+            h[a] = std::min(h[a], m.n[a] - 1);
+        }
+        for (int a = 0; a < c->dim; ++a) {
+            lo[a] = any ? std::min(lo[a], l[a]) : l[a];
+            hi[a] = any ? std::max(hi[a], h[a]) : h[a];
+        }
+        any = true;
+    }
+    if (any)
+        for (int a = 0; a < c->dim; ++a) bn[a] = std::max(0, hi[a] - lo[a] + 1);
+    else
+        bn[0] = 0;
+    const bool box = bn[0] > 0 && bn[1] > 0 && bn[2] > 0;
+    HIPCHK(c, launch_fill_i32(c->relax_state, 4, 0, st), "fill");
+    if (max_sweeps > 0) {
+        HIPCHK(c, launch_fill_u64(c->dmax, max_sweeps, 0ull, st), "fill");
+        HIPCHK(c, hipMemcpyAsync(c->pos_tmp, pos, (size_t)c->dim * N * sizeof(double), hipMemcpyDeviceToDevice, st),
+               "copy");
+    }
+    for (int s = 0; s < max_sweeps; ++s) {
+        const double* pin = (s & 1) ? c->pos_tmp : pos;
+        double* pout = (s & 1) ? pos : c->pos_tmp;
+        // an empty band (no body) still runs one sweep over nothing, as in the definition
+        HIPCHK(c, launch_relax(m, B, c->kl0, c->spring, c->eps_l0, role, c->band, pin, pout, lo, box ? bn : lo, c->dmax,
+                               s, c->relax_state, st),
+               "relax");
+    }
+    if (max_sweeps & 1) HIPCHK(c, launch_copy_band(m, c->band, c->pos_tmp, pos, lo, bn, st), "copy back");
+    HIPCHK(c, launch_normals(m, B, role, pos, normal, st), "normals");
+    if (info) {
+        HIPCHK(c, hipStreamSynchronize(st), "mcd_update_dps");
+        int h[16];
+        int rs[4];
+        HIPCHK(c, hipMemcpy(h, c->cnt + CNT_TRANS, 11 * sizeof(int), hipMemcpyDeviceToHost), "copy");
+        HIPCHK(c, hipMemcpy(rs, c->relax_state, 4 * sizeof(int), hipMemcpyDeviceToHost), "copy");
+        for (int k = 0; k < 9; ++k) info->counts[k] = h[k];
+        info->band_cells = h[9];
+        info->role_errors = h[10];
+        info->sweeps = rs[1];
+        if (h[10]) {
+            HIPCHK(c, launch_fill_i32(c->cnt + CNT_LATCH_ROLE, 1, 0, st), "fill");
+            return fail(c, MCD_ERR_ROLE, "mcd_update_dps: void<->inner role transition%s");
+        }
+    }
+    return MCD_OK;
+}
+
+mcd_status mcd_build_stencils(mcd_ctx* c, int set, const double* pos, const int8_t* role, const double* normal,
+                              const mcd_bc_table* bc) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set, false)) return fail(c, MCD_ERR_ARG, "mcd_build_stencils: bad set index%s");
+    if (!pos || !role || !normal) return fail(c, MCD_ERR_ARG, "mcd_build_stencils: null array%s");
+    BcDev b;
+    if (!make_bc(bc, &b)) return fail(c, MCD_ERR_ARG, "mcd_build_stencils: invalid bc table%s");
+    HIPCHK(c, launch_fill_i32(c->cnt + CNT_MLS, 2, 0, c->stream), "fill");
+    HIPCHK(c, launch_fill_i32(c->cnt + CNT_MLS + 2, 1, 0x7fffffff, c->stream), "fill");
+    HIPCHK(c, launch_mls_build(c->m, pos, role, normal, b, c->re, c->rs, c->prm.weight_kind, c->sets[set].dev,
+                               c->cnt + CNT_MLS, c->cnt + CNT_LATCH_SING, c->stream),
+           "mls_build");
+    c->sets[set].built = 1;
+    return MCD_OK;
+}
+
+mcd_status mcd_get_stencils(mcd_ctx* c, int set, double* phi, uint32_t* masks, double* amat) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_get_stencils: set not built%s");
+    const size_t N = c->Nc;
+    const SetDev& d = c->sets[set].dev;
+    hipStream_t st = c->stream;
+    if (phi)
+        HIPCHK(c, hipMemcpyAsync(phi, d.phi, (size_t)c->NB * (c->S + 1) * N * sizeof(double), hipMemcpyDeviceToDevice, st),
+               "copy");
+    if (masks) {
+        HIPCHK(c, hipMemcpyAsync(masks, d.vmask, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy");
+        HIPCHK(c, hipMemcpyAsync(masks + N, d.nmask, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy");
+    }
+    if (amat)
+        HIPCHK(c, hipMemcpyAsync(amat, d.amat, (size_t)c->S * N * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+    return MCD_OK;
+}
+
+mcd_status mcd_apply(mcd_ctx* c, int set, int op, const double* in, int ncomp, const double* neumann_f,
+                     const double* shift, double* out) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_apply: set not built%s");
+    if (!in || !out) return fail(c, MCD_ERR_ARG, "mcd_apply: null array%s");
+    switch (op) {
+        case MCD_OP_PHI:
+        case MCD_OP_GRAD:
+            if (ncomp != 1) return fail(c, MCD_ERR_ARG, "mcd_apply: PHI/GRAD need ncomp = 1%s");
+            break;
+        case MCD_OP_LAP:
+            if (ncomp < 1 || ncomp > 16) return fail(c, MCD_ERR_ARG, "mcd_apply: bad ncomp%s");
+            break;
+        case MCD_OP_DIV:
+            if (ncomp != c->dim) return fail(c, MCD_ERR_ARG, "mcd_apply: DIV needs ncomp = dim%s");
+            break;
+        case MCD_OP_SHIFT:
+            if (ncomp < 1 || ncomp > 16 || !shift) return fail(c, MCD_ERR_ARG, "mcd_apply: SHIFT needs shift%s");
+            break;
+        default:
+            return fail(c, MCD_ERR_ARG, "mcd_apply: unknown op%s");
+    }
+    HIPCHK(c, launch_apply(c->m, c->sets[set].dev, op, in, ncomp, neumann_f, shift, out, 1.0, c->stream), "apply");
+    return MCD_OK;
+}
+
+mcd_status mcd_remap(mcd_ctx* c, int set_prev, const double* u, const double* pos_prev, const double* pos,
+                     const int8_t* role_prev, const int8_t* role, const mcd_body* bodies_prev,
+                     const mcd_body* bodies_new, int n_bodies, double* out) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set_prev, true)) return fail(c, MCD_ERR_ARG, "mcd_remap: set not built%s");
+    if (!u || !pos_prev || !pos || !role_prev || !role || !out || u == out)
+        return fail(c, MCD_ERR_ARG, "mcd_remap: null or aliased array%s");
+    BodiesDev Bp, Bn;
+    if (!make_bodies(c, bodies_prev, n_bodies, &Bp) || !make_bodies(c, bodies_new, n_bodies, &Bn))
+        return fail(c, MCD_ERR_ARG, "mcd_remap: invalid bodies%s");
+    HIPCHK(c, launch_fill_i32(c->cnt + CNT_REMAP, 2, 0, c->stream), "fill");
+    HIPCHK(c, launch_remap(c->m, c->sets[set_prev].dev, u, pos_prev, pos, role_prev, role, Bp, Bn, out,
+                           c->cnt + CNT_REMAP, c->stream),
+           "remap");
+    return MCD_OK;
+}
+
+mcd_status mcd_advect_diffuse(mcd_ctx* c, int set, const double* ut, double dt, double nu, const int8_t* role,
+                              const mcd_body* bodies, int n_bodies, double* ustar, double* rhs) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: set not built%s");
+    if (!ut || !role || !ustar || ut == ustar) return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: bad arrays%s");
+    if (!(dt > 0) || !(nu >= 0) || !isfinite(dt) || !isfinite(nu))
+        return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: bad dt/nu%s");
+    BodiesDev B;
+    if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: invalid bodies%s");
+    HIPCHK(c, launch_advect_diffuse(c->m, c->sets[set].dev, ut, dt, nu, role, B, ustar, c->stream), "advect");
+    if (rhs)
+        HIPCHK(c, launch_apply(c->m, c->sets[set].dev, MCD_OP_DIV, ustar, c->dim, nullptr, nullptr, rhs, 1.0 / dt,
+                               c->stream),
+               "rhs");
+    return MCD_OK;
+}
+
+mcd_status mcd_neumann_pressure(mcd_ctx* c, const int8_t* role, const double* normal, const mcd_body* bodies,
+                                int n_bodies, double* f) {
+    if (!c) return MCD_ERR_ARG;
+    if (!role || !normal || !f) return fail(c, MCD_ERR_ARG, "mcd_neumann_pressure: null array%s");
+    BodiesDev B;
+    if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_neumann_pressure: invalid bodies%s");
+    HIPCHK(c, launch_neumann_pressure(c->m, role, normal, B, f, c->stream), "neumann");
+    return MCD_OK;
+}
+
+mcd_status mcd_project(mcd_ctx* c, int set, const double* P, const double* f, const double* ustar, double dt,
+                       const int8_t* role, const mcd_body* bodies, int n_bodies, double* u) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_project: set not built%s");
+    if (!P || !ustar || !role || !u || u == ustar) return fail(c, MCD_ERR_ARG, "mcd_project: bad arrays%s");
+    if (!(dt > 0) || !isfinite(dt)) return fail(c, MCD_ERR_ARG, "mcd_project: bad dt%s");
+    BodiesDev B;
+    if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_project: invalid bodies%s");
+    HIPCHK(c, launch_project(c->m, c->sets[set].dev, P, f, ustar, dt, role, B, u, c->stream), "project");
+    return MCD_OK;
+}
+
+mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* neumann_f, double* p,
+                         const mcd_solve_opts* opts, mcd_solve_info* info) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: set not built%s");
+    if (!rhs || !p || !opts || !info) return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: null argument%s");
+    if (!(opts->tol > 0) || opts->max_iter < 1 ||
+        (opts->precision != MCD_PREC_FP64 && opts->precision != MCD_PREC_FP32_REFINE) ||
+        (opts->guess != MCD_GUESS_ZERO && opts->guess != MCD_GUESS_CALLER))
+        return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid options%s");
+    if (opts->precision == MCD_PREC_FP32_REFINE && (!(opts->inner_tol > 0) || opts->max_outer < 1))
+        return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid refinement options%s");
+    SolveParams sp{opts->tol, opts->max_iter, opts->precision, opts->guess == MCD_GUESS_CALLER, opts->inner_tol,
+                   opts->max_outer, opts->check_every};
+    HIPCHK(c, launch_fill_i32(c->cnt + CNT_BAD, 1, 0, c->stream), "fill");
+    SolveOut o;
+    HIPCHK(c, solve_ppe_impl(c->m, c->sets[set].dev, *c->kw, rhs, neumann_f, p, sp, &o, c->cnt + CNT_BAD, c->stream),
+           "solve");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "solve");
+    int bad = 0;
+    HIPCHK(c, hipMemcpy(&bad, c->cnt + CNT_BAD, sizeof(int), hipMemcpyDeviceToHost), "copy");
+    info->iterations = o.iterations;
+    info->restarts = o.restarts;
+    info->refinements = o.refinements;
+    info->converged = o.converged;
+    info->true_rel_residual = o.rel;
+    info->rhs_norm = o.bnorm;
+    if (bad) return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: non-finite right-hand side%s");
+    if (!o.converged) return fail(c, MCD_ERR_NOT_CONVERGED, "mcd_solve_ppe: tolerance not reached%s");
+    return MCD_OK;
+}
+
+mcd_status mcd_profile(mcd_ctx* c, int enable) {
+    if (!c) return MCD_ERR_ARG;
+    HIPCHK(c, krylov_profile(c->kw, enable ? 1 : 0), "mcd_profile");
+    return MCD_OK;
+}
+
+mcd_status mcd_profile_read(mcd_ctx* c, double* ms_p, long long* n_p, double* ms_s, long long* n_s, int reset) {
+    if (!c || !ms_p || !n_p || !ms_s || !n_s) return MCD_ERR_ARG;
+    krylov_profile_read(c->kw, ms_p, n_p, ms_s, n_s, reset);
+    return MCD_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,293 @@
+// Applying MLS weights (Eq. intrp_chi_1 and its derivatives) and the
+// fractional-step glue of Sec. 3.3 / Appendix A.  One thread per DP; the
+// weight planes are read coalesced, neighbour field values hit L1/L2.
+#include "common.h"
+
+namespace mcd {
+
+// Phi at cell c for scalar field fld: sum_value W_j (f_j - f_c) + sum_Neumann W^N_j g_j.
+template <int DIM>
+__device__ __forceinline__ void poly_at(const MeshDev& m, const SetDev& st, int c, const int ijk[3],
+                                        const double* __restrict__ fld, const double* __restrict__ fneu, double* Phi) {
+    constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
+    const size_t Nc = (size_t)m.Nc;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) Phi[q] = 0.0;
+    const uint32_t vm = st.vmask[c], nm = st.nmask[c];
+    if ((vm | nm) == 0) return;
+    const double fc = fld[c];
+    for (int s = 0; s < S; ++s) {
+        if (s == CEN) continue;
+        const bool v = (vm >> s) & 1u;
+        const bool n = fneu && ((nm >> s) & 1u);
+        if (!v && !n) continue;
+        int j;
+        double sh[3];
+        neighbour<DIM>(m, ijk, s, j, sh);
+        const double d = v ? fld[j] - fc : fneu[j];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Phi[q] += st.phi[((size_t)q * (S + 1) + s) * Nc + c] * d;
+    }
+    if (fneu && ((nm >> S) & 1u)) {
+        const double fcn = fneu[c];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Phi[q] += st.phi[((size_t)q * (S + 1) + S) * Nc + c] * fcn;
+    }
+}
+
+template <int DIM>
+__device__ __forceinline__ double taylor(double fc, const double* Phi, const double* shift, double rs) {
+    constexpr int NB = Dims<DIM>::NB;
+    double X[DIM], p[NB];
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) X[a] = shift[a] / rs;
+    basis<DIM>(X, p);
+    double acc = fc;
+#pragma unroll
+    for (int q = 0; q < NB; ++q) acc += p[q] * Phi[q];
+    return acc;
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_apply(MeshDev m, SetDev st, int op, const double* __restrict__ in,
+                                                  int ncomp, const double* __restrict__ fneu,
+                                                  const double* __restrict__ shift, double* __restrict__ out,
+                                                  double scale) {
+    constexpr int NB = Dims<DIM>::NB;
+    const size_t Nc = (size_t)m.Nc;
+    const double rs = st.rs;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        int ijk[3];
+        cell_ijk(m, c, ijk);
+        double Phi[NB];
+        if (op == MCD_OP_PHI || op == MCD_OP_GRAD) {
+            poly_at<DIM>(m, st, c, ijk, in, fneu, Phi);
+            if (op == MCD_OP_PHI) {
+#pragma unroll
+                for (int q = 0; q < NB; ++q) out[q * Nc + c] = Phi[q] * scale;
+            } else {
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) out[a * Nc + c] = Phi[a] / rs * scale;
+            }
+        } else if (op == MCD_OP_DIV) {
+            double acc = 0.0;
+            for (int a = 0; a < DIM; ++a) {
+                poly_at<DIM>(m, st, c, ijk, in + a * Nc, fneu ? fneu + a * Nc : nullptr, Phi);
+                acc += Phi[a] / rs;
+            }
+            out[c] = acc * scale;
+        } else if (op == MCD_OP_LAP) {
+            for (int k = 0; k < ncomp; ++k) {
+                poly_at<DIM>(m, st, c, ijk, in + k * Nc, fneu ? fneu + k * Nc : nullptr, Phi);
+                out[k * Nc + c] = diag2<DIM>(Phi) / (rs * rs) * scale;
+            }
+        } else {  // MCD_OP_SHIFT
+            double sv[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) sv[a] = shift[a * Nc + c];
+            for (int k = 0; k < ncomp; ++k) {
+                poly_at<DIM>(m, st, c, ijk, in + k * Nc, fneu ? fneu + k * Nc : nullptr, Phi);
+                out[k * Nc + c] = taylor<DIM>(in[k * Nc + c], Phi, sv, rs);
+            }
+        }
+    }
+}
+
+// Appendix A remap: u~ = u^k(x^{k+1}) with the step-k weights.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const double* __restrict__ u,
+                                                  const double* __restrict__ pos_prev,
+                                                  const double* __restrict__ pos,
+                                                  const int8_t* __restrict__ role_prev,
+                                                  const int8_t* __restrict__ role, BodiesDev Bp, BodiesDev Bn,
+                                                  double* __restrict__ out, int* counters) {
+    constexpr int NB = Dims<DIM>::NB;
+    const size_t Nc = (size_t)m.Nc;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        const int rn = role[c];
+        if (rn == MCD_ROLE_INNER) {
+            int src = c;
+            const int rp = role_prev[c];
+            if (rp != MCD_ROLE_INNER) {
+                int ijk[3];
+                cell_ijk(m, c, ijk);
+                int off[3] = {0, 0, 0};
+                for (int b = 0; b < Bp.n; ++b) {
+                    if (rp != Bp.id[b]) continue;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        const double g = pos_prev[a * Nc + c] - Bp.c[b][a];
+                        off[a] = g > 0.0 ? 1 : (g < 0.0 ? -1 : 0);
+                    }
+                }
+                bool ok = true;
+                int cp = 0, stride = 1;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) {
+                    const int ii = ijk[a] + off[a];
+                    ok = ok && ii >= 0 && ii < m.n[a];
+                    cp += (ii < 0 ? 0 : (ii >= m.n[a] ? m.n[a] - 1 : ii)) * stride;
+                    stride *= m.n[a];
+                }
+                const bool good = ok && role_prev[cp] == MCD_ROLE_INNER;
+                src = good ? cp : c;
+                atomicAdd(&counters[good ? 0 : 1], 1);
+            }
+            int sijk[3];
+            cell_ijk(m, src, sijk);
+            double dx[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) dx[a] = pos[a * Nc + c] - pos_prev[a * Nc + src];
+            for (int a = 0; a < DIM; ++a) {
+                double Phi[NB];
+                poly_at<DIM>(m, sp, src, sijk, u + a * Nc, nullptr, Phi);
+                out[a * Nc + c] = taylor<DIM>(u[a * Nc + src], Phi, dx, sp.rs);
+            }
+        } else {
+            double v[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) v[a] = 0.0;
+            for (int b = 0; b < Bn.n; ++b)
+                if (rn == Bn.id[b]) {
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) v[a] = Bn.vel[b][a];
+                }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) out[a * Nc + c] = v[a];
+        }
+    }
+}
+
+// u* = F_MOC + nu dt lap u~ (Eq. intermed_vel) at inner DPs.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_advect_diffuse(MeshDev m, SetDev st, const double* __restrict__ ut,
+                                                           double dt, double nu, const int8_t* __restrict__ role,
+                                                           BodiesDev B, double* __restrict__ ustar) {
+    constexpr int NB = Dims<DIM>::NB;
+    const size_t Nc = (size_t)m.Nc;
+    const double rs = st.rs;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        const int rn = role[c];
+        if (rn == MCD_ROLE_INNER) {
+            int ijk[3];
+            cell_ijk(m, c, ijk);
+            double sh[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) sh[a] = -ut[a * Nc + c] * dt;
+            for (int a = 0; a < DIM; ++a) {
+                double Phi[NB];
+                poly_at<DIM>(m, st, c, ijk, ut + a * Nc, nullptr, Phi);
+                const double fm = taylor<DIM>(ut[a * Nc + c], Phi, sh, rs);
+                ustar[a * Nc + c] = fm + nu * dt * (diag2<DIM>(Phi) / (rs * rs));
+            }
+        } else {
+            double v[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) v[a] = 0.0;
+            for (int b = 0; b < B.n; ++b)
+                if (rn == B.id[b]) {
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) v[a] = B.vel[b][a];
+                }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) ustar[a * Nc + c] = v[a];
+        }
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_neumann_pressure(MeshDev m, const int8_t* __restrict__ role,
+                                                             const double* __restrict__ normal, BodiesDev B,
+                                                             double* __restrict__ f) {
+    const size_t Nc = (size_t)m.Nc;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        const int rn = role[c];
+        double v = 0.0;
+        for (int b = 0; b < B.n; ++b)
+            if (rn == B.id[b]) {
+                double acc = 0.0;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) acc += B.dvdt[b][a] * normal[a * Nc + c];
+                v = -acc;
+            }
+        f[c] = v;
+    }
+}
+
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_project(MeshDev m, SetDev st, const double* __restrict__ P,
+                                                    const double* __restrict__ f, const double* __restrict__ ustar,
+                                                    double dt, const int8_t* __restrict__ role, BodiesDev B,
+                                                    double* __restrict__ u) {
+    constexpr int NB = Dims<DIM>::NB;
+    const size_t Nc = (size_t)m.Nc;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        const int rn = role[c];
+        if (rn == MCD_ROLE_INNER) {
+            int ijk[3];
+            cell_ijk(m, c, ijk);
+            double Phi[NB];
+            poly_at<DIM>(m, st, c, ijk, P, f, Phi);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) u[a * Nc + c] = ustar[a * Nc + c] - dt * (Phi[a] / st.rs);
+        } else {
+            double v[DIM];
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) v[a] = 0.0;
+            for (int b = 0; b < B.n; ++b)
+                if (rn == B.id[b]) {
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) v[a] = B.vel[b][a];
+                }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) u[a * Nc + c] = v[a];
+        }
+    }
+}
+
+static inline int grid_cells(int n) {
+    int g = (n + kBlock - 1) / kBlock;
+    return g < 1 ? 1 : (g > 8192 ? 8192 : g);
+}
+
+#define MCD_DISPATCH(KERNEL, ...)                                                                       \
+    do {                                                                                                \
+        if (m.dim == 2)                                                                                 \
+            hipLaunchKernelGGL(KERNEL<2>, dim3(grid_cells(m.Nc)), dim3(kBlock), 0, st, __VA_ARGS__);    \
+        else                                                                                            \
+            hipLaunchKernelGGL(KERNEL<3>, dim3(grid_cells(m.Nc)), dim3(kBlock), 0, st, __VA_ARGS__);    \
+    } while (0)
+
+hipError_t launch_apply(const MeshDev& m, const SetDev& set, int op, const double* in, int ncomp,
+                        const double* fneu, const double* shift, double* out, double scale, hipStream_t st) {
+    MCD_DISPATCH(k_apply, m, set, op, in, ncomp, fneu, shift, out, scale);
+    return hipGetLastError();
+}
+
+hipError_t launch_remap(const MeshDev& m, const SetDev& set_prev, const double* u, const double* pos_prev,
+                        const double* pos, const int8_t* role_prev, const int8_t* role, const BodiesDev& Bprev,
+                        const BodiesDev& Bnew, double* out, int* counters, hipStream_t st) {
+    MCD_DISPATCH(k_remap, m, set_prev, u, pos_prev, pos, role_prev, role, Bprev, Bnew, out, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_advect_diffuse(const MeshDev& m, const SetDev& set, const double* ut, double dt, double nu,
+                                 const int8_t* role, const BodiesDev& B, double* ustar, hipStream_t st) {
+    MCD_DISPATCH(k_advect_diffuse, m, set, ut, dt, nu, role, B, ustar);
+    return hipGetLastError();
+}
+
+hipError_t launch_neumann_pressure(const MeshDev& m, const int8_t* role, const double* normal,
+                                   const BodiesDev& B, double* f, hipStream_t st) {
+    MCD_DISPATCH(k_neumann_pressure, m, role, normal, B, f);
+    return hipGetLastError();
+}
+
+hipError_t launch_project(const MeshDev& m, const SetDev& set, const double* P, const double* f,
+                          const double* ustar, double dt, const int8_t* role, const BodiesDev& B, double* u,
+                          hipStream_t st) {
+    MCD_DISPATCH(k_project, m, set, P, f, ustar, dt, role, B, u);
+    return hipGetLastError();
+}
+
+}  // namespace mcd

@@ -1,0 +1,272 @@
+// Internal definitions shared by the libmcd HIP sources (gfx950).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/mcd.h"
+
+namespace mcd {
+
+constexpr int kBlock = 256;          // 4 wave64 per block
+constexpr int kMaxBodies = MCD_MAX_BODIES;
+
+struct MeshDev {
+    int dim;
+    int n[3];
+    int Nc;
+    double origin[3];
+    double l0;
+    int periodic[3];
+    double length[3];   // n[a] * l0
+    int walls;
+    int wall_id;
+};
+
+struct BodiesDev {
+    int n;
+    int id[kMaxBodies];
+    double c[kMaxBodies][3];
+    double R[kMaxBodies];
+    double R2[kMaxBodies];      // R * R computed on the host
+    double vel[kMaxBodies][3];
+    double dvdt[kMaxBodies][3];
+};
+
+struct BcDev {
+    int type[MCD_MAX_IDS];
+    int pin_first;
+};
+
+// Storage of one stencil set (all planes are [.][Nc]).
+struct SetDev {
+    double* phi;        // [nb][S+1][Nc]
+    uint32_t* vmask;    // [Nc] bit s: slot s is a value row
+    uint32_t* nmask;    // [Nc] bit s: slot s is a Neumann row; bit S: own Neumann row
+    double* amat;       // [S][Nc] PPE matrix (unknown rows/cols)
+    float* amat32;      // [S][Nc]
+    uint8_t* unknown;   // [Nc]
+    double rs;
+};
+
+template <int DIM> struct Dims;
+template <> struct Dims<2> { static constexpr int NB = 5, S = 9, CEN = 4; };
+template <> struct Dims<3> { static constexpr int NB = 9, S = 27, CEN = 13; };
+
+// ---------------------------------------------------------------------------
+// Geometry helpers
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ void cell_ijk(const MeshDev& m, int c, int ijk[3]) {
+    ijk[0] = c % m.n[0];
+    int r = c / m.n[0];
+    ijk[1] = r % m.n[1];
+    ijk[2] = r / m.n[1];
+}
+
+// Neighbour of cell ijk at slot s (offset (s%3-1, s/3%3-1, s/9-1)).  Returns
+// false outside a non-periodic mesh.  shift[a] = wrap * L_a so that the
+// neighbour's image position is x_j + shift[a].
+template <int DIM>
+__device__ __forceinline__ bool neighbour(const MeshDev& m, const int ijk[3], int s, int& j, double shift[3]) {
+    int o[3] = {s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1};
+    int idx = 0, stride = 1;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        int ii = ijk[a] + o[a];
+        int w = 0;
+        if (ii < 0) {
+            if (!m.periodic[a]) return false;
+            ii += m.n[a];
+            w = -1;
+        } else if (ii >= m.n[a]) {
+            if (!m.periodic[a]) return false;
+            ii -= m.n[a];
+            w = 1;
+        }
+        shift[a] = (double)w * m.length[a];
+        idx += ii * stride;
+        stride *= m.n[a];
+    }
+    j = idx;
+    return true;
+}
+
+template <int DIM>
+__device__ __forceinline__ int slot_nonzeros(int s) {
+    int o[3] = {s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1};
+    int nz = 0;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) nz += (o[a] != 0);
+    return nz;
+}
+
+// 0: no row, 1: value row (inner or Dirichlet id), 2: Neumann row.
+__device__ __forceinline__ int row_kind(int rj, const BcDev& bc) {
+    if (rj == MCD_ROLE_INNER) return 1;
+    if (rj <= 0) return 0;
+    return bc.type[rj & (MCD_MAX_IDS - 1)] == MCD_BC_NEUMANN ? 2 : 1;
+}
+
+__device__ __forceinline__ bool is_unknown(int rj, int j, const BcDev& bc) {
+    if (bc.pin_first && j == 0) return false;
+    if (rj == MCD_ROLE_INNER) return true;
+    if (rj <= 0) return false;
+    return bc.type[rj & (MCD_MAX_IDS - 1)] == MCD_BC_NEUMANN;
+}
+
+// ---------------------------------------------------------------------------
+// Quadratic basis (Eq. p_ic) and its normal derivative
+// 3D order: X, Y, Z, X^2/2, Y^2/2, Z^2/2, XY, YZ, ZX
+// ---------------------------------------------------------------------------
+
+template <int DIM> __device__ __forceinline__ void basis(const double* X, double* p);
+template <> __device__ __forceinline__ void basis<2>(const double* X, double* p) {
+    p[0] = X[0];
+    p[1] = X[1];
+    p[2] = 0.5 * X[0] * X[0];
+    p[3] = X[0] * X[1];
+    p[4] = 0.5 * X[1] * X[1];
+}
+template <> __device__ __forceinline__ void basis<3>(const double* X, double* p) {
+    p[0] = X[0];
+    p[1] = X[1];
+    p[2] = X[2];
+    p[3] = 0.5 * X[0] * X[0];
+    p[4] = 0.5 * X[1] * X[1];
+    p[5] = 0.5 * X[2] * X[2];
+    p[6] = X[0] * X[1];
+    p[7] = X[1] * X[2];
+    p[8] = X[2] * X[0];
+}
+
+template <int DIM> __device__ __forceinline__ void basis_normal(const double* X, const double* nv, double* p);
+template <> __device__ __forceinline__ void basis_normal<2>(const double* X, const double* nv, double* p) {
+    p[0] = nv[0];
+    p[1] = nv[1];
+    p[2] = nv[0] * X[0];
+    p[3] = nv[0] * X[1] + nv[1] * X[0];
+    p[4] = nv[1] * X[1];
+}
+template <> __device__ __forceinline__ void basis_normal<3>(const double* X, const double* nv, double* p) {
+    p[0] = nv[0];
+    p[1] = nv[1];
+    p[2] = nv[2];
+    p[3] = nv[0] * X[0];
+    p[4] = nv[1] * X[1];
+    p[5] = nv[2] * X[2];
+    p[6] = nv[0] * X[1] + nv[1] * X[0];
+    p[7] = nv[1] * X[2] + nv[2] * X[1];
+    p[8] = nv[2] * X[0] + nv[0] * X[2];
+}
+
+// Pure second-derivative components (sum / r_s^2 = laplacian).
+template <int DIM> __device__ __forceinline__ double diag2(const double* P);
+template <> __device__ __forceinline__ double diag2<2>(const double* P) { return P[2] + P[4]; }
+template <> __device__ __forceinline__ double diag2<3>(const double* P) { return P[3] + P[4] + P[5]; }
+
+// ---------------------------------------------------------------------------
+// Reductions (wave64 shuffles, then LDS across the 4 waves of a block)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    return v;
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+    return v;
+}
+
+// Sums N values over the block; result valid in thread 0.
+template <int N>
+__device__ __forceinline__ void block_sum(double (&v)[N], double (*lds)[kBlock / 64]) {
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        double s = wave_sum(v[q]);
+        if (lane == 0) lds[q][wid] = s;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < N; ++q) {
+            double s = 0.0;
+#pragma unroll
+            for (int w = 0; w < kBlock / 64; ++w) s += lds[q][w];
+            v[q] = s;
+        }
+    }
+}
+
+// Maps the hardware block index to a logical one so that the blocks each XCD
+// receives (hardware dispatch is round-robin over the 8 XCDs) cover one
+// contiguous range of cells; neighbouring rows then share that XCD's L2.
+__device__ __forceinline__ int xcd_block(int b, int nblocks) {
+    const int per = nblocks >> 3;
+    if ((nblocks & 7) != 0) return b;
+    return (b & 7) * per + (b >> 3);
+}
+
+// ---------------------------------------------------------------------------
+// Host-side launchers (defined in the .hip sources)
+// ---------------------------------------------------------------------------
+
+struct Ctx;
+
+hipError_t launch_roles(const MeshDev& m, const BodiesDev& B, double band_l0, int8_t* role, int8_t* role_prev,
+                        double* pos, double* pos_prev, uint8_t* trans, uint8_t* band, int* counts,
+                        int* latch, hipStream_t st);
+hipError_t launch_relax(const MeshDev& m, const BodiesDev& B, double kl0, const double* spring, double eps_l0,
+                        const int8_t* role, const uint8_t* band, const double* pin, double* pout,
+                        const int box_lo[3], const int box_n[3], unsigned long long* dmax, int sweep,
+                        int* state, hipStream_t st);
+hipError_t launch_copy_band(const MeshDev& m, const uint8_t* band, const double* src, double* dst,
+                            const int box_lo[3], const int box_n[3], hipStream_t st);
+hipError_t launch_normals(const MeshDev& m, const BodiesDev& B, const int8_t* role, const double* pos,
+                          double* normal, hipStream_t st);
+hipError_t launch_fill_u64(unsigned long long* p, int n, unsigned long long v, hipStream_t st);
+hipError_t launch_fill_i32(int* p, int n, int v, hipStream_t st);
+
+hipError_t launch_mls_build(const MeshDev& m, const double* pos, const int8_t* role, const double* normal,
+                            const BcDev& bc, double re, double rs, int wkind, const SetDev& set, int* counters,
+                            int* latch, hipStream_t st);
+
+hipError_t launch_apply(const MeshDev& m, const SetDev& set, int op, const double* in, int ncomp,
+                        const double* fneu, const double* shift, double* out, double scale, hipStream_t st);
+hipError_t launch_remap(const MeshDev& m, const SetDev& set_prev, const double* u, const double* pos_prev,
+                        const double* pos, const int8_t* role_prev, const int8_t* role, const BodiesDev& Bprev,
+                        const BodiesDev& Bnew, double* out, int* counters, hipStream_t st);
+hipError_t launch_advect_diffuse(const MeshDev& m, const SetDev& set, const double* ut, double dt, double nu,
+                                 const int8_t* role, const BodiesDev& B, double* ustar, hipStream_t st);
+hipError_t launch_neumann_pressure(const MeshDev& m, const int8_t* role, const double* normal,
+                                   const BodiesDev& B, double* f, hipStream_t st);
+hipError_t launch_project(const MeshDev& m, const SetDev& set, const double* P, const double* f,
+                          const double* ustar, double dt, const int8_t* role, const BodiesDev& B, double* u,
+                          hipStream_t st);
+
+struct KrylovWork;
+struct SolveParams {
+    double tol;
+    int max_iter;
+    int precision;
+    int caller_guess;
+    double inner_tol;
+    int max_outer;
+    int check_every;
+};
+struct SolveOut {
+    int iterations, restarts, refinements, converged;
+    double rel, bnorm;
+};
+hipError_t krylov_alloc(int Nc, KrylovWork** out);
+void krylov_free(KrylovWork* w);
+hipError_t krylov_profile(KrylovWork* w, int enable);
+void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms_s, long long* n_s, int reset);
+hipError_t solve_ppe_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
+                          double* p, const SolveParams& sp, SolveOut* out, int* bad, hipStream_t st);
+
+}  // namespace mcd

@@ -1,0 +1,309 @@
+"""Thin ctypes binding of libmcd (include/mcd.h).
+
+Argument marshalling only: every step of the hot path runs in the HIP
+library.  Arrays are torch CUDA tensors (device memory owned by the caller);
+their data pointers and the current HIP stream are passed through.  Loading
+fails loudly when libmcd.so has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmcd.so")
+
+MCD_OK = 0
+STATUS = {0: "MCD_OK", 1: "MCD_ERR_ARG", 2: "MCD_ERR_SINGULAR", 3: "MCD_ERR_NOT_CONVERGED",
+          4: "MCD_ERR_BREAKDOWN", 5: "MCD_ERR_ROLE", 6: "MCD_ERR_HIP", 7: "MCD_ERR_OOM"}
+ROLE_INNER, ROLE_VOID = -1, 0
+BC_DIRICHLET, BC_NEUMANN = 0, 1
+WEIGHT_COS2, WEIGHT_GAUSS = 0, 1
+PREC_FP64, PREC_FP32_REFINE = 0, 1
+GUESS_ZERO, GUESS_CALLER = 0, 1
+OP_PHI, OP_GRAD, OP_LAP, OP_DIV, OP_SHIFT = 0, 1, 2, 3, 4
+MAX_IDS = 16
+MAX_BODIES = 8
+MAX_SETS = 4
+
+EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
+            "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
+            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_profile", "mcd_profile_read")
+
+
+class MeshDesc(C.Structure):
+    _fields_ = [("dim", C.c_int), ("n", C.c_int * 3), ("origin", C.c_double * 3), ("l0", C.c_double),
+                ("periodic", C.c_int * 3), ("walls", C.c_int), ("wall_id", C.c_int)]
+
+
+class Params(C.Structure):
+    _fields_ = [("weight_kind", C.c_int), ("re_over_l0", C.c_double), ("rs_over_l0", C.c_double),
+                ("kappa", C.c_double), ("band_over_l0", C.c_double), ("eps_relax", C.c_double)]
+
+
+class Body(C.Structure):
+    _fields_ = [("id", C.c_int), ("centre", C.c_double * 3), ("radius", C.c_double),
+                ("velocity", C.c_double * 3), ("dvdt", C.c_double * 3)]
+
+
+class BcTable(C.Structure):
+    _fields_ = [("type", C.c_int * MAX_IDS), ("pin_first", C.c_int)]
+
+
+class UpdateInfo(C.Structure):
+    _fields_ = [("sweeps", C.c_int), ("band_cells", C.c_int), ("counts", C.c_int * 9), ("role_errors", C.c_int)]
+
+
+class SolveOpts(C.Structure):
+    _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
+                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int)]
+
+
+class SolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("refinements", C.c_int), ("converged", C.c_int),
+                ("true_rel_residual", C.c_double), ("rhs_norm", C.c_double)]
+
+
+class McdError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__(f"{STATUS.get(status, status)}: {msg}")
+        self.status = status
+
+
+_lib = None
+
+
+def load():
+    """Loads libmcd.so (built in-tree); raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(f"libmcd.so not found at {LIB_PATH}: build it with __graft_entry__.build()")
+    lib = C.CDLL(LIB_PATH)
+    vp, i, d = C.c_void_p, C.c_int, C.c_double
+    P = C.POINTER
+    sig = {
+        "mcd_create": (i, [P(MeshDesc), P(Params), vp, P(vp)]),
+        "mcd_destroy": (None, [vp]),
+        "mcd_set_stream": (i, [vp, vp]),
+        "mcd_sync": (i, [vp]),
+        "mcd_last_error": (C.c_char_p, [vp]),
+        "mcd_update_dps": (i, [vp, P(Body), i, i, vp, vp, vp, vp, vp, vp, P(UpdateInfo)]),
+        "mcd_build_stencils": (i, [vp, i, vp, vp, vp, P(BcTable)]),
+        "mcd_get_stencils": (i, [vp, i, vp, vp, vp]),
+        "mcd_apply": (i, [vp, i, i, vp, i, vp, vp, vp]),
+        "mcd_remap": (i, [vp, i, vp, vp, vp, vp, vp, P(Body), P(Body), i, vp]),
+        "mcd_advect_diffuse": (i, [vp, i, vp, d, d, vp, P(Body), i, vp, vp]),
+        "mcd_neumann_pressure": (i, [vp, vp, vp, P(Body), i, vp]),
+        "mcd_project": (i, [vp, i, vp, vp, vp, d, vp, P(Body), i, vp]),
+        "mcd_solve_ppe": (i, [vp, i, vp, vp, vp, P(SolveOpts), P(SolveInfo)]),
+        "mcd_profile": (i, [vp, i]),
+        "mcd_profile_read": (i, [vp, P(d), P(C.c_longlong), P(d), P(C.c_longlong), i]),
+    }
+    for name, (res, args) in sig.items():
+        f = getattr(lib, name)
+        f.restype = res
+        f.argtypes = args
+    _lib = lib
+    return lib
+
+
+_SIZES = {torch.float64: 8, torch.float32: 4, torch.int8: 1, torch.uint8: 1, torch.int32: 4}
+
+
+def _ptr(t, numel=None, dtype=None):
+    """Device pointer of a contiguous CUDA tensor; checks dtype and that it
+    holds at least `numel` elements (kernels index up to that extent)."""
+    if t is None:
+        return None
+    if not t.is_cuda:
+        raise ValueError("libmcd takes device tensors")
+    if not t.is_contiguous():
+        raise ValueError("libmcd takes contiguous tensors")
+    if dtype is not None and t.dtype not in (dtype if isinstance(dtype, tuple) else (dtype,)):
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"tensor has {t.numel()} elements, the call reads/writes {numel}")
+    return C.c_void_p(t.data_ptr())
+
+
+def bodies_array(bodies):
+    """bodies: list of dicts with id, centre, radius, velocity, dvdt."""
+    n = len(bodies)
+    arr = (Body * max(n, 1))()
+    for k, b in enumerate(bodies):
+        arr[k].id = int(b["id"])
+        arr[k].radius = float(b["radius"])
+        for a in range(3):
+            arr[k].centre[a] = float(b["centre"][a]) if a < len(b["centre"]) else 0.0
+            v = b.get("velocity", ())
+            arr[k].velocity[a] = float(v[a]) if a < len(v) else 0.0
+            g = b.get("dvdt", ())
+            arr[k].dvdt[a] = float(g[a]) if a < len(g) else 0.0
+    return arr, n
+
+
+def bc_table(bc: dict, pin_first=False):
+    t = BcTable()
+    for k in range(MAX_IDS):
+        t.type[k] = BC_DIRICHLET
+    for bid, typ in bc.items():
+        t.type[int(bid)] = int(typ)
+    t.pin_first = 1 if pin_first else 0
+    return t
+
+
+class Context:
+    """One libmcd context (mesh + workspaces) on the current device/stream."""
+
+    def __init__(self, dim, n, origin, l0, periodic=(False, False, False), walls=False, wall_id=1,
+                 weight="cos2", re_over_l0=2.5, rs_over_l0=1.0, kappa=0.2, band_over_l0=5.0, eps_relax=1e-6,
+                 stream=None):
+        self.lib = load()
+        md = MeshDesc()
+        md.dim = dim
+        for a in range(3):
+            md.n[a] = int(n[a]) if a < dim else 1
+            md.origin[a] = float(origin[a]) if a < dim else 0.0
+            md.periodic[a] = int(bool(periodic[a])) if a < len(periodic) else 0
+        md.l0 = float(l0)
+        md.walls = int(bool(walls))
+        md.wall_id = int(wall_id)
+        pr = Params()
+        pr.weight_kind = WEIGHT_COS2 if weight == "cos2" else WEIGHT_GAUSS
+        pr.re_over_l0, pr.rs_over_l0, pr.kappa = re_over_l0, rs_over_l0, kappa
+        pr.band_over_l0, pr.eps_relax = band_over_l0, eps_relax
+        self.dim = dim
+        self.n = tuple(int(v) for v in n[:dim])
+        self.Nc = 1
+        for v in self.n:
+            self.Nc *= v
+        self.nb = 5 if dim == 2 else 9
+        self.S = 9 if dim == 2 else 27
+        if stream is None:
+            stream = torch.cuda.current_stream().cuda_stream
+        h = C.c_void_p()
+        st = self.lib.mcd_create(C.byref(md), C.byref(pr), C.c_void_p(stream), C.byref(h))
+        if st != MCD_OK:
+            raise McdError(st, "mcd_create failed")
+        self.h = h
+
+    @classmethod
+    def from_case(cls, case, **kw):
+        from .configs import WALL_ID
+        return cls(case.dim, case.n, case.origin, case.l0, case.periodic, case.walls, WALL_ID, case.weight,
+                   case.re_over_l0, case.rs_over_l0, case.kappa, case.band_over_l0, case.eps_relax, **kw)
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mcd_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def _check(self, st, what):
+        if st != MCD_OK:
+            msg = self.lib.mcd_last_error(self.h)
+            raise McdError(st, f"{what}: {msg.decode() if msg else ''}")
+
+    @staticmethod
+    def _vec(t, numel):
+        return _ptr(t, numel, torch.float64)
+
+    # --- calls -------------------------------------------------------------
+    def sync(self):
+        self._check(self.lib.mcd_sync(self.h), "mcd_sync")
+
+    def update_dps(self, bodies, max_sweeps, pos, role, pos_prev, role_prev, trans, normal, info=True):
+        arr, n = bodies_array(bodies)
+        ui = UpdateInfo()
+        V, D, N = self._vec, self.dim * self.Nc, self.Nc
+        st = self.lib.mcd_update_dps(self.h, arr, n, int(max_sweeps), V(pos, D), _ptr(role, N, torch.int8),
+                                     V(pos_prev, D), _ptr(role_prev, N, torch.int8), _ptr(trans, N, torch.uint8),
+                                     V(normal, D), C.byref(ui) if info else None)
+        self._check(st, "mcd_update_dps")
+        if info:
+            return {"sweeps": ui.sweeps, "band_cells": ui.band_cells, "counts": list(ui.counts),
+                    "role_errors": ui.role_errors}
+        return None
+
+    def build_stencils(self, set_id, pos, role, normal, bc: dict, pin_first=False):
+        t = bc_table(bc, pin_first)
+        D, N = self.dim * self.Nc, self.Nc
+        self._check(self.lib.mcd_build_stencils(self.h, int(set_id), self._vec(pos, D), _ptr(role, N, torch.int8),
+                                                self._vec(normal, D), C.byref(t)), "mcd_build_stencils")
+
+    def get_stencils(self, set_id, phi=None, masks=None, amat=None):
+        N = self.Nc
+        self._check(self.lib.mcd_get_stencils(self.h, int(set_id), self._vec(phi, self.nb * (self.S + 1) * N),
+                                              _ptr(masks, 2 * N, (torch.int32,)), self._vec(amat, self.S * N)),
+                    "mcd_get_stencils")
+
+    def apply(self, set_id, op, inp, ncomp, out, neumann_f=None, shift=None):
+        N = self.Nc
+        n_out = {OP_PHI: self.nb, OP_GRAD: self.dim, OP_LAP: ncomp, OP_DIV: 1, OP_SHIFT: ncomp}.get(op, 0)
+        V = self._vec
+        self._check(self.lib.mcd_apply(self.h, int(set_id), int(op), V(inp, ncomp * N), int(ncomp),
+                                       V(neumann_f, ncomp * N), V(shift, self.dim * N), V(out, n_out * N)),
+                    "mcd_apply")
+
+    def remap(self, set_prev, u, pos_prev, pos, role_prev, role, bodies_prev, bodies_new, out):
+        bp, n = bodies_array(bodies_prev)
+        bn, n2 = bodies_array(bodies_new)
+        assert n == n2
+        D, N, V = self.dim * self.Nc, self.Nc, self._vec
+        self._check(self.lib.mcd_remap(self.h, int(set_prev), V(u, D), V(pos_prev, D), V(pos, D),
+                                       _ptr(role_prev, N, torch.int8), _ptr(role, N, torch.int8), bp, bn, n,
+                                       V(out, D)), "mcd_remap")
+
+    def advect_diffuse(self, set_id, ut, dt, nu, role, bodies, ustar, rhs=None):
+        arr, n = bodies_array(bodies)
+        D, N, V = self.dim * self.Nc, self.Nc, self._vec
+        self._check(self.lib.mcd_advect_diffuse(self.h, int(set_id), V(ut, D), float(dt), float(nu),
+                                                _ptr(role, N, torch.int8), arr, n, V(ustar, D), V(rhs, N)),
+                    "mcd_advect_diffuse")
+
+    def neumann_pressure(self, role, normal, bodies, f):
+        arr, n = bodies_array(bodies)
+        N = self.Nc
+        self._check(self.lib.mcd_neumann_pressure(self.h, _ptr(role, N, torch.int8), self._vec(normal, self.dim * N),
+                                                  arr, n, self._vec(f, N)), "mcd_neumann_pressure")
+
+    def project(self, set_id, P, f, ustar, dt, role, bodies, u):
+        arr, n = bodies_array(bodies)
+        D, N, V = self.dim * self.Nc, self.Nc, self._vec
+        self._check(self.lib.mcd_project(self.h, int(set_id), V(P, N), V(f, N), V(ustar, D), float(dt),
+                                         _ptr(role, N, torch.int8), arr, n, V(u, D)), "mcd_project")
+
+    def solve_ppe(self, set_id, rhs, p, neumann_f=None, tol=1e-8, max_iter=20000, precision=PREC_FP64,
+                  guess=GUESS_ZERO, inner_tol=1e-4, max_outer=30, check_every=16, raise_on_fail=True):
+        o = SolveOpts()
+        o.tol, o.max_iter, o.precision, o.guess = tol, int(max_iter), int(precision), int(guess)
+        o.inner_tol, o.max_outer, o.check_every = inner_tol, int(max_outer), int(check_every)
+        info = SolveInfo()
+        N, V = self.Nc, self._vec
+        st = self.lib.mcd_solve_ppe(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), C.byref(o),
+                                    C.byref(info))
+        out = {"iterations": info.iterations, "restarts": info.restarts, "refinements": info.refinements,
+               "converged": bool(info.converged), "true_rel_residual": info.true_rel_residual,
+               "rhs_norm": info.rhs_norm, "status": st}
+        if raise_on_fail:
+            self._check(st, "mcd_solve_ppe")
+        return out
+
+    def profile(self, enable=True):
+        self._check(self.lib.mcd_profile(self.h, int(bool(enable))), "mcd_profile")
+
+    def profile_read(self, reset=True):
+        mp, ms = C.c_double(), C.c_double()
+        npp, ns = C.c_longlong(), C.c_longlong()
+        self._check(self.lib.mcd_profile_read(self.h, C.byref(mp), C.byref(npp), C.byref(ms), C.byref(ns),
+                                              int(bool(reset))), "mcd_profile_read")
+        return {"p_ms": mp.value, "p_n": npp.value, "s_ms": ms.value, "s_n": ns.value}

@@ -1,0 +1,129 @@
+"""GPU time stepper: one MCD projection step through libmcd.
+
+Order of one step k -> k+1 (Sec. 3.3 with the DP update of Sec. 2.3-2.4):
+rearrange DPs and reassign roles at t^{k+1}; remap u^k to x^{k+1} with the
+step-k velocity weights; build the velocity and pressure weights at x^{k+1};
+u* and the PPE right-hand side; Neumann datum -dV/dt . n; Bi-CGSTAB; project.
+Every step runs in libmcd kernels; this module only sequences the calls and
+owns the device arrays (torch tensors on one stream).
+"""
+from __future__ import annotations
+
+import math
+
+import numpy as np
+import torch
+
+from . import inputs
+from .configs import WALL_ID
+from . import mcd as M
+
+SET_VEL = (0, 1)   # ping-pong: velocity weights of step k and step k+1
+SET_P = 2
+
+
+class GpuSim:
+    def __init__(self, case, precision=M.PREC_FP64, device="cuda", check_every=16, update_info=True):
+        self.case = case
+        self.device = device
+        self.precision = precision
+        self.check_every = check_every
+        self.update_info = update_info
+        self.ctx = M.Context.from_case(case)
+        dim, Nc = case.dim, case.n_cells
+        f64 = dict(dtype=torch.float64, device=device)
+        pos0 = inputs.jittered_positions(case.n, case.origin, case.l0, case.jitter_seed)
+        self.pos = torch.tensor(pos0, **f64).contiguous()
+        self.pos_prev = torch.zeros_like(self.pos)
+        self.normal = torch.zeros_like(self.pos)
+        self.role = torch.full((Nc,), M.ROLE_INNER, dtype=torch.int8, device=device)
+        self.role_prev = torch.zeros_like(self.role)
+        self.trans = torch.zeros((Nc,), dtype=torch.uint8, device=device)
+        self.u = torch.zeros((dim, Nc), **f64)
+        self.ut = torch.zeros_like(self.u)
+        self.ustar = torch.zeros_like(self.u)
+        self.rhs = torch.zeros((Nc,), **f64)
+        self.P = torch.zeros((Nc,), **f64)
+        self.fP = torch.zeros((Nc,), **f64)
+        self.k = 0
+        self.t = 0.0
+        self.log = []
+        self.same_sets = case.bc_pressure == case.bc_velocity
+        self.bodies = self.bodies_at(0.0, prev=None)
+        # initial masking (its transitions from the placeholder roles are not meaningful)
+        self.ctx.update_dps(self.bodies, 0, self.pos, self.role, self.pos_prev, self.role_prev, self.trans,
+                            self.normal, info=False)
+        try:
+            self.ctx.sync()
+        except M.McdError as e:
+            if e.status != 5:
+                raise
+        n_init = case.n_relax_init if self.bodies else 0
+        self.init_info = self.ctx.update_dps(self.bodies, n_init, self.pos, self.role, self.pos_prev,
+                                             self.role_prev, self.trans, self.normal, info=True)
+        role_h = self.role.cpu().numpy()
+        if case.name.startswith("C1"):
+            u0 = inputs.tgv_velocity(self.pos.cpu().numpy(), 0.0, case.nu)
+        else:
+            u0 = np.zeros((dim, Nc))
+        for b in self.bodies:
+            for a in range(dim):
+                u0[a, role_h == b["id"]] = b["velocity"][a]
+        self.u.copy_(torch.tensor(u0, **f64))
+        self.vel_slot = 0
+        self.ctx.build_stencils(SET_VEL[self.vel_slot], self.pos, self.role, self.normal, case.bc_velocity,
+                                case.pin_first if self.same_sets else False)
+        torch.cuda.synchronize()
+
+    def bodies_at(self, t, prev):
+        b = self.case.body
+        if b is None:
+            return []
+        vel = b.motion.velocity(t)
+        if prev is None:
+            dvdt = (0.0,) * len(vel)
+        else:
+            dvdt = tuple((vn - vo) / self.case.dt for vn, vo in zip(vel, prev[0]["velocity"]))
+        return [{"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
+                 "dvdt": dvdt}]
+
+    def step(self):
+        case, ctx = self.case, self.ctx
+        tn = (self.k + 1) * case.dt
+        bodies_new = self.bodies_at(tn, self.bodies) if self.bodies else []
+        upd = ctx.update_dps(bodies_new, case.n_relax, self.pos, self.role, self.pos_prev, self.role_prev,
+                             self.trans, self.normal, info=self.update_info)
+        old = SET_VEL[self.vel_slot]
+        new = SET_VEL[1 - self.vel_slot]
+        ctx.remap(old, self.u, self.pos_prev, self.pos, self.role_prev, self.role, self.bodies, bodies_new, self.ut)
+        # one set serves both fields when their boundary conditions agree (the pin
+        # only shapes the PPE matrix of a set, never its weights)
+        ctx.build_stencils(new, self.pos, self.role, self.normal, case.bc_velocity,
+                           case.pin_first if self.same_sets else False)
+        pset = new
+        if not self.same_sets:
+            ctx.build_stencils(SET_P, self.pos, self.role, self.normal, case.bc_pressure, case.pin_first)
+            pset = SET_P
+        ctx.advect_diffuse(new, self.ut, case.dt, case.nu, self.role, bodies_new, self.ustar, self.rhs)
+        ctx.neumann_pressure(self.role, self.normal, bodies_new, self.fP)
+        info = ctx.solve_ppe(pset, self.rhs, self.P, self.fP, tol=case.tol, precision=self.precision,
+                             guess=M.GUESS_CALLER, check_every=self.check_every)
+        ctx.project(pset, self.P, self.fP, self.ustar, case.dt, self.role, bodies_new, self.u)
+        self.vel_slot = 1 - self.vel_slot
+        self.bodies = bodies_new
+        self.k += 1
+        self.t = tn
+        rec = {"k": self.k, "iters": info["iterations"], "restarts": info["restarts"],
+               "refinements": info["refinements"], "rel_res": info["true_rel_residual"],
+               "converged": info["converged"]}
+        if upd is not None:
+            rec.update({"sweeps": upd["sweeps"], "trans": upd["counts"]})
+        self.log.append(rec)
+        return rec
+
+    def n_active(self):
+        return int((self.role != M.ROLE_VOID).sum().item())
+
+    def kinetic_energy(self):
+        sel = self.role == M.ROLE_INNER
+        return float((self.u[:, sel] ** 2).sum().item())
