@@ -249,7 +249,8 @@ class RelaxConsts:
 def relax_sweep(mesh, consts, bodies, role, band, pos):
     """One Jacobi sweep over the band cells; returns (new positions, max |dx|).
 
-    (ii) Spring forces: for every non-void neighbour j in the 3x3(x3) block,
+    (ii) Spring forces: for every non-void neighbour j in the 3x3(x3) block
+    (a neighbour at distance 0 is skipped: it has no direction),
     F += G(r') x_ij/|x_ij| with G = 1 - |x_ij|/l_spring, l_spring = l0 for an
     edge, sqrt(2) l0 for a diagonal (sqrt(3) l0 for a 3D corner: reading);
     explicit Euler x* = x - (kappa l0) F (dimensionless form times l0).
@@ -277,6 +278,7 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
             for a in range(1, dim):
                 d2 = d2 + d[a] * d[a]
             dist = np.sqrt(d2)
+            ok &= dist > 0.0           # a coincident neighbour has no direction
             L = consts.spring[sum(1 for v in off if v != 0)]
             g = 1.0 - dist / L
             for a in range(dim):
@@ -452,8 +454,9 @@ def mls_build(mesh, pos, role, normal, bc, re, rs, kind="cos2", idx=None, chunk=
     M = sum_{Lambda_c} w_j p_j p_j^T + sum_{Lambda^N_c} w_j p^N_j p^N_j^T,
     with Lambda_c the inner and Dirichlet DPs of the block and Lambda^N_c its
     Neumann DPs (Eq. set), the DP itself included when it is Neumann.  M is
-    factored by textbook Cholesky; a pivot <= 1e-14 trace(M)/m flags the DP
-    singular (its weights are set to zero).
+    factored by textbook Cholesky.  A DP with fewer rows of positive weight
+    than basis terms (M rank-deficient), or a pivot <= 1e-12 trace(M)/m, is
+    flagged singular and its weights are set to zero.
     """
     if idx is None:
         idx = np.arange(mesh.Nc)
@@ -503,10 +506,12 @@ def _mls_chunk(mesh, pos, role, normal, bc, re, rs, wkind, idx):
         rows.append((s, rk, w, a_row))
         kinds[s] = rk
         nbrs[s] = np.where(j >= 0, j, -1)
-    # moment matrix, slots in order
+    # moment matrix, slots in order; rows with zero weight carry no information
     M = np.zeros((m, m, K))
+    nrows = np.zeros(K, dtype=np.int64)
     for s, rk, w, a_row in rows:
         M += w[None, None, :] * a_row[:, None, :] * a_row[None, :, :]
+        nrows += (rk > 0) & (w > 0.0)
     # textbook Cholesky M = L L^T
     L = np.zeros_like(M)
     tr = np.zeros(K)
@@ -517,7 +522,7 @@ def _mls_chunk(mesh, pos, role, normal, bc, re, rs, wkind, idx):
         dsum = M[jcol, jcol].copy()
         for k in range(jcol):
             dsum = dsum - L[jcol, k] * L[jcol, k]
-        bad = dsum <= 1e-14 * tr / m
+        bad = dsum <= 1e-12 * tr / m
         singular |= bad
         ljj = np.sqrt(np.where(bad, 1.0, dsum))
         L[jcol, jcol] = ljj
@@ -526,6 +531,7 @@ def _mls_chunk(mesh, pos, role, normal, bc, re, rs, wkind, idx):
             for k in range(jcol):
                 acc = acc - L[i, k] * L[jcol, k]
             L[i, jcol] = acc / ljj
+    singular |= nrows < m        # fewer rows than basis terms: M has no full rank
     singular &= active
 
     def solve(rhs):
@@ -563,6 +569,29 @@ def _mls_chunk(mesh, pos, role, normal, bc, re, rs, wkind, idx):
 # ---------------------------------------------------------------------------
 # Applying the weights (Eq. intrp_chi_1 and derivative readings)
 # ---------------------------------------------------------------------------
+
+def moment_cond(mesh, pos, role, normal, bc, re, rs, kind, idx):
+    """2-norm condition number of the MLS moment matrix M at DPs idx (for
+    error bounds in tests)."""
+    dim, m = mesh.dim, n_basis(mesh.dim)
+    ijk = mesh.ijk(np.asarray(idx))
+    xc = pos[:, idx]
+    M = np.zeros((len(idx), m, m))
+    for s, off in enumerate(mesh.offsets):
+        j, wrap = mesh.neighbour(ijk, off)
+        jj = np.where(j >= 0, j, 0)
+        rk = np.where(j >= 0, _row_kind(role[jj], bc), 0)
+        if s == mesh.centre:
+            rk = np.where(rk == 2, 2, 0)
+        d = [(pos[a, jj] + wrap[a] * mesh.length[a]) - xc[a] for a in range(dim)]
+        r = np.sqrt(sum(v * v for v in d))
+        w = np.where(rk > 0, weight(r, re, kind), 0.0)
+        X = [v / rs for v in d]
+        a_row = np.where(rk == 2, np.array(basis_normal(X, [normal[a, jj] for a in range(dim)])),
+                         np.array(basis(X)))
+        M += w[:, None, None] * a_row.T[:, :, None] * a_row.T[:, None, :]
+    return np.linalg.cond(M)
+
 
 def poly_coeffs(mesh, st, fld, f_neu=None):
     """Phi at the stencil set's DPs for scalar field fld (Nc,).

@@ -183,7 +183,7 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
     if (e == hipSuccess) e = alloc((void**)&c->relax_state, 4 * sizeof(int));
     if (e == hipSuccess) e = alloc((void**)&c->cnt, CNT_N * sizeof(int));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->cnt_host, CNT_N * sizeof(int), hipHostMallocDefault);
-    if (e == hipSuccess) e = krylov_alloc((int)N, &c->kw);
+    if (e == hipSuccess) e = krylov_alloc(c->m, &c->kw);
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         mcd_destroy(c);

@@ -262,7 +262,7 @@ struct SolveOut {
     int iterations, restarts, refinements, converged;
     double rel, bnorm;
 };
-hipError_t krylov_alloc(int Nc, KrylovWork** out);
+hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out);
 void krylov_free(KrylovWork* w);
 hipError_t krylov_profile(KrylovWork* w, int enable);
 void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms_s, long long* n_s, int reset);

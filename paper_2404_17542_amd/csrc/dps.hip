@@ -156,6 +156,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
 #pragma unroll
             for (int a = 1; a < DIM; ++a) d2 = d2 + d[a] * d[a];
             const double dist = sqrt(d2);
+            if (!(dist > 0.0)) continue;   // a coincident neighbour has no direction
             const int nz = slot_nonzeros<DIM>(s);
             const double L = nz == 1 ? sp1 : (nz == 2 ? sp2 : sp3);
             const double g = 1.0 - dist / L;

@@ -17,6 +17,8 @@
 // are run-to-run deterministic, and computes the scalars of the next stage.
 // Vectors are zero at non-unknown cells; matrix rows/columns of non-unknown
 // cells are zero.
+#include <hip/hip_ext.h>
+
 #include "common.h"
 
 namespace mcd {
@@ -24,15 +26,19 @@ namespace mcd {
 struct KState {
     double rho, alpha, omega;
     double bb, rr, rr0, rv;
-    double ts, tt, rsv, rtv;
     double tol2;
-    int done;       // 0 running, 1 recurrence converged, 2 breakdown
+    int done;       // 0 running, 1 recurrence/true residual converged, 2 breakdown
     int iter;
-    unsigned int ticket;
-    int pad;
+    int pad[2];
 };
 
-constexpr int kMaxGrid = 2048;
+// Fixed launch shape of the stage kernels: 512 blocks x 512 threads
+// (16 waves per CU on 256 CUs); per-block partial sums of one stage are
+// reduced by every block of the next stage in a fixed order, so no grid
+// barrier, fence or atomic is needed and every block derives bitwise the
+// same scalars.
+constexpr int kKBlock = 512;
+constexpr int kKGrid = 512;
 
 template <typename T>
 struct KVec {
@@ -41,18 +47,39 @@ struct KVec {
     const T* b;
 };
 
-// Sum of A[s][c] * val(j) over the stencil slots of cell c.
+struct KBufs {
+    double* part[3];     // [NQ][cap] partials of init / P / S stages
+    KState* st[3];       // state written by block 0 of init/finish, P, S
+    int nblk;            // blocks (= partials) of the stage kernels in use
+    int cap;             // partials capacity per quantity
+    int ntx;             // tiles per row (2D tiled kernels)
+    int ntiles;          // tiles of the mesh (2D)
+    int tpb;             // tiles per block (2D)
+};
+
+// Sum of A[s][c] * val(j) over the stencil slots of cell c.  Interior cells
+// use constant slot offsets; cells on the mesh edge take the general path.
 template <int DIM, typename T, typename F>
 __device__ __forceinline__ T spmv_row(const MeshDev& m, const T* __restrict__ A, int c, F val) {
     constexpr int S = Dims<DIM>::S;
     const size_t Nc = (size_t)m.Nc;
     int ijk[3];
     cell_ijk(m, c, ijk);
+    bool interior = ijk[0] > 0 && ijk[0] < m.n[0] - 1 && ijk[1] > 0 && ijk[1] < m.n[1] - 1;
+    if (DIM == 3) interior = interior && ijk[2] > 0 && ijk[2] < m.n[2] - 1;
     T acc = 0;
+    if (interior) {
+        const int n0 = m.n[0], n01 = m.n[0] * m.n[1];
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const int off = (s % 3 - 1) + (DIM > 1 ? ((s / 3) % 3 - 1) * n0 : 0) + (DIM > 2 ? (s / 9 - 1) * n01 : 0);
+            acc += A[(size_t)s * Nc + c] * val(c + off);
+        }
+        return acc;
+    }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const T a = A[(size_t)s * Nc + c];
-        if (a == T(0)) continue;
         int j;
         double sh[3];
         if (!neighbour<DIM>(m, ijk, s, j, sh)) continue;
@@ -61,169 +88,477 @@ __device__ __forceinline__ T spmv_row(const MeshDev& m, const T* __restrict__ A,
     return acc;
 }
 
-// Block-reduce NQ partial sums, then the last block reduces all blocks'
-// partials (fixed order) into tot[] (valid in thread 0 of the last block).
+// Block sum of NQ values; result broadcast to every thread.
 template <int NQ>
-__device__ __forceinline__ bool grid_reduce(double (&v)[NQ], double* part, KState* ks, double (&tot)[NQ]) {
-    __shared__ double lds[NQ][kBlock / 64];
-    __shared__ bool last;
-    block_sum<NQ>(v, lds);
-    const int G = gridDim.x;
-    if (threadIdx.x == 0) {
+__device__ __forceinline__ void block_sum_all(double (&v)[NQ]) {
+    __shared__ double lds[NQ][kKBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) part[q * kMaxGrid + blockIdx.x] = v[q];
-        __threadfence();
-        const unsigned t = atomicAdd(&ks->ticket, 1u);
-        last = (t == (unsigned)(G - 1));
+    for (int q = 0; q < NQ; ++q) {
+        const double s = wave_sum(v[q]);
+        if (lane == 0) lds[q][wid] = s;
     }
     __syncthreads();
-    if (!last) return false;
-    __threadfence();
-    double acc[NQ];
 #pragma unroll
-    for (int q = 0; q < NQ; ++q) acc[q] = 0.0;
-    for (int b = threadIdx.x; b < G; b += kBlock) {
+    for (int q = 0; q < NQ; ++q) {
+        double s = 0.0;
 #pragma unroll
-        for (int q = 0; q < NQ; ++q) acc[q] += __builtin_nontemporal_load(&part[q * kMaxGrid + b]);
+        for (int w = 0; w < kKBlock / 64; ++w) s += lds[q][w];
+        v[q] = s;
     }
     __syncthreads();
-    block_sum<NQ>(acc, lds);
-    if (threadIdx.x == 0) {
-#pragma unroll
-        for (int q = 0; q < NQ; ++q) tot[q] = acc[q];
-        ks->ticket = 0;
-    }
-    return true;
 }
 
-// r0 = b - A x;  rhat = r0 (stored in s and rhat);  dots: r0.r0 (and b.b).
-template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_kinit(MeshDev m, KVec<T> V, double* part, KState* ks, int with_bb,
-                                                  double tol2) {
-    double v[2] = {0.0, 0.0};
-    const int G = gridDim.x;
-    const int lb = xcd_block(blockIdx.x, G);
-    for (int c = lb * blockDim.x + threadIdx.x; c < m.Nc; c += G * blockDim.x) {
-        const T* x = V.x;
-        const T ax = spmv_row<DIM, T>(m, V.A, c, [&](int j) { return x[j]; });
-        const T bc = V.b[c];
-        const T r = bc - ax;
-        V.s[c] = r;
-        V.rhat[c] = r;
-        v[0] += (double)r * (double)r;
-        v[1] += (double)bc * (double)bc;
+// Every block reduces the NQ x nblk partials of the previous stage in the
+// same fixed order (thread t sums partials t, t + 512, ...; then a fixed
+// block tree), so all blocks obtain bitwise the same totals.
+template <int NQ>
+__device__ __forceinline__ void reduce_partials(const double* __restrict__ part, const KBufs& K, double (&tot)[NQ]) {
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double s = 0.0;
+        for (int b = threadIdx.x; b < K.nblk; b += kKBlock) s += part[q * K.cap + b];
+        tot[q] = s;
     }
+    block_sum_all<NQ>(tot);
+}
+
+template <int NQ>
+__device__ __forceinline__ void write_partials(double (&v)[NQ], double* part, const KBufs& K) {
+    block_sum_all<NQ>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) part[q * K.cap + blockIdx.x] = v[q];
+    }
+}
+
+// r0 = b - A x;  rhat = r0 (kept in s and rhat);  partials r0.r0, b.b.
+template <int DIM, typename T>
+__global__ __launch_bounds__(kKBlock) void k_kinit(MeshDev m, KVec<T> V, KBufs K) {
+    const T* __restrict__ x = V.x;
+    const T* __restrict__ bp = V.b;
+    const T* __restrict__ A = V.A;
+    T* __restrict__ sp = V.s;
+    T* __restrict__ rh = V.rhat;
+    double a0 = 0.0, a1 = 0.0;
+    const int lb = xcd_block(blockIdx.x, kKGrid);
+    for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
+        const T ax = spmv_row<DIM, T>(m, A, c, [&](int j) { return x[j]; });
+        const T bc = bp[c];
+        const T r = bc - ax;
+        sp[c] = r;
+        rh[c] = r;
+        a0 += (double)r * (double)r;
+        a1 += (double)bc * (double)bc;
+    }
+    double v[2] = {a0, a1};
+    write_partials<2>(v, K.part[0], K);
+}
+
+// One block: reduce the init partials into the state the first P-stage reads.
+__global__ __launch_bounds__(kKBlock) void k_kfinish(KBufs K, int with_bb, double tol2, int keep_iter) {
     double tot[2];
-    if (grid_reduce<2>(v, part, ks, tot) && threadIdx.x == 0) {
+    reduce_partials<2>(K.part[0], K, tot);
+    if (threadIdx.x == 0) {
+        KState* S = K.st[2];
         if (with_bb) {
-            ks->bb = tot[1];
-            ks->tol2 = tol2;
-            ks->iter = 0;
+            S->bb = tot[1];
+            S->tol2 = tol2;
         }
-        ks->rr = tot[0];
-        ks->rr0 = tot[0];
-        ks->rho = tot[0];
-        ks->alpha = 1.0;
-        ks->omega = 1.0;
-        ks->done = (tot[0] <= ks->tol2 * ks->bb) ? 1 : 0;
+        if (!keep_iter) S->iter = 0;
+        S->rr = tot[0];
+        S->rr0 = tot[0];
+        S->rho = tot[0];
+        S->alpha = 1.0;
+        S->omega = 1.0;
+        S->done = (tot[0] <= S->tol2 * S->bb) ? 1 : 0;
     }
 }
 
 template <int DIM, typename T, bool FIRST>
-__global__ __launch_bounds__(kBlock) void k_kP(MeshDev m, KVec<T> V, int par, double* part, KState* ks) {
-    if (ks->done) return;
-    const double alpha = ks->alpha;
-    double omega = 1.0, beta = 0.0, rho_new = ks->rho;
+__global__ __launch_bounds__(kKBlock) void k_kP(MeshDev m, KVec<T> V, int par, KBufs K) {
+    const KState* __restrict__ in = K.st[2];
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    if (in->done) {
+        if (leader) *K.st[1] = *in;
+        return;
+    }
+    const double alpha = in->alpha;
+    double omega = 1.0, beta = 0.0, rho_new = in->rho;
     if (!FIRST) {
-        omega = ks->ts / ks->tt;
-        rho_new = ks->rsv - omega * ks->rtv;
-        beta = (rho_new / ks->rho) * (alpha / omega);
+        double tot[4];
+        reduce_partials<4>(K.part[2], K, tot);   // t.s, t.t, rhat.s, rhat.t
+        omega = tot[0] / tot[1];
+        rho_new = tot[2] - omega * tot[3];
+        beta = (rho_new / in->rho) * (alpha / omega);
+        if (!(tot[1] > 0.0) || !isfinite(omega) || !isfinite(beta) || omega == 0.0 ||
+            fabs(rho_new) < 1e-30 * in->rr0) {
+            if (leader) {
+                *K.st[1] = *in;
+                K.st[1]->done = 2;
+            }
+            return;
+        }
     }
     const T ta = (T)alpha, tw = (T)omega, tb = (T)beta;
     const T* __restrict__ s = V.s;
     const T* __restrict__ t = V.t;
     const T* __restrict__ po = V.p[par];
     const T* __restrict__ vo = V.v[par];
+    const T* __restrict__ rh = V.rhat;
+    const T* __restrict__ A = V.A;
     T* __restrict__ pn = V.p[par ^ 1];
     T* __restrict__ vn = V.v[par ^ 1];
-    double acc[2] = {0.0, 0.0};
-    const int G = gridDim.x;
-    const int lb = xcd_block(blockIdx.x, G);
-    for (int c = lb * blockDim.x + threadIdx.x; c < m.Nc; c += G * blockDim.x) {
-        T pc;
-        T rc;
+    T* __restrict__ rp = V.r;
+    T* __restrict__ xp = V.x;
+    double a0 = 0.0, a1 = 0.0;
+    const int lb = xcd_block(blockIdx.x, kKGrid);
+    for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
+        T pc, rc;
         if (FIRST) {
             rc = s[c];
             pc = rc;
         } else {
             rc = s[c] - tw * t[c];
-            V.x[c] = V.x[c] + ta * po[c] + tw * s[c];
+            xp[c] = xp[c] + ta * po[c] + tw * s[c];
             pc = rc + tb * (po[c] - tw * vo[c]);
         }
-        V.r[c] = rc;
+        rp[c] = rc;
         pn[c] = pc;
         T av;
-        if (FIRST) {
-            av = spmv_row<DIM, T>(m, V.A, c, [&](int j) { return s[j]; });
-        } else {
-            av = spmv_row<DIM, T>(m, V.A, c, [&](int j) {
-                return (s[j] - tw * t[j]) + tb * (po[j] - tw * vo[j]);
-            });
-        }
+        if (FIRST)
+            av = spmv_row<DIM, T>(m, A, c, [&](int j) { return s[j]; });
+        else
+            av = spmv_row<DIM, T>(m, A, c, [&](int j) { return (s[j] - tw * t[j]) + tb * (po[j] - tw * vo[j]); });
         vn[c] = av;
-        acc[0] += (double)V.rhat[c] * (double)av;
-        acc[1] += (double)rc * (double)rc;
+        a0 += (double)rh[c] * (double)av;
+        a1 += (double)rc * (double)rc;
     }
-    double tot[2];
-    if (grid_reduce<2>(acc, part, ks, tot) && threadIdx.x == 0) {
-        ks->rv = tot[0];
-        ks->rr = tot[1];
-        if (!FIRST) {
-            ks->omega = omega;
-            ks->rho = rho_new;
-        }
-        if (tot[1] <= ks->tol2 * ks->bb) {
-            ks->done = 1;
-        } else {
-            const double a = rho_new / tot[0];
-            const bool bad = !(tot[0] != 0.0) || !isfinite(a) || !isfinite(beta) ||
-                             fabs(rho_new) < 1e-30 * ks->rr0;
-            if (bad)
-                ks->done = 2;
-            else
-                ks->alpha = a;
-        }
+    double acc[2] = {a0, a1};
+    write_partials<2>(acc, K.part[1], K);
+    if (leader) {
+        *K.st[1] = *in;
+        K.st[1]->rho = rho_new;
+        K.st[1]->omega = omega;
     }
 }
 
 template <int DIM, typename T>
-__global__ __launch_bounds__(kBlock) void k_kS(MeshDev m, KVec<T> V, int par, double* part, KState* ks) {
-    if (ks->done) return;
-    const T ta = (T)ks->alpha;
+__global__ __launch_bounds__(kKBlock) void k_kS(MeshDev m, KVec<T> V, int par, KBufs K) {
+    const KState* __restrict__ in = K.st[1];
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    if (in->done) {
+        if (leader) *K.st[2] = *in;
+        return;
+    }
+    double tot[2];
+    reduce_partials<2>(K.part[1], K, tot);       // rhat.v, r.r
+    const double alpha = in->rho / tot[0];
+    int done = 0;
+    if (tot[1] <= in->tol2 * in->bb) {
+        done = 1;                                // x already holds the converged iterate
+    } else if (!(tot[0] != 0.0) || !isfinite(alpha)) {
+        done = 2;
+    }
+    if (done) {
+        if (leader) {
+            *K.st[2] = *in;
+            K.st[2]->rv = tot[0];
+            K.st[2]->rr = tot[1];
+            K.st[2]->done = done;
+        }
+        return;
+    }
+    const T ta = (T)alpha;
     const T* __restrict__ r = V.r;
     const T* __restrict__ vn = V.v[par ^ 1];
-    double acc[4] = {0.0, 0.0, 0.0, 0.0};
-    const int G = gridDim.x;
-    const int lb = xcd_block(blockIdx.x, G);
-    for (int c = lb * blockDim.x + threadIdx.x; c < m.Nc; c += G * blockDim.x) {
+    const T* __restrict__ rhp = V.rhat;
+    const T* __restrict__ A = V.A;
+    T* __restrict__ sp = V.s;
+    T* __restrict__ tp = V.t;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int lb = xcd_block(blockIdx.x, kKGrid);
+    for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
         const T sc = r[c] - ta * vn[c];
-        const T tc = spmv_row<DIM, T>(m, V.A, c, [&](int j) { return r[j] - ta * vn[j]; });
-        V.s[c] = sc;
-        V.t[c] = tc;
-        const double rh = (double)V.rhat[c];
-        acc[0] += (double)tc * (double)sc;
-        acc[1] += (double)tc * (double)tc;
-        acc[2] += rh * (double)sc;
-        acc[3] += rh * (double)tc;
+        const T tc = spmv_row<DIM, T>(m, A, c, [&](int j) { return r[j] - ta * vn[j]; });
+        sp[c] = sc;
+        tp[c] = tc;
+        const double rh = (double)rhp[c];
+        a0 += (double)tc * (double)sc;
+        a1 += (double)tc * (double)tc;
+        a2 += rh * (double)sc;
+        a3 += rh * (double)tc;
     }
-    double tot[4];
-    if (grid_reduce<4>(acc, part, ks, tot) && threadIdx.x == 0) {
-        ks->ts = tot[0];
-        ks->tt = tot[1];
-        ks->rsv = tot[2];
-        ks->rtv = tot[3];
-        ks->iter += 1;
-        if (!(tot[1] > 0.0)) ks->done = 2;
+    double acc[4] = {a0, a1, a2, a3};
+    write_partials<4>(acc, K.part[2], K);
+    if (leader) {
+        *K.st[2] = *in;
+        K.st[2]->rv = tot[0];
+        K.st[2]->rr = tot[1];
+        K.st[2]->alpha = alpha;
+        K.st[2]->iter = in->iter + 1;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// 2D stage kernels on LDS tiles.  A block of 512 threads owns a 64 x 8 tile
+// of cells; the operand of the stencil product (x, p' or s) is formed once
+// per tile-plus-halo cell (66 x 10) into LDS, coalesced along rows, and the
+// 9-point product then reads LDS only.  The owner of a tile cell also does
+// that cell's element-wise updates in the same pass.
+// ---------------------------------------------------------------------------
+
+constexpr int TX = 64, TY = 8, HX = TX + 2, HY = TY + 2, NH = HX * HY;
+static_assert(TX * TY == kKBlock, "one tile cell per thread");
+
+// cell index of mesh position (gx, gy) with periodic wrap; -1 outside
+__device__ __forceinline__ int halo_cell(const MeshDev& m, int gx, int gy) {
+    if (gx < 0) {
+        if (!m.periodic[0]) return -1;
+        gx += m.n[0];
+    } else if (gx >= m.n[0]) {
+        if (!m.periodic[0]) return -1;
+        gx -= m.n[0];
+    }
+    if (gy < 0) {
+        if (!m.periodic[1]) return -1;
+        gy += m.n[1];
+    } else if (gy >= m.n[1]) {
+        if (!m.periodic[1]) return -1;
+        gy -= m.n[1];
+    }
+    return gx + m.n[0] * gy;
+}
+
+template <typename T>
+__device__ __forceinline__ T stencil_lds(const T* __restrict__ A, size_t Nc, int c, const T* lds, int lx, int ly) {
+    T acc = 0;
+#pragma unroll
+    for (int s = 0; s < 9; ++s) acc += A[(size_t)s * Nc + c] * lds[(ly + s / 3) * HX + (lx + s % 3)];
+    return acc;
+}
+
+// Tiles of a block: a contiguous run [first, first + count) of the row-major
+// tile order, so consecutive tiles of a block share halo rows and the blocks
+// an XCD receives cover one contiguous band of the mesh.
+struct TileRun {
+    int first, count;
+};
+
+__device__ __forceinline__ TileRun tiles_of(const KBufs& K) {
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    const int first = lb * K.tpb;
+    int count = K.ntiles - first;
+    count = count < 0 ? 0 : (count > K.tpb ? K.tpb : count);
+    return TileRun{first, count};
+}
+
+__device__ __forceinline__ void tile_origin(const KBufs& K, int tile, int& tx0, int& ty0) {
+    tx0 = (tile % K.ntx) * TX;
+    ty0 = (tile / K.ntx) * TY;
+}
+
+template <typename T>
+__global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T> V, KBufs K) {
+    __shared__ T xl[NH];
+    const T* __restrict__ xp = V.x;
+    const T* __restrict__ bp = V.b;
+    const T* __restrict__ A = V.A;
+    T* __restrict__ sp = V.s;
+    T* __restrict__ rh = V.rhat;
+    const TileRun run = tiles_of(K);
+    double a0 = 0.0, a1 = 0.0;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    for (int k = 0; k < run.count; ++k) {
+        int tx0, ty0;
+        tile_origin(K, run.first + k, tx0, ty0);
+        for (int e = threadIdx.x; e < NH; e += kKBlock) {
+            const int j = halo_cell(m, tx0 + e % HX - 1, ty0 + e / HX - 1);
+            xl[e] = j >= 0 ? xp[j] : T(0);
+        }
+        __syncthreads();
+        const int gx = tx0 + lx, gy = ty0 + ly;
+        if (gx < m.n[0] && gy < m.n[1]) {
+            const int c = gx + m.n[0] * gy;
+            const T ax = stencil_lds<T>(A, (size_t)m.Nc, c, xl, lx, ly);
+            const T bc = bp[c];
+            const T r = bc - ax;
+            sp[c] = r;
+            rh[c] = r;
+            a0 += (double)r * (double)r;
+            a1 += (double)bc * (double)bc;
+        }
+        __syncthreads();
+    }
+    double v[2] = {a0, a1};
+    write_partials<2>(v, K.part[0], K);
+}
+
+template <typename T, bool FIRST>
+__global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T> V, int par, KBufs K) {
+    __shared__ T pl[NH];
+    const KState* __restrict__ in = K.st[2];
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    if (in->done) {
+        if (leader) *K.st[1] = *in;
+        return;
+    }
+    const double alpha = in->alpha;
+    double omega = 1.0, beta = 0.0, rho_new = in->rho;
+    if (!FIRST) {
+        double tot[4];
+        reduce_partials<4>(K.part[2], K, tot);   // t.s, t.t, rhat.s, rhat.t
+        omega = tot[0] / tot[1];
+        rho_new = tot[2] - omega * tot[3];
+        beta = (rho_new / in->rho) * (alpha / omega);
+        if (!(tot[1] > 0.0) || !isfinite(omega) || !isfinite(beta) || omega == 0.0 ||
+            fabs(rho_new) < 1e-30 * in->rr0) {
+            if (leader) {
+                *K.st[1] = *in;
+                K.st[1]->done = 2;
+            }
+            return;
+        }
+    }
+    const T ta = (T)alpha, tw = (T)omega, tb = (T)beta;
+    const T* __restrict__ sp = V.s;
+    const T* __restrict__ tp = V.t;
+    const T* __restrict__ po = V.p[par];
+    const T* __restrict__ vo = V.v[par];
+    const T* __restrict__ rh = V.rhat;
+    const T* __restrict__ A = V.A;
+    T* __restrict__ pn = V.p[par ^ 1];
+    T* __restrict__ vn = V.v[par ^ 1];
+    T* __restrict__ rp = V.r;
+    T* __restrict__ xp = V.x;
+    const TileRun run = tiles_of(K);
+    double a0 = 0.0, a1 = 0.0;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    for (int k = 0; k < run.count; ++k) {
+        int tx0, ty0;
+        tile_origin(K, run.first + k, tx0, ty0);
+        for (int e = threadIdx.x; e < NH; e += kKBlock) {
+            const int hx = e % HX, hy = e / HX;
+            const int gx = tx0 + hx - 1, gy = ty0 + hy - 1;
+            const int j = halo_cell(m, gx, gy);
+            T pv = 0;
+            if (j >= 0) {
+                const T sj = sp[j];
+                T rj, poj = 0;
+                if (FIRST) {
+                    rj = sj;
+                    pv = rj;
+                } else {
+                    const T tj = tp[j];
+                    poj = po[j];
+                    const T voj = vo[j];
+                    rj = sj - tw * tj;
+                    pv = rj + tb * (poj - tw * voj);
+                }
+                const bool own = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1];
+                if (own) {
+                    rp[j] = rj;
+                    pn[j] = pv;
+                    if (!FIRST) xp[j] = xp[j] + ta * poj + tw * sj;
+                    a1 += (double)rj * (double)rj;
+                }
+            }
+            pl[e] = pv;
+        }
+        __syncthreads();
+        const int gx = tx0 + lx, gy = ty0 + ly;
+        if (gx < m.n[0] && gy < m.n[1]) {
+            const int c = gx + m.n[0] * gy;
+            const T av = stencil_lds<T>(A, (size_t)m.Nc, c, pl, lx, ly);
+            vn[c] = av;
+            a0 += (double)rh[c] * (double)av;
+        }
+        __syncthreads();
+    }
+    double acc[2] = {a0, a1};
+    write_partials<2>(acc, K.part[1], K);
+    if (leader) {
+        *K.st[1] = *in;
+        K.st[1]->rho = rho_new;
+        K.st[1]->omega = omega;
+    }
+}
+
+template <typename T>
+__global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T> V, int par, KBufs K) {
+    __shared__ T sl[NH];
+    const KState* __restrict__ in = K.st[1];
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    if (in->done) {
+        if (leader) *K.st[2] = *in;
+        return;
+    }
+    double tot[2];
+    reduce_partials<2>(K.part[1], K, tot);       // rhat.v, r.r
+    const double alpha = in->rho / tot[0];
+    int done = 0;
+    if (tot[1] <= in->tol2 * in->bb) {
+        done = 1;                                // x already holds the converged iterate
+    } else if (!(tot[0] != 0.0) || !isfinite(alpha)) {
+        done = 2;
+    }
+    if (done) {
+        if (leader) {
+            *K.st[2] = *in;
+            K.st[2]->rv = tot[0];
+            K.st[2]->rr = tot[1];
+            K.st[2]->done = done;
+        }
+        return;
+    }
+    const T ta = (T)alpha;
+    const T* __restrict__ rp = V.r;
+    const T* __restrict__ vn = V.v[par ^ 1];
+    const T* __restrict__ rh = V.rhat;
+    const T* __restrict__ A = V.A;
+    T* __restrict__ sp = V.s;
+    T* __restrict__ tp = V.t;
+    const TileRun run = tiles_of(K);
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    for (int k = 0; k < run.count; ++k) {
+        int tx0, ty0;
+        tile_origin(K, run.first + k, tx0, ty0);
+        for (int e = threadIdx.x; e < NH; e += kKBlock) {
+            const int hx = e % HX, hy = e / HX;
+            const int gx = tx0 + hx - 1, gy = ty0 + hy - 1;
+            const int j = halo_cell(m, gx, gy);
+            T sv = 0;
+            if (j >= 0) {
+                sv = rp[j] - ta * vn[j];
+                const bool own = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1];
+                if (own) sp[j] = sv;
+            }
+            sl[e] = sv;
+        }
+        __syncthreads();
+        const int gx = tx0 + lx, gy = ty0 + ly;
+        if (gx < m.n[0] && gy < m.n[1]) {
+            const int c = gx + m.n[0] * gy;
+            const T tcv = stencil_lds<T>(A, (size_t)m.Nc, c, sl, lx, ly);
+            const T sc = sl[(ly + 1) * HX + lx + 1];
+            tp[c] = tcv;
+            const double r = (double)rh[c];
+            a0 += (double)tcv * (double)sc;
+            a1 += (double)tcv * (double)tcv;
+            a2 += r * (double)sc;
+            a3 += r * (double)tcv;
+        }
+        __syncthreads();
+    }
+    double acc[4] = {a0, a1, a2, a3};
+    write_partials<4>(acc, K.part[2], K);
+    if (leader) {
+        *K.st[2] = *in;
+        K.st[2]->rv = tot[0];
+        K.st[2]->rr = tot[1];
+        K.st[2]->alpha = alpha;
+        K.st[2]->iter = in->iter + 1;
     }
 }
 
@@ -296,20 +631,32 @@ __global__ void k_refine(int Nc, const float* __restrict__ d, double inv_scale, 
 // Host side
 // ---------------------------------------------------------------------------
 
+struct GraphEntry {
+    const void* A;
+    int fp32;
+    hipGraphExec_t exec;
+};
+
 struct KrylovWork {
     int Nc;
-    int grid;
-    double* part;          // [4][kMaxGrid]
-    KState* ks;            // device
-    KState* ks32;          // device (inner FP32 solve)
+    KBufs kb64, kb32;      // partials and stage states of the FP64 and FP32 solves
     KState* host;          // pinned [2]
     hipEvent_t ev[2];
+    hipEvent_t join;       // orders the solve stream after the caller's stream
+    hipStream_t st;        // solve stream (default priority, owned)
     KVec<double> v64;
     KVec<float> v32;
     double* beff;
     float* b32;
     int* bad_host;         // pinned
-    // optional timing of the stage kernels (events on the solve stream)
+    // replayed chunks of kGraphIters iterations (per operator and precision)
+    static constexpr int kGraphIters = 16;
+    static constexpr int kMaxGraphs = 16;
+    GraphEntry graphs[kMaxGraphs];
+    int ngraphs = 0;
+    int use_graphs = 1;
+    // optional timing of the stage kernels: start/stop events stamped by the
+    // kernel dispatch itself (hipExtLaunchKernelGGL)
     int profile = 0;
     static constexpr int kProf = 4096;
     hipEvent_t pev[kProf][4];
@@ -319,45 +666,98 @@ struct KrylovWork {
     long long cnt[2] = {0, 0};
 };
 
+// Enqueues one Bi-CGSTAB iteration (P- and S-stage) with operand parity par.
 template <int DIM, typename T>
-static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T>& V, KState* ks, int budget,
-                                 int check_every, hipStream_t st, int* iters_out, int* done_out) {
+static void enqueue_iteration(const MeshDev& m, const KVec<T>& V, const KBufs& K, int par, bool first,
+                              hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, hipEvent_t e3) {
+    const dim3 G(K.nblk), B(kKBlock);
+    if (m.dim == 2) {
+        if (first)
+            hipExtLaunchKernelGGL((k_t2_P<T, true>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        else
+            hipExtLaunchKernelGGL((k_t2_P<T, false>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_t2_S<T>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+    } else {
+        if (first)
+            hipExtLaunchKernelGGL((k_kP<DIM, T, true>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        else
+            hipExtLaunchKernelGGL((k_kP<DIM, T, false>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_kS<DIM, T>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+    }
+}
+
+// Graph of kGraphIters non-first iterations starting at parity 1 (an even
+// count, so every replay starts and ends at parity 1).
+template <int DIM, typename T>
+static hipError_t chunk_graph(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K,
+                              hipGraphExec_t* out) {
+    const int fp32 = sizeof(T) == 4;
+    for (int i = 0; i < w.ngraphs; ++i)
+        if (w.graphs[i].A == (const void*)V.A && w.graphs[i].fp32 == fp32) {
+            *out = w.graphs[i].exec;
+            return hipSuccess;
+        }
+    if (w.ngraphs == KrylovWork::kMaxGraphs) return hipErrorNotSupported;
+    hipError_t e = hipStreamBeginCapture(w.st, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) return e;
+    int par = 1;
+    for (int q = 0; q < KrylovWork::kGraphIters; ++q) {
+        enqueue_iteration<DIM, T>(m, V, K, par, false, w.st, nullptr, nullptr, nullptr, nullptr);
+        par ^= 1;
+    }
+    hipGraph_t g;
+    if ((e = hipStreamEndCapture(w.st, &g)) != hipSuccess) return e;
+    hipGraphExec_t ex;
+    e = hipGraphInstantiate(&ex, g, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(g);
+    if (e != hipSuccess) return e;
+    w.graphs[w.ngraphs++] = GraphEntry{(const void*)V.A, fp32, ex};
+    *out = ex;
+    return hipSuccess;
+}
+
+template <int DIM, typename T>
+static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K, int iter0,
+                                 int budget, int check_every, hipStream_t st, int* iters_out, int* done_out) {
     // Pipelined chunks: chunk q+1 is enqueued before chunk q's state is
-    // examined, so the GPU never waits for the host.  Kernels of a chunk
-    // return at once when the state says done.
+    // examined, so the GPU never waits for the host.  Stage kernels return at
+    // once when the state they read says done.  Without kernel timing, full
+    // chunks are replays of a captured graph.
     int par = 0;
     bool first = true;
     int chunk = 0, last = -1, launched = 0;
     hipError_t e = hipSuccess;
-    const int G = w.grid;
-    const int iter0 = w.host[0].iter;   // state before this call (host copy is current)
+    hipGraphExec_t graph = nullptr;
+    const bool timing = w.profile == 1;
+    if (!timing && w.use_graphs) {
+        if ((e = chunk_graph<DIM, T>(m, w, V, K, &graph)) != hipSuccess) graph = nullptr;
+    }
     w.np = 0;
     while (budget > 0) {
-        const int n = budget < check_every ? budget : check_every;
-        budget -= n;
-        for (int q = 0; q < n; ++q) {
-            const bool rec = w.profile == 1 && w.np < KrylovWork::kProf;
-            if (rec) {
-                w.pidx[w.np] = iter0 + launched;
-                (void)hipEventRecord(w.pev[w.np][0], st);
+        int n = budget < check_every ? budget : check_every;
+        const bool replay = graph && !first && par == 1 && budget >= KrylovWork::kGraphIters;
+        if (replay) {
+            n = KrylovWork::kGraphIters;
+            if ((e = hipGraphLaunch(graph, st)) != hipSuccess) return e;
+            launched += n;
+        } else {
+            if (graph && !first && par == 1 && n > 1) n = 1;   // keep a partial chunk short
+            for (int q = 0; q < n; ++q) {
+                const bool rec = timing && w.np < KrylovWork::kProf;
+                hipEvent_t* ev = rec ? w.pev[w.np] : nullptr;
+                if (rec) w.pidx[w.np] = iter0 + launched;
+                enqueue_iteration<DIM, T>(m, V, K, par, first, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr,
+                                          ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
+                if (rec) ++w.np;
+                ++launched;
+                first = false;
+                par ^= 1;
             }
-            if (first)
-                hipLaunchKernelGGL((k_kP<DIM, T, true>), dim3(G), dim3(kBlock), 0, st, m, V, par, w.part, ks);
-            else
-                hipLaunchKernelGGL((k_kP<DIM, T, false>), dim3(G), dim3(kBlock), 0, st, m, V, par, w.part, ks);
-            if (rec) (void)hipEventRecord(w.pev[w.np][1], st);
-            if (rec) (void)hipEventRecord(w.pev[w.np][2], st);
-            hipLaunchKernelGGL((k_kS<DIM, T>), dim3(G), dim3(kBlock), 0, st, m, V, par, w.part, ks);
-            if (rec) {
-                (void)hipEventRecord(w.pev[w.np][3], st);
-                ++w.np;
-            }
-            ++launched;
-            first = false;
-            par ^= 1;
         }
+        budget -= n;
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if ((e = hipMemcpyAsync(&w.host[chunk & 1], ks, sizeof(KState), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        if ((e = hipMemcpyAsync(&w.host[chunk & 1], K.st[2], sizeof(KState), hipMemcpyDeviceToHost, st)) !=
+            hipSuccess)
             return e;
         if ((e = hipEventRecord(w.ev[chunk & 1], st)) != hipSuccess) return e;
         last = chunk;
@@ -368,7 +768,7 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T>&
         ++chunk;
     }
     if (last < 0) {
-        *iters_out = 0;
+        *iters_out = iter0;
         *done_out = 0;
         return hipSuccess;
     }
@@ -391,34 +791,43 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T>&
     return hipSuccess;
 }
 
+// r = b - A x, rhat = r and the state the next P-stage starts from;
+// synchronises and returns that state.
 template <int DIM, typename T>
-static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T>& V, KState* ks, int with_bb, double tol2,
+static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K, int with_bb, double tol2,
                         hipStream_t st, KState* out) {
-    hipLaunchKernelGGL((k_kinit<DIM, T>), dim3(w.grid), dim3(kBlock), 0, st, m, V, w.part, ks, with_bb, tol2);
-    hipError_t e = hipMemcpyAsync(&w.host[0], ks, sizeof(KState), hipMemcpyDeviceToHost, st);
+    if (m.dim == 2)
+        hipLaunchKernelGGL((k_t2_init<T>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+    else
+        hipLaunchKernelGGL((k_kinit<DIM, T>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+    hipLaunchKernelGGL(k_kfinish, dim3(1), dim3(kKBlock), 0, st, K, with_bb, tol2, with_bb ? 0 : 1);
+    hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&w.host[0], K.st[2], sizeof(KState), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     *out = w.host[0];
-    return hipGetLastError();
+    return hipSuccess;
 }
 
-// Plain Bi-CGSTAB with restarts; returns iterations, restarts, rr/bb.
+// Bi-CGSTAB with restarts from the true residual; returns iterations,
+// restarts, ||r||/||b|| of the final true residual.
 template <int DIM, typename T>
-static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T>& V, KState* ks, double tol, int max_iter,
-                           int check_every, hipStream_t st, int* iters, int* restarts, double* rel, int* conv) {
+static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K, double tol,
+                           int max_iter, int check_every, hipStream_t st, int* iters, int* restarts, double* rel,
+                           int* conv) {
     KState h;
-    hipError_t e = kinit<DIM, T>(m, w, V, ks, 1, tol * tol, st, &h);
+    hipError_t e = kinit<DIM, T>(m, w, V, K, 1, tol * tol, st, &h);
     if (e != hipSuccess) return e;
     *restarts = 0;
     *iters = 0;
     const double bb = h.bb;
     while (!h.done && h.iter < max_iter) {
         int it = 0, done = 0;
-        if ((e = run_iterations<DIM, T>(m, w, V, ks, max_iter - h.iter, check_every, st, &it, &done)) != hipSuccess)
+        if ((e = run_iterations<DIM, T>(m, w, V, K, h.iter, max_iter - h.iter, check_every, st, &it, &done)) !=
+            hipSuccess)
             return e;
-        // confirm with the true residual; restarts from it if needed
-        if ((e = kinit<DIM, T>(m, w, V, ks, 0, tol * tol, st, &h)) != hipSuccess) return e;
-        h.iter = it;
+        // confirm with the true residual; restart from it if needed
+        if ((e = kinit<DIM, T>(m, w, V, K, 0, tol * tol, st, &h)) != hipSuccess) return e;
         if (!h.done) *restarts += 1;
     }
     *iters = h.iter;
@@ -447,7 +856,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     if (sp.precision == MCD_PREC_FP64) {
         int it = 0, rst = 0, conv = 0;
         double rel = 0.0;
-        if ((e = bicgstab<DIM, double>(m, w, V, w.ks, sp.tol, sp.max_iter, check, st, &it, &rst, &rel, &conv)) !=
+        if ((e = bicgstab<DIM, double>(m, w, V, w.kb64, sp.tol, sp.max_iter, check, st, &it, &rst, &rel, &conv)) !=
             hipSuccess)
             return e;
         out->iterations = it;
@@ -460,7 +869,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         KVec<float> V32 = w.v32;
         V32.A = set.amat32;
         KState h;
-        if ((e = kinit<DIM, double>(m, w, V, w.ks, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
+        if ((e = kinit<DIM, double>(m, w, V, w.kb64, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
         const double bb = h.bb;
         int total = 0, outer = 0, rst_total = 0;
         while (!h.done && outer < sp.max_outer && total < sp.max_iter) {
@@ -468,13 +877,13 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
             hipLaunchKernelGGL(k_to32, dim3(g), dim3(kBlock), 0, st, m.Nc, V.s, 1.0 / nr, (float*)V32.b, V32.x);
             int it = 0, rst = 0, conv = 0;
             double rel = 0.0;
-            if ((e = bicgstab<DIM, float>(m, w, V32, w.ks32, sp.inner_tol, sp.max_iter - total, check, st, &it, &rst,
+            if ((e = bicgstab<DIM, float>(m, w, V32, w.kb32, sp.inner_tol, sp.max_iter - total, check, st, &it, &rst,
                                           &rel, &conv)) != hipSuccess)
                 return e;
             total += it;
             rst_total += rst;
             hipLaunchKernelGGL(k_refine, dim3(g), dim3(kBlock), 0, st, m.Nc, V32.x, nr, V.x);
-            if ((e = kinit<DIM, double>(m, w, V, w.ks, 0, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
+            if ((e = kinit<DIM, double>(m, w, V, w.kb64, 0, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
             ++outer;
         }
         out->iterations = total;
@@ -488,10 +897,18 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     return hipGetLastError();
 }
 
+// The solve runs on the workspace's own stream (ordered after the caller's
+// stream by an event) so that its chunks can be captured and replayed as
+// graphs; it returns after that stream is idle.
 hipError_t solve_ppe_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
-                          double* p, const SolveParams& sp, SolveOut* out, int* bad, hipStream_t st) {
-    return m.dim == 2 ? solve_dim<2>(m, set, w, rhs, fneu, p, sp, out, bad, st)
-                      : solve_dim<3>(m, set, w, rhs, fneu, p, sp, out, bad, st);
+                          double* p, const SolveParams& sp, SolveOut* out, int* bad, hipStream_t caller) {
+    hipError_t e = hipEventRecord(w.join, caller);
+    if (e != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(w.st, w.join, 0)) != hipSuccess) return e;
+    e = m.dim == 2 ? solve_dim<2>(m, set, w, rhs, fneu, p, sp, out, bad, w.st)
+                   : solve_dim<3>(m, set, w, rhs, fneu, p, sp, out, bad, w.st);
+    const hipError_t e2 = hipStreamSynchronize(w.st);
+    return e != hipSuccess ? e : e2;
 }
 
 template <typename T>
@@ -514,19 +931,34 @@ static void free_vec(KVec<T>& V) {
         if (q) (void)hipFree(q);
 }
 
-hipError_t krylov_alloc(int Nc, KrylovWork** out) {
+hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     KrylovWork* w = new KrylovWork{};
     *out = w;
+    const int Nc = m.Nc;
     w->Nc = Nc;
-    int g = (Nc + kBlock - 1) / kBlock;
-    w->grid = g > kMaxGrid ? kMaxGrid : (g < 8 ? 8 : (g + 7) / 8 * 8);
-    if (w->grid > kMaxGrid) w->grid = kMaxGrid;
     hipError_t e;
-    if ((e = hipMalloc((void**)&w->part, 4 * kMaxGrid * sizeof(double))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&w->ks, sizeof(KState))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&w->ks32, sizeof(KState))) != hipSuccess) return e;
-    if ((e = hipMemset(w->ks, 0, sizeof(KState))) != hipSuccess) return e;
-    if ((e = hipMemset(w->ks32, 0, sizeof(KState))) != hipSuccess) return e;
+    // 2D: one block per 64 x 8 tile; 3D: a fixed grid with grid-stride loops
+    int ntx = 0, nblk = kKGrid, ntiles = 0, tpb = 0;
+    if (m.dim == 2) {
+        ntx = (m.n[0] + TX - 1) / TX;
+        ntiles = ntx * ((m.n[1] + TY - 1) / TY);
+        nblk = ntiles < kKGrid ? ntiles : kKGrid;
+        tpb = (ntiles + nblk - 1) / nblk;
+    }
+    const int cap = kKGrid;
+    for (KBufs* K : {&w->kb64, &w->kb32}) {
+        K->nblk = nblk;
+        K->cap = cap;
+        K->ntx = ntx;
+        K->ntiles = ntiles;
+        K->tpb = tpb;
+        for (int q = 0; q < 3; ++q) {
+            if ((e = hipMalloc((void**)&K->part[q], 4 * (size_t)cap * sizeof(double))) != hipSuccess) return e;
+            if ((e = hipMemset(K->part[q], 0, 4 * (size_t)cap * sizeof(double))) != hipSuccess) return e;
+            if ((e = hipMalloc((void**)&K->st[q], sizeof(KState))) != hipSuccess) return e;
+            if ((e = hipMemset(K->st[q], 0, sizeof(KState))) != hipSuccess) return e;
+        }
+    }
     if ((e = hipHostMalloc((void**)&w->host, 2 * sizeof(KState), hipHostMallocDefault)) != hipSuccess) return e;
     for (int i = 0; i < 2; ++i)
         if ((e = hipEventCreateWithFlags(&w->ev[i], hipEventDisableTiming)) != hipSuccess) return e;
@@ -536,6 +968,8 @@ hipError_t krylov_alloc(int Nc, KrylovWork** out) {
     if ((e = hipMalloc((void**)&w->b32, (size_t)Nc * sizeof(float))) != hipSuccess) return e;
     w->v32.b = w->b32;
     if ((e = hipHostMalloc((void**)&w->bad_host, sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
+    if ((e = hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&w->join, hipEventDisableTiming)) != hipSuccess) return e;
     return hipSuccess;
 }
 
@@ -566,9 +1000,11 @@ void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms
 
 void krylov_free(KrylovWork* w) {
     if (!w) return;
-    if (w->part) (void)hipFree(w->part);
-    if (w->ks) (void)hipFree(w->ks);
-    if (w->ks32) (void)hipFree(w->ks32);
+    for (KBufs* K : {&w->kb64, &w->kb32})
+        for (int q = 0; q < 3; ++q) {
+            if (K->part[q]) (void)hipFree(K->part[q]);
+            if (K->st[q]) (void)hipFree(K->st[q]);
+        }
     if (w->host) (void)hipHostFree(w->host);
     for (int i = 0; i < 2; ++i)
         if (w->ev[i]) (void)hipEventDestroy(w->ev[i]);
@@ -577,6 +1013,9 @@ void krylov_free(KrylovWork* w) {
     if (w->beff) (void)hipFree(w->beff);
     if (w->b32) (void)hipFree(w->b32);
     if (w->bad_host) (void)hipHostFree(w->bad_host);
+    for (int i = 0; i < w->ngraphs; ++i) (void)hipGraphExecDestroy(w->graphs[i].exec);
+    if (w->join) (void)hipEventDestroy(w->join);
+    if (w->st) (void)hipStreamDestroy(w->st);
     if (w->profile)
         for (int k = 0; k < KrylovWork::kProf; ++k)
             for (int q = 0; q < 4; ++q) (void)hipEventDestroy(w->pev[k][q]);

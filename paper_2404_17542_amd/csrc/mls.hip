@@ -77,6 +77,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
 #pragma unroll
         for (int q = 0; q < NP; ++q) M[q] = 0.0;
         uint32_t vm = 0, nm = 0;
+        int nrows = 0;
         if (rc != MCD_ROLE_VOID) {
             for (int s = 0; s < S; ++s) {
                 int j;
@@ -87,6 +88,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                     vm |= 1u << s;
                 else
                     nm |= 1u << (s == CEN ? S : s);
+                nrows += (w > 0.0) ? 1 : 0;
                 int q = 0;
 #pragma unroll
                 for (int r = 0; r < NB; ++r) {
@@ -102,12 +104,14 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
         for (int r = 0; r < NB; ++r) tr += M[r * (r + 1) / 2 + r];
         bool sing = (rc == MCD_ROLE_VOID);
         if (!sing) {
+            // fewer rows of positive weight than basis terms: M is rank-deficient
+            if (nrows < NB) sing = true;
 #pragma unroll
             for (int jc = 0; jc < NB; ++jc) {
                 double dsum = M[jc * (jc + 1) / 2 + jc];
 #pragma unroll
                 for (int k = 0; k < jc; ++k) dsum -= M[jc * (jc + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
-                if (!(dsum > 1e-14 * tr / NB)) {
+                if (!(dsum > 1e-12 * tr / NB)) {
                     sing = true;
                     dsum = 1.0;
                 }

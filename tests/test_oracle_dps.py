@@ -147,3 +147,28 @@ def test_transition_codes():
     prev = np.array([0, 0, -1, -1, 2, 2, 0, -1, 2], np.int8)
     new = np.array([0, -1, 0, -1, 0, -1, 2, 2, 2], np.int8)
     assert list(O.transition_codes(prev, new)) == [0, 1, 3, 4, 6, 7, 2, 5, 8]
+
+
+def _perturbed_regular_3d(kappa, sweeps):
+    n = 8
+    m = O.Mesh(3, (n, n, n), (0.0,) * 3, 1.0, (True,) * 3)
+    pos = inputs.cell_centroids(m.n, m.origin, 1.0)
+    rng = np.random.default_rng(0)
+    pos = pos + 0.05 * rng.uniform(-1, 1, pos.shape)
+    role = np.full(m.Nc, O.INNER, np.int8)
+    consts = O.RelaxConsts.make(1.0, kappa)
+    mxs = []
+    for _ in range(sweeps):
+        pos, mx = O.relax_sweep(m, consts, [], role, np.arange(m.Nc), pos)
+        mxs.append(mx)
+    return mxs
+
+
+def test_relaxation_stability_3d_reading():
+    """Reading for 3D: with the 26 springs of the 3x3x3 block the explicit
+    step is stable for kappa = 1/10 (perturbations of a regular grid decay)
+    and unstable for the 2D value 1/5 (they grow until the mesh clamp)."""
+    stable = _perturbed_regular_3d(0.1, 30)
+    assert stable[-1] < 0.2 * stable[0]
+    unstable = _perturbed_regular_3d(0.2, 30)
+    assert max(unstable[5:]) > 2 * unstable[0]
