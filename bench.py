@@ -35,6 +35,19 @@ def stage_bytes(n_unknown, dim, value_bytes):
     return n_unknown * (slots + 5) * value_bytes
 
 
+def workload_name(case, n_active, precision):
+    grid = "x".join(str(v) for v in case.n)
+    if case.name.startswith("C1"):
+        what = "periodic Taylor-Green vortex"
+    elif case.name.startswith("C2"):
+        what = "oscillating cylinder (D=1, A=0.2D, moving DPs and roles)"
+    else:
+        what = "moving sphere (D=0.25, A=0.2D, moving DPs and roles)"
+    stencil = "3x3" if case.dim == 2 else "3x3x3"
+    return (f"{what} {grid}, {n_active} active DPs (one per cell, +-0.2 l0 jitter), Re=100, "
+            f"quadratic MLS {stencil}, PPE Bi-CGSTAB to 1e-8 ({precision})")
+
+
 def cpu_baseline(case, steps):
     from threadpoolctl import threadpool_limits
 
@@ -58,7 +71,10 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--n", type=int, default=512)
+    ap.add_argument("--workload", choices=["tgv", "cylinder", "sphere"], default="tgv",
+                    help="tgv: 512^2 periodic Taylor-Green (default line); cylinder: 1024^2 oscillating "
+                         "cylinder; sphere: 128^3 moving sphere")
+    ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -78,15 +94,20 @@ def main():
 
     torch.cuda.set_device(0)
     mcd.load()
-    case = configs.c1_taylor_green(n=args.n, steps=args.steps)
+    if args.workload == "tgv":
+        case = configs.c1_taylor_green(n=args.n or 512, steps=args.steps)
+    elif args.workload == "cylinder":
+        case = configs.c2_oscillating_cylinder(n=args.n or 1024, steps=args.steps)
+    else:
+        case = configs.c4_moving_sphere(n=args.n or 128, steps=args.steps)
     prec = mcd.PREC_FP64 if args.precision == "fp64" else mcd.PREC_FP32_REFINE
     log(f"setting up {case.name}")
     sim = GpuSim(case, precision=prec, update_info=False)
-    n_active = sim.n_active()
     for _ in range(args.warmup):
         sim.step()
     torch.cuda.synchronize()
     log(f"warm-up done ({args.warmup} steps)")
+    n_active = sim.n_active()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for k in range(args.steps):
@@ -111,7 +132,7 @@ def main():
         torch.cuda.synchronize()
         prof = sim.ctx.profile_read(reset=True)
         sim.ctx.profile(False)
-        n_unknown = n_active - (1 if case.pin_first else 0)
+        n_unknown = int(sim.ctx_unknown_count()) if hasattr(sim, "ctx_unknown_count") else n_active
         vb = 8 if args.precision == "fp64" else 4
         bytes_per = stage_bytes(n_unknown, case.dim, vb)
         avg_s = prof["s_ms"] / max(prof["s_n"], 1) * 1e-3
@@ -126,9 +147,7 @@ def main():
            "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
            "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
            "data": "synthetic",
-           "config": {"workload": f"periodic Taylor-Green vortex {case.n[0]}x{case.n[1]}, {n_active} DPs "
-                                  f"(one per cell, +-0.2 l0 jitter), Re=100, dt=0.2 l0, quadratic MLS 3x3, "
-                                  f"PPE Bi-CGSTAB to 1e-8 ({args.precision})",
+           "config": {"workload": workload_name(case, n_active, args.precision),
                       "dps": n_active, "ppe_iters_per_step": sum(iters) / len(iters), "max_true_rel_res": worst},
            "roofline": roofline}
     if not args.no_cpu_baseline and args.cpu_steps > 0:

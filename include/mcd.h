@@ -232,9 +232,11 @@ typedef struct {
     int max_iter;        /* total Bi-CGSTAB iterations (all restarts/refinements) */
     int precision;       /* MCD_PREC_FP64 or MCD_PREC_FP32_REFINE */
     int guess;           /* MCD_GUESS_ZERO or MCD_GUESS_CALLER (p on entry) */
-    double inner_tol;    /* FP32 inner solve tolerance (FP32_REFINE) */
+    double inner_tol;    /* FP32 inner solve: relative recurrence residual per refinement step
+                            (FP32_REFINE; about 1e-2, since FP32 Krylov stalls near cond(A) u_32) */
     int max_outer;       /* refinement steps (FP32_REFINE) */
-    int check_every;     /* iterations between host convergence checks */
+    int check_every;     /* iterations between host convergence checks (16 = graph chunk) */
+    int max_inner;       /* cap on inner iterations per refinement step (0 = none) */
 } mcd_solve_opts;
 
 typedef struct {

@@ -257,6 +257,7 @@ struct SolveParams {
     double inner_tol;
     int max_outer;
     int check_every;
+    int max_inner;
 };
 struct SolveOut {
     int iterations, restarts, refinements, converged;

@@ -648,6 +648,7 @@ struct KrylovWork {
     KVec<float> v32;
     double* beff;
     float* b32;
+    double* xsave;         // iterate before a refinement step
     int* bad_host;         // pinned
     // replayed chunks of kGraphIters iterations (per operator and precision)
     static constexpr int kGraphIters = 16;
@@ -814,7 +815,7 @@ static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const
 template <int DIM, typename T>
 static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K, double tol,
                            int max_iter, int check_every, hipStream_t st, int* iters, int* restarts, double* rel,
-                           int* conv) {
+                           int* conv, bool confirm = true) {
     KState h;
     hipError_t e = kinit<DIM, T>(m, w, V, K, 1, tol * tol, st, &h);
     if (e != hipSuccess) return e;
@@ -826,6 +827,14 @@ static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T>& V, co
         if ((e = run_iterations<DIM, T>(m, w, V, K, h.iter, max_iter - h.iter, check_every, st, &it, &done)) !=
             hipSuccess)
             return e;
+        if (!confirm) {
+            // inner solve of the refinement: the FP64 outer residual is the check
+            h = w.host[0];
+            h.iter = it;
+            h.done = done == 1 ? 1 : 0;
+            h.rr = 0.0;
+            break;
+        }
         // confirm with the true residual; restart from it if needed
         if ((e = kinit<DIM, T>(m, w, V, K, 0, tol * tol, st, &h)) != hipSuccess) return e;
         if (!h.done) *restarts += 1;
@@ -865,26 +874,59 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         out->rel = rel;
         out->bnorm = sqrt(w.host[0].bb);
     } else {
-        // FP64 iterative refinement around an FP32 Bi-CGSTAB (FP64 dots)
+        // FP64 iterative refinement around an FP32 Bi-CGSTAB (FP64 dots).
+        // A correction that does not lower the FP64 true residual is undone
+        // and the inner tolerance loosened; after two such rejections the
+        // solve finishes with FP64 Bi-CGSTAB from the current iterate, so the
+        // tolerance is always met on the FP64 operator.
         KVec<float> V32 = w.v32;
         V32.A = set.amat32;
         KState h;
         if ((e = kinit<DIM, double>(m, w, V, w.kb64, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
         const double bb = h.bb;
-        int total = 0, outer = 0, rst_total = 0;
+        int total = 0, outer = 0, rst_total = 0, rejected = 0, fallback = 0;
+        double itol = sp.inner_tol;
         while (!h.done && outer < sp.max_outer && total < sp.max_iter) {
             const double nr = sqrt(h.rr);
+            const double rr_old = h.rr;
+            if ((e = hipMemcpyAsync(w.xsave, V.x, (size_t)m.Nc * sizeof(double), hipMemcpyDeviceToDevice, st)) !=
+                hipSuccess)
+                return e;
             hipLaunchKernelGGL(k_to32, dim3(g), dim3(kBlock), 0, st, m.Nc, V.s, 1.0 / nr, (float*)V32.b, V32.x);
             int it = 0, rst = 0, conv = 0;
             double rel = 0.0;
-            if ((e = bicgstab<DIM, float>(m, w, V32, w.kb32, sp.inner_tol, sp.max_iter - total, check, st, &it, &rst,
-                                          &rel, &conv)) != hipSuccess)
+            const int left = sp.max_iter - total;
+            const int cap = sp.max_inner > 0 && sp.max_inner < left ? sp.max_inner : left;
+            if ((e = bicgstab<DIM, float>(m, w, V32, w.kb32, itol, cap, check, st, &it, &rst, &rel, &conv, false)) !=
+                hipSuccess)
                 return e;
             total += it;
             rst_total += rst;
             hipLaunchKernelGGL(k_refine, dim3(g), dim3(kBlock), 0, st, m.Nc, V32.x, nr, V.x);
             if ((e = kinit<DIM, double>(m, w, V, w.kb64, 0, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
             ++outer;
+            if (!(h.rr < rr_old)) {
+                if ((e = hipMemcpyAsync(V.x, w.xsave, (size_t)m.Nc * sizeof(double), hipMemcpyDeviceToDevice, st)) !=
+                    hipSuccess)
+                    return e;
+                if ((e = kinit<DIM, double>(m, w, V, w.kb64, 0, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
+                itol = itol * 3.0 < 0.5 ? itol * 3.0 : 0.5;
+                if (++rejected >= 2) {
+                    fallback = 1;
+                    break;
+                }
+            }
+        }
+        if (fallback && !h.done && total < sp.max_iter) {
+            int it = 0, rst = 0, conv = 0;
+            double rel = 0.0;
+            if ((e = bicgstab<DIM, double>(m, w, V, w.kb64, sp.tol, sp.max_iter - total, check, st, &it, &rst, &rel,
+                                           &conv)) != hipSuccess)
+                return e;
+            total += it;
+            rst_total += rst + 1;
+            h.done = conv ? 1 : 0;
+            h.rr = rel * rel * bb;
         }
         out->iterations = total;
         out->restarts = rst_total;
@@ -966,6 +1008,7 @@ hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     if ((e = alloc_vec(w->v32, Nc)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->beff, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->b32, (size_t)Nc * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&w->xsave, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
     w->v32.b = w->b32;
     if ((e = hipHostMalloc((void**)&w->bad_host, sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
     if ((e = hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking)) != hipSuccess) return e;
@@ -1012,6 +1055,7 @@ void krylov_free(KrylovWork* w) {
     free_vec(w->v32);
     if (w->beff) (void)hipFree(w->beff);
     if (w->b32) (void)hipFree(w->b32);
+    if (w->xsave) (void)hipFree(w->xsave);
     if (w->bad_host) (void)hipHostFree(w->bad_host);
     for (int i = 0; i < w->ngraphs; ++i) (void)hipGraphExecDestroy(w->graphs[i].exec);
     if (w->join) (void)hipEventDestroy(w->join);

@@ -58,7 +58,8 @@ class UpdateInfo(C.Structure):
 
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
-                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int)]
+                ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
+                ("max_inner", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -283,10 +284,14 @@ class Context:
                                          _ptr(role, N, torch.int8), arr, n, V(u, D)), "mcd_project")
 
     def solve_ppe(self, set_id, rhs, p, neumann_f=None, tol=1e-8, max_iter=20000, precision=PREC_FP64,
-                  guess=GUESS_ZERO, inner_tol=1e-4, max_outer=30, check_every=16, raise_on_fail=True):
+                  guess=GUESS_ZERO, inner_tol=1e-2, max_outer=40, check_every=16, max_inner=None,
+                  raise_on_fail=True):
         o = SolveOpts()
         o.tol, o.max_iter, o.precision, o.guess = tol, int(max_iter), int(precision), int(guess)
         o.inner_tol, o.max_outer, o.check_every = inner_tol, int(max_outer), int(check_every)
+        if max_inner is None:
+            max_inner = max(200, int(4 * self.Nc ** (1.0 / self.dim)))
+        o.max_inner = int(max_inner)
         info = SolveInfo()
         N, V = self.Nc, self._vec
         st = self.lib.mcd_solve_ppe(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), C.byref(o),

@@ -121,6 +121,14 @@ class GpuSim:
         self.log.append(rec)
         return rec
 
+    def ctx_unknown_count(self):
+        """PPE unknowns of the current step (inner and Neumann DPs, minus a pin)."""
+        unk = self.role == M.ROLE_INNER
+        for bid, typ in self.case.bc_pressure.items():
+            if typ == M.BC_NEUMANN:
+                unk |= self.role == bid
+        return int(unk.sum().item()) - (1 if self.case.pin_first else 0)
+
     def n_active(self):
         return int((self.role != M.ROLE_VOID).sum().item())
 
