@@ -259,6 +259,45 @@ mcd_status mcd_solve_ppe(mcd_ctx* ctx, int set, const double* rhs, const double*
                          double* p, const mcd_solve_opts* opts, mcd_solve_info* info);
 
 /* ---------------------------------------------------------------------
+ * Learned PPE initial guess (2D): a U-Net on the background mesh.
+ * One DP per cell makes the DP arrays NHWC images (row y, column x).
+ * Inputs: b / rms(b), p_prev / rms(b) (the warm start), one-hot roles
+ * (inner, body, wall); output h; guess = p_prev + rms(b) h at unknown cells
+ * (FP64).  Levels L: per level two 3x3 convolutions with ReLU, 2x2 mean
+ * pooling down, nearest 2x upsampling and concatenation with the skip up,
+ * a 3x3 head to one channel.  BF16 weights and activations, FP32
+ * accumulation on the matrix cores; FP32 master weights trained with Adam.
+ * Parameters: flat FP32 vector, convolutions in the order enc0a, enc0b, ...,
+ * enc(L-1)b, dec(L-2)a, dec(L-2)b, ..., dec0a, dec0b, head, each W[9][cin][cout]
+ * (tap t = 3 dy + dx, offset (dx - 1, dy - 1)) then b[cout].
+ * ------------------------------------------------------------------- */
+
+typedef struct mcd_model mcd_model;
+
+/* channels: host array of `levels` (2..5) widths, multiples of 16 in
+ * [16, 256]; the mesh must be divisible by 2^(levels-1).  body_id: role id
+ * of the body for the one-hot input.  Weights start at zero (set them). */
+mcd_status mcd_model_create(mcd_ctx* ctx, int levels, const int* channels, int body_id, mcd_model** out);
+void mcd_model_destroy(mcd_model* model);
+size_t mcd_model_num_params(const mcd_model* model);
+/* host arrays of mcd_model_num_params floats; set resets the optimiser */
+mcd_status mcd_model_set_params(mcd_model* model, const float* theta, size_t n);
+mcd_status mcd_model_get_params(mcd_model* model, float* theta, size_t n);
+/* gradient of the loss of the last training step (host array) */
+mcd_status mcd_model_get_grads(mcd_model* model, float* grad, size_t n);
+/* copy of the head output h [Nc] of the last forward pass (device, FP32) */
+mcd_status mcd_model_output(mcd_model* model, float* h);
+/* p_out := p_prev + rms(b) h at unknown cells (rows of bc); rhs, p_prev,
+ * p_out [Nc] f64, role [Nc] i8 (device); bc host. */
+mcd_status mcd_model_infer(mcd_model* model, const double* rhs, const double* p_prev, const int8_t* role,
+                           const mcd_bc_table* bc, double* p_out);
+/* One Adam step (lr > 0; lr = 0 computes the gradient only) on the loss
+ * sum_unknown (p_prev/rms + h - p_target/rms)^2 / sum_unknown (p_target/rms)^2.
+ * loss: host, nullable (synchronises when given). */
+mcd_status mcd_model_train_step(mcd_model* model, const double* rhs, const double* p_prev, const double* p_target,
+                                const int8_t* role, const mcd_bc_table* bc, double lr, double* loss);
+
+/* ---------------------------------------------------------------------
  * Kernel timing (measurement aid)
  * ------------------------------------------------------------------- */
 

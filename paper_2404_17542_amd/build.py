@@ -22,6 +22,7 @@ SOURCES = {
     "mls.hip": [],
     "apply.hip": [],
     "krylov.hip": [],
+    "unet.hip": [],
     "api.hip": [],
 }
 

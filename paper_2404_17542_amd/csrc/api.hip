@@ -460,6 +460,101 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
     return MCD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Learned initial guess
+// ---------------------------------------------------------------------------
+
+struct mcd_model {
+    mcd_ctx* ctx;
+    UNet* net;
+};
+
+mcd_status mcd_model_create(mcd_ctx* c, int levels, const int* channels, int body_id, mcd_model** out) {
+    if (!c || !channels || !out) return MCD_ERR_ARG;
+    *out = nullptr;
+    if (c->dim != 2) return fail(c, MCD_ERR_ARG, "mcd_model_create: the network is 2D%s");
+    if (levels < 2 || levels > 5) return fail(c, MCD_ERR_ARG, "mcd_model_create: levels must be 2..5%s");
+    const int H = c->m.n[1], W = c->m.n[0];
+    if ((H % (1 << (levels - 1))) || (W % (1 << (levels - 1))))
+        return fail(c, MCD_ERR_ARG, "mcd_model_create: mesh not divisible by 2^(levels-1)%s");
+    for (int l = 0; l < levels; ++l)
+        if (channels[l] < 16 || channels[l] > 256 || channels[l] % 16)
+            return fail(c, MCD_ERR_ARG, "mcd_model_create: channels must be multiples of 16 in [16, 256]%s");
+    if (body_id < 1 || body_id >= MCD_MAX_IDS) return fail(c, MCD_ERR_ARG, "mcd_model_create: bad body id%s");
+    UNet* u = nullptr;
+    hipError_t e = unet_create(H, W, levels, channels, body_id, c->desc.walls ? c->desc.wall_id : -2, &u);
+    if (e != hipSuccess) {
+        unet_free(u);
+        return e == hipErrorOutOfMemory ? MCD_ERR_OOM : hipfail(c, e, "mcd_model_create");
+    }
+    *out = new mcd_model{c, u};
+    return MCD_OK;
+}
+
+void mcd_model_destroy(mcd_model* md) {
+    if (!md) return;
+    (void)hipStreamSynchronize(md->ctx->stream);
+    unet_free(md->net);
+    delete md;
+}
+
+size_t mcd_model_num_params(const mcd_model* md) { return md ? unet_nparams(*md->net) : 0; }
+
+mcd_status mcd_model_set_params(mcd_model* md, const float* theta, size_t n) {
+    if (!md || !theta || n != unet_nparams(*md->net)) return MCD_ERR_ARG;
+    mcd_ctx* c = md->ctx;
+    HIPCHK(c, hipMemcpyAsync(unet_theta(*md->net), theta, n * 4, hipMemcpyHostToDevice, c->stream), "set_params");
+    HIPCHK(c, unet_weights_to_bf16(*md->net, c->stream), "set_params");
+    unet_reset_optimizer(*md->net, c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream), "set_params");
+    return MCD_OK;
+}
+
+mcd_status mcd_model_get_params(mcd_model* md, float* theta, size_t n) {
+    if (!md || !theta || n != unet_nparams(*md->net)) return MCD_ERR_ARG;
+    mcd_ctx* c = md->ctx;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "get_params");
+    HIPCHK(c, hipMemcpy(theta, unet_theta(*md->net), n * 4, hipMemcpyDeviceToHost), "get_params");
+    return MCD_OK;
+}
+
+mcd_status mcd_model_get_grads(mcd_model* md, float* grad, size_t n) {
+    if (!md || !grad || n != unet_nparams(*md->net)) return MCD_ERR_ARG;
+    mcd_ctx* c = md->ctx;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "get_grads");
+    HIPCHK(c, hipMemcpy(grad, unet_grad(*md->net), n * 4, hipMemcpyDeviceToHost), "get_grads");
+    return MCD_OK;
+}
+
+mcd_status mcd_model_output(mcd_model* md, float* h) {
+    if (!md || !h) return MCD_ERR_ARG;
+    mcd_ctx* c = md->ctx;
+    HIPCHK(c, hipMemcpyAsync(h, unet_head_out(*md->net), c->Nc * 4, hipMemcpyDeviceToDevice, c->stream), "output");
+    return MCD_OK;
+}
+
+mcd_status mcd_model_infer(mcd_model* md, const double* rhs, const double* p_prev, const int8_t* role,
+                           const mcd_bc_table* bc, double* p_out) {
+    if (!md || !rhs || !p_prev || !role || !p_out) return MCD_ERR_ARG;
+    mcd_ctx* c = md->ctx;
+    BcDev b;
+    if (!make_bc(bc, &b)) return fail(c, MCD_ERR_ARG, "mcd_model_infer: invalid bc table%s");
+    HIPCHK(c, unet_infer(*md->net, rhs, p_prev, role, b, p_out, c->stream), "mcd_model_infer");
+    return MCD_OK;
+}
+
+mcd_status mcd_model_train_step(mcd_model* md, const double* rhs, const double* p_prev, const double* p_target,
+                                const int8_t* role, const mcd_bc_table* bc, double lr, double* loss) {
+    if (!md || !rhs || !p_prev || !p_target || !role) return MCD_ERR_ARG;
+    mcd_ctx* c = md->ctx;
+    BcDev b;
+    if (!make_bc(bc, &b)) return fail(c, MCD_ERR_ARG, "mcd_model_train_step: invalid bc table%s");
+    if (!(lr >= 0) || !isfinite(lr)) return fail(c, MCD_ERR_ARG, "mcd_model_train_step: bad learning rate%s");
+    HIPCHK(c, unet_train_step(*md->net, rhs, p_prev, p_target, role, b, (float)lr, c->stream, loss),
+           "mcd_model_train_step");
+    return MCD_OK;
+}
+
 mcd_status mcd_profile(mcd_ctx* c, int enable) {
     if (!c) return MCD_ERR_ARG;
     HIPCHK(c, krylov_profile(c->kw, enable ? 1 : 0), "mcd_profile");

@@ -270,4 +270,18 @@ void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms
 hipError_t solve_ppe_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
                           double* p, const SolveParams& sp, SolveOut* out, int* bad, hipStream_t st);
 
+struct UNet;
+hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall_id, UNet** out);
+void unet_free(UNet* u);
+hipError_t unet_weights_to_bf16(UNet& u, hipStream_t st);
+hipError_t unet_infer(UNet& u, const double* b, const double* pprev, const int8_t* role, const BcDev& bc,
+                      double* out, hipStream_t st);
+hipError_t unet_train_step(UNet& u, const double* b, const double* pprev, const double* Pt, const int8_t* role,
+                           const BcDev& bc, float lr, hipStream_t st, double* loss_out);
+size_t unet_nparams(const UNet& u);
+float* unet_theta(UNet& u);
+float* unet_grad(UNet& u);
+float* unet_head_out(UNet& u);
+void unet_reset_optimizer(UNet& u, hipStream_t st);
+
 }  // namespace mcd

@@ -1,0 +1,795 @@
+// Learned PPE initial guess: a U-Net on the background mesh (one DP per
+// cell makes DP arrays NHWC images: row = y, column = x, channels last).
+//
+// BF16 weights and activations, FP32 accumulation on the matrix cores
+// (v_mfma_f32_32x32x16_bf16).  A 3x3 convolution is an implicit GEMM:
+//   Y[p][n] = sum_t sum_k In[p + o_t][k] W[t][n][k],
+// rows = pixels, columns = output channels, K = 9 taps x input channels.
+// The input In of a decoder convolution is concat(skip (this level),
+// nearest 2x upsample of the coarser level) and is read directly from the
+// two tensors, so neither the upsampled image nor the concatenation is ever
+// written.  The data gradient is the same kernel with the tap-flipped,
+// transposed weights; the weight gradient is a GEMM over pixels with
+// deterministic per-chunk partial sums.
+//
+// Lane layout of the 32x32x16 bf16 MFMA (gfx950): lane l holds
+// A[row = l%32][k = 8(l/32) + j], B[k = 8(l/32) + j][col = l%32], j = 0..7,
+// and D element i at row 8(i/4) + 4(l/32) + i%4, col l%32.
+#include "common.h"
+
+namespace mcd {
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int kIn = 16;       // packed input channels
+constexpr int kMaxLevels = 5;
+
+// Input of a convolution: concat(x0 (c0 channels, H x W), up2(x1) (c1
+// channels, (H/2) x (W/2))).
+struct ConvIn {
+    const __bf16* x0;
+    int c0;
+    const __bf16* x1;
+    int c1;
+    int H, W;
+};
+
+__device__ __forceinline__ bf16x8 zero8() {
+    bf16x8 z;
+#pragma unroll
+    for (int j = 0; j < 8; ++j) z[j] = (__bf16)0.0f;
+    return z;
+}
+
+// 8 consecutive input channels [k0, k0 + 8) at (y, x); zero outside the image.
+__device__ __forceinline__ bf16x8 load8(const ConvIn& in, int y, int x, int k0) {
+    if (y < 0 || y >= in.H || x < 0 || x >= in.W) return zero8();
+    if (k0 < in.c0) return *(const bf16x8*)(in.x0 + (size_t)(y * in.W + x) * in.c0 + k0);
+    const int W1 = in.W >> 1;
+    return *(const bf16x8*)(in.x1 + (size_t)((y >> 1) * W1 + (x >> 1)) * in.c1 + (k0 - in.c0));
+}
+
+__device__ __forceinline__ __bf16 load1(const ConvIn& in, int y, int x, int k) {
+    if (y < 0 || y >= in.H || x < 0 || x >= in.W) return (__bf16)0.0f;
+    if (k < in.c0) return in.x0[(size_t)(y * in.W + x) * in.c0 + k];
+    const int W1 = in.W >> 1;
+    return in.x1[(size_t)((y >> 1) * W1 + (x >> 1)) * in.c1 + (k - in.c0)];
+}
+
+// Implicit-GEMM 3x3 convolution.  Wk: [9][NT*32][K] bf16 (K = c0 + c1, zero
+// rows for n >= cout).  A block of 4 waves covers 128 consecutive pixels;
+// each wave owns 32 pixels and all NT column tiles.
+template <int NT>
+__global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __restrict__ Wk,
+                                                   const float* __restrict__ bias, int cout, int relu,
+                                                   __bf16* __restrict__ Y) {
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int P = in.H * in.W;
+    const int p0 = (blockIdx.x * 4 + wave) * 32;
+    if (p0 >= P) return;
+    const int pm = p0 + (l & 31);
+    const bool valid = pm < P;
+    const int ym = valid ? pm / in.W : 0, xm = valid ? pm % in.W : 0;
+    const int K = in.c0 + in.c1;
+    const int half = 8 * (l >> 5);
+    f32x16 acc[NT];
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt)
+#pragma unroll
+        for (int i = 0; i < 16; ++i) acc[nt][i] = 0.0f;
+    for (int t = 0; t < 9; ++t) {
+        const int dy = t / 3 - 1, dx = t % 3 - 1;
+        const __bf16* wt = Wk + (size_t)t * NT * 32 * K;
+        for (int k0 = 0; k0 < K; k0 += 16) {
+            const int kk = k0 + half;
+            const bf16x8 a = valid ? load8(in, ym + dy, xm + dx, kk) : zero8();
+#pragma unroll
+            for (int nt = 0; nt < NT; ++nt) {
+                const bf16x8 b = *(const bf16x8*)(wt + (size_t)(nt * 32 + (l & 31)) * K + kk);
+                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[nt], 0, 0, 0);
+            }
+        }
+    }
+#pragma unroll
+    for (int nt = 0; nt < NT; ++nt) {
+        const int n = nt * 32 + (l & 31);
+        if (n >= cout) continue;
+        const float bn = bias ? bias[n] : 0.0f;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) {
+            const int p = p0 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
+            if (p >= P) continue;
+            float v = acc[nt][i] + bn;
+            if (relu) v = fmaxf(v, 0.0f);
+            Y[(size_t)p * cout + n] = (__bf16)v;
+        }
+    }
+}
+
+// Weight gradient: part[chunk][t][k][n] = sum over the chunk's pixels p of
+// In[p + o_t][k] dY[p][n]  (k < K padded to 32, n < cout padded to 32).
+// One wave per (t, k-tile, n-tile) output tile; blockIdx.x = pixel chunk.
+__global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, const __bf16* __restrict__ dY, int cout, int ktiles,
+                                                    int ntiles, int chunk, float* __restrict__ part) {
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int tile = blockIdx.y * 4 + wave;
+    const int per_tap = ktiles * ntiles;
+    if (tile >= 9 * per_tap) return;
+    const int t = tile / per_tap, kt = (tile % per_tap) / ntiles, nt = tile % ntiles;
+    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const int K = in.c0 + in.c1;
+    const int P = in.H * in.W;
+    const int q_begin = blockIdx.x * chunk;
+    const int q_end = min(P, q_begin + chunk);
+    const int k = kt * 32 + (l & 31), n = nt * 32 + (l & 31);
+    const int half = 8 * (l >> 5);
+    f32x16 acc;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    for (int q0 = q_begin; q0 < q_end; q0 += 16) {
+        bf16x8 a, b;
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+            const int q = q0 + half + j;
+            const bool ok = q < q_end;
+            const int y = ok ? q / in.W : 0, x = ok ? q % in.W : 0;
+            a[j] = (ok && k < K) ? load1(in, y + dy, x + dx, k) : (__bf16)0.0f;
+            b[j] = (ok && n < cout) ? dY[(size_t)q * cout + n] : (__bf16)0.0f;
+        }
+        acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+    }
+    // D rows are k (from A), columns n (from B)
+    const int Kp = ktiles * 32, Np = ntiles * 32;
+    float* dst = part + ((size_t)blockIdx.x * 9 + t) * Kp * Np;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        const int kr = kt * 32 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
+        dst[(size_t)kr * Np + n] = acc[i];
+    }
+}
+
+// grad[t][k][n] (theta layout W[t][ci][co]) = sum over chunks of part.
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int K, int cout, int Kp, int Np,
+                               float* __restrict__ g) {
+    const int total = 9 * K * cout;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int t = e / (K * cout), k = (e / cout) % K, n = e % cout;
+        double s = 0.0;
+        for (int c = 0; c < nchunks; ++c) s += part[((size_t)c * 9 + t) * Kp * Np + (size_t)k * Np + n];
+        g[e] = (float)s;
+    }
+}
+
+// Column sums of a [P][C] bf16 matrix: partials per block, then a reduction.
+__global__ __launch_bounds__(256) void k_colsum_part(const __bf16* __restrict__ X, int P, int C, int rows_per_block,
+                                                     float* __restrict__ part) {
+    const int r0 = blockIdx.x * rows_per_block, r1 = min(P, r0 + rows_per_block);
+    for (int c = threadIdx.x; c < C; c += blockDim.x) {
+        float s = 0.0f;
+        for (int r = r0; r < r1; ++r) s += (float)X[(size_t)r * C + c];
+        part[(size_t)blockIdx.x * C + c] = s;
+    }
+}
+
+__global__ void k_colsum_reduce(const float* __restrict__ part, int nblk, int C, float* __restrict__ g) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < C; c += gridDim.x * blockDim.x) {
+        double s = 0.0;
+        for (int b = 0; b < nblk; ++b) s += part[(size_t)b * C + c];
+        g[c] = (float)s;
+    }
+}
+
+__global__ void k_relu_mask(__bf16* __restrict__ g, const __bf16* __restrict__ y, size_t n) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x)
+        if (!((float)y[i] > 0.0f)) g[i] = (__bf16)0.0f;
+}
+
+// 2x2 mean pool: out (H/2 x W/2 x C) from in (H x W x C).
+__global__ void k_pool(const __bf16* __restrict__ in, int H, int W, int C, __bf16* __restrict__ out) {
+    const int W2 = W >> 1, total = (H >> 1) * W2 * C;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int c = e % C, p = e / C, y = p / W2, x = p % W2;
+        const size_t b0 = ((size_t)(2 * y) * W + 2 * x) * C + c;
+        const float s = (float)in[b0] + (float)in[b0 + C] + (float)in[b0 + (size_t)W * C] +
+                        (float)in[b0 + (size_t)W * C + C];
+        out[e] = (__bf16)(0.25f * s);
+    }
+}
+
+// g_fine (H x W x C) += g_coarse / 4 broadcast over each 2x2 block.
+__global__ void k_pool_bwd_add(const __bf16* __restrict__ gc, int H, int W, int C, __bf16* __restrict__ gf) {
+    const int total = H * W * C;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int c = e % C, p = e / C, y = p / W, x = p % W;
+        const float v = (float)gf[e] + 0.25f * (float)gc[((size_t)(y >> 1) * (W >> 1) + (x >> 1)) * C + c];
+        gf[e] = (__bf16)v;
+    }
+}
+
+// Gradient of concat(skip, up2(coarse)): skip part written to gs, upsample
+// part summed over each 2x2 block into gcoarse ((H/2) x (W/2) x c1).
+__global__ void k_cat_split(const __bf16* __restrict__ gcat, int H, int W, int c0, int c1, __bf16* __restrict__ gs,
+                            __bf16* __restrict__ gcoarse) {
+    const int C = c0 + c1;
+    const int n_skip = H * W * c0;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_skip; e += gridDim.x * blockDim.x) {
+        const int c = e % c0, p = e / c0;
+        gs[e] = gcat[(size_t)p * C + c];
+    }
+    const int W2 = W >> 1, n_c = (H >> 1) * W2 * c1;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_c; e += gridDim.x * blockDim.x) {
+        const int c = e % c1, p = e / c1, y = p / W2, x = p % W2;
+        const size_t b0 = ((size_t)(2 * y) * W + 2 * x) * C + c0 + c;
+        const float s = (float)gcat[b0] + (float)gcat[b0 + C] + (float)gcat[b0 + (size_t)W * C] +
+                        (float)gcat[b0 + (size_t)W * C + C];
+        gcoarse[e] = (__bf16)s;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Head (C -> 1, FP32 on the vector units), input packing, loss, Adam
+// ---------------------------------------------------------------------------
+
+// h[p] = bh + sum_t sum_c X[p + o_t][c] Wh[t][c]
+__global__ void k_head_fwd(const __bf16* __restrict__ X, int H, int W, int C, const float* __restrict__ Wh,
+                           const float* __restrict__ bh, float* __restrict__ h) {
+    const int P = H * W;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const int y = p / W, x = p % W;
+        float s = bh[0];
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+            const __bf16* xp = X + (size_t)(yy * W + xx) * C;
+            const float* wp = Wh + t * C;
+            for (int c = 0; c < C; ++c) s += (float)xp[c] * wp[c];
+        }
+        h[p] = s;
+    }
+}
+
+// gX[p][c] = sum_t dh[p - o_t] Wh[t][c]
+__global__ void k_head_bwd_data(const float* __restrict__ dh, int H, int W, int C, const float* __restrict__ Wh,
+                                __bf16* __restrict__ gX) {
+    const int total = H * W * C;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
+        const int c = e % C, p = e / C, y = p / W, x = p % W;
+        float s = 0.0f;
+        for (int t = 0; t < 9; ++t) {
+            const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
+            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+            s += dh[yy * W + xx] * Wh[t * C + c];
+        }
+        gX[e] = (__bf16)s;
+    }
+}
+
+// partials of dWh[t][c] = sum_p X[p + o_t][c] dh[p] and dbh = sum_p dh[p]
+__global__ __launch_bounds__(256) void k_head_wgrad_part(const __bf16* __restrict__ X, int H, int W, int C,
+                                                         const float* __restrict__ dh, int rows_per_block,
+                                                         float* __restrict__ part) {
+    const int P = H * W, r0 = blockIdx.x * rows_per_block, r1 = min(P, r0 + rows_per_block);
+    const int n = 9 * C + 1;
+    for (int e = threadIdx.x; e < n; e += blockDim.x) {
+        float s = 0.0f;
+        if (e == 9 * C) {
+            for (int p = r0; p < r1; ++p) s += dh[p];
+        } else {
+            const int t = e / C, c = e % C;
+            for (int p = r0; p < r1; ++p) {
+                const int y = p / W + t / 3 - 1, x = p % W + t % 3 - 1;
+                if (y < 0 || y >= H || x < 0 || x >= W) continue;
+                s += (float)X[(size_t)(y * W + x) * C + c] * dh[p];
+            }
+        }
+        part[(size_t)blockIdx.x * n + e] = s;
+    }
+}
+
+// unknown cells of the PPE (inner and Neumann ids)
+__device__ __forceinline__ bool unk_of(int r, const BcDev& bc) {
+    if (r == MCD_ROLE_INNER) return true;
+    if (r <= 0) return false;
+    return bc.type[r & (MCD_MAX_IDS - 1)] == MCD_BC_NEUMANN;
+}
+
+// partials of sum over unknown cells of b^2
+__global__ __launch_bounds__(256) void k_sumsq_part(const double* __restrict__ b, const int8_t* __restrict__ role,
+                                                    BcDev bc, int P, double* __restrict__ part, double* count) {
+    __shared__ double lds[2][4];
+    double s = 0.0, n = 0.0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
+        if (unk_of(role[p], bc)) {
+            s += b[p] * b[p];
+            n += 1.0;
+        }
+    double v[2] = {s, n};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        part[blockIdx.x] = v[0];
+        count[blockIdx.x] = v[1];
+    }
+}
+
+// rms = sqrt(mean b^2 over unknown cells) from the partials (one block)
+__global__ void k_rms(const double* __restrict__ part, const double* __restrict__ count, int nblk, double* rms) {
+    __shared__ double lds[2][4];
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        v[0] += part[b];
+        v[1] += count[b];
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        const double r = v[1] > 0 ? sqrt(v[0] / v[1]) : 1.0;
+        *rms = r > 0 ? r : 1.0;
+    }
+}
+
+__global__ void k_pack(const double* __restrict__ b, const double* __restrict__ pprev,
+                       const int8_t* __restrict__ role, BcDev bc, int body_id, int wall_id, int P,
+                       const double* __restrict__ rms, __bf16* __restrict__ x0) {
+    const double inv = 1.0 / *rms;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        const int r = role[p];
+        const bool u = unk_of(r, bc);
+        float v[kIn];
+#pragma unroll
+        for (int c = 0; c < kIn; ++c) v[c] = 0.0f;
+        v[0] = u ? (float)(b[p] * inv) : 0.0f;
+        v[1] = u ? (float)(pprev[p] * inv) : 0.0f;
+        v[2] = r == MCD_ROLE_INNER ? 1.0f : 0.0f;
+        v[3] = r == body_id ? 1.0f : 0.0f;
+        v[4] = r == wall_id ? 1.0f : 0.0f;
+#pragma unroll
+        for (int c = 0; c < kIn; ++c) x0[(size_t)p * kIn + c] = (__bf16)v[c];
+    }
+}
+
+// partials of num = sum_u (h - (P - Pprev)/rms)^2 and den = sum_u (P/rms)^2
+__global__ __launch_bounds__(256) void k_loss_part(const float* __restrict__ h, const double* __restrict__ Pt,
+                                                   const double* __restrict__ pprev, const int8_t* __restrict__ role,
+                                                   BcDev bc, int P, const double* __restrict__ rms,
+                                                   double* __restrict__ part) {
+    __shared__ double lds[2][4];
+    const double inv = 1.0 / *rms;
+    double num = 0.0, den = 0.0;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
+        if (unk_of(role[p], bc)) {
+            const double tc = (Pt[p] - pprev[p]) * inv;
+            const double d = (double)h[p] - tc;
+            num += d * d;
+            den += (Pt[p] * inv) * (Pt[p] * inv);
+        }
+    double v[2] = {num, den};
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = v[0];
+        part[2 * blockIdx.x + 1] = v[1];
+    }
+}
+
+// loss = num / den (one block) and dh = 2 (h - tc) / den at unknown cells
+__global__ void k_loss_finish(const double* __restrict__ part, int nblk, double* loss) {
+    __shared__ double lds[2][4];
+    double v[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        v[0] += part[2 * b];
+        v[1] += part[2 * b + 1];
+    }
+    block_sum<2>(v, lds);
+    if (threadIdx.x == 0) {
+        loss[1] = v[1] > 0 ? v[1] : 1.0;
+        loss[0] = v[0] / loss[1];
+    }
+}
+
+__global__ void k_loss_grad(const float* __restrict__ h, const double* __restrict__ Pt,
+                            const double* __restrict__ pprev, const int8_t* __restrict__ role, BcDev bc, int P,
+                            const double* __restrict__ rms, const double* __restrict__ loss, float* __restrict__ dh) {
+    const double inv = 1.0 / *rms, den = loss[1];
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+        float g = 0.0f;
+        if (unk_of(role[p], bc)) g = (float)(2.0 * ((double)h[p] - (Pt[p] - pprev[p]) * inv) / den);
+        dh[p] = g;
+    }
+}
+
+// guess = pprev + rms * h at unknown cells (FP64); other cells untouched
+__global__ void k_unpack(const float* __restrict__ h, const double* __restrict__ pprev,
+                         const int8_t* __restrict__ role, BcDev bc, int P, const double* __restrict__ rms,
+                         double* __restrict__ out) {
+    const double r = *rms;
+    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
+        if (unk_of(role[p], bc)) out[p] = pprev[p] + r * (double)h[p];
+}
+
+// Adam (Kingma & Ba) on FP32 master weights with bias correction.
+__global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __restrict__ v,
+                       const float* __restrict__ g, size_t n, float lr, float b1, float b2, float eps, float c1,
+                       float c2) {
+    for (size_t i = blockIdx.x * (size_t)blockDim.x + threadIdx.x; i < n; i += (size_t)gridDim.x * blockDim.x) {
+        const float gi = g[i];
+        const float mi = b1 * m[i] + (1.0f - b1) * gi;
+        const float vi = b2 * v[i] + (1.0f - b2) * gi * gi;
+        m[i] = mi;
+        v[i] = vi;
+        th[i] = th[i] - lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+    }
+}
+
+// theta W[t][ci][co] -> forward Wf[t][n = co (padded)][k = ci] and data-gradient
+// Wb[t][n = ci (padded)][k = co] = W[8 - t][ci][co]
+__global__ void k_weights_bf16(const float* __restrict__ W, int cin, int cout, int npf, int npb,
+                               __bf16* __restrict__ Wf, __bf16* __restrict__ Wb) {
+    const int nf = 9 * npf * cin, nb = 9 * npb * cout;
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += gridDim.x * blockDim.x) {
+        const int t = e / (npf * cin), n = (e / cin) % npf, k = e % cin;
+        Wf[e] = (__bf16)(n < cout ? W[(t * cin + k) * cout + n] : 0.0f);
+    }
+    for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nb; e += gridDim.x * blockDim.x) {
+        const int t = e / (npb * cout), n = (e / cout) % npb, k = e % cout;
+        Wb[e] = (__bf16)(n < cin ? W[((8 - t) * cin + n) * cout + k] : 0.0f);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side
+// ---------------------------------------------------------------------------
+
+struct ConvLayer {
+    int cin, cout;       // cin includes both concat inputs
+    size_t w_off, b_off; // offsets in the flat parameter vector
+    int npf, npb;        // padded column counts of the forward / data-gradient GEMMs
+    __bf16 *Wf, *Wb;
+};
+
+struct UNet {
+    int L;
+    int ch[kMaxLevels];
+    int H, W;
+    int body_id, wall_id;
+    size_t nparams;
+    float *theta, *grad, *m, *v;
+    int nlayers;
+    ConvLayer layers[4 * kMaxLevels + 1];
+    // activations (bf16) and gradients
+    __bf16* x0;
+    __bf16 *in[kMaxLevels], *ea[kMaxLevels], *eb[kMaxLevels], *da[kMaxLevels], *db[kMaxLevels];
+    __bf16 *g_eb[kMaxLevels], *g_ea[kMaxLevels], *g_da[kMaxLevels], *g_db[kMaxLevels], *g_in[kMaxLevels];
+    __bf16* g_cat;       // largest concat gradient
+    float *h, *dh;
+    float* part;         // weight-gradient partials
+    size_t part_cap;     // floats
+    double* red;         // reduction scratch
+    double* rms;         // [1]
+    double* loss;        // [2]
+    double* loss_host;   // pinned [2]
+    long long step;
+};
+
+static inline int grid_of(size_t n, int block = 256) {
+    size_t g = (n + block - 1) / block;
+    return (int)(g < 1 ? 1 : (g > 8192 ? 8192 : g));
+}
+
+static hipError_t launch_conv(const ConvIn& in, const __bf16* Wk, int np, const float* bias, int cout, int relu,
+                              __bf16* Y, hipStream_t st) {
+    const int P = in.H * in.W;
+    const dim3 g((P + 127) / 128), b(256);
+    switch (np / 32) {
+        case 1: hipLaunchKernelGGL(k_conv_mfma<1>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
+        case 2: hipLaunchKernelGGL(k_conv_mfma<2>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
+        case 3: hipLaunchKernelGGL(k_conv_mfma<3>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
+        case 4: hipLaunchKernelGGL(k_conv_mfma<4>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
+        case 5: hipLaunchKernelGGL(k_conv_mfma<5>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
+        case 6: hipLaunchKernelGGL(k_conv_mfma<6>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
+        case 7: hipLaunchKernelGGL(k_conv_mfma<7>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
+        case 8: hipLaunchKernelGGL(k_conv_mfma<8>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// weight and bias gradient of one conv layer into u.grad
+static hipError_t layer_grads(UNet& u, const ConvLayer& Lr, const ConvIn& in, const __bf16* dY, hipStream_t st) {
+    const int P = in.H * in.W;
+    const int K = in.c0 + in.c1;
+    const int kt = (K + 31) / 32, nt = (Lr.cout + 31) / 32;
+    const size_t tile_floats = (size_t)9 * kt * 32 * nt * 32;
+    int nchunks = (int)(u.part_cap / tile_floats);
+    if (nchunks > 256) nchunks = 256;
+    if (nchunks < 1) return hipErrorInvalidValue;
+    int chunk = (P + nchunks - 1) / nchunks;
+    chunk = (chunk + 15) / 16 * 16;
+    nchunks = (P + chunk - 1) / chunk;
+    const int tiles = 9 * kt * nt;
+    hipLaunchKernelGGL(k_conv_wgrad, dim3(nchunks, (tiles + 3) / 4), dim3(256), 0, st, in, dY, Lr.cout, kt, nt,
+                       chunk, u.part);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid_of((size_t)9 * K * Lr.cout)), dim3(256), 0, st, u.part, nchunks, K,
+                       Lr.cout, kt * 32, nt * 32, u.grad + Lr.w_off);
+    const int rows = (P + 255) / 256;
+    const int nb = (P + rows - 1) / rows;
+    hipLaunchKernelGGL(k_colsum_part, dim3(nb), dim3(256), 0, st, dY, P, Lr.cout, rows, u.part);
+    hipLaunchKernelGGL(k_colsum_reduce, dim3(1), dim3(256), 0, st, u.part, nb, Lr.cout, u.grad + Lr.b_off);
+    return hipGetLastError();
+}
+
+static ConvIn conv_in(const __bf16* x0, int c0, const __bf16* x1, int c1, int H, int W) {
+    return ConvIn{x0, c0, x1, c1, H, W};
+}
+
+hipError_t unet_weights_to_bf16(UNet& u, hipStream_t st) {
+    for (int i = 0; i < u.nlayers - 1; ++i) {
+        const ConvLayer& Lr = u.layers[i];
+        hipLaunchKernelGGL(k_weights_bf16, dim3(grid_of((size_t)9 * 256 * 256)), dim3(256), 0, st,
+                           u.theta + Lr.w_off, Lr.cin, Lr.cout, Lr.npf, Lr.npb, Lr.Wf, Lr.Wb);
+    }
+    return hipGetLastError();
+}
+
+// Forward pass; leaves the head output h (FP32) and all activations.
+hipError_t unet_forward(UNet& u, const double* b, const double* pprev, const int8_t* role, const BcDev& bc,
+                        hipStream_t st) {
+    const int P = u.H * u.W;
+    const int nb = 256;
+    hipLaunchKernelGGL(k_sumsq_part, dim3(nb), dim3(256), 0, st, b, role, bc, P, u.red, u.red + nb);
+    hipLaunchKernelGGL(k_rms, dim3(1), dim3(256), 0, st, u.red, u.red + nb, nb, u.rms);
+    hipLaunchKernelGGL(k_pack, dim3(grid_of(P)), dim3(256), 0, st, b, pprev, role, bc, u.body_id, u.wall_id, P,
+                       u.rms, u.x0);
+    int li = 0;
+    for (int l = 0; l < u.L; ++l) {
+        const int H = u.H >> l, W = u.W >> l;
+        const __bf16* src = u.x0;
+        int csrc = kIn;
+        if (l > 0) {
+            hipLaunchKernelGGL(k_pool, dim3(grid_of((size_t)H * W * u.ch[l - 1])), dim3(256), 0, st, u.eb[l - 1],
+                               H * 2, W * 2, u.ch[l - 1], u.in[l]);
+            src = u.in[l];
+            csrc = u.ch[l - 1];
+        }
+        const ConvLayer& A = u.layers[li++];
+        hipError_t e = launch_conv(conv_in(src, csrc, nullptr, 0, H, W), A.Wf, A.npf, u.theta + A.b_off, A.cout, 1,
+                                   u.ea[l], st);
+        if (e != hipSuccess) return e;
+        const ConvLayer& B = u.layers[li++];
+        e = launch_conv(conv_in(u.ea[l], u.ch[l], nullptr, 0, H, W), B.Wf, B.npf, u.theta + B.b_off, B.cout, 1,
+                        u.eb[l], st);
+        if (e != hipSuccess) return e;
+    }
+    for (int l = u.L - 2; l >= 0; --l) {
+        const int H = u.H >> l, W = u.W >> l;
+        const __bf16* coarse = (l + 1 == u.L - 1) ? u.eb[l + 1] : u.db[l + 1];
+        const ConvLayer& A = u.layers[li++];
+        hipError_t e = launch_conv(conv_in(u.eb[l], u.ch[l], coarse, u.ch[l + 1], H, W), A.Wf, A.npf,
+                                   u.theta + A.b_off, A.cout, 1, u.da[l], st);
+        if (e != hipSuccess) return e;
+        const ConvLayer& B = u.layers[li++];
+        e = launch_conv(conv_in(u.da[l], u.ch[l], nullptr, 0, H, W), B.Wf, B.npf, u.theta + B.b_off, B.cout, 1,
+                        u.db[l], st);
+        if (e != hipSuccess) return e;
+    }
+    const ConvLayer& Hd = u.layers[li];
+    const __bf16* last = u.L > 1 ? u.db[0] : u.eb[0];
+    hipLaunchKernelGGL(k_head_fwd, dim3(grid_of(P)), dim3(256), 0, st, last, u.H, u.W, u.ch[0], u.theta + Hd.w_off,
+                       u.theta + Hd.b_off, u.h);
+    return hipGetLastError();
+}
+
+static hipError_t bwd_data(const ConvLayer& Lr, const __bf16* dY, int H, int W, __bf16* dX, hipStream_t st) {
+    // data gradient = forward convolution of dY with the flipped, transposed weights
+    return launch_conv(conv_in(dY, Lr.cout, nullptr, 0, H, W), Lr.Wb, Lr.npb, nullptr, Lr.cin, 0, dX, st);
+}
+
+// Forward, loss against the target pressure, backward, Adam step.
+hipError_t unet_train_step(UNet& u, const double* b, const double* pprev, const double* Pt, const int8_t* role,
+                           const BcDev& bc, float lr, hipStream_t st, double* loss_out) {
+    hipError_t e = unet_forward(u, b, pprev, role, bc, st);
+    if (e != hipSuccess) return e;
+    const int P = u.H * u.W;
+    const int nb = 256;
+    hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, st, u.h, Pt, pprev, role, bc, P, u.rms, u.red);
+    hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, st, u.red, nb, u.loss);
+    hipLaunchKernelGGL(k_loss_grad, dim3(grid_of(P)), dim3(256), 0, st, u.h, Pt, pprev, role, bc, P, u.rms, u.loss,
+                       u.dh);
+    // head
+    const int nl = u.nlayers;
+    const ConvLayer& Hd = u.layers[nl - 1];
+    const int C0 = u.ch[0];
+    const __bf16* last = u.L > 1 ? u.db[0] : u.eb[0];
+    __bf16* g_last = u.L > 1 ? u.g_db[0] : u.g_eb[0];
+    hipLaunchKernelGGL(k_head_bwd_data, dim3(grid_of((size_t)P * C0)), dim3(256), 0, st, u.dh, u.H, u.W, C0,
+                       u.theta + Hd.w_off, g_last);
+    {
+        const int rows = (P + 255) / 256, nblk = (P + rows - 1) / rows;
+        hipLaunchKernelGGL(k_head_wgrad_part, dim3(nblk), dim3(256), 0, st, last, u.H, u.W, C0, u.dh, rows, u.part);
+        hipLaunchKernelGGL(k_colsum_reduce, dim3(1), dim3(256), 0, st, u.part, nblk, 9 * C0 + 1, u.grad + Hd.w_off);
+    }
+    // decoder, unwound from level 0 upwards (layer index of dec(l)a: 2L + 2(L-2-l))
+    for (int l = 0; l <= u.L - 2; ++l) {
+        const int H = u.H >> l, W = u.W >> l;
+        const size_t n = (size_t)H * W * u.ch[l];
+        const ConvLayer& A = u.layers[2 * u.L + 2 * (u.L - 2 - l)];
+        const ConvLayer& B = u.layers[2 * u.L + 2 * (u.L - 2 - l) + 1];
+        hipLaunchKernelGGL(k_relu_mask, dim3(grid_of(n)), dim3(256), 0, st, u.g_db[l], u.db[l], n);
+        if ((e = layer_grads(u, B, conv_in(u.da[l], u.ch[l], nullptr, 0, H, W), u.g_db[l], st)) != hipSuccess)
+            return e;
+        if ((e = bwd_data(B, u.g_db[l], H, W, u.g_da[l], st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_relu_mask, dim3(grid_of(n)), dim3(256), 0, st, u.g_da[l], u.da[l], n);
+        const __bf16* coarse = (l + 1 == u.L - 1) ? u.eb[l + 1] : u.db[l + 1];
+        if ((e = layer_grads(u, A, conv_in(u.eb[l], u.ch[l], coarse, u.ch[l + 1], H, W), u.g_da[l], st)) !=
+            hipSuccess)
+            return e;
+        if ((e = bwd_data(A, u.g_da[l], H, W, u.g_cat, st)) != hipSuccess) return e;
+        __bf16* gcoarse = (l + 1 == u.L - 1) ? u.g_eb[l + 1] : u.g_db[l + 1];
+        hipLaunchKernelGGL(k_cat_split, dim3(grid_of((size_t)H * W * u.ch[l])), dim3(256), 0, st, u.g_cat, H, W,
+                           u.ch[l], u.ch[l + 1], u.g_eb[l], gcoarse);
+    }
+    // encoder, from the bottom
+    for (int l = u.L - 1; l >= 0; --l) {
+        const int H = u.H >> l, W = u.W >> l;
+        const size_t n = (size_t)H * W * u.ch[l];
+        const ConvLayer& A = u.layers[2 * l];
+        const ConvLayer& B = u.layers[2 * l + 1];
+        hipLaunchKernelGGL(k_relu_mask, dim3(grid_of(n)), dim3(256), 0, st, u.g_eb[l], u.eb[l], n);
+        if ((e = layer_grads(u, B, conv_in(u.ea[l], u.ch[l], nullptr, 0, H, W), u.g_eb[l], st)) != hipSuccess)
+            return e;
+        if ((e = bwd_data(B, u.g_eb[l], H, W, u.g_ea[l], st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_relu_mask, dim3(grid_of(n)), dim3(256), 0, st, u.g_ea[l], u.ea[l], n);
+        const __bf16* src = l > 0 ? u.in[l] : u.x0;
+        const int csrc = l > 0 ? u.ch[l - 1] : kIn;
+        if ((e = layer_grads(u, A, conv_in(src, csrc, nullptr, 0, H, W), u.g_ea[l], st)) != hipSuccess) return e;
+        if (l > 0) {
+            if ((e = bwd_data(A, u.g_ea[l], H, W, u.g_in[l], st)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid_of((size_t)4 * H * W * u.ch[l - 1])), dim3(256), 0, st,
+                               u.g_in[l], 2 * H, 2 * W, u.ch[l - 1], u.g_eb[l - 1]);
+        }
+    }
+    u.step += 1;
+    const float b1 = 0.9f, b2 = 0.999f;
+    const float c1 = 1.0f - powf(b1, (float)u.step), c2 = 1.0f - powf(b2, (float)u.step);
+    if (lr > 0.0f) {
+        hipLaunchKernelGGL(k_adam, dim3(grid_of(u.nparams)), dim3(256), 0, st, u.theta, u.m, u.v, u.grad, u.nparams,
+                           lr, b1, b2, 1e-8f, c1, c2);
+        if ((e = unet_weights_to_bf16(u, st)) != hipSuccess) return e;
+    }
+    if (loss_out) {
+        if ((e = hipMemcpyAsync(u.loss_host, u.loss, 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess)
+            return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        *loss_out = u.loss_host[0];
+    }
+    return hipGetLastError();
+}
+
+hipError_t unet_infer(UNet& u, const double* b, const double* pprev, const int8_t* role, const BcDev& bc,
+                      double* out, hipStream_t st) {
+    hipError_t e = unet_forward(u, b, pprev, role, bc, st);
+    if (e != hipSuccess) return e;
+    const int P = u.H * u.W;
+    hipLaunchKernelGGL(k_unpack, dim3(grid_of(P)), dim3(256), 0, st, u.h, pprev, role, bc, P, u.rms, out);
+    return hipGetLastError();
+}
+
+static hipError_t dalloc(void** p, size_t bytes) {
+    hipError_t e = hipMalloc(p, bytes < 16 ? 16 : bytes);
+    if (e == hipSuccess) e = hipMemset(*p, 0, bytes < 16 ? 16 : bytes);
+    return e;
+}
+
+void unet_free(UNet* u) {
+    if (!u) return;
+    void* ptrs[] = {u->theta, u->grad, u->m, u->v, u->x0, u->g_cat, u->h, u->dh, u->part, u->red, u->rms, u->loss};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    if (u->loss_host) (void)hipHostFree(u->loss_host);
+    for (int l = 0; l < kMaxLevels; ++l) {
+        void* q[] = {u->in[l], u->ea[l], u->eb[l], u->da[l], u->db[l], u->g_eb[l], u->g_ea[l], u->g_da[l],
+                     u->g_db[l], u->g_in[l]};
+        for (void* p : q)
+            if (p) (void)hipFree(p);
+    }
+    for (int i = 0; i < u->nlayers; ++i) {
+        if (u->layers[i].Wf) (void)hipFree(u->layers[i].Wf);
+        if (u->layers[i].Wb) (void)hipFree(u->layers[i].Wb);
+    }
+    delete u;
+}
+
+// Layer table in the flat parameter order: enc0a, enc0b, ..., dec(L-2)a,
+// dec(L-2)b, ..., dec0a, dec0b, head; each W[9][cin][cout] then b[cout].
+hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall_id, UNet** out) {
+    UNet* u = new UNet{};
+    *out = u;
+    u->L = L;
+    u->H = H;
+    u->W = W;
+    u->body_id = body_id;
+    u->wall_id = wall_id;
+    for (int l = 0; l < L; ++l) u->ch[l] = ch[l];
+    size_t off = 0;
+    int n = 0;
+    auto add = [&](int cin, int cout) {
+        ConvLayer& Lr = u->layers[n++];
+        Lr.cin = cin;
+        Lr.cout = cout;
+        Lr.w_off = off;
+        off += (size_t)9 * cin * cout;
+        Lr.b_off = off;
+        off += cout;
+        Lr.npf = (cout + 31) / 32 * 32;
+        Lr.npb = (cin + 31) / 32 * 32;
+    };
+    int prev = kIn;
+    for (int l = 0; l < L; ++l) {
+        add(prev, ch[l]);
+        add(ch[l], ch[l]);
+        prev = ch[l];
+    }
+    for (int l = L - 2; l >= 0; --l) {
+        add(ch[l] + ch[l + 1], ch[l]);
+        add(ch[l], ch[l]);
+    }
+    add(ch[0], 1);
+    u->nlayers = n;
+    u->nparams = off;
+    hipError_t e;
+    const size_t np = off;
+    if ((e = dalloc((void**)&u->theta, np * 4)) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->grad, np * 4)) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->m, np * 4)) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->v, np * 4)) != hipSuccess) return e;
+    for (int i = 0; i < n - 1; ++i) {
+        ConvLayer& Lr = u->layers[i];
+        if ((e = dalloc((void**)&Lr.Wf, (size_t)9 * Lr.npf * Lr.cin * 2)) != hipSuccess) return e;
+        if ((e = dalloc((void**)&Lr.Wb, (size_t)9 * Lr.npb * Lr.cout * 2)) != hipSuccess) return e;
+    }
+    const size_t P = (size_t)H * W;
+    if ((e = dalloc((void**)&u->x0, P * kIn * 2)) != hipSuccess) return e;
+    size_t catmax = 0, partmax = 0;
+    for (int l = 0; l < L; ++l) {
+        const size_t Pl = P >> (2 * l);
+        const size_t c = ch[l];
+        if (l > 0 && (e = dalloc((void**)&u->in[l], Pl * ch[l - 1] * 2)) != hipSuccess) return e;
+        if (l > 0 && (e = dalloc((void**)&u->g_in[l], Pl * ch[l - 1] * 2)) != hipSuccess) return e;
+        if ((e = dalloc((void**)&u->ea[l], Pl * c * 2)) != hipSuccess) return e;
+        if ((e = dalloc((void**)&u->eb[l], Pl * c * 2)) != hipSuccess) return e;
+        if ((e = dalloc((void**)&u->g_ea[l], Pl * c * 2)) != hipSuccess) return e;
+        if ((e = dalloc((void**)&u->g_eb[l], Pl * c * 2)) != hipSuccess) return e;
+        if (l <= L - 2) {
+            if ((e = dalloc((void**)&u->da[l], Pl * c * 2)) != hipSuccess) return e;
+            if ((e = dalloc((void**)&u->db[l], Pl * c * 2)) != hipSuccess) return e;
+            if ((e = dalloc((void**)&u->g_da[l], Pl * c * 2)) != hipSuccess) return e;
+            if ((e = dalloc((void**)&u->g_db[l], Pl * c * 2)) != hipSuccess) return e;
+            catmax = catmax > Pl * (c + ch[l + 1]) ? catmax : Pl * (c + ch[l + 1]);
+        }
+    }
+    for (int i = 0; i < n; ++i) {
+        const size_t kt = (u->layers[i].cin + 31) / 32, nt = (u->layers[i].cout + 31) / 32;
+        const size_t t = 9 * kt * 32 * nt * 32;
+        partmax = partmax > t ? partmax : t;
+    }
+    u->part_cap = partmax * 64 > (size_t)(256 * (9 * 256 + 1)) ? partmax * 64 : (size_t)(256 * (9 * 256 + 1));
+    if ((e = dalloc((void**)&u->g_cat, (catmax ? catmax : 16) * 2)) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->h, P * 4)) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->dh, P * 4)) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->part, u->part_cap * 4)) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->red, 1024 * sizeof(double))) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->rms, sizeof(double))) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->loss, 2 * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipHostMalloc((void**)&u->loss_host, 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return e;
+    return hipDeviceSynchronize();
+}
+
+size_t unet_nparams(const UNet& u) { return u.nparams; }
+float* unet_theta(UNet& u) { return u.theta; }
+float* unet_grad(UNet& u) { return u.grad; }
+float* unet_head_out(UNet& u) { return u.h; }
+void unet_reset_optimizer(UNet& u, hipStream_t st) {
+    (void)hipMemsetAsync(u.m, 0, u.nparams * 4, st);
+    (void)hipMemsetAsync(u.v, 0, u.nparams * 4, st);
+    u.step = 0;
+}
+
+}  // namespace mcd

@@ -102,6 +102,17 @@ class Oscillation:
         return tuple(v)
 
 
+def he_normal_params(shapes, seed):
+    """Seeded initial network parameters: for each (cin, cout) 3x3 conv, weights
+    N(0, 2 / (9 cin)) of shape [9][cin][cout] then zero biases (flat FP32)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    parts = []
+    for cin, cout in shapes:
+        parts.append(rng.standard_normal(9 * cin * cout) * np.sqrt(2.0 / (9 * cin)))
+        parts.append(np.zeros(cout))
+    return np.concatenate(parts).astype(np.float32)
+
+
 def random_unet_batch(rng_seed, shape, dtype=np.float32):
     """Seeded normal tensor for network tests (no method arithmetic)."""
     rng = np.random.Generator(np.random.PCG64(rng_seed))

@@ -30,7 +30,10 @@ MAX_SETS = 4
 
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
             "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
-            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_profile", "mcd_profile_read")
+            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_profile", "mcd_profile_read",
+            "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
+            "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_infer",
+            "mcd_model_train_step")
 
 
 class MeshDesc(C.Structure):
@@ -102,6 +105,15 @@ def load():
         "mcd_project": (i, [vp, i, vp, vp, vp, d, vp, P(Body), i, vp]),
         "mcd_solve_ppe": (i, [vp, i, vp, vp, vp, P(SolveOpts), P(SolveInfo)]),
         "mcd_profile": (i, [vp, i]),
+        "mcd_model_create": (i, [vp, i, P(i), i, P(vp)]),
+        "mcd_model_destroy": (None, [vp]),
+        "mcd_model_num_params": (C.c_size_t, [vp]),
+        "mcd_model_set_params": (i, [vp, vp, C.c_size_t]),
+        "mcd_model_get_params": (i, [vp, vp, C.c_size_t]),
+        "mcd_model_get_grads": (i, [vp, vp, C.c_size_t]),
+        "mcd_model_output": (i, [vp, vp]),
+        "mcd_model_infer": (i, [vp, vp, vp, vp, P(BcTable), vp]),
+        "mcd_model_train_step": (i, [vp, vp, vp, vp, vp, P(BcTable), d, P(d)]),
         "mcd_profile_read": (i, [vp, P(d), P(C.c_longlong), P(d), P(C.c_longlong), i]),
     }
     for name, (res, args) in sig.items():
@@ -312,3 +324,69 @@ class Context:
         self._check(self.lib.mcd_profile_read(self.h, C.byref(mp), C.byref(npp), C.byref(ms), C.byref(ns),
                                               int(bool(reset))), "mcd_profile_read")
         return {"p_ms": mp.value, "p_n": npp.value, "s_ms": ms.value, "s_n": ns.value}
+
+
+class Model:
+    """Learned initial guess (U-Net) bound to a 2D context."""
+
+    def __init__(self, ctx: Context, channels=(16, 32, 64, 128), body_id=2):
+        import numpy as np
+        self.ctx = ctx
+        self.lib = ctx.lib
+        self.channels = tuple(int(c) for c in channels)
+        arr = (C.c_int * len(self.channels))(*self.channels)
+        h = C.c_void_p()
+        ctx._check(self.lib.mcd_model_create(ctx.h, len(self.channels), arr, int(body_id), C.byref(h)),
+                   "mcd_model_create")
+        self.h = h
+        self.n = int(self.lib.mcd_model_num_params(self.h))
+        self._np = np
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.mcd_model_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def set_params(self, theta):
+        t = self._np.ascontiguousarray(theta, dtype=self._np.float32)
+        if t.size != self.n:
+            raise ValueError(f"expected {self.n} parameters, got {t.size}")
+        self.ctx._check(self.lib.mcd_model_set_params(self.h, t.ctypes.data_as(C.c_void_p), self.n),
+                        "mcd_model_set_params")
+
+    def get_params(self):
+        t = self._np.zeros(self.n, dtype=self._np.float32)
+        self.ctx._check(self.lib.mcd_model_get_params(self.h, t.ctypes.data_as(C.c_void_p), self.n),
+                        "mcd_model_get_params")
+        return t
+
+    def get_grads(self):
+        t = self._np.zeros(self.n, dtype=self._np.float32)
+        self.ctx._check(self.lib.mcd_model_get_grads(self.h, t.ctypes.data_as(C.c_void_p), self.n),
+                        "mcd_model_get_grads")
+        return t
+
+    def output(self, h):
+        self.ctx._check(self.lib.mcd_model_output(self.h, _ptr(h, self.ctx.Nc, torch.float32)), "mcd_model_output")
+
+    def infer(self, rhs, p_prev, role, bc: dict, p_out):
+        t = bc_table(bc)
+        N, V = self.ctx.Nc, self.ctx._vec
+        self.ctx._check(self.lib.mcd_model_infer(self.h, V(rhs, N), V(p_prev, N), _ptr(role, N, torch.int8),
+                                                 C.byref(t), V(p_out, N)), "mcd_model_infer")
+
+    def train_step(self, rhs, p_prev, p_target, role, bc: dict, lr, want_loss=True):
+        t = bc_table(bc)
+        N, V = self.ctx.Nc, self.ctx._vec
+        loss = C.c_double(float("nan"))
+        self.ctx._check(self.lib.mcd_model_train_step(self.h, V(rhs, N), V(p_prev, N), V(p_target, N),
+                                                      _ptr(role, N, torch.int8), C.byref(t), float(lr),
+                                                      C.byref(loss) if want_loss else None),
+                        "mcd_model_train_step")
+        return loss.value

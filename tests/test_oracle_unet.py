@@ -1,0 +1,81 @@
+"""Pins of the CPU reference U-Net: hand-written backward against central
+finite differences in FP64 (mini-net), layer identities, and Adam."""
+import numpy as np
+import pytest
+
+from oracle import unet as U
+
+
+def _mini(seed=0):
+    ch = (8, 16)
+    cin = 5
+    theta = U.init_params(ch, seed, cin=cin, dtype=np.float64)
+    rng = np.random.default_rng(seed + 1)
+    x = rng.standard_normal((16, 16, cin))
+    target = rng.standard_normal((16, 16))
+    mask = rng.uniform(size=(16, 16)) > 0.2
+    return ch, cin, theta, x, target, mask
+
+
+def _loss(theta, ch, cin, x, target, mask):
+    out, _ = U.forward(theta, x, ch, cin)
+    return U.loss_and_grad_out(out, target, mask)[0]
+
+
+def test_backward_matches_finite_differences():
+    ch, cin, theta, x, target, mask = _mini()
+    out, cache = U.forward(theta, x, ch, cin)
+    loss, dout = U.loss_and_grad_out(out, target, mask)
+    g = U.backward(theta, cache, dout, ch, cin)
+    assert g.shape == theta.shape
+    rng = np.random.default_rng(7)
+    idx = rng.choice(len(theta), 60, replace=False)
+    h = 1e-6
+    for i in idx:
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        fd = (_loss(tp, ch, cin, x, target, mask) - _loss(tm, ch, cin, x, target, mask)) / (2 * h)
+        assert fd == pytest.approx(g[i], rel=1e-5, abs=1e-9)
+    # directional derivative over all parameters at once
+    d = rng.standard_normal(len(theta))
+    fd = (_loss(theta + h * d, ch, cin, x, target, mask) - _loss(theta - h * d, ch, cin, x, target, mask)) / (2 * h)
+    assert fd == pytest.approx(g @ d, rel=1e-6)
+
+
+def test_layer_identities():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((8, 8, 3))
+    # identity kernel (centre tap) reproduces the input
+    W = np.zeros((9, 3, 3))
+    W[4] = np.eye(3)
+    assert np.allclose(U.conv3x3(x, W, np.zeros(3)), x)
+    # a shift kernel moves the image by one pixel with zero fill
+    W = np.zeros((9, 3, 3))
+    W[5] = np.eye(3)               # offset (+1, 0): out[y, x] = in[y, x+1]
+    y = U.conv3x3(x, W, np.zeros(3))
+    assert np.allclose(y[:, :-1], x[:, 1:]) and np.allclose(y[:, -1], 0)
+    # pooling is the adjoint of (upsampling / 4)
+    a = rng.standard_normal((8, 8, 2))
+    b = rng.standard_normal((4, 4, 2))
+    assert np.sum(U.pool2(a) * b) == pytest.approx(np.sum(a * U.up2(b) / 4))
+    assert np.allclose(U.pool2_backward(b), U.up2(b) / 4)
+
+
+def test_untrained_net_starts_near_the_warm_start():
+    """out = head(...) + channel 1: with a zero head the net is the warm start."""
+    ch = (16, 32)
+    theta = U.init_params(ch, 0)
+    P = U.unpack(theta, ch)
+    P["head"][0][:] = 0.0
+    rng = np.random.default_rng(0)
+    x = rng.standard_normal((16, 16, U.IN_CHANNELS)).astype(np.float32)
+    out, _ = U.forward(theta, x, ch)
+    assert np.allclose(out, x[:, :, 1])
+
+
+def test_adam_first_step_moves_by_lr():
+    theta = np.zeros(4)
+    g = np.array([1.0, -2.0, 0.5, 0.0])
+    t, m, v = U.adam_update(theta, np.zeros(4), np.zeros(4), g, 1, lr=0.01)
+    assert np.allclose(t[:3], -0.01 * np.sign(g[:3]), rtol=1e-6) and t[3] == 0.0
