@@ -258,15 +258,28 @@ typedef struct {
 mcd_status mcd_solve_ppe(mcd_ctx* ctx, int set, const double* rhs, const double* neumann_f,
                          double* p, const mcd_solve_opts* opts, mcd_solve_info* info);
 
+/* Residual of the PPE of set `set` at p (Sec. 3.3, the pressure Poisson
+ * equation as assembled for mcd_solve_ppe): r = b_eff - A p on unknown rows,
+ * where b_eff is rhs with the Dirichlet columns (values of p at known DPs)
+ * and the Neumann data moved over; r = 0 at other cells.  rhs, neumann_f
+ * (nullable), p, r: [Nc] f64 device.  norms: host [2] = (||r||_2,
+ * ||b_eff||_2), nullable.  Synchronises.  MCD_ERR_ARG for an unbuilt set or
+ * a non-finite right-hand side. */
+mcd_status mcd_ppe_residual(mcd_ctx* ctx, int set, const double* rhs, const double* neumann_f, const double* p,
+                            double* r, double* norms);
+
 /* ---------------------------------------------------------------------
- * Learned PPE initial guess (2D): a U-Net on the background mesh.
+ * Learned PPE initial guess (2D): a U-Net on the background mesh.  Not part
+ * of the MCD method: a network that corrects the warm start of the solve.
  * One DP per cell makes the DP arrays NHWC images (row y, column x).
- * Inputs: b / rms(b), p_prev / rms(b) (the warm start), one-hot roles
- * (inner, body, wall); output h; guess = p_prev + rms(b) h at unknown cells
- * (FP64).  Levels L: per level two 3x3 convolutions with ReLU, 2x2 mean
- * pooling down, nearest 2x upsampling and concatenation with the skip up,
- * a 3x3 head to one channel.  BF16 weights and activations, FP32
- * accumulation on the matrix cores; FP32 master weights trained with Adam.
+ * Inputs: r / rms(r), where r is the PPE residual of the warm start p_prev
+ * (mcd_ppe_residual), p_prev / rms(p_prev), one-hot roles (inner, body,
+ * wall); output h; guess = p_prev + s rms(r) h at unknown cells (FP64), s =
+ * the model's output scale.  rms over unknown cells (1 where it is 0).
+ * Levels L: per level two 3x3 convolutions with ReLU, 2x2 mean pooling down,
+ * nearest 2x upsampling and concatenation with the skip up, a 3x3 head to one
+ * channel.  BF16 weights and activations, FP32 accumulation on the matrix
+ * cores; FP32 master weights trained with Adam.
  * Parameters: flat FP32 vector, convolutions in the order enc0a, enc0b, ...,
  * enc(L-1)b, dec(L-2)a, dec(L-2)b, ..., dec0a, dec0b, head, each W[9][cin][cout]
  * (tap t = 3 dy + dx, offset (dx - 1, dy - 1)) then b[cout].
@@ -287,14 +300,18 @@ mcd_status mcd_model_get_params(mcd_model* model, float* theta, size_t n);
 mcd_status mcd_model_get_grads(mcd_model* model, float* grad, size_t n);
 /* copy of the head output h [Nc] of the last forward pass (device, FP32) */
 mcd_status mcd_model_output(mcd_model* model, float* h);
-/* p_out := p_prev + rms(b) h at unknown cells (rows of bc); rhs, p_prev,
- * p_out [Nc] f64, role [Nc] i8 (device); bc host. */
-mcd_status mcd_model_infer(mcd_model* model, const double* rhs, const double* p_prev, const int8_t* role,
+/* output scale s > 0 (default 1): the typical size of the correction in
+ * units of rms(r); a training set fixes it once */
+mcd_status mcd_model_set_output_scale(mcd_model* model, double s);
+/* p_out := p_prev + s rms(resid) h at unknown cells (rows of bc); other cells
+ * of p_out untouched.  resid = mcd_ppe_residual of p_prev; resid, p_prev,
+ * p_out [Nc] f64, role [Nc] i8 (device); bc host.  p_out may alias p_prev. */
+mcd_status mcd_model_infer(mcd_model* model, const double* resid, const double* p_prev, const int8_t* role,
                            const mcd_bc_table* bc, double* p_out);
 /* One Adam step (lr > 0; lr = 0 computes the gradient only) on the loss
- * sum_unknown (p_prev/rms + h - p_target/rms)^2 / sum_unknown (p_target/rms)^2.
+ * sum_unknown (h - t)^2 / sum_unknown t^2, t = (p_target - p_prev) / (s rms(resid)).
  * loss: host, nullable (synchronises when given). */
-mcd_status mcd_model_train_step(mcd_model* model, const double* rhs, const double* p_prev, const double* p_target,
+mcd_status mcd_model_train_step(mcd_model* model, const double* resid, const double* p_prev, const double* p_target,
                                 const int8_t* role, const mcd_bc_table* bc, double lr, double* loss);
 
 /* ---------------------------------------------------------------------

@@ -18,12 +18,13 @@ Weights of a conv: W[t][ci][co] and bias b[co]; the flat parameter vector
 lists the convs in the order enc0a, enc0b, enc1a, ..., dec(L-2)a, dec(L-2)b,
 ..., dec0a, dec0b, head, each as W then b.
 
-Input packing: channel 0 = b / rms(b over unknown cells), channel 1 = the
-previous pressure (the solver's warm start) / rms(b), channels 2..4 =
+Input packing: channel 0 = r / rms(r), where r is the PPE residual of the
+warm start p_prev; channel 1 = p_prev / rms(p_prev); channels 2..4 =
 one-hot (inner, body boundary, wall); remaining input channels are zero.
-The head predicts a correction: out = head(...) + channel 1, so the network
-refines the warm start.  Target = P / rms(b).
-Loss = sum_unknown (out - target)^2 / sum_unknown target^2.
+rms is over unknown cells and 1 where it is 0.  The head output h is a
+correction: guess = p_prev + s rms(r) h at unknown cells (s = output scale).
+Target t = (P - p_prev) / (s rms(r)); loss = sum_unknown (h - t)^2 /
+sum_unknown t^2.
 """
 from __future__ import annotations
 
@@ -120,18 +121,27 @@ def up2_backward(dy):
 # network
 # ---------------------------------------------------------------------------
 
-def pack_input(b, p_prev, role, unknown, n, cin=IN_CHANNELS, body_id=2, wall_id=1):
-    """(H, W, cin) image from DP arrays of an n0 x n1 mesh; returns (x, rms)."""
+def _rms(v, unknown):
+    r = np.sqrt(np.mean(v[unknown] ** 2)) if unknown.any() else 1.0
+    return r if r > 0 else 1.0
+
+
+def pack_input(r, p_prev, role, unknown, n, cin=IN_CHANNELS, body_id=2, wall_id=1):
+    """(H, W, cin) image from DP arrays of an n0 x n1 mesh; returns (x, rms(r))."""
     n0, n1 = n
-    rms = np.sqrt(np.mean(b[unknown] ** 2)) if unknown.any() else 1.0
-    rms = rms if rms > 0 else 1.0
+    rr, rp = _rms(r, unknown), _rms(p_prev, unknown)
     x = np.zeros((n1, n0, cin))
-    x[:, :, 0] = np.where(unknown, b / rms, 0.0).reshape(n1, n0)
-    x[:, :, 1] = np.where(unknown, p_prev / rms, 0.0).reshape(n1, n0)
+    x[:, :, 0] = np.where(unknown, r / rr, 0.0).reshape(n1, n0)
+    x[:, :, 1] = np.where(unknown, p_prev / rp, 0.0).reshape(n1, n0)
     x[:, :, 2] = (role == -1).reshape(n1, n0)
     x[:, :, 3] = (role == body_id).reshape(n1, n0)
     x[:, :, 4] = (role == wall_id).reshape(n1, n0)
-    return x, rms
+    return x, rr
+
+
+def correction_target(p_target, p_prev, rms_r, scale, n):
+    """t = (P - p_prev) / (s rms(r)) as an (H, W) image."""
+    return ((p_target - p_prev) / (scale * rms_r)).reshape(n[1], n[0])
 
 
 def forward(theta, x, ch, cin=IN_CHANNELS):
@@ -156,13 +166,14 @@ def forward(theta, x, ch, cin=IN_CHANNELS):
         cache[f"dec{l}a"] = a
         h = np.maximum(conv3x3(a, *P[f"dec{l}b"]), 0.0)
         cache[f"dec{l}b"] = h
-    out = conv3x3(h, *P["head"])[:, :, 0] + x[:, :, 1]
+    out = conv3x3(h, *P["head"])[:, :, 0]
     cache["last"] = h
     return out, cache
 
 
 def loss_and_grad_out(out, target, mask):
-    """Relative masked MSE and its gradient w.r.t. out."""
+    """Relative masked MSE of the head output against the correction target
+    and its gradient w.r.t. the head output."""
     den = np.sum(np.where(mask, target, 0.0) ** 2)
     den = den if den > 0 else 1.0
     diff = np.where(mask, out - target, 0.0)

@@ -8,6 +8,8 @@ the velocity set.
 from __future__ import annotations
 
 import math
+
+import numpy as np
 from dataclasses import dataclass, field, replace
 from typing import Optional
 
@@ -94,6 +96,24 @@ def c2_oscillating_cylinder(n=1024, steps=50):
                 body=Body(radius=0.5 * diam, motion=Oscillation((0.0, 0.0), amp, freq, 0)),
                 nu=u_max * diam / 100.0, dt=(1.0 / 800.0) * (1024.0 / n), steps=steps,
                 bc_pressure={1: DIRICHLET, 2: NEUMANN}, bc_velocity={1: NEUMANN, 2: DIRICHLET})
+
+
+def c3_cylinder_variant(seed, n=1024, steps=120):
+    """A C2-shaped trajectory for the learned-guess data set: amplitude
+    A ~ U[0.1, 0.4] D and frequency f ~ U[0.5, 2] drawn from PCG64(seed),
+    Re = 100 kept (nu follows the peak body speed), the DP jitter seeded by
+    `seed`, and the step shortened where the body is faster than in C2 so
+    that the CFL number stays that of C2."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    diam = 1.0
+    amp = float(rng.uniform(0.1, 0.4)) * diam
+    freq = float(rng.uniform(0.5, 2.0))
+    u_max = 2 * math.pi * freq * amp
+    u_ref = 2 * math.pi * 1.0 * 0.2
+    base = c2_oscillating_cylinder(n=n, steps=steps)
+    return replace(base, name=f"C3-cylinder-{n}-seed{seed}", jitter_seed=int(seed),
+                   body=Body(radius=0.5 * diam, motion=Oscillation((0.0, 0.0), amp, freq, 0)),
+                   nu=u_max * diam / 100.0, dt=base.dt * min(1.0, u_ref / u_max))
 
 
 def c4_moving_sphere(n=128, steps=20):

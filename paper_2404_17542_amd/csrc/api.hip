@@ -460,6 +460,25 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
     return MCD_OK;
 }
 
+mcd_status mcd_ppe_residual(mcd_ctx* c, int set, const double* rhs, const double* neumann_f, const double* p,
+                            double* r, double* norms) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual: set not built%s");
+    if (!rhs || !p || !r) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual: null argument%s");
+    HIPCHK(c, launch_fill_i32(c->cnt + CNT_BAD, 1, 0, c->stream), "fill");
+    double nr[2] = {0.0, 0.0};
+    HIPCHK(c, ppe_residual_impl(c->m, c->sets[set].dev, *c->kw, rhs, neumann_f, p, r, nr, c->cnt + CNT_BAD, c->stream),
+           "residual");
+    int bad = 0;
+    HIPCHK(c, hipMemcpy(&bad, c->cnt + CNT_BAD, sizeof(int), hipMemcpyDeviceToHost), "copy");
+    if (bad) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual: non-finite right-hand side%s");
+    if (norms) {
+        norms[0] = nr[0];
+        norms[1] = nr[1];
+    }
+    return MCD_OK;
+}
+
 // ---------------------------------------------------------------------------
 // Learned initial guess
 // ---------------------------------------------------------------------------
@@ -530,6 +549,13 @@ mcd_status mcd_model_output(mcd_model* md, float* h) {
     if (!md || !h) return MCD_ERR_ARG;
     mcd_ctx* c = md->ctx;
     HIPCHK(c, hipMemcpyAsync(h, unet_head_out(*md->net), c->Nc * 4, hipMemcpyDeviceToDevice, c->stream), "output");
+    return MCD_OK;
+}
+
+mcd_status mcd_model_set_output_scale(mcd_model* md, double s) {
+    if (!md) return MCD_ERR_ARG;
+    if (!(s > 0) || !isfinite(s)) return fail(md->ctx, MCD_ERR_ARG, "mcd_model_set_output_scale: s must be > 0%s");
+    unet_set_output_scale(*md->net, s);
     return MCD_OK;
 }
 

@@ -269,6 +269,8 @@ hipError_t krylov_profile(KrylovWork* w, int enable);
 void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms_s, long long* n_s, int reset);
 hipError_t solve_ppe_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
                           double* p, const SolveParams& sp, SolveOut* out, int* bad, hipStream_t st);
+hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
+                             const double* p, double* r, double norms[2], int* bad, hipStream_t st);
 
 struct UNet;
 hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall_id, UNet** out);
@@ -283,5 +285,6 @@ float* unet_theta(UNet& u);
 float* unet_grad(UNet& u);
 float* unet_head_out(UNet& u);
 void unet_reset_optimizer(UNet& u, hipStream_t st);
+void unet_set_output_scale(UNet& u, double s);
 
 }  // namespace mcd

@@ -607,6 +607,47 @@ __global__ __launch_bounds__(kBlock) void k_ppe_rhs(MeshDev m, SetDev st, const 
     }
 }
 
+// r = b_eff - A x at unknown rows (0 elsewhere), with per-block partial sums
+// of r.r and b_eff.b_eff.  x is zero at non-unknown cells.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_ppe_resid(MeshDev m, const double* __restrict__ A,
+                                                      const uint8_t* __restrict__ unknown,
+                                                      const double* __restrict__ beff, const double* __restrict__ x,
+                                                      double* __restrict__ r, double* __restrict__ part) {
+    __shared__ double lds[2][kBlock / 64];
+    double rr = 0.0, bb = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (unknown[c]) {
+            v = beff[c] - spmv_row<DIM, double>(m, A, c, [&](int j) { return x[j]; });
+            rr += v * v;
+            bb += beff[c] * beff[c];
+        }
+        r[c] = v;
+    }
+    double q[2] = {rr, bb};
+    block_sum<2>(q, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = q[0];
+        part[2 * blockIdx.x + 1] = q[1];
+    }
+}
+
+// Sums the partials in block order (one block).
+__global__ void k_resid_finish(const double* __restrict__ part, int nblk, double* __restrict__ out) {
+    __shared__ double lds[2][kBlock / 64];
+    double q[2] = {0.0, 0.0};
+    for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
+        q[0] += part[2 * b];
+        q[1] += part[2 * b + 1];
+    }
+    block_sum<2>(q, lds);
+    if (threadIdx.x == 0) {
+        out[0] = sqrt(q[0]);
+        out[1] = sqrt(q[1]);
+    }
+}
+
 // p := x at unknown cells.
 __global__ void k_writeback(int Nc, const uint8_t* __restrict__ unknown, const double* __restrict__ x,
                             double* __restrict__ p) {
@@ -971,6 +1012,35 @@ static void free_vec(KVec<T>& V) {
     T* ptrs[9] = {V.x, V.r, V.rhat, V.s, V.t, V.p[0], V.p[1], V.v[0], V.v[1]};
     for (T* q : ptrs)
         if (q) (void)hipFree(q);
+}
+
+// Residual of the PPE at p: r = (rhs - Dirichlet and Neumann columns) - A p
+// on unknown rows.  norms = (||r||_2, ||b_eff||_2).  Runs on the caller's
+// stream and returns after it has drained.
+hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
+                             const double* p, double* r, double norms[2], int* bad, hipStream_t st) {
+    const int g = (m.Nc + kBlock - 1) / kBlock > 8192 ? 8192 : (m.Nc + kBlock - 1) / kBlock;
+    const int gr = (m.Nc + kBlock - 1) / kBlock > 2 * kKGrid ? 2 * kKGrid : (m.Nc + kBlock - 1) / kBlock;
+    double* part = w.kb64.part[0];     // 4 * cap >= 2 * gr doubles
+    double* fin = w.kb64.part[1];
+    if (m.dim == 2) {
+        hipLaunchKernelGGL(k_ppe_rhs<2>, dim3(g), dim3(kBlock), 0, st, m, set, rhs, p, fneu, 1, w.beff, w.v64.x, bad);
+        hipLaunchKernelGGL(k_ppe_resid<2>, dim3(gr), dim3(kBlock), 0, st, m, set.amat, set.unknown, w.beff, w.v64.x,
+                           r, part);
+    } else {
+        hipLaunchKernelGGL(k_ppe_rhs<3>, dim3(g), dim3(kBlock), 0, st, m, set, rhs, p, fneu, 1, w.beff, w.v64.x, bad);
+        hipLaunchKernelGGL(k_ppe_resid<3>, dim3(gr), dim3(kBlock), 0, st, m, set.amat, set.unknown, w.beff, w.v64.x,
+                           r, part);
+    }
+    hipLaunchKernelGGL(k_resid_finish, dim3(1), dim3(kBlock), 0, st, part, gr, fin);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(w.host, fin, 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const double* h = reinterpret_cast<const double*>(w.host);
+    norms[0] = h[0];
+    norms[1] = h[1];
+    return hipSuccess;
 }
 
 hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {

@@ -294,73 +294,79 @@ __device__ __forceinline__ bool unk_of(int r, const BcDev& bc) {
     return bc.type[r & (MCD_MAX_IDS - 1)] == MCD_BC_NEUMANN;
 }
 
-// partials of sum over unknown cells of b^2
-__global__ __launch_bounds__(256) void k_sumsq_part(const double* __restrict__ b, const int8_t* __restrict__ role,
-                                                    BcDev bc, int P, double* __restrict__ part, double* count) {
-    __shared__ double lds[2][4];
-    double s = 0.0, n = 0.0;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
-        if (unk_of(role[p], bc)) {
-            s += b[p] * b[p];
+// partials over unknown cells of r^2, p^2 and the cell count
+__global__ __launch_bounds__(256) void k_sumsq_part(const double* __restrict__ r, const double* __restrict__ p,
+                                                    const int8_t* __restrict__ role, BcDev bc, int P,
+                                                    double* __restrict__ part) {
+    __shared__ double lds[3][4];
+    double sr = 0.0, sp = 0.0, n = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < P; c += gridDim.x * blockDim.x)
+        if (unk_of(role[c], bc)) {
+            sr += r[c] * r[c];
+            sp += p[c] * p[c];
             n += 1.0;
         }
-    double v[2] = {s, n};
-    block_sum<2>(v, lds);
+    double v[3] = {sr, sp, n};
+    block_sum<3>(v, lds);
     if (threadIdx.x == 0) {
-        part[blockIdx.x] = v[0];
-        count[blockIdx.x] = v[1];
+        part[3 * blockIdx.x] = v[0];
+        part[3 * blockIdx.x + 1] = v[1];
+        part[3 * blockIdx.x + 2] = v[2];
     }
 }
 
-// rms = sqrt(mean b^2 over unknown cells) from the partials (one block)
-__global__ void k_rms(const double* __restrict__ part, const double* __restrict__ count, int nblk, double* rms) {
-    __shared__ double lds[2][4];
-    double v[2] = {0.0, 0.0};
+// rms[0] = rms(r), rms[1] = rms(p) over unknown cells (1 where 0), one block
+__global__ void k_rms(const double* __restrict__ part, int nblk, double* rms) {
+    __shared__ double lds[3][4];
+    double v[3] = {0.0, 0.0, 0.0};
     for (int b = threadIdx.x; b < nblk; b += blockDim.x) {
-        v[0] += part[b];
-        v[1] += count[b];
+        v[0] += part[3 * b];
+        v[1] += part[3 * b + 1];
+        v[2] += part[3 * b + 2];
     }
-    block_sum<2>(v, lds);
+    block_sum<3>(v, lds);
     if (threadIdx.x == 0) {
-        const double r = v[1] > 0 ? sqrt(v[0] / v[1]) : 1.0;
-        *rms = r > 0 ? r : 1.0;
+        const double rr = v[2] > 0 ? sqrt(v[0] / v[2]) : 1.0;
+        const double rp = v[2] > 0 ? sqrt(v[1] / v[2]) : 1.0;
+        rms[0] = rr > 0 ? rr : 1.0;
+        rms[1] = rp > 0 ? rp : 1.0;
     }
 }
 
-__global__ void k_pack(const double* __restrict__ b, const double* __restrict__ pprev,
+__global__ void k_pack(const double* __restrict__ r, const double* __restrict__ pprev,
                        const int8_t* __restrict__ role, BcDev bc, int body_id, int wall_id, int P,
                        const double* __restrict__ rms, __bf16* __restrict__ x0) {
-    const double inv = 1.0 / *rms;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
-        const int r = role[p];
-        const bool u = unk_of(r, bc);
+    const double inv_r = 1.0 / rms[0], inv_p = 1.0 / rms[1];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < P; c += gridDim.x * blockDim.x) {
+        const int ro = role[c];
+        const bool u = unk_of(ro, bc);
         float v[kIn];
 #pragma unroll
-        for (int c = 0; c < kIn; ++c) v[c] = 0.0f;
-        v[0] = u ? (float)(b[p] * inv) : 0.0f;
-        v[1] = u ? (float)(pprev[p] * inv) : 0.0f;
-        v[2] = r == MCD_ROLE_INNER ? 1.0f : 0.0f;
-        v[3] = r == body_id ? 1.0f : 0.0f;
-        v[4] = r == wall_id ? 1.0f : 0.0f;
+        for (int q = 0; q < kIn; ++q) v[q] = 0.0f;
+        v[0] = u ? (float)(r[c] * inv_r) : 0.0f;
+        v[1] = u ? (float)(pprev[c] * inv_p) : 0.0f;
+        v[2] = ro == MCD_ROLE_INNER ? 1.0f : 0.0f;
+        v[3] = ro == body_id ? 1.0f : 0.0f;
+        v[4] = ro == wall_id ? 1.0f : 0.0f;
 #pragma unroll
-        for (int c = 0; c < kIn; ++c) x0[(size_t)p * kIn + c] = (__bf16)v[c];
+        for (int q = 0; q < kIn; ++q) x0[(size_t)c * kIn + q] = (__bf16)v[q];
     }
 }
 
-// partials of num = sum_u (h - (P - Pprev)/rms)^2 and den = sum_u (P/rms)^2
+// partials of num = sum_u (h - t)^2 and den = sum_u t^2, t = (P - Pprev) / (s rms(r))
 __global__ __launch_bounds__(256) void k_loss_part(const float* __restrict__ h, const double* __restrict__ Pt,
                                                    const double* __restrict__ pprev, const int8_t* __restrict__ role,
-                                                   BcDev bc, int P, const double* __restrict__ rms,
+                                                   BcDev bc, int P, const double* __restrict__ rms, double scale,
                                                    double* __restrict__ part) {
     __shared__ double lds[2][4];
-    const double inv = 1.0 / *rms;
+    const double inv = 1.0 / (scale * rms[0]);
     double num = 0.0, den = 0.0;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
-        if (unk_of(role[p], bc)) {
-            const double tc = (Pt[p] - pprev[p]) * inv;
-            const double d = (double)h[p] - tc;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < P; c += gridDim.x * blockDim.x)
+        if (unk_of(role[c], bc)) {
+            const double t = (Pt[c] - pprev[c]) * inv;
+            const double d = (double)h[c] - t;
             num += d * d;
-            den += (Pt[p] * inv) * (Pt[p] * inv);
+            den += t * t;
         }
     double v[2] = {num, den};
     block_sum<2>(v, lds);
@@ -370,7 +376,7 @@ __global__ __launch_bounds__(256) void k_loss_part(const float* __restrict__ h, 
     }
 }
 
-// loss = num / den (one block) and dh = 2 (h - tc) / den at unknown cells
+// loss = num / den (one block); den = 1 where it is 0
 __global__ void k_loss_finish(const double* __restrict__ part, int nblk, double* loss) {
     __shared__ double lds[2][4];
     double v[2] = {0.0, 0.0};
@@ -385,24 +391,26 @@ __global__ void k_loss_finish(const double* __restrict__ part, int nblk, double*
     }
 }
 
+// dh = 2 (h - t) / den at unknown cells, 0 elsewhere
 __global__ void k_loss_grad(const float* __restrict__ h, const double* __restrict__ Pt,
                             const double* __restrict__ pprev, const int8_t* __restrict__ role, BcDev bc, int P,
-                            const double* __restrict__ rms, const double* __restrict__ loss, float* __restrict__ dh) {
-    const double inv = 1.0 / *rms, den = loss[1];
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
+                            const double* __restrict__ rms, double scale, const double* __restrict__ loss,
+                            float* __restrict__ dh) {
+    const double inv = 1.0 / (scale * rms[0]), den = loss[1];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < P; c += gridDim.x * blockDim.x) {
         float g = 0.0f;
-        if (unk_of(role[p], bc)) g = (float)(2.0 * ((double)h[p] - (Pt[p] - pprev[p]) * inv) / den);
-        dh[p] = g;
+        if (unk_of(role[c], bc)) g = (float)(2.0 * ((double)h[c] - (Pt[c] - pprev[c]) * inv) / den);
+        dh[c] = g;
     }
 }
 
-// guess = pprev + rms * h at unknown cells (FP64); other cells untouched
+// guess = pprev + s rms(r) h at unknown cells (FP64); other cells untouched
 __global__ void k_unpack(const float* __restrict__ h, const double* __restrict__ pprev,
                          const int8_t* __restrict__ role, BcDev bc, int P, const double* __restrict__ rms,
-                         double* __restrict__ out) {
-    const double r = *rms;
-    for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x)
-        if (unk_of(role[p], bc)) out[p] = pprev[p] + r * (double)h[p];
+                         double scale, double* __restrict__ out) {
+    const double f = scale * rms[0];
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < P; c += gridDim.x * blockDim.x)
+        if (unk_of(role[c], bc)) out[c] = pprev[c] + f * (double)h[c];
 }
 
 // Adam (Kingma & Ba) on FP32 master weights with bias correction.
@@ -463,7 +471,8 @@ struct UNet {
     float* part;         // weight-gradient partials
     size_t part_cap;     // floats
     double* red;         // reduction scratch
-    double* rms;         // [1]
+    double* rms;         // [2]: rms(r), rms(p_prev)
+    double out_scale;    // s of the guess p_prev + s rms(r) h
     double* loss;        // [2]
     double* loss_host;   // pinned [2]
     long long step;
@@ -534,8 +543,8 @@ hipError_t unet_forward(UNet& u, const double* b, const double* pprev, const int
                         hipStream_t st) {
     const int P = u.H * u.W;
     const int nb = 256;
-    hipLaunchKernelGGL(k_sumsq_part, dim3(nb), dim3(256), 0, st, b, role, bc, P, u.red, u.red + nb);
-    hipLaunchKernelGGL(k_rms, dim3(1), dim3(256), 0, st, u.red, u.red + nb, nb, u.rms);
+    hipLaunchKernelGGL(k_sumsq_part, dim3(nb), dim3(256), 0, st, b, pprev, role, bc, P, u.red);
+    hipLaunchKernelGGL(k_rms, dim3(1), dim3(256), 0, st, u.red, nb, u.rms);
     hipLaunchKernelGGL(k_pack, dim3(grid_of(P)), dim3(256), 0, st, b, pprev, role, bc, u.body_id, u.wall_id, P,
                        u.rms, u.x0);
     int li = 0;
@@ -589,10 +598,11 @@ hipError_t unet_train_step(UNet& u, const double* b, const double* pprev, const 
     if (e != hipSuccess) return e;
     const int P = u.H * u.W;
     const int nb = 256;
-    hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, st, u.h, Pt, pprev, role, bc, P, u.rms, u.red);
+    hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, st, u.h, Pt, pprev, role, bc, P, u.rms, u.out_scale,
+                       u.red);
     hipLaunchKernelGGL(k_loss_finish, dim3(1), dim3(256), 0, st, u.red, nb, u.loss);
-    hipLaunchKernelGGL(k_loss_grad, dim3(grid_of(P)), dim3(256), 0, st, u.h, Pt, pprev, role, bc, P, u.rms, u.loss,
-                       u.dh);
+    hipLaunchKernelGGL(k_loss_grad, dim3(grid_of(P)), dim3(256), 0, st, u.h, Pt, pprev, role, bc, P, u.rms,
+                       u.out_scale, u.loss, u.dh);
     // head
     const int nl = u.nlayers;
     const ConvLayer& Hd = u.layers[nl - 1];
@@ -668,7 +678,8 @@ hipError_t unet_infer(UNet& u, const double* b, const double* pprev, const int8_
     hipError_t e = unet_forward(u, b, pprev, role, bc, st);
     if (e != hipSuccess) return e;
     const int P = u.H * u.W;
-    hipLaunchKernelGGL(k_unpack, dim3(grid_of(P)), dim3(256), 0, st, u.h, pprev, role, bc, P, u.rms, out);
+    hipLaunchKernelGGL(k_unpack, dim3(grid_of(P)), dim3(256), 0, st, u.h, pprev, role, bc, P, u.rms, u.out_scale,
+                       out);
     return hipGetLastError();
 }
 
@@ -707,6 +718,7 @@ hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall
     u->W = W;
     u->body_id = body_id;
     u->wall_id = wall_id;
+    u->out_scale = 1.0;
     for (int l = 0; l < L; ++l) u->ch[l] = ch[l];
     size_t off = 0;
     int n = 0;
@@ -776,7 +788,7 @@ hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall
     if ((e = dalloc((void**)&u->dh, P * 4)) != hipSuccess) return e;
     if ((e = dalloc((void**)&u->part, u->part_cap * 4)) != hipSuccess) return e;
     if ((e = dalloc((void**)&u->red, 1024 * sizeof(double))) != hipSuccess) return e;
-    if ((e = dalloc((void**)&u->rms, sizeof(double))) != hipSuccess) return e;
+    if ((e = dalloc((void**)&u->rms, 2 * sizeof(double))) != hipSuccess) return e;
     if ((e = dalloc((void**)&u->loss, 2 * sizeof(double))) != hipSuccess) return e;
     if ((e = hipHostMalloc((void**)&u->loss_host, 2 * sizeof(double), hipHostMallocDefault)) != hipSuccess) return e;
     return hipDeviceSynchronize();
@@ -786,6 +798,7 @@ size_t unet_nparams(const UNet& u) { return u.nparams; }
 float* unet_theta(UNet& u) { return u.theta; }
 float* unet_grad(UNet& u) { return u.grad; }
 float* unet_head_out(UNet& u) { return u.h; }
+void unet_set_output_scale(UNet& u, double s) { u.out_scale = s; }
 void unet_reset_optimizer(UNet& u, hipStream_t st) {
     (void)hipMemsetAsync(u.m, 0, u.nparams * 4, st);
     (void)hipMemsetAsync(u.v, 0, u.nparams * 4, st);

@@ -30,9 +30,11 @@ MAX_SETS = 4
 
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
             "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
-            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_profile", "mcd_profile_read",
+            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_ppe_residual", "mcd_profile",
+            "mcd_profile_read",
             "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
-            "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_infer",
+            "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_set_output_scale",
+            "mcd_model_infer",
             "mcd_model_train_step")
 
 
@@ -104,6 +106,7 @@ def load():
         "mcd_neumann_pressure": (i, [vp, vp, vp, P(Body), i, vp]),
         "mcd_project": (i, [vp, i, vp, vp, vp, d, vp, P(Body), i, vp]),
         "mcd_solve_ppe": (i, [vp, i, vp, vp, vp, P(SolveOpts), P(SolveInfo)]),
+        "mcd_ppe_residual": (i, [vp, i, vp, vp, vp, vp, P(d)]),
         "mcd_profile": (i, [vp, i]),
         "mcd_model_create": (i, [vp, i, P(i), i, P(vp)]),
         "mcd_model_destroy": (None, [vp]),
@@ -112,6 +115,7 @@ def load():
         "mcd_model_get_params": (i, [vp, vp, C.c_size_t]),
         "mcd_model_get_grads": (i, [vp, vp, C.c_size_t]),
         "mcd_model_output": (i, [vp, vp]),
+        "mcd_model_set_output_scale": (i, [vp, d]),
         "mcd_model_infer": (i, [vp, vp, vp, vp, P(BcTable), vp]),
         "mcd_model_train_step": (i, [vp, vp, vp, vp, vp, P(BcTable), d, P(d)]),
         "mcd_profile_read": (i, [vp, P(d), P(C.c_longlong), P(d), P(C.c_longlong), i]),
@@ -315,6 +319,14 @@ class Context:
             self._check(st, "mcd_solve_ppe")
         return out
 
+    def ppe_residual(self, set_id, rhs, p, r, neumann_f=None):
+        """r := b_eff - A p on unknown rows; returns (||r||, ||b_eff||)."""
+        norms = (C.c_double * 2)()
+        N, V = self.Nc, self._vec
+        self._check(self.lib.mcd_ppe_residual(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), V(r, N),
+                                              norms), "mcd_ppe_residual")
+        return norms[0], norms[1]
+
     def profile(self, enable=True):
         self._check(self.lib.mcd_profile(self.h, int(bool(enable))), "mcd_profile")
 
@@ -375,17 +387,21 @@ class Model:
     def output(self, h):
         self.ctx._check(self.lib.mcd_model_output(self.h, _ptr(h, self.ctx.Nc, torch.float32)), "mcd_model_output")
 
-    def infer(self, rhs, p_prev, role, bc: dict, p_out):
+    def set_output_scale(self, s):
+        self.ctx._check(self.lib.mcd_model_set_output_scale(self.h, float(s)), "mcd_model_set_output_scale")
+
+    def infer(self, resid, p_prev, role, bc: dict, p_out):
+        """p_out := p_prev + s rms(resid) h; resid = PPE residual of p_prev."""
         t = bc_table(bc)
         N, V = self.ctx.Nc, self.ctx._vec
-        self.ctx._check(self.lib.mcd_model_infer(self.h, V(rhs, N), V(p_prev, N), _ptr(role, N, torch.int8),
+        self.ctx._check(self.lib.mcd_model_infer(self.h, V(resid, N), V(p_prev, N), _ptr(role, N, torch.int8),
                                                  C.byref(t), V(p_out, N)), "mcd_model_infer")
 
-    def train_step(self, rhs, p_prev, p_target, role, bc: dict, lr, want_loss=True):
+    def train_step(self, resid, p_prev, p_target, role, bc: dict, lr, want_loss=True):
         t = bc_table(bc)
         N, V = self.ctx.Nc, self.ctx._vec
         loss = C.c_double(float("nan"))
-        self.ctx._check(self.lib.mcd_model_train_step(self.h, V(rhs, N), V(p_prev, N), V(p_target, N),
+        self.ctx._check(self.lib.mcd_model_train_step(self.h, V(resid, N), V(p_prev, N), V(p_target, N),
                                                       _ptr(role, N, torch.int8), C.byref(t), float(lr),
                                                       C.byref(loss) if want_loss else None),
                         "mcd_model_train_step")

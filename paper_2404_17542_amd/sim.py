@@ -3,7 +3,9 @@
 Order of one step k -> k+1 (Sec. 3.3 with the DP update of Sec. 2.3-2.4):
 rearrange DPs and reassign roles at t^{k+1}; remap u^k to x^{k+1} with the
 step-k velocity weights; build the velocity and pressure weights at x^{k+1};
-u* and the PPE right-hand side; Neumann datum -dV/dt . n; Bi-CGSTAB; project.
+u* and the PPE right-hand side; Neumann datum -dV/dt . n; the initial guess
+(previous pressure, zero, or the previous pressure corrected by the learned
+network); Bi-CGSTAB; project.
 Every step runs in libmcd kernels; this module only sequences the calls and
 owns the device arrays (torch tensors on one stream).
 """
@@ -23,8 +25,12 @@ SET_P = 2
 
 
 class GpuSim:
-    def __init__(self, case, precision=M.PREC_FP64, device="cuda", check_every=16, update_info=True):
+    def __init__(self, case, precision=M.PREC_FP64, device="cuda", check_every=16, update_info=True,
+                 guess="warm", model=None):
         self.case = case
+        self.guess = guess
+        self.model = model
+        self.resid = None
         self.device = device
         self.precision = precision
         self.check_every = check_every
@@ -87,7 +93,9 @@ class GpuSim:
         return [{"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
                  "dvdt": dvdt}]
 
-    def step(self):
+    def prepare(self):
+        """First half of a step: DP update at t^{k+1}, remap, weights, u* and
+        the PPE data.  Leaves (pset, bodies_new, update info)."""
         case, ctx = self.case, self.ctx
         tn = (self.k + 1) * case.dt
         bodies_new = self.bodies_at(tn, self.bodies) if self.bodies else []
@@ -106,13 +114,32 @@ class GpuSim:
             pset = SET_P
         ctx.advect_diffuse(new, self.ut, case.dt, case.nu, self.role, bodies_new, self.ustar, self.rhs)
         ctx.neumann_pressure(self.role, self.normal, bodies_new, self.fP)
-        info = ctx.solve_ppe(pset, self.rhs, self.P, self.fP, tol=case.tol, precision=self.precision,
-                             guess=M.GUESS_CALLER, check_every=self.check_every)
-        ctx.project(pset, self.P, self.fP, self.ustar, case.dt, self.role, bodies_new, self.u)
+        return pset, bodies_new, upd
+
+    def initial_guess(self, pset, mode):
+        """Prepares the solver's initial guess and returns the solver's guess
+        flag: 'warm' keeps P^k, 'zero' starts from 0 at the unknowns,
+        'learned' adds the network's correction to P^k (the network reads the
+        PPE residual of P^k under the new weights)."""
+        if mode == "warm":
+            return M.GUESS_CALLER
+        if mode == "zero":
+            return M.GUESS_ZERO
+        if mode != "learned" or self.model is None:
+            raise ValueError(f"unknown initial guess {mode!r} (or no model for 'learned')")
+        if self.resid is None:
+            self.resid = torch.zeros_like(self.P)
+        self.ctx.ppe_residual(pset, self.rhs, self.P, self.resid, self.fP)
+        self.model.infer(self.resid, self.P, self.role, self.case.bc_pressure, self.P)
+        return M.GUESS_CALLER
+
+    def finish(self, pset, bodies_new, info, upd):
+        case = self.case
+        self.ctx.project(pset, self.P, self.fP, self.ustar, case.dt, self.role, bodies_new, self.u)
         self.vel_slot = 1 - self.vel_slot
         self.bodies = bodies_new
         self.k += 1
-        self.t = tn
+        self.t = (self.k) * case.dt
         rec = {"k": self.k, "iters": info["iterations"], "restarts": info["restarts"],
                "refinements": info["refinements"], "rel_res": info["true_rel_residual"],
                "converged": info["converged"]}
@@ -120,6 +147,15 @@ class GpuSim:
             rec.update({"sweeps": upd["sweeps"], "trans": upd["counts"]})
         self.log.append(rec)
         return rec
+
+    def solve(self, pset, guess=M.GUESS_CALLER):
+        return self.ctx.solve_ppe(pset, self.rhs, self.P, self.fP, tol=self.case.tol, precision=self.precision,
+                                  guess=guess, check_every=self.check_every)
+
+    def step(self):
+        pset, bodies_new, upd = self.prepare()
+        info = self.solve(pset, self.initial_guess(pset, self.guess))
+        return self.finish(pset, bodies_new, info, upd)
 
     def ctx_unknown_count(self):
         """PPE unknowns of the current step (inner and Neumann DPs, minus a pin)."""

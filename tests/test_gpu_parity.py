@@ -337,6 +337,36 @@ def test_ppe_cylinder_neumann(M):
         assert np.linalg.norm(b - A @ pg[uidx]) / np.linalg.norm(b) <= 1e-8
 
 
+def test_ppe_residual_matches_oracle(M):
+    """mcd_ppe_residual = b_eff - A p of the oracle's assembled system, with
+    Dirichlet values taken from p and Neumann data moved to the right side."""
+    case = configs.c2_oscillating_cylinder(n=128)
+    m, pos, role, nrm = _arranged(case)
+    rng = np.random.default_rng(5)
+    rhs = rng.standard_normal(m.Nc)
+    f = np.where(role == 2, rng.standard_normal(m.Nc), 0.0)
+    p = rng.standard_normal(m.Nc)            # random values at known DPs act as Dirichlet data
+    ctx = M.Context.from_case(case)
+    ctx.build_stencils(2, _dev(pos), _dev(role, torch.int8), _dev(nrm), case.bc_pressure)
+    st = O.mls_build(m, pos, role, nrm, case.bc_pressure, case.re_over_l0 * case.l0, case.l0, case.weight)
+    A, beff, uidx = O.ppe_system(m, st, role, case.bc_pressure, rhs, p, f)
+    r_ora = beff - A @ p[uidx]
+    r = _dev(np.full(m.Nc, 9.0))
+    nr, nb = ctx.ppe_residual(2, _dev(rhs), _dev(p), r, _dev(f))
+    rg = np_(r)
+    unk = np.zeros(m.Nc, bool)
+    unk[uidx] = True
+    assert np.all(rg[~unk] == 0.0)
+    err = np.abs(rg[uidx] - r_ora) / (np.abs(beff) + np.abs(A) @ np.abs(p[uidx]))
+    assert err.max() <= 1e-13, err.max()
+    assert nr == pytest.approx(np.linalg.norm(r_ora), rel=1e-12)
+    assert nb == pytest.approx(np.linalg.norm(beff), rel=1e-12)
+    # the solver's own stopping quantity agrees: after a solve, ||r|| / ||b_eff|| <= tol
+    info = ctx.solve_ppe(2, _dev(rhs), pp := _dev(p), _dev(f), guess=M.GUESS_CALLER)
+    nr2, nb2 = ctx.ppe_residual(2, _dev(rhs), pp, r, _dev(f))
+    assert nr2 / nb2 <= 1e-8 and nr2 / nb2 == pytest.approx(info["true_rel_residual"], rel=1e-6)
+
+
 def test_ppe_not_converged_and_bad_rhs(M):
     case, m, pos, role, nrm, st, rhs, g = _c0_problem(32)
     ctx = M.Context.from_case(case)

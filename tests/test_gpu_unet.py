@@ -27,12 +27,14 @@ def _dev(a, dtype=torch.float64):
 
 
 def _problem(n=64, seed=0):
+    """Network inputs of a cylinder mesh: a residual-like field b, a smooth
+    warm start and a nearby target pressure."""
     case = configs.c2_oscillating_cylinder(n=n)
     m = O.Mesh.from_case(case)
     role = O.roles(m, oracle_bodies(case, 0.0))
     unknown = O.unknown_mask(role, case.bc_pressure)
     rng = np.random.default_rng(seed)
-    b = rng.standard_normal(m.Nc) * 50.0
+    b = np.where(unknown, rng.standard_normal(m.Nc) * 50.0, 0.0)
     pos = inputs.cell_centroids(case.n, case.origin, case.l0)
     smooth = np.sin(pos[0]) * np.cos(0.7 * pos[1])
     p_prev = np.where(unknown, smooth + 0.1 * rng.standard_normal(m.Nc), 0.0)
@@ -40,11 +42,12 @@ def _problem(n=64, seed=0):
     return case, m, role, unknown, b, p_prev, p_tgt
 
 
-@pytest.mark.parametrize("ch", [(16, 32), (16, 32, 64)])
-def test_unet_forward_loss_and_gradients_match_reference(M, ch):
+@pytest.mark.parametrize("ch,scale", [((16, 32), 1.0), ((16, 32, 64), 2.5)])
+def test_unet_forward_loss_and_gradients_match_reference(M, ch, scale):
     case, m, role, unknown, b, p_prev, p_tgt = _problem()
     ctx = M.Context.from_case(case)
     model = M.Model(ctx, ch)
+    model.set_output_scale(scale)
     shapes = [(a, c) for _, a, c in U.layer_shapes(ch)]
     theta = inputs.he_normal_params(shapes, 5)
     # a small non-zero head so that gradients reach every layer
@@ -58,14 +61,14 @@ def test_unet_forward_loss_and_gradients_match_reference(M, ch):
     model.output(h_gpu)
     h_gpu = np_(h_gpu)
     # reference in FP64
-    x, rms = U.pack_input(b, p_prev, role, unknown, case.n)
+    x, rr = U.pack_input(b, p_prev, role, unknown, case.n)
     th64 = theta.astype(np.float64)
     out, cache = U.forward(th64, x, ch)
-    h_ref = (out - x[:, :, 1]).reshape(-1)
+    h_ref = out.reshape(-1)
     rel = np.linalg.norm(h_gpu - h_ref) / np.linalg.norm(h_ref)
     assert rel <= 2e-2, rel
-    loss_ref, dout = U.loss_and_grad_out(out, (p_tgt / rms).reshape(case.n[1], case.n[0]),
-                                         unknown.reshape(case.n[1], case.n[0]))
+    tgt = U.correction_target(p_tgt, p_prev, rr, scale, case.n)
+    loss_ref, dout = U.loss_and_grad_out(out, tgt, unknown.reshape(case.n[1], case.n[0]))
     assert loss == pytest.approx(loss_ref, rel=2e-2)
     g_ref = U.backward(th64, cache, dout, ch)
     off = 0
@@ -80,7 +83,7 @@ def test_unet_forward_loss_and_gradients_match_reference(M, ch):
             assert np.linalg.norm(gg) == pytest.approx(np.linalg.norm(gr), rel=5e-2), (name, part)
 
 
-def test_unet_infer_adds_the_correction_to_the_warm_start(M):
+def test_unet_infer_adds_the_scaled_correction_to_the_warm_start(M):
     case, m, role, unknown, b, p_prev, p_tgt = _problem()
     ctx = M.Context.from_case(case)
     ch = (16, 32)
@@ -93,12 +96,29 @@ def test_unet_infer_adds_the_correction_to_the_warm_start(M):
     o = np_(out)
     assert np.array_equal(o[unknown], p_prev[unknown])
     assert np.all(o[~unknown] == 7.0)
+    # non-zero head: p_prev + s rms(r) h with the kernels' own h
+    theta = inputs.he_normal_params([(a, c) for _, a, c in U.layer_shapes(ch)], 2)
+    model.set_params(theta)
+    model.set_output_scale(3.0)
+    pp = _dev(p_prev)
+    model.infer(_dev(b), pp, _dev(role, torch.int8), case.bc_pressure, pp)      # in place
+    h = torch.zeros(m.Nc, dtype=torch.float32, device="cuda")
+    model.output(h)
+    h = np_(h).astype(np.float64)
+    _, rr = U.pack_input(b, p_prev, role, unknown, case.n)
+    expect = p_prev + 3.0 * rr * h
+    got = np_(pp)
+    assert np.allclose(got[unknown], expect[unknown], rtol=1e-12, atol=1e-12 * np.abs(expect).max())
+    assert np.array_equal(got[~unknown], p_prev[~unknown])
+    with pytest.raises(M.McdError):
+        model.set_output_scale(0.0)
 
 
 def test_unet_training_reduces_loss(M):
     """Adam on one fixed sample whose target is a learnable function of the
-    inputs (1.1 x the warm start).  The FP64 reference network trained the same
-    way ends 200 steps at 0.09 x the first loss; the BF16 kernels must reach
+    inputs (1.1 x the warm start, i.e. a correction proportional to input
+    channel 1).  The FP64 reference network trained the same way ends 200
+    steps at a small fraction of the first loss; the BF16 kernels must reach
     0.3 x."""
     case, m, role, unknown, b, p_prev, _ = _problem(seed=2)
     p_tgt = 1.1 * p_prev
@@ -114,4 +134,5 @@ def test_unet_training_reduces_loss(M):
     for _ in range(200):
         model.train_step(*args, lr, want_loss=False)
     last = model.train_step(*args, lr)
+    assert first == pytest.approx(1.0)
     assert np.isfinite(last) and last < 0.3 * first, (first, last)

@@ -62,8 +62,8 @@ def test_layer_identities():
     assert np.allclose(U.pool2_backward(b), U.up2(b) / 4)
 
 
-def test_untrained_net_starts_near_the_warm_start():
-    """out = head(...) + channel 1: with a zero head the net is the warm start."""
+def test_zero_head_predicts_no_correction():
+    """The head output is the correction to the warm start: a zero head gives 0."""
     ch = (16, 32)
     theta = U.init_params(ch, 0)
     P = U.unpack(theta, ch)
@@ -71,7 +71,33 @@ def test_untrained_net_starts_near_the_warm_start():
     rng = np.random.default_rng(0)
     x = rng.standard_normal((16, 16, U.IN_CHANNELS)).astype(np.float32)
     out, _ = U.forward(theta, x, ch)
-    assert np.allclose(out, x[:, :, 1])
+    assert np.all(out == 0.0)
+
+
+def test_pack_input_scales_each_field_by_its_own_rms():
+    rng = np.random.default_rng(4)
+    n = (8, 4)
+    role = np.full(32, -1, dtype=np.int8)
+    role[:3] = 0
+    role[3:5] = 2
+    role[5:8] = 1
+    unknown = (role == -1) | (role == 2)
+    r = rng.standard_normal(32) * 1e3
+    p = rng.standard_normal(32) * 1e-2
+    x, rr = U.pack_input(r, p, role, unknown, n)
+    assert x.shape == (4, 8, U.IN_CHANNELS)
+    c0 = x[:, :, 0].reshape(-1)[unknown]
+    c1 = x[:, :, 1].reshape(-1)[unknown]
+    assert np.sqrt(np.mean(c0 ** 2)) == pytest.approx(1.0) and np.sqrt(np.mean(c1 ** 2)) == pytest.approx(1.0)
+    assert rr == pytest.approx(np.sqrt(np.mean(r[unknown] ** 2)))
+    assert np.all(x[:, :, :2].reshape(-1, 2)[~unknown] == 0.0)
+    assert np.array_equal(x[:, :, 2].reshape(-1), (role == -1).astype(float))
+    assert np.array_equal(x[:, :, 3].reshape(-1), (role == 2).astype(float))
+    assert np.array_equal(x[:, :, 4].reshape(-1), (role == 1).astype(float))
+    # the correction target undoes the guess formula p_prev + s rms(r) h
+    pt = p + 0.3 * rng.standard_normal(32)
+    t = U.correction_target(pt, p, rr, 2.5, n).reshape(-1)
+    assert np.allclose(p + 2.5 * rr * t, pt)
 
 
 def test_adam_first_step_moves_by_lr():
