@@ -6,6 +6,12 @@ u* and the PPE right-hand side, Bi-CGSTAB to a true relative residual of
 1e-8 (FP64), projection.  Inputs are resident in HBM before the timed
 region starts.  Prints one JSON line.
 
+Other forms: --workload cylinder|sphere, --precision mixed (FP32-stored
+matrix with FP64 residual replacement) or refine (FP32 Bi-CGSTAB inside
+FP64 refinement), --guess zero|learned (--weights: a file written by
+paper_2404_17542_amd.learned).  The tolerance is judged on the FP64
+operator in every form.
+
 --gpus N with N > 1 exits: this build runs on one GPU.
 """
 from __future__ import annotations
@@ -28,11 +34,18 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_bytes(n_unknown, dim, value_bytes):
+def stage_bytes(n_unknown, dim, matrix_bytes, vector_bytes):
     """Algorithmic bytes of one S-stage launch (s = r - alpha v; t = A s):
     A (3^dim planes) + r, v, rhat read once + s, t written once."""
     slots = 3 ** dim
-    return n_unknown * (slots + 5) * value_bytes
+    return n_unknown * (slots * matrix_bytes + 5 * vector_bytes)
+
+
+PRECISIONS = {"fp64": ("PREC_FP64", 8, 8, "f64", "FP64"),
+              "mixed": ("PREC_FP32_MATRIX", 4, 8, "f32 matrix + f64",
+                        "FP32-stored matrix, FP64 vectors, FP64 residual replacement"),
+              "refine": ("PREC_FP32_REFINE", 4, 4, "f32 + f64 refinement",
+                         "FP32 Bi-CGSTAB inside FP64 refinement")}
 
 
 def workload_name(case, n_active, precision):
@@ -75,7 +88,10 @@ def main():
                     help="tgv: 512^2 periodic Taylor-Green (default line); cylinder: 1024^2 oscillating "
                          "cylinder; sphere: 128^3 moving sphere")
     ap.add_argument("--n", type=int, default=None)
-    ap.add_argument("--precision", choices=["fp64", "mixed"], default="fp64")
+    ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp64")
+    ap.add_argument("--guess", choices=["warm", "zero", "learned"], default="warm",
+                    help="PPE initial guess: previous pressure (default), zero, or the learned correction")
+    ap.add_argument("--weights", default=None, help="network weights for --guess learned")
     ap.add_argument("--cpu-steps", type=int, default=2)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -100,9 +116,16 @@ def main():
         case = configs.c2_oscillating_cylinder(n=args.n or 1024, steps=args.steps)
     else:
         case = configs.c4_moving_sphere(n=args.n or 128, steps=args.steps)
-    prec = mcd.PREC_FP64 if args.precision == "fp64" else mcd.PREC_FP32_REFINE
+    prec_name, mat_b, vec_b, dtype, prec_text = PRECISIONS[args.precision]
+    prec = getattr(mcd, prec_name)
     log(f"setting up {case.name}")
     sim = GpuSim(case, precision=prec, update_info=False)
+    if args.guess == "learned":
+        if not args.weights:
+            raise SystemExit("--guess learned needs --weights (written by paper_2404_17542_amd.learned)")
+        from paper_2404_17542_amd import learned
+        sim.model = learned.load_model(sim.ctx, args.weights)
+    sim.guess = args.guess
     for _ in range(args.warmup):
         sim.step()
     torch.cuda.synchronize()
@@ -133,8 +156,7 @@ def main():
         prof = sim.ctx.profile_read(reset=True)
         sim.ctx.profile(False)
         n_unknown = int(sim.ctx_unknown_count()) if hasattr(sim, "ctx_unknown_count") else n_active
-        vb = 8 if args.precision == "fp64" else 4
-        bytes_per = stage_bytes(n_unknown, case.dim, vb)
+        bytes_per = stage_bytes(n_unknown, case.dim, mat_b, vec_b)
         avg_s = prof["s_ms"] / max(prof["s_n"], 1) * 1e-3
         achieved = bytes_per / avg_s / 1e9 if avg_s > 0 else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -145,10 +167,11 @@ def main():
                     "p_stage_avg_us": prof["p_ms"] / max(prof["p_n"], 1) * 1e3}
     out = {"metric": METRIC, "value": value, "unit": "DP-steps/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3, "higher_is_better": True,
-           "scaling": "weak", "vs_baseline": None, "dtype": "f64" if args.precision == "fp64" else "f32+f64",
+           "scaling": "weak", "vs_baseline": None, "dtype": dtype,
            "data": "synthetic",
-           "config": {"workload": workload_name(case, n_active, args.precision),
-                      "dps": n_active, "ppe_iters_per_step": sum(iters) / len(iters), "max_true_rel_res": worst},
+           "config": {"workload": workload_name(case, n_active, prec_text),
+                      "dps": n_active, "precision": args.precision, "initial_guess": args.guess,
+                      "ppe_iters_per_step": sum(iters) / len(iters), "max_true_rel_res": worst},
            "roofline": roofline}
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         log(f"timing the CPU oracle on {args.cpu_steps} steps")

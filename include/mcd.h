@@ -47,7 +47,15 @@ typedef enum {
 enum { MCD_ROLE_INNER = -1, MCD_ROLE_VOID = 0 };
 enum { MCD_BC_DIRICHLET = 0, MCD_BC_NEUMANN = 1 };
 enum { MCD_WEIGHT_COS2 = 0, MCD_WEIGHT_GAUSS = 1 };
-enum { MCD_PREC_FP64 = 0, MCD_PREC_FP32_REFINE = 1 };
+/* Arithmetic of the PPE solve (the tolerance is judged on the FP64 operator
+ * in every mode):
+ *   FP64         FP64 matrix, vectors and dots.
+ *   FP32_REFINE  FP64 iterative refinement around an FP32 Bi-CGSTAB (FP32
+ *                matrix and vectors, FP64 dots).
+ *   FP32_MATRIX  FP64 Bi-CGSTAB whose matrix products read the FP32-stored
+ *                matrix, with the residual periodically recomputed with the
+ *                FP64 matrix and replaced (Krylov space kept). */
+enum { MCD_PREC_FP64 = 0, MCD_PREC_FP32_REFINE = 1, MCD_PREC_FP32_MATRIX = 2 };
 enum { MCD_GUESS_ZERO = 0, MCD_GUESS_CALLER = 1 };
 
 #define MCD_MAX_IDS 16      /* boundary ids 1 .. 15 */
@@ -230,19 +238,25 @@ mcd_status mcd_project(mcd_ctx* ctx, int set, const double* P, const double* f,
 typedef struct {
     double tol;          /* stop when ||b - A x||_2 <= tol ||b||_2 over unknown rows */
     int max_iter;        /* total Bi-CGSTAB iterations (all restarts/refinements) */
-    int precision;       /* MCD_PREC_FP64 or MCD_PREC_FP32_REFINE */
+    int precision;       /* MCD_PREC_FP64, MCD_PREC_FP32_REFINE or MCD_PREC_FP32_MATRIX */
     int guess;           /* MCD_GUESS_ZERO or MCD_GUESS_CALLER (p on entry) */
-    double inner_tol;    /* FP32 inner solve: relative recurrence residual per refinement step
-                            (FP32_REFINE; about 1e-2, since FP32 Krylov stalls near cond(A) u_32) */
-    int max_outer;       /* refinement steps (FP32_REFINE) */
+    double inner_tol;    /* FP32_REFINE: relative recurrence residual of each FP32 inner solve
+                            (about 1e-2: FP32 Krylov stalls near cond(A) u_32);
+                            FP32_MATRIX: the residual is replaced once the recursive residual is
+                            below inner_tol times its largest value since the last
+                            replacement (about 0.03) */
+    int max_outer;       /* FP32_REFINE: refinement steps; FP32_MATRIX: replacements before plain
+                            FP64 Bi-CGSTAB takes over */
     int check_every;     /* iterations between host convergence checks (16 = graph chunk) */
-    int max_inner;       /* cap on inner iterations per refinement step (0 = none) */
+    int max_inner;       /* FP32_REFINE: cap on inner iterations per refinement step (0 = none) */
 } mcd_solve_opts;
 
 typedef struct {
     int iterations;           /* Bi-CGSTAB iterations executed */
-    int restarts;             /* restarts (true-residual check failed or breakdown) */
-    int refinements;          /* FP64 refinement steps (FP32_REFINE) */
+    int restarts;             /* restarts of the recursion (true-residual check failed,
+                                 breakdown, stall, hand-over to FP64) */
+    int refinements;          /* refinement steps (FP32_REFINE) or residual replacements
+                                 (FP32_MATRIX) */
     int converged;
     double true_rel_residual; /* ||b - A64 x|| / ||b|| in FP64 at exit */
     double rhs_norm;          /* ||b|| of the effective right-hand side */

@@ -709,6 +709,7 @@ def ppe_system(mesh, st, role, bc, rhs, g, f_neu, pin_first=False):
 class SolveInfo:
     iterations: int = 0
     restarts: int = 0
+    refinements: int = 0
     true_rel_residual: float = np.nan
     converged: bool = False
 
@@ -782,18 +783,41 @@ def solve_ppe(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess=
     return p, info, (A, beff, uidx)
 
 
+def fp32_operator(A, vec_dtype):
+    """Product with the FP32 copy of the PPE matrix in difference form: the
+    off-diagonal weights a_ij rounded to FP32 act on differences,
+    (A32 x)_i = sum_j a32_ij (x_j - x_i) + fl32(rowsum_i) x_i, so the zero row
+    sum of a stencil row survives the rounding.  Differences and products are
+    formed in vec_dtype (float32 or float64) and summed in FP64."""
+    A = A.tocoo()
+    off = A.row != A.col
+    rows, cols = A.row[off], A.col[off]
+    a32 = A.data[off].astype(np.float32).astype(vec_dtype)
+    rowsum = np.asarray(A.sum(axis=1)).reshape(-1)
+    d32 = rowsum.astype(np.float32).astype(vec_dtype)
+    n = A.shape[0]
+
+    def matvec(x):
+        x = x.astype(vec_dtype)
+        contrib = (a32 * (x[cols] - x[rows])).astype(vec_dtype)
+        y = np.bincount(rows, weights=contrib.astype(np.float64), minlength=n) + (d32 * x).astype(np.float64)
+        return y.astype(vec_dtype)
+    return matvec
+
+
 def solve_ppe_mixed(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess="zero",
                     inner_tol=1e-2, max_outer=40, max_iter=20000, max_inner=3000):
     """FP32-operator Bi-CGSTAB inside FP64 iterative refinement.
 
-    A32 = FP64 weights rounded to FP32, FP32 vectors, FP64 dot products;
+    A32 = the FP32 copy of the matrix in difference form (fp32_operator),
+    FP32 vectors, FP64 dot products;
     the residual b - A64 x and the update x += d are FP64.  A correction that
     does not lower the FP64 residual is undone and the inner tolerance
     loosened (x3, at most 0.5); after two rejections FP64 Bi-CGSTAB finishes
     from the current iterate.
     """
     A, beff, uidx = ppe_system(mesh, st, role, bc, rhs, p_in, f_neu, pin_first)
-    A32 = A.astype(np.float32)
+    A32 = fp32_operator(A, np.float32)
     x = p_in[uidx].astype(np.float64) if guess == "caller" else np.zeros(len(uidx))
     nb = float(np.linalg.norm(beff))
     info = SolveInfo()
@@ -843,13 +867,13 @@ def _bicgstab32(A32, b32, tol, max_iter):
             break
         beta = (rho_new / rho) * (alpha / omega)
         p = (r + np.float32(beta) * (p - np.float32(omega) * v)).astype(np.float32)
-        v = A32 @ p
+        v = A32(p)
         rv = dot(rhat, v)
         if rv == 0.0:
             break
         alpha = rho_new / rv
         s = (r - np.float32(alpha) * v).astype(np.float32)
-        t = A32 @ s
+        t = A32(s)
         tt = dot(t, t)
         omega = dot(t, s) / tt if tt > 0 else 0.0
         x = (x + np.float32(alpha) * p + np.float32(omega) * s).astype(np.float32)
@@ -859,6 +883,81 @@ def _bicgstab32(A32, b32, tol, max_iter):
         if math.sqrt(dot(r, r)) <= tol * nb or omega == 0.0:
             break
     return x, it
+
+
+def solve_ppe_fp32_matrix(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess="zero",
+                          inner_tol=0.1, max_outer=500, max_iter=20000):
+    """Bi-CGSTAB in FP64 whose matrix products use the FP32-rounded matrix,
+    with residual replacement ("reliable updates", Sleijpen & van der Vorst
+    1996).
+
+    Every product A32 p, A32 s takes the FP32 copy of the matrix in
+    difference form (fp32_operator; the products and all vectors stay FP64).  When the recursive residual has
+    fallen to inner_tol times its largest norm since the last replacement,
+    or to the tolerance, r := b - A64 x is recomputed with the FP64 matrix
+    and the recursion continues from it (search direction and shadow residual
+    kept); the tolerance is only accepted on that FP64 residual.  A breakdown
+    restarts from the FP64 residual; more than max_outer replacements hand
+    over to FP64 Bi-CGSTAB.
+    """
+    A, beff, uidx = ppe_system(mesh, st, role, bc, rhs, p_in, f_neu, pin_first)
+    A32 = fp32_operator(A, np.float64)
+    x = p_in[uidx].astype(np.float64) if guess == "caller" else np.zeros(len(uidx))
+    nb = float(np.linalg.norm(beff))
+    info = SolveInfo()
+    r = beff - A @ x
+    fallback = False
+    while nb > 0 and np.linalg.norm(r) > tol * nb and info.iterations < max_iter and not fallback:
+        rhat = r.copy()
+        rho = alpha = omega = 1.0
+        p = np.zeros_like(x)
+        v = np.zeros_like(x)
+        rmax = float(np.linalg.norm(r))
+        while info.iterations < max_iter:
+            rho_new = float(rhat @ r)
+            beta = (rho_new / rho) * (alpha / omega)
+            p = r + beta * (p - omega * v)
+            v = A32(p)
+            rv = float(rhat @ v)
+            if rv == 0.0:
+                info.restarts += 1
+                r = beff - A @ x
+                break
+            alpha = rho_new / rv
+            s = r - alpha * v
+            t = A32(s)
+            tt = float(t @ t)
+            omega = float(t @ s) / tt if tt > 0 else 0.0
+            x = x + alpha * p + omega * s
+            r = s - omega * t
+            rho = rho_new
+            info.iterations += 1
+            nr = float(np.linalg.norm(r))
+            if omega == 0.0:
+                info.restarts += 1
+                r = beff - A @ x
+                break
+            if nr <= max(tol * nb, inner_tol * rmax):
+                r = beff - A @ x                     # replacement with the FP64 matrix
+                info.refinements += 1
+                rr = float(r @ r)
+                if math.sqrt(rr) <= tol * nb:
+                    break
+                if info.refinements > max_outer:
+                    fallback = True
+                    break
+                rmax = math.sqrt(rr)
+            else:
+                rmax = max(rmax, nr)
+    if fallback and np.linalg.norm(r) > tol * nb and info.iterations < max_iter:
+        x, inf64 = bicgstab(A, beff, x, tol, max_iter - info.iterations)
+        info.iterations += inf64.iterations
+        info.restarts += inf64.restarts + 1
+    info.true_rel_residual = float(np.linalg.norm(beff - A @ x)) / nb if nb > 0 else 0.0
+    info.converged = info.true_rel_residual <= tol
+    p = p_in.copy()
+    p[uidx] = x
+    return p, info
 
 
 # ---------------------------------------------------------------------------

@@ -434,11 +434,12 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
     if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: set not built%s");
     if (!rhs || !p || !opts || !info) return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: null argument%s");
     if (!(opts->tol > 0) || opts->max_iter < 1 ||
-        (opts->precision != MCD_PREC_FP64 && opts->precision != MCD_PREC_FP32_REFINE) ||
+        (opts->precision != MCD_PREC_FP64 && opts->precision != MCD_PREC_FP32_REFINE &&
+         opts->precision != MCD_PREC_FP32_MATRIX) ||
         (opts->guess != MCD_GUESS_ZERO && opts->guess != MCD_GUESS_CALLER))
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid options%s");
-    if (opts->precision == MCD_PREC_FP32_REFINE && (!(opts->inner_tol > 0) || opts->max_outer < 1 ||
-                                                    opts->max_inner < 0))
+    if (opts->precision != MCD_PREC_FP64 &&
+        (!(opts->inner_tol > 0) || !(opts->inner_tol < 1) || opts->max_outer < 1 || opts->max_inner < 0))
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid refinement options%s");
     SolveParams sp{opts->tol,       opts->max_iter,  opts->precision, opts->guess == MCD_GUESS_CALLER,
                    opts->inner_tol, opts->max_outer, opts->check_every, opts->max_inner};

@@ -19,6 +19,8 @@
 // cells are zero.
 #include <hip/hip_ext.h>
 
+#include <cmath>
+
 #include "common.h"
 
 namespace mcd {
@@ -27,10 +29,19 @@ struct KState {
     double rho, alpha, omega;
     double bb, rr, rr0, rv;
     double tol2;
-    int done;       // 0 running, 1 recurrence/true residual converged, 2 breakdown
+    double rho_prev;   // rho of the previous iteration (kept by the P-stage)
+    double rho_res;    // rhat.r of a replaced residual (resume P-stage)
+    double delta2;     // > 0: also stop when r.r <= delta2 * rr_max (residual replacement due)
+    double rr_max;     // largest r.r since the recursion started or its residual was replaced
+    int done;          // 0 running, 1 recurrence below the stop threshold, 2 breakdown
     int iter;
     int pad[2];
 };
+
+// P-stage modes: a normal iteration; the first iteration after an (re)start
+// (r = p = s); resuming after the residual was replaced by a recomputed one
+// (r given, x already current, beta from the replaced rho).
+enum { P_NORMAL = 0, P_FIRST = 1, P_RESUME = 2 };
 
 // Fixed launch shape of the stage kernels: 512 blocks x 512 threads
 // (16 waves per CU on 256 CUs); per-block partial sums of one stage are
@@ -40,10 +51,10 @@ struct KState {
 constexpr int kKBlock = 512;
 constexpr int kKGrid = 512;
 
-template <typename T>
+template <typename T, typename TA = T>
 struct KVec {
     T *x, *r, *rhat, *s, *t, *p[2], *v[2];
-    const T* A;      // [S][Nc]
+    const TA* A;     // [S][Nc]; TA = float for an FP32-stored matrix with FP64 vectors
     const T* b;
 };
 
@@ -59,31 +70,42 @@ struct KBufs {
 
 // Sum of A[s][c] * val(j) over the stencil slots of cell c.  Interior cells
 // use constant slot offsets; cells on the mesh edge take the general path.
-template <int DIM, typename T, typename F>
-__device__ __forceinline__ T spmv_row(const MeshDev& m, const T* __restrict__ A, int c, F val) {
-    constexpr int S = Dims<DIM>::S;
+template <int DIM, typename T, typename TA, typename F>
+__device__ __forceinline__ T spmv_row(const MeshDev& m, const TA* __restrict__ A, int c, F val) {
+    // An FP32-stored matrix is in difference form (centre slot = row sum):
+    // sum_j a_j (x_j - x_c) + rowsum x_c.  FP64 matrices use the plain form.
+    constexpr bool DIFF = sizeof(TA) < sizeof(double);
+    constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
     const size_t Nc = (size_t)m.Nc;
     int ijk[3];
     cell_ijk(m, c, ijk);
     bool interior = ijk[0] > 0 && ijk[0] < m.n[0] - 1 && ijk[1] > 0 && ijk[1] < m.n[1] - 1;
     if (DIM == 3) interior = interior && ijk[2] > 0 && ijk[2] < m.n[2] - 1;
+    const T xc = DIFF ? val(c) : T(0);
     T acc = 0;
     if (interior) {
         const int n0 = m.n[0], n01 = m.n[0] * m.n[1];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int off = (s % 3 - 1) + (DIM > 1 ? ((s / 3) % 3 - 1) * n0 : 0) + (DIM > 2 ? (s / 9 - 1) * n01 : 0);
-            acc += A[(size_t)s * Nc + c] * val(c + off);
+            const T a = (T)A[(size_t)s * Nc + c];
+            if (DIFF)
+                acc += s == CEN ? a * xc : a * (val(c + off) - xc);
+            else
+                acc += a * val(c + off);
         }
         return acc;
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const T a = A[(size_t)s * Nc + c];
+        const T a = (T)A[(size_t)s * Nc + c];
         int j;
         double sh[3];
         if (!neighbour<DIM>(m, ijk, s, j, sh)) continue;
-        acc += a * val(j);
+        if (DIFF)
+            acc += s == CEN ? a * xc : a * (val(j) - xc);
+        else
+            acc += a * val(j);
     }
     return acc;
 }
@@ -133,17 +155,17 @@ __device__ __forceinline__ void write_partials(double (&v)[NQ], double* part, co
 }
 
 // r0 = b - A x;  rhat = r0 (kept in s and rhat);  partials r0.r0, b.b.
-template <int DIM, typename T>
-__global__ __launch_bounds__(kKBlock) void k_kinit(MeshDev m, KVec<T> V, KBufs K) {
+template <int DIM, typename T, typename TA>
+__global__ __launch_bounds__(kKBlock) void k_kinit(MeshDev m, KVec<T, TA> V, KBufs K) {
     const T* __restrict__ x = V.x;
     const T* __restrict__ bp = V.b;
-    const T* __restrict__ A = V.A;
+    const TA* __restrict__ A = V.A;
     T* __restrict__ sp = V.s;
     T* __restrict__ rh = V.rhat;
     double a0 = 0.0, a1 = 0.0;
     const int lb = xcd_block(blockIdx.x, kKGrid);
     for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
-        const T ax = spmv_row<DIM, T>(m, A, c, [&](int j) { return x[j]; });
+        const T ax = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return x[j]; });
         const T bc = bp[c];
         const T r = bc - ax;
         sp[c] = r;
@@ -156,7 +178,7 @@ __global__ __launch_bounds__(kKBlock) void k_kinit(MeshDev m, KVec<T> V, KBufs K
 }
 
 // One block: reduce the init partials into the state the first P-stage reads.
-__global__ __launch_bounds__(kKBlock) void k_kfinish(KBufs K, int with_bb, double tol2, int keep_iter) {
+__global__ __launch_bounds__(kKBlock) void k_kfinish(KBufs K, int with_bb, double tol2, int keep_iter, double delta2) {
     double tot[2];
     reduce_partials<2>(K.part[0], K, tot);
     if (threadIdx.x == 0) {
@@ -168,6 +190,8 @@ __global__ __launch_bounds__(kKBlock) void k_kfinish(KBufs K, int with_bb, doubl
         if (!keep_iter) S->iter = 0;
         S->rr = tot[0];
         S->rr0 = tot[0];
+        S->rr_max = tot[0];
+        S->delta2 = delta2;
         S->rho = tot[0];
         S->alpha = 1.0;
         S->omega = 1.0;
@@ -175,38 +199,53 @@ __global__ __launch_bounds__(kKBlock) void k_kfinish(KBufs K, int with_bb, doubl
     }
 }
 
-template <int DIM, typename T, bool FIRST>
-__global__ __launch_bounds__(kKBlock) void k_kP(MeshDev m, KVec<T> V, int par, KBufs K) {
+// beta, omega and the new rho of a P-stage; false (and done = 2 written by
+// the leader) on breakdown.
+template <int MODE>
+__device__ __forceinline__ bool p_scalars(const KState* in, const KBufs& K, bool leader, double& omega, double& beta,
+                                          double& rho_new) {
+    omega = 1.0;
+    beta = 0.0;
+    rho_new = in->rho;
+    if (MODE == P_FIRST) return true;
+    if (MODE == P_NORMAL) {
+        double tot[4];
+        reduce_partials<4>(K.part[2], K, tot);   // t.s, t.t, rhat.s, rhat.t
+        omega = tot[0] / tot[1];
+        rho_new = tot[2] - omega * tot[3];
+        beta = (rho_new / in->rho) * (in->alpha / omega);
+        if (tot[1] > 0.0 && isfinite(omega) && isfinite(beta) && omega != 0.0 && fabs(rho_new) >= 1e-30 * in->rr0)
+            return true;
+    } else {
+        omega = in->omega;
+        rho_new = in->rho_res;
+        beta = (rho_new / in->rho_prev) * (in->alpha / omega);
+        if (isfinite(beta) && omega != 0.0 && fabs(rho_new) >= 1e-30 * in->rr0) return true;
+    }
+    if (leader) {
+        *K.st[1] = *in;
+        K.st[1]->done = 2;
+    }
+    return false;
+}
+
+template <int DIM, typename T, typename TA, int MODE>
+__global__ __launch_bounds__(kKBlock) void k_kP(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     const KState* __restrict__ in = K.st[2];
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
     if (in->done) {
         if (leader) *K.st[1] = *in;
         return;
     }
-    const double alpha = in->alpha;
-    double omega = 1.0, beta = 0.0, rho_new = in->rho;
-    if (!FIRST) {
-        double tot[4];
-        reduce_partials<4>(K.part[2], K, tot);   // t.s, t.t, rhat.s, rhat.t
-        omega = tot[0] / tot[1];
-        rho_new = tot[2] - omega * tot[3];
-        beta = (rho_new / in->rho) * (alpha / omega);
-        if (!(tot[1] > 0.0) || !isfinite(omega) || !isfinite(beta) || omega == 0.0 ||
-            fabs(rho_new) < 1e-30 * in->rr0) {
-            if (leader) {
-                *K.st[1] = *in;
-                K.st[1]->done = 2;
-            }
-            return;
-        }
-    }
-    const T ta = (T)alpha, tw = (T)omega, tb = (T)beta;
+    double omega, beta, rho_new;
+    if (!p_scalars<MODE>(in, K, leader, omega, beta, rho_new)) return;
+    const T ta = (T)in->alpha, tw = (T)omega, tb = (T)beta;
     const T* __restrict__ s = V.s;
     const T* __restrict__ t = V.t;
     const T* __restrict__ po = V.p[par];
     const T* __restrict__ vo = V.v[par];
     const T* __restrict__ rh = V.rhat;
-    const T* __restrict__ A = V.A;
+    const TA* __restrict__ A = V.A;
     T* __restrict__ pn = V.p[par ^ 1];
     T* __restrict__ vn = V.v[par ^ 1];
     T* __restrict__ rp = V.r;
@@ -215,21 +254,26 @@ __global__ __launch_bounds__(kKBlock) void k_kP(MeshDev m, KVec<T> V, int par, K
     const int lb = xcd_block(blockIdx.x, kKGrid);
     for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
         T pc, rc;
-        if (FIRST) {
+        if (MODE == P_FIRST) {
             rc = s[c];
             pc = rc;
+        } else if (MODE == P_RESUME) {
+            rc = rp[c];
+            pc = rc + tb * (po[c] - tw * vo[c]);
         } else {
             rc = s[c] - tw * t[c];
             xp[c] = xp[c] + ta * po[c] + tw * s[c];
             pc = rc + tb * (po[c] - tw * vo[c]);
         }
-        rp[c] = rc;
+        if (MODE != P_RESUME) rp[c] = rc;
         pn[c] = pc;
         T av;
-        if (FIRST)
-            av = spmv_row<DIM, T>(m, A, c, [&](int j) { return s[j]; });
+        if (MODE == P_FIRST)
+            av = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return s[j]; });
+        else if (MODE == P_RESUME)
+            av = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return rp[j] + tb * (po[j] - tw * vo[j]); });
         else
-            av = spmv_row<DIM, T>(m, A, c, [&](int j) { return (s[j] - tw * t[j]) + tb * (po[j] - tw * vo[j]); });
+            av = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return (s[j] - tw * t[j]) + tb * (po[j] - tw * vo[j]); });
         vn[c] = av;
         a0 += (double)rh[c] * (double)av;
         a1 += (double)rc * (double)rc;
@@ -238,13 +282,14 @@ __global__ __launch_bounds__(kKBlock) void k_kP(MeshDev m, KVec<T> V, int par, K
     write_partials<2>(acc, K.part[1], K);
     if (leader) {
         *K.st[1] = *in;
+        K.st[1]->rho_prev = in->rho;
         K.st[1]->rho = rho_new;
         K.st[1]->omega = omega;
     }
 }
 
-template <int DIM, typename T>
-__global__ __launch_bounds__(kKBlock) void k_kS(MeshDev m, KVec<T> V, int par, KBufs K) {
+template <int DIM, typename T, typename TA>
+__global__ __launch_bounds__(kKBlock) void k_kS(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     const KState* __restrict__ in = K.st[1];
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
     if (in->done) {
@@ -255,8 +300,8 @@ __global__ __launch_bounds__(kKBlock) void k_kS(MeshDev m, KVec<T> V, int par, K
     reduce_partials<2>(K.part[1], K, tot);       // rhat.v, r.r
     const double alpha = in->rho / tot[0];
     int done = 0;
-    if (tot[1] <= in->tol2 * in->bb) {
-        done = 1;                                // x already holds the converged iterate
+    if (tot[1] <= fmax(in->tol2 * in->bb, in->delta2 * in->rr_max)) {
+        done = 1;                                // x already holds the iterate of this residual
     } else if (!(tot[0] != 0.0) || !isfinite(alpha)) {
         done = 2;
     }
@@ -273,14 +318,14 @@ __global__ __launch_bounds__(kKBlock) void k_kS(MeshDev m, KVec<T> V, int par, K
     const T* __restrict__ r = V.r;
     const T* __restrict__ vn = V.v[par ^ 1];
     const T* __restrict__ rhp = V.rhat;
-    const T* __restrict__ A = V.A;
+    const TA* __restrict__ A = V.A;
     T* __restrict__ sp = V.s;
     T* __restrict__ tp = V.t;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     const int lb = xcd_block(blockIdx.x, kKGrid);
     for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
         const T sc = r[c] - ta * vn[c];
-        const T tc = spmv_row<DIM, T>(m, A, c, [&](int j) { return r[j] - ta * vn[j]; });
+        const T tc = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return r[j] - ta * vn[j]; });
         sp[c] = sc;
         tp[c] = tc;
         const double rh = (double)rhp[c];
@@ -295,6 +340,7 @@ __global__ __launch_bounds__(kKBlock) void k_kS(MeshDev m, KVec<T> V, int par, K
         *K.st[2] = *in;
         K.st[2]->rv = tot[0];
         K.st[2]->rr = tot[1];
+        K.st[2]->rr_max = fmax(in->rr_max, tot[1]);
         K.st[2]->alpha = alpha;
         K.st[2]->iter = in->iter + 1;
     }
@@ -330,11 +376,21 @@ __device__ __forceinline__ int halo_cell(const MeshDev& m, int gx, int gy) {
     return gx + m.n[0] * gy;
 }
 
-template <typename T>
-__device__ __forceinline__ T stencil_lds(const T* __restrict__ A, size_t Nc, int c, const T* lds, int lx, int ly) {
+template <typename T, typename TA>
+__device__ __forceinline__ T stencil_lds(const TA* __restrict__ A, size_t Nc, int c, const T* lds, int lx, int ly) {
     T acc = 0;
+    if constexpr (sizeof(TA) < sizeof(double)) {
+        // FP32-stored matrix in difference form (centre slot = row sum)
+        const T xc = lds[(ly + 1) * HX + lx + 1];
 #pragma unroll
-    for (int s = 0; s < 9; ++s) acc += A[(size_t)s * Nc + c] * lds[(ly + s / 3) * HX + (lx + s % 3)];
+        for (int s = 0; s < 9; ++s) {
+            const T a = (T)A[(size_t)s * Nc + c];
+            acc += s == 4 ? a * xc : a * (lds[(ly + s / 3) * HX + (lx + s % 3)] - xc);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 9; ++s) acc += (T)A[(size_t)s * Nc + c] * lds[(ly + s / 3) * HX + (lx + s % 3)];
+    }
     return acc;
 }
 
@@ -358,12 +414,12 @@ __device__ __forceinline__ void tile_origin(const KBufs& K, int tile, int& tx0, 
     ty0 = (tile / K.ntx) * TY;
 }
 
-template <typename T>
-__global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T> V, KBufs K) {
+template <typename T, typename TA>
+__global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T, TA> V, KBufs K) {
     __shared__ T xl[NH];
     const T* __restrict__ xp = V.x;
     const T* __restrict__ bp = V.b;
-    const T* __restrict__ A = V.A;
+    const TA* __restrict__ A = V.A;
     T* __restrict__ sp = V.s;
     T* __restrict__ rh = V.rhat;
     const TileRun run = tiles_of(K);
@@ -380,7 +436,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T> V, KBufs
         const int gx = tx0 + lx, gy = ty0 + ly;
         if (gx < m.n[0] && gy < m.n[1]) {
             const int c = gx + m.n[0] * gy;
-            const T ax = stencil_lds<T>(A, (size_t)m.Nc, c, xl, lx, ly);
+            const T ax = stencil_lds<T, TA>(A, (size_t)m.Nc, c, xl, lx, ly);
             const T bc = bp[c];
             const T r = bc - ax;
             sp[c] = r;
@@ -394,8 +450,8 @@ __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T> V, KBufs
     write_partials<2>(v, K.part[0], K);
 }
 
-template <typename T, bool FIRST>
-__global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T> V, int par, KBufs K) {
+template <typename T, typename TA, int MODE>
+__global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T pl[NH];
     const KState* __restrict__ in = K.st[2];
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
@@ -403,30 +459,15 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T> V, int par,
         if (leader) *K.st[1] = *in;
         return;
     }
-    const double alpha = in->alpha;
-    double omega = 1.0, beta = 0.0, rho_new = in->rho;
-    if (!FIRST) {
-        double tot[4];
-        reduce_partials<4>(K.part[2], K, tot);   // t.s, t.t, rhat.s, rhat.t
-        omega = tot[0] / tot[1];
-        rho_new = tot[2] - omega * tot[3];
-        beta = (rho_new / in->rho) * (alpha / omega);
-        if (!(tot[1] > 0.0) || !isfinite(omega) || !isfinite(beta) || omega == 0.0 ||
-            fabs(rho_new) < 1e-30 * in->rr0) {
-            if (leader) {
-                *K.st[1] = *in;
-                K.st[1]->done = 2;
-            }
-            return;
-        }
-    }
-    const T ta = (T)alpha, tw = (T)omega, tb = (T)beta;
+    double omega, beta, rho_new;
+    if (!p_scalars<MODE>(in, K, leader, omega, beta, rho_new)) return;
+    const T ta = (T)in->alpha, tw = (T)omega, tb = (T)beta;
     const T* __restrict__ sp = V.s;
     const T* __restrict__ tp = V.t;
     const T* __restrict__ po = V.p[par];
     const T* __restrict__ vo = V.v[par];
     const T* __restrict__ rh = V.rhat;
-    const T* __restrict__ A = V.A;
+    const TA* __restrict__ A = V.A;
     T* __restrict__ pn = V.p[par ^ 1];
     T* __restrict__ vn = V.v[par ^ 1];
     T* __restrict__ rp = V.r;
@@ -443,12 +484,16 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T> V, int par,
             const int j = halo_cell(m, gx, gy);
             T pv = 0;
             if (j >= 0) {
-                const T sj = sp[j];
-                T rj, poj = 0;
-                if (FIRST) {
-                    rj = sj;
+                T rj, sj = 0, poj = 0;
+                if (MODE == P_FIRST) {
+                    rj = sp[j];
                     pv = rj;
+                } else if (MODE == P_RESUME) {
+                    rj = rp[j];
+                    poj = po[j];
+                    pv = rj + tb * (poj - tw * vo[j]);
                 } else {
+                    sj = sp[j];
                     const T tj = tp[j];
                     poj = po[j];
                     const T voj = vo[j];
@@ -457,9 +502,9 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T> V, int par,
                 }
                 const bool own = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1];
                 if (own) {
-                    rp[j] = rj;
+                    if (MODE != P_RESUME) rp[j] = rj;
                     pn[j] = pv;
-                    if (!FIRST) xp[j] = xp[j] + ta * poj + tw * sj;
+                    if (MODE == P_NORMAL) xp[j] = xp[j] + ta * poj + tw * sj;
                     a1 += (double)rj * (double)rj;
                 }
             }
@@ -469,7 +514,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T> V, int par,
         const int gx = tx0 + lx, gy = ty0 + ly;
         if (gx < m.n[0] && gy < m.n[1]) {
             const int c = gx + m.n[0] * gy;
-            const T av = stencil_lds<T>(A, (size_t)m.Nc, c, pl, lx, ly);
+            const T av = stencil_lds<T, TA>(A, (size_t)m.Nc, c, pl, lx, ly);
             vn[c] = av;
             a0 += (double)rh[c] * (double)av;
         }
@@ -479,13 +524,14 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T> V, int par,
     write_partials<2>(acc, K.part[1], K);
     if (leader) {
         *K.st[1] = *in;
+        K.st[1]->rho_prev = in->rho;
         K.st[1]->rho = rho_new;
         K.st[1]->omega = omega;
     }
 }
 
-template <typename T>
-__global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T> V, int par, KBufs K) {
+template <typename T, typename TA>
+__global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T sl[NH];
     const KState* __restrict__ in = K.st[1];
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
@@ -497,8 +543,8 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T> V, int par,
     reduce_partials<2>(K.part[1], K, tot);       // rhat.v, r.r
     const double alpha = in->rho / tot[0];
     int done = 0;
-    if (tot[1] <= in->tol2 * in->bb) {
-        done = 1;                                // x already holds the converged iterate
+    if (tot[1] <= fmax(in->tol2 * in->bb, in->delta2 * in->rr_max)) {
+        done = 1;                                // x already holds the iterate of this residual
     } else if (!(tot[0] != 0.0) || !isfinite(alpha)) {
         done = 2;
     }
@@ -515,7 +561,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T> V, int par,
     const T* __restrict__ rp = V.r;
     const T* __restrict__ vn = V.v[par ^ 1];
     const T* __restrict__ rh = V.rhat;
-    const T* __restrict__ A = V.A;
+    const TA* __restrict__ A = V.A;
     T* __restrict__ sp = V.s;
     T* __restrict__ tp = V.t;
     const TileRun run = tiles_of(K);
@@ -540,7 +586,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T> V, int par,
         const int gx = tx0 + lx, gy = ty0 + ly;
         if (gx < m.n[0] && gy < m.n[1]) {
             const int c = gx + m.n[0] * gy;
-            const T tcv = stencil_lds<T>(A, (size_t)m.Nc, c, sl, lx, ly);
+            const T tcv = stencil_lds<T, TA>(A, (size_t)m.Nc, c, sl, lx, ly);
             const T sc = sl[(ly + 1) * HX + lx + 1];
             tp[c] = tcv;
             const double r = (double)rh[c];
@@ -557,6 +603,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T> V, int par,
         *K.st[2] = *in;
         K.st[2]->rv = tot[0];
         K.st[2]->rr = tot[1];
+        K.st[2]->rr_max = fmax(in->rr_max, tot[1]);
         K.st[2]->alpha = alpha;
         K.st[2]->iter = in->iter + 1;
     }
@@ -619,7 +666,7 @@ __global__ __launch_bounds__(kBlock) void k_ppe_resid(MeshDev m, const double* _
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
         double v = 0.0;
         if (unknown[c]) {
-            v = beff[c] - spmv_row<DIM, double>(m, A, c, [&](int j) { return x[j]; });
+            v = beff[c] - spmv_row<DIM, double, double>(m, A, c, [&](int j) { return x[j]; });
             rr += v * v;
             bb += beff[c] * beff[c];
         }
@@ -645,6 +692,45 @@ __global__ void k_resid_finish(const double* __restrict__ part, int nblk, double
     if (threadIdx.x == 0) {
         out[0] = sqrt(q[0]);
         out[1] = sqrt(q[1]);
+    }
+}
+
+// Residual replacement (FP32-stored matrix, FP64 vectors): r = b_eff - A64 x
+// with the FP64 matrix at unknown rows (0 elsewhere); partials of rhat.r and
+// r.r.  Launched with the stage grid so that the partials match its
+// reduction.
+template <int DIM>
+__global__ __launch_bounds__(kKBlock) void k_true_replace(MeshDev m, const double* __restrict__ A64,
+                                                          const uint8_t* __restrict__ unknown,
+                                                          const double* __restrict__ beff, KVec<double, float> V,
+                                                          KBufs K) {
+    const double* __restrict__ x = V.x;
+    const double* __restrict__ rh = V.rhat;
+    double* __restrict__ r = V.r;
+    double a0 = 0.0, a1 = 0.0;
+    const int lb = xcd_block(blockIdx.x, gridDim.x);
+    for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += gridDim.x * kKBlock) {
+        double v = 0.0;
+        if (unknown[c]) v = beff[c] - spmv_row<DIM, double, double>(m, A64, c, [&](int j) { return x[j]; });
+        r[c] = v;
+        a0 += rh[c] * v;
+        a1 += v * v;
+    }
+    double acc[2] = {a0, a1};
+    write_partials<2>(acc, K.part[0], K);
+}
+
+// One block: the state a resume P-stage reads; done = 1 when the replaced
+// residual already meets the tolerance.
+__global__ __launch_bounds__(kKBlock) void k_replace_finish(KBufs K) {
+    double tot[2];
+    reduce_partials<2>(K.part[0], K, tot);
+    if (threadIdx.x == 0) {
+        KState* S = K.st[2];
+        S->rho_res = tot[0];
+        S->rr = tot[1];
+        S->rr_max = tot[1];
+        S->done = tot[1] <= S->tol2 * S->bb ? 1 : 0;
     }
 }
 
@@ -708,30 +794,35 @@ struct KrylovWork {
     long long cnt[2] = {0, 0};
 };
 
-// Enqueues one Bi-CGSTAB iteration (P- and S-stage) with operand parity par.
-template <int DIM, typename T>
-static void enqueue_iteration(const MeshDev& m, const KVec<T>& V, const KBufs& K, int par, bool first,
+// Enqueues one Bi-CGSTAB iteration (P-stage in `mode`, then S-stage) with
+// operand parity par.
+template <int DIM, typename T, typename TA>
+static void enqueue_iteration(const MeshDev& m, const KVec<T, TA>& V, const KBufs& K, int par, int mode,
                               hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, hipEvent_t e3) {
     const dim3 G(K.nblk), B(kKBlock);
     if (m.dim == 2) {
-        if (first)
-            hipExtLaunchKernelGGL((k_t2_P<T, true>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        if (mode == P_FIRST)
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_FIRST>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        else if (mode == P_RESUME)
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_RESUME>), G, B, 0, st, e0, e1, 0, m, V, par, K);
         else
-            hipExtLaunchKernelGGL((k_t2_P<T, false>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        hipExtLaunchKernelGGL((k_t2_S<T>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_NORMAL>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_t2_S<T, TA>), G, B, 0, st, e2, e3, 0, m, V, par, K);
     } else {
-        if (first)
-            hipExtLaunchKernelGGL((k_kP<DIM, T, true>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        if (mode == P_FIRST)
+            hipExtLaunchKernelGGL((k_kP<DIM, T, TA, P_FIRST>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        else if (mode == P_RESUME)
+            hipExtLaunchKernelGGL((k_kP<DIM, T, TA, P_RESUME>), G, B, 0, st, e0, e1, 0, m, V, par, K);
         else
-            hipExtLaunchKernelGGL((k_kP<DIM, T, false>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        hipExtLaunchKernelGGL((k_kS<DIM, T>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_kP<DIM, T, TA, P_NORMAL>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_kS<DIM, T, TA>), G, B, 0, st, e2, e3, 0, m, V, par, K);
     }
 }
 
 // Graph of kGraphIters non-first iterations starting at parity 1 (an even
 // count, so every replay starts and ends at parity 1).
-template <int DIM, typename T>
-static hipError_t chunk_graph(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K,
+template <int DIM, typename T, typename TA>
+static hipError_t chunk_graph(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K,
                               hipGraphExec_t* out) {
     const int fp32 = sizeof(T) == 4;
     for (int i = 0; i < w.ngraphs; ++i)
@@ -744,7 +835,7 @@ static hipError_t chunk_graph(const MeshDev& m, KrylovWork& w, const KVec<T>& V,
     if (e != hipSuccess) return e;
     int par = 1;
     for (int q = 0; q < KrylovWork::kGraphIters; ++q) {
-        enqueue_iteration<DIM, T>(m, V, K, par, false, w.st, nullptr, nullptr, nullptr, nullptr);
+        enqueue_iteration<DIM, T, TA>(m, V, K, par, P_NORMAL, w.st, nullptr, nullptr, nullptr, nullptr);
         par ^= 1;
     }
     hipGraph_t g;
@@ -758,21 +849,24 @@ static hipError_t chunk_graph(const MeshDev& m, KrylovWork& w, const KVec<T>& V,
     return hipSuccess;
 }
 
-template <int DIM, typename T>
-static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K, int iter0,
-                                 int budget, int check_every, hipStream_t st, int* iters_out, int* done_out) {
+// Runs up to `budget` iterations; the first one's P-stage is in mode0 with
+// parity par0 (the P-stage of iteration k always has parity k % 2).
+template <int DIM, typename T, typename TA>
+static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K, int iter0,
+                                 int budget, int check_every, hipStream_t st, int* iters_out, int* done_out,
+                                 int mode0 = P_FIRST) {
     // Pipelined chunks: chunk q+1 is enqueued before chunk q's state is
     // examined, so the GPU never waits for the host.  Stage kernels return at
     // once when the state they read says done.  Without kernel timing, full
     // chunks are replays of a captured graph.
-    int par = 0;
+    int par = iter0 & 1;
     bool first = true;
     int chunk = 0, last = -1, launched = 0;
     hipError_t e = hipSuccess;
     hipGraphExec_t graph = nullptr;
     const bool timing = w.profile == 1;
     if (!timing && w.use_graphs) {
-        if ((e = chunk_graph<DIM, T>(m, w, V, K, &graph)) != hipSuccess) graph = nullptr;
+        if ((e = chunk_graph<DIM, T, TA>(m, w, V, K, &graph)) != hipSuccess) graph = nullptr;
     }
     w.np = 0;
     while (budget > 0) {
@@ -783,12 +877,14 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T>&
             if ((e = hipGraphLaunch(graph, st)) != hipSuccess) return e;
             launched += n;
         } else {
-            if (graph && !first && par == 1 && n > 1) n = 1;   // keep a partial chunk short
+            // with a graph, single iterations only bridge to parity 1 or finish a short budget
+            if (graph && n > 1) n = 1;
             for (int q = 0; q < n; ++q) {
                 const bool rec = timing && w.np < KrylovWork::kProf;
                 hipEvent_t* ev = rec ? w.pev[w.np] : nullptr;
                 if (rec) w.pidx[w.np] = iter0 + launched;
-                enqueue_iteration<DIM, T>(m, V, K, par, first, st, ev ? ev[0] : nullptr, ev ? ev[1] : nullptr,
+                enqueue_iteration<DIM, T, TA>(m, V, K, par, first ? mode0 : P_NORMAL, st, ev ? ev[0] : nullptr,
+                                          ev ? ev[1] : nullptr,
                                           ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
                 if (rec) ++w.np;
                 ++launched;
@@ -835,14 +931,14 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T>&
 
 // r = b - A x, rhat = r and the state the next P-stage starts from;
 // synchronises and returns that state.
-template <int DIM, typename T>
-static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K, int with_bb, double tol2,
-                        hipStream_t st, KState* out) {
+template <int DIM, typename T, typename TA>
+static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K, int with_bb, double tol2,
+                        hipStream_t st, KState* out, double delta2 = 0.0) {
     if (m.dim == 2)
-        hipLaunchKernelGGL((k_t2_init<T>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+        hipLaunchKernelGGL((k_t2_init<T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
     else
-        hipLaunchKernelGGL((k_kinit<DIM, T>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
-    hipLaunchKernelGGL(k_kfinish, dim3(1), dim3(kKBlock), 0, st, K, with_bb, tol2, with_bb ? 0 : 1);
+        hipLaunchKernelGGL((k_kinit<DIM, T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+    hipLaunchKernelGGL(k_kfinish, dim3(1), dim3(kKBlock), 0, st, K, with_bb, tol2, with_bb ? 0 : 1, delta2);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = hipMemcpyAsync(&w.host[0], K.st[2], sizeof(KState), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
@@ -853,19 +949,21 @@ static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const
 
 // Bi-CGSTAB with restarts from the true residual; returns iterations,
 // restarts, ||r||/||b|| of the final true residual.
-template <int DIM, typename T>
-static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T>& V, const KBufs& K, double tol,
+template <int DIM, typename T, typename TA>
+static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K, double tol,
                            int max_iter, int check_every, hipStream_t st, int* iters, int* restarts, double* rel,
                            int* conv, bool confirm = true) {
     KState h;
-    hipError_t e = kinit<DIM, T>(m, w, V, K, 1, tol * tol, st, &h);
+    hipError_t e = kinit<DIM, T, TA>(m, w, V, K, 1, tol * tol, st, &h);
     if (e != hipSuccess) return e;
     *restarts = 0;
     *iters = 0;
     const double bb = h.bb;
+    int idle = 0;
     while (!h.done && h.iter < max_iter) {
+        const int before = h.iter;
         int it = 0, done = 0;
-        if ((e = run_iterations<DIM, T>(m, w, V, K, h.iter, max_iter - h.iter, check_every, st, &it, &done)) !=
+        if ((e = run_iterations<DIM, T, TA>(m, w, V, K, h.iter, max_iter - h.iter, check_every, st, &it, &done)) !=
             hipSuccess)
             return e;
         if (!confirm) {
@@ -877,8 +975,13 @@ static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T>& V, co
             break;
         }
         // confirm with the true residual; restart from it if needed
-        if ((e = kinit<DIM, T>(m, w, V, K, 0, tol * tol, st, &h)) != hipSuccess) return e;
+        if ((e = kinit<DIM, T, TA>(m, w, V, K, 0, tol * tol, st, &h)) != hipSuccess) return e;
         if (!h.done) *restarts += 1;
+        // a restart that makes no progress (a non-finite iterate, or the
+        // recurrence and the true residual straddling the tolerance) ends
+        // the solve unconverged instead of looping
+        idle = h.iter == before ? idle + 1 : 0;
+        if (idle >= 2 || !std::isfinite(h.rr)) break;
     }
     *iters = h.iter;
     *rel = bb > 0 ? sqrt(h.rr / bb) : 0.0;
@@ -906,7 +1009,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     if (sp.precision == MCD_PREC_FP64) {
         int it = 0, rst = 0, conv = 0;
         double rel = 0.0;
-        if ((e = bicgstab<DIM, double>(m, w, V, w.kb64, sp.tol, sp.max_iter, check, st, &it, &rst, &rel, &conv)) !=
+        if ((e = bicgstab<DIM, double, double>(m, w, V, w.kb64, sp.tol, sp.max_iter, check, st, &it, &rst, &rel, &conv)) !=
             hipSuccess)
             return e;
         out->iterations = it;
@@ -914,6 +1017,97 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         out->converged = conv;
         out->rel = rel;
         out->bnorm = sqrt(w.host[0].bb);
+    } else if (sp.precision == MCD_PREC_FP32_MATRIX) {
+        // FP64 Bi-CGSTAB whose stage products read the FP32-stored matrix
+        // (half the matrix bytes; products and all vectors in FP64), with
+        // residual replacement: when the recursive residual has fallen by
+        // inner_tol below its largest value since the last replacement (or
+        // to the tolerance), r := b - A64 x is recomputed with the FP64
+        // matrix and the recursion resumes from it with its Krylov space
+        // kept.  Convergence is only declared on that FP64 residual.  A
+        // breakdown restarts from the FP64 residual; more than max_outer
+        // replacements, two rounds without an iteration, or an FP64 residual
+        // 100x above the best one seen hand over to plain FP64 Bi-CGSTAB
+        // from the current iterate.
+        KVec<double, float> VM;
+        VM.x = V.x;
+        VM.r = V.r;
+        VM.rhat = V.rhat;
+        VM.s = V.s;
+        VM.t = V.t;
+        VM.p[0] = V.p[0];
+        VM.p[1] = V.p[1];
+        VM.v[0] = V.v[0];
+        VM.v[1] = V.v[1];
+        VM.A = set.amat32;
+        VM.b = w.beff;
+        const double tol2 = sp.tol * sp.tol, delta2 = sp.inner_tol * sp.inner_tol;
+        KState h;
+        if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 1, tol2, st, &h, delta2)) != hipSuccess) return e;
+        const double bb = h.bb;
+        int mode = P_FIRST, repl = 0, idle = 0, restarts = 0, fallback = 0;
+        double rr_best = h.rr;
+        while (!h.done && h.iter < sp.max_iter) {
+            const int before = h.iter;
+            int it = 0, done = 0;
+            if ((e = run_iterations<DIM, double, float>(m, w, VM, w.kb64, h.iter, sp.max_iter - h.iter, check, st,
+                                                        &it, &done, mode)) != hipSuccess)
+                return e;
+            if (done == 0) {          // iteration budget spent
+                h.iter = it;
+                break;
+            }
+            hipLaunchKernelGGL(k_true_replace<DIM>, dim3(w.kb64.nblk), dim3(kKBlock), 0, st, m, set.amat,
+                               set.unknown, w.beff, VM, w.kb64);
+            hipLaunchKernelGGL(k_replace_finish, dim3(1), dim3(kKBlock), 0, st, w.kb64);
+            if ((e = hipGetLastError()) != hipSuccess) return e;
+            if ((e = hipMemcpyAsync(&w.host[0], w.kb64.st[2], sizeof(KState), hipMemcpyDeviceToHost, st)) !=
+                hipSuccess)
+                return e;
+            if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+            h = w.host[0];
+            ++repl;
+            if (h.done) break;
+            rr_best = fmin(rr_best, h.rr);
+            idle = h.iter == before ? idle + 1 : 0;
+            // no progress, too many replacements, or a recursion that has
+            // drifted away (FP64 residual 100x above its best): plain FP64
+            if (idle >= 2 || repl > sp.max_outer || !std::isfinite(h.rr) || h.rr > 1e4 * rr_best) {
+                fallback = 1;
+                break;
+            }
+            if (done == 2) {          // breakdown: new recursion from the FP64 residual
+                if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 0, tol2, st, &h, delta2)) != hipSuccess)
+                    return e;
+                ++restarts;
+                mode = P_FIRST;
+            } else {
+                mode = P_RESUME;
+            }
+        }
+        int total = h.iter;
+        bool conv = h.done == 1 || bb == 0.0;
+        double rr = h.rr;
+        if (fallback && !conv && total < sp.max_iter) {
+            if (!std::isfinite(h.rr))      // a non-finite iterate: start over from zero
+                hipLaunchKernelGGL(k_ppe_rhs<DIM>, dim3(g), dim3(kBlock), 0, st, m, set, rhs, p, fneu, 0, w.beff,
+                                   w.v64.x, bad);
+            int it = 0, rst = 0, c64 = 0;
+            double rel = 0.0;
+            if ((e = bicgstab<DIM, double, double>(m, w, V, w.kb64, sp.tol, sp.max_iter - total, check, st, &it, &rst,
+                                                   &rel, &c64)) != hipSuccess)
+                return e;
+            total += it;
+            restarts += rst + 1;
+            conv = c64 != 0;
+            rr = rel * rel * bb;
+        }
+        out->iterations = total;
+        out->restarts = restarts;
+        out->refinements = repl;
+        out->converged = conv ? 1 : 0;
+        out->rel = bb > 0 ? sqrt(rr / bb) : 0.0;
+        out->bnorm = sqrt(bb);
     } else {
         // FP64 iterative refinement around an FP32 Bi-CGSTAB (FP64 dots).
         // A correction that does not lower the FP64 true residual is undone
@@ -923,7 +1117,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         KVec<float> V32 = w.v32;
         V32.A = set.amat32;
         KState h;
-        if ((e = kinit<DIM, double>(m, w, V, w.kb64, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
+        if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
         const double bb = h.bb;
         int total = 0, outer = 0, rst_total = 0, rejected = 0, fallback = 0;
         double itol = sp.inner_tol;
@@ -938,19 +1132,19 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
             double rel = 0.0;
             const int left = sp.max_iter - total;
             const int cap = sp.max_inner > 0 && sp.max_inner < left ? sp.max_inner : left;
-            if ((e = bicgstab<DIM, float>(m, w, V32, w.kb32, itol, cap, check, st, &it, &rst, &rel, &conv, false)) !=
+            if ((e = bicgstab<DIM, float, float>(m, w, V32, w.kb32, itol, cap, check, st, &it, &rst, &rel, &conv, false)) !=
                 hipSuccess)
                 return e;
             total += it;
             rst_total += rst;
             hipLaunchKernelGGL(k_refine, dim3(g), dim3(kBlock), 0, st, m.Nc, V32.x, nr, V.x);
-            if ((e = kinit<DIM, double>(m, w, V, w.kb64, 0, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
+            if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 0, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
             ++outer;
             if (!(h.rr < rr_old)) {
                 if ((e = hipMemcpyAsync(V.x, w.xsave, (size_t)m.Nc * sizeof(double), hipMemcpyDeviceToDevice, st)) !=
                     hipSuccess)
                     return e;
-                if ((e = kinit<DIM, double>(m, w, V, w.kb64, 0, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
+                if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 0, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
                 itol = itol * 3.0 < 0.5 ? itol * 3.0 : 0.5;
                 if (++rejected >= 2) {
                     fallback = 1;
@@ -961,7 +1155,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         if (fallback && !h.done && total < sp.max_iter) {
             int it = 0, rst = 0, conv = 0;
             double rel = 0.0;
-            if ((e = bicgstab<DIM, double>(m, w, V, w.kb64, sp.tol, sp.max_iter - total, check, st, &it, &rst, &rel,
+            if ((e = bicgstab<DIM, double, double>(m, w, V, w.kb64, sp.tol, sp.max_iter - total, check, st, &it, &rst, &rel,
                                            &conv)) != hipSuccess)
                 return e;
             total += it;

@@ -143,7 +143,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
         double cacc[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) cacc[q] = 0.0;
-        double diag_sum = 0.0;
+        double diag_sum = 0.0, off_sum = 0.0;
         for (int s = 0; s < S; ++s) {
             const int slot = (s == CEN) ? S : s;
             const bool isv = (vm >> s) & 1u, isn = (nm >> slot) & 1u;
@@ -191,6 +191,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                 if (st.amat) {
                     st.amat[(size_t)s * Nc + c] = lap;
                     st.amat32[(size_t)s * Nc + c] = (float)lap;
+                    off_sum += lap;
                 }
             } else {
 #pragma unroll
@@ -200,9 +201,13 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
 #pragma unroll
         for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + CEN) * Nc + c] = -cacc[q];
         if (st.amat) {
+            // FP32 copy in difference form: its centre slot holds the row sum
+            // (zero for rows without known neighbours), so that products
+            // sum a_j (x_j - x_c) + rowsum x_c and keep the exact
+            // cancellation of the stencil on smooth fields
             const double dg = unk_c ? -diag_sum : 0.0;
             st.amat[(size_t)CEN * Nc + c] = dg;
-            st.amat32[(size_t)CEN * Nc + c] = (float)dg;
+            st.amat32[(size_t)CEN * Nc + c] = (float)(dg + off_sum);
         }
     }
 }

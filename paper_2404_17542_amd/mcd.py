@@ -21,7 +21,7 @@ STATUS = {0: "MCD_OK", 1: "MCD_ERR_ARG", 2: "MCD_ERR_SINGULAR", 3: "MCD_ERR_NOT_
 ROLE_INNER, ROLE_VOID = -1, 0
 BC_DIRICHLET, BC_NEUMANN = 0, 1
 WEIGHT_COS2, WEIGHT_GAUSS = 0, 1
-PREC_FP64, PREC_FP32_REFINE = 0, 1
+PREC_FP64, PREC_FP32_REFINE, PREC_FP32_MATRIX = 0, 1, 2
 GUESS_ZERO, GUESS_CALLER = 0, 1
 OP_PHI, OP_GRAD, OP_LAP, OP_DIV, OP_SHIFT = 0, 1, 2, 3, 4
 MAX_IDS = 16
@@ -300,8 +300,12 @@ class Context:
                                          _ptr(role, N, torch.int8), arr, n, V(u, D)), "mcd_project")
 
     def solve_ppe(self, set_id, rhs, p, neumann_f=None, tol=1e-8, max_iter=20000, precision=PREC_FP64,
-                  guess=GUESS_ZERO, inner_tol=1e-2, max_outer=40, check_every=16, max_inner=None,
+                  guess=GUESS_ZERO, inner_tol=None, max_outer=None, check_every=16, max_inner=None,
                   raise_on_fail=True):
+        if inner_tol is None:
+            inner_tol = 0.03 if precision == PREC_FP32_MATRIX else 1e-2
+        if max_outer is None:
+            max_outer = 500 if precision == PREC_FP32_MATRIX else 40
         o = SolveOpts()
         o.tol, o.max_iter, o.precision, o.guess = tol, int(max_iter), int(precision), int(guess)
         o.inner_tol, o.max_outer, o.check_every = inner_tol, int(max_outer), int(check_every)

@@ -298,13 +298,13 @@ def _c0_problem(n):
     return case, m, pos, role, nrm, st, rhs, g
 
 
-@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+@pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32_matrix"])
 def test_ppe_manufactured_residual_on_both_operators(M, precision):
     case, m, pos, role, nrm, st, rhs, g = _c0_problem(32)
     ctx = M.Context.from_case(case)
     ctx.build_stencils(0, _dev(pos), _dev(role, torch.int8), _dev(nrm), case.bc_pressure)
     p = _dev(g)
-    prec = M.PREC_FP64 if precision == "fp64" else M.PREC_FP32_REFINE
+    prec = {"fp64": M.PREC_FP64, "mixed": M.PREC_FP32_REFINE, "fp32_matrix": M.PREC_FP32_MATRIX}[precision]
     info = ctx.solve_ppe(0, _dev(rhs), p, tol=1e-8, precision=prec)
     assert info["converged"] and info["true_rel_residual"] <= 1e-8
     A, b, uidx = O.ppe_system(m, st, role, case.bc_pressure, rhs, g, None)
@@ -314,7 +314,7 @@ def test_ppe_manufactured_residual_on_both_operators(M, precision):
     po, _, _ = O.solve_ppe(m, st, role, case.bc_pressure, rhs, g, None, 1e-12)
     rel = np.linalg.norm(pg - po) / np.linalg.norm(po)
     assert rel < 1e-6, rel
-    if precision == "mixed":
+    if precision != "fp64":
         assert info["refinements"] >= 1
 
 
@@ -329,12 +329,16 @@ def test_ppe_cylinder_neumann(M):
     ctx.build_stencils(2, _dev(pos), _dev(role, torch.int8), _dev(nrm), case.bc_pressure)
     st = O.mls_build(m, pos, role, nrm, case.bc_pressure, case.re_over_l0 * case.l0, case.l0, case.weight)
     A, b, uidx = O.ppe_system(m, st, role, case.bc_pressure, rhs, g, f)
-    for prec in (M.PREC_FP64, M.PREC_FP32_REFINE):
+    iters = {}
+    for prec in (M.PREC_FP64, M.PREC_FP32_REFINE, M.PREC_FP32_MATRIX):
         p = _dev(g)
         info = ctx.solve_ppe(2, _dev(rhs), p, _dev(f), precision=prec)
+        iters[prec] = info["iterations"]
         assert info["true_rel_residual"] <= 1e-8
         pg = np_(p)
         assert np.linalg.norm(b - A @ pg[uidx]) / np.linalg.norm(b) <= 1e-8
+    # the FP32-stored matrix keeps the FP64 Krylov space: about FP64's count
+    assert iters[M.PREC_FP32_MATRIX] <= 1.5 * iters[M.PREC_FP64] + 16, iters
 
 
 def test_ppe_residual_matches_oracle(M):

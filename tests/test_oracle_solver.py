@@ -60,6 +60,45 @@ def test_mixed_refinement_reaches_fp64_tolerance():
     pm, im = O.solve_ppe_mixed(m, st, role, case.bc_pressure, rhs, g, None, 1e-8)
     assert im.converged and im.true_rel_residual <= 1e-8 and im.restarts >= 2
     assert np.linalg.norm(pm - p64) / np.linalg.norm(p64) < 1e-7
+    # without refinement, scipy's Bi-CGSTAB entirely in FP32 (judged on the
+    # FP64 operator) stalls far above the tolerance
+    from scipy.sparse.linalg import bicgstab
+    A, beff, uidx = O.ppe_system(m, st, role, case.bc_pressure, rhs, g, None)
+    nb = np.linalg.norm(beff)
+    x32, _ = bicgstab(A.astype(np.float32), (beff / nb).astype(np.float32), rtol=1e-12, maxiter=2000)
+    assert x32.dtype == np.float32
+    rel32 = np.linalg.norm(beff - A @ (x32.astype(np.float64) * nb)) / nb
+    assert rel32 > 1e-7, rel32
+
+
+def test_fp32_matrix_with_residual_replacement():
+    """FP32-stored matrix in the products, FP64 vectors: the replacement
+    brings the FP64 residual to 1e-8, about as fast as FP64; without it the
+    recursion converges to the solution of the rounded matrix, whose FP64
+    residual stalls above the tolerance."""
+    case, m, pos, role, st = _c0(48)
+    rhs = inputs.manufactured_rhs(pos)
+    g = np.where(role == O.INNER, 0.0, inputs.manufactured_pressure(pos))
+    p64, i64, _ = O.solve_ppe(m, st, role, case.bc_pressure, rhs, g, None, 1e-8)
+    pm, im = O.solve_ppe_fp32_matrix(m, st, role, case.bc_pressure, rhs, g, None, 1e-8)
+    assert im.converged and im.true_rel_residual <= 1e-8 and im.refinements >= 2
+    assert np.linalg.norm(pm - p64) / np.linalg.norm(p64) < 1e-7
+    assert im.iterations <= 1.5 * i64.iterations + 10, (im.iterations, i64.iterations)
+    # the FP32 operator in difference form against a plain per-entry rounding:
+    # on a smooth field its product error is orders of magnitude smaller,
+    # because the rounded stencil rows still sum to zero
+    A, beff, uidx = O.ppe_system(m, st, role, case.bc_pressure, rhs, g, None)
+    xs = p64[uidx]
+    exact = A @ xs
+    e_diff = np.linalg.norm(O.fp32_operator(A, np.float64)(xs) - exact)
+    e_plain = np.linalg.norm(A.astype(np.float32).astype(np.float64) @ xs - exact)
+    assert e_diff < 0.1 * e_plain, (e_diff, e_plain)
+    # and on a constant field (A x is the row sum: zero on inner rows, what
+    # remains is the FP32 rounding of the rows next to Dirichlet DPs)
+    one = np.ones(len(uidx))
+    e_diff = np.linalg.norm(O.fp32_operator(A, np.float64)(one) - A @ one)
+    e_plain = np.linalg.norm(A.astype(np.float32).astype(np.float64) @ one - A @ one)
+    assert e_diff < 0.1 * e_plain, (e_diff, e_plain)
 
 
 def test_remap_identity_and_quadratic_exactness():
