@@ -177,16 +177,17 @@ __global__ __launch_bounds__(kKBlock) void k_kinit(MeshDev m, KVec<T, TA> V, KBu
     write_partials<2>(v, K.part[0], K);
 }
 
-// One block: reduce the init partials into the state the first P-stage reads.
-__global__ __launch_bounds__(kKBlock) void k_kfinish(KBufs K, int with_bb, double tol2, int keep_iter, double delta2) {
+// One block: reduce the init partials into the state the first P-stage
+// reads.  done tests r.r against tol2 * bb; the recursion that follows stops
+// at tol2_next * bb (tighter after a recurrence that converged while the
+// true residual did not).
+__global__ __launch_bounds__(kKBlock) void k_kfinish(KBufs K, int with_bb, double tol2, int keep_iter, double delta2,
+                                                     double tol2_next) {
     double tot[2];
     reduce_partials<2>(K.part[0], K, tot);
     if (threadIdx.x == 0) {
         KState* S = K.st[2];
-        if (with_bb) {
-            S->bb = tot[1];
-            S->tol2 = tol2;
-        }
+        if (with_bb) S->bb = tot[1];
         if (!keep_iter) S->iter = 0;
         S->rr = tot[0];
         S->rr0 = tot[0];
@@ -195,7 +196,8 @@ __global__ __launch_bounds__(kKBlock) void k_kfinish(KBufs K, int with_bb, doubl
         S->rho = tot[0];
         S->alpha = 1.0;
         S->omega = 1.0;
-        S->done = (tot[0] <= S->tol2 * S->bb) ? 1 : 0;
+        S->done = (tot[0] <= tol2 * S->bb) ? 1 : 0;
+        S->tol2 = tol2_next;
     }
 }
 
@@ -722,7 +724,7 @@ __global__ __launch_bounds__(kKBlock) void k_true_replace(MeshDev m, const doubl
 
 // One block: the state a resume P-stage reads; done = 1 when the replaced
 // residual already meets the tolerance.
-__global__ __launch_bounds__(kKBlock) void k_replace_finish(KBufs K) {
+__global__ __launch_bounds__(kKBlock) void k_replace_finish(KBufs K, double tol2, double tol2_next) {
     double tot[2];
     reduce_partials<2>(K.part[0], K, tot);
     if (threadIdx.x == 0) {
@@ -730,7 +732,8 @@ __global__ __launch_bounds__(kKBlock) void k_replace_finish(KBufs K) {
         S->rho_res = tot[0];
         S->rr = tot[1];
         S->rr_max = tot[1];
-        S->done = tot[1] <= S->tol2 * S->bb ? 1 : 0;
+        S->done = tot[1] <= tol2 * S->bb ? 1 : 0;
+        S->tol2 = tol2_next;
     }
 }
 
@@ -779,6 +782,7 @@ struct KrylovWork {
     int* bad_host;         // pinned
     // replayed chunks of kGraphIters iterations (per operator and precision)
     static constexpr int kGraphIters = 16;
+    static constexpr int kStallIters = 2000;   // see run_iterations
     static constexpr int kMaxGraphs = 16;
     GraphEntry graphs[kMaxGraphs];
     int ngraphs = 0;
@@ -854,13 +858,15 @@ static hipError_t chunk_graph(const MeshDev& m, KrylovWork& w, const KVec<T, TA>
 template <int DIM, typename T, typename TA>
 static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K, int iter0,
                                  int budget, int check_every, hipStream_t st, int* iters_out, int* done_out,
-                                 int mode0 = P_FIRST) {
+                                 int mode0 = P_FIRST, double* rr_out = nullptr) {
     // Pipelined chunks: chunk q+1 is enqueued before chunk q's state is
     // examined, so the GPU never waits for the host.  Stage kernels return at
     // once when the state they read says done.  Without kernel timing, full
     // chunks are replays of a captured graph.
     int par = iter0 & 1;
-    bool first = true;
+    bool first = true, stalled = false;
+    double rr_mark = 0.0;
+    int it_mark = -1;
     int chunk = 0, last = -1, launched = 0;
     hipError_t e = hipSuccess;
     hipGraphExec_t graph = nullptr;
@@ -901,7 +907,17 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, 
         last = chunk;
         if (chunk > 0) {
             if ((e = hipEventSynchronize(w.ev[(chunk - 1) & 1])) != hipSuccess) return e;
-            if (w.host[(chunk - 1) & 1].done) break;
+            const KState& q = w.host[(chunk - 1) & 1];
+            if (q.done) break;
+            // stagnation: no tenfold drop of the recurrence residual within
+            // kStallIters iterations ends the run so that the caller restarts
+            if (q.rr < 0.01 * rr_mark || it_mark < 0) {
+                rr_mark = q.rr;
+                it_mark = q.iter;
+            } else if (q.iter - it_mark > KrylovWork::kStallIters) {
+                stalled = true;
+                break;
+            }
         }
         ++chunk;
     }
@@ -913,6 +929,8 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, 
     if ((e = hipEventSynchronize(w.ev[last & 1])) != hipSuccess) return e;
     *iters_out = w.host[last & 1].iter;
     *done_out = w.host[last & 1].done;
+    if (stalled && *done_out == 0) *done_out = 3;
+    if (rr_out) *rr_out = w.host[last & 1].rr;
     // stage kernels that ran before convergence did work; later ones returned at once
     for (int k = 0; k < w.np; ++k) {
         if (w.pidx[k] >= *iters_out) continue;
@@ -933,12 +951,13 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, 
 // synchronises and returns that state.
 template <int DIM, typename T, typename TA>
 static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K, int with_bb, double tol2,
-                        hipStream_t st, KState* out, double delta2 = 0.0) {
+                        hipStream_t st, KState* out, double delta2 = 0.0, double tol2_next = -1.0) {
     if (m.dim == 2)
         hipLaunchKernelGGL((k_t2_init<T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
     else
         hipLaunchKernelGGL((k_kinit<DIM, T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
-    hipLaunchKernelGGL(k_kfinish, dim3(1), dim3(kKBlock), 0, st, K, with_bb, tol2, with_bb ? 0 : 1, delta2);
+    hipLaunchKernelGGL(k_kfinish, dim3(1), dim3(kKBlock), 0, st, K, with_bb, tol2, with_bb ? 0 : 1, delta2,
+                       tol2_next < 0.0 ? tol2 : tol2_next);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     if ((e = hipMemcpyAsync(&w.host[0], K.st[2], sizeof(KState), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
@@ -960,6 +979,7 @@ static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V
     *iters = 0;
     const double bb = h.bb;
     int idle = 0;
+    double tight = 1.0;
     while (!h.done && h.iter < max_iter) {
         const int before = h.iter;
         int it = 0, done = 0;
@@ -974,9 +994,14 @@ static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V
             h.rr = 0.0;
             break;
         }
-        // confirm with the true residual; restart from it if needed
-        if ((e = kinit<DIM, T, TA>(m, w, V, K, 0, tol * tol, st, &h)) != hipSuccess) return e;
-        if (!h.done) *restarts += 1;
+        // confirm with the true residual; restart from it if needed, with the
+        // recurrence held to a tighter threshold when it had claimed convergence
+        const double next = done == 1 ? tight * 0.25 : tight;
+        if ((e = kinit<DIM, T, TA>(m, w, V, K, 0, tol * tol, st, &h, 0.0, tol * tol * next)) != hipSuccess) return e;
+        if (!h.done) {
+            *restarts += 1;
+            tight = next > 1e-6 ? next : 1e-6;
+        }
         // a restart that makes no progress (a non-finite iterate, or the
         // recurrence and the true residual straddling the tolerance) ends
         // the solve unconverged instead of looping
@@ -1046,12 +1071,13 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 1, tol2, st, &h, delta2)) != hipSuccess) return e;
         const double bb = h.bb;
         int mode = P_FIRST, repl = 0, idle = 0, restarts = 0, fallback = 0;
-        double rr_best = h.rr;
+        double rr_best = h.rr, tight = 1.0;
         while (!h.done && h.iter < sp.max_iter) {
             const int before = h.iter;
             int it = 0, done = 0;
+            double rr_rec = 0.0;
             if ((e = run_iterations<DIM, double, float>(m, w, VM, w.kb64, h.iter, sp.max_iter - h.iter, check, st,
-                                                        &it, &done, mode)) != hipSuccess)
+                                                        &it, &done, mode, &rr_rec)) != hipSuccess)
                 return e;
             if (done == 0) {          // iteration budget spent
                 h.iter = it;
@@ -1059,7 +1085,10 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
             }
             hipLaunchKernelGGL(k_true_replace<DIM>, dim3(w.kb64.nblk), dim3(kKBlock), 0, st, m, set.amat,
                                set.unknown, w.beff, VM, w.kb64);
-            hipLaunchKernelGGL(k_replace_finish, dim3(1), dim3(kKBlock), 0, st, w.kb64);
+            // a recurrence that reached the tolerance without the FP64 residual
+            // doing so continues to a tighter one
+            if (done == 1 && rr_rec <= tol2 * tight * bb) tight = tight * 0.25 > 1e-6 ? tight * 0.25 : 1e-6;
+            hipLaunchKernelGGL(k_replace_finish, dim3(1), dim3(kKBlock), 0, st, w.kb64, tol2, tol2 * tight);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(&w.host[0], w.kb64.st[2], sizeof(KState), hipMemcpyDeviceToHost, st)) !=
                 hipSuccess)
@@ -1076,8 +1105,9 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
                 fallback = 1;
                 break;
             }
-            if (done == 2) {          // breakdown: new recursion from the FP64 residual
-                if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 0, tol2, st, &h, delta2)) != hipSuccess)
+            if (done >= 2) {          // breakdown or stagnation: new recursion from the FP64 residual
+                if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 0, tol2, st, &h, delta2, tol2 * tight)) !=
+                    hipSuccess)
                     return e;
                 ++restarts;
                 mode = P_FIRST;
