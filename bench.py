@@ -61,6 +61,22 @@ def workload_name(case, n_active, precision):
             f"quadratic MLS {stencil}, PPE Bi-CGSTAB to 1e-8 ({precision})")
 
 
+def measured_traffic(workload_key):
+    """HBM bytes per S-stage launch from the committed counter summary of this
+    workload, or None when there is none or the kernel source has changed
+    since the counters were taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", f"pmc_k_t2_{workload_key}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    with open(os.path.join(ROOT, d["source"]), "rb") as f:
+        if hashlib.sha256(f.read()).hexdigest() != d["source_sha256"]:
+            return None
+    return d["bytes_per_launch"]
+
+
 def cpu_baseline(case, steps):
     from threadpoolctl import threadpool_limits
 
@@ -159,8 +175,11 @@ def main():
         bytes_per = stage_bytes(n_unknown, case.dim, mat_b, vec_b)
         avg_s = prof["s_ms"] / max(prof["s_n"], 1) * 1e-3
         achieved = bytes_per / avg_s / 1e9 if avg_s > 0 else None
+        key = f"{'taylor_green' if case.name.startswith('C1') else case.name}_{case.n[0]}_{args.precision}"
+        traffic = measured_traffic(key) if case.dim == 2 else None
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                    "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": None,
+                    "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
+                    "traffic_unit": "bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
                     "kernel": "k_kS (Bi-CGSTAB S-stage: s = r - alpha v, t = A s, 4 dots)",
                     "avg_us": avg_s * 1e6, "launches": prof["s_n"], "bytes_per_launch": bytes_per,
                     "timed_launches_from": f"{args.timing_steps} steps after the timed region",
