@@ -108,7 +108,7 @@ def main():
     ap.add_argument("--guess", choices=["warm", "zero", "learned"], default="warm",
                     help="PPE initial guess: previous pressure (default), zero, or the learned correction")
     ap.add_argument("--weights", default=None, help="network weights for --guess learned")
-    ap.add_argument("--cpu-steps", type=int, default=2)
+    ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
     ap.add_argument("--timing-steps", type=int, default=3,
