@@ -180,7 +180,7 @@ def main():
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                     "traffic_unit": "bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
-                    "kernel": "k_kS (Bi-CGSTAB S-stage: s = r - alpha v, t = A s, 4 dots)",
+                    "kernel": f"k_t{case.dim}_S (Bi-CGSTAB S-stage: s = r - alpha v, t = A s, 4 dots)",
                     "avg_us": avg_s * 1e6, "launches": prof["s_n"], "bytes_per_launch": bytes_per,
                     "timed_launches_from": f"{args.timing_steps} steps after the timed region",
                     "p_stage_avg_us": prof["p_ms"] / max(prof["p_n"], 1) * 1e3}

@@ -63,9 +63,10 @@ struct KBufs {
     KState* st[3];       // state written by block 0 of init/finish, P, S
     int nblk;            // blocks (= partials) of the stage kernels in use
     int cap;             // partials capacity per quantity
-    int ntx;             // tiles per row (2D tiled kernels)
-    int ntiles;          // tiles of the mesh (2D)
-    int tpb;             // tiles per block (2D)
+    int ntx;             // tiles per row
+    int nty;             // tile rows per plane (3D bricks)
+    int ntiles;          // tiles (2D) or bricks (3D) of the mesh
+    int tpb;             // tiles or bricks per block
 };
 
 // Sum of A[s][c] * val(j) over the stencil slots of cell c.  Interior cells
@@ -154,29 +155,6 @@ __device__ __forceinline__ void write_partials(double (&v)[NQ], double* part, co
     }
 }
 
-// r0 = b - A x;  rhat = r0 (kept in s and rhat);  partials r0.r0, b.b.
-template <int DIM, typename T, typename TA>
-__global__ __launch_bounds__(kKBlock) void k_kinit(MeshDev m, KVec<T, TA> V, KBufs K) {
-    const T* __restrict__ x = V.x;
-    const T* __restrict__ bp = V.b;
-    const TA* __restrict__ A = V.A;
-    T* __restrict__ sp = V.s;
-    T* __restrict__ rh = V.rhat;
-    double a0 = 0.0, a1 = 0.0;
-    const int lb = xcd_block(blockIdx.x, kKGrid);
-    for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
-        const T ax = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return x[j]; });
-        const T bc = bp[c];
-        const T r = bc - ax;
-        sp[c] = r;
-        rh[c] = r;
-        a0 += (double)r * (double)r;
-        a1 += (double)bc * (double)bc;
-    }
-    double v[2] = {a0, a1};
-    write_partials<2>(v, K.part[0], K);
-}
-
 // One block: reduce the init partials into the state the first P-stage
 // reads.  done tests r.r against tol2 * bb; the recursion that follows stops
 // at tol2_next * bb (tighter after a recurrence that converged while the
@@ -229,123 +207,6 @@ __device__ __forceinline__ bool p_scalars(const KState* in, const KBufs& K, bool
         K.st[1]->done = 2;
     }
     return false;
-}
-
-template <int DIM, typename T, typename TA, int MODE>
-__global__ __launch_bounds__(kKBlock) void k_kP(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
-    const KState* __restrict__ in = K.st[2];
-    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
-    if (in->done) {
-        if (leader) *K.st[1] = *in;
-        return;
-    }
-    double omega, beta, rho_new;
-    if (!p_scalars<MODE>(in, K, leader, omega, beta, rho_new)) return;
-    const T ta = (T)in->alpha, tw = (T)omega, tb = (T)beta;
-    const T* __restrict__ s = V.s;
-    const T* __restrict__ t = V.t;
-    const T* __restrict__ po = V.p[par];
-    const T* __restrict__ vo = V.v[par];
-    const T* __restrict__ rh = V.rhat;
-    const TA* __restrict__ A = V.A;
-    T* __restrict__ pn = V.p[par ^ 1];
-    T* __restrict__ vn = V.v[par ^ 1];
-    T* __restrict__ rp = V.r;
-    T* __restrict__ xp = V.x;
-    double a0 = 0.0, a1 = 0.0;
-    const int lb = xcd_block(blockIdx.x, kKGrid);
-    for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
-        T pc, rc;
-        if (MODE == P_FIRST) {
-            rc = s[c];
-            pc = rc;
-        } else if (MODE == P_RESUME) {
-            rc = rp[c];
-            pc = rc + tb * (po[c] - tw * vo[c]);
-        } else {
-            rc = s[c] - tw * t[c];
-            xp[c] = xp[c] + ta * po[c] + tw * s[c];
-            pc = rc + tb * (po[c] - tw * vo[c]);
-        }
-        if (MODE != P_RESUME) rp[c] = rc;
-        pn[c] = pc;
-        T av;
-        if (MODE == P_FIRST)
-            av = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return s[j]; });
-        else if (MODE == P_RESUME)
-            av = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return rp[j] + tb * (po[j] - tw * vo[j]); });
-        else
-            av = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return (s[j] - tw * t[j]) + tb * (po[j] - tw * vo[j]); });
-        vn[c] = av;
-        a0 += (double)rh[c] * (double)av;
-        a1 += (double)rc * (double)rc;
-    }
-    double acc[2] = {a0, a1};
-    write_partials<2>(acc, K.part[1], K);
-    if (leader) {
-        *K.st[1] = *in;
-        K.st[1]->rho_prev = in->rho;
-        K.st[1]->rho = rho_new;
-        K.st[1]->omega = omega;
-    }
-}
-
-template <int DIM, typename T, typename TA>
-__global__ __launch_bounds__(kKBlock) void k_kS(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
-    const KState* __restrict__ in = K.st[1];
-    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
-    if (in->done) {
-        if (leader) *K.st[2] = *in;
-        return;
-    }
-    double tot[2];
-    reduce_partials<2>(K.part[1], K, tot);       // rhat.v, r.r
-    const double alpha = in->rho / tot[0];
-    int done = 0;
-    if (tot[1] <= fmax(in->tol2 * in->bb, in->delta2 * in->rr_max)) {
-        done = 1;                                // x already holds the iterate of this residual
-    } else if (!(tot[0] != 0.0) || !isfinite(alpha)) {
-        done = 2;
-    }
-    if (done) {
-        if (leader) {
-            *K.st[2] = *in;
-            K.st[2]->rv = tot[0];
-            K.st[2]->rr = tot[1];
-            K.st[2]->done = done;
-        }
-        return;
-    }
-    const T ta = (T)alpha;
-    const T* __restrict__ r = V.r;
-    const T* __restrict__ vn = V.v[par ^ 1];
-    const T* __restrict__ rhp = V.rhat;
-    const TA* __restrict__ A = V.A;
-    T* __restrict__ sp = V.s;
-    T* __restrict__ tp = V.t;
-    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    const int lb = xcd_block(blockIdx.x, kKGrid);
-    for (int c = lb * kKBlock + threadIdx.x; c < m.Nc; c += kKGrid * kKBlock) {
-        const T sc = r[c] - ta * vn[c];
-        const T tc = spmv_row<DIM, T, TA>(m, A, c, [&](int j) { return r[j] - ta * vn[j]; });
-        sp[c] = sc;
-        tp[c] = tc;
-        const double rh = (double)rhp[c];
-        a0 += (double)tc * (double)sc;
-        a1 += (double)tc * (double)tc;
-        a2 += rh * (double)sc;
-        a3 += rh * (double)tc;
-    }
-    double acc[4] = {a0, a1, a2, a3};
-    write_partials<4>(acc, K.part[2], K);
-    if (leader) {
-        *K.st[2] = *in;
-        K.st[2]->rv = tot[0];
-        K.st[2]->rr = tot[1];
-        K.st[2]->rr_max = fmax(in->rr_max, tot[1]);
-        K.st[2]->alpha = alpha;
-        K.st[2]->iter = in->iter + 1;
-    }
 }
 
 // ---------------------------------------------------------------------------
@@ -611,6 +472,261 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
     }
 }
 
+// ---------------------------------------------------------------------------
+// 3D stage kernels (2.5D).  A block of 512 threads owns a 64 x 8 column of
+// cells and marches it over TZ3 planes (a brick).  The operand of the
+// 27-point product is formed once per plane of the brick plus one halo
+// plane below and above, into a ring of three (66 x 10) planes in LDS, so the
+// product reads LDS only; the owner of a cell does its element-wise updates
+// when its plane is formed.
+// ---------------------------------------------------------------------------
+
+constexpr int TZ3 = 8;
+
+// cell index of mesh position (gx, gy, gz) with periodic wrap; -1 outside
+__device__ __forceinline__ int halo_cell3(const MeshDev& m, int gx, int gy, int gz) {
+    if (gz < 0) {
+        if (!m.periodic[2]) return -1;
+        gz += m.n[2];
+    } else if (gz >= m.n[2]) {
+        if (!m.periodic[2]) return -1;
+        gz -= m.n[2];
+    }
+    const int j = halo_cell(m, gx, gy);
+    return j < 0 ? -1 : j + m.n[0] * m.n[1] * gz;
+}
+
+__device__ __forceinline__ void brick_origin(const KBufs& K, int brick, int& tx0, int& ty0, int& tz0) {
+    tx0 = (brick % K.ntx) * TX;
+    ty0 = ((brick / K.ntx) % K.nty) * TY;
+    tz0 = (brick / (K.ntx * K.nty)) * TZ3;
+}
+
+// 27-point product from the ring planes (slots of planes z-1, z, z+1).
+template <typename T, typename TA>
+__device__ __forceinline__ T stencil3_lds(const TA* __restrict__ A, size_t Nc, int c, const T (*ring)[NH], int s0,
+                                          int s1, int s2, int lx, int ly) {
+    const int sl[3] = {s0, s1, s2};
+    T acc = 0;
+    if constexpr (sizeof(TA) < sizeof(double)) {
+        const T xc = ring[s1][(ly + 1) * HX + lx + 1];
+#pragma unroll
+        for (int s = 0; s < 27; ++s) {
+            const T a = (T)A[(size_t)s * Nc + c];
+            const T v = ring[sl[s / 9]][(ly + (s / 3) % 3) * HX + (lx + s % 3)];
+            acc += s == 13 ? a * xc : a * (v - xc);
+        }
+    } else {
+#pragma unroll
+        for (int s = 0; s < 27; ++s)
+            acc += (T)A[(size_t)s * Nc + c] * ring[sl[s / 9]][(ly + (s / 3) % 3) * HX + (lx + s % 3)];
+    }
+    return acc;
+}
+
+// Marches the bricks of this block: form(gz, slot, own_plane) fills a ring
+// slot with the operand of plane gz (doing the owners' updates when
+// own_plane); out(c, s0, s1, s2) consumes the product at cell c.
+template <typename T, typename FORM, typename OUT>
+__device__ __forceinline__ void march_bricks(const MeshDev& m, const KBufs& K, FORM form, OUT out) {
+    const TileRun run = tiles_of(K);
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    for (int k = 0; k < run.count; ++k) {
+        int tx0, ty0, tz0;
+        brick_origin(K, run.first + k, tx0, ty0, tz0);
+        const int tz1 = min(tz0 + TZ3, m.n[2]);
+        form(tx0, ty0, tz0 - 1, 0, false);
+        form(tx0, ty0, tz0, 1, true);
+        for (int z = tz0; z < tz1; ++z) {
+            form(tx0, ty0, z + 1, (z - tz0 + 2) % 3, z + 1 < tz1);
+            __syncthreads();
+            const int gx = tx0 + lx, gy = ty0 + ly;
+            if (gx < m.n[0] && gy < m.n[1])
+                out(gx + m.n[0] * (gy + m.n[1] * z), (z - tz0) % 3, (z - tz0 + 1) % 3, (z - tz0 + 2) % 3);
+            __syncthreads();
+        }
+    }
+}
+
+template <typename T, typename TA>
+__global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, KBufs K) {
+    __shared__ T ring[3][NH];
+    const T* __restrict__ xp = V.x;
+    const T* __restrict__ bp = V.b;
+    const TA* __restrict__ A = V.A;
+    T* __restrict__ sp = V.s;
+    T* __restrict__ rh = V.rhat;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    double a0 = 0.0, a1 = 0.0;
+    march_bricks<T>(
+        m, K,
+        [&](int tx0, int ty0, int gz, int slot, bool) {
+            for (int e = threadIdx.x; e < NH; e += kKBlock) {
+                const int j = halo_cell3(m, tx0 + e % HX - 1, ty0 + e / HX - 1, gz);
+                ring[slot][e] = j >= 0 ? xp[j] : T(0);
+            }
+        },
+        [&](int c, int s0, int s1, int s2) {
+            const T ax = stencil3_lds<T, TA>(A, (size_t)m.Nc, c, ring, s0, s1, s2, lx, ly);
+            const T bc = bp[c];
+            const T r = bc - ax;
+            sp[c] = r;
+            rh[c] = r;
+            a0 += (double)r * (double)r;
+            a1 += (double)bc * (double)bc;
+        });
+    double v[2] = {a0, a1};
+    write_partials<2>(v, K.part[0], K);
+}
+
+template <typename T, typename TA, int MODE>
+__global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
+    __shared__ T ring[3][NH];
+    const KState* __restrict__ in = K.st[2];
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    if (in->done) {
+        if (leader) *K.st[1] = *in;
+        return;
+    }
+    double omega, beta, rho_new;
+    if (!p_scalars<MODE>(in, K, leader, omega, beta, rho_new)) return;
+    const T ta = (T)in->alpha, tw = (T)omega, tb = (T)beta;
+    const T* __restrict__ sp = V.s;
+    const T* __restrict__ tp = V.t;
+    const T* __restrict__ po = V.p[par];
+    const T* __restrict__ vo = V.v[par];
+    const T* __restrict__ rh = V.rhat;
+    const TA* __restrict__ A = V.A;
+    T* __restrict__ pn = V.p[par ^ 1];
+    T* __restrict__ vn = V.v[par ^ 1];
+    T* __restrict__ rp = V.r;
+    T* __restrict__ xp = V.x;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    double a0 = 0.0, a1 = 0.0;
+    march_bricks<T>(
+        m, K,
+        [&](int tx0, int ty0, int gz, int slot, bool own_plane) {
+            for (int e = threadIdx.x; e < NH; e += kKBlock) {
+                const int hx = e % HX, hy = e / HX;
+                const int gx = tx0 + hx - 1, gy = ty0 + hy - 1;
+                const int j = halo_cell3(m, gx, gy, gz);
+                T pv = 0;
+                if (j >= 0) {
+                    T rj, sj = 0, poj = 0;
+                    if (MODE == P_FIRST) {
+                        rj = sp[j];
+                        pv = rj;
+                    } else if (MODE == P_RESUME) {
+                        rj = rp[j];
+                        poj = po[j];
+                        pv = rj + tb * (poj - tw * vo[j]);
+                    } else {
+                        sj = sp[j];
+                        const T tj = tp[j];
+                        poj = po[j];
+                        const T voj = vo[j];
+                        rj = sj - tw * tj;
+                        pv = rj + tb * (poj - tw * voj);
+                    }
+                    if (own_plane && hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1]) {
+                        if (MODE != P_RESUME) rp[j] = rj;
+                        pn[j] = pv;
+                        if (MODE == P_NORMAL) xp[j] = xp[j] + ta * poj + tw * sj;
+                        a1 += (double)rj * (double)rj;
+                    }
+                }
+                ring[slot][e] = pv;
+            }
+        },
+        [&](int c, int s0, int s1, int s2) {
+            const T av = stencil3_lds<T, TA>(A, (size_t)m.Nc, c, ring, s0, s1, s2, lx, ly);
+            vn[c] = av;
+            a0 += (double)rh[c] * (double)av;
+        });
+    double acc[2] = {a0, a1};
+    write_partials<2>(acc, K.part[1], K);
+    if (leader) {
+        *K.st[1] = *in;
+        K.st[1]->rho_prev = in->rho;
+        K.st[1]->rho = rho_new;
+        K.st[1]->omega = omega;
+    }
+}
+
+template <typename T, typename TA>
+__global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
+    __shared__ T ring[3][NH];
+    const KState* __restrict__ in = K.st[1];
+    const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    if (in->done) {
+        if (leader) *K.st[2] = *in;
+        return;
+    }
+    double tot[2];
+    reduce_partials<2>(K.part[1], K, tot);       // rhat.v, r.r
+    const double alpha = in->rho / tot[0];
+    int done = 0;
+    if (tot[1] <= fmax(in->tol2 * in->bb, in->delta2 * in->rr_max)) {
+        done = 1;
+    } else if (!(tot[0] != 0.0) || !isfinite(alpha)) {
+        done = 2;
+    }
+    if (done) {
+        if (leader) {
+            *K.st[2] = *in;
+            K.st[2]->rv = tot[0];
+            K.st[2]->rr = tot[1];
+            K.st[2]->done = done;
+        }
+        return;
+    }
+    const T ta = (T)alpha;
+    const T* __restrict__ rp = V.r;
+    const T* __restrict__ vn = V.v[par ^ 1];
+    const T* __restrict__ rh = V.rhat;
+    const TA* __restrict__ A = V.A;
+    T* __restrict__ sp = V.s;
+    T* __restrict__ tp = V.t;
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    march_bricks<T>(
+        m, K,
+        [&](int tx0, int ty0, int gz, int slot, bool own_plane) {
+            for (int e = threadIdx.x; e < NH; e += kKBlock) {
+                const int hx = e % HX, hy = e / HX;
+                const int gx = tx0 + hx - 1, gy = ty0 + hy - 1;
+                const int j = halo_cell3(m, gx, gy, gz);
+                T sv = 0;
+                if (j >= 0) {
+                    sv = rp[j] - ta * vn[j];
+                    if (own_plane && hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1])
+                        sp[j] = sv;
+                }
+                ring[slot][e] = sv;
+            }
+        },
+        [&](int c, int s0, int s1, int s2) {
+            const T tcv = stencil3_lds<T, TA>(A, (size_t)m.Nc, c, ring, s0, s1, s2, lx, ly);
+            const T sc = ring[s1][(ly + 1) * HX + lx + 1];
+            tp[c] = tcv;
+            const double r = (double)rh[c];
+            a0 += (double)tcv * (double)sc;
+            a1 += (double)tcv * (double)tcv;
+            a2 += r * (double)sc;
+            a3 += r * (double)tcv;
+        });
+    double acc[4] = {a0, a1, a2, a3};
+    write_partials<4>(acc, K.part[2], K);
+    if (leader) {
+        *K.st[2] = *in;
+        K.st[2]->rv = tot[0];
+        K.st[2]->rr = tot[1];
+        K.st[2]->rr_max = fmax(in->rr_max, tot[1]);
+        K.st[2]->alpha = alpha;
+        K.st[2]->iter = in->iter + 1;
+    }
+}
+
 // b_eff = rhs - (Dirichlet columns) g - (Neumann rows) f at unknown rows; x0.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_ppe_rhs(MeshDev m, SetDev st, const double* __restrict__ rhs,
@@ -814,12 +930,12 @@ static void enqueue_iteration(const MeshDev& m, const KVec<T, TA>& V, const KBuf
         hipExtLaunchKernelGGL((k_t2_S<T, TA>), G, B, 0, st, e2, e3, 0, m, V, par, K);
     } else {
         if (mode == P_FIRST)
-            hipExtLaunchKernelGGL((k_kP<DIM, T, TA, P_FIRST>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_FIRST>), G, B, 0, st, e0, e1, 0, m, V, par, K);
         else if (mode == P_RESUME)
-            hipExtLaunchKernelGGL((k_kP<DIM, T, TA, P_RESUME>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_RESUME>), G, B, 0, st, e0, e1, 0, m, V, par, K);
         else
-            hipExtLaunchKernelGGL((k_kP<DIM, T, TA, P_NORMAL>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        hipExtLaunchKernelGGL((k_kS<DIM, T, TA>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_NORMAL>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_t3_S<T, TA>), G, B, 0, st, e2, e3, 0, m, V, par, K);
     }
 }
 
@@ -955,7 +1071,7 @@ static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, c
     if (m.dim == 2)
         hipLaunchKernelGGL((k_t2_init<T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
     else
-        hipLaunchKernelGGL((k_kinit<DIM, T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+        hipLaunchKernelGGL((k_t3_init<T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
     hipLaunchKernelGGL(k_kfinish, dim3(1), dim3(kKBlock), 0, st, K, with_bb, tol2, with_bb ? 0 : 1, delta2,
                        tol2_next < 0.0 ? tol2 : tol2_next);
     hipError_t e = hipGetLastError();
@@ -1273,19 +1389,18 @@ hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     const int Nc = m.Nc;
     w->Nc = Nc;
     hipError_t e;
-    // 2D: one block per 64 x 8 tile; 3D: a fixed grid with grid-stride loops
-    int ntx = 0, nblk = kKGrid, ntiles = 0, tpb = 0;
-    if (m.dim == 2) {
-        ntx = (m.n[0] + TX - 1) / TX;
-        ntiles = ntx * ((m.n[1] + TY - 1) / TY);
-        nblk = ntiles < kKGrid ? ntiles : kKGrid;
-        tpb = (ntiles + nblk - 1) / nblk;
-    }
+    // one block per 64 x 8 tile (2D) or 64 x 8 x 8 brick (3D), at most kKGrid
+    // blocks, each looping over a contiguous run of tiles
+    const int ntx = (m.n[0] + TX - 1) / TX, nty = (m.n[1] + TY - 1) / TY;
+    const int ntiles = ntx * nty * (m.dim == 3 ? (m.n[2] + TZ3 - 1) / TZ3 : 1);
+    const int nblk = ntiles < kKGrid ? ntiles : kKGrid;
+    const int tpb = (ntiles + nblk - 1) / nblk;
     const int cap = kKGrid;
     for (KBufs* K : {&w->kb64, &w->kb32}) {
         K->nblk = nblk;
         K->cap = cap;
         K->ntx = ntx;
+        K->nty = nty;
         K->ntiles = ntiles;
         K->tpb = tpb;
         for (int q = 0; q < 3; ++q) {

@@ -341,6 +341,52 @@ def test_ppe_cylinder_neumann(M):
     assert iters[M.PREC_FP32_MATRIX] <= 1.5 * iters[M.PREC_FP64] + 16, iters
 
 
+@pytest.mark.parametrize("n", [20, 24])
+def test_ppe_sphere_3d(M, n):
+    """3D PPE (plane-marching stage kernels, ragged bricks at n = 20) in every
+    precision: true residual <= 1e-8 on the oracle's assembled operator."""
+    case = configs.c4_moving_sphere(n=n)
+    m, pos, role, nrm = _arranged(case)
+    rng = np.random.default_rng(3)
+    rhs = rng.standard_normal(m.Nc)
+    f = np.where(role == 2, rng.standard_normal(m.Nc), 0.0)
+    g = np.zeros(m.Nc)
+    ctx = M.Context.from_case(case)
+    ctx.build_stencils(2, _dev(pos), _dev(role, torch.int8), _dev(nrm), case.bc_pressure)
+    st = O.mls_build(m, pos, role, nrm, case.bc_pressure, case.re_over_l0 * case.l0, case.l0, case.weight)
+    A, b, uidx = O.ppe_system(m, st, role, case.bc_pressure, rhs, g, f)
+    sols = []
+    for prec in (M.PREC_FP64, M.PREC_FP32_MATRIX, M.PREC_FP32_REFINE):
+        p = _dev(g)
+        info = ctx.solve_ppe(2, _dev(rhs), p, _dev(f), precision=prec)
+        assert info["converged"] and info["true_rel_residual"] <= 1e-8, (prec, info)
+        pg = np_(p)
+        assert np.linalg.norm(b - A @ pg[uidx]) / np.linalg.norm(b) <= 1e-8 * (1 + 1e-6), prec
+        sols.append(pg[uidx])
+    for q in sols[1:]:
+        assert np.linalg.norm(q - sols[0]) / np.linalg.norm(sols[0]) < 1e-5
+    r = _dev(np.zeros(m.Nc))
+    nr, nb = ctx.ppe_residual(2, _dev(rhs), _dev(g), r, _dev(f))
+    assert nb == pytest.approx(np.linalg.norm(b), rel=1e-12)
+    assert np.abs(np_(r)[uidx] - (b - A @ g[uidx])).max() <= 1e-12 * np.abs(b).max()
+
+
+def test_sphere_steps_match_oracle(M):
+    """Whole 3D steps (moving sphere, 16^3): DP arrays bit-exact, velocity
+    within 1e-6 of the oracle."""
+    from paper_2404_17542_amd.sim import GpuSim
+    case = configs.c4_moving_sphere(n=16, steps=3)
+    g = GpuSim(case)
+    o = OracleSim(case)
+    assert bits_equal(np_(g.pos), o.pos)
+    for _ in range(3):
+        rg = g.step()
+        o.step()
+        assert rg["converged"] and rg["rel_res"] <= 1e-8
+        assert bits_equal(np_(g.pos), o.pos) and bits_equal(np_(g.role), o.role)
+    assert np.abs(np_(g.u) - o.u).max() / max(np.abs(o.u).max(), 1e-30) < 1e-6
+
+
 def test_ppe_residual_matches_oracle(M):
     """mcd_ppe_residual = b_eff - A p of the oracle's assembled system, with
     Dirichlet values taken from p and Neumann data moved to the right side."""
