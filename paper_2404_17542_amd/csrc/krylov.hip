@@ -313,18 +313,89 @@ __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T, TA> V, K
     write_partials<2>(v, K.part[0], K);
 }
 
+// LDS-only block barrier: waits for this wave's LDS traffic, not for its
+// outstanding global loads (the stage kernels never read in one thread what
+// another thread of the block wrote to global memory in the same kernel).
+__device__ __forceinline__ void sync_lds() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+// block_sum_all with LDS-only barriers (same arithmetic and order)
+template <int NQ>
+__device__ __forceinline__ void block_sum_lds(double (&v)[NQ]) {
+    __shared__ double lds[NQ][kKBlock / 64];
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const double sq = wave_sum(v[q]);
+        if (lane == 0) lds[q][wid] = sq;
+    }
+    sync_lds();
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        double sq = 0.0;
+#pragma unroll
+        for (int w = 0; w < kKBlock / 64; ++w) sq += lds[q][w];
+        v[q] = sq;
+    }
+    sync_lds();
+}
+
+// This block's partials of a stage (one per thread; kKGrid <= kKBlock).
+template <int NQ>
+__device__ __forceinline__ void load_partials(const double* __restrict__ part, const KBufs& K, double (&q)[NQ]) {
+#pragma unroll
+    for (int k = 0; k < NQ; ++k) q[k] = (int)threadIdx.x < K.nblk ? part[k * K.cap + threadIdx.x] : 0.0;
+}
+
+template <int NQ>
+__device__ __forceinline__ void store_partials(double (&v)[NQ], double* part, const KBufs& K) {
+    block_sum_lds<NQ>(v);
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) part[q * K.cap + blockIdx.x] = v[q];
+    }
+}
+
+// Operands of one halo element of a P-stage tile.
+template <typename T>
+struct HaloP {
+    int j;
+    bool own;
+    T s, t, p, v, x;
+};
+
+template <typename T, int MODE>
+__device__ __forceinline__ void load_halo_p(const MeshDev& m, int tx0, int ty0, int e, const T* __restrict__ sp, const T* __restrict__ tp,
+                                            const T* __restrict__ po, const T* __restrict__ vo,
+                                            const T* __restrict__ rp, const T* __restrict__ xp, HaloP<T>& h) {
+    const int hx = e % HX, hy = e / HX;
+    const int gx = tx0 + hx - 1, gy = ty0 + hy - 1;
+    h.j = halo_cell(m, gx, gy);
+    h.own = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1];
+    if (h.j < 0) return;
+    if (MODE == P_FIRST) {
+        h.s = sp[h.j];
+    } else if (MODE == P_RESUME) {
+        h.s = rp[h.j];               // the replaced residual
+        h.p = po[h.j];
+        h.v = vo[h.j];
+    } else {
+        h.s = sp[h.j];
+        h.t = tp[h.j];
+        h.p = po[h.j];
+        h.v = vo[h.j];
+        if (h.own) h.x = xp[h.j];
+    }
+}
+
+// P-stage (2D).  Every load the first tile needs (state, the S-stage
+// partials, the halo operands, the matrix row, rhat) is issued before the
+// block reduction, and the next tile's halo operands while the current tile
+// is formed, so that the memory latencies overlap.
 template <typename T, typename TA, int MODE>
 __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T pl[NH];
     const KState* __restrict__ in = K.st[2];
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
-    if (in->done) {
-        if (leader) *K.st[1] = *in;
-        return;
-    }
-    double omega, beta, rho_new;
-    if (!p_scalars<MODE>(in, K, leader, omega, beta, rho_new)) return;
-    const T ta = (T)in->alpha, tw = (T)omega, tb = (T)beta;
     const T* __restrict__ sp = V.s;
     const T* __restrict__ tp = V.t;
     const T* __restrict__ po = V.p[par];
@@ -336,55 +407,110 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
     T* __restrict__ rp = V.r;
     T* __restrict__ xp = V.x;
     const TileRun run = tiles_of(K);
-    double a0 = 0.0, a1 = 0.0;
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const size_t Nc = (size_t)m.Nc;
+    const int e0 = threadIdx.x, e1 = threadIdx.x + kKBlock;
+    const bool has1 = e1 < NH;
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+    if (MODE == P_NORMAL) load_partials<4>(K.part[2], K, q);   // t.s, t.t, rhat.s, rhat.t
+    HaloP<T> h0{-1, false, 0, 0, 0, 0, 0}, h1{-1, false, 0, 0, 0, 0, 0};
+    int tx0n = 0, ty0n = 0, c = -1;
+    TA a[9];
+    T rhc = 0;
+    if (run.count > 0) {
+        tile_origin(K, run.first, tx0n, ty0n);
+        load_halo_p<T, MODE>(m, tx0n, ty0n, e0, sp, tp, po, vo, rp, xp, h0);
+        if (has1) load_halo_p<T, MODE>(m, tx0n, ty0n, e1, sp, tp, po, vo, rp, xp, h1);
+    }
+    if (in->done) {
+        if (leader) *K.st[1] = *in;
+        return;
+    }
+    double omega = 1.0, beta = 0.0, rho_new = in->rho;
+    bool ok = true;
+    if (MODE == P_NORMAL) {
+        block_sum_lds<4>(q);
+        omega = q[0] / q[1];
+        rho_new = q[2] - omega * q[3];
+        beta = (rho_new / in->rho) * (in->alpha / omega);
+        ok = q[1] > 0.0 && isfinite(omega) && isfinite(beta) && omega != 0.0 && fabs(rho_new) >= 1e-30 * in->rr0;
+    } else if (MODE == P_RESUME) {
+        omega = in->omega;
+        rho_new = in->rho_res;
+        beta = (rho_new / in->rho_prev) * (in->alpha / omega);
+        ok = isfinite(beta) && omega != 0.0 && fabs(rho_new) >= 1e-30 * in->rr0;
+    }
+    if (!ok) {
+        if (leader) {
+            *K.st[1] = *in;
+            K.st[1]->done = 2;
+        }
+        return;
+    }
+    const T ta = (T)in->alpha, tw = (T)omega, tb = (T)beta;
+    double a0 = 0.0, a1 = 0.0;
     for (int k = 0; k < run.count; ++k) {
-        int tx0, ty0;
-        tile_origin(K, run.first + k, tx0, ty0);
-        for (int e = threadIdx.x; e < NH; e += kKBlock) {
-            const int hx = e % HX, hy = e / HX;
-            const int gx = tx0 + hx - 1, gy = ty0 + hy - 1;
-            const int j = halo_cell(m, gx, gy);
+        const int tx0 = tx0n, ty0 = ty0n;
+        {
+            const int gxo = tx0 + lx, gyo = ty0 + ly;
+            c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
+            if (c >= 0) {
+#pragma unroll
+                for (int s = 0; s < 9; ++s) a[s] = A[(size_t)s * Nc + c];
+                rhc = rh[c];
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const HaloP<T>& h = u == 0 ? h0 : h1;
+            const int e = u == 0 ? e0 : e1;
+            if (u == 1 && !has1) break;
             T pv = 0;
-            if (j >= 0) {
-                T rj, sj = 0, poj = 0;
+            if (h.j >= 0) {
+                T rj;
                 if (MODE == P_FIRST) {
-                    rj = sp[j];
+                    rj = h.s;
                     pv = rj;
                 } else if (MODE == P_RESUME) {
-                    rj = rp[j];
-                    poj = po[j];
-                    pv = rj + tb * (poj - tw * vo[j]);
+                    rj = h.s;
+                    pv = rj + tb * (h.p - tw * h.v);
                 } else {
-                    sj = sp[j];
-                    const T tj = tp[j];
-                    poj = po[j];
-                    const T voj = vo[j];
-                    rj = sj - tw * tj;
-                    pv = rj + tb * (poj - tw * voj);
+                    rj = h.s - tw * h.t;
+                    pv = rj + tb * (h.p - tw * h.v);
                 }
-                const bool own = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1];
-                if (own) {
-                    if (MODE != P_RESUME) rp[j] = rj;
-                    pn[j] = pv;
-                    if (MODE == P_NORMAL) xp[j] = xp[j] + ta * poj + tw * sj;
+                if (h.own) {
+                    if (MODE != P_RESUME) rp[h.j] = rj;
+                    pn[h.j] = pv;
+                    if (MODE == P_NORMAL) xp[h.j] = h.x + ta * h.p + tw * h.s;
                     a1 += (double)rj * (double)rj;
                 }
             }
             pl[e] = pv;
         }
-        __syncthreads();
-        const int gx = tx0 + lx, gy = ty0 + ly;
-        if (gx < m.n[0] && gy < m.n[1]) {
-            const int c = gx + m.n[0] * gy;
-            const T av = stencil_lds<T, TA>(A, (size_t)m.Nc, c, pl, lx, ly);
-            vn[c] = av;
-            a0 += (double)rh[c] * (double)av;
+        if (k + 1 < run.count) {
+            tile_origin(K, run.first + k + 1, tx0n, ty0n);
+            load_halo_p<T, MODE>(m, tx0n, ty0n, e0, sp, tp, po, vo, rp, xp, h0);
+            if (has1) load_halo_p<T, MODE>(m, tx0n, ty0n, e1, sp, tp, po, vo, rp, xp, h1);
         }
-        __syncthreads();
+        sync_lds();
+        if (c >= 0) {
+            T av = 0;
+            if constexpr (sizeof(TA) < sizeof(double)) {
+                const T xc = pl[(ly + 1) * HX + lx + 1];
+#pragma unroll
+                for (int s = 0; s < 9; ++s)
+                    av += s == 4 ? (T)a[s] * xc : (T)a[s] * (pl[(ly + s / 3) * HX + (lx + s % 3)] - xc);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 9; ++s) av += (T)a[s] * pl[(ly + s / 3) * HX + (lx + s % 3)];
+            }
+            vn[c] = av;
+            a0 += (double)rhc * (double)av;
+        }
+        sync_lds();
     }
     double acc[2] = {a0, a1};
-    write_partials<2>(acc, K.part[1], K);
+    store_partials<2>(acc, K.part[1], K);
     if (leader) {
         *K.st[1] = *in;
         K.st[1]->rho_prev = in->rho;
@@ -393,17 +519,55 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
     }
 }
 
+// S-stage (2D), load-first like the P-stage.
 template <typename T, typename TA>
 __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T sl[NH];
     const KState* __restrict__ in = K.st[1];
     const bool leader = blockIdx.x == 0 && threadIdx.x == 0;
+    const T* __restrict__ rp = V.r;
+    const T* __restrict__ vn = V.v[par ^ 1];
+    const T* __restrict__ rh = V.rhat;
+    const TA* __restrict__ A = V.A;
+    T* __restrict__ sp = V.s;
+    T* __restrict__ tp = V.t;
+    const TileRun run = tiles_of(K);
+    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const size_t Nc = (size_t)m.Nc;
+    const int e0 = threadIdx.x, e1 = threadIdx.x + kKBlock;
+    const bool has1 = e1 < NH;
+    double tot[2];
+    load_partials<2>(K.part[1], K, tot);           // rhat.v, r.r
+    int j0 = -1, j1 = -1, tx0n = 0, ty0n = 0, c = -1;
+    T r0 = 0, v0 = 0, r1 = 0, v1 = 0, rhc = 0;
+    TA a[9];
+    if (run.count > 0) {
+        tile_origin(K, run.first, tx0n, ty0n);
+        j0 = halo_cell(m, tx0n + e0 % HX - 1, ty0n + e0 / HX - 1);
+        if (j0 >= 0) {
+            r0 = rp[j0];
+            v0 = vn[j0];
+        }
+        if (has1) {
+            j1 = halo_cell(m, tx0n + e1 % HX - 1, ty0n + e1 / HX - 1);
+            if (j1 >= 0) {
+                r1 = rp[j1];
+                v1 = vn[j1];
+            }
+        }
+        const int gxo = tx0n + lx, gyo = ty0n + ly;
+        c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
+        if (c >= 0) {
+#pragma unroll
+            for (int s = 0; s < 9; ++s) a[s] = A[(size_t)s * Nc + c];
+            rhc = rh[c];
+        }
+    }
     if (in->done) {
         if (leader) *K.st[2] = *in;
         return;
     }
-    double tot[2];
-    reduce_partials<2>(K.part[1], K, tot);       // rhat.v, r.r
+    block_sum_lds<2>(tot);
     const double alpha = in->rho / tot[0];
     int done = 0;
     if (tot[1] <= fmax(in->tol2 * in->bb, in->delta2 * in->rr_max)) {
@@ -421,47 +585,75 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
         return;
     }
     const T ta = (T)alpha;
-    const T* __restrict__ rp = V.r;
-    const T* __restrict__ vn = V.v[par ^ 1];
-    const T* __restrict__ rh = V.rhat;
-    const TA* __restrict__ A = V.A;
-    T* __restrict__ sp = V.s;
-    T* __restrict__ tp = V.t;
-    const TileRun run = tiles_of(K);
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
-    const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     for (int k = 0; k < run.count; ++k) {
-        int tx0, ty0;
-        tile_origin(K, run.first + k, tx0, ty0);
-        for (int e = threadIdx.x; e < NH; e += kKBlock) {
-            const int hx = e % HX, hy = e / HX;
-            const int gx = tx0 + hx - 1, gy = ty0 + hy - 1;
-            const int j = halo_cell(m, gx, gy);
-            T sv = 0;
-            if (j >= 0) {
-                sv = rp[j] - ta * vn[j];
-                const bool own = hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1];
-                if (own) sp[j] = sv;
+        const int tx0 = tx0n, ty0 = ty0n;
+        if (k > 0) {
+            const int gxo = tx0 + lx, gyo = ty0 + ly;
+            c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
+            if (c >= 0) {
+#pragma unroll
+                for (int s = 0; s < 9; ++s) a[s] = A[(size_t)s * Nc + c];
+                rhc = rh[c];
             }
-            sl[e] = sv;
         }
-        __syncthreads();
-        const int gx = tx0 + lx, gy = ty0 + ly;
-        if (gx < m.n[0] && gy < m.n[1]) {
-            const int c = gx + m.n[0] * gy;
-            const T tcv = stencil_lds<T, TA>(A, (size_t)m.Nc, c, sl, lx, ly);
+        {
+            const int hx = e0 % HX, hy = e0 / HX, gx = tx0 + hx - 1, gy = ty0 + hy - 1;
+            T sv = 0;
+            if (j0 >= 0) {
+                sv = r0 - ta * v0;
+                if (hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1]) sp[j0] = sv;
+            }
+            sl[e0] = sv;
+        }
+        if (has1) {
+            const int hx = e1 % HX, hy = e1 / HX, gx = tx0 + hx - 1, gy = ty0 + hy - 1;
+            T sv = 0;
+            if (j1 >= 0) {
+                sv = r1 - ta * v1;
+                if (hx >= 1 && hx <= TX && hy >= 1 && hy <= TY && gx < m.n[0] && gy < m.n[1]) sp[j1] = sv;
+            }
+            sl[e1] = sv;
+        }
+        if (k + 1 < run.count) {
+            tile_origin(K, run.first + k + 1, tx0n, ty0n);
+            j0 = halo_cell(m, tx0n + e0 % HX - 1, ty0n + e0 / HX - 1);
+            if (j0 >= 0) {
+                r0 = rp[j0];
+                v0 = vn[j0];
+            }
+            if (has1) {
+                j1 = halo_cell(m, tx0n + e1 % HX - 1, ty0n + e1 / HX - 1);
+                if (j1 >= 0) {
+                    r1 = rp[j1];
+                    v1 = vn[j1];
+                }
+            }
+        }
+        sync_lds();
+        if (c >= 0) {
+            T tcv = 0;
+            if constexpr (sizeof(TA) < sizeof(double)) {
+                const T xc = sl[(ly + 1) * HX + lx + 1];
+#pragma unroll
+                for (int s = 0; s < 9; ++s)
+                    tcv += s == 4 ? (T)a[s] * xc : (T)a[s] * (sl[(ly + s / 3) * HX + (lx + s % 3)] - xc);
+            } else {
+#pragma unroll
+                for (int s = 0; s < 9; ++s) tcv += (T)a[s] * sl[(ly + s / 3) * HX + (lx + s % 3)];
+            }
             const T sc = sl[(ly + 1) * HX + lx + 1];
             tp[c] = tcv;
-            const double r = (double)rh[c];
+            const double r = (double)rhc;
             a0 += (double)tcv * (double)sc;
             a1 += (double)tcv * (double)tcv;
             a2 += r * (double)sc;
             a3 += r * (double)tcv;
         }
-        __syncthreads();
+        sync_lds();
     }
     double acc[4] = {a0, a1, a2, a3};
-    write_partials<4>(acc, K.part[2], K);
+    store_partials<4>(acc, K.part[2], K);
     if (leader) {
         *K.st[2] = *in;
         K.st[2]->rv = tot[0];

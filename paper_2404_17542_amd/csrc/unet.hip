@@ -59,15 +59,19 @@ __device__ __forceinline__ __bf16 load1(const ConvIn& in, int y, int x, int k) {
 
 // Implicit-GEMM 3x3 convolution.  Wk: [9][NT*32][K] bf16 (K = c0 + c1, zero
 // rows for n >= cout).  A block of 4 waves covers 128 consecutive pixels;
-// each wave owns 32 pixels and all NT column tiles.
+// each wave owns 32 pixels and all NT column tiles.  The epilogue (bias,
+// ReLU, BF16) goes through a per-wave 32 x 32 LDS tile so that every lane
+// stores 16 contiguous bytes (8 channels of one pixel); cout must be a
+// multiple of 16.
 template <int NT>
 __global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __restrict__ Wk,
                                                    const float* __restrict__ bias, int cout, int relu,
                                                    __bf16* __restrict__ Y) {
+    __shared__ __bf16 stage[4][32 * 32];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int P = in.H * in.W;
     const int p0 = (blockIdx.x * 4 + wave) * 32;
-    if (p0 >= P) return;
+    const bool active = p0 < P;
     const int pm = p0 + (l & 31);
     const bool valid = pm < P;
     const int ym = valid ? pm / in.W : 0, xm = valid ? pm % in.W : 0;
@@ -78,32 +82,42 @@ __global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __re
     for (int nt = 0; nt < NT; ++nt)
 #pragma unroll
         for (int i = 0; i < 16; ++i) acc[nt][i] = 0.0f;
-    for (int t = 0; t < 9; ++t) {
-        const int dy = t / 3 - 1, dx = t % 3 - 1;
-        const __bf16* wt = Wk + (size_t)t * NT * 32 * K;
-        for (int k0 = 0; k0 < K; k0 += 16) {
-            const int kk = k0 + half;
-            const bf16x8 a = valid ? load8(in, ym + dy, xm + dx, kk) : zero8();
+    if (active) {
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3 - 1, dx = t % 3 - 1;
+            const __bf16* wt = Wk + (size_t)t * NT * 32 * K;
+            for (int k0 = 0; k0 < K; k0 += 16) {
+                const int kk = k0 + half;
+                const bf16x8 a = valid ? load8(in, ym + dy, xm + dx, kk) : zero8();
 #pragma unroll
-            for (int nt = 0; nt < NT; ++nt) {
-                const bf16x8 b = *(const bf16x8*)(wt + (size_t)(nt * 32 + (l & 31)) * K + kk);
-                acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[nt], 0, 0, 0);
+                for (int nt = 0; nt < NT; ++nt) {
+                    const bf16x8 b = *(const bf16x8*)(wt + (size_t)(nt * 32 + (l & 31)) * K + kk);
+                    acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[nt], 0, 0, 0);
+                }
             }
         }
     }
+    __bf16* sw = stage[wave];
+    const int row = l >> 1, col0 = 16 * (l & 1);
 #pragma unroll
     for (int nt = 0; nt < NT; ++nt) {
         const int n = nt * 32 + (l & 31);
-        if (n >= cout) continue;
-        const float bn = bias ? bias[n] : 0.0f;
+        const float bn = (bias && n < cout) ? bias[n] : 0.0f;
 #pragma unroll
         for (int i = 0; i < 16; ++i) {
-            const int p = p0 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
-            if (p >= P) continue;
             float v = acc[nt][i] + bn;
             if (relu) v = fmaxf(v, 0.0f);
-            Y[(size_t)p * cout + n] = (__bf16)v;
+            sw[(8 * (i >> 2) + 4 * (l >> 5) + (i & 3)) * 32 + (l & 31)] = (__bf16)v;
         }
+        __syncthreads();
+        const int p = p0 + row, nc = nt * 32 + col0;
+        if (active && p < P && nc < cout) {
+            const bf16x8* src = (const bf16x8*)(sw + row * 32 + col0);
+            bf16x8* dst = (bf16x8*)(Y + (size_t)p * cout + nc);
+            dst[0] = src[0];
+            dst[1] = src[1];
+        }
+        __syncthreads();
     }
 }
 
@@ -231,7 +245,7 @@ __global__ void k_cat_split(const __bf16* __restrict__ gcat, int H, int W, int c
 // Head (C -> 1, FP32 on the vector units), input packing, loss, Adam
 // ---------------------------------------------------------------------------
 
-// h[p] = bh + sum_t sum_c X[p + o_t][c] Wh[t][c]
+// h[p] = bh + sum_t sum_c X[p + o_t][c] Wh[t][c]  (C a multiple of 8: 16-byte loads)
 __global__ void k_head_fwd(const __bf16* __restrict__ X, int H, int W, int C, const float* __restrict__ Wh,
                            const float* __restrict__ bh, float* __restrict__ h) {
     const int P = H * W;
@@ -241,9 +255,13 @@ __global__ void k_head_fwd(const __bf16* __restrict__ X, int H, int W, int C, co
         for (int t = 0; t < 9; ++t) {
             const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
             if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-            const __bf16* xp = X + (size_t)(yy * W + xx) * C;
+            const bf16x8* xp = (const bf16x8*)(X + (size_t)(yy * W + xx) * C);
             const float* wp = Wh + t * C;
-            for (int c = 0; c < C; ++c) s += (float)xp[c] * wp[c];
+            for (int q = 0; q < C / 8; ++q) {
+                const bf16x8 v = xp[q];
+#pragma unroll
+                for (int j = 0; j < 8; ++j) s += (float)v[j] * wp[8 * q + j];
+            }
         }
         h[p] = s;
     }
