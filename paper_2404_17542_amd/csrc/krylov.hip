@@ -694,48 +694,58 @@ __device__ __forceinline__ void brick_origin(const KBufs& K, int brick, int& tx0
     tz0 = (brick / (K.ntx * K.nty)) * TZ3;
 }
 
-// 27-point product from the ring planes (slots of planes z-1, z, z+1).
+// Matrix row of cell c (27 slot planes) into registers.
+template <typename TA>
+__device__ __forceinline__ void load_row27(const TA* __restrict__ A, size_t Nc, int c, TA (&a)[27]) {
+#pragma unroll
+    for (int s = 0; s < 27; ++s) a[s] = A[(size_t)s * Nc + c];
+}
+
+// 27-point product of a preloaded row with the ring planes (slots of planes
+// z-1, z, z+1).
 template <typename T, typename TA>
-__device__ __forceinline__ T stencil3_lds(const TA* __restrict__ A, size_t Nc, int c, const T (*ring)[NH], int s0,
-                                          int s1, int s2, int lx, int ly) {
+__device__ __forceinline__ T stencil3_lds(const TA (&a)[27], const T (*ring)[NH], int s0, int s1, int s2, int lx,
+                                          int ly) {
     const int sl[3] = {s0, s1, s2};
     T acc = 0;
     if constexpr (sizeof(TA) < sizeof(double)) {
         const T xc = ring[s1][(ly + 1) * HX + lx + 1];
 #pragma unroll
         for (int s = 0; s < 27; ++s) {
-            const T a = (T)A[(size_t)s * Nc + c];
             const T v = ring[sl[s / 9]][(ly + (s / 3) % 3) * HX + (lx + s % 3)];
-            acc += s == 13 ? a * xc : a * (v - xc);
+            acc += s == 13 ? (T)a[s] * xc : (T)a[s] * (v - xc);
         }
     } else {
 #pragma unroll
-        for (int s = 0; s < 27; ++s)
-            acc += (T)A[(size_t)s * Nc + c] * ring[sl[s / 9]][(ly + (s / 3) % 3) * HX + (lx + s % 3)];
+        for (int s = 0; s < 27; ++s) acc += (T)a[s] * ring[sl[s / 9]][(ly + (s / 3) % 3) * HX + (lx + s % 3)];
     }
     return acc;
 }
 
 // Marches the bricks of this block: form(gz, slot, own_plane) fills a ring
 // slot with the operand of plane gz (doing the owners' updates when
-// own_plane); out(c, s0, s1, s2) consumes the product at cell c.
-template <typename T, typename FORM, typename OUT>
-__device__ __forceinline__ void march_bricks(const MeshDev& m, const KBufs& K, FORM form, OUT out) {
+// own_plane); pre(c) issues the loads of output cell c (matrix row) before
+// the next plane is formed, so that they overlap; out(c, s0, s1, s2)
+// consumes the product at cell c.  Barriers are LDS-only.
+template <typename T, typename FORM, typename PRE, typename OUT>
+__device__ __forceinline__ void march_bricks(const MeshDev& m, const KBufs& K, FORM form, PRE pre, OUT out) {
     const TileRun run = tiles_of(K);
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     for (int k = 0; k < run.count; ++k) {
         int tx0, ty0, tz0;
         brick_origin(K, run.first + k, tx0, ty0, tz0);
         const int tz1 = min(tz0 + TZ3, m.n[2]);
+        const int gx = tx0 + lx, gy = ty0 + ly;
+        const bool inside = gx < m.n[0] && gy < m.n[1];
         form(tx0, ty0, tz0 - 1, 0, false);
         form(tx0, ty0, tz0, 1, true);
         for (int z = tz0; z < tz1; ++z) {
+            const int c = gx + m.n[0] * (gy + m.n[1] * z);
+            if (inside) pre(c);
             form(tx0, ty0, z + 1, (z - tz0 + 2) % 3, z + 1 < tz1);
-            __syncthreads();
-            const int gx = tx0 + lx, gy = ty0 + ly;
-            if (gx < m.n[0] && gy < m.n[1])
-                out(gx + m.n[0] * (gy + m.n[1] * z), (z - tz0) % 3, (z - tz0 + 1) % 3, (z - tz0 + 2) % 3);
-            __syncthreads();
+            sync_lds();
+            if (inside) out(c, (z - tz0) % 3, (z - tz0 + 1) % 3, (z - tz0 + 2) % 3);
+            sync_lds();
         }
     }
 }
@@ -750,6 +760,8 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
     T* __restrict__ rh = V.rhat;
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0;
+    TA a[27];
+    T bcv = 0;
     march_bricks<T>(
         m, K,
         [&](int tx0, int ty0, int gz, int slot, bool) {
@@ -758,9 +770,13 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
                 ring[slot][e] = j >= 0 ? xp[j] : T(0);
             }
         },
+        [&](int c) {
+            load_row27<TA>(A, (size_t)m.Nc, c, a);
+            bcv = bp[c];
+        },
         [&](int c, int s0, int s1, int s2) {
-            const T ax = stencil3_lds<T, TA>(A, (size_t)m.Nc, c, ring, s0, s1, s2, lx, ly);
-            const T bc = bp[c];
+            const T ax = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
+            const T bc = bcv;
             const T r = bc - ax;
             sp[c] = r;
             rh[c] = r;
@@ -795,6 +811,8 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
     T* __restrict__ xp = V.x;
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0;
+    TA a[27];
+    T rhc = 0;
     march_bricks<T>(
         m, K,
         [&](int tx0, int ty0, int gz, int slot, bool own_plane) {
@@ -830,10 +848,14 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
                 ring[slot][e] = pv;
             }
         },
+        [&](int c) {
+            load_row27<TA>(A, (size_t)m.Nc, c, a);
+            rhc = rh[c];
+        },
         [&](int c, int s0, int s1, int s2) {
-            const T av = stencil3_lds<T, TA>(A, (size_t)m.Nc, c, ring, s0, s1, s2, lx, ly);
+            const T av = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
             vn[c] = av;
-            a0 += (double)rh[c] * (double)av;
+            a0 += (double)rhc * (double)av;
         });
     double acc[2] = {a0, a1};
     write_partials<2>(acc, K.part[1], K);
@@ -881,6 +903,8 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
     T* __restrict__ tp = V.t;
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    TA a[27];
+    T rhc = 0;
     march_bricks<T>(
         m, K,
         [&](int tx0, int ty0, int gz, int slot, bool own_plane) {
@@ -897,11 +921,15 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
                 ring[slot][e] = sv;
             }
         },
+        [&](int c) {
+            load_row27<TA>(A, (size_t)m.Nc, c, a);
+            rhc = rh[c];
+        },
         [&](int c, int s0, int s1, int s2) {
-            const T tcv = stencil3_lds<T, TA>(A, (size_t)m.Nc, c, ring, s0, s1, s2, lx, ly);
+            const T tcv = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
             const T sc = ring[s1][(ly + 1) * HX + lx + 1];
             tp[c] = tcv;
-            const double r = (double)rh[c];
+            const double r = (double)rhc;
             a0 += (double)tcv * (double)sc;
             a1 += (double)tcv * (double)tcv;
             a2 += r * (double)sc;
