@@ -1073,6 +1073,12 @@ __global__ __launch_bounds__(kKBlock) void k_replace_finish(KBufs K, double tol2
     }
 }
 
+// x := 0 (a zero right-hand side has the zero solution).
+template <typename T>
+__global__ void k_zero(int Nc, T* __restrict__ x) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < Nc; c += gridDim.x * blockDim.x) x[c] = T(0);
+}
+
 // p := x at unknown cells.
 __global__ void k_writeback(int Nc, const uint8_t* __restrict__ unknown, const double* __restrict__ x,
                             double* __restrict__ p) {
@@ -1314,6 +1320,13 @@ static hipError_t bicgstab(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V
     *restarts = 0;
     *iters = 0;
     const double bb = h.bb;
+    if (bb == 0.0) {
+        const int gz = (m.Nc + kBlock - 1) / kBlock > 8192 ? 8192 : (m.Nc + kBlock - 1) / kBlock;
+        hipLaunchKernelGGL(k_zero<T>, dim3(gz), dim3(kBlock), 0, st, m.Nc, V.x);
+        *rel = 0.0;
+        *conv = 1;
+        return hipGetLastError();
+    }
     int idle = 0;
     double tight = 1.0;
     while (!h.done && h.iter < max_iter) {
@@ -1406,6 +1419,11 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         KState h;
         if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 1, tol2, st, &h, delta2)) != hipSuccess) return e;
         const double bb = h.bb;
+        if (bb == 0.0) {             // zero right-hand side: the zero solution
+            hipLaunchKernelGGL(k_zero<double>, dim3(g), dim3(kBlock), 0, st, m.Nc, V.x);
+            h.done = 1;
+            h.rr = 0.0;
+        }
         int mode = P_FIRST, repl = 0, idle = 0, restarts = 0, fallback = 0;
         double rr_best = h.rr, tight = 1.0;
         while (!h.done && h.iter < sp.max_iter) {
@@ -1485,6 +1503,11 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         KState h;
         if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
         const double bb = h.bb;
+        if (bb == 0.0) {             // zero right-hand side: the zero solution
+            hipLaunchKernelGGL(k_zero<double>, dim3(g), dim3(kBlock), 0, st, m.Nc, V.x);
+            h.done = 1;
+            h.rr = 0.0;
+        }
         int total = 0, outer = 0, rst_total = 0, rejected = 0, fallback = 0;
         double itol = sp.inner_tol;
         while (!h.done && outer < sp.max_outer && total < sp.max_iter) {
