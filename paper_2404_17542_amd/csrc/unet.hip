@@ -57,67 +57,67 @@ __device__ __forceinline__ __bf16 load1(const ConvIn& in, int y, int x, int k) {
     return in.x1[(size_t)((y >> 1) * W1 + (x >> 1)) * in.c1 + (k - in.c0)];
 }
 
-// Implicit-GEMM 3x3 convolution.  Wk: [9][NT*32][K] bf16 (K = c0 + c1, zero
-// rows for n >= cout).  A block of 4 waves covers 128 consecutive pixels;
-// each wave owns 32 pixels and all NT column tiles.  The epilogue (bias,
+// Implicit-GEMM 3x3 convolution on LDS tiles.  Wk: [9][NT*32][K] bf16
+// (K = c0 + c1, zero rows for n >= cout).  A block of 4 waves owns a tile of
+// 4 image rows x 32 columns (wave w: row w, one pixel per MFMA row).  The
+// input is staged through LDS 16 channels at a time as a (4+2) x (32+2)
+// halo tile, so each input pixel is read from memory once per chunk and the
+// nine taps read their A fragments (8 channels per lane) from LDS; B
+// fragments come from the (cache-resident) weights.  The epilogue (bias,
 // ReLU, BF16) goes through a per-wave 32 x 32 LDS tile so that every lane
-// stores 16 contiguous bytes (8 channels of one pixel); cout must be a
-// multiple of 16.
-template <int NT>
-__global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __restrict__ Wk,
+// stores 16 contiguous bytes; cout must be a multiple of 16.
+constexpr int kCR = 4, kCC = 32, kHR = kCR + 2, kHC = kCC + 2, kHalo = kHR * kHC;
+
+// One 32-column tile of output channels per block (blockIdx.z), so that small
+// coarse-level images still spread over the whole chip.
+__global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __restrict__ Wk, int np,
                                                    const float* __restrict__ bias, int cout, int relu,
                                                    __bf16* __restrict__ Y) {
-    __shared__ __bf16 stage[4][32 * 32];
+    __shared__ __attribute__((aligned(16))) __bf16 tile[kHalo * 16];
+    __shared__ __attribute__((aligned(16))) __bf16 stage[4][32 * 32];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int P = in.H * in.W;
-    const int p0 = (blockIdx.x * 4 + wave) * 32;
-    const bool active = p0 < P;
-    const int pm = p0 + (l & 31);
-    const bool valid = pm < P;
-    const int ym = valid ? pm / in.W : 0, xm = valid ? pm % in.W : 0;
+    const int tx0 = blockIdx.x * kCC, ty0 = blockIdx.y * kCR, nt = blockIdx.z;
     const int K = in.c0 + in.c1;
     const int half = 8 * (l >> 5);
-    f32x16 acc[NT];
+    f32x16 acc;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt)
-#pragma unroll
-        for (int i = 0; i < 16; ++i) acc[nt][i] = 0.0f;
-    if (active) {
-        for (int t = 0; t < 9; ++t) {
-            const int dy = t / 3 - 1, dx = t % 3 - 1;
-            const __bf16* wt = Wk + (size_t)t * NT * 32 * K;
-            for (int k0 = 0; k0 < K; k0 += 16) {
-                const int kk = k0 + half;
-                const bf16x8 a = valid ? load8(in, ym + dy, xm + dx, kk) : zero8();
-#pragma unroll
-                for (int nt = 0; nt < NT; ++nt) {
-                    const bf16x8 b = *(const bf16x8*)(wt + (size_t)(nt * 32 + (l & 31)) * K + kk);
-                    acc[nt] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc[nt], 0, 0, 0);
-                }
-            }
+    for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+        // stage channels [k0, k0 + 16) of the halo tile: 2 vectors of 8 per pixel
+        for (int v = threadIdx.x; v < 2 * kHalo; v += 256) {
+            const int px = v >> 1, hv = v & 1;
+            const int y = ty0 - 1 + px / kHC, x = tx0 - 1 + px % kHC;
+            *(bf16x8*)(tile + px * 16 + 8 * hv) = load8(in, y, x, k0 + 8 * hv);
         }
+        __syncthreads();
+        const __bf16* wn = Wk + (size_t)(nt * 32 + (l & 31)) * K + k0 + half;
+#pragma unroll
+        for (int t = 0; t < 9; ++t) {
+            const int dy = t / 3, dx = t % 3;     // halo offsets 0..2
+            const bf16x8 a = *(const bf16x8*)(tile + ((wave + dy) * kHC + (l & 31) + dx) * 16 + half);
+            const bf16x8 b = *(const bf16x8*)(wn + (size_t)t * np * K);
+            acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
+        }
+        __syncthreads();
     }
     __bf16* sw = stage[wave];
     const int row = l >> 1, col0 = 16 * (l & 1);
+    const int y = ty0 + wave, x = tx0 + row;
+    const int n = nt * 32 + (l & 31);
+    const float bn = (bias && n < cout) ? bias[n] : 0.0f;
 #pragma unroll
-    for (int nt = 0; nt < NT; ++nt) {
-        const int n = nt * 32 + (l & 31);
-        const float bn = (bias && n < cout) ? bias[n] : 0.0f;
-#pragma unroll
-        for (int i = 0; i < 16; ++i) {
-            float v = acc[nt][i] + bn;
-            if (relu) v = fmaxf(v, 0.0f);
-            sw[(8 * (i >> 2) + 4 * (l >> 5) + (i & 3)) * 32 + (l & 31)] = (__bf16)v;
-        }
-        __syncthreads();
-        const int p = p0 + row, nc = nt * 32 + col0;
-        if (active && p < P && nc < cout) {
-            const bf16x8* src = (const bf16x8*)(sw + row * 32 + col0);
-            bf16x8* dst = (bf16x8*)(Y + (size_t)p * cout + nc);
-            dst[0] = src[0];
-            dst[1] = src[1];
-        }
-        __syncthreads();
+    for (int i = 0; i < 16; ++i) {
+        float v = acc[i] + bn;
+        if (relu) v = fmaxf(v, 0.0f);
+        sw[(8 * (i >> 2) + 4 * (l >> 5) + (i & 3)) * 32 + (l & 31)] = (__bf16)v;
+    }
+    __syncthreads();
+    const int nc = nt * 32 + col0;
+    if (y < in.H && x < in.W && nc < cout) {
+        const bf16x8* src = (const bf16x8*)(sw + row * 32 + col0);
+        bf16x8* dst = (bf16x8*)(Y + ((size_t)y * in.W + x) * cout + nc);
+        dst[0] = src[0];
+        dst[1] = src[1];
     }
 }
 
@@ -503,19 +503,9 @@ static inline int grid_of(size_t n, int block = 256) {
 
 static hipError_t launch_conv(const ConvIn& in, const __bf16* Wk, int np, const float* bias, int cout, int relu,
                               __bf16* Y, hipStream_t st) {
-    const int P = in.H * in.W;
-    const dim3 g((P + 127) / 128), b(256);
-    switch (np / 32) {
-        case 1: hipLaunchKernelGGL(k_conv_mfma<1>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
-        case 2: hipLaunchKernelGGL(k_conv_mfma<2>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
-        case 3: hipLaunchKernelGGL(k_conv_mfma<3>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
-        case 4: hipLaunchKernelGGL(k_conv_mfma<4>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
-        case 5: hipLaunchKernelGGL(k_conv_mfma<5>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
-        case 6: hipLaunchKernelGGL(k_conv_mfma<6>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
-        case 7: hipLaunchKernelGGL(k_conv_mfma<7>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
-        case 8: hipLaunchKernelGGL(k_conv_mfma<8>, g, b, 0, st, in, Wk, bias, cout, relu, Y); break;
-        default: return hipErrorInvalidValue;
-    }
+    if (np % 32) return hipErrorInvalidValue;
+    const dim3 g((in.W + kCC - 1) / kCC, (in.H + kCR - 1) / kCR, np / 32), b(256);
+    hipLaunchKernelGGL(k_conv_mfma, g, b, 0, st, in, Wk, np, bias, cout, relu, Y);
     return hipGetLastError();
 }
 
