@@ -175,14 +175,34 @@ __global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int 
     }
 }
 
-// Column sums of a [P][C] bf16 matrix: partials per block, then a reduction.
+// Column sums of a [P][C] bf16 matrix (C a multiple of 8, at most 256):
+// partials per block, then a reduction.  Thread (rho, g) of a block sums
+// channels [8g, 8g + 8) over rows r0 + rho, r0 + rho + R, ... with 16-byte
+// loads (consecutive threads read consecutive bytes of a row), then the R
+// row phases are summed in a fixed order through LDS.
 __global__ __launch_bounds__(256) void k_colsum_part(const __bf16* __restrict__ X, int P, int C, int rows_per_block,
                                                      float* __restrict__ part) {
+    __shared__ float red[2048];
+    const int G = C / 8, R = 256 / G;
+    const int g = threadIdx.x % G, rho = threadIdx.x / G;
     const int r0 = blockIdx.x * rows_per_block, r1 = min(P, r0 + rows_per_block);
+    float acc[8];
+#pragma unroll
+    for (int j = 0; j < 8; ++j) acc[j] = 0.0f;
+    if (rho < R) {
+        for (int r = r0 + rho; r < r1; r += R) {
+            const bf16x8 v = *(const bf16x8*)(X + (size_t)r * C + 8 * g);
+#pragma unroll
+            for (int j = 0; j < 8; ++j) acc[j] += (float)v[j];
+        }
+#pragma unroll
+        for (int j = 0; j < 8; ++j) red[rho * C + 8 * g + j] = acc[j];
+    }
+    __syncthreads();
     for (int c = threadIdx.x; c < C; c += blockDim.x) {
-        float s = 0.0f;
-        for (int r = r0; r < r1; ++r) s += (float)X[(size_t)r * C + c];
-        part[(size_t)blockIdx.x * C + c] = s;
+        float sum = 0.0f;
+        for (int q = 0; q < R; ++q) sum += red[q * C + c];
+        part[(size_t)blockIdx.x * C + c] = sum;
     }
 }
 
@@ -284,24 +304,59 @@ __global__ void k_head_bwd_data(const float* __restrict__ dh, int H, int W, int 
 }
 
 // partials of dWh[t][c] = sum_p X[p + o_t][c] dh[p] and dbh = sum_p dh[p]
+// (C a multiple of 8, at most 256).  Thread (rho, g) accumulates channels
+// [8g, 8g + 8) of all nine taps over pixels r0 + rho, r0 + rho + R, ... with
+// 16-byte loads; the R row phases are then summed tap by tap in a fixed
+// order through LDS.  part[block][t C + c], part[block][9 C] = bias.
 __global__ __launch_bounds__(256) void k_head_wgrad_part(const __bf16* __restrict__ X, int H, int W, int C,
                                                          const float* __restrict__ dh, int rows_per_block,
                                                          float* __restrict__ part) {
+    __shared__ float red[2048];
+    __shared__ float redb[256];
     const int P = H * W, r0 = blockIdx.x * rows_per_block, r1 = min(P, r0 + rows_per_block);
     const int n = 9 * C + 1;
-    for (int e = threadIdx.x; e < n; e += blockDim.x) {
-        float s = 0.0f;
-        if (e == 9 * C) {
-            for (int p = r0; p < r1; ++p) s += dh[p];
-        } else {
-            const int t = e / C, c = e % C;
-            for (int p = r0; p < r1; ++p) {
-                const int y = p / W + t / 3 - 1, x = p % W + t % 3 - 1;
-                if (y < 0 || y >= H || x < 0 || x >= W) continue;
-                s += (float)X[(size_t)(y * W + x) * C + c] * dh[p];
+    const int G = C / 8, R = 256 / G;
+    const int g = threadIdx.x % G, rho = threadIdx.x / G;
+    float acc[9][8];
+#pragma unroll
+    for (int t = 0; t < 9; ++t)
+#pragma unroll
+        for (int j = 0; j < 8; ++j) acc[t][j] = 0.0f;
+    float db = 0.0f;
+    if (rho < R) {
+        for (int p = r0 + rho; p < r1; p += R) {
+            const float w = dh[p];
+            if (g == 0) db += w;
+            const int y = p / W, x = p % W;
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
+                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                const bf16x8 v = *(const bf16x8*)(X + (size_t)(yy * W + xx) * C + 8 * g);
+#pragma unroll
+                for (int j = 0; j < 8; ++j) acc[t][j] += (float)v[j] * w;
             }
         }
-        part[(size_t)blockIdx.x * n + e] = s;
+    }
+    redb[threadIdx.x] = (rho < R && g == 0) ? db : 0.0f;
+#pragma unroll
+    for (int t = 0; t < 9; ++t) {
+        if (rho < R) {
+#pragma unroll
+            for (int j = 0; j < 8; ++j) red[rho * C + 8 * g + j] = acc[t][j];
+        }
+        __syncthreads();
+        for (int c = threadIdx.x; c < C; c += blockDim.x) {
+            float sum = 0.0f;
+            for (int q = 0; q < R; ++q) sum += red[q * C + c];
+            part[(size_t)blockIdx.x * n + t * C + c] = sum;
+        }
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+        float sum = 0.0f;
+        for (int q = 0; q < R; ++q) sum += redb[q * G];
+        part[(size_t)blockIdx.x * n + 9 * C] = sum;
     }
 }
 
