@@ -249,6 +249,10 @@ typedef struct {
                             FP64 Bi-CGSTAB takes over */
     int check_every;     /* iterations between host convergence checks (16 = graph chunk) */
     int max_inner;       /* FP32_REFINE: cap on inner iterations per refinement step (0 = none) */
+    double fp64_below;   /* FP32_MATRIX: once the residual is below fp64_below times ||b||, the
+                            products read the FP64 matrix and replacements stop (0 = never;
+                            about 1e-2: the FP32 products' error on smooth modes costs
+                            iterations near the tolerance) */
 } mcd_solve_opts;
 
 typedef struct {

@@ -439,10 +439,12 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
         (opts->guess != MCD_GUESS_ZERO && opts->guess != MCD_GUESS_CALLER))
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid options%s");
     if (opts->precision != MCD_PREC_FP64 &&
-        (!(opts->inner_tol > 0) || !(opts->inner_tol < 1) || opts->max_outer < 1 || opts->max_inner < 0))
+        (!(opts->inner_tol > 0) || !(opts->inner_tol < 1) || opts->max_outer < 1 || opts->max_inner < 0 ||
+         !(opts->fp64_below >= 0) || !(opts->fp64_below < 1)))
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid refinement options%s");
     SolveParams sp{opts->tol,       opts->max_iter,  opts->precision, opts->guess == MCD_GUESS_CALLER,
-                   opts->inner_tol, opts->max_outer, opts->check_every, opts->max_inner};
+                   opts->inner_tol, opts->max_outer, opts->check_every, opts->max_inner,
+                   opts->fp64_below};
     HIPCHK(c, launch_fill_i32(c->cnt + CNT_BAD, 1, 0, c->stream), "fill");
     SolveOut o;
     HIPCHK(c, solve_ppe_impl(c->m, c->sets[set].dev, *c->kw, rhs, neumann_f, p, sp, &o, c->cnt + CNT_BAD, c->stream),

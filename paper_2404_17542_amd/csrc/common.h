@@ -258,6 +258,7 @@ struct SolveParams {
     int max_outer;
     int check_every;
     int max_inner;
+    double fp64_below;
 };
 struct SolveOut {
     int iterations, restarts, refinements, converged;

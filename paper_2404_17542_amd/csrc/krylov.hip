@@ -1060,7 +1060,7 @@ __global__ __launch_bounds__(kKBlock) void k_true_replace(MeshDev m, const doubl
 
 // One block: the state a resume P-stage reads; done = 1 when the replaced
 // residual already meets the tolerance.
-__global__ __launch_bounds__(kKBlock) void k_replace_finish(KBufs K, double tol2, double tol2_next) {
+__global__ __launch_bounds__(kKBlock) void k_replace_finish(KBufs K, double tol2, double tol2_next, double delta2_next) {
     double tot[2];
     reduce_partials<2>(K.part[0], K, tot);
     if (threadIdx.x == 0) {
@@ -1070,6 +1070,7 @@ __global__ __launch_bounds__(kKBlock) void k_replace_finish(KBufs K, double tol2
         S->rr_max = tot[1];
         S->done = tot[1] <= tol2 * S->bb ? 1 : 0;
         S->tol2 = tol2_next;
+        S->delta2 = delta2_next;
     }
 }
 
@@ -1426,13 +1427,19 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         }
         int mode = P_FIRST, repl = 0, idle = 0, restarts = 0, fallback = 0;
         double rr_best = h.rr, tight = 1.0;
+        bool fp64_phase = false;
         while (!h.done && h.iter < sp.max_iter) {
             const int before = h.iter;
             int it = 0, done = 0;
             double rr_rec = 0.0;
-            if ((e = run_iterations<DIM, double, float>(m, w, VM, w.kb64, h.iter, sp.max_iter - h.iter, check, st,
-                                                        &it, &done, mode, &rr_rec)) != hipSuccess)
+            if (fp64_phase) {
+                if ((e = run_iterations<DIM, double, double>(m, w, V, w.kb64, h.iter, sp.max_iter - h.iter, check, st,
+                                                             &it, &done, mode, &rr_rec)) != hipSuccess)
+                    return e;
+            } else if ((e = run_iterations<DIM, double, float>(m, w, VM, w.kb64, h.iter, sp.max_iter - h.iter, check,
+                                                               st, &it, &done, mode, &rr_rec)) != hipSuccess) {
                 return e;
+            }
             if (done == 0) {          // iteration budget spent
                 h.iter = it;
                 break;
@@ -1442,7 +1449,10 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
             // a recurrence that reached the tolerance without the FP64 residual
             // doing so continues to a tighter one
             if (done == 1 && rr_rec <= tol2 * tight * bb) tight = tight * 0.25 > 1e-6 ? tight * 0.25 : 1e-6;
-            hipLaunchKernelGGL(k_replace_finish, dim3(1), dim3(kKBlock), 0, st, w.kb64, tol2, tol2 * tight);
+            // the FP64 phase needs no further replacements before the tolerance
+            const bool tail = fp64_phase || rr_rec <= sp.fp64_below * sp.fp64_below * bb;
+            hipLaunchKernelGGL(k_replace_finish, dim3(1), dim3(kKBlock), 0, st, w.kb64, tol2, tol2 * tight,
+                               tail ? 0.0 : delta2);
             if ((e = hipGetLastError()) != hipSuccess) return e;
             if ((e = hipMemcpyAsync(&w.host[0], w.kb64.st[2], sizeof(KState), hipMemcpyDeviceToHost, st)) !=
                 hipSuccess)
@@ -1459,6 +1469,9 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
                 fallback = 1;
                 break;
             }
+            // close to the tolerance the products switch to the FP64 matrix (the
+            // vectors are FP64 already, so the recursion just goes on)
+            if (tail) fp64_phase = true;
             if (done >= 2) {          // breakdown or stagnation: new recursion from the FP64 residual
                 if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 0, tol2, st, &h, delta2, tol2 * tight)) !=
                     hipSuccess)

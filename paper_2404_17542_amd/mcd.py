@@ -64,7 +64,7 @@ class UpdateInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
-                ("max_inner", C.c_int)]
+                ("max_inner", C.c_int), ("fp64_below", C.c_double)]
 
 
 class SolveInfo(C.Structure):
@@ -301,17 +301,20 @@ class Context:
 
     def solve_ppe(self, set_id, rhs, p, neumann_f=None, tol=1e-8, max_iter=20000, precision=PREC_FP64,
                   guess=GUESS_ZERO, inner_tol=None, max_outer=None, check_every=16, max_inner=None,
-                  raise_on_fail=True):
+                  fp64_below=None, raise_on_fail=True):
         if inner_tol is None:
             inner_tol = 0.03 if precision == PREC_FP32_MATRIX else 1e-2
         if max_outer is None:
             max_outer = 500 if precision == PREC_FP32_MATRIX else 40
+        if fp64_below is None:
+            fp64_below = 1e-2 if precision == PREC_FP32_MATRIX else 0.0
         o = SolveOpts()
         o.tol, o.max_iter, o.precision, o.guess = tol, int(max_iter), int(precision), int(guess)
         o.inner_tol, o.max_outer, o.check_every = inner_tol, int(max_outer), int(check_every)
         if max_inner is None:
             max_inner = max(200, int(4 * self.Nc ** (1.0 / self.dim)))
         o.max_inner = int(max_inner)
+        o.fp64_below = float(fp64_below)
         info = SolveInfo()
         N, V = self.Nc, self._vec
         st = self.lib.mcd_solve_ppe(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), C.byref(o),
