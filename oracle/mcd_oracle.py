@@ -886,7 +886,7 @@ def _bicgstab32(A32, b32, tol, max_iter):
 
 
 def solve_ppe_fp32_matrix(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess="zero",
-                          inner_tol=0.1, max_outer=500, max_iter=20000):
+                          inner_tol=0.03, max_outer=500, max_iter=20000, fp64_below=1e-2):
     """Bi-CGSTAB in FP64 whose matrix products use the FP32-rounded matrix,
     with residual replacement ("reliable updates", Sleijpen & van der Vorst
     1996).
@@ -896,12 +896,16 @@ def solve_ppe_fp32_matrix(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=F
     fallen to inner_tol times its largest norm since the last replacement,
     or to the tolerance, r := b - A64 x is recomputed with the FP64 matrix
     and the recursion continues from it (search direction and shadow residual
-    kept); the tolerance is only accepted on that FP64 residual.  A breakdown
-    restarts from the FP64 residual; more than max_outer replacements hand
-    over to FP64 Bi-CGSTAB.
+    kept); the tolerance is only accepted on that FP64 residual.  Once a
+    replacement finds the residual below fp64_below ||b||, the products use
+    the FP64 matrix and no further replacements are made before the
+    tolerance.  A breakdown restarts from the FP64 residual; more than
+    max_outer replacements hand over to FP64 Bi-CGSTAB.
     """
     A, beff, uidx = ppe_system(mesh, st, role, bc, rhs, p_in, f_neu, pin_first)
     A32 = fp32_operator(A, np.float64)
+    prod = A32
+    trigger = inner_tol
     x = p_in[uidx].astype(np.float64) if guess == "caller" else np.zeros(len(uidx))
     nb = float(np.linalg.norm(beff))
     info = SolveInfo()
@@ -917,7 +921,7 @@ def solve_ppe_fp32_matrix(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=F
             rho_new = float(rhat @ r)
             beta = (rho_new / rho) * (alpha / omega)
             p = r + beta * (p - omega * v)
-            v = A32(p)
+            v = prod(p)
             rv = float(rhat @ v)
             if rv == 0.0:
                 info.restarts += 1
@@ -925,7 +929,7 @@ def solve_ppe_fp32_matrix(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=F
                 break
             alpha = rho_new / rv
             s = r - alpha * v
-            t = A32(s)
+            t = prod(s)
             tt = float(t @ t)
             omega = float(t @ s) / tt if tt > 0 else 0.0
             x = x + alpha * p + omega * s
@@ -937,7 +941,7 @@ def solve_ppe_fp32_matrix(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=F
                 info.restarts += 1
                 r = beff - A @ x
                 break
-            if nr <= max(tol * nb, inner_tol * rmax):
+            if nr <= max(tol * nb, trigger * rmax):
                 r = beff - A @ x                     # replacement with the FP64 matrix
                 info.refinements += 1
                 rr = float(r @ r)
@@ -946,6 +950,9 @@ def solve_ppe_fp32_matrix(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=F
                 if info.refinements > max_outer:
                     fallback = True
                     break
+                if math.sqrt(rr) <= fp64_below * nb:    # FP64 products from here on
+                    prod = lambda q: A @ q
+                    trigger = 0.0
                 rmax = math.sqrt(rr)
             else:
                 rmax = max(rmax, nr)
