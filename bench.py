@@ -108,6 +108,8 @@ def main():
     ap.add_argument("--guess", choices=["warm", "zero", "learned"], default="warm",
                     help="PPE initial guess: previous pressure (default), zero, or the learned correction")
     ap.add_argument("--weights", default=None, help="network weights for --guess learned")
+    ap.add_argument("--precond", choices=["none", "jacobi"], default="none",
+                    help="none: the plain method (default); jacobi: diagonal right preconditioning")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -135,7 +137,8 @@ def main():
     prec_name, mat_b, vec_b, dtype, prec_text = PRECISIONS[args.precision]
     prec = getattr(mcd, prec_name)
     log(f"setting up {case.name}")
-    sim = GpuSim(case, precision=prec, update_info=False)
+    sim = GpuSim(case, precision=prec, update_info=False,
+                 precond=mcd.PRECOND_JACOBI if args.precond == "jacobi" else mcd.PRECOND_NONE)
     if args.guess == "learned":
         if not args.weights:
             raise SystemExit("--guess learned needs --weights (written by paper_2404_17542_amd.learned)")
@@ -190,6 +193,7 @@ def main():
            "data": "synthetic",
            "config": {"workload": workload_name(case, n_active, prec_text),
                       "dps": n_active, "precision": args.precision, "initial_guess": args.guess,
+                      "preconditioner": args.precond,
                       "ppe_iters_per_step": sum(iters) / len(iters), "max_true_rel_res": worst},
            "roofline": roofline}
     if not args.no_cpu_baseline and args.cpu_steps > 0:

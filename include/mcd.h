@@ -57,6 +57,7 @@ enum { MCD_WEIGHT_COS2 = 0, MCD_WEIGHT_GAUSS = 1 };
  *                FP64 matrix and replaced (Krylov space kept). */
 enum { MCD_PREC_FP64 = 0, MCD_PREC_FP32_REFINE = 1, MCD_PREC_FP32_MATRIX = 2 };
 enum { MCD_GUESS_ZERO = 0, MCD_GUESS_CALLER = 1 };
+enum { MCD_PRECOND_NONE = 0, MCD_PRECOND_JACOBI = 1 };
 
 #define MCD_MAX_IDS 16      /* boundary ids 1 .. 15 */
 #define MCD_MAX_BODIES 8
@@ -253,6 +254,14 @@ typedef struct {
                             products read the FP64 matrix and replacements stop (0 = never;
                             about 1e-2: the FP32 products' error on smooth modes costs
                             iterations near the tolerance) */
+    int precond;         /* MCD_PRECOND_NONE (the plain method) or MCD_PRECOND_JACOBI: right
+                            preconditioning with the diagonal D of the PPE matrix, done by
+                            solving (A D^-1) y = b and returning x = D^-1 y; the scaled matrix
+                            is formed once per solve in the workspace (FP64, plus its FP32 copy
+                            for the FP32 modes), the residual and the stopping rule stay those
+                            of A x = b, and the tolerance is confirmed on A (a miss is finished
+                            by unpreconditioned FP64 Bi-CGSTAB within max_iter).  Columns with
+                            a zero or non-finite diagonal are not scaled. */
 } mcd_solve_opts;
 
 typedef struct {

@@ -714,14 +714,21 @@ class SolveInfo:
     converged: bool = False
 
 
-def bicgstab(A, b, x0, tol, max_iter=20000, breakdown=1e-30):
-    """Unpreconditioned Bi-CGSTAB (van der Vorst, 1992), as named in Sec. 3.3.
+def bicgstab(A, b, x0, tol, max_iter=20000, breakdown=1e-30, minv=None):
+    """Bi-CGSTAB (van der Vorst, 1992), as named in Sec. 3.3; unpreconditioned
+    unless minv is given.
+
+    minv: the inverse of a diagonal right preconditioner M, as a vector
+    (Jacobi: 1/diag(A)).  Right preconditioning applies M^-1 to the search
+    directions before each product with A (v = A M^-1 p, t = A M^-1 s) and
+    updates x with the preconditioned directions, so r stays b - A x.
 
     Stopping (reading): recurrence ||r|| <= tol ||b||, then confirmed by the
     true residual b - A x; if that fails, restart from the true residual.
     A restart with r_hat = r also follows a (near-)breakdown of rho or
     r_hat.v.
     """
+    prec = (lambda q: q) if minv is None else (lambda q: minv * q)
     info = SolveInfo()
     x = x0.astype(np.float64).copy()
     nb = float(np.linalg.norm(b))
@@ -744,17 +751,19 @@ def bicgstab(A, b, x0, tol, max_iter=20000, breakdown=1e-30):
                 break
             beta = (rho_new / rho) * (alpha / omega)
             p = r + beta * (p - omega * v)
-            v = A @ p
+            ph = prec(p)
+            v = A @ ph
             rv = float(rhat @ v)
             if abs(rv) < breakdown * float(np.linalg.norm(rhat) * np.linalg.norm(v)):
                 restart = True
                 break
             alpha = rho_new / rv
             s = r - alpha * v
-            t = A @ s
+            sh = prec(s)
+            t = A @ sh
             tt = float(t @ t)
             omega = float(t @ s) / tt if tt > 0 else 0.0
-            x = x + alpha * p + omega * s
+            x = x + alpha * ph + omega * sh
             r = s - omega * t
             rho = rho_new
             info.iterations += 1
@@ -773,11 +782,27 @@ def bicgstab(A, b, x0, tol, max_iter=20000, breakdown=1e-30):
     return x, info
 
 
-def solve_ppe(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess="zero", max_iter=20000):
-    """Solve the PPE; p_in carries Dirichlet values (and the guess for 'caller')."""
+def jacobi_inverse_diagonal(A):
+    """1/diag(A) for the Jacobi preconditioner; rows whose diagonal is zero or
+    not finite are left unscaled (1)."""
+    d = A.diagonal().astype(np.float64)
+    ok = (d != 0.0) & np.isfinite(d)
+    out = np.ones_like(d)
+    out[ok] = 1.0 / d[ok]
+    return out
+
+
+def solve_ppe(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess="zero", max_iter=20000,
+              precond="none"):
+    """Solve the PPE; p_in carries Dirichlet values (and the guess for 'caller').
+    precond: 'none' (the plain method) or 'jacobi' (right preconditioning with
+    the diagonal of the PPE matrix)."""
     A, beff, uidx = ppe_system(mesh, st, role, bc, rhs, p_in, f_neu, pin_first)
     x0 = p_in[uidx] if guess == "caller" else np.zeros(len(uidx))
-    x, info = bicgstab(A, beff, x0, tol, max_iter)
+    if precond not in ("none", "jacobi"):
+        raise ValueError(f"unknown preconditioner {precond!r}")
+    minv = jacobi_inverse_diagonal(A) if precond == "jacobi" else None
+    x, info = bicgstab(A, beff, x0, tol, max_iter, minv=minv)
     p = p_in.copy()
     p[uidx] = x
     return p, info, (A, beff, uidx)

@@ -436,7 +436,8 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
     if (!(opts->tol > 0) || opts->max_iter < 1 ||
         (opts->precision != MCD_PREC_FP64 && opts->precision != MCD_PREC_FP32_REFINE &&
          opts->precision != MCD_PREC_FP32_MATRIX) ||
-        (opts->guess != MCD_GUESS_ZERO && opts->guess != MCD_GUESS_CALLER))
+        (opts->guess != MCD_GUESS_ZERO && opts->guess != MCD_GUESS_CALLER) ||
+        (opts->precond != MCD_PRECOND_NONE && opts->precond != MCD_PRECOND_JACOBI))
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid options%s");
     if (opts->precision != MCD_PREC_FP64 &&
         (!(opts->inner_tol > 0) || !(opts->inner_tol < 1) || opts->max_outer < 1 || opts->max_inner < 0 ||
@@ -444,7 +445,7 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid refinement options%s");
     SolveParams sp{opts->tol,       opts->max_iter,  opts->precision, opts->guess == MCD_GUESS_CALLER,
                    opts->inner_tol, opts->max_outer, opts->check_every, opts->max_inner,
-                   opts->fp64_below};
+                   opts->fp64_below, opts->precond};
     HIPCHK(c, launch_fill_i32(c->cnt + CNT_BAD, 1, 0, c->stream), "fill");
     SolveOut o;
     HIPCHK(c, solve_ppe_impl(c->m, c->sets[set].dev, *c->kw, rhs, neumann_f, p, sp, &o, c->cnt + CNT_BAD, c->stream),

@@ -259,6 +259,7 @@ struct SolveParams {
     int check_every;
     int max_inner;
     double fp64_below;
+    int precond;
 };
 struct SolveOut {
     int iterations, restarts, refinements, converged;

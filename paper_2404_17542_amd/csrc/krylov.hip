@@ -1100,6 +1100,65 @@ __global__ void k_refine(int Nc, const float* __restrict__ d, double inv_scale, 
         x[c] = x[c] + (double)d[c] * inv_scale;
 }
 
+// Jacobi (diagonal) right preconditioning of Bi-CGSTAB (Sec. 3.3 names the
+// solver; the preconditioner is the comparator of the learned guess).  With
+// D = diag(A), Bi-CGSTAB on (A D^-1) y = b followed by x = D^-1 y performs the
+// iterations of right-preconditioned Bi-CGSTAB (v = A D^-1 p, t = A D^-1 s)
+// and its residual b - (A D^-1) y is b - A x, so the stopping rule is
+// unchanged.  The column scaling is done once per solve.
+//
+// dinv := 1/diag at unknown rows (1 where the diagonal is zero or not
+// finite, and at known rows); x := D x (the initial guess in y).
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_jacobi_diag(MeshDev m, const double* __restrict__ A,
+                                                        const uint8_t* __restrict__ unknown,
+                                                        double* __restrict__ dinv, double* __restrict__ x) {
+    constexpr int CEN = Dims<DIM>::CEN;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        const double d = unknown[c] ? A[(size_t)CEN * m.Nc + c] : 0.0;
+        const bool ok = d != 0.0 && isfinite(d);
+        dinv[c] = ok ? 1.0 / d : 1.0;
+        if (ok) x[c] = x[c] * d;
+    }
+}
+
+// J[s][c] = A[s][c] dinv[j(c, s)] (FP64), and its FP32 copy in difference form
+// (centre slot = row sum of the scaled row), as the MLS build stores A.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_jacobi_matrix(MeshDev m, const double* __restrict__ A,
+                                                          const double* __restrict__ dinv, double* __restrict__ J,
+                                                          float* __restrict__ J32) {
+    constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
+    const size_t Nc = (size_t)m.Nc;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        int ijk[3];
+        cell_ijk(m, c, ijk);
+        double off_sum = 0.0, diag = 0.0;
+        for (int s = 0; s < S; ++s) {
+            const double a = A[(size_t)s * Nc + c];
+            double v = 0.0;
+            int j;
+            double sh[3];
+            if (a != 0.0 && neighbour<DIM>(m, ijk, s, j, sh)) v = a * dinv[j];
+            J[(size_t)s * Nc + c] = v;
+            if (s == CEN) {
+                diag = v;
+            } else {
+                J32[(size_t)s * Nc + c] = (float)v;
+                off_sum += v;
+            }
+        }
+        J32[(size_t)CEN * Nc + c] = (float)(diag + off_sum);
+    }
+}
+
+// x := D^-1 y at unknown rows.
+__global__ void k_jacobi_unscale(int Nc, const uint8_t* __restrict__ unknown, const double* __restrict__ dinv,
+                                 double* __restrict__ x) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < Nc; c += gridDim.x * blockDim.x)
+        if (unknown[c]) x[c] = x[c] * dinv[c];
+}
+
 // ---------------------------------------------------------------------------
 // Host side
 // ---------------------------------------------------------------------------
@@ -1122,6 +1181,9 @@ struct KrylovWork {
     double* beff;
     float* b32;
     double* xsave;         // iterate before a refinement step
+    double* dinv;          // [Nc] inverse diagonal (Jacobi)
+    double* jac64;         // [S][Nc] column-scaled matrix A D^-1 (Jacobi)
+    float* jac32;          // [S][Nc] its FP32 copy in difference form
     int* bad_host;         // pinned
     // replayed chunks of kGraphIters iterations (per operator and precision)
     static constexpr int kGraphIters = 16;
@@ -1377,8 +1439,20 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     *out = SolveOut{};
     if (*w.bad_host) return hipSuccess;     // caller reports the non-finite input
+    // the operator the Krylov iterations see: A, or A D^-1 with Jacobi
+    const double* A64 = set.amat;
+    const float* A32 = set.amat32;
+    const bool jacobi = sp.precond == MCD_PRECOND_JACOBI;
+    if (jacobi) {
+        hipLaunchKernelGGL(k_jacobi_diag<DIM>, dim3(g), dim3(kBlock), 0, st, m, set.amat, set.unknown, w.dinv,
+                           w.v64.x);
+        hipLaunchKernelGGL(k_jacobi_matrix<DIM>, dim3(g), dim3(kBlock), 0, st, m, set.amat, w.dinv, w.jac64, w.jac32);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        A64 = w.jac64;
+        A32 = w.jac32;
+    }
     KVec<double> V = w.v64;
-    V.A = set.amat;
+    V.A = A64;
     V.b = w.beff;
     const int check = sp.check_every > 0 ? sp.check_every : 8;
     if (sp.precision == MCD_PREC_FP64) {
@@ -1414,7 +1488,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         VM.p[1] = V.p[1];
         VM.v[0] = V.v[0];
         VM.v[1] = V.v[1];
-        VM.A = set.amat32;
+        VM.A = A32;
         VM.b = w.beff;
         const double tol2 = sp.tol * sp.tol, delta2 = sp.inner_tol * sp.inner_tol;
         KState h;
@@ -1444,7 +1518,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
                 h.iter = it;
                 break;
             }
-            hipLaunchKernelGGL(k_true_replace<DIM>, dim3(w.kb64.nblk), dim3(kKBlock), 0, st, m, set.amat,
+            hipLaunchKernelGGL(k_true_replace<DIM>, dim3(w.kb64.nblk), dim3(kKBlock), 0, st, m, A64,
                                set.unknown, w.beff, VM, w.kb64);
             // a recurrence that reached the tolerance without the FP64 residual
             // doing so continues to a tighter one
@@ -1512,7 +1586,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         // solve finishes with FP64 Bi-CGSTAB from the current iterate, so the
         // tolerance is always met on the FP64 operator.
         KVec<float> V32 = w.v32;
-        V32.A = set.amat32;
+        V32.A = A32;
         KState h;
         if ((e = kinit<DIM, double, double>(m, w, V, w.kb64, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
         const double bb = h.bb;
@@ -1571,6 +1645,30 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         out->converged = h.done == 1 || bb == 0.0;
         out->rel = bb > 0 ? sqrt(h.rr / bb) : 0.0;
         out->bnorm = sqrt(bb);
+    }
+    if (jacobi) {
+        // back to x = D^-1 y; the tolerance is confirmed on A itself (the
+        // scaled product differs from A x by rounding), and a miss is finished
+        // by unpreconditioned FP64 Bi-CGSTAB within the iteration budget
+        hipLaunchKernelGGL(k_jacobi_unscale, dim3(g), dim3(kBlock), 0, st, m.Nc, set.unknown, w.dinv, V.x);
+        KVec<double> V0 = V;
+        V0.A = set.amat;
+        if (out->bnorm > 0.0) {
+            KState h;
+            if ((e = kinit<DIM, double, double>(m, w, V0, w.kb64, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
+            double rel = sqrt(h.rr / h.bb);
+            int conv = h.done == 1;
+            if (!conv && out->iterations < sp.max_iter) {
+                int it = 0, rst = 0;
+                if ((e = bicgstab<DIM, double, double>(m, w, V0, w.kb64, sp.tol, sp.max_iter - out->iterations, check,
+                                                       st, &it, &rst, &rel, &conv)) != hipSuccess)
+                    return e;
+                out->iterations += it;
+                out->restarts += rst + 1;
+            }
+            out->rel = rel;
+            out->converged = conv ? 1 : 0;
+        }
     }
     hipLaunchKernelGGL(k_writeback, dim3(g), dim3(kBlock), 0, st, m.Nc, set.unknown, V.x, p);
     return hipGetLastError();
@@ -1674,6 +1772,10 @@ hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     if ((e = hipMalloc((void**)&w->beff, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->b32, (size_t)Nc * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->xsave, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
+    const size_t S = m.dim == 3 ? 27 : 9;
+    if ((e = hipMalloc((void**)&w->dinv, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&w->jac64, S * Nc * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&w->jac32, S * Nc * sizeof(float))) != hipSuccess) return e;
     w->v32.b = w->b32;
     if ((e = hipHostMalloc((void**)&w->bad_host, sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
     if ((e = hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking)) != hipSuccess) return e;
@@ -1721,6 +1823,9 @@ void krylov_free(KrylovWork* w) {
     if (w->beff) (void)hipFree(w->beff);
     if (w->b32) (void)hipFree(w->b32);
     if (w->xsave) (void)hipFree(w->xsave);
+    if (w->dinv) (void)hipFree(w->dinv);
+    if (w->jac64) (void)hipFree(w->jac64);
+    if (w->jac32) (void)hipFree(w->jac32);
     if (w->bad_host) (void)hipHostFree(w->bad_host);
     for (int i = 0; i < w->ngraphs; ++i) (void)hipGraphExecDestroy(w->graphs[i].exec);
     if (w->join) (void)hipEventDestroy(w->join);

@@ -130,8 +130,9 @@ def evaluate(model, seeds, n, n_spin, n_eval, modes=("zero", "warm", "learned"),
              log=print):
     """Held-out trajectories: at every evaluated step each mode solves the
     same PPE from its own guess; the trajectory advances with the warm-start
-    solution.  Returns per-mode iteration counts, initial relative residuals
-    and solve times (ms, guess included)."""
+    solution.  A mode is a guess ('zero', 'warm', 'learned'), optionally with
+    '+jacobi' for the Jacobi-preconditioned solve.  Returns per-mode iteration
+    counts, initial relative residuals and solve times (ms, guess included)."""
     if "warm" not in modes:
         raise ValueError("evaluation advances with the warm-start solution; include 'warm'")
     res = {m: {"iters": [], "rel0": [], "ms": []} for m in modes}
@@ -148,11 +149,13 @@ def evaluate(model, seeds, n, n_spin, n_eval, modes=("zero", "warm", "learned"),
             p_k = sim.P.clone()
             order = [m for m in modes if m != "warm"] + (["warm"] if "warm" in modes else [])
             for mode in order:
+                base, _, pre = mode.partition("+")
+                precond = {"": M.PRECOND_NONE, "jacobi": M.PRECOND_JACOBI}[pre]
                 sim.P.copy_(p_k)
                 torch.cuda.synchronize()
                 t0 = time.perf_counter()
-                flag = sim.initial_guess(pset, mode)
-                info = sim.solve(pset, flag)
+                flag = sim.initial_guess(pset, base)
+                info = sim.solve(pset, flag, precond)
                 torch.cuda.synchronize()
                 ms = (time.perf_counter() - t0) * 1e3
                 if flag == M.GUESS_ZERO:
@@ -160,7 +163,7 @@ def evaluate(model, seeds, n, n_spin, n_eval, modes=("zero", "warm", "learned"),
                 else:
                     # residual of the guess itself: re-form it from P^k (cheap)
                     g = p_k.clone()
-                    if mode == "learned":
+                    if base == "learned":
                         sim.ctx.ppe_residual(pset, sim.rhs, g, r, sim.fP)
                         model.infer(r, g, sim.role, case.bc_pressure, g)
                     nr, nb = sim.ctx.ppe_residual(pset, sim.rhs, g, r, sim.fP)
@@ -241,6 +244,8 @@ def main(argv=None):
     ap.add_argument("--out", default=None, help="weights file (.npz)")
     ap.add_argument("--weights", default=None, help="skip training: evaluate this weights file")
     ap.add_argument("--json", default=None, help="write the summary here")
+    ap.add_argument("--modes", default="zero,warm,learned",
+                    help="evaluated starts, comma-separated; '+jacobi' adds the Jacobi preconditioner")
     a = ap.parse_args(argv)
     if not torch.cuda.is_available():
         raise SystemExit("the learned guess runs on the GPU only")
@@ -272,7 +277,7 @@ def main(argv=None):
         if a.out:
             save_weights(a.out, model, scale, a.n, {"train_seeds": a.train_seeds, "epochs": a.epochs, "lr": a.lr})
         del data, train_set, hold
-    res = evaluate(model, _seeds(a.test_seeds), a.n, a.spin, a.eval_steps)
+    res = evaluate(model, _seeds(a.test_seeds), a.n, a.spin, a.eval_steps, modes=tuple(a.modes.split(",")))
     summary["eval"] = summarize(res)
     print(json.dumps(summary), flush=True)
     if a.json:

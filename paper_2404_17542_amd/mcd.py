@@ -23,6 +23,7 @@ BC_DIRICHLET, BC_NEUMANN = 0, 1
 WEIGHT_COS2, WEIGHT_GAUSS = 0, 1
 PREC_FP64, PREC_FP32_REFINE, PREC_FP32_MATRIX = 0, 1, 2
 GUESS_ZERO, GUESS_CALLER = 0, 1
+PRECOND_NONE, PRECOND_JACOBI = 0, 1
 OP_PHI, OP_GRAD, OP_LAP, OP_DIV, OP_SHIFT = 0, 1, 2, 3, 4
 MAX_IDS = 16
 MAX_BODIES = 8
@@ -64,7 +65,7 @@ class UpdateInfo(C.Structure):
 class SolveOpts(C.Structure):
     _fields_ = [("tol", C.c_double), ("max_iter", C.c_int), ("precision", C.c_int), ("guess", C.c_int),
                 ("inner_tol", C.c_double), ("max_outer", C.c_int), ("check_every", C.c_int),
-                ("max_inner", C.c_int), ("fp64_below", C.c_double)]
+                ("max_inner", C.c_int), ("fp64_below", C.c_double), ("precond", C.c_int)]
 
 
 class SolveInfo(C.Structure):
@@ -301,7 +302,7 @@ class Context:
 
     def solve_ppe(self, set_id, rhs, p, neumann_f=None, tol=1e-8, max_iter=20000, precision=PREC_FP64,
                   guess=GUESS_ZERO, inner_tol=None, max_outer=None, check_every=16, max_inner=None,
-                  fp64_below=None, raise_on_fail=True):
+                  fp64_below=None, precond=PRECOND_NONE, raise_on_fail=True):
         if inner_tol is None:
             inner_tol = 0.03 if precision == PREC_FP32_MATRIX else 1e-2
         if max_outer is None:
@@ -315,6 +316,7 @@ class Context:
             max_inner = max(200, int(4 * self.Nc ** (1.0 / self.dim)))
         o.max_inner = int(max_inner)
         o.fp64_below = float(fp64_below)
+        o.precond = int(precond)
         info = SolveInfo()
         N, V = self.Nc, self._vec
         st = self.lib.mcd_solve_ppe(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), C.byref(o),

@@ -26,9 +26,10 @@ SET_P = 2
 
 class GpuSim:
     def __init__(self, case, precision=M.PREC_FP64, device="cuda", check_every=16, update_info=True,
-                 guess="warm", model=None):
+                 guess="warm", model=None, precond=M.PRECOND_NONE):
         self.case = case
         self.guess = guess
+        self.precond = precond
         self.model = model
         self.resid = None
         self.device = device
@@ -148,9 +149,10 @@ class GpuSim:
         self.log.append(rec)
         return rec
 
-    def solve(self, pset, guess=M.GUESS_CALLER):
+    def solve(self, pset, guess=M.GUESS_CALLER, precond=None):
         return self.ctx.solve_ppe(pset, self.rhs, self.P, self.fP, tol=self.case.tol, precision=self.precision,
-                                  guess=guess, check_every=self.check_every)
+                                  guess=guess, check_every=self.check_every,
+                                  precond=self.precond if precond is None else precond)
 
     def step(self):
         pset, bodies_new, upd = self.prepare()

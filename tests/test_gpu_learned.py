@@ -2,8 +2,9 @@
 
 A U-Net is trained on the GPU (libmcd's BF16-MFMA kernels) on PPE solves of
 four seeded cylinder trajectories (128^2 mesh), then every PPE of a held-out
-trajectory is solved three times to the same tolerance: from zero, from the
-previous pressure (warm start) and from the learned guess.
+trajectory is solved to the same tolerance from zero, from the previous
+pressure (warm start) and from the learned guess, and from zero and the warm
+start with the Jacobi preconditioner (the classical comparator).
 """
 import numpy as np
 import pytest
@@ -38,11 +39,13 @@ def test_learned_guess_gain_on_held_out_trajectory(L):
     # loss 1 is the warm start itself (relative squared error of the correction)
     assert before == pytest.approx(1.0)
     assert after < 0.7, after
-    res = L.evaluate(model, [2000], n, n_spin=10, n_eval=8, log=lambda *_: None)
+    modes = ("zero", "zero+jacobi", "warm+jacobi", "learned", "warm")
+    res = L.evaluate(model, [2000], n, n_spin=10, n_eval=8, modes=modes, log=lambda *_: None)
     s = L.summarize(res)
     msg = str(s)
+    print(msg)
     # every solve reaches the tolerance whatever the guess
-    assert all(np.isfinite(v) for m in ("zero", "warm", "learned") for v in res[m]["iters"]), msg
+    assert all(np.isfinite(v) for m in modes for v in res[m]["iters"]), msg
     # the network's guess has a smaller initial residual than the warm start ...
     assert s["learned"]["mean_rel0"] < 0.6 * s["warm"]["mean_rel0"], msg
     # ... and needs fewer Bi-CGSTAB iterations than the zero start; against

@@ -36,6 +36,45 @@ def test_bicgstab_matches_dense_solve(n):
     np.testing.assert_allclose(lap[uidx], rhs[uidx], rtol=0, atol=1e-9 * np.abs(rhs).max())
 
 
+def test_jacobi_on_a_diagonal_system_takes_one_iteration():
+    """Right preconditioning with M = diag(A) makes A M^-1 = I on a diagonal
+    matrix: one iteration gives x = b / d exactly (to rounding), while the
+    plain method needs several (distinct eigenvalues)."""
+    import scipy.sparse as sp
+    rng = np.random.Generator(np.random.PCG64(11))
+    d = rng.uniform(0.5, 50.0, 40)
+    A = sp.diags(d).tocsr()
+    b = rng.standard_normal(40)
+    x, info = O.bicgstab(A, b, np.zeros(40), 1e-12, minv=O.jacobi_inverse_diagonal(A))
+    assert info.iterations == 1
+    np.testing.assert_allclose(x, b / d, rtol=1e-14)
+    _, plain = O.bicgstab(A, b, np.zeros(40), 1e-12)
+    assert plain.iterations > 3
+
+
+def test_jacobi_is_the_column_scaled_plain_solve():
+    """Bi-CGSTAB right-preconditioned by D equals plain Bi-CGSTAB on A D^-1
+    with x = D^-1 y, iteration for iteration (up to rounding, which Bi-CGSTAB
+    amplifies after a few dozen iterations; compared over the first 12), and
+    the preconditioned PPE solve reaches the dense solution."""
+    case, m, pos, role, st = _c0(32)
+    rhs = inputs.manufactured_rhs(pos)
+    g = np.where(role == O.INNER, 0.0, inputs.manufactured_pressure(pos))
+    p, info, (A, b, uidx) = O.solve_ppe(m, st, role, case.bc_pressure, rhs, g, None, 1e-10, precond="jacobi")
+    assert info.converged and info.true_rel_residual <= 1e-10
+    dense = np.linalg.solve(A.toarray(), b)
+    np.testing.assert_allclose(p[uidx], dense, rtol=0, atol=1e-8 * np.abs(dense).max())
+    minv = O.jacobi_inverse_diagonal(A)
+    assert np.all(minv < 0)          # the MLS Laplacian's diagonal is negative
+    import scipy.sparse as sp
+    x12, _ = O.bicgstab(A, b, np.zeros(len(b)), 1e-30, max_iter=12, minv=minv)
+    y12, _ = O.bicgstab((A @ sp.diags(minv)).tocsr(), b, np.zeros(len(b)), 1e-30, max_iter=12)
+    np.testing.assert_allclose(minv * y12, x12, rtol=0, atol=1e-12 * np.abs(x12).max())
+    # a left-preconditioned or unpreconditioned loop takes other iterates
+    xp, _ = O.bicgstab(A, b, np.zeros(len(b)), 1e-30, max_iter=12)
+    assert np.abs(xp - x12).max() > 1e-6 * np.abs(x12).max()
+
+
 def test_manufactured_convergence_order():
     """p = sin 2 pi x sin 2 pi y: the RMS error of the jittered quadratic MLS
     Poisson solve falls at order >= 1.5 between the two finest meshes."""
