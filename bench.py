@@ -110,6 +110,8 @@ def main():
     ap.add_argument("--weights", default=None, help="network weights for --guess learned")
     ap.add_argument("--precond", choices=["none", "jacobi"], default="none",
                     help="none: the plain method (default); jacobi: diagonal right preconditioning")
+    ap.add_argument("--no-autotune", action="store_true",
+                    help="keep the default stage-kernel shape instead of timing the candidates after warm-up")
     ap.add_argument("--cpu-steps", type=int, default=4)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-kernel-timing", action="store_true")
@@ -149,6 +151,11 @@ def main():
         sim.step()
     torch.cuda.synchronize()
     log(f"warm-up done ({args.warmup} steps)")
+    tune = None
+    if not args.no_autotune:
+        tune = sim.ctx.autotune(sim.tuning_set())
+        log(f"autotuned stage-kernel shape: {tune['shape']} from "
+            + ", ".join(f"{c['grid']}x{c['depth']}: {c['us_per_iter']:.2f} us" for c in tune["candidates"]))
     n_active = sim.n_active()
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -194,6 +201,7 @@ def main():
            "config": {"workload": workload_name(case, n_active, prec_text),
                       "dps": n_active, "precision": args.precision, "initial_guess": args.guess,
                       "preconditioner": args.precond,
+                      "stage_shape": sim.ctx.get_shape(), "autotuned": tune is not None,
                       "ppe_iters_per_step": sum(iters) / len(iters), "max_true_rel_res": worst},
            "roofline": roofline}
     if not args.no_cpu_baseline and args.cpu_steps > 0:

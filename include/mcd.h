@@ -342,6 +342,43 @@ mcd_status mcd_model_train_step(mcd_model* model, const double* resid, const dou
                                 const int8_t* role, const mcd_bc_table* bc, double lr, double* loss);
 
 /* ---------------------------------------------------------------------
+ * Launch shape of the Krylov stage kernels and its autotuner
+ *
+ * The stage kernels of mcd_solve_ppe (Bi-CGSTAB, Sec. 3.3) give each block
+ * of 512 threads a contiguous run of 64 x 8-cell tiles (2D) or of
+ * 64 x 8 x depth-cell bricks marched plane by plane (3D).  The shape is the
+ * block count `grid` (1..512; clipped to the number of tiles) and, in 3D, the
+ * brick depth in planes (1..n_z; 1 in 2D).  Default: grid 512, depth 8.  The
+ * shape changes the summation order of the dot products (results stay
+ * within the solve's tolerance; for one shape they are run-to-run
+ * bit-identical).
+ * ------------------------------------------------------------------- */
+
+#define MCD_TUNE_MAX 32
+typedef struct {
+    int n;                           /* candidates timed */
+    int grid[MCD_TUNE_MAX];          /* block count asked for */
+    int depth[MCD_TUNE_MAX];         /* 3D brick depth (1 in 2D) */
+    double us_per_iter[MCD_TUNE_MAX];/* FP64 P- + S-stage microseconds per iteration (best of two
+                                        runs); < 0: rejected (the timing recursion stopped early) */
+    int chosen;                      /* index now in use (-1: none usable, shape unchanged) */
+} mcd_tuning;
+
+/* Times every candidate shape on the FP64 operator of built set `set`
+ * (iters >= 1 iterations of a problem with b = 1 at the unknown rows, after
+ * two untimed ones, each candidate twice), then applies the fastest; the
+ * default shape is kept when it is within 2 % of the fastest.  Uses the
+ * solver workspace (the next solve overwrites it) and synchronises.  out:
+ * host. */
+mcd_status mcd_autotune(mcd_ctx* ctx, int set, int iters, mcd_tuning* out);
+/* Applies a shape (e.g. one found earlier by mcd_autotune); MCD_ERR_ARG when
+ * outside the limits above. */
+mcd_status mcd_set_shape(mcd_ctx* ctx, int grid, int depth);
+/* The shape in use: block count asked for, brick depth, and the blocks
+ * launched (grid clipped to the tiles).  Host pointers. */
+mcd_status mcd_get_shape(mcd_ctx* ctx, int* grid, int* depth, int* blocks);
+
+/* ---------------------------------------------------------------------
  * Kernel timing (measurement aid)
  * ------------------------------------------------------------------- */
 

@@ -585,6 +585,34 @@ mcd_status mcd_model_train_step(mcd_model* md, const double* rhs, const double* 
     return MCD_OK;
 }
 
+mcd_status mcd_autotune(mcd_ctx* c, int set, int iters, mcd_tuning* out) {
+    if (!c) return MCD_ERR_ARG;
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_autotune: set not built%s");
+    if (!out || iters < 1 || iters > 100000) return fail(c, MCD_ERR_ARG, "mcd_autotune: invalid arguments%s");
+    *out = mcd_tuning{};
+    out->chosen = -1;
+    HIPCHK(c, hipStreamSynchronize(c->stream), "autotune");
+    HIPCHK(c, krylov_autotune(c->m, c->sets[set].dev, *c->kw, iters, MCD_TUNE_MAX, &out->n, out->grid, out->depth,
+                              out->us_per_iter, &out->chosen),
+           "autotune");
+    return MCD_OK;
+}
+
+mcd_status mcd_set_shape(mcd_ctx* c, int grid, int depth) {
+    if (!c) return MCD_ERR_ARG;
+    const hipError_t e = krylov_set_shape(c->m, *c->kw, grid, depth);
+    if (e == hipErrorInvalidValue) return fail(c, MCD_ERR_ARG, "mcd_set_shape: shape outside the limits%s");
+    HIPCHK(c, e, "set_shape");
+    return MCD_OK;
+}
+
+mcd_status mcd_get_shape(mcd_ctx* c, int* grid, int* depth, int* blocks) {
+    if (!c) return MCD_ERR_ARG;
+    if (!grid || !depth || !blocks) return fail(c, MCD_ERR_ARG, "mcd_get_shape: null argument%s");
+    krylov_get_shape(*c->kw, grid, depth, blocks);
+    return MCD_OK;
+}
+
 mcd_status mcd_profile(mcd_ctx* c, int enable) {
     if (!c) return MCD_ERR_ARG;
     HIPCHK(c, krylov_profile(c->kw, enable ? 1 : 0), "mcd_profile");

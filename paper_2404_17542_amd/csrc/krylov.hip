@@ -43,13 +43,15 @@ struct KState {
 // (r given, x already current, beta from the replaced rho).
 enum { P_NORMAL = 0, P_FIRST = 1, P_RESUME = 2 };
 
-// Fixed launch shape of the stage kernels: 512 blocks x 512 threads
-// (16 waves per CU on 256 CUs); per-block partial sums of one stage are
-// reduced by every block of the next stage in a fixed order, so no grid
-// barrier, fence or atomic is needed and every block derives bitwise the
-// same scalars.
+// Launch shape of the stage kernels: blocks of 512 threads, at most 512 of
+// them (16 waves per CU on 256 CUs; by default exactly min(512, tiles));
+// per-block partial sums of one stage are reduced by every block of the next
+// stage in a fixed order, so no grid barrier, fence or atomic is needed and
+// every block derives bitwise the same scalars.  The block count and the 3D
+// brick depth are run-time parameters (chosen by the autotuner).
 constexpr int kKBlock = 512;
 constexpr int kKGrid = 512;
+constexpr int kDefaultDepth = 8;
 
 template <typename T, typename TA = T>
 struct KVec {
@@ -67,6 +69,7 @@ struct KBufs {
     int nty;             // tile rows per plane (3D bricks)
     int ntiles;          // tiles (2D) or bricks (3D) of the mesh
     int tpb;             // tiles or bricks per block
+    int tz;              // planes per brick (3D)
 };
 
 // Sum of A[s][c] * val(j) over the stencil slots of cell c.  Interior cells
@@ -666,14 +669,12 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
 
 // ---------------------------------------------------------------------------
 // 3D stage kernels (2.5D).  A block of 512 threads owns a 64 x 8 column of
-// cells and marches it over TZ3 planes (a brick).  The operand of the
+// cells and marches it over K.tz planes (a brick).  The operand of the
 // 27-point product is formed once per plane of the brick plus one halo
 // plane below and above, into a ring of three (66 x 10) planes in LDS, so the
 // product reads LDS only; the owner of a cell does its element-wise updates
 // when its plane is formed.
 // ---------------------------------------------------------------------------
-
-constexpr int TZ3 = 8;
 
 // cell index of mesh position (gx, gy, gz) with periodic wrap; -1 outside
 __device__ __forceinline__ int halo_cell3(const MeshDev& m, int gx, int gy, int gz) {
@@ -691,7 +692,7 @@ __device__ __forceinline__ int halo_cell3(const MeshDev& m, int gx, int gy, int 
 __device__ __forceinline__ void brick_origin(const KBufs& K, int brick, int& tx0, int& ty0, int& tz0) {
     tx0 = (brick % K.ntx) * TX;
     ty0 = ((brick / K.ntx) % K.nty) * TY;
-    tz0 = (brick / (K.ntx * K.nty)) * TZ3;
+    tz0 = (brick / (K.ntx * K.nty)) * K.tz;
 }
 
 // Matrix row of cell c (27 slot planes) into registers.
@@ -734,7 +735,7 @@ __device__ __forceinline__ void march_bricks(const MeshDev& m, const KBufs& K, F
     for (int k = 0; k < run.count; ++k) {
         int tx0, ty0, tz0;
         brick_origin(K, run.first + k, tx0, ty0, tz0);
-        const int tz1 = min(tz0 + TZ3, m.n[2]);
+        const int tz1 = min(tz0 + K.tz, m.n[2]);
         const int gx = tx0 + lx, gy = ty0 + ly;
         const bool inside = gx < m.n[0] && gy < m.n[1];
         form(tx0, ty0, tz0 - 1, 0, false);
@@ -1192,6 +1193,7 @@ struct KrylovWork {
     GraphEntry graphs[kMaxGraphs];
     int ngraphs = 0;
     int use_graphs = 1;
+    int grid_req = kKGrid;   // block count asked for (the shape clips it to the tiles)
     // optional timing of the stage kernels: start/stop events stamped by the
     // kernel dispatch itself (hipExtLaunchKernelGGL)
     int profile = 0;
@@ -1737,26 +1739,161 @@ hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w,
     return hipSuccess;
 }
 
+// Stage-kernel shape: 64 x 8 tiles (2D) or 64 x 8 x depth bricks (3D), at
+// most `grid` (<= kKGrid) blocks, each looping over a contiguous run of
+// tiles.  Returns false for a shape outside those limits.
+static bool shape_of(const MeshDev& m, int grid, int depth, KBufs& K) {
+    if (grid < 1 || grid > kKGrid || (m.dim == 3 && (depth < 1 || depth > m.n[2])) || (m.dim == 2 && depth != 1))
+        return false;
+    const int ntx = (m.n[0] + TX - 1) / TX, nty = (m.n[1] + TY - 1) / TY;
+    const int ntiles = ntx * nty * (m.dim == 3 ? (m.n[2] + depth - 1) / depth : 1);
+    const int nblk = ntiles < grid ? ntiles : grid;
+    K.nblk = nblk;
+    K.ntx = ntx;
+    K.nty = nty;
+    K.ntiles = ntiles;
+    K.tpb = (ntiles + nblk - 1) / nblk;
+    K.tz = m.dim == 3 ? depth : 1;
+    return true;
+}
+
+// Applies a stage-kernel shape to both precisions; captured chunk graphs
+// hold the old one, so they are dropped.
+hipError_t krylov_set_shape(const MeshDev& m, KrylovWork& w, int grid, int depth) {
+    KBufs K = w.kb64;
+    if (!shape_of(m, grid, depth, K)) return hipErrorInvalidValue;
+    hipError_t e = hipStreamSynchronize(w.st);
+    if (e != hipSuccess) return e;
+    for (int i = 0; i < w.ngraphs; ++i) (void)hipGraphExecDestroy(w.graphs[i].exec);
+    w.ngraphs = 0;
+    for (KBufs* Q : {&w.kb64, &w.kb32}) {
+        Q->nblk = K.nblk;
+        Q->ntx = K.ntx;
+        Q->nty = K.nty;
+        Q->ntiles = K.ntiles;
+        Q->tpb = K.tpb;
+        Q->tz = K.tz;
+    }
+    w.grid_req = grid;
+    return hipSuccess;
+}
+
+void krylov_get_shape(const KrylovWork& w, int* grid, int* depth, int* blocks) {
+    *grid = w.grid_req;
+    *depth = w.kb64.tz;
+    *blocks = w.kb64.nblk;
+}
+
+// b := 1 and x := 0 at unknown rows (0 elsewhere): the timing problem.
+__global__ void k_tune_problem(int Nc, const uint8_t* __restrict__ unknown, double* __restrict__ b,
+                               double* __restrict__ x) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < Nc; c += gridDim.x * blockDim.x) {
+        b[c] = unknown[c] ? 1.0 : 0.0;
+        x[c] = 0.0;
+    }
+}
+
+// Times `iters` FP64 iterations (after two untimed ones) of the stage kernels
+// in the current shape on the set's operator; *ok = 0 when the recursion
+// stopped early (a breakdown would make later launches return at once).
+template <int DIM>
+static hipError_t time_shape(const MeshDev& m, const SetDev& set, KrylovWork& w, int iters, hipEvent_t t0,
+                             hipEvent_t t1, float* ms, int* ok) {
+    hipStream_t st = w.st;
+    KVec<double> V = w.v64;
+    V.A = set.amat;
+    V.b = w.beff;
+    const int g = (m.Nc + kBlock - 1) / kBlock > 8192 ? 8192 : (m.Nc + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_tune_problem, dim3(g), dim3(kBlock), 0, st, m.Nc, set.unknown, w.beff, V.x);
+    KState h;
+    hipError_t e = kinit<DIM, double, double>(m, w, V, w.kb64, 1, 0.0, st, &h);
+    if (e != hipSuccess) return e;
+    enqueue_iteration<DIM, double, double>(m, V, w.kb64, 0, P_FIRST, st, nullptr, nullptr, nullptr, nullptr);
+    enqueue_iteration<DIM, double, double>(m, V, w.kb64, 1, P_NORMAL, st, nullptr, nullptr, nullptr, nullptr);
+    if ((e = hipEventRecord(t0, st)) != hipSuccess) return e;
+    for (int q = 0; q < iters; ++q)
+        enqueue_iteration<DIM, double, double>(m, V, w.kb64, q & 1, P_NORMAL, st, nullptr, nullptr, nullptr, nullptr);
+    if ((e = hipEventRecord(t1, st)) != hipSuccess) return e;
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(&w.host[0], w.kb64.st[2], sizeof(KState), hipMemcpyDeviceToHost, st)) != hipSuccess)
+        return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if ((e = hipEventElapsedTime(ms, t0, t1)) != hipSuccess) return e;
+    *ok = w.host[0].done == 0 && w.host[0].iter == iters + 2;
+    return hipSuccess;
+}
+
+// Autotuner of the stage-kernel shape: every candidate (block count, and
+// brick depth in 3D) is timed on the set's FP64 operator, each twice,
+// keeping the faster run; the fastest candidate is applied, unless the
+// default shape is within 2 % of it (the default is kept then, so that
+// timing noise does not change the shape, and with it the summation order,
+// from run to run).  Results: per candidate (grid, depth, us per iteration,
+// < 0 when rejected) and the index applied.
+hipError_t krylov_autotune(const MeshDev& m, const SetDev& set, KrylovWork& w, int iters, int max_cand,
+                           int* n_out, int* grid_out, int* depth_out, double* us_out, int* chosen) {
+    static const int grids[] = {128, 256, 384, 512};
+    static const int depths3[] = {4, 8, 16};
+    const int nd = m.dim == 3 ? 3 : 1;
+    int n = 0;
+    for (int di = 0; di < nd; ++di) {
+        const int depth = m.dim == 3 ? depths3[di] : 1;
+        if (m.dim == 3 && depth > m.n[2]) continue;
+        int last_nblk = -1;
+        for (int grid : grids) {
+            KBufs K = w.kb64;
+            if (!shape_of(m, grid, depth, K) || K.nblk == last_nblk) continue;    // same effective shape
+            last_nblk = K.nblk;
+            if (n == max_cand) break;
+            grid_out[n] = grid;
+            depth_out[n] = depth;
+            ++n;
+        }
+    }
+    hipEvent_t t0 = nullptr, t1 = nullptr;
+    hipError_t e = hipEventCreate(&t0);
+    if (e == hipSuccess) e = hipEventCreate(&t1);
+    const int grid0 = w.grid_req, depth0 = w.kb64.tz;
+    int best = -1, dflt = -1;
+    for (int i = 0; i < n && e == hipSuccess; ++i) {
+        if ((e = krylov_set_shape(m, w, grid_out[i], depth_out[i])) != hipSuccess) break;
+        float ms = 0.f, ms2 = 0.f;
+        int ok = 0, ok2 = 0;
+        e = m.dim == 2 ? time_shape<2>(m, set, w, iters, t0, t1, &ms, &ok) : time_shape<3>(m, set, w, iters, t0, t1, &ms, &ok);
+        if (e != hipSuccess) break;
+        e = m.dim == 2 ? time_shape<2>(m, set, w, iters, t0, t1, &ms2, &ok2)
+                       : time_shape<3>(m, set, w, iters, t0, t1, &ms2, &ok2);
+        if (e != hipSuccess) break;
+        us_out[i] = ok && ok2 ? 1e3 * (double)fminf(ms, ms2) / iters : -1.0;
+        if (us_out[i] > 0 && (best < 0 || us_out[i] < us_out[best])) best = i;
+        if (grid_out[i] == kKGrid && depth_out[i] == (m.dim == 3 ? kDefaultDepth : 1)) dflt = i;
+    }
+    if (t0) (void)hipEventDestroy(t0);
+    if (t1) (void)hipEventDestroy(t1);
+    if (e != hipSuccess) {
+        (void)krylov_set_shape(m, w, grid0, depth0);
+        return e;
+    }
+    if (best >= 0 && dflt >= 0 && us_out[dflt] > 0 && us_out[dflt] <= 1.02 * us_out[best]) best = dflt;
+    *n_out = n;
+    *chosen = best;
+    if (best < 0) return krylov_set_shape(m, w, grid0, depth0);
+    return krylov_set_shape(m, w, grid_out[best], depth_out[best]);
+}
+
 hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     KrylovWork* w = new KrylovWork{};
     *out = w;
     const int Nc = m.Nc;
     w->Nc = Nc;
     hipError_t e;
-    // one block per 64 x 8 tile (2D) or 64 x 8 x 8 brick (3D), at most kKGrid
-    // blocks, each looping over a contiguous run of tiles
-    const int ntx = (m.n[0] + TX - 1) / TX, nty = (m.n[1] + TY - 1) / TY;
-    const int ntiles = ntx * nty * (m.dim == 3 ? (m.n[2] + TZ3 - 1) / TZ3 : 1);
-    const int nblk = ntiles < kKGrid ? ntiles : kKGrid;
-    const int tpb = (ntiles + nblk - 1) / nblk;
+    KBufs K0{};
+    (void)shape_of(m, kKGrid, m.dim == 3 ? kDefaultDepth : 1, K0);
+    w->grid_req = kKGrid;
     const int cap = kKGrid;
     for (KBufs* K : {&w->kb64, &w->kb32}) {
-        K->nblk = nblk;
+        *K = K0;
         K->cap = cap;
-        K->ntx = ntx;
-        K->nty = nty;
-        K->ntiles = ntiles;
-        K->tpb = tpb;
         for (int q = 0; q < 3; ++q) {
             if ((e = hipMalloc((void**)&K->part[q], 4 * (size_t)cap * sizeof(double))) != hipSuccess) return e;
             if ((e = hipMemset(K->part[q], 0, 4 * (size_t)cap * sizeof(double))) != hipSuccess) return e;

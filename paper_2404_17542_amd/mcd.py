@@ -32,7 +32,7 @@ MAX_SETS = 4
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
             "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
             "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_ppe_residual", "mcd_profile",
-            "mcd_profile_read",
+            "mcd_profile_read", "mcd_autotune", "mcd_set_shape", "mcd_get_shape",
             "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
             "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_set_output_scale",
             "mcd_model_infer",
@@ -71,6 +71,14 @@ class SolveOpts(C.Structure):
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("restarts", C.c_int), ("refinements", C.c_int), ("converged", C.c_int),
                 ("true_rel_residual", C.c_double), ("rhs_norm", C.c_double)]
+
+
+TUNE_MAX = 32
+
+
+class Tuning(C.Structure):
+    _fields_ = [("n", C.c_int), ("grid", C.c_int * TUNE_MAX), ("depth", C.c_int * TUNE_MAX),
+                ("us_per_iter", C.c_double * TUNE_MAX), ("chosen", C.c_int)]
 
 
 class McdError(RuntimeError):
@@ -120,6 +128,9 @@ def load():
         "mcd_model_infer": (i, [vp, vp, vp, vp, P(BcTable), vp]),
         "mcd_model_train_step": (i, [vp, vp, vp, vp, vp, P(BcTable), d, P(d)]),
         "mcd_profile_read": (i, [vp, P(d), P(C.c_longlong), P(d), P(C.c_longlong), i]),
+        "mcd_autotune": (i, [vp, i, i, P(Tuning)]),
+        "mcd_set_shape": (i, [vp, i, i]),
+        "mcd_get_shape": (i, [vp, P(i), P(i), P(i)]),
     }
     for name, (res, args) in sig.items():
         f = getattr(lib, name)
@@ -335,6 +346,24 @@ class Context:
         self._check(self.lib.mcd_ppe_residual(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), V(r, N),
                                               norms), "mcd_ppe_residual")
         return norms[0], norms[1]
+
+    def autotune(self, set_id, iters=32):
+        """Times the stage-kernel shapes on the set's operator and applies the
+        fastest (see mcd_autotune); returns the candidates and the choice."""
+        t = Tuning()
+        self._check(self.lib.mcd_autotune(self.h, int(set_id), int(iters), C.byref(t)), "mcd_autotune")
+        cands = [{"grid": t.grid[k], "depth": t.depth[k], "us_per_iter": t.us_per_iter[k]} for k in range(t.n)]
+        return {"candidates": cands, "chosen": t.chosen, "shape": self.get_shape()}
+
+    def set_shape(self, grid, depth=None):
+        if depth is None:
+            depth = 8 if self.dim == 3 else 1
+        self._check(self.lib.mcd_set_shape(self.h, int(grid), int(depth)), "mcd_set_shape")
+
+    def get_shape(self):
+        g, dp, b = C.c_int(), C.c_int(), C.c_int()
+        self._check(self.lib.mcd_get_shape(self.h, C.byref(g), C.byref(dp), C.byref(b)), "mcd_get_shape")
+        return {"grid": g.value, "depth": dp.value, "blocks": b.value}
 
     def profile(self, enable=True):
         self._check(self.lib.mcd_profile(self.h, int(bool(enable))), "mcd_profile")

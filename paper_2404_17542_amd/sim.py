@@ -117,6 +117,15 @@ class GpuSim:
         ctx.neumann_pressure(self.role, self.normal, bodies_new, self.fP)
         return pset, bodies_new, upd
 
+    def tuning_set(self):
+        """A built pressure set at the current positions, for the stage-kernel
+        autotuner (the velocity set when both fields share one; otherwise the
+        pressure set is built now, which the next step rebuilds anyway)."""
+        if self.same_sets:
+            return SET_VEL[self.vel_slot]
+        self.ctx.build_stencils(SET_P, self.pos, self.role, self.normal, self.case.bc_pressure, self.case.pin_first)
+        return SET_P
+
     def initial_guess(self, pset, mode):
         """Prepares the solver's initial guess and returns the solver's guess
         flag: 'warm' keeps P^k, 'zero' starts from 0 at the unknowns,
