@@ -2,8 +2,11 @@
 
 TEST INFRASTRUCTURE (see mcd_oracle).  Not part of the paper: the
 benchmark specification asks for a small network on the background mesh
-that predicts the pressure initial guess.  Images are NHWC (rows = y,
-columns = x, channels last); one DP per cell makes the DP arrays images.
+that predicts the pressure initial guess.  Images are channels-last arrays
+over the mesh axes in reverse order: (y, x, C) in 2D, (z, y, x, C) in 3D;
+one DP per cell makes the DP arrays images.  Everything below works for
+either dimension: a "3x3" convolution has 3^d taps and pooling and
+upsampling act on 2^d blocks.
 
 Architecture (levels L, channels ch[0..L-1]):
   encoder level l: conv3x3 -> ReLU -> conv3x3 -> ReLU  (ch[l] out; input of
@@ -13,7 +16,8 @@ Architecture (levels L, channels ch[0..L-1]):
                    2x upsample of the level l+1 output) -> conv3x3 -> ReLU ->
                    conv3x3 -> ReLU  (ch[l] out)
   head:            conv3x3 ch[0] -> 1 (no activation)
-Convolutions use zero padding; tap t = 3*dy + dx is the offset (dx-1, dy-1).
+Convolutions use zero padding; tap t = 3*dy + dx is the offset (dx-1, dy-1)
+in 2D and t = 9*dz + 3*dy + dx the offset (dx-1, dy-1, dz-1) in 3D.
 Weights of a conv: W[t][ci][co] and bias b[co]; the flat parameter vector
 lists the convs in the order enc0a, enc0b, enc1a, ..., dec(L-2)a, dec(L-2)b,
 ..., dec0a, dec0b, head, each as W then b.
@@ -49,72 +53,97 @@ def layer_shapes(ch, cin=IN_CHANNELS):
     return out
 
 
-def n_params(ch, cin=IN_CHANNELS):
-    return sum(9 * a * b + b for _, a, b in layer_shapes(ch, cin))
+def n_params(ch, cin=IN_CHANNELS, dim=2):
+    T = 3 ** dim
+    return sum(T * a * b + b for _, a, b in layer_shapes(ch, cin))
 
 
-def unpack(theta, ch, cin=IN_CHANNELS):
+def unpack(theta, ch, cin=IN_CHANNELS, dim=2):
+    T = 3 ** dim
     params, off = {}, 0
     for name, a, b in layer_shapes(ch, cin):
-        W = theta[off:off + 9 * a * b].reshape(9, a, b)
-        off += 9 * a * b
+        W = theta[off:off + T * a * b].reshape(T, a, b)
+        off += T * a * b
         bias = theta[off:off + b]
         off += b
         params[name] = (W, bias)
     return params
 
 
-def init_params(ch, seed, cin=IN_CHANNELS, dtype=np.float32):
+def init_params(ch, seed, cin=IN_CHANNELS, dtype=np.float32, dim=2):
     """Seeded He-normal weights and zero biases from the shared input generator."""
     from paper_2404_17542_amd.inputs import he_normal_params
-    return he_normal_params([(a, b) for _, a, b in layer_shapes(ch, cin)], seed).astype(dtype)
+    return he_normal_params([(a, b) for _, a, b in layer_shapes(ch, cin)], seed, taps=3 ** dim).astype(dtype)
 
 
 # ---------------------------------------------------------------------------
 # layers
 # ---------------------------------------------------------------------------
 
+def _taps(nd):
+    """Tap offsets (0..2 per spatial axis, first axis slowest) in tap order."""
+    return [np.unravel_index(t, (3,) * nd) for t in range(3 ** nd)]
+
+
+def _window(o, shape):
+    return tuple(slice(a, a + n) for a, n in zip(o, shape))
+
+
 def conv3x3(x, W, b):
-    H, Wd, _ = x.shape
-    xp = np.pad(x, ((1, 1), (1, 1), (0, 0)))
-    out = np.zeros((H, Wd, W.shape[2]), dtype=np.result_type(x, W))
-    for t in range(9):
-        dy, dx = t // 3, t % 3
-        out += xp[dy:dy + H, dx:dx + Wd, :] @ W[t]
+    """Zero-padded 3^d-tap convolution of a channels-last image."""
+    nd = x.ndim - 1
+    sp = x.shape[:nd]
+    xp = np.pad(x, [(1, 1)] * nd + [(0, 0)])
+    out = np.zeros(sp + (W.shape[2],), dtype=np.result_type(x, W))
+    for t, o in enumerate(_taps(nd)):
+        out += xp[_window(o, sp)] @ W[t]
     return out + b
 
 
 def conv3x3_backward(x, W, dy_):
     """Gradients of y = conv3x3(x, W, b) for upstream dy."""
-    H, Wd, _ = x.shape
-    xp = np.pad(x, ((1, 1), (1, 1), (0, 0)))
+    nd = x.ndim - 1
+    sp = x.shape[:nd]
+    xp = np.pad(x, [(1, 1)] * nd + [(0, 0)])
     dW = np.zeros_like(W)
     dxp = np.zeros_like(xp)
-    for t in range(9):
-        dy, dx = t // 3, t % 3
-        xs = xp[dy:dy + H, dx:dx + Wd, :]
-        dW[t] = xs.reshape(-1, xs.shape[2]).T @ dy_.reshape(-1, dy_.shape[2])
-        dxp[dy:dy + H, dx:dx + Wd, :] += dy_ @ W[t].T
-    db = dy_.sum(axis=(0, 1))
-    return dxp[1:-1, 1:-1, :], dW, db
+    for t, o in enumerate(_taps(nd)):
+        xs = xp[_window(o, sp)]
+        dW[t] = xs.reshape(-1, xs.shape[-1]).T @ dy_.reshape(-1, dy_.shape[-1])
+        dxp[_window(o, sp)] += dy_ @ W[t].T
+    db = dy_.reshape(-1, dy_.shape[-1]).sum(axis=0)
+    return dxp[(slice(1, -1),) * nd], dW, db
+
+
+def _blocks(x):
+    """View of a channels-last image as (n0, 2, n1, 2, ..., C) blocks."""
+    nd = x.ndim - 1
+    shp = []
+    for n in x.shape[:nd]:
+        shp += [n // 2, 2]
+    return x.reshape(shp + [x.shape[-1]]), tuple(range(1, 2 * nd, 2))
 
 
 def pool2(x):
-    H, W, C = x.shape
-    return x.reshape(H // 2, 2, W // 2, 2, C).mean(axis=(1, 3))
-
-
-def pool2_backward(dy):
-    return np.repeat(np.repeat(dy, 2, axis=0), 2, axis=1) / 4.0
+    """Mean over 2^d blocks."""
+    v, ax = _blocks(x)
+    return v.mean(axis=ax)
 
 
 def up2(x):
-    return np.repeat(np.repeat(x, 2, axis=0), 2, axis=1)
+    """Nearest 2x upsampling along every spatial axis."""
+    for a in range(x.ndim - 1):
+        x = np.repeat(x, 2, axis=a)
+    return x
+
+
+def pool2_backward(dy):
+    return up2(dy) / 2.0 ** (dy.ndim - 1)
 
 
 def up2_backward(dy):
-    H, W, C = dy.shape
-    return dy.reshape(H // 2, 2, W // 2, 2, C).sum(axis=(1, 3))
+    v, ax = _blocks(dy)
+    return v.sum(axis=ax)
 
 
 # ---------------------------------------------------------------------------
@@ -126,26 +155,32 @@ def _rms(v, unknown):
     return r if r > 0 else 1.0
 
 
+def image_shape(n):
+    """Spatial image shape of a mesh with n = (n0, n1[, n2]) cells (x fastest)."""
+    return tuple(int(v) for v in reversed(tuple(n)))
+
+
 def pack_input(r, p_prev, role, unknown, n, cin=IN_CHANNELS, body_id=2, wall_id=1):
-    """(H, W, cin) image from DP arrays of an n0 x n1 mesh; returns (x, rms(r))."""
-    n0, n1 = n
+    """Channels-last image from DP arrays of an n0 x n1 (x n2) mesh; returns
+    (x, rms(r))."""
+    sp = image_shape(n)
     rr, rp = _rms(r, unknown), _rms(p_prev, unknown)
-    x = np.zeros((n1, n0, cin))
-    x[:, :, 0] = np.where(unknown, r / rr, 0.0).reshape(n1, n0)
-    x[:, :, 1] = np.where(unknown, p_prev / rp, 0.0).reshape(n1, n0)
-    x[:, :, 2] = (role == -1).reshape(n1, n0)
-    x[:, :, 3] = (role == body_id).reshape(n1, n0)
-    x[:, :, 4] = (role == wall_id).reshape(n1, n0)
+    x = np.zeros(sp + (cin,))
+    x[..., 0] = np.where(unknown, r / rr, 0.0).reshape(sp)
+    x[..., 1] = np.where(unknown, p_prev / rp, 0.0).reshape(sp)
+    x[..., 2] = (role == -1).reshape(sp)
+    x[..., 3] = (role == body_id).reshape(sp)
+    x[..., 4] = (role == wall_id).reshape(sp)
     return x, rr
 
 
 def correction_target(p_target, p_prev, rms_r, scale, n):
-    """t = (P - p_prev) / (s rms(r)) as an (H, W) image."""
-    return ((p_target - p_prev) / (scale * rms_r)).reshape(n[1], n[0])
+    """t = (P - p_prev) / (s rms(r)) as an image."""
+    return ((p_target - p_prev) / (scale * rms_r)).reshape(image_shape(n))
 
 
 def forward(theta, x, ch, cin=IN_CHANNELS):
-    P = unpack(theta, ch, cin)
+    P = unpack(theta, ch, cin, x.ndim - 1)
     L = len(ch)
     cache = {"x": x}
     h = x
@@ -160,13 +195,13 @@ def forward(theta, x, ch, cin=IN_CHANNELS):
         cache[f"enc{l}b"] = h
         enc.append(h)
     for l in range(L - 2, -1, -1):
-        cat = np.concatenate([enc[l], up2(h)], axis=2)
+        cat = np.concatenate([enc[l], up2(h)], axis=-1)
         cache[f"cat{l}"] = cat
         a = np.maximum(conv3x3(cat, *P[f"dec{l}a"]), 0.0)
         cache[f"dec{l}a"] = a
         h = np.maximum(conv3x3(a, *P[f"dec{l}b"]), 0.0)
         cache[f"dec{l}b"] = h
-    out = conv3x3(h, *P["head"])[:, :, 0]
+    out = conv3x3(h, *P["head"])[..., 0]
     cache["last"] = h
     return out, cache
 
@@ -182,10 +217,10 @@ def loss_and_grad_out(out, target, mask):
 
 def backward(theta, cache, dout, ch, cin=IN_CHANNELS):
     """Gradient of the flat parameter vector for upstream d(out)."""
-    P = unpack(theta, ch, cin)
+    P = unpack(theta, ch, cin, cache["x"].ndim - 1)
     L = len(ch)
     grads = {}
-    dh, dW, db = conv3x3_backward(cache["last"], P["head"][0], dout[:, :, None])
+    dh, dW, db = conv3x3_backward(cache["last"], P["head"][0], dout[..., None])
     grads["head"] = (dW, db)
     denc = [None] * L
     for l in range(0, L - 1):
@@ -197,8 +232,8 @@ def backward(theta, cache, dout, ch, cin=IN_CHANNELS):
         dcat, dW, db = conv3x3_backward(cache[f"cat{l}"], P[f"dec{l}a"][0], da)
         grads[f"dec{l}a"] = (dW, db)
         c = ch[l]
-        denc[l] = dcat[:, :, :c]
-        dh = up2_backward(dcat[:, :, c:])
+        denc[l] = dcat[..., :c]
+        dh = up2_backward(dcat[..., c:])
     # dh is now the gradient of the bottom encoder output (level L-1)
     for l in range(L - 1, -1, -1):
         if l < L - 1:

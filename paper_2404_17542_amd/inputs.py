@@ -102,13 +102,14 @@ class Oscillation:
         return tuple(v)
 
 
-def he_normal_params(shapes, seed):
-    """Seeded initial network parameters: for each (cin, cout) 3x3 conv, weights
-    N(0, 2 / (9 cin)) of shape [9][cin][cout] then zero biases (flat FP32)."""
+def he_normal_params(shapes, seed, taps=9):
+    """Seeded initial network parameters: for each (cin, cout) convolution of
+    `taps` taps (9 in 2D, 27 in 3D), weights N(0, 2 / (taps cin)) of shape
+    [taps][cin][cout] then zero biases (flat FP32)."""
     rng = np.random.Generator(np.random.PCG64(seed))
     parts = []
     for cin, cout in shapes:
-        parts.append(rng.standard_normal(9 * cin * cout) * np.sqrt(2.0 / (9 * cin)))
+        parts.append(rng.standard_normal(taps * cin * cout) * np.sqrt(2.0 / (taps * cin)))
         parts.append(np.zeros(cout))
     return np.concatenate(parts).astype(np.float32)
 

@@ -105,3 +105,70 @@ def test_adam_first_step_moves_by_lr():
     g = np.array([1.0, -2.0, 0.5, 0.0])
     t, m, v = U.adam_update(theta, np.zeros(4), np.zeros(4), g, 1, lr=0.01)
     assert np.allclose(t[:3], -0.01 * np.sign(g[:3]), rtol=1e-6) and t[3] == 0.0
+
+
+# ---------------------------------------------------------------------------
+# 3D network (27-tap convolutions, 2x2x2 pooling), same code path
+# ---------------------------------------------------------------------------
+
+def test_backward_matches_finite_differences_3d():
+    ch, cin = (8, 16), 5
+    theta = U.init_params(ch, 3, cin=cin, dtype=np.float64, dim=3)
+    assert len(theta) == U.n_params(ch, cin, dim=3) == sum(27 * a * b + b for _, a, b in U.layer_shapes(ch, cin))
+    rng = np.random.default_rng(8)
+    x = rng.standard_normal((4, 8, 6, cin))          # (z, y, x): unequal axes catch transpositions
+    target = rng.standard_normal((4, 8, 6))
+    mask = rng.uniform(size=(4, 8, 6)) > 0.2
+    out, cache = U.forward(theta, x, ch, cin)
+    assert out.shape == (4, 8, 6)
+    loss, dout = U.loss_and_grad_out(out, target, mask)
+    g = U.backward(theta, cache, dout, ch, cin)
+
+    def f(th):
+        return U.loss_and_grad_out(U.forward(th, x, ch, cin)[0], target, mask)[0]
+
+    h = 1e-6
+    for i in rng.choice(len(theta), 40, replace=False):
+        tp, tm = theta.copy(), theta.copy()
+        tp[i] += h
+        tm[i] -= h
+        assert (f(tp) - f(tm)) / (2 * h) == pytest.approx(g[i], rel=1e-5, abs=1e-9)
+    d = rng.standard_normal(len(theta))
+    assert (f(theta + h * d) - f(theta - h * d)) / (2 * h) == pytest.approx(g @ d, rel=1e-6)
+
+
+def test_3d_conv_of_a_z_constant_image_is_the_2d_conv():
+    """With an input constant along z, an interior plane of the 27-tap
+    convolution is the 9-tap convolution with the three z-planes of taps
+    summed; the first plane sees only the taps dz = 0, +1 (zero padding)."""
+    rng = np.random.default_rng(5)
+    x2 = rng.standard_normal((7, 5, 3))
+    x3 = np.repeat(x2[None], 6, axis=0)
+    W3 = rng.standard_normal((27, 3, 4))
+    b = rng.standard_normal(4)
+    y3 = U.conv3x3(x3, W3, b)
+    W2_all = W3[0:9] + W3[9:18] + W3[18:27]
+    for z in range(1, 5):
+        assert np.allclose(y3[z], U.conv3x3(x2, W2_all, b))
+    assert np.allclose(y3[0], U.conv3x3(x2, W3[9:18] + W3[18:27], b))
+    assert np.allclose(y3[5], U.conv3x3(x2, W3[0:9] + W3[9:18], b))
+    # the centre tap alone is the identity map
+    W = np.zeros((27, 3, 3))
+    W[13] = np.eye(3)
+    assert np.allclose(U.conv3x3(x3, W, np.zeros(3)), x3)
+    # tap 22 = (dz, dy, dx) = (2, 1, 1): out[z] = in[z + 1]
+    W = np.zeros((27, 3, 3))
+    W[22] = np.eye(3)
+    xr = rng.standard_normal((4, 3, 3, 3))
+    y = U.conv3x3(xr, W, np.zeros(3))
+    assert np.allclose(y[:-1], xr[1:]) and np.allclose(y[-1], 0)
+
+
+def test_3d_pool_and_upsample():
+    rng = np.random.default_rng(6)
+    a = rng.standard_normal((4, 6, 8, 2))
+    b = rng.standard_normal((2, 3, 4, 2))
+    assert np.sum(U.pool2(a) * b) == pytest.approx(np.sum(a * U.up2(b) / 8))
+    assert np.allclose(U.pool2(U.up2(b)), b)
+    assert U.pool2(a)[1, 2, 3, 1] == pytest.approx(a[2:4, 4:6, 6:8, 1].mean())
+    assert np.allclose(U.up2_backward(U.up2(b)), 8 * b)
