@@ -130,3 +130,20 @@ def c4_moving_sphere(n=128, steps=20):
                 body=Body(radius=0.5 * diam, motion=Oscillation((0.5, 0.5, 0.5), amp, freq, 0)),
                 nu=u_max * diam / 100.0, dt=(1.0 / 200.0) * (128.0 / n), steps=steps,
                 bc_pressure={1: DIRICHLET, 2: NEUMANN}, bc_velocity={1: NEUMANN, 2: DIRICHLET})
+
+
+def c4_sphere_variant(seed, n=128, steps=60):
+    """A C4-shaped trajectory for the 3D learned-guess data set: amplitude
+    A ~ U[0.1, 0.4] D and frequency f ~ U[0.5, 2] drawn from PCG64(seed), as
+    for the cylinder variants, Re = 100 kept, the DP jitter seeded by `seed`
+    and the step shortened where the sphere is faster than in C4."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    base = c4_moving_sphere(n=n, steps=steps)
+    diam = 2 * base.body.radius
+    amp = float(rng.uniform(0.1, 0.4)) * diam
+    freq = float(rng.uniform(0.5, 2.0))
+    u_max = 2 * math.pi * freq * amp
+    u_ref = 2 * math.pi * 1.0 * 0.2 * diam
+    return replace(base, name=f"C4-sphere-{n}-seed{seed}", jitter_seed=int(seed),
+                   body=Body(radius=0.5 * diam, motion=Oscillation((0.5, 0.5, 0.5), amp, freq, 0)),
+                   nu=u_max * diam / 100.0, dt=base.dt * min(1.0, u_ref / u_max))
