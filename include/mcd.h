@@ -296,26 +296,28 @@ mcd_status mcd_ppe_residual(mcd_ctx* ctx, int set, const double* rhs, const doub
                             double* r, double* norms);
 
 /* ---------------------------------------------------------------------
- * Learned PPE initial guess (2D): a U-Net on the background mesh.  Not part
- * of the MCD method: a network that corrects the warm start of the solve.
- * One DP per cell makes the DP arrays NHWC images (row y, column x).
+ * Learned PPE initial guess (2D and 3D): a U-Net on the background mesh.
+ * Not part of the MCD method: a network that corrects the warm start of the
+ * solve.  One DP per cell makes the DP arrays channels-last images: (y, x)
+ * in 2D, (z, y, x) in 3D, x fastest.
  * Inputs: r / rms(r), where r is the PPE residual of the warm start p_prev
  * (mcd_ppe_residual), p_prev / rms(p_prev), one-hot roles (inner, body,
  * wall); output h; guess = p_prev + s rms(r) h at unknown cells (FP64), s =
  * the model's output scale.  rms over unknown cells (1 where it is 0).
- * Levels L: per level two 3x3 convolutions with ReLU, 2x2 mean pooling down,
- * nearest 2x upsampling and concatenation with the skip up, a 3x3 head to one
- * channel.  BF16 weights and activations, FP32 accumulation on the matrix
+ * Levels L: per level two 3x3 (3x3x3) convolutions with ReLU, 2x2 (2x2x2)
+ * mean pooling down, nearest 2x upsampling and concatenation with the skip
+ * up, a 3x3 (3x3x3) head to one channel.  BF16 weights and activations, FP32 accumulation on the matrix
  * cores; FP32 master weights trained with Adam.
  * Parameters: flat FP32 vector, convolutions in the order enc0a, enc0b, ...,
- * enc(L-1)b, dec(L-2)a, dec(L-2)b, ..., dec0a, dec0b, head, each W[9][cin][cout]
- * (tap t = 3 dy + dx, offset (dx - 1, dy - 1)) then b[cout].
+ * enc(L-1)b, dec(L-2)a, dec(L-2)b, ..., dec0a, dec0b, head, each W[T][cin][cout]
+ * then b[cout]; T = 9 taps in 2D (tap t = 3 dy + dx, offset (dx - 1, dy - 1)),
+ * 27 in 3D (t = 9 dz + 3 dy + dx, offset (dx - 1, dy - 1, dz - 1)).
  * ------------------------------------------------------------------- */
 
 typedef struct mcd_model mcd_model;
 
 /* channels: host array of `levels` (2..5) widths, multiples of 16 in
- * [16, 256]; the mesh must be divisible by 2^(levels-1).  body_id: role id
+ * [16, 256]; every mesh axis must be divisible by 2^(levels-1).  body_id: role id
  * of the body for the one-hot input.  Weights start at zero (set them). */
 mcd_status mcd_model_create(mcd_ctx* ctx, int levels, const int* channels, int body_id, mcd_model** out);
 void mcd_model_destroy(mcd_model* model);

@@ -495,17 +495,17 @@ struct mcd_model {
 mcd_status mcd_model_create(mcd_ctx* c, int levels, const int* channels, int body_id, mcd_model** out) {
     if (!c || !channels || !out) return MCD_ERR_ARG;
     *out = nullptr;
-    if (c->dim != 2) return fail(c, MCD_ERR_ARG, "mcd_model_create: the network is 2D%s");
     if (levels < 2 || levels > 5) return fail(c, MCD_ERR_ARG, "mcd_model_create: levels must be 2..5%s");
-    const int H = c->m.n[1], W = c->m.n[0];
-    if ((H % (1 << (levels - 1))) || (W % (1 << (levels - 1))))
+    const int H = c->m.n[1], W = c->m.n[0], D = c->dim == 3 ? c->m.n[2] : 1;
+    const int q = 1 << (levels - 1);
+    if ((H % q) || (W % q) || (c->dim == 3 && (D % q)))
         return fail(c, MCD_ERR_ARG, "mcd_model_create: mesh not divisible by 2^(levels-1)%s");
     for (int l = 0; l < levels; ++l)
         if (channels[l] < 16 || channels[l] > 256 || channels[l] % 16)
             return fail(c, MCD_ERR_ARG, "mcd_model_create: channels must be multiples of 16 in [16, 256]%s");
     if (body_id < 1 || body_id >= MCD_MAX_IDS) return fail(c, MCD_ERR_ARG, "mcd_model_create: bad body id%s");
     UNet* u = nullptr;
-    hipError_t e = unet_create(H, W, levels, channels, body_id, c->desc.walls ? c->desc.wall_id : -2, &u);
+    hipError_t e = unet_create(c->dim, D, H, W, levels, channels, body_id, c->desc.walls ? c->desc.wall_id : -2, &u);
     if (e != hipSuccess) {
         unet_free(u);
         return e == hipErrorOutOfMemory ? MCD_ERR_OOM : hipfail(c, e, "mcd_model_create");

@@ -279,7 +279,7 @@ hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w,
                              const double* p, double* r, double norms[2], int* bad, hipStream_t st);
 
 struct UNet;
-hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall_id, UNet** out);
+hipError_t unet_create(int dim, int D, int H, int W, int L, const int* ch, int body_id, int wall_id, UNet** out);
 void unet_free(UNet* u);
 hipError_t unet_weights_to_bf16(UNet& u, hipStream_t st);
 hipError_t unet_infer(UNet& u, const double* b, const double* pprev, const int8_t* role, const BcDev& bc,

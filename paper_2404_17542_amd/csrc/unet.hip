@@ -1,10 +1,13 @@
 // Learned PPE initial guess: a U-Net on the background mesh (one DP per
-// cell makes DP arrays NHWC images: row = y, column = x, channels last).
+// cell makes DP arrays channels-last images: (y, x, C) in 2D, (z, y, x, C)
+// in 3D, x fastest).  Kernels are templated on the dimension: a "3x3"
+// convolution has 9 taps in 2D and 27 in 3D, pooling and upsampling act on
+// 2x2 or 2x2x2 blocks.
 //
 // BF16 weights and activations, FP32 accumulation on the matrix cores
 // (v_mfma_f32_32x32x16_bf16).  A 3x3 convolution is an implicit GEMM:
 //   Y[p][n] = sum_t sum_k In[p + o_t][k] W[t][n][k],
-// rows = pixels, columns = output channels, K = 9 taps x input channels.
+// rows = pixels, columns = output channels, K = taps x input channels.
 // The input In of a decoder convolution is concat(skip (this level),
 // nearest 2x upsample of the coarser level) and is read directly from the
 // two tensors, so neither the upsampled image nor the concatenation is ever
@@ -25,14 +28,16 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 constexpr int kIn = 16;       // packed input channels
 constexpr int kMaxLevels = 5;
 
-// Input of a convolution: concat(x0 (c0 channels, H x W), up2(x1) (c1
-// channels, (H/2) x (W/2))).
+// Input of a convolution: concat(x0 (c0 channels, D x H x W), up2(x1) (c1
+// channels, (D/2 in 3D, else 1) x (H/2) x (W/2))).  D = 1 and zs = 0 in 2D;
+// zs = 1 in 3D (the coarse level is halved in z too).
 struct ConvIn {
     const __bf16* x0;
     int c0;
     const __bf16* x1;
     int c1;
-    int H, W;
+    int D, H, W;
+    int zs;
 };
 
 __device__ __forceinline__ bf16x8 zero8() {
@@ -42,41 +47,66 @@ __device__ __forceinline__ bf16x8 zero8() {
     return z;
 }
 
-// 8 consecutive input channels [k0, k0 + 8) at (y, x); zero outside the image.
-__device__ __forceinline__ bf16x8 load8(const ConvIn& in, int y, int x, int k0) {
-    if (y < 0 || y >= in.H || x < 0 || x >= in.W) return zero8();
-    if (k0 < in.c0) return *(const bf16x8*)(in.x0 + (size_t)(y * in.W + x) * in.c0 + k0);
-    const int W1 = in.W >> 1;
-    return *(const bf16x8*)(in.x1 + (size_t)((y >> 1) * W1 + (x >> 1)) * in.c1 + (k0 - in.c0));
+__device__ __forceinline__ bool outside(const ConvIn& in, int z, int y, int x) {
+    return z < 0 || z >= in.D || y < 0 || y >= in.H || x < 0 || x >= in.W;
 }
 
-__device__ __forceinline__ __bf16 load1(const ConvIn& in, int y, int x, int k) {
-    if (y < 0 || y >= in.H || x < 0 || x >= in.W) return (__bf16)0.0f;
-    if (k < in.c0) return in.x0[(size_t)(y * in.W + x) * in.c0 + k];
-    const int W1 = in.W >> 1;
-    return in.x1[(size_t)((y >> 1) * W1 + (x >> 1)) * in.c1 + (k - in.c0)];
+// pixel index of (z, y, x) in the fine image and of its parent in the coarse one
+__device__ __forceinline__ size_t fine_px(const ConvIn& in, int z, int y, int x) {
+    return ((size_t)z * in.H + y) * in.W + x;
+}
+__device__ __forceinline__ size_t coarse_px(const ConvIn& in, int z, int y, int x) {
+    return ((size_t)(z >> in.zs) * (in.H >> 1) + (y >> 1)) * (in.W >> 1) + (x >> 1);
 }
 
-// Implicit-GEMM 3x3 convolution on LDS tiles.  Wk: [9][NT*32][K] bf16
+// 8 consecutive input channels [k0, k0 + 8) at (z, y, x); zero outside the image.
+__device__ __forceinline__ bf16x8 load8(const ConvIn& in, int z, int y, int x, int k0) {
+    if (outside(in, z, y, x)) return zero8();
+    if (k0 < in.c0) return *(const bf16x8*)(in.x0 + fine_px(in, z, y, x) * in.c0 + k0);
+    return *(const bf16x8*)(in.x1 + coarse_px(in, z, y, x) * in.c1 + (k0 - in.c0));
+}
+
+__device__ __forceinline__ __bf16 load1(const ConvIn& in, int z, int y, int x, int k) {
+    if (outside(in, z, y, x)) return (__bf16)0.0f;
+    if (k < in.c0) return in.x0[fine_px(in, z, y, x) * in.c0 + k];
+    return in.x1[coarse_px(in, z, y, x) * in.c1 + (k - in.c0)];
+}
+
+// taps of a convolution and the offset of tap t along z, y, x (-1..1)
+template <int DIM>
+struct Taps {
+    static constexpr int T = DIM == 3 ? 27 : 9;
+    static constexpr int HZ = DIM == 3 ? 3 : 1;     // planes of the halo
+    __device__ static int dz(int t) { return DIM == 3 ? t / 9 - 1 : 0; }
+    __device__ static int dy(int t) { return (t / 3) % 3 - 1; }
+    __device__ static int dx(int t) { return t % 3 - 1; }
+};
+
+// Implicit-GEMM 3x3 convolution on LDS tiles.  Wk: [T][NT*32][K] bf16
 // (K = c0 + c1, zero rows for n >= cout).  A block of 4 waves owns a tile of
-// 4 image rows x 32 columns (wave w: row w, one pixel per MFMA row).  The
-// input is staged through LDS 16 channels at a time as a (4+2) x (32+2)
-// halo tile, so each input pixel is read from memory once per chunk and the
-// nine taps read their A fragments (8 channels per lane) from LDS; B
-// fragments come from the (cache-resident) weights.  The epilogue (bias,
-// ReLU, BF16) goes through a per-wave 32 x 32 LDS tile so that every lane
-// stores 16 contiguous bytes; cout must be a multiple of 16.
+// 4 image rows x 32 columns of one plane (wave w: row w, one pixel per MFMA
+// row).  The input is staged through LDS 16 channels at a time as a
+// (4+2) x (32+2) halo tile (times the 3 planes z-1..z+1 in 3D), so each
+// input pixel is read from memory once per chunk and the taps read their A
+// fragments (8 channels per lane) from LDS; B fragments come from the
+// (cache-resident) weights.  The epilogue (bias, ReLU, BF16) goes through a
+// per-wave 32 x 32 LDS tile so that every lane stores 16 contiguous bytes;
+// cout must be a multiple of 16.
 constexpr int kCR = 4, kCC = 32, kHR = kCR + 2, kHC = kCC + 2, kHalo = kHR * kHC;
 
-// One 32-column tile of output channels per block (blockIdx.z), so that small
-// coarse-level images still spread over the whole chip.
+// Grid: x = column tiles, y = row tiles x planes, z = 32-column tiles of
+// output channels (so that small coarse-level images still spread over the
+// whole chip).
+template <int DIM>
 __global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __restrict__ Wk, int np,
                                                    const float* __restrict__ bias, int cout, int relu,
                                                    __bf16* __restrict__ Y) {
-    __shared__ __attribute__((aligned(16))) __bf16 tile[kHalo * 16];
+    using TP = Taps<DIM>;
+    __shared__ __attribute__((aligned(16))) __bf16 tile[TP::HZ * kHalo * 16];
     __shared__ __attribute__((aligned(16))) __bf16 stage[4][32 * 32];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
-    const int tx0 = blockIdx.x * kCC, ty0 = blockIdx.y * kCR, nt = blockIdx.z;
+    const int nty = (in.H + kCR - 1) / kCR;
+    const int tx0 = blockIdx.x * kCC, ty0 = (blockIdx.y % nty) * kCR, z = blockIdx.y / nty, nt = blockIdx.z;
     const int K = in.c0 + in.c1;
     const int half = 8 * (l >> 5);
     f32x16 acc;
@@ -84,17 +114,19 @@ __global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __re
     for (int i = 0; i < 16; ++i) acc[i] = 0.0f;
     for (int k0 = 0; k0 < K; k0 += 16) {
         // stage channels [k0, k0 + 16) of the halo tile: 2 vectors of 8 per pixel
-        for (int v = threadIdx.x; v < 2 * kHalo; v += 256) {
+        for (int v = threadIdx.x; v < 2 * TP::HZ * kHalo; v += 256) {
             const int px = v >> 1, hv = v & 1;
-            const int y = ty0 - 1 + px / kHC, x = tx0 - 1 + px % kHC;
-            *(bf16x8*)(tile + px * 16 + 8 * hv) = load8(in, y, x, k0 + 8 * hv);
+            const int pz = px / kHalo, pr = px % kHalo;
+            const int y = ty0 - 1 + pr / kHC, x = tx0 - 1 + pr % kHC;
+            *(bf16x8*)(tile + px * 16 + 8 * hv) = load8(in, z - TP::HZ / 2 + pz, y, x, k0 + 8 * hv);
         }
         __syncthreads();
         const __bf16* wn = Wk + (size_t)(nt * 32 + (l & 31)) * K + k0 + half;
 #pragma unroll
-        for (int t = 0; t < 9; ++t) {
-            const int dy = t / 3, dx = t % 3;     // halo offsets 0..2
-            const bf16x8 a = *(const bf16x8*)(tile + ((wave + dy) * kHC + (l & 31) + dx) * 16 + half);
+        for (int t = 0; t < TP::T; ++t) {
+            // halo offsets 0..2 along z (3D), y, x
+            const int hz = TP::dz(t) + TP::HZ / 2, hy = TP::dy(t) + 1, hx = TP::dx(t) + 1;
+            const bf16x8 a = *(const bf16x8*)(tile + ((hz * kHR + wave + hy) * kHC + (l & 31) + hx) * 16 + half);
             const bf16x8 b = *(const bf16x8*)(wn + (size_t)t * np * K);
             acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
         }
@@ -115,7 +147,7 @@ __global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __re
     const int nc = nt * 32 + col0;
     if (y < in.H && x < in.W && nc < cout) {
         const bf16x8* src = (const bf16x8*)(sw + row * 32 + col0);
-        bf16x8* dst = (bf16x8*)(Y + ((size_t)y * in.W + x) * cout + nc);
+        bf16x8* dst = (bf16x8*)(Y + fine_px(in, z, y, x) * cout + nc);
         dst[0] = src[0];
         dst[1] = src[1];
     }
@@ -124,16 +156,18 @@ __global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __re
 // Weight gradient: part[chunk][t][k][n] = sum over the chunk's pixels p of
 // In[p + o_t][k] dY[p][n]  (k < K padded to 32, n < cout padded to 32).
 // One wave per (t, k-tile, n-tile) output tile; blockIdx.x = pixel chunk.
+template <int DIM>
 __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, const __bf16* __restrict__ dY, int cout, int ktiles,
                                                     int ntiles, int chunk, float* __restrict__ part) {
+    using TP = Taps<DIM>;
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int tile = blockIdx.y * 4 + wave;
     const int per_tap = ktiles * ntiles;
-    if (tile >= 9 * per_tap) return;
+    if (tile >= TP::T * per_tap) return;
     const int t = tile / per_tap, kt = (tile % per_tap) / ntiles, nt = tile % ntiles;
-    const int dy = t / 3 - 1, dx = t % 3 - 1;
+    const int dz = TP::dz(t), dy = TP::dy(t), dx = TP::dx(t);
     const int K = in.c0 + in.c1;
-    const int P = in.H * in.W;
+    const int P = in.D * in.H * in.W;
     const int q_begin = blockIdx.x * chunk;
     const int q_end = min(P, q_begin + chunk);
     const int k = kt * 32 + (l & 31), n = nt * 32 + (l & 31);
@@ -147,15 +181,15 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, const __bf16* __r
         for (int j = 0; j < 8; ++j) {
             const int q = q0 + half + j;
             const bool ok = q < q_end;
-            const int y = ok ? q / in.W : 0, x = ok ? q % in.W : 0;
-            a[j] = (ok && k < K) ? load1(in, y + dy, x + dx, k) : (__bf16)0.0f;
+            const int x = ok ? q % in.W : 0, y = ok ? (q / in.W) % in.H : 0, z = ok ? q / (in.W * in.H) : 0;
+            a[j] = (ok && k < K) ? load1(in, z + dz, y + dy, x + dx, k) : (__bf16)0.0f;
             b[j] = (ok && n < cout) ? dY[(size_t)q * cout + n] : (__bf16)0.0f;
         }
         acc = __builtin_amdgcn_mfma_f32_32x32x16_bf16(a, b, acc, 0, 0, 0);
     }
     // D rows are k (from A), columns n (from B)
     const int Kp = ktiles * 32, Np = ntiles * 32;
-    float* dst = part + ((size_t)blockIdx.x * 9 + t) * Kp * Np;
+    float* dst = part + ((size_t)blockIdx.x * TP::T + t) * Kp * Np;
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
         const int kr = kt * 32 + 8 * (i >> 2) + 4 * (l >> 5) + (i & 3);
@@ -163,14 +197,14 @@ __global__ __launch_bounds__(256) void k_conv_wgrad(ConvIn in, const __bf16* __r
     }
 }
 
-// grad[t][k][n] (theta layout W[t][ci][co]) = sum over chunks of part.
-__global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int K, int cout, int Kp, int Np,
+// grad[t][k][n] (theta layout W[t][ci][co]) = sum over chunks of part (T taps).
+__global__ void k_wgrad_reduce(const float* __restrict__ part, int nchunks, int T, int K, int cout, int Kp, int Np,
                                float* __restrict__ g) {
-    const int total = 9 * K * cout;
+    const int total = T * K * cout;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
         const int t = e / (K * cout), k = (e / cout) % K, n = e % cout;
         double s = 0.0;
-        for (int c = 0; c < nchunks; ++c) s += part[((size_t)c * 9 + t) * Kp * Np + (size_t)k * Np + n];
+        for (int c = 0; c < nchunks; ++c) s += part[((size_t)c * T + t) * Kp * Np + (size_t)k * Np + n];
         g[e] = (float)s;
     }
 }
@@ -219,45 +253,66 @@ __global__ void k_relu_mask(__bf16* __restrict__ g, const __bf16* __restrict__ y
         if (!((float)y[i] > 0.0f)) g[i] = (__bf16)0.0f;
 }
 
-// 2x2 mean pool: out (H/2 x W/2 x C) from in (H x W x C).
-__global__ void k_pool(const __bf16* __restrict__ in, int H, int W, int C, __bf16* __restrict__ out) {
-    const int W2 = W >> 1, total = (H >> 1) * W2 * C;
+// Sum over the 2x2 (2D) or 2x2x2 (3D) block of coarse pixel (z, y, x) of a
+// fine D x H x W image, channel offset `c` of row width C.
+template <int DIM>
+__device__ __forceinline__ float block_sum2(const __bf16* __restrict__ f, int H, int W, int C, int z, int y, int x,
+                                            int c) {
+    float s = 0.0f;
+#pragma unroll
+    for (int dz = 0; dz < (DIM == 3 ? 2 : 1); ++dz) {
+        const int zf = DIM == 3 ? 2 * z + dz : z;
+#pragma unroll
+        for (int dy = 0; dy < 2; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 2; ++dx)
+                s += (float)f[(((size_t)zf * H + 2 * y + dy) * W + 2 * x + dx) * C + c];
+    }
+    return s;
+}
+
+// Mean pool over 2x2 (2x2x2) blocks: out (D' x H/2 x W/2 x C) from in
+// (D x H x W x C), D' = D/2 in 3D, 1 in 2D.
+template <int DIM>
+__global__ void k_pool(const __bf16* __restrict__ in, int D, int H, int W, int C, __bf16* __restrict__ out) {
+    const int H2 = H >> 1, W2 = W >> 1, D2 = DIM == 3 ? D >> 1 : 1;
+    const int total = D2 * H2 * W2 * C;
+    const float f = DIM == 3 ? 0.125f : 0.25f;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-        const int c = e % C, p = e / C, y = p / W2, x = p % W2;
-        const size_t b0 = ((size_t)(2 * y) * W + 2 * x) * C + c;
-        const float s = (float)in[b0] + (float)in[b0 + C] + (float)in[b0 + (size_t)W * C] +
-                        (float)in[b0 + (size_t)W * C + C];
-        out[e] = (__bf16)(0.25f * s);
+        const int c = e % C, p = e / C, x = p % W2, y = (p / W2) % H2, z = p / (W2 * H2);
+        out[e] = (__bf16)(f * block_sum2<DIM>(in, H, W, C, z, y, x, c));
     }
 }
 
-// g_fine (H x W x C) += g_coarse / 4 broadcast over each 2x2 block.
-__global__ void k_pool_bwd_add(const __bf16* __restrict__ gc, int H, int W, int C, __bf16* __restrict__ gf) {
-    const int total = H * W * C;
+// g_fine (D x H x W x C) += g_coarse / 4 (/ 8 in 3D) broadcast over each block.
+template <int DIM>
+__global__ void k_pool_bwd_add(const __bf16* __restrict__ gc, int D, int H, int W, int C, __bf16* __restrict__ gf) {
+    const int total = D * H * W * C;
+    const int zs = DIM == 3 ? 1 : 0;
+    const float f = DIM == 3 ? 0.125f : 0.25f;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-        const int c = e % C, p = e / C, y = p / W, x = p % W;
-        const float v = (float)gf[e] + 0.25f * (float)gc[((size_t)(y >> 1) * (W >> 1) + (x >> 1)) * C + c];
-        gf[e] = (__bf16)v;
+        const int c = e % C, p = e / C, x = p % W, y = (p / W) % H, z = p / (W * H);
+        const size_t pc = ((size_t)(z >> zs) * (H >> 1) + (y >> 1)) * (W >> 1) + (x >> 1);
+        gf[e] = (__bf16)((float)gf[e] + f * (float)gc[pc * C + c]);
     }
 }
 
 // Gradient of concat(skip, up2(coarse)): skip part written to gs, upsample
-// part summed over each 2x2 block into gcoarse ((H/2) x (W/2) x c1).
-__global__ void k_cat_split(const __bf16* __restrict__ gcat, int H, int W, int c0, int c1, __bf16* __restrict__ gs,
-                            __bf16* __restrict__ gcoarse) {
+// part summed over each 2x2 (2x2x2) block into gcoarse.
+template <int DIM>
+__global__ void k_cat_split(const __bf16* __restrict__ gcat, int D, int H, int W, int c0, int c1,
+                            __bf16* __restrict__ gs, __bf16* __restrict__ gcoarse) {
     const int C = c0 + c1;
-    const int n_skip = H * W * c0;
+    const int n_skip = D * H * W * c0;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_skip; e += gridDim.x * blockDim.x) {
         const int c = e % c0, p = e / c0;
         gs[e] = gcat[(size_t)p * C + c];
     }
-    const int W2 = W >> 1, n_c = (H >> 1) * W2 * c1;
+    const int H2 = H >> 1, W2 = W >> 1, D2 = DIM == 3 ? D >> 1 : 1;
+    const int n_c = D2 * H2 * W2 * c1;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n_c; e += gridDim.x * blockDim.x) {
-        const int c = e % c1, p = e / c1, y = p / W2, x = p % W2;
-        const size_t b0 = ((size_t)(2 * y) * W + 2 * x) * C + c0 + c;
-        const float s = (float)gcat[b0] + (float)gcat[b0 + C] + (float)gcat[b0 + (size_t)W * C] +
-                        (float)gcat[b0 + (size_t)W * C + C];
-        gcoarse[e] = (__bf16)s;
+        const int c = e % c1, p = e / c1, x = p % W2, y = (p / W2) % H2, z = p / (W2 * H2);
+        gcoarse[e] = (__bf16)block_sum2<DIM>(gcat, H, W, C, z, y, x, c0 + c);
     }
 }
 
@@ -266,16 +321,18 @@ __global__ void k_cat_split(const __bf16* __restrict__ gcat, int H, int W, int c
 // ---------------------------------------------------------------------------
 
 // h[p] = bh + sum_t sum_c X[p + o_t][c] Wh[t][c]  (C a multiple of 8: 16-byte loads)
-__global__ void k_head_fwd(const __bf16* __restrict__ X, int H, int W, int C, const float* __restrict__ Wh,
+template <int DIM>
+__global__ void k_head_fwd(const __bf16* __restrict__ X, int D, int H, int W, int C, const float* __restrict__ Wh,
                            const float* __restrict__ bh, float* __restrict__ h) {
-    const int P = H * W;
+    using TP = Taps<DIM>;
+    const int P = D * H * W;
     for (int p = blockIdx.x * blockDim.x + threadIdx.x; p < P; p += gridDim.x * blockDim.x) {
-        const int y = p / W, x = p % W;
+        const int x = p % W, y = (p / W) % H, z = p / (W * H);
         float s = bh[0];
-        for (int t = 0; t < 9; ++t) {
-            const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-            const bf16x8* xp = (const bf16x8*)(X + (size_t)(yy * W + xx) * C);
+        for (int t = 0; t < TP::T; ++t) {
+            const int zz = z + TP::dz(t), yy = y + TP::dy(t), xx = x + TP::dx(t);
+            if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+            const bf16x8* xp = (const bf16x8*)(X + (((size_t)zz * H + yy) * W + xx) * C);
             const float* wp = Wh + t * C;
             for (int q = 0; q < C / 8; ++q) {
                 const bf16x8 v = xp[q];
@@ -288,33 +345,39 @@ __global__ void k_head_fwd(const __bf16* __restrict__ X, int H, int W, int C, co
 }
 
 // gX[p][c] = sum_t dh[p - o_t] Wh[t][c]
-__global__ void k_head_bwd_data(const float* __restrict__ dh, int H, int W, int C, const float* __restrict__ Wh,
-                                __bf16* __restrict__ gX) {
-    const int total = H * W * C;
+template <int DIM>
+__global__ void k_head_bwd_data(const float* __restrict__ dh, int D, int H, int W, int C,
+                                const float* __restrict__ Wh, __bf16* __restrict__ gX) {
+    using TP = Taps<DIM>;
+    const int total = D * H * W * C;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < total; e += gridDim.x * blockDim.x) {
-        const int c = e % C, p = e / C, y = p / W, x = p % W;
+        const int c = e % C, p = e / C, x = p % W, y = (p / W) % H, z = p / (W * H);
         float s = 0.0f;
-        for (int t = 0; t < 9; ++t) {
-            const int yy = y - (t / 3 - 1), xx = x - (t % 3 - 1);
-            if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-            s += dh[yy * W + xx] * Wh[t * C + c];
+        for (int t = 0; t < TP::T; ++t) {
+            const int zz = z - TP::dz(t), yy = y - TP::dy(t), xx = x - TP::dx(t);
+            if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+            s += dh[((size_t)zz * H + yy) * W + xx] * Wh[t * C + c];
         }
         gX[e] = (__bf16)s;
     }
 }
 
 // partials of dWh[t][c] = sum_p X[p + o_t][c] dh[p] and dbh = sum_p dh[p]
-// (C a multiple of 8, at most 256).  Thread (rho, g) accumulates channels
-// [8g, 8g + 8) of all nine taps over pixels r0 + rho, r0 + rho + R, ... with
-// 16-byte loads; the R row phases are then summed tap by tap in a fixed
-// order through LDS.  part[block][t C + c], part[block][9 C] = bias.
-__global__ __launch_bounds__(256) void k_head_wgrad_part(const __bf16* __restrict__ X, int H, int W, int C,
+// (C a multiple of 8, at most 256).  blockIdx.y selects a group of nine taps
+// (one group in 2D, three in 3D).  Thread (rho, g) accumulates channels
+// [8g, 8g + 8) of the group's taps over pixels r0 + rho, r0 + rho + R, ...
+// with 16-byte loads; the R row phases are then summed tap by tap in a fixed
+// order through LDS.  part[block][t C + c], part[block][T C] = bias (group 0).
+template <int DIM>
+__global__ __launch_bounds__(256) void k_head_wgrad_part(const __bf16* __restrict__ X, int D, int H, int W, int C,
                                                          const float* __restrict__ dh, int rows_per_block,
                                                          float* __restrict__ part) {
+    using TP = Taps<DIM>;
     __shared__ float red[2048];
     __shared__ float redb[256];
-    const int P = H * W, r0 = blockIdx.x * rows_per_block, r1 = min(P, r0 + rows_per_block);
-    const int n = 9 * C + 1;
+    const int P = D * H * W, r0 = blockIdx.x * rows_per_block, r1 = min(P, r0 + rows_per_block);
+    const int n = TP::T * C + 1;
+    const int tg = 9 * blockIdx.y;
     const int G = C / 8, R = 256 / G;
     const int g = threadIdx.x % G, rho = threadIdx.x / G;
     float acc[9][8];
@@ -327,12 +390,12 @@ __global__ __launch_bounds__(256) void k_head_wgrad_part(const __bf16* __restric
         for (int p = r0 + rho; p < r1; p += R) {
             const float w = dh[p];
             if (g == 0) db += w;
-            const int y = p / W, x = p % W;
+            const int x = p % W, y = (p / W) % H, z = p / (W * H);
 #pragma unroll
             for (int t = 0; t < 9; ++t) {
-                const int yy = y + t / 3 - 1, xx = x + t % 3 - 1;
-                if (yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
-                const bf16x8 v = *(const bf16x8*)(X + (size_t)(yy * W + xx) * C + 8 * g);
+                const int zz = z + TP::dz(tg + t), yy = y + TP::dy(tg + t), xx = x + TP::dx(tg + t);
+                if (zz < 0 || zz >= D || yy < 0 || yy >= H || xx < 0 || xx >= W) continue;
+                const bf16x8 v = *(const bf16x8*)(X + (((size_t)zz * H + yy) * W + xx) * C + 8 * g);
 #pragma unroll
                 for (int j = 0; j < 8; ++j) acc[t][j] += (float)v[j] * w;
             }
@@ -349,14 +412,14 @@ __global__ __launch_bounds__(256) void k_head_wgrad_part(const __bf16* __restric
         for (int c = threadIdx.x; c < C; c += blockDim.x) {
             float sum = 0.0f;
             for (int q = 0; q < R; ++q) sum += red[q * C + c];
-            part[(size_t)blockIdx.x * n + t * C + c] = sum;
+            part[(size_t)blockIdx.x * n + (tg + t) * C + c] = sum;
         }
         __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0 && blockIdx.y == 0) {
         float sum = 0.0f;
         for (int q = 0; q < R; ++q) sum += redb[q * G];
-        part[(size_t)blockIdx.x * n + 9 * C] = sum;
+        part[(size_t)blockIdx.x * n + TP::T * C] = sum;
     }
 }
 
@@ -501,17 +564,17 @@ __global__ void k_adam(float* __restrict__ th, float* __restrict__ m, float* __r
 }
 
 // theta W[t][ci][co] -> forward Wf[t][n = co (padded)][k = ci] and data-gradient
-// Wb[t][n = ci (padded)][k = co] = W[8 - t][ci][co]
-__global__ void k_weights_bf16(const float* __restrict__ W, int cin, int cout, int npf, int npb,
+// Wb[t][n = ci (padded)][k = co] = W[T - 1 - t][ci][co] (the tap of the opposite offset)
+__global__ void k_weights_bf16(const float* __restrict__ W, int T, int cin, int cout, int npf, int npb,
                                __bf16* __restrict__ Wf, __bf16* __restrict__ Wb) {
-    const int nf = 9 * npf * cin, nb = 9 * npb * cout;
+    const int nf = T * npf * cin, nb = T * npb * cout;
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nf; e += gridDim.x * blockDim.x) {
         const int t = e / (npf * cin), n = (e / cin) % npf, k = e % cin;
         Wf[e] = (__bf16)(n < cout ? W[(t * cin + k) * cout + n] : 0.0f);
     }
     for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < nb; e += gridDim.x * blockDim.x) {
         const int t = e / (npb * cout), n = (e / cout) % npb, k = e % cout;
-        Wb[e] = (__bf16)(n < cin ? W[((8 - t) * cin + n) * cout + k] : 0.0f);
+        Wb[e] = (__bf16)(n < cin ? W[((T - 1 - t) * cin + n) * cout + k] : 0.0f);
     }
 }
 
@@ -529,7 +592,8 @@ struct ConvLayer {
 struct UNet {
     int L;
     int ch[kMaxLevels];
-    int H, W;
+    int dim, T;          // 2 or 3; taps per convolution (9 or 27)
+    int D, H, W;         // level-0 image (D = 1 in 2D)
     int body_id, wall_id;
     size_t nparams;
     float *theta, *grad, *m, *v;
@@ -559,28 +623,35 @@ static inline int grid_of(size_t n, int block = 256) {
 static hipError_t launch_conv(const ConvIn& in, const __bf16* Wk, int np, const float* bias, int cout, int relu,
                               __bf16* Y, hipStream_t st) {
     if (np % 32) return hipErrorInvalidValue;
-    const dim3 g((in.W + kCC - 1) / kCC, (in.H + kCR - 1) / kCR, np / 32), b(256);
-    hipLaunchKernelGGL(k_conv_mfma, g, b, 0, st, in, Wk, np, bias, cout, relu, Y);
+    const dim3 g((in.W + kCC - 1) / kCC, (in.H + kCR - 1) / kCR * in.D, np / 32), b(256);
+    if (in.zs)
+        hipLaunchKernelGGL(k_conv_mfma<3>, g, b, 0, st, in, Wk, np, bias, cout, relu, Y);
+    else
+        hipLaunchKernelGGL(k_conv_mfma<2>, g, b, 0, st, in, Wk, np, bias, cout, relu, Y);
     return hipGetLastError();
 }
 
 // weight and bias gradient of one conv layer into u.grad
 static hipError_t layer_grads(UNet& u, const ConvLayer& Lr, const ConvIn& in, const __bf16* dY, hipStream_t st) {
-    const int P = in.H * in.W;
+    const int P = in.D * in.H * in.W;
     const int K = in.c0 + in.c1;
     const int kt = (K + 31) / 32, nt = (Lr.cout + 31) / 32;
-    const size_t tile_floats = (size_t)9 * kt * 32 * nt * 32;
+    const size_t tile_floats = (size_t)u.T * kt * 32 * nt * 32;
     int nchunks = (int)(u.part_cap / tile_floats);
     if (nchunks > 256) nchunks = 256;
     if (nchunks < 1) return hipErrorInvalidValue;
     int chunk = (P + nchunks - 1) / nchunks;
     chunk = (chunk + 15) / 16 * 16;
     nchunks = (P + chunk - 1) / chunk;
-    const int tiles = 9 * kt * nt;
-    hipLaunchKernelGGL(k_conv_wgrad, dim3(nchunks, (tiles + 3) / 4), dim3(256), 0, st, in, dY, Lr.cout, kt, nt,
-                       chunk, u.part);
-    hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid_of((size_t)9 * K * Lr.cout)), dim3(256), 0, st, u.part, nchunks, K,
-                       Lr.cout, kt * 32, nt * 32, u.grad + Lr.w_off);
+    const int tiles = u.T * kt * nt;
+    if (u.dim == 3)
+        hipLaunchKernelGGL(k_conv_wgrad<3>, dim3(nchunks, (tiles + 3) / 4), dim3(256), 0, st, in, dY, Lr.cout, kt, nt,
+                           chunk, u.part);
+    else
+        hipLaunchKernelGGL(k_conv_wgrad<2>, dim3(nchunks, (tiles + 3) / 4), dim3(256), 0, st, in, dY, Lr.cout, kt, nt,
+                           chunk, u.part);
+    hipLaunchKernelGGL(k_wgrad_reduce, dim3(grid_of((size_t)u.T * K * Lr.cout)), dim3(256), 0, st, u.part, nchunks,
+                       u.T, K, Lr.cout, kt * 32, nt * 32, u.grad + Lr.w_off);
     const int rows = (P + 255) / 256;
     const int nb = (P + rows - 1) / rows;
     hipLaunchKernelGGL(k_colsum_part, dim3(nb), dim3(256), 0, st, dY, P, Lr.cout, rows, u.part);
@@ -588,23 +659,41 @@ static hipError_t layer_grads(UNet& u, const ConvLayer& Lr, const ConvIn& in, co
     return hipGetLastError();
 }
 
-static ConvIn conv_in(const __bf16* x0, int c0, const __bf16* x1, int c1, int H, int W) {
-    return ConvIn{x0, c0, x1, c1, H, W};
+// image extent of level l (D = 1 in 2D)
+struct Lvl {
+    int D, H, W;
+    size_t P() const { return (size_t)D * H * W; }
+};
+static Lvl level(const UNet& u, int l) {
+    return Lvl{u.dim == 3 ? u.D >> l : 1, u.H >> l, u.W >> l};
+}
+
+static ConvIn conv_in(const UNet& u, const __bf16* x0, int c0, const __bf16* x1, int c1, const Lvl& v) {
+    return ConvIn{x0, c0, x1, c1, v.D, v.H, v.W, u.dim == 3 ? 1 : 0};
 }
 
 hipError_t unet_weights_to_bf16(UNet& u, hipStream_t st) {
     for (int i = 0; i < u.nlayers - 1; ++i) {
         const ConvLayer& Lr = u.layers[i];
-        hipLaunchKernelGGL(k_weights_bf16, dim3(grid_of((size_t)9 * 256 * 256)), dim3(256), 0, st,
-                           u.theta + Lr.w_off, Lr.cin, Lr.cout, Lr.npf, Lr.npb, Lr.Wf, Lr.Wb);
+        hipLaunchKernelGGL(k_weights_bf16, dim3(grid_of((size_t)u.T * 256 * 256)), dim3(256), 0, st,
+                           u.theta + Lr.w_off, u.T, Lr.cin, Lr.cout, Lr.npf, Lr.npb, Lr.Wf, Lr.Wb);
     }
     return hipGetLastError();
 }
 
+// launch helpers of the dimension-templated element kernels
+#define UNET_LAUNCH(u, kern, grid, ...)                                                        \
+    do {                                                                                       \
+        if ((u).dim == 3)                                                                      \
+            hipLaunchKernelGGL(kern<3>, grid, dim3(256), 0, st, __VA_ARGS__);                  \
+        else                                                                                   \
+            hipLaunchKernelGGL(kern<2>, grid, dim3(256), 0, st, __VA_ARGS__);                  \
+    } while (0)
+
 // Forward pass; leaves the head output h (FP32) and all activations.
 hipError_t unet_forward(UNet& u, const double* b, const double* pprev, const int8_t* role, const BcDev& bc,
                         hipStream_t st) {
-    const int P = u.H * u.W;
+    const int P = (int)level(u, 0).P();
     const int nb = 256;
     hipLaunchKernelGGL(k_sumsq_part, dim3(nb), dim3(256), 0, st, b, pprev, role, bc, P, u.red);
     hipLaunchKernelGGL(k_rms, dim3(1), dim3(256), 0, st, u.red, nb, u.rms);
@@ -612,46 +701,48 @@ hipError_t unet_forward(UNet& u, const double* b, const double* pprev, const int
                        u.rms, u.x0);
     int li = 0;
     for (int l = 0; l < u.L; ++l) {
-        const int H = u.H >> l, W = u.W >> l;
+        const Lvl v = level(u, l);
         const __bf16* src = u.x0;
         int csrc = kIn;
         if (l > 0) {
-            hipLaunchKernelGGL(k_pool, dim3(grid_of((size_t)H * W * u.ch[l - 1])), dim3(256), 0, st, u.eb[l - 1],
-                               H * 2, W * 2, u.ch[l - 1], u.in[l]);
+            const Lvl f = level(u, l - 1);
+            UNET_LAUNCH(u, k_pool, dim3(grid_of(v.P() * u.ch[l - 1])), u.eb[l - 1], f.D, f.H, f.W, u.ch[l - 1],
+                        u.in[l]);
             src = u.in[l];
             csrc = u.ch[l - 1];
         }
         const ConvLayer& A = u.layers[li++];
-        hipError_t e = launch_conv(conv_in(src, csrc, nullptr, 0, H, W), A.Wf, A.npf, u.theta + A.b_off, A.cout, 1,
+        hipError_t e = launch_conv(conv_in(u, src, csrc, nullptr, 0, v), A.Wf, A.npf, u.theta + A.b_off, A.cout, 1,
                                    u.ea[l], st);
         if (e != hipSuccess) return e;
         const ConvLayer& B = u.layers[li++];
-        e = launch_conv(conv_in(u.ea[l], u.ch[l], nullptr, 0, H, W), B.Wf, B.npf, u.theta + B.b_off, B.cout, 1,
+        e = launch_conv(conv_in(u, u.ea[l], u.ch[l], nullptr, 0, v), B.Wf, B.npf, u.theta + B.b_off, B.cout, 1,
                         u.eb[l], st);
         if (e != hipSuccess) return e;
     }
     for (int l = u.L - 2; l >= 0; --l) {
-        const int H = u.H >> l, W = u.W >> l;
+        const Lvl v = level(u, l);
         const __bf16* coarse = (l + 1 == u.L - 1) ? u.eb[l + 1] : u.db[l + 1];
         const ConvLayer& A = u.layers[li++];
-        hipError_t e = launch_conv(conv_in(u.eb[l], u.ch[l], coarse, u.ch[l + 1], H, W), A.Wf, A.npf,
+        hipError_t e = launch_conv(conv_in(u, u.eb[l], u.ch[l], coarse, u.ch[l + 1], v), A.Wf, A.npf,
                                    u.theta + A.b_off, A.cout, 1, u.da[l], st);
         if (e != hipSuccess) return e;
         const ConvLayer& B = u.layers[li++];
-        e = launch_conv(conv_in(u.da[l], u.ch[l], nullptr, 0, H, W), B.Wf, B.npf, u.theta + B.b_off, B.cout, 1,
+        e = launch_conv(conv_in(u, u.da[l], u.ch[l], nullptr, 0, v), B.Wf, B.npf, u.theta + B.b_off, B.cout, 1,
                         u.db[l], st);
         if (e != hipSuccess) return e;
     }
     const ConvLayer& Hd = u.layers[li];
     const __bf16* last = u.L > 1 ? u.db[0] : u.eb[0];
-    hipLaunchKernelGGL(k_head_fwd, dim3(grid_of(P)), dim3(256), 0, st, last, u.H, u.W, u.ch[0], u.theta + Hd.w_off,
-                       u.theta + Hd.b_off, u.h);
+    UNET_LAUNCH(u, k_head_fwd, dim3(grid_of(P)), last, u.D, u.H, u.W, u.ch[0], u.theta + Hd.w_off,
+                u.theta + Hd.b_off, u.h);
     return hipGetLastError();
 }
 
-static hipError_t bwd_data(const ConvLayer& Lr, const __bf16* dY, int H, int W, __bf16* dX, hipStream_t st) {
+static hipError_t bwd_data(const UNet& u, const ConvLayer& Lr, const __bf16* dY, const Lvl& v, __bf16* dX,
+                           hipStream_t st) {
     // data gradient = forward convolution of dY with the flipped, transposed weights
-    return launch_conv(conv_in(dY, Lr.cout, nullptr, 0, H, W), Lr.Wb, Lr.npb, nullptr, Lr.cin, 0, dX, st);
+    return launch_conv(conv_in(u, dY, Lr.cout, nullptr, 0, v), Lr.Wb, Lr.npb, nullptr, Lr.cin, 0, dX, st);
 }
 
 // Forward, loss against the target pressure, backward, Adam step.
@@ -659,7 +750,7 @@ hipError_t unet_train_step(UNet& u, const double* b, const double* pprev, const 
                            const BcDev& bc, float lr, hipStream_t st, double* loss_out) {
     hipError_t e = unet_forward(u, b, pprev, role, bc, st);
     if (e != hipSuccess) return e;
-    const int P = u.H * u.W;
+    const int P = (int)level(u, 0).P();
     const int nb = 256;
     hipLaunchKernelGGL(k_loss_part, dim3(nb), dim3(256), 0, st, u.h, Pt, pprev, role, bc, P, u.rms, u.out_scale,
                        u.red);
@@ -672,51 +763,53 @@ hipError_t unet_train_step(UNet& u, const double* b, const double* pprev, const 
     const int C0 = u.ch[0];
     const __bf16* last = u.L > 1 ? u.db[0] : u.eb[0];
     __bf16* g_last = u.L > 1 ? u.g_db[0] : u.g_eb[0];
-    hipLaunchKernelGGL(k_head_bwd_data, dim3(grid_of((size_t)P * C0)), dim3(256), 0, st, u.dh, u.H, u.W, C0,
-                       u.theta + Hd.w_off, g_last);
+    UNET_LAUNCH(u, k_head_bwd_data, dim3(grid_of((size_t)P * C0)), u.dh, u.D, u.H, u.W, C0, u.theta + Hd.w_off,
+                g_last);
     {
         const int rows = (P + 255) / 256, nblk = (P + rows - 1) / rows;
-        hipLaunchKernelGGL(k_head_wgrad_part, dim3(nblk), dim3(256), 0, st, last, u.H, u.W, C0, u.dh, rows, u.part);
-        hipLaunchKernelGGL(k_colsum_reduce, dim3(1), dim3(256), 0, st, u.part, nblk, 9 * C0 + 1, u.grad + Hd.w_off);
+        UNET_LAUNCH(u, k_head_wgrad_part, dim3(nblk, u.T / 9), last, u.D, u.H, u.W, C0, u.dh, rows, u.part);
+        hipLaunchKernelGGL(k_colsum_reduce, dim3(1), dim3(256), 0, st, u.part, nblk, u.T * C0 + 1,
+                           u.grad + Hd.w_off);
     }
     // decoder, unwound from level 0 upwards (layer index of dec(l)a: 2L + 2(L-2-l))
     for (int l = 0; l <= u.L - 2; ++l) {
-        const int H = u.H >> l, W = u.W >> l;
-        const size_t n = (size_t)H * W * u.ch[l];
+        const Lvl v = level(u, l);
+        const size_t n = v.P() * u.ch[l];
         const ConvLayer& A = u.layers[2 * u.L + 2 * (u.L - 2 - l)];
         const ConvLayer& B = u.layers[2 * u.L + 2 * (u.L - 2 - l) + 1];
         hipLaunchKernelGGL(k_relu_mask, dim3(grid_of(n)), dim3(256), 0, st, u.g_db[l], u.db[l], n);
-        if ((e = layer_grads(u, B, conv_in(u.da[l], u.ch[l], nullptr, 0, H, W), u.g_db[l], st)) != hipSuccess)
+        if ((e = layer_grads(u, B, conv_in(u, u.da[l], u.ch[l], nullptr, 0, v), u.g_db[l], st)) != hipSuccess)
             return e;
-        if ((e = bwd_data(B, u.g_db[l], H, W, u.g_da[l], st)) != hipSuccess) return e;
+        if ((e = bwd_data(u, B, u.g_db[l], v, u.g_da[l], st)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_relu_mask, dim3(grid_of(n)), dim3(256), 0, st, u.g_da[l], u.da[l], n);
         const __bf16* coarse = (l + 1 == u.L - 1) ? u.eb[l + 1] : u.db[l + 1];
-        if ((e = layer_grads(u, A, conv_in(u.eb[l], u.ch[l], coarse, u.ch[l + 1], H, W), u.g_da[l], st)) !=
+        if ((e = layer_grads(u, A, conv_in(u, u.eb[l], u.ch[l], coarse, u.ch[l + 1], v), u.g_da[l], st)) !=
             hipSuccess)
             return e;
-        if ((e = bwd_data(A, u.g_da[l], H, W, u.g_cat, st)) != hipSuccess) return e;
+        if ((e = bwd_data(u, A, u.g_da[l], v, u.g_cat, st)) != hipSuccess) return e;
         __bf16* gcoarse = (l + 1 == u.L - 1) ? u.g_eb[l + 1] : u.g_db[l + 1];
-        hipLaunchKernelGGL(k_cat_split, dim3(grid_of((size_t)H * W * u.ch[l])), dim3(256), 0, st, u.g_cat, H, W,
-                           u.ch[l], u.ch[l + 1], u.g_eb[l], gcoarse);
+        UNET_LAUNCH(u, k_cat_split, dim3(grid_of(v.P() * u.ch[l])), u.g_cat, v.D, v.H, v.W, u.ch[l], u.ch[l + 1],
+                    u.g_eb[l], gcoarse);
     }
     // encoder, from the bottom
     for (int l = u.L - 1; l >= 0; --l) {
-        const int H = u.H >> l, W = u.W >> l;
-        const size_t n = (size_t)H * W * u.ch[l];
+        const Lvl v = level(u, l);
+        const size_t n = v.P() * u.ch[l];
         const ConvLayer& A = u.layers[2 * l];
         const ConvLayer& B = u.layers[2 * l + 1];
         hipLaunchKernelGGL(k_relu_mask, dim3(grid_of(n)), dim3(256), 0, st, u.g_eb[l], u.eb[l], n);
-        if ((e = layer_grads(u, B, conv_in(u.ea[l], u.ch[l], nullptr, 0, H, W), u.g_eb[l], st)) != hipSuccess)
+        if ((e = layer_grads(u, B, conv_in(u, u.ea[l], u.ch[l], nullptr, 0, v), u.g_eb[l], st)) != hipSuccess)
             return e;
-        if ((e = bwd_data(B, u.g_eb[l], H, W, u.g_ea[l], st)) != hipSuccess) return e;
+        if ((e = bwd_data(u, B, u.g_eb[l], v, u.g_ea[l], st)) != hipSuccess) return e;
         hipLaunchKernelGGL(k_relu_mask, dim3(grid_of(n)), dim3(256), 0, st, u.g_ea[l], u.ea[l], n);
         const __bf16* src = l > 0 ? u.in[l] : u.x0;
         const int csrc = l > 0 ? u.ch[l - 1] : kIn;
-        if ((e = layer_grads(u, A, conv_in(src, csrc, nullptr, 0, H, W), u.g_ea[l], st)) != hipSuccess) return e;
+        if ((e = layer_grads(u, A, conv_in(u, src, csrc, nullptr, 0, v), u.g_ea[l], st)) != hipSuccess) return e;
         if (l > 0) {
-            if ((e = bwd_data(A, u.g_ea[l], H, W, u.g_in[l], st)) != hipSuccess) return e;
-            hipLaunchKernelGGL(k_pool_bwd_add, dim3(grid_of((size_t)4 * H * W * u.ch[l - 1])), dim3(256), 0, st,
-                               u.g_in[l], 2 * H, 2 * W, u.ch[l - 1], u.g_eb[l - 1]);
+            if ((e = bwd_data(u, A, u.g_ea[l], v, u.g_in[l], st)) != hipSuccess) return e;
+            const Lvl f = level(u, l - 1);
+            UNET_LAUNCH(u, k_pool_bwd_add, dim3(grid_of(f.P() * u.ch[l - 1])), u.g_in[l], f.D, f.H, f.W,
+                        u.ch[l - 1], u.g_eb[l - 1]);
         }
     }
     u.step += 1;
@@ -740,7 +833,7 @@ hipError_t unet_infer(UNet& u, const double* b, const double* pprev, const int8_
                       double* out, hipStream_t st) {
     hipError_t e = unet_forward(u, b, pprev, role, bc, st);
     if (e != hipSuccess) return e;
-    const int P = u.H * u.W;
+    const int P = (int)level(u, 0).P();
     hipLaunchKernelGGL(k_unpack, dim3(grid_of(P)), dim3(256), 0, st, u.h, pprev, role, bc, P, u.rms, u.out_scale,
                        out);
     return hipGetLastError();
@@ -772,11 +865,14 @@ void unet_free(UNet* u) {
 }
 
 // Layer table in the flat parameter order: enc0a, enc0b, ..., dec(L-2)a,
-// dec(L-2)b, ..., dec0a, dec0b, head; each W[9][cin][cout] then b[cout].
-hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall_id, UNet** out) {
+// dec(L-2)b, ..., dec0a, dec0b, head; each W[T][cin][cout] then b[cout].
+hipError_t unet_create(int dim, int D, int H, int W, int L, const int* ch, int body_id, int wall_id, UNet** out) {
     UNet* u = new UNet{};
     *out = u;
     u->L = L;
+    u->dim = dim;
+    u->T = dim == 3 ? 27 : 9;
+    u->D = dim == 3 ? D : 1;
     u->H = H;
     u->W = W;
     u->body_id = body_id;
@@ -790,7 +886,7 @@ hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall
         Lr.cin = cin;
         Lr.cout = cout;
         Lr.w_off = off;
-        off += (size_t)9 * cin * cout;
+        off += (size_t)u->T * cin * cout;
         Lr.b_off = off;
         off += cout;
         Lr.npf = (cout + 31) / 32 * 32;
@@ -817,14 +913,14 @@ hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall
     if ((e = dalloc((void**)&u->v, np * 4)) != hipSuccess) return e;
     for (int i = 0; i < n - 1; ++i) {
         ConvLayer& Lr = u->layers[i];
-        if ((e = dalloc((void**)&Lr.Wf, (size_t)9 * Lr.npf * Lr.cin * 2)) != hipSuccess) return e;
-        if ((e = dalloc((void**)&Lr.Wb, (size_t)9 * Lr.npb * Lr.cout * 2)) != hipSuccess) return e;
+        if ((e = dalloc((void**)&Lr.Wf, (size_t)u->T * Lr.npf * Lr.cin * 2)) != hipSuccess) return e;
+        if ((e = dalloc((void**)&Lr.Wb, (size_t)u->T * Lr.npb * Lr.cout * 2)) != hipSuccess) return e;
     }
-    const size_t P = (size_t)H * W;
+    const size_t P = level(*u, 0).P();
     if ((e = dalloc((void**)&u->x0, P * kIn * 2)) != hipSuccess) return e;
     size_t catmax = 0, partmax = 0;
     for (int l = 0; l < L; ++l) {
-        const size_t Pl = P >> (2 * l);
+        const size_t Pl = level(*u, l).P();
         const size_t c = ch[l];
         if (l > 0 && (e = dalloc((void**)&u->in[l], Pl * ch[l - 1] * 2)) != hipSuccess) return e;
         if (l > 0 && (e = dalloc((void**)&u->g_in[l], Pl * ch[l - 1] * 2)) != hipSuccess) return e;
@@ -842,10 +938,11 @@ hipError_t unet_create(int H, int W, int L, const int* ch, int body_id, int wall
     }
     for (int i = 0; i < n; ++i) {
         const size_t kt = (u->layers[i].cin + 31) / 32, nt = (u->layers[i].cout + 31) / 32;
-        const size_t t = 9 * kt * 32 * nt * 32;
+        const size_t t = (size_t)u->T * kt * 32 * nt * 32;
         partmax = partmax > t ? partmax : t;
     }
-    u->part_cap = partmax * 64 > (size_t)(256 * (9 * 256 + 1)) ? partmax * 64 : (size_t)(256 * (9 * 256 + 1));
+    const size_t head_part = (size_t)256 * (u->T * 256 + 1);
+    u->part_cap = partmax * 64 > head_part ? partmax * 64 : head_part;
     if ((e = dalloc((void**)&u->g_cat, (catmax ? catmax : 16) * 2)) != hipSuccess) return e;
     if ((e = dalloc((void**)&u->h, P * 4)) != hipSuccess) return e;
     if ((e = dalloc((void**)&u->dh, P * 4)) != hipSuccess) return e;

@@ -8,9 +8,10 @@ solve still runs to the same tolerance, so the guess changes the iteration
 count and never the accepted solution.
 
 Data set: C2-shaped trajectories (configs.c3_cylinder_variant: seeded
-amplitude, frequency and DP jitter) run with the plain method and the warm
-start.  After a spin-up, every step k -> k+1 gives one sample
-(r, P^k, roles, P^{k+1}); P^{k+1} is the converged FP64 solution.
+amplitude, frequency and DP jitter), or C4-shaped ones for the 3D network
+(configs.c4_sphere_variant), run with the plain method and the warm start.
+After a spin-up, every step k -> k+1 gives one sample (r, P^k, roles,
+P^{k+1}); P^{k+1} is the converged FP64 solution.
 
 Everything here sequences libmcd calls; samples stay in device memory.
 """
@@ -49,11 +50,15 @@ def unknown_mask(role, bc):
     return unk
 
 
-def collect(seeds, n, n_spin, n_save, log=print):
+VARIANTS = {"cylinder": configs.c3_cylinder_variant, "sphere": configs.c4_sphere_variant}
+BASE_CASES = {"cylinder": configs.c2_oscillating_cylinder, "sphere": configs.c4_moving_sphere}
+
+
+def collect(seeds, n, n_spin, n_save, log=print, flow="cylinder"):
     """Samples of the trajectories `seeds` (plain FP64 method, warm start)."""
     out = []
     for seed in seeds:
-        case = configs.c3_cylinder_variant(seed, n=n)
+        case = VARIANTS[flow](seed, n=n)
         sim = GpuSim(case, update_info=False)
         t0 = time.perf_counter()
         iters = []
@@ -127,7 +132,7 @@ def eval_loss(model, samples, bc):
 
 
 def evaluate(model, seeds, n, n_spin, n_eval, modes=("zero", "warm", "learned"), precision=M.PREC_FP64,
-             log=print):
+             log=print, flow="cylinder"):
     """Held-out trajectories: at every evaluated step each mode solves the
     same PPE from its own guess; the trajectory advances with the warm-start
     solution.  A mode is a guess ('zero', 'warm', 'learned'), optionally with
@@ -137,7 +142,7 @@ def evaluate(model, seeds, n, n_spin, n_eval, modes=("zero", "warm", "learned"),
         raise ValueError("evaluation advances with the warm-start solution; include 'warm'")
     res = {m: {"iters": [], "rel0": [], "ms": []} for m in modes}
     for seed in seeds:
-        case = configs.c3_cylinder_variant(seed, n=n)
+        case = VARIANTS[flow](seed, n=n)
         sim = GpuSim(case, precision=precision, update_info=False, model=model)
         r = torch.empty_like(sim.P)
         for k in range(n_spin + n_eval):
@@ -209,7 +214,7 @@ def load_model(ctx, path):
     return model
 
 
-def init_theta(channels, seed):
+def init_theta(channels, seed, dim=2):
     """He-normal weights with a zero head: the untrained guess is the warm start."""
     from .inputs import he_normal_params
     shapes, prev = [], 16
@@ -219,8 +224,9 @@ def init_theta(channels, seed):
     for l in range(len(channels) - 2, -1, -1):
         shapes += [(channels[l] + channels[l + 1], channels[l]), (channels[l], channels[l])]
     shapes.append((channels[0], 1))
-    theta = he_normal_params(shapes, seed)
-    theta[-(9 * channels[0] + 1):] = 0.0
+    taps = 3 ** dim
+    theta = he_normal_params(shapes, seed, taps=taps)
+    theta[-(taps * channels[0] + 1):] = 0.0
     return theta
 
 
@@ -231,7 +237,9 @@ def _seeds(spec):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description="train and evaluate the learned PPE initial guess")
-    ap.add_argument("--n", type=int, default=1024)
+    ap.add_argument("--flow", choices=sorted(VARIANTS), default="cylinder",
+                    help="cylinder: 2D network on C2-shaped flows; sphere: 3D network on C4-shaped flows")
+    ap.add_argument("--n", type=int, default=None, help="mesh cells per axis (default 1024 in 2D, 128 in 3D)")
     ap.add_argument("--channels", default="16,32,64,128")
     ap.add_argument("--train-seeds", default="1000-1019")
     ap.add_argument("--test-seeds", default="2000-2004")
@@ -251,21 +259,24 @@ def main(argv=None):
         raise SystemExit("the learned guess runs on the GPU only")
     M.load()
     ch = tuple(int(c) for c in a.channels.split(","))
-    bc = configs.c2_oscillating_cylinder(n=a.n).bc_pressure
-    ctx = M.Context.from_case(configs.c2_oscillating_cylinder(n=a.n))
-    summary = {"n": a.n, "channels": ch}
+    if a.n is None:
+        a.n = 1024 if a.flow == "cylinder" else 128
+    base = BASE_CASES[a.flow](n=a.n)
+    bc = base.bc_pressure
+    ctx = M.Context.from_case(base)
+    summary = {"flow": a.flow, "n": a.n, "channels": ch}
     if a.weights:
         model = load_model(ctx, a.weights)
     else:
         t0 = time.perf_counter()
-        data = collect(_seeds(a.train_seeds), a.n, a.spin, a.save)
+        data = collect(_seeds(a.train_seeds), a.n, a.spin, a.save, flow=a.flow)
         summary["collect_s"] = time.perf_counter() - t0
         summary["samples"] = len(data)
         hold = data[-max(1, len(data) // 20):]
         train_set = data[:len(data) - len(hold)]
         scale = output_scale(train_set, bc)
         model = M.Model(ctx, ch)
-        model.set_params(init_theta(ch, a.seed))
+        model.set_params(init_theta(ch, a.seed, dim=base.dim))
         model.set_output_scale(scale)
         summary["output_scale"] = scale
         summary["val_loss_before"] = eval_loss(model, hold, bc)
@@ -275,9 +286,11 @@ def main(argv=None):
         summary["val_loss_after"] = eval_loss(model, hold, bc)
         print(f"val loss {summary['val_loss_before']:.4g} -> {summary['val_loss_after']:.4g}", flush=True)
         if a.out:
-            save_weights(a.out, model, scale, a.n, {"train_seeds": a.train_seeds, "epochs": a.epochs, "lr": a.lr})
+            save_weights(a.out, model, scale, a.n, {"flow": a.flow, "train_seeds": a.train_seeds,
+                                                    "epochs": a.epochs, "lr": a.lr})
         del data, train_set, hold
-    res = evaluate(model, _seeds(a.test_seeds), a.n, a.spin, a.eval_steps, modes=tuple(a.modes.split(",")))
+    res = evaluate(model, _seeds(a.test_seeds), a.n, a.spin, a.eval_steps, modes=tuple(a.modes.split(",")),
+                   flow=a.flow)
     summary["eval"] = summarize(res)
     print(json.dumps(summary), flush=True)
     if a.json:

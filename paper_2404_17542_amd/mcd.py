@@ -377,7 +377,7 @@ class Context:
 
 
 class Model:
-    """Learned initial guess (U-Net) bound to a 2D context."""
+    """Learned initial guess (U-Net) bound to a context (2D or 3D mesh)."""
 
     def __init__(self, ctx: Context, channels=(16, 32, 64, 128), body_id=2):
         import numpy as np
