@@ -6,7 +6,9 @@ u* and the PPE right-hand side, Bi-CGSTAB to a true relative residual of
 1e-8 (FP64), projection.  Inputs are resident in HBM before the timed
 region starts.  Prints one JSON line.
 
-Other forms: --workload cylinder|sphere, --precision mixed (FP32-stored
+Other forms: --workload cylinder|sphere|manufactured (the last: the 32x32
+manufactured-solution Poisson problem, a step being the MLS build plus one
+PPE solve from zero, a latency figure), --precision mixed (FP32-stored
 matrix with FP64 residual replacement) or refine (FP32 Bi-CGSTAB inside
 FP64 refinement), --guess zero|learned (--weights: a file written by
 paper_2404_17542_amd.learned).  The tolerance is judged on the FP64
@@ -95,12 +97,84 @@ def cpu_baseline(case, steps):
                       f"{os.cpu_count()} logical CPUs"}
 
 
+def bench_manufactured(args):
+    """32x32 unit square, p = sin 2pi x sin 2pi y with Dirichlet walls and the
+    Gaussian weight: each step rebuilds the weights and solves the PPE from
+    zero to 1e-8 (FP64).  Latency of the smallest configuration."""
+    import numpy as np
+    import torch
+
+    from paper_2404_17542_amd import configs, inputs, mcd
+    from paper_2404_17542_amd.sim import GpuSim
+
+    torch.cuda.set_device(0)
+    mcd.load()
+    case = configs.c0_manufactured(n=args.n or 32)
+    sim = GpuSim(case, update_info=False)
+    ctx = sim.ctx
+    pos_h = sim.pos.cpu().numpy()
+    role_h = sim.role.cpu().numpy()
+    rhs = torch.tensor(inputs.manufactured_rhs(pos_h), dtype=torch.float64, device="cuda")
+    g = np.where(role_h == mcd.ROLE_INNER, 0.0, inputs.manufactured_pressure(pos_h))
+    p0 = torch.tensor(g, dtype=torch.float64, device="cuda")
+    p = p0.clone()
+
+    def step():
+        ctx.build_stencils(0, sim.pos, sim.role, sim.normal, case.bc_pressure)
+        p.copy_(p0)
+        return ctx.solve_ppe(0, rhs, p, tol=1e-8, guess=mcd.GUESS_ZERO)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    infos = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        infos.append(step())
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    assert all(i["converged"] for i in infos)
+    n_active = int((role_h != mcd.ROLE_VOID).sum())
+    err = np.abs(p.cpu().numpy() - inputs.manufactured_pressure(pos_h))[role_h == mcd.ROLE_INNER].max()
+    out = {"metric": METRIC, "value": n_active * args.steps / elapsed, "unit": "DP-steps/s", "n_gpus": 1,
+           "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": f"manufactured Poisson p = sin(2 pi x) sin(2 pi y), unit square "
+                                  f"{case.n[0]}x{case.n[1]}, {n_active} DPs (+-0.2 l0 jitter, walls on the "
+                                  f"boundary), Gaussian-weight quadratic MLS 3x3, Dirichlet walls, one PPE "
+                                  f"solve from zero to 1e-8 (FP64) per step",
+                      "dps": n_active, "precision": "fp64", "initial_guess": "zero",
+                      "ppe_iters_per_step": sum(i["iterations"] for i in infos) / len(infos),
+                      "max_true_rel_res": max(i["true_rel_residual"] for i in infos),
+                      "max_abs_error_vs_exact": float(err)},
+           "roofline": None}
+    if not args.no_cpu_baseline:
+        from threadpoolctl import threadpool_limits
+
+        from oracle import mcd_oracle as O
+        m = O.Mesh.from_case(case)
+        nrm = sim.normal.cpu().numpy()
+        with threadpool_limits(limits=1):
+            reps = 0
+            t0 = time.perf_counter()
+            while reps < 5 or time.perf_counter() - t0 < 2.0:
+                st = O.mls_build(m, pos_h, role_h, nrm, case.bc_pressure, case.re_over_l0 * case.l0, case.l0,
+                                 case.weight)
+                O.solve_ppe(m, st, role_h, case.bc_pressure, inputs.manufactured_rhs(pos_h), g, None, 1e-8)
+                reps += 1
+            dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": n_active * reps / dt, "unit": "DP-steps/s", "cores": 1, "kind": "oracle",
+                               "sample": f"{reps} steps (MLS build + PPE solve) of the same problem, numpy/scipy "
+                                         f"FP64, 1 thread, {dt:.1f} s"}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["tgv", "cylinder", "sphere"], default="tgv",
+    ap.add_argument("--workload", choices=["tgv", "cylinder", "sphere", "manufactured"], default="tgv",
                     help="tgv: 512^2 periodic Taylor-Green (default line); cylinder: 1024^2 oscillating "
                          "cylinder; sphere: 128^3 moving sphere")
     ap.add_argument("--n", type=int, default=None)
@@ -122,6 +196,9 @@ def main():
         print(f"bench.py runs on one GPU only (asked for {args.gpus}); the multi-GPU design is not built.",
               file=sys.stderr)
         sys.exit(2)
+
+    if args.workload == "manufactured":
+        return bench_manufactured(args)
 
     import torch
 

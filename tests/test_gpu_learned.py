@@ -53,3 +53,33 @@ def test_learned_guess_gain_on_held_out_trajectory(L):
     # a few per cent either way), which this test records but does not claim
     assert s["learned_vs_zero_iter_ratio"] < 0.97, msg
     assert 0.8 < s["learned_vs_warm_iter_ratio"] < 1.2, msg
+
+
+def test_learned_guess_3d_on_held_out_sphere_trajectory(L):
+    """The 3D network (27-tap convolutions) trained on PPE solves of four
+    seeded moving-sphere trajectories (32^3 mesh): the held-out loss falls
+    below the warm start's, and every held-out PPE still reaches the
+    tolerance from every start."""
+    from paper_2404_17542_amd import configs, mcd as M
+    n, ch = 32, (16, 32, 64)
+    bc = configs.c4_moving_sphere(n=n).bc_pressure
+    data = L.collect(range(1000, 1004), n, n_spin=6, n_save=30, log=lambda *_: None, flow="sphere")
+    held = L.collect([2000], n, n_spin=6, n_save=6, log=lambda *_: None, flow="sphere")
+    ctx = M.Context.from_case(configs.c4_moving_sphere(n=n))
+    model = M.Model(ctx, ch)
+    model.set_params(L.init_theta(ch, 0, dim=3))
+    model.set_output_scale(L.output_scale(data, bc))
+    before = L.eval_loss(model, held, bc)
+    L.train(model, data, bc, epochs=8, lr=5e-4, seed=0, log=lambda *_: None)
+    after = L.eval_loss(model, held, bc)
+    modes = ("zero", "warm+jacobi", "learned", "warm")
+    res = L.evaluate(model, [2000], n, n_spin=6, n_eval=6, modes=modes, log=lambda *_: None, flow="sphere")
+    s = L.summarize(res)
+    print({"loss_before": before, "loss_after": after, **s})
+    assert before == pytest.approx(1.0)
+    assert after < 0.7, after             # measured 0.34
+    assert all(np.isfinite(v) for m in modes for v in res[m]["iters"]), s
+    # the guess's initial residual is well below the warm start's (measured
+    # 0.41 x); at 32^3 a solve takes only ~40 iterations, and the count is
+    # about that of the warm start, which this test records but does not claim
+    assert s["learned"]["mean_rel0"] < 0.7 * s["warm"]["mean_rel0"], s
