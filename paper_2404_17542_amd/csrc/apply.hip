@@ -1,9 +1,59 @@
 // Applying MLS weights (Eq. intrp_chi_1 and its derivatives) and the
 // fractional-step glue of Sec. 3.3 / Appendix A.  One thread per DP; the
 // weight planes are read coalesced, neighbour field values hit L1/L2.
+// Vector fields (velocity components) share one pass over the weights: each
+// weight is read once and applied to every component, since the weight
+// planes (NB x (S+1) doubles per DP, 2 KB in 3D) are most of the bytes.
 #include "common.h"
 
 namespace mcd {
+
+// Phi of NC scalar fields at cell c in one pass over the weight planes:
+// Phi[k] = sum_value W_j (f_kj - f_kc) + sum_Neumann W^N_j g_kj, field k at
+// fld + k Nc, its Neumann data at fneu + k Nc (fneu may be null).  Per
+// component the operations and their order are those of a single field.
+template <int DIM, int NC>
+__device__ __forceinline__ void poly_multi(const MeshDev& m, const SetDev& st, int c, const int ijk[3],
+                                           const double* __restrict__ fld, const double* __restrict__ fneu,
+                                           double (&Phi)[NC][Dims<DIM>::NB]) {
+    constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
+    const size_t Nc = (size_t)m.Nc;
+#pragma unroll
+    for (int k = 0; k < NC; ++k)
+#pragma unroll
+        for (int q = 0; q < NB; ++q) Phi[k][q] = 0.0;
+    const uint32_t vm = st.vmask[c], nm = st.nmask[c];
+    if ((vm | nm) == 0) return;
+    double fc[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) fc[k] = fld[k * Nc + c];
+    for (int s = 0; s < S; ++s) {
+        if (s == CEN) continue;
+        const bool v = (vm >> s) & 1u;
+        const bool n = fneu && ((nm >> s) & 1u);
+        if (!v && !n) continue;
+        int j;
+        double sh[3];
+        neighbour<DIM>(m, ijk, s, j, sh);
+        double d[NC];
+#pragma unroll
+        for (int k = 0; k < NC; ++k) d[k] = v ? fld[k * Nc + j] - fc[k] : fneu[k * Nc + j];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const double w = st.phi[((size_t)q * (S + 1) + s) * Nc + c];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) Phi[k][q] += w * d[k];
+        }
+    }
+    if (fneu && ((nm >> S) & 1u)) {
+#pragma unroll
+        for (int q = 0; q < NB; ++q) {
+            const double w = st.phi[((size_t)q * (S + 1) + S) * Nc + c];
+#pragma unroll
+            for (int k = 0; k < NC; ++k) Phi[k][q] += w * fneu[k * Nc + c];
+        }
+    }
+}
 
 // Phi at cell c for scalar field fld: sum_value W_j (f_j - f_c) + sum_Neumann W^N_j g_j.
 template <int DIM>
@@ -70,24 +120,38 @@ __global__ __launch_bounds__(kBlock) void k_apply(MeshDev m, SetDev st, int op, 
                 for (int a = 0; a < DIM; ++a) out[a * Nc + c] = Phi[a] / rs * scale;
             }
         } else if (op == MCD_OP_DIV) {
+            double P3[DIM][NB];
+            poly_multi<DIM, DIM>(m, st, c, ijk, in, fneu, P3);
             double acc = 0.0;
-            for (int a = 0; a < DIM; ++a) {
-                poly_at<DIM>(m, st, c, ijk, in + a * Nc, fneu ? fneu + a * Nc : nullptr, Phi);
-                acc += Phi[a] / rs;
-            }
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) acc += P3[a][a] / rs;
             out[c] = acc * scale;
         } else if (op == MCD_OP_LAP) {
-            for (int k = 0; k < ncomp; ++k) {
-                poly_at<DIM>(m, st, c, ijk, in + k * Nc, fneu ? fneu + k * Nc : nullptr, Phi);
-                out[k * Nc + c] = diag2<DIM>(Phi) / (rs * rs) * scale;
+            if (ncomp == DIM) {
+                double P3[DIM][NB];
+                poly_multi<DIM, DIM>(m, st, c, ijk, in, fneu, P3);
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) out[k * Nc + c] = diag2<DIM>(P3[k]) / (rs * rs) * scale;
+            } else {
+                for (int k = 0; k < ncomp; ++k) {
+                    poly_at<DIM>(m, st, c, ijk, in + k * Nc, fneu ? fneu + k * Nc : nullptr, Phi);
+                    out[k * Nc + c] = diag2<DIM>(Phi) / (rs * rs) * scale;
+                }
             }
         } else {  // MCD_OP_SHIFT
             double sv[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) sv[a] = shift[a * Nc + c];
-            for (int k = 0; k < ncomp; ++k) {
-                poly_at<DIM>(m, st, c, ijk, in + k * Nc, fneu ? fneu + k * Nc : nullptr, Phi);
-                out[k * Nc + c] = taylor<DIM>(in[k * Nc + c], Phi, sv, rs);
+            if (ncomp == DIM) {
+                double P3[DIM][NB];
+                poly_multi<DIM, DIM>(m, st, c, ijk, in, fneu, P3);
+#pragma unroll
+                for (int k = 0; k < DIM; ++k) out[k * Nc + c] = taylor<DIM>(in[k * Nc + c], P3[k], sv, rs);
+            } else {
+                for (int k = 0; k < ncomp; ++k) {
+                    poly_at<DIM>(m, st, c, ijk, in + k * Nc, fneu ? fneu + k * Nc : nullptr, Phi);
+                    out[k * Nc + c] = taylor<DIM>(in[k * Nc + c], Phi, sv, rs);
+                }
             }
         }
     }
@@ -138,11 +202,10 @@ __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const do
             double dx[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) dx[a] = pos[a * Nc + c] - pos_prev[a * Nc + src];
-            for (int a = 0; a < DIM; ++a) {
-                double Phi[NB];
-                poly_at<DIM>(m, sp, src, sijk, u + a * Nc, nullptr, Phi);
-                out[a * Nc + c] = taylor<DIM>(u[a * Nc + src], Phi, dx, sp.rs);
-            }
+            double P3[DIM][NB];
+            poly_multi<DIM, DIM>(m, sp, src, sijk, u, nullptr, P3);
+#pragma unroll
+            for (int a = 0; a < DIM; ++a) out[a * Nc + c] = taylor<DIM>(u[a * Nc + src], P3[a], dx, sp.rs);
         } else {
             double v[DIM];
 #pragma unroll
@@ -174,11 +237,12 @@ __global__ __launch_bounds__(kBlock) void k_advect_diffuse(MeshDev m, SetDev st,
             double sh[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) sh[a] = -ut[a * Nc + c] * dt;
+            double P3[DIM][NB];
+            poly_multi<DIM, DIM>(m, st, c, ijk, ut, nullptr, P3);
+#pragma unroll
             for (int a = 0; a < DIM; ++a) {
-                double Phi[NB];
-                poly_at<DIM>(m, st, c, ijk, ut + a * Nc, nullptr, Phi);
-                const double fm = taylor<DIM>(ut[a * Nc + c], Phi, sh, rs);
-                ustar[a * Nc + c] = fm + nu * dt * (diag2<DIM>(Phi) / (rs * rs));
+                const double fm = taylor<DIM>(ut[a * Nc + c], P3[a], sh, rs);
+                ustar[a * Nc + c] = fm + nu * dt * (diag2<DIM>(P3[a]) / (rs * rs));
             }
         } else {
             double v[DIM];

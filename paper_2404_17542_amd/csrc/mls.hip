@@ -98,7 +98,9 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                 }
             }
         }
-        // Cholesky M = L L^T in place (packed lower triangle)
+        // Cholesky M = L L^T in place (packed lower triangle); the diagonal
+        // slots keep 1 / L_jj, so that the triangular solves of pass 2
+        // multiply instead of divide
         double tr = 0.0;
 #pragma unroll
         for (int r = 0; r < NB; ++r) tr += M[r * (r + 1) / 2 + r];
@@ -116,8 +118,8 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                     dsum = 1.0;
                 }
                 const double ljj = sqrt(dsum);
-                M[jc * (jc + 1) / 2 + jc] = ljj;
                 const double inv = 1.0 / ljj;
+                M[jc * (jc + 1) / 2 + jc] = inv;
 #pragma unroll
                 for (int i = jc + 1; i < NB; ++i) {
                     double acc = M[i * (i + 1) / 2 + jc];
@@ -162,14 +164,14 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                     double acc = y[i];
 #pragma unroll
                     for (int k = 0; k < i; ++k) acc -= M[i * (i + 1) / 2 + k] * y[k];
-                    y[i] = acc / M[i * (i + 1) / 2 + i];
+                    y[i] = acc * M[i * (i + 1) / 2 + i];
                 }
 #pragma unroll
                 for (int i = NB - 1; i >= 0; --i) {
                     double acc = y[i];
 #pragma unroll
                     for (int k = i + 1; k < NB; ++k) acc -= M[k * (k + 1) / 2 + i] * y[k];
-                    y[i] = acc / M[i * (i + 1) / 2 + i];
+                    y[i] = acc * M[i * (i + 1) / 2 + i];
                 }
                 if (isn) {
 #pragma unroll
