@@ -12,7 +12,10 @@ namespace mcd {
 // Phi[k] = sum_value W_j (f_kj - f_kc) + sum_Neumann W^N_j g_kj, field k at
 // fld + k Nc, its Neumann data at fneu + k Nc (fneu may be null).  Per
 // component the operations and their order are those of a single field.
-template <int DIM, int NC>
+// Only basis components q < Q1 are formed (Q1 = DIM: the gradient), the
+// others are left 0, so a first-derivative operator reads DIM of the NB
+// weight planes.
+template <int DIM, int NC, int Q1 = Dims<DIM>::NB>
 __device__ __forceinline__ void poly_multi(const MeshDev& m, const SetDev& st, int c, const int ijk[3],
                                            const double* __restrict__ fld, const double* __restrict__ fneu,
                                            double (&Phi)[NC][Dims<DIM>::NB]) {
@@ -39,7 +42,7 @@ __device__ __forceinline__ void poly_multi(const MeshDev& m, const SetDev& st, i
 #pragma unroll
         for (int k = 0; k < NC; ++k) d[k] = v ? fld[k * Nc + j] - fc[k] : fneu[k * Nc + j];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
+        for (int q = 0; q < Q1; ++q) {
             const double w = st.phi[((size_t)q * (S + 1) + s) * Nc + c];
 #pragma unroll
             for (int k = 0; k < NC; ++k) Phi[k][q] += w * d[k];
@@ -47,7 +50,7 @@ __device__ __forceinline__ void poly_multi(const MeshDev& m, const SetDev& st, i
     }
     if (fneu && ((nm >> S) & 1u)) {
 #pragma unroll
-        for (int q = 0; q < NB; ++q) {
+        for (int q = 0; q < Q1; ++q) {
             const double w = st.phi[((size_t)q * (S + 1) + S) * Nc + c];
 #pragma unroll
             for (int k = 0; k < NC; ++k) Phi[k][q] += w * fneu[k * Nc + c];
@@ -110,18 +113,18 @@ __global__ __launch_bounds__(kBlock) void k_apply(MeshDev m, SetDev st, int op, 
         int ijk[3];
         cell_ijk(m, c, ijk);
         double Phi[NB];
-        if (op == MCD_OP_PHI || op == MCD_OP_GRAD) {
+        if (op == MCD_OP_PHI) {
             poly_at<DIM>(m, st, c, ijk, in, fneu, Phi);
-            if (op == MCD_OP_PHI) {
 #pragma unroll
-                for (int q = 0; q < NB; ++q) out[q * Nc + c] = Phi[q] * scale;
-            } else {
+            for (int q = 0; q < NB; ++q) out[q * Nc + c] = Phi[q] * scale;
+        } else if (op == MCD_OP_GRAD) {
+            double P1[1][NB];
+            poly_multi<DIM, 1, DIM>(m, st, c, ijk, in, fneu, P1);
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) out[a * Nc + c] = Phi[a] / rs * scale;
-            }
+            for (int a = 0; a < DIM; ++a) out[a * Nc + c] = P1[0][a] / rs * scale;
         } else if (op == MCD_OP_DIV) {
             double P3[DIM][NB];
-            poly_multi<DIM, DIM>(m, st, c, ijk, in, fneu, P3);
+            poly_multi<DIM, DIM, DIM>(m, st, c, ijk, in, fneu, P3);
             double acc = 0.0;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) acc += P3[a][a] / rs;
@@ -290,10 +293,10 @@ __global__ __launch_bounds__(kBlock) void k_project(MeshDev m, SetDev st, const 
         if (rn == MCD_ROLE_INNER) {
             int ijk[3];
             cell_ijk(m, c, ijk);
-            double Phi[NB];
-            poly_at<DIM>(m, st, c, ijk, P, f, Phi);
+            double P1[1][NB];
+            poly_multi<DIM, 1, DIM>(m, st, c, ijk, P, f, P1);
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) u[a * Nc + c] = ustar[a * Nc + c] - dt * (Phi[a] / st.rs);
+            for (int a = 0; a < DIM; ++a) u[a * Nc + c] = ustar[a * Nc + c] - dt * (P1[0][a] / st.rs);
         } else {
             double v[DIM];
 #pragma unroll
