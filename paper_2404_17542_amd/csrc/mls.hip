@@ -21,33 +21,61 @@ __device__ __forceinline__ double mls_weight(double r, double re, int kind) {
     return exp(-4.0 * r * r / (re * re));
 }
 
+// Tiles of the build: 64 x 4 cells (2D) or 32 x 4 x 2 (3D), one cell per
+// thread of a 256-thread block; the tile plus a one-cell halo is staged in
+// LDS (positions already shifted to the periodic image seen from the tile,
+// normals, roles, cell indices), so the 2 x 27 neighbour reads per DP of the
+// two passes are LDS reads.  Pass 1 keeps each row's weight w_j in LDS for
+// pass 2.
+template <int DIM> struct MlsTile;
+template <> struct MlsTile<2> { static constexpr int X = 64, Y = 4, Z = 1; };
+template <> struct MlsTile<3> { static constexpr int X = 32, Y = 4, Z = 2; };
+
 template <int DIM>
-__device__ __forceinline__ int row_of(const MeshDev& m, const double* __restrict__ pos, const int8_t* __restrict__ role,
-                                      const double* __restrict__ normal, const BcDev& bc, const int ijk[3],
-                                      const double* xc, int s, double re, double rs, int wkind, int& j, double& w,
-                                      double* a) {
-    constexpr int CEN = Dims<DIM>::CEN;
-    double sh[3];
-    if (!neighbour<DIM>(m, ijk, s, j, sh)) return 0;
-    int kind = row_kind(role[j], bc);
-    if (s == CEN && kind != 2) return 0;   // the DP itself: only its Neumann row
+struct MlsHalo {
+    static constexpr int X = MlsTile<DIM>::X + 2, Y = MlsTile<DIM>::Y + 2, Z = DIM == 3 ? MlsTile<DIM>::Z + 2 : 1;
+    static constexpr int N = X * Y * Z;
+    double p[DIM][N];      // neighbour position (periodic image)
+    double nv[DIM][N];     // neighbour normal
+    int j[N];              // cell index, -1 outside a non-periodic mesh
+    int8_t r[N];           // role
+};
+
+// halo slot of the neighbour at stencil slot s of tile cell (lx, ly, lz)
+template <int DIM>
+__device__ __forceinline__ int halo_slot(int lx, int ly, int lz, int s) {
+    using H = MlsHalo<DIM>;
+    const int ox = s % 3 - 1, oy = (s / 3) % 3 - 1, oz = DIM == 3 ? s / 9 - 1 : 0;
+    const int hz = DIM == 3 ? lz + 1 + oz : 0;
+    return (hz * H::Y + (ly + 1 + oy)) * H::X + (lx + 1 + ox);
+}
+
+// Row of neighbour slot e: kind (0 none, 1 value, 2 Neumann), its basis
+// vector a (value or normal-derivative row, Eq. obj_func) and, when
+// want_w, its weight.
+template <int DIM>
+__device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, int e, bool centre,
+                                       const double* xc, double re, double rs, int wkind, bool want_w, double& w,
+                                       double* a) {
+    if (H.j[e] < 0) return 0;
+    const int kind = row_kind(H.r[e], bc);
+    if (centre && kind != 2) return 0;     // the DP itself: only its Neumann row
     if (kind == 0) return 0;
-    const size_t Nc = (size_t)m.Nc;
     double d[DIM], X[DIM];
     double r2 = 0.0;
 #pragma unroll
     for (int q = 0; q < DIM; ++q) {
-        d[q] = (pos[q * Nc + j] + sh[q]) - xc[q];
+        d[q] = H.p[q][e] - xc[q];
         r2 += d[q] * d[q];
         X[q] = d[q] / rs;
     }
-    w = mls_weight(sqrt(r2), re, wkind);
+    if (want_w) w = mls_weight(sqrt(r2), re, wkind);
     if (kind == 1) {
         basis<DIM>(X, a);
     } else {
         double nv[DIM];
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) nv[q] = normal[q * Nc + j];
+        for (int q = 0; q < DIM; ++q) nv[q] = H.nv[q][e];
         basis_normal<DIM>(X, nv, a);
     }
     return kind;
@@ -61,165 +89,215 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                                                       int* latch) {
     constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
     constexpr int NP = NB * (NB + 1) / 2;
+    using T = MlsTile<DIM>;
+    using HT = MlsHalo<DIM>;
+    static_assert(T::X * T::Y * T::Z == kBlock, "one tile cell per thread");
+    __shared__ HT H;
+    __shared__ double wc[S][kBlock];
     const size_t Nc = (size_t)m.Nc;
+    const int ntx = (m.n[0] + T::X - 1) / T::X, nty = (m.n[1] + T::Y - 1) / T::Y;
+    const int ntz = DIM == 3 ? (m.n[2] + T::Z - 1) / T::Z : 1;
+    const int ntiles = ntx * nty * ntz;
+    const int lx = threadIdx.x % T::X, ly = (threadIdx.x / T::X) % T::Y, lz = threadIdx.x / (T::X * T::Y);
     const int nblk = gridDim.x;
     const int lb = xcd_block(blockIdx.x, nblk);
-    for (int c = lb * blockDim.x + threadIdx.x; c < m.Nc; c += nblk * blockDim.x) {
-        const int rc = role[c];
-        int ijk[3];
-        cell_ijk(m, c, ijk);
-        double xc[DIM];
+    for (int tile = lb; tile < ntiles; tile += nblk) {
+        const int o[3] = {(tile % ntx) * T::X, ((tile / ntx) % nty) * T::Y, (tile / (ntx * nty)) * T::Z};
+        // stage the tile and its halo
+        for (int e = threadIdx.x; e < HT::N; e += kBlock) {
+            const int h[3] = {e % HT::X, (e / HT::X) % HT::Y, e / (HT::X * HT::Y)};
+            int idx = 0, stride = 1;
+            bool in = true;
+            double sh[3] = {0.0, 0.0, 0.0};
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) xc[q] = pos[q * Nc + c];
-        const bool unk_c = is_unknown(rc, c, bc);
-        st.unknown[c] = unk_c ? 1 : 0;
-        double M[NP];
-#pragma unroll
-        for (int q = 0; q < NP; ++q) M[q] = 0.0;
-        uint32_t vm = 0, nm = 0;
-        int nrows = 0;
-        if (rc != MCD_ROLE_VOID) {
-            for (int s = 0; s < S; ++s) {
-                int j;
-                double w, a[NB];
-                const int kind = row_of<DIM>(m, pos, role, normal, bc, ijk, xc, s, re, rs, wkind, j, w, a);
-                if (!kind) continue;
-                if (kind == 1)
-                    vm |= 1u << s;
-                else
-                    nm |= 1u << (s == CEN ? S : s);
-                nrows += (w > 0.0) ? 1 : 0;
-                int q = 0;
-#pragma unroll
-                for (int r = 0; r < NB; ++r) {
-                    const double wa = w * a[r];
-#pragma unroll
-                    for (int k = 0; k <= r; ++k) M[q++] += wa * a[k];
+            for (int a = 0; a < DIM; ++a) {
+                int ii = o[a] - 1 + h[a];
+                // beyond every active cell's neighbourhood (a tile wider than
+                // the mesh): not a neighbour of anything, left outside
+                if (ii < -1 || ii > m.n[a]) in = false;
+                if (ii < 0) {
+                    in = in && m.periodic[a];
+                    ii += m.n[a];
+                    sh[a] = -m.length[a];
+                } else if (ii >= m.n[a]) {
+                    in = in && m.periodic[a];
+                    ii -= m.n[a];
+                    sh[a] = m.length[a];
                 }
+                idx += ii * stride;
+                stride *= m.n[a];
+            }
+            H.j[e] = in ? idx : -1;
+            H.r[e] = in ? role[idx] : (int8_t)0;
+#pragma unroll
+            for (int q = 0; q < DIM; ++q) {
+                H.p[q][e] = in ? pos[q * Nc + idx] + sh[q] : 0.0;
+                H.nv[q][e] = in ? normal[q * Nc + idx] : 0.0;
             }
         }
-        // Cholesky M = L L^T in place (packed lower triangle); the diagonal
-        // slots keep 1 / L_jj, so that the triangular solves of pass 2
-        // multiply instead of divide
-        double tr = 0.0;
+        __syncthreads();
+        const int gx = o[0] + lx, gy = o[1] + ly, gz = DIM == 3 ? o[2] + lz : 0;
+        const bool active = gx < m.n[0] && gy < m.n[1] && (DIM == 2 || gz < m.n[2]);
+        if (active) {
+            const int c = gx + m.n[0] * (gy + m.n[1] * gz);
+            const int ecen = halo_slot<DIM>(lx, ly, lz, CEN);
+            const int rc = H.r[ecen];
+            double xc[DIM];
 #pragma unroll
-        for (int r = 0; r < NB; ++r) tr += M[r * (r + 1) / 2 + r];
-        bool sing = (rc == MCD_ROLE_VOID);
-        if (!sing) {
-            // fewer rows of positive weight than basis terms: M is rank-deficient
-            if (nrows < NB) sing = true;
+            for (int q = 0; q < DIM; ++q) xc[q] = H.p[q][ecen];
+            const bool unk_c = is_unknown(rc, c, bc);
+            st.unknown[c] = unk_c ? 1 : 0;
+            double M[NP];
 #pragma unroll
-            for (int jc = 0; jc < NB; ++jc) {
-                double dsum = M[jc * (jc + 1) / 2 + jc];
+            for (int q = 0; q < NP; ++q) M[q] = 0.0;
+            uint32_t vm = 0, nm = 0;
+            int nrows = 0;
+            if (rc != MCD_ROLE_VOID) {
+                for (int s = 0; s < S; ++s) {
+                    double w = 0.0, a[NB];
+                    const int kind = row_lds<DIM>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs, wkind,
+                                                  true, w, a);
+                    wc[s][threadIdx.x] = w;
+                    if (!kind) continue;
+                    if (kind == 1)
+                        vm |= 1u << s;
+                    else
+                        nm |= 1u << (s == CEN ? S : s);
+                    nrows += (w > 0.0) ? 1 : 0;
+                    int q = 0;
 #pragma unroll
-                for (int k = 0; k < jc; ++k) dsum -= M[jc * (jc + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
-                if (!(dsum > 1e-12 * tr / NB)) {
-                    sing = true;
-                    dsum = 1.0;
+                    for (int r = 0; r < NB; ++r) {
+                        const double wa = w * a[r];
+#pragma unroll
+                        for (int k = 0; k <= r; ++k) M[q++] += wa * a[k];
+                    }
                 }
-                const double ljj = sqrt(dsum);
-                const double inv = 1.0 / ljj;
-                M[jc * (jc + 1) / 2 + jc] = inv;
+            }
+            // Cholesky M = L L^T in place (packed lower triangle); the diagonal
+            // slots keep 1 / L_jj, so that the triangular solves of pass 2
+            // multiply instead of divide
+            double tr = 0.0;
 #pragma unroll
-                for (int i = jc + 1; i < NB; ++i) {
-                    double acc = M[i * (i + 1) / 2 + jc];
+            for (int r = 0; r < NB; ++r) tr += M[r * (r + 1) / 2 + r];
+            bool sing = (rc == MCD_ROLE_VOID);
+            if (!sing) {
+                // fewer rows of positive weight than basis terms: M is rank-deficient
+                if (nrows < NB) sing = true;
 #pragma unroll
-                    for (int k = 0; k < jc; ++k) acc -= M[i * (i + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
-                    M[i * (i + 1) / 2 + jc] = acc * inv;
+                for (int jc = 0; jc < NB; ++jc) {
+                    double dsum = M[jc * (jc + 1) / 2 + jc];
+#pragma unroll
+                    for (int k = 0; k < jc; ++k) dsum -= M[jc * (jc + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
+                    if (!(dsum > 1e-12 * tr / NB)) {
+                        sing = true;
+                        dsum = 1.0;
+                    }
+                    const double ljj = sqrt(dsum);
+                    const double inv = 1.0 / ljj;
+                    M[jc * (jc + 1) / 2 + jc] = inv;
+#pragma unroll
+                    for (int i = jc + 1; i < NB; ++i) {
+                        double acc = M[i * (i + 1) / 2 + jc];
+#pragma unroll
+                        for (int k = 0; k < jc; ++k) acc -= M[i * (i + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
+                        M[i * (i + 1) / 2 + jc] = acc * inv;
+                    }
+                }
+                if (sing) {
+                    atomicAdd(&counters[rc == MCD_ROLE_INNER ? 0 : 1], 1);
+                    if (rc == MCD_ROLE_INNER) {
+                        atomicMin(&counters[2], c);
+                        atomicAdd(latch, 1);
+                    }
                 }
             }
             if (sing) {
-                atomicAdd(&counters[rc == MCD_ROLE_INNER ? 0 : 1], 1);
-                if (rc == MCD_ROLE_INNER) {
-                    atomicMin(&counters[2], c);
-                    atomicAdd(latch, 1);
-                }
+                vm = 0;
+                nm = 0;
             }
-        }
-        if (sing) {
-            vm = 0;
-            nm = 0;
-        }
-        st.vmask[c] = vm;
-        st.nmask[c] = nm;
-        double cacc[NB];
+            st.vmask[c] = vm;
+            st.nmask[c] = nm;
+            double cacc[NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) cacc[q] = 0.0;
-        double diag_sum = 0.0, off_sum = 0.0;
-        for (int s = 0; s < S; ++s) {
-            const int slot = (s == CEN) ? S : s;
-            const bool isv = (vm >> s) & 1u, isn = (nm >> slot) & 1u;
-            double y[NB];
+            for (int q = 0; q < NB; ++q) cacc[q] = 0.0;
+            double diag_sum = 0.0, off_sum = 0.0;
+            for (int s = 0; s < S; ++s) {
+                const int slot = (s == CEN) ? S : s;
+                const bool isv = (vm >> s) & 1u, isn = (nm >> slot) & 1u;
+                const int e = halo_slot<DIM>(lx, ly, lz, s);
+                double y[NB];
 #pragma unroll
-            for (int q = 0; q < NB; ++q) y[q] = 0.0;
-            int j = -1;
-            if (isv || isn) {
-                double w, a[NB];
-                row_of<DIM>(m, pos, role, normal, bc, ijk, xc, s, re, rs, wkind, j, w, a);
+                for (int q = 0; q < NB; ++q) y[q] = 0.0;
+                if (isv || isn) {
+                    double w = wc[s][threadIdx.x], a[NB];
+                    row_lds<DIM>(H, bc, e, s == CEN, xc, re, rs, wkind, false, w, a);
 #pragma unroll
-                for (int q = 0; q < NB; ++q) y[q] = w * a[q];
-                // forward L z = y, backward L^T y = z
+                    for (int q = 0; q < NB; ++q) y[q] = w * a[q];
+                    // forward L z = y, backward L^T y = z
 #pragma unroll
-                for (int i = 0; i < NB; ++i) {
-                    double acc = y[i];
+                    for (int i = 0; i < NB; ++i) {
+                        double acc = y[i];
 #pragma unroll
-                    for (int k = 0; k < i; ++k) acc -= M[i * (i + 1) / 2 + k] * y[k];
-                    y[i] = acc * M[i * (i + 1) / 2 + i];
+                        for (int k = 0; k < i; ++k) acc -= M[i * (i + 1) / 2 + k] * y[k];
+                        y[i] = acc * M[i * (i + 1) / 2 + i];
+                    }
+#pragma unroll
+                    for (int i = NB - 1; i >= 0; --i) {
+                        double acc = y[i];
+#pragma unroll
+                        for (int k = i + 1; k < NB; ++k) acc -= M[k * (k + 1) / 2 + i] * y[k];
+                        y[i] = acc * M[i * (i + 1) / 2 + i];
+                    }
+                    if (isn) {
+#pragma unroll
+                        for (int q = 0; q < NB; ++q) y[q] *= rs;
+                    } else {
+#pragma unroll
+                        for (int q = 0; q < NB; ++q) cacc[q] += y[q];
+                    }
                 }
+                if (s != CEN) {
 #pragma unroll
-                for (int i = NB - 1; i >= 0; --i) {
-                    double acc = y[i];
-#pragma unroll
-                    for (int k = i + 1; k < NB; ++k) acc -= M[k * (k + 1) / 2 + i] * y[k];
-                    y[i] = acc * M[i * (i + 1) / 2 + i];
-                }
-                if (isn) {
-#pragma unroll
-                    for (int q = 0; q < NB; ++q) y[q] *= rs;
+                    for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + s) * Nc + c] = y[q];
+                    double lap = 0.0;
+                    if (isv && unk_c) {
+                        lap = diag2<DIM>(y) / (rs * rs);
+                        diag_sum += lap;
+                        if (!is_unknown(H.r[e], H.j[e], bc)) lap = 0.0;
+                    }
+                    if (st.amat) {
+                        st.amat[(size_t)s * Nc + c] = lap;
+                        st.amat32[(size_t)s * Nc + c] = (float)lap;
+                        off_sum += lap;
+                    }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < NB; ++q) cacc[q] += y[q];
+                    for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + S) * Nc + c] = y[q];
                 }
             }
-            if (s != CEN) {
 #pragma unroll
-                for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + s) * Nc + c] = y[q];
-                double lap = 0.0;
-                if (isv && unk_c) {
-                    lap = diag2<DIM>(y) / (rs * rs);
-                    diag_sum += lap;
-                    if (!is_unknown(role[j], j, bc)) lap = 0.0;
-                }
-                if (st.amat) {
-                    st.amat[(size_t)s * Nc + c] = lap;
-                    st.amat32[(size_t)s * Nc + c] = (float)lap;
-                    off_sum += lap;
-                }
-            } else {
-#pragma unroll
-                for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + S) * Nc + c] = y[q];
+            for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + CEN) * Nc + c] = -cacc[q];
+            if (st.amat) {
+                // FP32 copy in difference form: its centre slot holds the row sum
+                // (zero for rows without known neighbours), so that products
+                // sum a_j (x_j - x_c) + rowsum x_c and keep the exact
+                // cancellation of the stencil on smooth fields
+                const double dg = unk_c ? -diag_sum : 0.0;
+                st.amat[(size_t)CEN * Nc + c] = dg;
+                st.amat32[(size_t)CEN * Nc + c] = (float)(dg + off_sum);
             }
         }
-#pragma unroll
-        for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + CEN) * Nc + c] = -cacc[q];
-        if (st.amat) {
-            // FP32 copy in difference form: its centre slot holds the row sum
-            // (zero for rows without known neighbours), so that products
-            // sum a_j (x_j - x_c) + rowsum x_c and keep the exact
-            // cancellation of the stencil on smooth fields
-            const double dg = unk_c ? -diag_sum : 0.0;
-            st.amat[(size_t)CEN * Nc + c] = dg;
-            st.amat32[(size_t)CEN * Nc + c] = (float)(dg + off_sum);
-        }
+        __syncthreads();
     }
 }
 
 hipError_t launch_mls_build(const MeshDev& m, const double* pos, const int8_t* role, const double* normal,
                             const BcDev& bc, double re, double rs, int wkind, const SetDev& set, int* counters,
                             int* latch, hipStream_t st) {
-    long long g = ((long long)m.Nc + kBlock - 1) / kBlock;
+    // one tile per block and round, at most 4096 blocks looping over the tiles
+    long long g = m.dim == 2 ? (long long)((m.n[0] + 63) / 64) * ((m.n[1] + 3) / 4)
+                             : (long long)((m.n[0] + 31) / 32) * ((m.n[1] + 3) / 4) * ((m.n[2] + 1) / 2);
     if (g > 4096) g = 4096;
-    g = (g + 7) / 8 * 8;
     if (m.dim == 2)
         hipLaunchKernelGGL(k_mls_build<2>, dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re, rs, wkind,
                            set, counters, latch);
