@@ -221,6 +221,19 @@ def test_weights_full_size_sampled(M):
     _weights_parity(M, case, case.bc_pressure, idx=idx)
 
 
+def test_sphere_full_size_arrangement_and_weights(M):
+    """128^3 moving sphere at the benchmark size: the initial arrangement
+    (500 sweeps) and 2 steps bit-exact, then the weights of 3000 sampled DPs
+    plus every sphere-boundary DP within 1e-12 (LDS-tiled build, 3D)."""
+    case = configs.c4_moving_sphere(n=128)
+    _dps_parity(M, case, steps=2, init_sweeps=case.n_relax_init)
+    m = O.Mesh.from_case(case)
+    r0 = O.roles(m, oracle_bodies(case, 0.0))
+    rng = np.random.default_rng(4)
+    idx = np.union1d(rng.choice(case.n_cells, 3000, replace=False), np.nonzero(r0 == 2)[0])
+    _weights_parity(M, case, case.bc_pressure, idx=idx)
+
+
 def test_weights_deterministic(M):
     case = configs.c2_oscillating_cylinder(n=128)
     m, pos, role, nrm = _arranged(case)
