@@ -63,12 +63,12 @@ def workload_name(case, n_active, precision):
             f"quadratic MLS {stencil}, PPE Bi-CGSTAB to 1e-8 ({precision})")
 
 
-def measured_traffic(workload_key):
+def measured_traffic(workload_key, dim=2):
     """HBM bytes per S-stage launch from the committed counter summary of this
     workload, or None when there is none or the kernel source has changed
     since the counters were taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"pmc_k_t2_{workload_key}.json")
+    path = os.path.join(ROOT, "profiles", f"pmc_k_t{dim}_{workload_key}.json")
     if not os.path.exists(path):
         return None
     with open(path) as f:
@@ -262,8 +262,8 @@ def main():
         bytes_per = stage_bytes(n_unknown, case.dim, mat_b, vec_b)
         avg_s = prof["s_ms"] / max(prof["s_n"], 1) * 1e-3
         achieved = bytes_per / avg_s / 1e9 if avg_s > 0 else None
-        key = f"{'taylor_green' if case.name.startswith('C1') else case.name}_{case.n[0]}_{args.precision}"
-        traffic = measured_traffic(key) if case.dim == 2 else None
+        flow = {"C1": "taylor_green", "C2": "cylinder", "C4": "sphere"}[case.name[:2]]
+        traffic = measured_traffic(f"{flow}_{case.n[0]}_{args.precision}", case.dim)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
                     "traffic_unit": "bytes per launch (FETCH_SIZE, WRITE_SIZE, copy-calibrated)",
