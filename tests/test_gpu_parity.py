@@ -488,28 +488,35 @@ def test_ppe_not_converged_and_bad_rhs(M):
     assert ei.value.status == 1
 
 
+@pytest.mark.parametrize("precond", ["none", "jacobi"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed", "fp32_matrix"])
-def test_ppe_zero_rhs_and_no_unknowns(M, precision):
+def test_ppe_zero_rhs_and_no_unknowns(M, precision, precond):
     """Degenerate PPEs: a zero effective right-hand side has the zero solution
     whatever the initial guess (0 iterations, converged); a set whose DPs are
-    all Dirichlet has nothing to solve and leaves p unchanged."""
+    all Dirichlet has nothing to solve and leaves p unchanged; with and
+    without the Jacobi preconditioner."""
     prec = {"fp64": M.PREC_FP64, "mixed": M.PREC_FP32_REFINE, "fp32_matrix": M.PREC_FP32_MATRIX}[precision]
+    pc = {"none": M.PRECOND_NONE, "jacobi": M.PRECOND_JACOBI}[precond]
     case, m, pos, role, nrm, st, rhs, g = _c0_problem(32)
     ctx = M.Context.from_case(case)
     ctx.build_stencils(0, _dev(pos), _dev(role, torch.int8), _dev(nrm), case.bc_pressure)
     rng = np.random.default_rng(2)
     guess = np.where(role == O.INNER, rng.standard_normal(m.Nc), 0.0)
     p = _dev(guess)
-    info = ctx.solve_ppe(0, _dev(np.zeros(m.Nc)), p, guess=M.GUESS_CALLER, precision=prec)
+    info = ctx.solve_ppe(0, _dev(np.zeros(m.Nc)), p, guess=M.GUESS_CALLER, precision=prec, precond=pc)
     assert info["converged"] and info["iterations"] == 0 and info["rhs_norm"] == 0.0
     assert np.all(np_(p) == 0.0)
     # every DP a (Dirichlet) wall DP: no unknown rows at all
     role_w = np.ones(m.Nc, dtype=np.int8)
     ctx.build_stencils(1, _dev(pos), _dev(role_w, torch.int8), _dev(nrm), case.bc_pressure)
     pt = _dev(g)
-    info = ctx.solve_ppe(1, _dev(np.ones(m.Nc)), pt, precision=prec)
+    info = ctx.solve_ppe(1, _dev(np.ones(m.Nc)), pt, precision=prec, precond=pc)
     assert info["converged"] and info["iterations"] == 0
     assert np.array_equal(np_(pt), g)
+    # an unknown preconditioner is an argument error
+    with pytest.raises(M.McdError) as ei:
+        ctx.solve_ppe(0, _dev(rhs), _dev(g), precision=prec, precond=7)
+    assert ei.value.status == 1
     # meshes below 3 cells per axis are rejected at creation
     with pytest.raises(M.McdError) as ei:
         M.Context.from_case(configs.c0_manufactured(2))
