@@ -11,7 +11,7 @@ manufactured-solution Poisson problem, a step being the MLS build plus one
 PPE solve from zero, a latency figure), --precision mixed (FP32-stored
 matrix with FP64 residual replacement) or refine (FP32 Bi-CGSTAB inside
 FP64 refinement), --guess zero|learned (--weights: a file written by
-paper_2404_17542_amd.learned).  The tolerance is judged on the FP64
+paper_2404_17542_amd.learned).  The tolerance is checked on the FP64
 operator in every form.
 
 --gpus N with N > 1 exits: this build runs on one GPU.
@@ -169,6 +169,30 @@ def bench_manufactured(args):
     print(json.dumps(out), flush=True)
 
 
+def error_vs_plain_fp64(sim, mcd):
+    """One extra (untimed) step: its PPE is solved by the form under test and,
+    from the same previous pressure, by the plain method (FP64, warm start, no
+    preconditioner); returns ||P_form - P_plain|| / ||P_plain|| over unknown
+    DPs.  The step then continues with the form's solution."""
+    import torch
+    pset, bodies_new, upd = sim.prepare()
+    p_k = sim.P.clone()
+    info = sim.solve(pset, sim.initial_guess(pset, sim.guess))
+    p_form = sim.P.clone()
+    sim.P.copy_(p_k)
+    sim.ctx.solve_ppe(pset, sim.rhs, sim.P, sim.fP, tol=sim.case.tol, precision=mcd.PREC_FP64,
+                      guess=mcd.GUESS_CALLER, precond=mcd.PRECOND_NONE, check_every=sim.check_every)
+    unk = sim.role == mcd.ROLE_INNER
+    for bid, typ in sim.case.bc_pressure.items():
+        if typ == mcd.BC_NEUMANN:
+            unk |= sim.role == bid
+    ref = sim.P[unk]
+    rel = float(torch.linalg.vector_norm(p_form[unk] - ref) / torch.linalg.vector_norm(ref))
+    sim.P.copy_(p_form)
+    sim.finish(pset, bodies_new, info, upd)
+    return rel
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -281,6 +305,9 @@ def main():
                       "stage_shape": sim.ctx.get_shape(), "autotuned": tune is not None,
                       "ppe_iters_per_step": sum(iters) / len(iters), "max_true_rel_res": worst},
            "roofline": roofline}
+    if args.precision != "fp64" or args.guess != "warm" or args.precond != "none":
+        # the error of this form against the plain FP64 method, on one more step
+        out["config"]["error_vs_plain_fp64"] = error_vs_plain_fp64(sim, mcd)
     if not args.no_cpu_baseline and args.cpu_steps > 0:
         log(f"timing the CPU oracle on {args.cpu_steps} steps")
         out["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -47,7 +47,7 @@ typedef enum {
 enum { MCD_ROLE_INNER = -1, MCD_ROLE_VOID = 0 };
 enum { MCD_BC_DIRICHLET = 0, MCD_BC_NEUMANN = 1 };
 enum { MCD_WEIGHT_COS2 = 0, MCD_WEIGHT_GAUSS = 1 };
-/* Arithmetic of the PPE solve (the tolerance is judged on the FP64 operator
+/* Arithmetic of the PPE solve (the tolerance is checked on the FP64 operator
  * in every mode):
  *   FP64         FP64 matrix, vectors and dots.
  *   FP32_REFINE  FP64 iterative refinement around an FP32 Bi-CGSTAB (FP32

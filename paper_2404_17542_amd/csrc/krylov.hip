@@ -1854,6 +1854,9 @@ hipError_t krylov_autotune(const MeshDev& m, const SetDev& set, KrylovWork& w, i
     hipError_t e = hipEventCreate(&t0);
     if (e == hipSuccess) e = hipEventCreate(&t1);
     const int grid0 = w.grid_req, depth0 = w.kb64.tz;
+    // the candidate with the default shape's effective block count and depth
+    KBufs K0 = w.kb64;
+    (void)shape_of(m, kKGrid, m.dim == 3 ? kDefaultDepth : 1, K0);
     int best = -1, dflt = -1;
     for (int i = 0; i < n && e == hipSuccess; ++i) {
         if ((e = krylov_set_shape(m, w, grid_out[i], depth_out[i])) != hipSuccess) break;
@@ -1866,7 +1869,9 @@ hipError_t krylov_autotune(const MeshDev& m, const SetDev& set, KrylovWork& w, i
         if (e != hipSuccess) break;
         us_out[i] = ok && ok2 ? 1e3 * (double)fminf(ms, ms2) / iters : -1.0;
         if (us_out[i] > 0 && (best < 0 || us_out[i] < us_out[best])) best = i;
-        if (grid_out[i] == kKGrid && depth_out[i] == (m.dim == 3 ? kDefaultDepth : 1)) dflt = i;
+        KBufs Ki = w.kb64;
+        (void)shape_of(m, grid_out[i], depth_out[i], Ki);
+        if (Ki.nblk == K0.nblk && Ki.tz == K0.tz) dflt = i;
     }
     if (t0) (void)hipEventDestroy(t0);
     if (t1) (void)hipEventDestroy(t1);

@@ -96,7 +96,7 @@ def load():
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
-        raise RuntimeError(f"libmcd.so not found at {LIB_PATH}: build it with __graft_entry__.build()")
+        raise RuntimeError(f"libmcd.so not found at {LIB_PATH}: build it with python -m paper_2404_17542_amd.build")
     lib = C.CDLL(LIB_PATH)
     vp, i, d = C.c_void_p, C.c_int, C.c_double
     P = C.POINTER

@@ -99,7 +99,7 @@ def test_mixed_refinement_reaches_fp64_tolerance():
     pm, im = O.solve_ppe_mixed(m, st, role, case.bc_pressure, rhs, g, None, 1e-8)
     assert im.converged and im.true_rel_residual <= 1e-8 and im.restarts >= 2
     assert np.linalg.norm(pm - p64) / np.linalg.norm(p64) < 1e-7
-    # without refinement, scipy's Bi-CGSTAB entirely in FP32 (judged on the
+    # without refinement, scipy's Bi-CGSTAB entirely in FP32 (checked on the
     # FP64 operator) stalls far above the tolerance
     from scipy.sparse.linalg import bicgstab
     A, beff, uidx = O.ppe_system(m, st, role, case.bc_pressure, rhs, g, None)
