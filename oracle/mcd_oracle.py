@@ -1107,3 +1107,109 @@ def neumann_pressure_data(mesh, role, normal, bodies, dvdt):
             acc = acc + dvdt[b.body_id][a] * normal[a]
         f = np.where(sel, -acc, f)
     return f
+
+
+# ---------------------------------------------------------------------------
+# Fluid force on a moving body (Sec. 3.4, evaluation of fluid forces acting
+# on moving boundaries), 2D
+# ---------------------------------------------------------------------------
+
+def diamond_angle(dx, dy):
+    """A monotone stand-in for the polar angle of (dx, dy) in [0, 4) made of
+    + - / only (so that the ordering does not depend on a libm atan2)."""
+    dx = np.asarray(dx, dtype=np.float64)
+    dy = np.asarray(dy, dtype=np.float64)
+    out = np.empty_like(dx)
+    q0 = (dy >= 0) & (dx >= 0)
+    q1 = (dy >= 0) & (dx < 0)
+    q2 = (dy < 0) & (dx < 0)
+    q3 = (dy < 0) & (dx >= 0)
+    out[q0] = dy[q0] / (dx[q0] + dy[q0])
+    out[q1] = 1.0 - dx[q1] / (-dx[q1] + dy[q1])
+    out[q2] = 2.0 - dy[q2] / (-dx[q2] - dy[q2])
+    out[q3] = 3.0 + dx[q3] / (dx[q3] - dy[q3])
+    return out
+
+
+def basis_gradient(X):
+    """d p / d X_a of the 2D quadratic basis (X, Y, X^2/2, XY, Y^2/2): rows a = x, y."""
+    x, y = X
+    one, zero = np.ones_like(x), np.zeros_like(x)
+    return [[one, zero, x, y, zero], [zero, one, zero, x, y]]
+
+
+def fluid_force(mesh, pos, role, normal, bodies, bc_u, bc_p, u, p, f_neu, re, rs, mu, kind="cos2"):
+    """Force of the fluid on each body: F = sum over its boundary DPs of
+    t_i dGamma_i with t = (-P I + mu (grad u + grad u^T)) . n (n = the DP's
+    unit normal, pointing into the fluid).
+
+    dGamma_i is the mean distance to the two neighbouring boundary DPs along
+    the surface; the neighbours are the predecessor and successor in the
+    order of the polar angle about the body centre (reading; ties by cell
+    index).  P and grad u at x_i come from the chi_c = 1 reconstruction of
+    the shifted support: the centre is the cell i + sign(n) (per axis, no
+    shift for a zero component), whose own fit (its velocity weights with the
+    body DPs as Dirichlet values, its pressure weights with the Neumann
+    datum) is evaluated at x_i.  A shifted centre that is not an inner DP
+    falls back to the DP's own fit (counted).  Returns ([F_b], [(n_b, fallbacks_b)]).
+    """
+    if mesh.dim != 2:
+        raise ValueError("the surface element of the paper is 2D")
+    forces, counts = [], []
+    for b in bodies:
+        sel = np.nonzero(role == b.body_id)[0]
+        if len(sel) == 0:
+            forces.append(np.zeros(2))
+            counts.append((0, 0))
+            continue
+        ang = diamond_angle(pos[0, sel] - b.centre[0], pos[1, sel] - b.centre[1])
+        order = np.lexsort((sel, ang))
+        cells = sel[order]
+        xs = pos[:, cells]
+        prev = np.roll(xs, 1, axis=1)
+        nxt = np.roll(xs, -1, axis=1)
+        dgam = 0.5 * (np.sqrt((xs[0] - prev[0]) ** 2 + (xs[1] - prev[1]) ** 2)
+                      + np.sqrt((xs[0] - nxt[0]) ** 2 + (xs[1] - nxt[1]) ** 2))
+        # shifted centres
+        ijk = mesh.ijk(cells)
+        cen = np.empty_like(cells)
+        nfb = 0
+        for k, c in enumerate(cells):
+            o = [0, 0]
+            for a in range(2):
+                na = normal[a, c]
+                o[a] = 1 if na > 0 else (-1 if na < 0 else 0)
+            ii, jj = ijk[0][k] + o[0], ijk[1][k] + o[1]
+            cand = -1
+            if 0 <= ii < mesh.n[0] and 0 <= jj < mesh.n[1]:
+                cand = ii + mesh.n[0] * jj
+            if cand < 0 or role[cand] != INNER:
+                cand = c
+                nfb += 1
+            cen[k] = cand
+        st_u = mls_build(mesh, pos, role, normal, bc_u, re, rs, kind, idx=cen)
+        st_p = mls_build(mesh, pos, role, normal, bc_p, re, rs, kind, idx=cen)
+        X = [(xs[a] - pos[a, cen]) / rs for a in range(2)]
+        pv = basis(X)
+        dp = basis_gradient(X)
+        Pp = poly_coeffs(mesh, st_p, p, f_neu)
+        P_at = p[cen].copy()
+        for q in range(5):
+            P_at = P_at + pv[q] * Pp[q]
+        G = np.zeros((2, 2, len(cells)))          # G[a, b] = d u_a / d x_b at x_i
+        for a in range(2):
+            Pu = poly_coeffs(mesh, st_u, u[a])
+            for bb in range(2):
+                acc = np.zeros(len(cells))
+                for q in range(5):
+                    acc = acc + dp[bb][q] * Pu[q]
+                G[a, bb] = acc / rs
+        n = normal[:, cells]
+        t = np.zeros((2, len(cells)))
+        for a in range(2):
+            t[a] = -P_at * n[a]
+            for bb in range(2):
+                t[a] = t[a] + mu * (G[a, bb] + G[bb, a]) * n[bb]
+        forces.append(np.array([np.sum(t[0] * dgam), np.sum(t[1] * dgam)]))
+        counts.append((len(cells), nfb))
+    return forces, counts
