@@ -232,6 +232,27 @@ mcd_status mcd_project(mcd_ctx* ctx, int set, const double* P, const double* f,
                        const double* ustar, double dt, const int8_t* role,
                        const mcd_body* bodies, int n_bodies, double* u);
 
+/* Fluid force on each body (Sec. 3.4, evaluation of fluid forces acting on
+ * moving boundaries), 2D meshes: F = sum over the body's boundary DPs i of
+ * t_i dGamma_i, t = (-P I + mu (grad u + grad u^T)) . n, n = normal[.][i]
+ * (the unit normal into the fluid, as written by mcd_update_dps).  dGamma_i
+ * is the mean distance from x_i to its two neighbouring boundary DPs, the
+ * neighbours being the predecessor and successor in the order of the polar
+ * angle about the body centre (ties by cell index).  P and grad u at x_i are
+ * the chi_c = 1 reconstruction (Eq. intrp_chi_1 and its derivative) of the
+ * support shifted into the fluid: the fit of the cell one step along
+ * sign(n_x), sign(n_y) (no step for a zero component), evaluated at x_i;
+ * when that cell is not an inner DP the DP's own fit is used (counted).
+ * set_u: velocity weights (body DPs Dirichlet, holding the body velocity in
+ * u [2][Nc]); set_p: pressure weights with their Neumann data neumann_f
+ * [Nc] (NULL = 0) and p [Nc].  mu: dynamic viscosity.  force: host
+ * [n_bodies][2], in the order of `bodies`; counts: host [n_bodies][2] or
+ * NULL: boundary DPs and fallbacks.  At most 4096 boundary DPs per body
+ * (MCD_ERR_ARG beyond).  Synchronises. */
+mcd_status mcd_fluid_force(mcd_ctx* ctx, int set_u, int set_p, const double* u, const double* p,
+                           const double* neumann_f, const double* pos, const int8_t* role, const double* normal,
+                           const mcd_body* bodies, int n_bodies, double mu, double* force, int* counts);
+
 /* ---------------------------------------------------------------------
  * Pressure Poisson solve (Eq. pressure_poisson, Bi-CGSTAB)
  * ------------------------------------------------------------------- */

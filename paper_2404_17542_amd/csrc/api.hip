@@ -44,6 +44,7 @@ struct mcd_ctx {
     int* relax_state = nullptr;
     int* cnt = nullptr;
     int* cnt_host = nullptr;    // pinned
+    double* fbuf = nullptr;     // fluid-force results: [bodies][2] doubles, then [bodies][3] ints
     KrylovWork* kw = nullptr;
     // host constants of the arrangement (computed once, used identically by every call)
     double kl0 = 0, spring[4] = {0, 0, 0, 0}, eps_l0 = 0, band_l0 = 0, re = 0, rs = 0;
@@ -182,6 +183,7 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
     if (e == hipSuccess) e = alloc((void**)&c->dmax, (size_t)c->max_sweeps_alloc * sizeof(unsigned long long));
     if (e == hipSuccess) e = alloc((void**)&c->relax_state, 4 * sizeof(int));
     if (e == hipSuccess) e = alloc((void**)&c->cnt, CNT_N * sizeof(int));
+    if (e == hipSuccess) e = alloc((void**)&c->fbuf, 4 * MCD_MAX_BODIES * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->cnt_host, CNT_N * sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = krylov_alloc(c->m, &c->kw);
     if (e == hipSuccess) e = hipDeviceSynchronize();
@@ -202,7 +204,7 @@ void mcd_destroy(mcd_ctx* c) {
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }
-    void* ptrs[5] = {c->pos_tmp, c->band, c->dmax, c->relax_state, c->cnt};
+    void* ptrs[6] = {c->pos_tmp, c->band, c->dmax, c->relax_state, c->cnt, c->fbuf};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     if (c->cnt_host) (void)hipHostFree(c->cnt_host);
@@ -425,6 +427,42 @@ mcd_status mcd_project(mcd_ctx* c, int set, const double* P, const double* f, co
     BodiesDev B;
     if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_project: invalid bodies%s");
     HIPCHK(c, launch_project(c->m, c->sets[set].dev, P, f, ustar, dt, role, B, u, c->stream), "project");
+    return MCD_OK;
+}
+
+mcd_status mcd_fluid_force(mcd_ctx* c, int set_u, int set_p, const double* u, const double* p,
+                           const double* neumann_f, const double* pos, const int8_t* role, const double* normal,
+                           const mcd_body* bodies, int n_bodies, double mu, double* force, int* counts) {
+    if (!c) return MCD_ERR_ARG;
+    if (c->dim != 2) return fail(c, MCD_ERR_ARG, "mcd_fluid_force: 2D meshes only%s");
+    if (!valid_set(c, set_u, true) || !valid_set(c, set_p, true))
+        return fail(c, MCD_ERR_ARG, "mcd_fluid_force: set not built%s");
+    if (!u || !p || !pos || !role || !normal || !force || n_bodies < 1 || !(mu >= 0) || !isfinite(mu))
+        return fail(c, MCD_ERR_ARG, "mcd_fluid_force: invalid arguments%s");
+    BodiesDev B;
+    if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_fluid_force: invalid bodies%s");
+    double* dout = c->fbuf;
+    int* dcnt = (int*)(c->fbuf + 2 * MCD_MAX_BODIES);
+    HIPCHK(c, launch_force(c->m, c->sets[set_u].dev, c->sets[set_p].dev, u, p, neumann_f, pos, role, normal, B, mu,
+                           dout, dcnt, c->stream),
+           "fluid_force");
+    double hf[2 * MCD_MAX_BODIES];
+    int hc[3 * MCD_MAX_BODIES];
+    HIPCHK(c, hipMemcpyAsync(hf, dout, 2 * B.n * sizeof(double), hipMemcpyDeviceToHost, c->stream), "copy");
+    HIPCHK(c, hipMemcpyAsync(hc, dcnt, 3 * B.n * sizeof(int), hipMemcpyDeviceToHost, c->stream), "copy");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "fluid_force");
+    for (int k = 0; k < n_bodies; ++k) {
+        int s = -1;                   // the body's slot in id order
+        for (int q = 0; q < B.n; ++q)
+            if (B.id[q] == bodies[k].id) s = q;
+        if (hc[3 * s + 2]) return fail(c, MCD_ERR_ARG, "mcd_fluid_force: more than 4096 boundary DPs on a body%s");
+        force[2 * k] = hf[2 * s];
+        force[2 * k + 1] = hf[2 * s + 1];
+        if (counts) {
+            counts[2 * k] = hc[3 * s];
+            counts[2 * k + 1] = hc[3 * s + 1];
+        }
+    }
     return MCD_OK;
 }
 

@@ -312,6 +312,196 @@ __global__ __launch_bounds__(kBlock) void k_project(MeshDev m, SetDev st, const 
     }
 }
 
+// ---------------------------------------------------------------------------
+// Fluid force on a moving body (Sec. 3.4, evaluation of fluid forces acting on
+// moving boundaries), 2D: F = sum over the body's boundary DPs of t_i dGamma_i,
+// t = (-P I + mu (grad u + grad u^T)) . n.  One block per body: the body's
+// boundary DPs (found in a box around it) are ordered by a libm-free polar
+// angle about the body centre; dGamma_i is the mean distance to the angular
+// predecessor and successor; P and grad u at x_i come from the fit of the
+// cell shifted by sign(n) (per axis), evaluated at x_i (chi_c = 1
+// reconstruction), or from the DP's own fit when that cell is not inner.
+// ---------------------------------------------------------------------------
+
+constexpr int kForceMax = 4096;      // boundary DPs per body
+constexpr int kForceBlock = 1024;
+
+struct ForceBoxes {
+    int lo[kMaxBodies][2], hi[kMaxBodies][2];
+};
+
+// monotone stand-in for the polar angle in [0, 4), from + - / only
+__device__ __forceinline__ double diamond_angle(double dx, double dy) {
+#pragma clang fp contract(off)
+    if (dy >= 0.0) return dx >= 0.0 ? dy / (dx + dy) : 1.0 - dx / (-dx + dy);
+    return dx < 0.0 ? 2.0 - dy / (-dx - dy) : 3.0 + dx / (dx - dy);
+}
+
+__device__ __forceinline__ double seg_len(const double* __restrict__ pos, size_t Nc, int a, int b) {
+#pragma clang fp contract(off)
+    const double dx = pos[a] - pos[b], dy = pos[Nc + a] - pos[Nc + b];
+    return sqrt(dx * dx + dy * dy);
+}
+
+__global__ __launch_bounds__(kForceBlock) void k_force(MeshDev m, SetDev su, SetDev sp, const double* __restrict__ u,
+                                                      const double* __restrict__ p,
+                                                      const double* __restrict__ fneu,
+                                                      const double* __restrict__ pos,
+                                                      const int8_t* __restrict__ role,
+                                                      const double* __restrict__ normal, BodiesDev B, ForceBoxes box,
+                                                      double mu, double* __restrict__ out, int* __restrict__ cnt) {
+    __shared__ int list[kForceMax];
+    __shared__ double key[kForceMax];
+    __shared__ double fy[kForceMax];
+    __shared__ int count, fallbacks;
+    const int b = blockIdx.x;
+    const size_t Nc = (size_t)m.Nc;
+    const double rs = su.rs;
+    if (threadIdx.x == 0) {
+        count = 0;
+        fallbacks = 0;
+    }
+    __syncthreads();
+    // 1. the body's boundary DPs in its box (in arbitrary order)
+    const int nx = box.hi[b][0] - box.lo[b][0] + 1, ny = box.hi[b][1] - box.lo[b][1] + 1;
+    for (int e = threadIdx.x; e < nx * ny; e += kForceBlock) {
+        const int c = box.lo[b][0] + e % nx + m.n[0] * (box.lo[b][1] + e / nx);
+        if (role[c] == B.id[b]) {
+            const int k = atomicAdd(&count, 1);
+            if (k < kForceMax) list[k] = c;
+        }
+    }
+    __syncthreads();
+    const int n = count;
+    if (n > kForceMax || n == 0) {
+        if (threadIdx.x == 0) {
+            out[2 * b] = 0.0;
+            out[2 * b + 1] = 0.0;
+            cnt[3 * b] = n;
+            cnt[3 * b + 1] = 0;
+            cnt[3 * b + 2] = n > kForceMax ? 1 : 0;
+        }
+        return;
+    }
+    // 2. sort by (angle, cell index): bitonic over the next power of two
+    int P2 = 1;
+    while (P2 < n) P2 <<= 1;
+    for (int k = threadIdx.x; k < P2; k += kForceBlock) {
+        if (k < n) {
+            const int c = list[k];
+            key[k] = diamond_angle(pos[c] - B.c[b][0], pos[Nc + c] - B.c[b][1]);
+        } else {
+            key[k] = 1e300;
+            list[k] = 0x7fffffff;
+        }
+    }
+    __syncthreads();
+    for (int k = 2; k <= P2; k <<= 1) {
+        for (int j = k >> 1; j > 0; j >>= 1) {
+            for (int i = threadIdx.x; i < P2; i += kForceBlock) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const bool up = (i & k) == 0;
+                    const bool gt = key[i] > key[l] || (key[i] == key[l] && list[i] > list[l]);
+                    if (gt == up) {
+                        const double tk = key[i];
+                        key[i] = key[l];
+                        key[l] = tk;
+                        const int tl = list[i];
+                        list[i] = list[l];
+                        list[l] = tl;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    // 3. traction times surface element per DP, in sorted order (key reused for the x part)
+    double fx_k[kForceMax / kForceBlock], fy_k[kForceMax / kForceBlock];
+    int nk = 0;
+    for (int k = threadIdx.x; k < n; k += kForceBlock, ++nk) {
+        const int c = list[k];
+        const int cp = list[(k + n - 1) % n], cn = list[(k + 1) % n];
+        const double dgam = 0.5 * (seg_len(pos, Nc, c, cp) + seg_len(pos, Nc, c, cn));
+        int ijk[3];
+        cell_ijk(m, c, ijk);
+        const double nv[2] = {normal[c], normal[Nc + c]};
+        const int ii = ijk[0] + (nv[0] > 0.0 ? 1 : (nv[0] < 0.0 ? -1 : 0));
+        const int jj = ijk[1] + (nv[1] > 0.0 ? 1 : (nv[1] < 0.0 ? -1 : 0));
+        int ci = -1;
+        if (ii >= 0 && ii < m.n[0] && jj >= 0 && jj < m.n[1]) ci = ii + m.n[0] * jj;
+        if (ci < 0 || role[ci] != MCD_ROLE_INNER) {
+            ci = c;
+            atomicAdd(&fallbacks, 1);
+        }
+        int cijk[3];
+        cell_ijk(m, ci, cijk);
+        double Pu[2][5], Pp[1][5];
+        poly_multi<2, 2>(m, su, ci, cijk, u, nullptr, Pu);
+        poly_multi<2, 1>(m, sp, ci, cijk, p, fneu, Pp);
+        const double X[2] = {(pos[c] - pos[ci]) / rs, (pos[Nc + c] - pos[Nc + ci]) / rs};
+        double pv[5];
+        basis<2>(X, pv);
+        double P = p[ci];
+#pragma unroll
+        for (int q = 0; q < 5; ++q) P += pv[q] * Pp[0][q];
+        // d p / d X_x = (1, 0, X, Y, 0), d p / d X_y = (0, 1, 0, X, Y)
+        double G[2][2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            G[a][0] = (Pu[a][0] + X[0] * Pu[a][2] + X[1] * Pu[a][3]) / rs;
+            G[a][1] = (Pu[a][1] + X[0] * Pu[a][3] + X[1] * Pu[a][4]) / rs;
+        }
+        double t[2];
+#pragma unroll
+        for (int a = 0; a < 2; ++a) {
+            t[a] = -P * nv[a];
+#pragma unroll
+            for (int bb = 0; bb < 2; ++bb) t[a] += mu * (G[a][bb] + G[bb][a]) * nv[bb];
+        }
+        fx_k[nk] = t[0] * dgam;
+        fy_k[nk] = t[1] * dgam;
+    }
+    __syncthreads();      // every thread is done reading key and list
+    nk = 0;
+    for (int k = threadIdx.x; k < n; k += kForceBlock, ++nk) {
+        key[k] = fx_k[nk];
+        fy[k] = fy_k[nk];
+    }
+    __syncthreads();
+    // 4. sums in the sorted order
+    if (threadIdx.x == 0) {
+        double sx = 0.0, sy = 0.0;
+        for (int k = 0; k < n; ++k) {
+            sx += key[k];
+            sy += fy[k];
+        }
+        out[2 * b] = sx;
+        out[2 * b + 1] = sy;
+        cnt[3 * b] = n;
+        cnt[3 * b + 1] = fallbacks;
+        cnt[3 * b + 2] = 0;
+    }
+}
+
+hipError_t launch_force(const MeshDev& m, const SetDev& su, const SetDev& sp, const double* u, const double* p,
+                        const double* fneu, const double* pos, const int8_t* role, const double* normal,
+                        const BodiesDev& B, double mu, double* out, int* cnt, hipStream_t st) {
+    ForceBoxes box{};
+    for (int b = 0; b < B.n; ++b)
+        for (int a = 0; a < 2; ++a) {
+            // cells within R + 2 l0 of the centre hold every boundary DP of the body
+            const double ext = B.R[b] + 2.0 * m.l0;
+            int lo = (int)floor((B.c[b][a] - ext - m.origin[a]) / m.l0);
+            int hi = (int)floor((B.c[b][a] + ext - m.origin[a]) / m.l0);
+            box.lo[b][a] = lo < 0 ? 0 : (lo >= m.n[a] ? m.n[a] - 1 : lo);
+            box.hi[b][a] = hi < 0 ? 0 : (hi >= m.n[a] ? m.n[a] - 1 : hi);
+        }
+    hipLaunchKernelGGL(k_force, dim3(B.n), dim3(kForceBlock), 0, st, m, su, sp, u, p, fneu, pos, role, normal, B, box,
+                       mu, out, cnt);
+    return hipGetLastError();
+}
+
 static inline int grid_cells(int n) {
     int g = (n + kBlock - 1) / kBlock;
     return g < 1 ? 1 : (g > 8192 ? 8192 : g);

@@ -247,6 +247,9 @@ hipError_t launch_neumann_pressure(const MeshDev& m, const int8_t* role, const d
 hipError_t launch_project(const MeshDev& m, const SetDev& set, const double* P, const double* f,
                           const double* ustar, double dt, const int8_t* role, const BodiesDev& B, double* u,
                           hipStream_t st);
+hipError_t launch_force(const MeshDev& m, const SetDev& su, const SetDev& sp, const double* u, const double* p,
+                        const double* fneu, const double* pos, const int8_t* role, const double* normal,
+                        const BodiesDev& B, double mu, double* out, int* cnt, hipStream_t st);
 
 struct KrylovWork;
 struct SolveParams {

@@ -32,7 +32,7 @@ MAX_SETS = 4
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
             "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
             "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_ppe_residual", "mcd_profile",
-            "mcd_profile_read", "mcd_autotune", "mcd_set_shape", "mcd_get_shape",
+            "mcd_profile_read", "mcd_autotune", "mcd_set_shape", "mcd_get_shape", "mcd_fluid_force",
             "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
             "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_set_output_scale",
             "mcd_model_infer",
@@ -129,6 +129,7 @@ def load():
         "mcd_model_train_step": (i, [vp, vp, vp, vp, vp, P(BcTable), d, P(d)]),
         "mcd_profile_read": (i, [vp, P(d), P(C.c_longlong), P(d), P(C.c_longlong), i]),
         "mcd_autotune": (i, [vp, i, i, P(Tuning)]),
+        "mcd_fluid_force": (i, [vp, i, i, vp, vp, vp, vp, vp, vp, P(Body), i, d, P(d), P(i)]),
         "mcd_set_shape": (i, [vp, i, i]),
         "mcd_get_shape": (i, [vp, P(i), P(i), P(i)]),
     }
@@ -346,6 +347,18 @@ class Context:
         self._check(self.lib.mcd_ppe_residual(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), V(r, N),
                                               norms), "mcd_ppe_residual")
         return norms[0], norms[1]
+
+    def fluid_force(self, set_u, set_p, u, p, pos, role, normal, bodies, mu, neumann_f=None):
+        """Force of the fluid on each body (2D; see mcd_fluid_force): returns
+        ([(Fx, Fy)] per body, [(boundary DPs, fallbacks)] per body)."""
+        arr, n = bodies_array(bodies)
+        F = (C.c_double * (2 * n))()
+        cnt = (C.c_int * (2 * n))()
+        D, N, V = self.dim * self.Nc, self.Nc, self._vec
+        self._check(self.lib.mcd_fluid_force(self.h, int(set_u), int(set_p), V(u, D), V(p, N), V(neumann_f, N),
+                                             V(pos, D), _ptr(role, N, torch.int8), V(normal, D), arr, n, float(mu),
+                                             F, cnt), "mcd_fluid_force")
+        return [(F[2 * k], F[2 * k + 1]) for k in range(n)], [(cnt[2 * k], cnt[2 * k + 1]) for k in range(n)]
 
     def autotune(self, set_id, iters=32):
         """Times the stage-kernel shapes on the set's operator and applies the

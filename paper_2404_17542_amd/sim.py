@@ -117,6 +117,15 @@ class GpuSim:
         ctx.neumann_pressure(self.role, self.normal, bodies_new, self.fP)
         return pset, bodies_new, upd
 
+    def forces(self):
+        """Fluid force on each body at the current step (after finish()):
+        velocity weights of this step, pressure weights of its solve, mu = nu
+        (unit density).  2D."""
+        vset = SET_VEL[self.vel_slot]
+        pset = vset if self.same_sets else SET_P
+        return self.ctx.fluid_force(vset, pset, self.u, self.P, self.pos, self.role, self.normal, self.bodies,
+                                    self.case.nu, self.fP)
+
     def tuning_set(self):
         """A built pressure set at the current positions, for the stage-kernel
         autotuner (the velocity set when both fields share one; otherwise the
