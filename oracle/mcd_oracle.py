@@ -238,12 +238,30 @@ class RelaxConsts:
     spring: tuple         # natural lengths by number of nonzero offset axes
     eps_l0: float         # stopping threshold eps_relax * l0
     band_l0: float        # 5 l0
+    fit_half_alpha: float = 0.0   # alpha / 2 of the boundary-fitted arrangement (0: the original one)
+    fit_re: float = 0.0           # its radius r_e
+    fit_pi_over_re: float = 0.0   # pi / r_e
 
     @classmethod
-    def make(cls, l0, kappa=0.2, eps_relax=1e-6, band_over_l0=5.0):
+    def make(cls, l0, kappa=0.2, eps_relax=1e-6, band_over_l0=5.0, fit_alpha=0.0, fit_re_over_l0=5.0):
+        re = fit_re_over_l0 * l0
         return cls(kl0=kappa * l0,
                    spring=(0.0, l0, math.sqrt(2.0) * l0, math.sqrt(3.0) * l0),
-                   eps_l0=eps_relax * l0, band_l0=band_over_l0 * l0)
+                   eps_l0=eps_relax * l0, band_l0=band_over_l0 * l0,
+                   fit_half_alpha=fit_alpha * 0.5, fit_re=re, fit_pi_over_re=math.pi / re)
+
+
+def fit_cos(x):
+    """cos x from its Taylor series through x^20, by Horner in x^2 with + and *
+    only (error below 1e-10 for |x| <= pi): a cosine that every
+    implementation evaluates to the same bits, for the weight beta of the
+    boundary-fitted arrangement."""
+    c = [(-1.0 if k % 2 else 1.0) / math.factorial(2 * k) for k in range(11)]
+    x2 = x * x
+    p = c[10]
+    for k in range(9, -1, -1):
+        p = p * x2 + c[k]
+    return p
 
 
 def relax_sweep(mesh, consts, bodies, role, band, pos):
@@ -255,7 +273,11 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
     edge, sqrt(2) l0 for a diagonal (sqrt(3) l0 for a 3D corner: reading);
     explicit Euler x* = x - (kappa l0) F (dimensionless form times l0).
     (iii) Boundary DPs: x** = x* + psi d, d = -grad psi/|grad psi|, i.e.
-    x** = x* - (psi/r) (x* - c) for a circle/sphere of centre c.
+    x** = x* - (psi/r) (x* - c) for a circle/sphere of centre c.  With the
+    boundary-fitted arrangement (Sec. 4, Eqs. dp_arrng_boundary-fit_x** and
+    dp_arrng_beta; alpha > 0) inner DPs also move: x** = x* + beta psi d with
+    beta = alpha/2 (1 + cos(pi psi / r_e)) for psi < r_e, else 0, where psi
+    and d belong to the nearest body (smallest psi, lower id on ties).
     (iv) Clamp every coordinate to the DP's own cell.
     Slots are visited in lexicographic order; sums are left to right.
     """
@@ -298,6 +320,28 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
             t = psi / r
             for a in range(dim):
                 xs[a] = np.where(sel, xs[a] - t * dd[a], xs[a])
+        if consts.fit_half_alpha > 0.0 and bodies:
+            inner = rb == INNER
+            best = None
+            for b in sorted(bodies, key=lambda q: q.body_id):
+                dd = [xs[a] - b.centre[a] for a in range(dim)]
+                r2 = dd[0] * dd[0]
+                for a in range(1, dim):
+                    r2 = r2 + dd[a] * dd[a]
+                r = np.sqrt(r2)
+                psi = r - b.radius
+                if best is None:
+                    best = (psi, r, dd)
+                else:
+                    closer = psi < best[0]
+                    best = (np.where(closer, psi, best[0]), np.where(closer, r, best[1]),
+                            [np.where(closer, dd[a], best[2][a]) for a in range(dim)])
+            psi, r, dd = best
+            move = inner & (psi < consts.fit_re)
+            beta = consts.fit_half_alpha * (1.0 + fit_cos(psi * consts.fit_pi_over_re))
+            t = (beta * psi) / r
+            for a in range(dim):
+                xs[a] = np.where(move, xs[a] - t * dd[a], xs[a])
     out = pos.copy()
     mx = 0.0
     for a in range(dim):

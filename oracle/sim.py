@@ -29,7 +29,8 @@ class OracleSim:
     def __init__(self, case, mixed=False):
         self.case = case
         self.mesh = O.Mesh.from_case(case)
-        self.consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0)
+        self.consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0,
+                                         case.fit_alpha, case.fit_re_over_l0)
         self.re = case.re_over_l0 * case.l0
         self.rs = case.rs_over_l0 * case.l0
         self.mixed = mixed

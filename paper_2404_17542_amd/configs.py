@@ -48,6 +48,8 @@ class Case:
     n_relax: int = 20
     n_relax_init: int = 500
     eps_relax: float = 1e-6
+    fit_alpha: float = 0.0        # boundary-fitted arrangement (Sec. 4): 0 = original, paper example 0.03
+    fit_re_over_l0: float = 5.0   # its radius r_e / l0
     body: Optional[Body] = None
     nu: float = 0.0
     dt: float = 0.0

@@ -40,7 +40,8 @@ def _dev(a, dtype=torch.float64):
 
 def _dps_parity(M, case, steps, init_sweeps, check_every_step=True):
     m = O.Mesh.from_case(case)
-    consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0)
+    consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0, case.fit_alpha,
+                                case.fit_re_over_l0)
     pos0 = inputs.jittered_positions(case.n, case.origin, case.l0, case.jitter_seed)
     ob = oracle_bodies(case, 0.0)
     role0 = O.roles(m, ob)
@@ -126,7 +127,8 @@ def test_role_error_on_body_jump(M):
 
 def _arranged(case, sweeps=100):
     m = O.Mesh.from_case(case)
-    consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0)
+    consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0, case.fit_alpha,
+                                case.fit_re_over_l0)
     pos = inputs.jittered_positions(case.n, case.origin, case.l0, case.jitter_seed)
     ob = oracle_bodies(case, 0.0)
     up = O.update_dps(m, consts, ob, pos, O.roles(m, ob), sweeps if ob else 0)

@@ -172,3 +172,55 @@ def test_relaxation_stability_3d_reading():
     assert stable[-1] < 0.2 * stable[0]
     unstable = _perturbed_regular_3d(0.2, 30)
     assert max(unstable[5:]) > 2 * unstable[0]
+
+
+# ---------------------------------------------------------------------------
+# Boundary-fitted arrangement (Sec. 4, Eqs. dp_arrng_boundary-fit_x** and
+# dp_arrng_beta)
+# ---------------------------------------------------------------------------
+
+def test_fit_cos_is_the_cosine():
+    x = np.linspace(-np.pi, np.pi, 20001)
+    assert np.abs(O.fit_cos(x) - np.cos(x)).max() < 1e-10
+    assert O.fit_cos(0.0) == 1.0 and abs(O.fit_cos(np.pi) + 1.0) < 1e-10
+
+
+def test_boundary_fitted_step_of_an_inner_dp():
+    """DPs at the centroids of a regular grid feel no spring force, so one
+    sweep moves an inner DP (whose neighbours are all inner) by exactly
+    beta psi towards the body with beta = alpha/2 (1 + cos(pi psi / r_e)) for
+    psi < r_e, and not at all for psi >= r_e; alpha = 0 is the original
+    algorithm bit for bit."""
+    n, l0 = 64, 1.0 / 64
+    m = O.Mesh(2, (n, n), (0.0, 0.0), l0)
+    body = O.BodyState((0.5 + 0.3 * l0, 0.5 - 0.2 * l0), 10 * l0, 2)
+    pos = inputs.cell_centroids(m.n, m.origin, l0)
+    role = O.roles(m, [body])
+    band = O.band_cells(m, [body], role, 5.0 * l0)
+    alpha, re_l0 = 0.03, 3.0          # r_e below the 5 l0 band: band DPs beyond r_e stay
+    fit = O.RelaxConsts.make(l0, fit_alpha=alpha, fit_re_over_l0=re_l0)
+    out, _ = O.relax_sweep(m, fit, [body], role, band, pos)
+    out0, _ = O.relax_sweep(m, O.RelaxConsts.make(l0), [body], role, band, pos)
+    out00, _ = O.relax_sweep(m, O.RelaxConsts.make(l0, fit_alpha=0.0), [body], role, band, pos)
+    assert np.array_equal(out0, out00)
+    ijk = m.ijk(band)
+    checked = far = 0
+    for k, c in enumerate(band):
+        if role[c] != O.INNER:
+            continue
+        nb = [(ijk[0][k] + dx) + n * (ijk[1][k] + dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1)]
+        if any(role[j] != O.INNER for j in nb):
+            continue                       # a boundary neighbour exerts a spring force
+        d = pos[:, c] - np.array(body.centre)
+        r = np.hypot(d[0], d[1])
+        psi = r - body.radius
+        moved = out[:, c] - out0[:, c]
+        if psi >= re_l0 * l0:
+            assert np.all(moved == 0.0)
+            far += 1
+            continue
+        beta = alpha / 2 * (1 + np.cos(np.pi * psi / (re_l0 * l0)))
+        # fit_cos is the cosine to 1e-10 (absolute), which bounds beta's error
+        np.testing.assert_allclose(moved, -beta * psi * d / r, rtol=0, atol=alpha * psi * 1e-10 + 1e-16)
+        checked += 1
+    assert checked > 20 and far > 0
