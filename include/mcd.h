@@ -82,6 +82,11 @@ typedef struct {
     double kappa;          /* relaxation coefficient [1/5] */
     double band_over_l0;   /* DPs re-positioned within this distance of a body [5] */
     double eps_relax;      /* relaxation stops when max |dx| <= eps_relax * l0 */
+    double fit_alpha;      /* boundary-fitted arrangement (Sec. 4, Eqs. dp_arrng_boundary-fit_x**,
+                              dp_arrng_beta): inner DPs of the band move by beta psi towards the
+                              nearest body, beta = fit_alpha/2 (1 + cos(pi psi / r_e)) for psi < r_e;
+                              0 = the original arrangement [0; the paper's example 0.03], in [0, 1] */
+    double fit_re_over_l0; /* its r_e / l0 [5]; > 0 when fit_alpha > 0 */
 } mcd_params;
 
 /* Rigid circle (2D) / sphere (3D) at one time level; host memory.

@@ -48,6 +48,7 @@ struct mcd_ctx {
     KrylovWork* kw = nullptr;
     // host constants of the arrangement (computed once, used identically by every call)
     double kl0 = 0, spring[4] = {0, 0, 0, 0}, eps_l0 = 0, band_l0 = 0, re = 0, rs = 0;
+    FitDev fit{0.0, 0.0, 0.0};
     std::string err;
 };
 
@@ -127,7 +128,9 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
     if (!(mesh->l0 > 0) || !isfinite(mesh->l0)) return MCD_ERR_ARG;
     if (mesh->walls && (mesh->wall_id < 1 || mesh->wall_id >= MCD_MAX_IDS)) return MCD_ERR_ARG;
     if (!(prm->re_over_l0 > 0) || !(prm->rs_over_l0 > 0) || !(prm->kappa > 0) || !(prm->band_over_l0 >= 0) ||
-        !(prm->eps_relax >= 0) || (prm->weight_kind != MCD_WEIGHT_COS2 && prm->weight_kind != MCD_WEIGHT_GAUSS))
+        !(prm->eps_relax >= 0) || (prm->weight_kind != MCD_WEIGHT_COS2 && prm->weight_kind != MCD_WEIGHT_GAUSS) ||
+        !(prm->fit_alpha >= 0 && prm->fit_alpha <= 1) ||
+        (prm->fit_alpha > 0 && (!(prm->fit_re_over_l0 > 0) || !isfinite(prm->fit_re_over_l0))))
         return MCD_ERR_ARG;
     mcd_ctx* c = new mcd_ctx();
     c->desc = *mesh;
@@ -157,6 +160,10 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
     c->spring[3] = sqrt(3.0) * l0;
     c->eps_l0 = prm->eps_relax * l0;
     c->band_l0 = prm->band_over_l0 * l0;
+    if (prm->fit_alpha > 0) {
+        const double re_fit = prm->fit_re_over_l0 * l0;
+        c->fit = FitDev{prm->fit_alpha * 0.5, re_fit, M_PI / re_fit};
+    }
     c->re = prm->re_over_l0 * l0;
     c->rs = prm->rs_over_l0 * l0;
 
@@ -290,7 +297,7 @@ mcd_status mcd_update_dps(mcd_ctx* c, const mcd_body* bodies, int n_bodies, int 
         const double* pin = (s & 1) ? c->pos_tmp : pos;
         double* pout = (s & 1) ? pos : c->pos_tmp;
         // an empty band (no body) still runs one sweep over nothing, as in the definition
-        HIPCHK(c, launch_relax(m, B, c->kl0, c->spring, c->eps_l0, role, c->band, pin, pout, lo, box ? bn : lo, c->dmax,
+        HIPCHK(c, launch_relax(m, B, c->kl0, c->spring, c->eps_l0, c->fit, role, c->band, pin, pout, lo, box ? bn : lo, c->dmax,
                                s, c->relax_state, st),
                "relax");
     }

@@ -220,8 +220,12 @@ struct Ctx;
 hipError_t launch_roles(const MeshDev& m, const BodiesDev& B, double band_l0, int8_t* role, int8_t* role_prev,
                         double* pos, double* pos_prev, uint8_t* trans, uint8_t* band, int* counts,
                         int* latch, hipStream_t st);
+// host constants of the boundary-fitted arrangement (half_alpha = 0: off)
+struct FitDev {
+    double half_alpha, re, pi_over_re;
+};
 hipError_t launch_relax(const MeshDev& m, const BodiesDev& B, double kl0, const double* spring, double eps_l0,
-                        const int8_t* role, const uint8_t* band, const double* pin, double* pout,
+                        const FitDev& fit, const int8_t* role, const uint8_t* band, const double* pin, double* pout,
                         const int box_lo[3], const int box_n[3], unsigned long long* dmax, int sweep,
                         int* state, hipStream_t st);
 hipError_t launch_copy_band(const MeshDev& m, const uint8_t* band, const double* src, double* dst,

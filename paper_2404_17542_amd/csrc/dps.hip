@@ -111,9 +111,30 @@ __global__ __launch_bounds__(kBlock) void k_roles(MeshDev m, BodiesDev B, double
 // state[0]: converged flag, state[1]: sweeps executed.
 // ---------------------------------------------------------------------------
 
+// cos x from its Taylor series through x^20 (error below 1e-10 for
+// |x| <= pi), by Horner in x^2 with + and * only, so that it gives the same
+// bits wherever it is evaluated (the weight beta of the boundary-fitted
+// arrangement enters the bit-exact DP positions).  Coefficients
+// (-1)^k / (2k)!, the factorials exact in FP64 up to 20!.
+__device__ __forceinline__ double fit_cos(double x) {
+    double c[11];
+    double f = 1.0;
+#pragma unroll
+    for (int k = 0; k <= 10; ++k) {
+        if (k > 0) f = f * (double)(2 * k - 1) * (double)(2 * k);
+        c[k] = (k % 2 ? -1.0 : 1.0) / f;
+    }
+    const double x2 = x * x;
+    double p = c[10];
+#pragma unroll
+    for (int k = 9; k >= 0; --k) p = p * x2 + c[k];
+    return p;
+}
+
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double kl0, double sp1, double sp2,
-                                                  double sp3, double eps_l0, const int8_t* __restrict__ role,
+                                                  double sp3, double eps_l0, FitDev fit,
+                                                  const int8_t* __restrict__ role,
                                                   const uint8_t* __restrict__ band, const double* __restrict__ pin,
                                                   double* __restrict__ pout, int lo0, int lo1, int lo2, int bn0,
                                                   int bn1, int bn2, unsigned long long* dmax, int sweep,
@@ -180,6 +201,33 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
             const double t = psi / r;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) xs[a] = xs[a] - t * dd[a];
+        }
+        if (fit.half_alpha > 0.0 && rc == MCD_ROLE_INNER && B.n > 0) {
+            // boundary-fitted arrangement: towards the nearest body (bodies
+            // are in ascending id order; ties keep the lower id)
+            double best = 0.0, rb = 1.0, db[DIM];
+            for (int b = 0; b < B.n; ++b) {
+                double dd[DIM];
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) dd[a] = xs[a] - B.c[b][a];
+                double r2 = dd[0] * dd[0];
+#pragma unroll
+                for (int a = 1; a < DIM; ++a) r2 = r2 + dd[a] * dd[a];
+                const double r = sqrt(r2);
+                const double psi = r - B.R[b];
+                if (b == 0 || psi < best) {
+                    best = psi;
+                    rb = r;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) db[a] = dd[a];
+                }
+            }
+            if (best < fit.re) {
+                const double beta = fit.half_alpha * (1.0 + fit_cos(best * fit.pi_over_re));
+                const double t = (beta * best) / rb;
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) xs[a] = xs[a] - t * db[a];
+            }
         }
 #pragma unroll
         for (int a = 0; a < DIM; ++a) {
@@ -290,18 +338,18 @@ hipError_t launch_roles(const MeshDev& m, const BodiesDev& B, double band_l0, in
 }
 
 hipError_t launch_relax(const MeshDev& m, const BodiesDev& B, double kl0, const double* spring, double eps_l0,
-                        const int8_t* role, const uint8_t* band, const double* pin, double* pout,
+                        const FitDev& fit, const int8_t* role, const uint8_t* band, const double* pin, double* pout,
                         const int box_lo[3], const int box_n[3], unsigned long long* dmax, int sweep,
                         int* state, hipStream_t st) {
     const long long nbox = (long long)box_n[0] * box_n[1] * box_n[2];
     const int g = grid_for(nbox);
     if (m.dim == 2)
         hipLaunchKernelGGL(k_relax<2>, dim3(g), dim3(kBlock), 0, st, m, B, kl0, spring[1], spring[2], spring[3],
-                           eps_l0, role, band, pin, pout, box_lo[0], box_lo[1], box_lo[2], box_n[0], box_n[1],
+                           eps_l0, fit, role, band, pin, pout, box_lo[0], box_lo[1], box_lo[2], box_n[0], box_n[1],
                            box_n[2], dmax, sweep, state);
     else
         hipLaunchKernelGGL(k_relax<3>, dim3(g), dim3(kBlock), 0, st, m, B, kl0, spring[1], spring[2], spring[3],
-                           eps_l0, role, band, pin, pout, box_lo[0], box_lo[1], box_lo[2], box_n[0], box_n[1],
+                           eps_l0, fit, role, band, pin, pout, box_lo[0], box_lo[1], box_lo[2], box_n[0], box_n[1],
                            box_n[2], dmax, sweep, state);
     return hipGetLastError();
 }

@@ -46,7 +46,8 @@ class MeshDesc(C.Structure):
 
 class Params(C.Structure):
     _fields_ = [("weight_kind", C.c_int), ("re_over_l0", C.c_double), ("rs_over_l0", C.c_double),
-                ("kappa", C.c_double), ("band_over_l0", C.c_double), ("eps_relax", C.c_double)]
+                ("kappa", C.c_double), ("band_over_l0", C.c_double), ("eps_relax", C.c_double),
+                ("fit_alpha", C.c_double), ("fit_re_over_l0", C.c_double)]
 
 
 class Body(C.Structure):
@@ -191,7 +192,7 @@ class Context:
 
     def __init__(self, dim, n, origin, l0, periodic=(False, False, False), walls=False, wall_id=1,
                  weight="cos2", re_over_l0=2.5, rs_over_l0=1.0, kappa=0.2, band_over_l0=5.0, eps_relax=1e-6,
-                 stream=None):
+                 stream=None, fit_alpha=0.0, fit_re_over_l0=5.0):
         self.lib = load()
         md = MeshDesc()
         md.dim = dim
@@ -206,6 +207,7 @@ class Context:
         pr.weight_kind = WEIGHT_COS2 if weight == "cos2" else WEIGHT_GAUSS
         pr.re_over_l0, pr.rs_over_l0, pr.kappa = re_over_l0, rs_over_l0, kappa
         pr.band_over_l0, pr.eps_relax = band_over_l0, eps_relax
+        pr.fit_alpha, pr.fit_re_over_l0 = float(fit_alpha), float(fit_re_over_l0)
         self.dim = dim
         self.n = tuple(int(v) for v in n[:dim])
         self.Nc = 1
@@ -224,6 +226,8 @@ class Context:
     @classmethod
     def from_case(cls, case, **kw):
         from .configs import WALL_ID
+        kw.setdefault("fit_alpha", case.fit_alpha)
+        kw.setdefault("fit_re_over_l0", case.fit_re_over_l0)
         return cls(case.dim, case.n, case.origin, case.l0, case.periodic, case.walls, WALL_ID, case.weight,
                    case.re_over_l0, case.rs_over_l0, case.kappa, case.band_over_l0, case.eps_relax, **kw)
 

@@ -102,6 +102,25 @@ def test_update_dps_bitexact_cylinder_full_size(M):
     _dps_parity(M, case, steps=4, init_sweeps=case.n_relax_init, check_every_step=True)
 
 
+@pytest.mark.parametrize("which", ["cylinder", "sphere"])
+def test_update_dps_bitexact_boundary_fitted(M, which):
+    """Boundary-fitted arrangement (alpha = 0.03, r_e = 5 l0): bit-exact over
+    the initial arrangement and several steps, and different from the
+    original arrangement."""
+    from dataclasses import replace
+    base = configs.c2_oscillating_cylinder(n=256) if which == "cylinder" else configs.c4_moving_sphere(n=32)
+    case = replace(base, fit_alpha=0.03, fit_re_over_l0=5.0)
+    _dps_parity(M, case, steps=10 if which == "cylinder" else 4, init_sweeps=200)
+    m = O.Mesh.from_case(case)
+    ob = oracle_bodies(case, 0.0)
+    pos0 = inputs.jittered_positions(case.n, case.origin, case.l0, case.jitter_seed)
+    fit = O.update_dps(m, O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0, 0.03, 5.0),
+                       ob, pos0, O.roles(m, ob), 200)
+    orig = O.update_dps(m, O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0), ob, pos0,
+                        O.roles(m, ob), 200)
+    assert np.abs(fit.pos - orig.pos).max() > 1e-3 * case.l0
+
+
 def test_role_error_on_body_jump(M):
     case = configs.c2_oscillating_cylinder(n=128)
     ctx = M.Context.from_case(case)
