@@ -92,7 +92,8 @@ typedef struct {
 /* Rigid circle (2D) / sphere (3D) at one time level; host memory.
  * psi = |x - centre| - radius (> 0 in the fluid, Sec. 2.5). */
 typedef struct {
-    int id;              /* role id of its boundary DPs (1 .. 15), != wall_id */
+    int id;              /* role id of its boundary DPs (1 .. 15), != wall_id, distinct
+                            within one body list (MCD_ERR_ARG otherwise) */
     double centre[3];
     double radius;
     double velocity[3];  /* V of Eq. (velocity_moving_boundary) (translation) */

@@ -59,10 +59,8 @@ class OracleSim:
         self.st_vel = self._build(case.bc_velocity)
 
     def bodies_at(self, t):
-        b = self.case.body
-        if b is None:
-            return []
-        return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t))]
+        return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t))
+                for b in self.case.rigid_bodies]
 
     def _build(self, bc):
         return O.mls_build(self.mesh, self.pos, self.role, self.normal, bc, self.re, self.rs,

@@ -1,7 +1,8 @@
 """Workload definitions (data only): mesh, DP jitter seed, bodies, physics constants.
 
 Role ids: the outer ring (2D) / shell (3D) of cells is the wall boundary with
-id WALL_ID; the moving rigid body has id BODY_ID.  Per-field boundary
+id WALL_ID; the moving rigid body has id BODY_ID (further bodies take the ids
+after it).  Per-field boundary
 conditions are given per id (Dirichlet or Neumann) for the pressure set and
 the velocity set.
 """
@@ -51,6 +52,7 @@ class Case:
     fit_alpha: float = 0.0        # boundary-fitted arrangement (Sec. 4): 0 = original, paper example 0.03
     fit_re_over_l0: float = 5.0   # its radius r_e / l0
     body: Optional[Body] = None
+    more_bodies: tuple = ()       # further bodies (distinct ids), after `body`
     nu: float = 0.0
     dt: float = 0.0
     steps: int = 1
@@ -59,6 +61,11 @@ class Case:
     bc_pressure: dict = field(default_factory=dict)
     bc_velocity: dict = field(default_factory=dict)
     pin_first: bool = False
+
+    @property
+    def rigid_bodies(self):
+        """Every body of the case: `body` first, then `more_bodies`."""
+        return ((self.body,) if self.body is not None else ()) + tuple(self.more_bodies)
 
     @property
     def n_cells(self):
@@ -98,6 +105,24 @@ def c2_oscillating_cylinder(n=1024, steps=50):
                 body=Body(radius=0.5 * diam, motion=Oscillation((0.0, 0.0), amp, freq, 0)),
                 nu=u_max * diam / 100.0, dt=(1.0 / 800.0) * (1024.0 / n), steps=steps,
                 bc_pressure={1: DIRICHLET, 2: NEUMANN}, bc_velocity={1: NEUMANN, 2: DIRICHLET})
+
+
+def c2_two_cylinders(n=256, steps=50):
+    """[-4, 4]^2 with two cylinders whose relaxation bands overlap: D = 1 at
+    (-0.9, 0) with x(t) = 0.15 sin(2 pi t) (id 2) and D = 0.7 at (0.5, 0)
+    with y(t) = 0.15 sin(2 pi t + pi/2) (id 3); the surface gap is 0.55 at
+    rest and 0.4 at the closest, so on a 128^2 mesh the 5 l0 bands overlap.  Re = 100 on the first cylinder's peak speed and diameter; walls
+    and bodies as in C2."""
+    amp, freq, diam = 0.15, 1.0, 1.0
+    u_max = 2 * math.pi * freq * amp
+    base = c2_oscillating_cylinder(n=n, steps=steps)
+    return replace(base, name=f"C2-two-cylinders-{n}", jitter_seed=5,
+                   body=Body(radius=0.5 * diam, motion=Oscillation((-0.9, 0.0), amp, freq, 0)),
+                   more_bodies=(Body(radius=0.35, motion=Oscillation((0.5, 0.0), amp, freq, 1, 0.5 * math.pi),
+                                     body_id=BODY_ID + 1),),
+                   nu=u_max * diam / 100.0,
+                   bc_pressure={1: DIRICHLET, 2: NEUMANN, 3: NEUMANN},
+                   bc_velocity={1: NEUMANN, 2: DIRICHLET, 3: DIRICHLET})
 
 
 def c3_cylinder_variant(seed, n=1024, steps=120):

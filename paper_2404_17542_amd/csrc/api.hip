@@ -83,6 +83,7 @@ static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* ou
     for (int k = 0; k < n; ++k) {
         const mcd_body& b = bodies[order[k]];
         if (b.id < 1 || b.id >= MCD_MAX_IDS || (c->desc.walls && b.id == c->desc.wall_id)) return false;
+        if (k > 0 && b.id == out->id[k - 1]) return false;     // ids are distinct
         if (!(b.radius > 0) || !isfinite(b.radius)) return false;
         out->id[k] = b.id;
         for (int a = 0; a < 3; ++a) {

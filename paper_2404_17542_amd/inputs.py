@@ -85,20 +85,21 @@ def tgv_pressure(pos, t, nu):
 
 @dataclass(frozen=True)
 class Oscillation:
-    """Body centre c(t) = c0 + A sin(2 pi f t) e_axis; velocity is its derivative."""
+    """Body centre c(t) = c0 + A sin(2 pi f t + phase) e_axis; velocity is its derivative."""
     c0: tuple
     amplitude: float
     freq: float
     axis: int = 0
+    phase: float = 0.0
 
     def centre(self, t):
         c = list(self.c0)
-        c[self.axis] = self.c0[self.axis] + self.amplitude * math.sin(2 * math.pi * self.freq * t)
+        c[self.axis] = self.c0[self.axis] + self.amplitude * math.sin(2 * math.pi * self.freq * t + self.phase)
         return tuple(float(v) for v in c)
 
     def velocity(self, t):
         v = [0.0] * len(self.c0)
-        v[self.axis] = 2 * math.pi * self.freq * self.amplitude * math.cos(2 * math.pi * self.freq * t)
+        v[self.axis] = 2 * math.pi * self.freq * self.amplitude * math.cos(2 * math.pi * self.freq * t + self.phase)
         return tuple(v)
 
 

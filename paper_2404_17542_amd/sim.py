@@ -83,16 +83,16 @@ class GpuSim:
         torch.cuda.synchronize()
 
     def bodies_at(self, t, prev):
-        b = self.case.body
-        if b is None:
-            return []
-        vel = b.motion.velocity(t)
-        if prev is None:
-            dvdt = (0.0,) * len(vel)
-        else:
-            dvdt = tuple((vn - vo) / self.case.dt for vn, vo in zip(vel, prev[0]["velocity"]))
-        return [{"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
-                 "dvdt": dvdt}]
+        out = []
+        for i, b in enumerate(self.case.rigid_bodies):
+            vel = b.motion.velocity(t)
+            if prev is None:
+                dvdt = (0.0,) * len(vel)
+            else:
+                dvdt = tuple((vn - vo) / self.case.dt for vn, vo in zip(vel, prev[i]["velocity"]))
+            out.append({"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
+                        "dvdt": dvdt})
+        return out
 
     def prepare(self):
         """First half of a step: DP update at t^{k+1}, remap, weights, u* and

@@ -9,18 +9,14 @@ def np_(t):
 
 
 def oracle_bodies(case, t):
-    b = case.body
-    if b is None:
-        return []
-    return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t))]
+    return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t))
+            for b in case.rigid_bodies]
 
 
 def gpu_bodies(case, t, dvdt=None):
-    b = case.body
-    if b is None:
-        return []
     return [{"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius,
-             "velocity": b.motion.velocity(t), "dvdt": dvdt or (0.0,) * case.dim}]
+             "velocity": b.motion.velocity(t), "dvdt": dvdt or (0.0,) * case.dim}
+            for b in case.rigid_bodies]
 
 
 def bits_equal(a, b):

@@ -26,3 +26,25 @@ def test_variants(variant, base):
         assert variant(seed, n=64) == c
         seen.add((m.amplitude, m.freq))
     assert len(seen) == 20
+
+
+def test_two_cylinders_case():
+    """Distinct body ids with a boundary condition each, the phase-shifted
+    oscillation of the second body (c(0) = c0 + A e_y), a surface gap that
+    stays positive over a period, and overlapping 5 l0 bands on 128^2."""
+    c = configs.c2_two_cylinders(n=128)
+    A, B = c.rigid_bodies
+    assert (A.body_id, B.body_id) == (configs.BODY_ID, configs.BODY_ID + 1)
+    for bc in (c.bc_pressure, c.bc_velocity):
+        assert set(bc) == {configs.WALL_ID, A.body_id, B.body_id}
+    assert B.motion.centre(0.0) == (0.5, 0.15)
+    assert abs(B.motion.velocity(0.0)[1]) < 1e-15
+    gaps = []
+    for k in range(200):
+        t = k / 200.0
+        ca, cb = A.motion.centre(t), B.motion.centre(t)
+        gaps.append(math.dist(ca, cb) - A.radius - B.radius)
+    assert 0.35 < min(gaps) < max(gaps) < 2 * c.band_over_l0 * c.l0 + 0.1
+    assert min(gaps) < 2 * c.band_over_l0 * c.l0
+    assert configs.c2_oscillating_cylinder(n=128).rigid_bodies == (configs.c2_oscillating_cylinder(n=128).body,)
+    assert configs.c1_taylor_green(n=64).rigid_bodies == ()

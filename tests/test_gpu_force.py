@@ -49,6 +49,36 @@ def test_force_matches_oracle_on_a_running_cylinder(M):
     assert np.abs(np.array(F[0]) - Fo[0]).max() <= 1e-10 * scale, (F[0], Fo[0], scale)
 
 
+def test_force_on_two_cylinders_matches_oracle(M):
+    """Two bodies: the force on each (in the order of the body list) equals
+    the oracle's; each body's surface elements are its own boundary DPs."""
+    from paper_2404_17542_amd.sim import GpuSim
+    case = configs.c2_two_cylinders(n=128, steps=4)
+    sim = GpuSim(case)
+    for _ in range(4):
+        sim.step()
+    F, cnt = sim.forces()
+    m = O.Mesh.from_case(case)
+    pos, role, nrm = np_(sim.pos), np_(sim.role), np_(sim.normal)
+    u, p, f = np_(sim.u), np_(sim.P), np_(sim.fP)
+    bodies = [O.BodyState(centre=tuple(b["centre"]), radius=b["radius"], body_id=b["id"]) for b in sim.bodies]
+    assert [b.body_id for b in bodies] == [2, 3]
+    re, rs = case.re_over_l0 * case.l0, case.rs_over_l0 * case.l0
+    Fo, co = O.fluid_force(m, pos, role, nrm, bodies, case.bc_velocity, case.bc_pressure, u, p, f, re, rs,
+                           case.nu, case.weight)
+    for k, body in enumerate(bodies):
+        assert cnt[k] == co[k] and cnt[k][0] == (role == body.body_id).sum()
+        scale = np.abs(p[role == body.body_id]).max() * 2 * math.pi * body.radius + 1e-30
+        assert np.abs(np.array(F[k]) - Fo[k]).max() <= 1e-10 * scale, (k, F[k], Fo[k], scale)
+    # the output rows follow the order of the body list
+    from paper_2404_17542_amd.sim import SET_P, SET_VEL
+    vset = SET_VEL[sim.vel_slot]
+    pset = vset if sim.same_sets else SET_P
+    Fr, cr = sim.ctx.fluid_force(vset, pset, sim.u, sim.P, sim.pos, sim.role, sim.normal, sim.bodies[::-1],
+                                 case.nu, sim.fP)
+    assert Fr == F[::-1] and cr == cnt[::-1]
+
+
 def _arranged(case, sweeps=100):
     m = O.Mesh.from_case(case)
     consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0)

@@ -121,6 +121,31 @@ def test_update_dps_bitexact_boundary_fitted(M, which):
     assert np.abs(fit.pos - orig.pos).max() > 1e-3 * case.l0
 
 
+@pytest.mark.parametrize("fit_alpha", [0.0, 0.03])
+def test_update_dps_bitexact_two_cylinders(M, fit_alpha):
+    """Two cylinders with overlapping bands (ids 2 and 3): nearest-body
+    roles, relaxation and (alpha > 0) boundary-fitted moves bit-exact over
+    the initial arrangement and 12 steps."""
+    from dataclasses import replace
+    case = replace(configs.c2_two_cylinders(n=128), fit_alpha=fit_alpha)
+    _dps_parity(M, case, steps=12, init_sweeps=200)
+
+
+def test_duplicate_body_ids_rejected(M):
+    case = configs.c2_two_cylinders(n=64)
+    ctx = M.Context.from_case(case)
+    pos = _dev(inputs.jittered_positions(case.n, case.origin, case.l0, 5))
+    role = torch.full((case.n_cells,), -1, dtype=torch.int8, device="cuda")
+    z = [torch.zeros_like(pos), torch.zeros_like(role), torch.zeros((case.n_cells,), dtype=torch.uint8, device="cuda"),
+         torch.zeros_like(pos)]
+    b = gpu_bodies(case, 0.0)
+    b[1]["id"] = b[0]["id"]
+    with pytest.raises(M.McdError) as ei:
+        ctx.update_dps(b, 0, pos, role, z[0], z[1], z[2], z[3], info=False)
+    assert ei.value.status == 1
+    assert np.all(np_(role) == -1)                                    # nothing ran
+
+
 def test_role_error_on_body_jump(M):
     case = configs.c2_oscillating_cylinder(n=128)
     ctx = M.Context.from_case(case)
@@ -587,6 +612,33 @@ def test_cylinder_steps_match_oracle(M):
         assert bits_equal(np_(g.pos), o.pos) and bits_equal(np_(g.role), o.role)
     assert np.abs(np_(g.u) - o.u).max() / np.abs(o.u).max() < 1e-6
     # pressure at inner DPs (body DPs carry decoupled collocation rows)
+    inner = o.role == O.INNER
+    P = np_(g.P)
+    assert np.abs(P - o.P)[inner].max() / np.abs(o.P[inner]).max() < 1e-5
+
+
+def test_two_cylinders_steps_match_oracle(M):
+    """Whole steps with two bodies (ids 2 and 3, bands overlapping): DP
+    arrays bit-exact, velocity within 1e-6 and inner pressure within 1e-5 of
+    the oracle; every body DP carries its own body's velocity."""
+    from paper_2404_17542_amd.sim import GpuSim
+    case = configs.c2_two_cylinders(n=128, steps=6)
+    g = GpuSim(case)
+    o = OracleSim(case)
+    assert bits_equal(np_(g.pos), o.pos) and bits_equal(np_(g.role), o.role)
+    for _ in range(6):
+        rg = g.step()
+        ro = o.step()
+        assert rg["converged"] and rg["rel_res"] <= 1e-8
+        assert rg["sweeps"] == ro["sweeps"] and rg["trans"] == ro["trans"]
+        assert bits_equal(np_(g.pos), o.pos) and bits_equal(np_(g.role), o.role)
+    ug = np_(g.u)
+    assert np.abs(ug - o.u).max() / np.abs(o.u).max() < 1e-6
+    for b in o.bodies:
+        sel = o.role == b.body_id
+        assert sel.sum() > 10
+        for a in range(2):
+            assert np.all(ug[a, sel] == b.velocity[a])
     inner = o.role == O.INNER
     P = np_(g.P)
     assert np.abs(P - o.P)[inner].max() / np.abs(o.P[inner]).max() < 1e-5

@@ -224,3 +224,97 @@ def test_boundary_fitted_step_of_an_inner_dp():
         np.testing.assert_allclose(moved, -beta * psi * d / r, rtol=0, atol=alpha * psi * 1e-10 + 1e-16)
         checked += 1
     assert checked > 20 and far > 0
+
+
+# ---------------------------------------------------------------------------
+# several bodies (Sec. 2.2-2.4 applied per body; nearest-body readings)
+# ---------------------------------------------------------------------------
+
+def test_two_separated_bodies_arrange_as_each_alone():
+    """Bodies whose bands are far apart: with a fixed sweep count (eps = 0)
+    the two-body roles and positions are, bit for bit, the union of the
+    single-body results; each body's cells carry its own id."""
+    from paper_2404_17542_amd import configs
+    case = configs.c2_oscillating_cylinder(n=64)
+    m = O.Mesh.from_case(case)
+    consts = O.RelaxConsts.make(case.l0, case.kappa, 0.0, case.band_over_l0)
+    A = O.BodyState((-2.0, 0.3), 0.6, 2)
+    B = O.BodyState((1.9, -0.2), 0.45, 3)
+    pos0 = inputs.jittered_positions(case.n, case.origin, case.l0, 3)
+
+    def arrange(bodies):
+        return O.update_dps(m, consts, bodies, pos0, O.roles(m, bodies), 40)
+
+    ua, ub, uab = arrange([A]), arrange([B]), arrange([B, A])      # order of the list is irrelevant
+    assert uab.sweeps == ua.sweeps == ub.sweeps == 40
+    assert np.array_equal(uab.role, np.where(ua.role != O.INNER, ua.role, ub.role))
+    assert (uab.role == 2).sum() > 10 and (uab.role == 3).sum() > 10
+    moved_a = np.any(ua.pos != pos0, axis=0)
+    assert np.array_equal(uab.pos.view(np.int64), np.where(moved_a[None], ua.pos, ub.pos).view(np.int64))
+    for up, b in ((ua, A), (ub, B)):
+        sel = up.role == b.body_id
+        assert np.array_equal(uab.normal[:, sel], up.normal[:, sel])
+
+
+def test_boundary_cell_takes_the_nearest_body_id():
+    """Two circles a few cells apart: every body-boundary cell carries the id
+    of the body with the smallest |psi| at its centroid (lower id on ties),
+    by brute force over the cells."""
+    n, l0 = 48, 1.0 / 48
+    m = O.Mesh(2, (n, n), (0.0, 0.0), l0)
+    A = O.BodyState((0.3, 0.5), 0.17, 2)
+    B = O.BodyState((0.68, 0.47), 0.16, 3)       # surface gap ~ 2.5 l0
+    role = O.roles(m, [A, B])
+    checked = 0
+    for c in range(m.Nc):
+        if role[c] in (O.INNER, O.VOID):
+            continue
+        i, j = c % n, c // n
+        x, y = (i + 0.5) * l0, (j + 0.5) * l0
+        pa = abs(math.hypot(x - A.centre[0], y - A.centre[1]) - A.radius)
+        pb = abs(math.hypot(x - B.centre[0], y - B.centre[1]) - B.radius)
+        assert role[c] == (3 if pb < pa else 2), c
+        checked += 1
+    assert checked > 40 and (role == 3).sum() > 15
+
+
+def test_boundary_fitted_step_toward_the_nearest_body():
+    """The boundary-fitted move of an inner DP between two bodies goes
+    towards the body of smaller psi at the DP (lower id on ties):
+    x -= beta psi (x - c)/|x - c| of that body (DPs at grid centroids feel
+    no spring force)."""
+    n, l0 = 64, 1.0 / 64
+    m = O.Mesh(2, (n, n), (0.0, 0.0), l0)
+    A = O.BodyState((0.3 + 0.2 * l0, 0.5), 9 * l0, 2)
+    B = O.BodyState((0.7 - 0.1 * l0, 0.5 + 0.3 * l0), 8 * l0, 3)
+    bodies = [A, B]
+    pos = inputs.cell_centroids(m.n, m.origin, l0)
+    role = O.roles(m, bodies)
+    band = O.band_cells(m, bodies, role, 5.0 * l0)
+    alpha, re_l0 = 0.03, 8.0
+    fit = O.RelaxConsts.make(l0, fit_alpha=alpha, fit_re_over_l0=re_l0)
+    out, _ = O.relax_sweep(m, fit, bodies, role, band, pos)
+    out0, _ = O.relax_sweep(m, O.RelaxConsts.make(l0), bodies, role, band, pos)
+    ijk = m.ijk(band)
+    toward = {2: 0, 3: 0}
+    for k, c in enumerate(band):
+        if role[c] != O.INNER:
+            continue
+        nb = [(ijk[0][k] + dx) + n * (ijk[1][k] + dy) for dx in (-1, 0, 1) for dy in (-1, 0, 1)]
+        if any(role[j] != O.INNER for j in nb):
+            continue
+        psis = []
+        for b in bodies:
+            d = pos[:, c] - np.array(b.centre)
+            psis.append(np.hypot(d[0], d[1]) - b.radius)
+        b = bodies[int(psis[1] < psis[0])]
+        d = pos[:, c] - np.array(b.centre)
+        r = np.hypot(d[0], d[1])
+        psi = r - b.radius
+        if psi >= re_l0 * l0:
+            continue
+        beta = alpha / 2 * (1 + np.cos(np.pi * psi / (re_l0 * l0)))
+        np.testing.assert_allclose(out[:, c] - out0[:, c], -beta * psi * d / r, rtol=0,
+                                   atol=alpha * psi * 1e-10 + 1e-16)
+        toward[b.body_id] += 1
+    assert toward[2] > 20 and toward[3] > 20

@@ -186,3 +186,20 @@ def test_taylor_green_decay_converges_first_order():
     r128 = _tgv_decay_ratio(128, t_end)
     assert 1.0 < r128 < r64 < 1.5
     assert (r128 - 1.0) < 0.65 * (r64 - 1.0)
+
+
+def test_two_body_steps():
+    """Two cylinders (ids 2 and 3) on 64^2: each step converges, every body
+    DP carries its own body's velocity, and the velocity field stays
+    bounded by a few times the peak body speed."""
+    case = configs.c2_two_cylinders(n=64, steps=3)
+    sim = OracleSim(case)
+    for _ in range(3):
+        rec = sim.step()
+        assert rec["converged"] and rec["rel_res"] <= 1e-8
+    for b in sim.bodies:
+        sel = sim.role == b.body_id
+        assert sel.sum() > 5
+        for a in range(2):
+            assert np.all(sim.u[a, sel] == b.velocity[a])
+    assert np.isfinite(sim.u).all() and np.abs(sim.u).max() < 5 * 2 * math.pi * 0.15
