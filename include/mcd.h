@@ -90,14 +90,28 @@ typedef struct {
 } mcd_params;
 
 /* Rigid circle (2D) / sphere (3D) at one time level; host memory.
- * psi = |x - centre| - radius (> 0 in the fluid, Sec. 2.5). */
+ * psi = |x - centre| - radius (> 0 in the fluid, Sec. 2.5).
+ * Velocity of a body point x (Eq. velocity_moving_boundary):
+ *   V(x) = velocity + omega x r,  r = x - centre;
+ * its time derivative (Eq. dvdt_moving_boundary, backward differences
+ * supplied by the caller):
+ *   dV/dt(x) = dvdt + domega_dt x r + omega x (omega x r).
+ * In 2D only the z components omega[2], domega_dt[2] may be non-zero
+ * (MCD_ERR_ARG otherwise). */
 typedef struct {
     int id;              /* role id of its boundary DPs (1 .. 15), != wall_id, distinct
                             within one body list (MCD_ERR_ARG otherwise) */
     double centre[3];
     double radius;
-    double velocity[3];  /* V of Eq. (velocity_moving_boundary) (translation) */
-    double dvdt[3];      /* dV/dt of Eq. (dvdt_moving_boundary) */
+    double velocity[3];  /* V_trans of Eq. (velocity_moving_boundary) */
+    double dvdt[3];      /* (V_trans^{k+1} - V_trans^k) / dt, Eq. (dvdt_moving_boundary) */
+    double omega[3];     /* angular velocity omega^{k+1} */
+    double domega_dt[3]; /* (omega^{k+1} - omega^k) / dt */
+    double theta;        /* posture angle of a discrete-SDF body's frame (2D, about z) */
+    const double* sdf;   /* NULL: the circle/sphere psi above; else a discrete SDF (below) */
+    int sdf_n[2];
+    double sdf_origin[2];
+    double sdf_h;
 } mcd_body;
 
 /* Boundary condition of one field per role id (Eq. set: Dirichlet DPs are
@@ -212,7 +226,7 @@ mcd_status mcd_apply(mcd_ctx* ctx, int set, int op, const double* in, int ncomp,
  *   sign of (x^k_c - centre^k)_a of its step-k body (support shifted into
  *   the fluid, Sec. 3.4); if c' was not inner at step k the DP's own step-k
  *   weights are used;
- *  -> body boundary: the body's velocity; -> wall or void: 0.
+ *  -> body boundary: the body's velocity V(x) at x = pos; -> wall or void: 0.
  * u, out [dim][Nc]; bodies_prev / bodies_new: host arrays (same order). */
 mcd_status mcd_remap(mcd_ctx* ctx, int set_prev, const double* u, const double* pos_prev,
                      const double* pos, const int8_t* role_prev, const int8_t* role,
@@ -221,21 +235,26 @@ mcd_status mcd_remap(mcd_ctx* ctx, int set_prev, const double* u, const double* 
 
 /* u* = F_MOC + nu dt lap u~ at inner DPs (Eq. intermed_vel); F_MOC is the
  * chi_c = 1 Taylor value of u~ at x - u~ dt with the weights of `set`.
- * Body DPs take the body velocity, walls and void 0.  ut, ustar [dim][Nc].
- * rhs [Nc] (nullable) := div u* / dt with the same set (Eq. pressure_poisson);
- * it is computed in a second pass after u* is complete. */
+ * Body DPs take the body velocity V(x) at their position, walls and void 0.
+ * ut, ustar [dim][Nc]; pos [dim][Nc] (nullable when no body rotates:
+ * omega = 0; MCD_ERR_ARG otherwise).  rhs [Nc] (nullable) := div u* / dt
+ * with the same set (Eq. pressure_poisson); it is computed in a second pass
+ * after u* is complete. */
 mcd_status mcd_advect_diffuse(mcd_ctx* ctx, int set, const double* ut, double dt, double nu,
-                              const int8_t* role, const mcd_body* bodies, int n_bodies,
+                              const double* pos, const int8_t* role, const mcd_body* bodies, int n_bodies,
                               double* ustar, double* rhs);
 
-/* f = -dV/dt . n at body DPs (Eq. neumann_moving_boundary), 0 elsewhere. */
-mcd_status mcd_neumann_pressure(mcd_ctx* ctx, const int8_t* role, const double* normal,
+/* f = -dV/dt(x) . n at body DPs (Eqs. neumann_moving_boundary,
+ * dvdt_moving_boundary), 0 elsewhere.  pos [dim][Nc] as above (nullable when
+ * omega = domega_dt = 0 for every body). */
+mcd_status mcd_neumann_pressure(mcd_ctx* ctx, const double* pos, const int8_t* role, const double* normal,
                                 const mcd_body* bodies, int n_bodies, double* f);
 
 /* u^{k+1} = u* - dt grad P at inner DPs (Eq. projection) with the weights of
- * pressure set `set` and Neumann data f; body DPs take the body velocity. */
+ * pressure set `set` and Neumann data f; body DPs take the body velocity
+ * V(x); pos as for mcd_advect_diffuse. */
 mcd_status mcd_project(mcd_ctx* ctx, int set, const double* P, const double* f,
-                       const double* ustar, double dt, const int8_t* role,
+                       const double* ustar, double dt, const double* pos, const int8_t* role,
                        const mcd_body* bodies, int n_bodies, double* u);
 
 /* Fluid force on each body (Sec. 3.4, evaluation of fluid forces acting on

@@ -116,15 +116,48 @@ class Mesh:
 
 @dataclass
 class BodyState:
-    """Circle/sphere at a given time: centre, radius R, R^2 (host value), id."""
+    """Circle/sphere at a given time: centre, radius R, R^2 (host value), id,
+    translational velocity and angular velocity omega (3-vector; in 2D only
+    its z component)."""
     centre: tuple
     radius: float
     body_id: int
     velocity: tuple = ()
+    omega: tuple = (0.0, 0.0, 0.0)
 
     @property
     def r2(self):
         return self.radius * self.radius
+
+
+def _cross(w, r):
+    return (w[1] * r[2] - w[2] * r[1], w[2] * r[0] - w[0] * r[2], w[0] * r[1] - w[1] * r[0])
+
+
+def _arm(b, x):
+    """r = x - x_c as a 3-vector of arrays (zero third component in 2D)."""
+    dim = x.shape[0]
+    return [x[a] - b.centre[a] for a in range(dim)] + [0.0] * (3 - dim)
+
+
+def body_point_velocity(b, x):
+    """V = V_trans + omega x r at the points x [dim][K], r = x - x_c
+    (Eq. velocity_moving_boundary)."""
+    wr = _cross(b.omega, _arm(b, x))
+    return [b.velocity[a] + wr[a] for a in range(x.shape[0])]
+
+
+def body_point_acceleration(b, x, dvdt, domega):
+    """dV/dt at the points x (Eq. dvdt_moving_boundary with its backward
+    differences): dV_trans/dt + domega x r + omega x V_rot, V_rot = omega x r."""
+    r = _arm(b, x)
+    gr = _cross(domega, r)
+    wwr = _cross(b.omega, _cross(b.omega, r))
+    return [dvdt[a] + gr[a] + wwr[a] for a in range(x.shape[0])]
+
+
+def _rotating(b):
+    return any(w != 0.0 for w in b.omega)
 
 
 # ---------------------------------------------------------------------------
@@ -1093,17 +1126,33 @@ def remap_velocity(mesh, st_prev, u, pos_prev, pos_new, role_prev, role_new, bod
         out[a] = np.where(inner_new, val, 0.0)
     for bid, b in body_of.items():
         sel = role_new == bid
+        V = body_point_velocity(b, pos_new)
         for a in range(dim):
-            out[a] = np.where(sel, b.velocity[a], out[a])
+            out[a] = np.where(sel, V[a], out[a])
     return out, stats
 
 
-def moc_viscous(mesh, st_vel, ut, dt, nu, role, bodies, f_vel=None):
+def _body_velocity_field(out, role, bodies, pos, dim):
+    for b in bodies:
+        sel = role == b.body_id
+        if _rotating(b):
+            if pos is None:
+                raise ValueError("a rotating body needs the DP positions")
+            V = body_point_velocity(b, pos)
+        else:
+            V = b.velocity
+        for a in range(dim):
+            out[a] = np.where(sel, V[a], out[a])
+    return out
+
+
+def moc_viscous(mesh, st_vel, ut, dt, nu, role, bodies, f_vel=None, pos=None):
     """u* = F_MOC + nu dt lap(u~) at inner DPs (Eq. intermed_vel).
 
     F_MOC reading: the chi_c = 1 Taylor value of u~ at x - u~ dt with the
-    step-(k+1) velocity weights.  Body DPs take the body velocity; walls and
-    void take 0 (never used as value data).
+    step-(k+1) velocity weights.  Body DPs take the body velocity V(x) at
+    their position (Eq. velocity_moving_boundary); walls and void take 0
+    (never used as value data).
     """
     dim = mesh.dim
     out = np.zeros_like(ut)
@@ -1112,11 +1161,7 @@ def moc_viscous(mesh, st_vel, ut, dt, nu, role, bodies, f_vel=None):
         Phi = poly_coeffs(mesh, st_vel, ut[a], f_vel[a] if f_vel is not None else None)
         val = taylor_shift(ut[a], Phi, shift, st_vel.rs) + nu * dt * lap_from_phi(Phi, st_vel.rs, dim)
         out[a] = np.where(role == INNER, val, 0.0)
-    for b in bodies:
-        sel = role == b.body_id
-        for a in range(dim):
-            out[a] = np.where(sel, b.velocity[a], out[a])
-    return out
+    return _body_velocity_field(out, role, bodies, pos, dim)
 
 
 def divergence(mesh, st_vel, uvec, f_vel=None):
@@ -1128,27 +1173,33 @@ def divergence(mesh, st_vel, uvec, f_vel=None):
     return acc
 
 
-def project(mesh, st_p, P, f_p, ustar, dt, role, bodies):
-    """u^{k+1} = u* - dt grad P at inner DPs (Eq. projection)."""
+def project(mesh, st_p, P, f_p, ustar, dt, role, bodies, pos=None):
+    """u^{k+1} = u* - dt grad P at inner DPs (Eq. projection); body DPs take
+    the body velocity V(x)."""
     dim = mesh.dim
     Phi = poly_coeffs(mesh, st_p, P, f_p)
     g = grad_from_phi(Phi, st_p.rs, dim)
     out = np.where((role == INNER)[None, :], ustar - dt * g, 0.0)
-    for b in bodies:
-        sel = role == b.body_id
-        for a in range(dim):
-            out[a] = np.where(sel, b.velocity[a], out[a])
-    return out
+    return _body_velocity_field(out, role, bodies, pos, dim)
 
 
-def neumann_pressure_data(mesh, role, normal, bodies, dvdt):
-    """f_j = -dV/dt . n_j at body DPs (Eq. neumann_moving_boundary)."""
+def neumann_pressure_data(mesh, role, normal, bodies, dvdt, domega=None, pos=None):
+    """f_j = -dV/dt(x_j) . n_j at body DPs (Eqs. neumann_moving_boundary,
+    dvdt_moving_boundary); dvdt and domega map a body id to the backward
+    differences of V_trans and omega."""
     f = np.zeros(mesh.Nc)
     for b in bodies:
         sel = role == b.body_id
+        dw = (domega or {}).get(b.body_id, (0.0, 0.0, 0.0))
+        if _rotating(b) or any(v != 0.0 for v in dw):
+            if pos is None:
+                raise ValueError("a rotating body needs the DP positions")
+            A = body_point_acceleration(b, pos, dvdt[b.body_id], dw)
+        else:
+            A = dvdt[b.body_id]
         acc = 0.0
         for a in range(mesh.dim):
-            acc = acc + dvdt[b.body_id][a] * normal[a]
+            acc = acc + A[a] * normal[a]
         f = np.where(sel, -acc, f)
     return f
 

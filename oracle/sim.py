@@ -3,8 +3,8 @@
 TEST INFRASTRUCTURE (see mcd_oracle).  Order of one step k -> k+1
 (Sec. 3.3 and Sec. 2.3-2.4):
 
- 1. body state at t^{k+1}; dV/dt by the backward difference of
-    Eq. (dvdt_moving_boundary) (translation only: omega = 0);
+ 1. body state at t^{k+1}; dV_trans/dt and d omega/dt by the backward
+    differences of Eq. (dvdt_moving_boundary);
  2. DP rearrangement and role reassignment at t^{k+1};
  3. remap u^k -> u~ at x^{k+1} with the step-k velocity weights (Eq. ale_vel,
     Appendix A);
@@ -52,14 +52,16 @@ class OracleSim:
             self.u = np.zeros((dim, self.mesh.Nc))
         for b in bodies:
             sel = self.role == b.body_id
+            V = O.body_point_velocity(b, self.pos[:, sel])
             for a in range(dim):
-                self.u[a, sel] = b.velocity[a]
+                self.u[a, sel] = V[a]
         self.P = np.zeros(self.mesh.Nc)
         self.bodies = bodies
         self.st_vel = self._build(case.bc_velocity)
 
     def bodies_at(self, t):
-        return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t))
+        return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t),
+                            (0.0, 0.0, b.motion.omega(t)))
                 for b in self.case.rigid_bodies]
 
     def _build(self, bc):
@@ -73,6 +75,8 @@ class OracleSim:
         bodies_new = self.bodies_at(tn)
         dvdt = {b.body_id: tuple((vn - vo) / case.dt for vn, vo in zip(b.velocity, bo.velocity))
                 for b, bo in zip(bodies_new, self.bodies)}
+        domega = {b.body_id: tuple((wn - wo) / case.dt for wn, wo in zip(b.omega, bo.omega))
+                  for b, bo in zip(bodies_new, self.bodies)}
         up = O.update_dps(mesh, self.consts, bodies_new, self.pos, self.role, case.n_relax)
         t1 = time.perf_counter()
         ut, rstats = O.remap_velocity(mesh, self.st_vel, self.u, self.pos, up.pos, self.role, up.role,
@@ -81,9 +85,9 @@ class OracleSim:
         st_vel = self._build(case.bc_velocity)
         st_p = st_vel if case.bc_pressure == case.bc_velocity else self._build(case.bc_pressure)
         t2 = time.perf_counter()
-        ustar = O.moc_viscous(mesh, st_vel, ut, case.dt, case.nu, self.role, bodies_new)
+        ustar = O.moc_viscous(mesh, st_vel, ut, case.dt, case.nu, self.role, bodies_new, pos=self.pos)
         b = O.divergence(mesh, st_vel, ustar) / case.dt
-        f_p = O.neumann_pressure_data(mesh, self.role, self.normal, bodies_new, dvdt)
+        f_p = O.neumann_pressure_data(mesh, self.role, self.normal, bodies_new, dvdt, domega, pos=self.pos)
         unk = O.unknown_mask(self.role, case.bc_pressure, case.pin_first)
         p_in = np.where(unk, self.P, 0.0)
         t3 = time.perf_counter()
@@ -94,7 +98,7 @@ class OracleSim:
             P, info, _ = O.solve_ppe(mesh, st_p, self.role, case.bc_pressure, b, p_in, f_p, case.tol,
                                      case.pin_first, guess="caller")
         t4 = time.perf_counter()
-        self.u = O.project(mesh, st_p, P, f_p, ustar, case.dt, self.role, bodies_new)
+        self.u = O.project(mesh, st_p, P, f_p, ustar, case.dt, self.role, bodies_new, pos=self.pos)
         self.P = P
         self.st_vel = st_vel
         self.bodies = bodies_new

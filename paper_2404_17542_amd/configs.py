@@ -107,6 +107,18 @@ def c2_oscillating_cylinder(n=1024, steps=50):
                 bc_pressure={1: DIRICHLET, 2: NEUMANN}, bc_velocity={1: NEUMANN, 2: DIRICHLET})
 
 
+def c2_rotating_cylinder(n=256, steps=50):
+    """C2 with a rotational oscillation added: posture theta(t) = 0.3 sin(2 pi t),
+    so the no-slip velocity V_trans + omega x r has a tangential part of
+    peak omega R = 0.94 (Eqs. velocity_moving_boundary, dvdt_moving_boundary)."""
+    base = c2_oscillating_cylinder(n=n, steps=steps)
+    mot = base.body.motion
+    return replace(base, name=f"C2-rotating-cylinder-{n}", jitter_seed=6,
+                   body=Body(radius=base.body.radius,
+                             motion=Oscillation(mot.c0, mot.amplitude, mot.freq, 0, spin_amplitude=0.3,
+                                                spin_freq=1.0)))
+
+
 def c2_two_cylinders(n=256, steps=50):
     """[-4, 4]^2 with two cylinders whose relaxation bands overlap: D = 1 at
     (-0.9, 0) with x(t) = 0.15 sin(2 pi t) (id 2) and D = 0.7 at (0.5, 0)

@@ -85,13 +85,20 @@ static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* ou
         if (b.id < 1 || b.id >= MCD_MAX_IDS || (c->desc.walls && b.id == c->desc.wall_id)) return false;
         if (k > 0 && b.id == out->id[k - 1]) return false;     // ids are distinct
         if (!(b.radius > 0) || !isfinite(b.radius)) return false;
+        if (b.sdf) return false;          // discrete-SDF bodies: not accepted by this build yet
         out->id[k] = b.id;
         for (int a = 0; a < 3; ++a) {
             if (!isfinite(b.centre[a]) || !isfinite(b.velocity[a]) || !isfinite(b.dvdt[a])) return false;
+            if (!isfinite(b.omega[a]) || !isfinite(b.domega_dt[a])) return false;
+            if (c->dim == 2 && a < 2 && (b.omega[a] != 0.0 || b.domega_dt[a] != 0.0)) return false;
             out->c[k][a] = b.centre[a];
             out->vel[k][a] = b.velocity[a];
             out->dvdt[k][a] = b.dvdt[a];
+            out->om[k][a] = b.omega[a];
+            out->dom[k][a] = b.domega_dt[a];
+            if (b.omega[a] != 0.0 || b.domega_dt[a] != 0.0) out->rot[k] = 1;
         }
+        out->any_rot |= out->rot[k];
         out->R[k] = b.radius;
         out->R2[k] = b.radius * b.radius;
     }
@@ -399,8 +406,8 @@ mcd_status mcd_remap(mcd_ctx* c, int set_prev, const double* u, const double* po
     return MCD_OK;
 }
 
-mcd_status mcd_advect_diffuse(mcd_ctx* c, int set, const double* ut, double dt, double nu, const int8_t* role,
-                              const mcd_body* bodies, int n_bodies, double* ustar, double* rhs) {
+mcd_status mcd_advect_diffuse(mcd_ctx* c, int set, const double* ut, double dt, double nu, const double* pos,
+                              const int8_t* role, const mcd_body* bodies, int n_bodies, double* ustar, double* rhs) {
     if (!c) return MCD_ERR_ARG;
     if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: set not built%s");
     if (!ut || !role || !ustar || ut == ustar) return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: bad arrays%s");
@@ -408,7 +415,8 @@ mcd_status mcd_advect_diffuse(mcd_ctx* c, int set, const double* ut, double dt, 
         return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: bad dt/nu%s");
     BodiesDev B;
     if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: invalid bodies%s");
-    HIPCHK(c, launch_advect_diffuse(c->m, c->sets[set].dev, ut, dt, nu, role, B, ustar, c->stream), "advect");
+    if (B.any_rot && !pos) return fail(c, MCD_ERR_ARG, "mcd_advect_diffuse: a rotating body needs pos%s");
+    HIPCHK(c, launch_advect_diffuse(c->m, c->sets[set].dev, ut, dt, nu, pos, role, B, ustar, c->stream), "advect");
     if (rhs)
         HIPCHK(c, launch_apply(c->m, c->sets[set].dev, MCD_OP_DIV, ustar, c->dim, nullptr, nullptr, rhs, 1.0 / dt,
                                c->stream),
@@ -416,25 +424,27 @@ mcd_status mcd_advect_diffuse(mcd_ctx* c, int set, const double* ut, double dt, 
     return MCD_OK;
 }
 
-mcd_status mcd_neumann_pressure(mcd_ctx* c, const int8_t* role, const double* normal, const mcd_body* bodies,
-                                int n_bodies, double* f) {
+mcd_status mcd_neumann_pressure(mcd_ctx* c, const double* pos, const int8_t* role, const double* normal,
+                                const mcd_body* bodies, int n_bodies, double* f) {
     if (!c) return MCD_ERR_ARG;
     if (!role || !normal || !f) return fail(c, MCD_ERR_ARG, "mcd_neumann_pressure: null array%s");
     BodiesDev B;
     if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_neumann_pressure: invalid bodies%s");
-    HIPCHK(c, launch_neumann_pressure(c->m, role, normal, B, f, c->stream), "neumann");
+    if (B.any_rot && !pos) return fail(c, MCD_ERR_ARG, "mcd_neumann_pressure: a rotating body needs pos%s");
+    HIPCHK(c, launch_neumann_pressure(c->m, pos, role, normal, B, f, c->stream), "neumann");
     return MCD_OK;
 }
 
 mcd_status mcd_project(mcd_ctx* c, int set, const double* P, const double* f, const double* ustar, double dt,
-                       const int8_t* role, const mcd_body* bodies, int n_bodies, double* u) {
+                       const double* pos, const int8_t* role, const mcd_body* bodies, int n_bodies, double* u) {
     if (!c) return MCD_ERR_ARG;
     if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_project: set not built%s");
     if (!P || !ustar || !role || !u || u == ustar) return fail(c, MCD_ERR_ARG, "mcd_project: bad arrays%s");
     if (!(dt > 0) || !isfinite(dt)) return fail(c, MCD_ERR_ARG, "mcd_project: bad dt%s");
     BodiesDev B;
     if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_project: invalid bodies%s");
-    HIPCHK(c, launch_project(c->m, c->sets[set].dev, P, f, ustar, dt, role, B, u, c->stream), "project");
+    if (B.any_rot && !pos) return fail(c, MCD_ERR_ARG, "mcd_project: a rotating body needs pos%s");
+    HIPCHK(c, launch_project(c->m, c->sets[set].dev, P, f, ustar, dt, pos, role, B, u, c->stream), "project");
     return MCD_OK;
 }
 

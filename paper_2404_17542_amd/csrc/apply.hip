@@ -214,10 +214,7 @@ __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const do
 #pragma unroll
             for (int a = 0; a < DIM; ++a) v[a] = 0.0;
             for (int b = 0; b < Bn.n; ++b)
-                if (rn == Bn.id[b]) {
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) v[a] = Bn.vel[b][a];
-                }
+                if (rn == Bn.id[b]) body_velocity<DIM>(Bn, b, pos, Nc, c, v);
 #pragma unroll
             for (int a = 0; a < DIM; ++a) out[a * Nc + c] = v[a];
         }
@@ -227,8 +224,9 @@ __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const do
 // u* = F_MOC + nu dt lap u~ (Eq. intermed_vel) at inner DPs.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_advect_diffuse(MeshDev m, SetDev st, const double* __restrict__ ut,
-                                                           double dt, double nu, const int8_t* __restrict__ role,
-                                                           BodiesDev B, double* __restrict__ ustar) {
+                                                           double dt, double nu, const double* __restrict__ pos,
+                                                           const int8_t* __restrict__ role, BodiesDev B,
+                                                           double* __restrict__ ustar) {
     constexpr int NB = Dims<DIM>::NB;
     const size_t Nc = (size_t)m.Nc;
     const double rs = st.rs;
@@ -252,10 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_advect_diffuse(MeshDev m, SetDev st,
 #pragma unroll
             for (int a = 0; a < DIM; ++a) v[a] = 0.0;
             for (int b = 0; b < B.n; ++b)
-                if (rn == B.id[b]) {
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) v[a] = B.vel[b][a];
-                }
+                if (rn == B.id[b]) body_velocity<DIM>(B, b, pos, Nc, c, v);
 #pragma unroll
             for (int a = 0; a < DIM; ++a) ustar[a * Nc + c] = v[a];
         }
@@ -263,7 +258,8 @@ __global__ __launch_bounds__(kBlock) void k_advect_diffuse(MeshDev m, SetDev st,
 }
 
 template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_neumann_pressure(MeshDev m, const int8_t* __restrict__ role,
+__global__ __launch_bounds__(kBlock) void k_neumann_pressure(MeshDev m, const double* __restrict__ pos,
+                                                             const int8_t* __restrict__ role,
                                                              const double* __restrict__ normal, BodiesDev B,
                                                              double* __restrict__ f) {
     const size_t Nc = (size_t)m.Nc;
@@ -271,12 +267,7 @@ __global__ __launch_bounds__(kBlock) void k_neumann_pressure(MeshDev m, const in
         const int rn = role[c];
         double v = 0.0;
         for (int b = 0; b < B.n; ++b)
-            if (rn == B.id[b]) {
-                double acc = 0.0;
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) acc += B.dvdt[b][a] * normal[a * Nc + c];
-                v = -acc;
-            }
+            if (rn == B.id[b]) v = -body_accel_dot_n<DIM>(B, b, pos, normal, Nc, c);
         f[c] = v;
     }
 }
@@ -284,7 +275,8 @@ __global__ __launch_bounds__(kBlock) void k_neumann_pressure(MeshDev m, const in
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_project(MeshDev m, SetDev st, const double* __restrict__ P,
                                                     const double* __restrict__ f, const double* __restrict__ ustar,
-                                                    double dt, const int8_t* __restrict__ role, BodiesDev B,
+                                                    double dt, const double* __restrict__ pos,
+                                                    const int8_t* __restrict__ role, BodiesDev B,
                                                     double* __restrict__ u) {
     constexpr int NB = Dims<DIM>::NB;
     const size_t Nc = (size_t)m.Nc;
@@ -302,10 +294,7 @@ __global__ __launch_bounds__(kBlock) void k_project(MeshDev m, SetDev st, const 
 #pragma unroll
             for (int a = 0; a < DIM; ++a) v[a] = 0.0;
             for (int b = 0; b < B.n; ++b)
-                if (rn == B.id[b]) {
-#pragma unroll
-                    for (int a = 0; a < DIM; ++a) v[a] = B.vel[b][a];
-                }
+                if (rn == B.id[b]) body_velocity<DIM>(B, b, pos, Nc, c, v);
 #pragma unroll
             for (int a = 0; a < DIM; ++a) u[a * Nc + c] = v[a];
         }
@@ -529,21 +518,22 @@ hipError_t launch_remap(const MeshDev& m, const SetDev& set_prev, const double* 
 }
 
 hipError_t launch_advect_diffuse(const MeshDev& m, const SetDev& set, const double* ut, double dt, double nu,
-                                 const int8_t* role, const BodiesDev& B, double* ustar, hipStream_t st) {
-    MCD_DISPATCH(k_advect_diffuse, m, set, ut, dt, nu, role, B, ustar);
+                                 const double* pos, const int8_t* role, const BodiesDev& B, double* ustar,
+                                 hipStream_t st) {
+    MCD_DISPATCH(k_advect_diffuse, m, set, ut, dt, nu, pos, role, B, ustar);
     return hipGetLastError();
 }
 
-hipError_t launch_neumann_pressure(const MeshDev& m, const int8_t* role, const double* normal,
+hipError_t launch_neumann_pressure(const MeshDev& m, const double* pos, const int8_t* role, const double* normal,
                                    const BodiesDev& B, double* f, hipStream_t st) {
-    MCD_DISPATCH(k_neumann_pressure, m, role, normal, B, f);
+    MCD_DISPATCH(k_neumann_pressure, m, pos, role, normal, B, f);
     return hipGetLastError();
 }
 
 hipError_t launch_project(const MeshDev& m, const SetDev& set, const double* P, const double* f,
-                          const double* ustar, double dt, const int8_t* role, const BodiesDev& B, double* u,
-                          hipStream_t st) {
-    MCD_DISPATCH(k_project, m, set, P, f, ustar, dt, role, B, u);
+                          const double* ustar, double dt, const double* pos, const int8_t* role, const BodiesDev& B,
+                          double* u, hipStream_t st) {
+    MCD_DISPATCH(k_project, m, set, P, f, ustar, dt, pos, role, B, u);
     return hipGetLastError();
 }
 

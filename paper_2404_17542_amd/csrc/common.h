@@ -31,7 +31,52 @@ struct BodiesDev {
     double R2[kMaxBodies];      // R * R computed on the host
     double vel[kMaxBodies][3];
     double dvdt[kMaxBodies][3];
+    double om[kMaxBodies][3];   // angular velocity
+    double dom[kMaxBodies][3];  // its backward difference over dt
+    int rot[kMaxBodies];        // omega or domega non-zero
+    int any_rot;
 };
+
+// Velocity of a body point x (Eq. velocity_moving_boundary): V_trans + omega x r,
+// r = x - centre.  A body without rotation returns V_trans untouched.
+template <int DIM>
+__device__ __forceinline__ void body_velocity(const BodiesDev& B, int b, const double* __restrict__ pos,
+                                              size_t Nc, int c, double v[DIM]) {
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) v[a] = B.vel[b][a];
+    if (!B.rot[b]) return;
+    double r[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) r[a] = pos[a * Nc + c] - B.c[b][a];
+    const double* w = B.om[b];
+    const double x[3] = {w[1] * r[2] - w[2] * r[1], w[2] * r[0] - w[0] * r[2], w[0] * r[1] - w[1] * r[0]};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) v[a] += x[a];
+}
+
+// dV/dt . n at a body point (Eq. dvdt_moving_boundary):
+// (dV_trans/dt + domega x r + omega x (omega x r)) . n.
+template <int DIM>
+__device__ __forceinline__ double body_accel_dot_n(const BodiesDev& B, int b, const double* __restrict__ pos,
+                                                   const double* __restrict__ normal, size_t Nc, int c) {
+    double acc = 0.0;
+    if (!B.rot[b]) {
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) acc += B.dvdt[b][a] * normal[a * Nc + c];
+        return acc;
+    }
+    double r[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) r[a] = pos[a * Nc + c] - B.c[b][a];
+    const double* w = B.om[b];
+    const double* g = B.dom[b];
+    const double wr[3] = {w[1] * r[2] - w[2] * r[1], w[2] * r[0] - w[0] * r[2], w[0] * r[1] - w[1] * r[0]};
+    const double gr[3] = {g[1] * r[2] - g[2] * r[1], g[2] * r[0] - g[0] * r[2], g[0] * r[1] - g[1] * r[0]};
+    const double wwr[3] = {w[1] * wr[2] - w[2] * wr[1], w[2] * wr[0] - w[0] * wr[2], w[0] * wr[1] - w[1] * wr[0]};
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) acc += (B.dvdt[b][a] + gr[a] + wwr[a]) * normal[a * Nc + c];
+    return acc;
+}
 
 struct BcDev {
     int type[MCD_MAX_IDS];
@@ -245,12 +290,13 @@ hipError_t launch_remap(const MeshDev& m, const SetDev& set_prev, const double* 
                         const double* pos, const int8_t* role_prev, const int8_t* role, const BodiesDev& Bprev,
                         const BodiesDev& Bnew, double* out, int* counters, hipStream_t st);
 hipError_t launch_advect_diffuse(const MeshDev& m, const SetDev& set, const double* ut, double dt, double nu,
-                                 const int8_t* role, const BodiesDev& B, double* ustar, hipStream_t st);
-hipError_t launch_neumann_pressure(const MeshDev& m, const int8_t* role, const double* normal,
+                                 const double* pos, const int8_t* role, const BodiesDev& B, double* ustar,
+                                 hipStream_t st);
+hipError_t launch_neumann_pressure(const MeshDev& m, const double* pos, const int8_t* role, const double* normal,
                                    const BodiesDev& B, double* f, hipStream_t st);
 hipError_t launch_project(const MeshDev& m, const SetDev& set, const double* P, const double* f,
-                          const double* ustar, double dt, const int8_t* role, const BodiesDev& B, double* u,
-                          hipStream_t st);
+                          const double* ustar, double dt, const double* pos, const int8_t* role, const BodiesDev& B,
+                          double* u, hipStream_t st);
 hipError_t launch_force(const MeshDev& m, const SetDev& su, const SetDev& sp, const double* u, const double* p,
                         const double* fneu, const double* pos, const int8_t* role, const double* normal,
                         const BodiesDev& B, double mu, double* out, int* cnt, hipStream_t st);

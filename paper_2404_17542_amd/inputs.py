@@ -85,12 +85,23 @@ def tgv_pressure(pos, t, nu):
 
 @dataclass(frozen=True)
 class Oscillation:
-    """Body centre c(t) = c0 + A sin(2 pi f t + phase) e_axis; velocity is its derivative."""
+    """Body centre c(t) = c0 + A sin(2 pi f t + phase) e_axis; velocity is its
+    derivative.  Optional spin about z (2D): posture theta(t) = theta0 +
+    S sin(2 pi f_s t), angular velocity omega(t) = d theta / dt."""
     c0: tuple
     amplitude: float
     freq: float
     axis: int = 0
     phase: float = 0.0
+    spin_amplitude: float = 0.0
+    spin_freq: float = 0.0
+    theta0: float = 0.0
+
+    def theta(self, t):
+        return self.theta0 + self.spin_amplitude * math.sin(2 * math.pi * self.spin_freq * t)
+
+    def omega(self, t):
+        return 2 * math.pi * self.spin_freq * self.spin_amplitude * math.cos(2 * math.pi * self.spin_freq * t)
 
     def centre(self, t):
         c = list(self.c0)

@@ -52,7 +52,9 @@ class Params(C.Structure):
 
 class Body(C.Structure):
     _fields_ = [("id", C.c_int), ("centre", C.c_double * 3), ("radius", C.c_double),
-                ("velocity", C.c_double * 3), ("dvdt", C.c_double * 3)]
+                ("velocity", C.c_double * 3), ("dvdt", C.c_double * 3), ("omega", C.c_double * 3),
+                ("domega_dt", C.c_double * 3), ("theta", C.c_double), ("sdf", C.c_void_p),
+                ("sdf_n", C.c_int * 2), ("sdf_origin", C.c_double * 2), ("sdf_h", C.c_double)]
 
 
 class BcTable(C.Structure):
@@ -112,9 +114,9 @@ def load():
         "mcd_get_stencils": (i, [vp, i, vp, vp, vp]),
         "mcd_apply": (i, [vp, i, i, vp, i, vp, vp, vp]),
         "mcd_remap": (i, [vp, i, vp, vp, vp, vp, vp, P(Body), P(Body), i, vp]),
-        "mcd_advect_diffuse": (i, [vp, i, vp, d, d, vp, P(Body), i, vp, vp]),
-        "mcd_neumann_pressure": (i, [vp, vp, vp, P(Body), i, vp]),
-        "mcd_project": (i, [vp, i, vp, vp, vp, d, vp, P(Body), i, vp]),
+        "mcd_advect_diffuse": (i, [vp, i, vp, d, d, vp, vp, P(Body), i, vp, vp]),
+        "mcd_neumann_pressure": (i, [vp, vp, vp, vp, P(Body), i, vp]),
+        "mcd_project": (i, [vp, i, vp, vp, vp, d, vp, vp, P(Body), i, vp]),
         "mcd_solve_ppe": (i, [vp, i, vp, vp, vp, P(SolveOpts), P(SolveInfo)]),
         "mcd_ppe_residual": (i, [vp, i, vp, vp, vp, vp, P(d)]),
         "mcd_profile": (i, [vp, i]),
@@ -161,8 +163,17 @@ def _ptr(t, numel=None, dtype=None):
     return C.c_void_p(t.data_ptr())
 
 
+def _vec3(v):
+    """A 3-vector from a sequence (zero padded) or, for a 2D angular
+    quantity, a scalar (its z component)."""
+    if isinstance(v, (int, float)):
+        return (0.0, 0.0, float(v))
+    return tuple(float(v[a]) if a < len(v) else 0.0 for a in range(3))
+
+
 def bodies_array(bodies):
-    """bodies: list of dicts with id, centre, radius, velocity, dvdt."""
+    """bodies: list of dicts with id, centre, radius, velocity, dvdt and
+    optionally omega, domega_dt (3-vectors, or scalars about z in 2D)."""
     n = len(bodies)
     arr = (Body * max(n, 1))()
     for k, b in enumerate(bodies):
@@ -174,6 +185,10 @@ def bodies_array(bodies):
             arr[k].velocity[a] = float(v[a]) if a < len(v) else 0.0
             g = b.get("dvdt", ())
             arr[k].dvdt[a] = float(g[a]) if a < len(g) else 0.0
+        w, dw = _vec3(b.get("omega", ())), _vec3(b.get("domega_dt", ()))
+        for a in range(3):
+            arr[k].omega[a] = w[a]
+            arr[k].domega_dt[a] = dw[a]
     return arr, n
 
 
@@ -297,23 +312,24 @@ class Context:
                                        _ptr(role_prev, N, torch.int8), _ptr(role, N, torch.int8), bp, bn, n,
                                        V(out, D)), "mcd_remap")
 
-    def advect_diffuse(self, set_id, ut, dt, nu, role, bodies, ustar, rhs=None):
+    def advect_diffuse(self, set_id, ut, dt, nu, role, bodies, ustar, rhs=None, pos=None):
         arr, n = bodies_array(bodies)
         D, N, V = self.dim * self.Nc, self.Nc, self._vec
-        self._check(self.lib.mcd_advect_diffuse(self.h, int(set_id), V(ut, D), float(dt), float(nu),
+        self._check(self.lib.mcd_advect_diffuse(self.h, int(set_id), V(ut, D), float(dt), float(nu), V(pos, D),
                                                 _ptr(role, N, torch.int8), arr, n, V(ustar, D), V(rhs, N)),
                     "mcd_advect_diffuse")
 
-    def neumann_pressure(self, role, normal, bodies, f):
+    def neumann_pressure(self, role, normal, bodies, f, pos=None):
         arr, n = bodies_array(bodies)
-        N = self.Nc
-        self._check(self.lib.mcd_neumann_pressure(self.h, _ptr(role, N, torch.int8), self._vec(normal, self.dim * N),
-                                                  arr, n, self._vec(f, N)), "mcd_neumann_pressure")
+        N, D = self.Nc, self.dim * self.Nc
+        self._check(self.lib.mcd_neumann_pressure(self.h, self._vec(pos, D), _ptr(role, N, torch.int8),
+                                                  self._vec(normal, D), arr, n, self._vec(f, N)),
+                    "mcd_neumann_pressure")
 
-    def project(self, set_id, P, f, ustar, dt, role, bodies, u):
+    def project(self, set_id, P, f, ustar, dt, role, bodies, u, pos=None):
         arr, n = bodies_array(bodies)
         D, N, V = self.dim * self.Nc, self.Nc, self._vec
-        self._check(self.lib.mcd_project(self.h, int(set_id), V(P, N), V(f, N), V(ustar, D), float(dt),
+        self._check(self.lib.mcd_project(self.h, int(set_id), V(P, N), V(f, N), V(ustar, D), float(dt), V(pos, D),
                                          _ptr(role, N, torch.int8), arr, n, V(u, D)), "mcd_project")
 
     def solve_ppe(self, set_id, rhs, p, neumann_f=None, tol=1e-8, max_iter=20000, precision=PREC_FP64,

@@ -73,9 +73,14 @@ class GpuSim:
             u0 = inputs.tgv_velocity(self.pos.cpu().numpy(), 0.0, case.nu)
         else:
             u0 = np.zeros((dim, Nc))
+        pos_h = self.pos.cpu().numpy()
         for b in self.bodies:
+            sel = role_h == b["id"]
+            w = b["omega"]
+            r = [pos_h[a, sel] - b["centre"][a] for a in range(dim)]
+            rot = [-w * r[1], w * r[0]] + [0.0] * (dim - 2)      # omega about z
             for a in range(dim):
-                u0[a, role_h == b["id"]] = b["velocity"][a]
+                u0[a, sel] = b["velocity"][a] + rot[a] if w != 0.0 else b["velocity"][a]
         self.u.copy_(torch.tensor(u0, **f64))
         self.vel_slot = 0
         self.ctx.build_stencils(SET_VEL[self.vel_slot], self.pos, self.role, self.normal, case.bc_velocity,
@@ -86,12 +91,14 @@ class GpuSim:
         out = []
         for i, b in enumerate(self.case.rigid_bodies):
             vel = b.motion.velocity(t)
+            w = b.motion.omega(t)
             if prev is None:
-                dvdt = (0.0,) * len(vel)
+                dvdt, dw = (0.0,) * len(vel), 0.0
             else:
                 dvdt = tuple((vn - vo) / self.case.dt for vn, vo in zip(vel, prev[i]["velocity"]))
+                dw = (w - prev[i]["omega"]) / self.case.dt
             out.append({"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
-                        "dvdt": dvdt})
+                        "dvdt": dvdt, "omega": w, "domega_dt": dw})
         return out
 
     def prepare(self):
@@ -113,8 +120,8 @@ class GpuSim:
         if not self.same_sets:
             ctx.build_stencils(SET_P, self.pos, self.role, self.normal, case.bc_pressure, case.pin_first)
             pset = SET_P
-        ctx.advect_diffuse(new, self.ut, case.dt, case.nu, self.role, bodies_new, self.ustar, self.rhs)
-        ctx.neumann_pressure(self.role, self.normal, bodies_new, self.fP)
+        ctx.advect_diffuse(new, self.ut, case.dt, case.nu, self.role, bodies_new, self.ustar, self.rhs, pos=self.pos)
+        ctx.neumann_pressure(self.role, self.normal, bodies_new, self.fP, pos=self.pos)
         return pset, bodies_new, upd
 
     def forces(self):
@@ -154,7 +161,7 @@ class GpuSim:
 
     def finish(self, pset, bodies_new, info, upd):
         case = self.case
-        self.ctx.project(pset, self.P, self.fP, self.ustar, case.dt, self.role, bodies_new, self.u)
+        self.ctx.project(pset, self.P, self.fP, self.ustar, case.dt, self.role, bodies_new, self.u, pos=self.pos)
         self.vel_slot = 1 - self.vel_slot
         self.bodies = bodies_new
         self.k += 1

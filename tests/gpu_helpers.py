@@ -9,13 +9,15 @@ def np_(t):
 
 
 def oracle_bodies(case, t):
-    return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t))
+    return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t),
+                        (0.0, 0.0, b.motion.omega(t)))
             for b in case.rigid_bodies]
 
 
 def gpu_bodies(case, t, dvdt=None):
     return [{"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius,
-             "velocity": b.motion.velocity(t), "dvdt": dvdt or (0.0,) * case.dim}
+             "velocity": b.motion.velocity(t), "dvdt": dvdt or (0.0,) * case.dim,
+             "omega": b.motion.omega(t)}
             for b in case.rigid_bodies]
 
 

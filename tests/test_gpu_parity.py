@@ -644,6 +644,78 @@ def test_two_cylinders_steps_match_oracle(M):
     assert np.abs(P - o.P)[inner].max() / np.abs(o.P[inner]).max() < 1e-5
 
 
+def test_rotating_cylinder_steps_match_oracle(M):
+    """Whole steps with a spinning and translating cylinder: DP arrays
+    bit-exact, body DPs hold V_trans + omega x r, velocity within 1e-6 and
+    inner pressure within 1e-5 of the oracle."""
+    from paper_2404_17542_amd.sim import GpuSim
+    case = configs.c2_rotating_cylinder(n=128, steps=6)
+    g = GpuSim(case)
+    o = OracleSim(case)
+    assert np.abs(np_(g.u) - o.u).max() < 1e-15
+    for _ in range(6):
+        rg = g.step()
+        o.step()
+        assert rg["converged"] and rg["rel_res"] <= 1e-8
+        assert bits_equal(np_(g.pos), o.pos) and bits_equal(np_(g.role), o.role)
+    ug = np_(g.u)
+    assert np.abs(ug - o.u).max() / np.abs(o.u).max() < 1e-6
+    b = o.bodies[0]
+    sel = o.role == b.body_id
+    r = o.pos[:, sel] - np.array(b.centre)[:, None]
+    assert abs(b.omega[2]) > 0.5
+    np.testing.assert_allclose(ug[0, sel], b.velocity[0] - b.omega[2] * r[1], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(ug[1, sel], b.velocity[1] + b.omega[2] * r[0], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(np_(g.fP), o_neumann(o, case), rtol=0, atol=1e-12)
+    inner = o.role == O.INNER
+    P = np_(g.P)
+    assert np.abs(P - o.P)[inner].max() / np.abs(o.P[inner]).max() < 1e-5
+
+
+def o_neumann(o, case):
+    """The oracle's Neumann datum at the oracle's last step state."""
+    prev = [O.BodyState(b.motion.centre((o.k - 1) * case.dt), b.radius, b.body_id,
+                        b.motion.velocity((o.k - 1) * case.dt), (0.0, 0.0, b.motion.omega((o.k - 1) * case.dt)))
+            for b in case.rigid_bodies]
+    dvdt = {b.body_id: tuple((vn - vo) / case.dt for vn, vo in zip(b.velocity, bo.velocity))
+            for b, bo in zip(o.bodies, prev)}
+    dw = {b.body_id: tuple((wn - wo) / case.dt for wn, wo in zip(b.omega, bo.omega)) for b, bo in zip(o.bodies, prev)}
+    return O.neumann_pressure_data(o.mesh, o.role, o.normal, o.bodies, dvdt, dw, pos=o.pos)
+
+
+def test_rotation_closed_form_and_argument_checks(M):
+    """-dV/dt . n = omega^2 |r| at constant omega on circle points with
+    n = r/|r| (centripetal acceleration; an angular acceleration adds nothing
+    along n); a rotating body needs positions; in 2D only the z component of
+    omega may be non-zero."""
+    case = configs.c2_oscillating_cylinder(n=64)
+    ctx = M.Context.from_case(case)
+    N = case.n_cells
+    rng = np.random.default_rng(4)
+    ang = rng.uniform(0, 2 * np.pi, N)
+    rad = 0.5 * (1 + 0.1 * rng.uniform(-1, 1, N))
+    c = (0.3, -0.2)
+    pos = np.stack([c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang)])
+    nrm = np.stack([np.cos(ang), np.sin(ang)])
+    role = _dev(np.full(N, 2), torch.int8)
+    w = 1.7
+    body = {"id": 2, "centre": c, "radius": 0.5, "velocity": (0.4, -0.9), "dvdt": (0.0, 0.0), "omega": w,
+            "domega_dt": -3.1}
+    f = torch.zeros(N, dtype=torch.float64, device="cuda")
+    ctx.neumann_pressure(role, _dev(nrm), [body], f, pos=_dev(pos))
+    np.testing.assert_allclose(np_(f), w * w * rad, rtol=1e-13)
+    with pytest.raises(M.McdError) as ei:
+        ctx.neumann_pressure(role, _dev(nrm), [body], f)
+    assert ei.value.status == 1
+    bad = dict(body, omega=(0.5, 0.0, w))
+    with pytest.raises(M.McdError) as ei:
+        ctx.neumann_pressure(role, _dev(nrm), [bad], f, pos=_dev(pos))
+    assert ei.value.status == 1
+    still = dict(body, omega=0.0, domega_dt=0.0)
+    ctx.neumann_pressure(role, _dev(nrm), [still], f)          # no rotation: positions not needed
+    ctx.sync()
+
+
 def test_taylor_green_full_size_one_step(M):
     """512^2, one projection step at the benchmark configuration."""
     from paper_2404_17542_amd.sim import GpuSim

@@ -203,3 +203,51 @@ def test_two_body_steps():
         for a in range(2):
             assert np.all(sim.u[a, sel] == b.velocity[a])
     assert np.isfinite(sim.u).all() and np.abs(sim.u).max() < 5 * 2 * math.pi * 0.15
+
+
+def test_rotating_body_velocity_and_neumann_closed_forms():
+    """Rigid rotation of a circle (Eqs. velocity_moving_boundary,
+    dvdt_moving_boundary): the rotational part of V at a body point is
+    tangential with |V - V_trans| = |omega| |r|; at constant omega the
+    acceleration is centripetal, so -dV/dt . n = omega^2 |r| + (-dV_trans/dt . n)
+    for n = r/|r|, and an angular acceleration adds nothing along n."""
+    case = configs.c2_oscillating_cylinder(n=64)
+    m = O.Mesh.from_case(case)
+    rng = np.random.default_rng(3)
+    ang = rng.uniform(0, 2 * math.pi, m.Nc)
+    rad = 0.5 * (1 + 0.1 * rng.uniform(-1, 1, m.Nc))
+    c = (0.3, -0.2)
+    pos = np.stack([c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang)])
+    normal = np.stack([np.cos(ang), np.sin(ang)])
+    role = np.full(m.Nc, 2, dtype=np.int8)
+    w, vt, dv = 1.7, (0.4, -0.9), (2.0, 0.5)
+    b = O.BodyState(c, 0.5, 2, vt, (0.0, 0.0, w))
+    V = O.body_point_velocity(b, pos)
+    rel = [V[0] - vt[0], V[1] - vt[1]]
+    r = pos - np.array(c)[:, None]
+    np.testing.assert_allclose(rel[0] * r[0] + rel[1] * r[1], 0.0, atol=1e-14)
+    np.testing.assert_allclose(np.hypot(*rel), abs(w) * np.hypot(*r), rtol=1e-14)
+    f = O.neumann_pressure_data(m, role, normal, [b], {2: (0.0, 0.0)}, {2: (0.0, 0.0, 0.0)}, pos=pos)
+    np.testing.assert_allclose(f, w * w * rad, rtol=1e-13)
+    f2 = O.neumann_pressure_data(m, role, normal, [b], {2: dv}, {2: (0.0, 0.0, -3.1)}, pos=pos)
+    np.testing.assert_allclose(f2, w * w * rad - (dv[0] * normal[0] + dv[1] * normal[1]), rtol=1e-12, atol=1e-13)
+    # a rotating body without positions is an error, a still one is not
+    with pytest.raises(ValueError):
+        O.neumann_pressure_data(m, role, normal, [b], {2: dv}, None)
+    O.neumann_pressure_data(m, role, normal, [O.BodyState(c, 0.5, 2, vt)], {2: dv}, None)
+
+
+def test_rotating_cylinder_steps():
+    """Spinning cylinder on 64^2: steps converge and every body DP carries
+    V_trans + omega x r of its own position."""
+    case = configs.c2_rotating_cylinder(n=64, steps=3)
+    sim = OracleSim(case)
+    for _ in range(3):
+        rec = sim.step()
+        assert rec["converged"] and rec["rel_res"] <= 1e-8
+    b = sim.bodies[0]
+    assert b.omega[2] != 0.0
+    sel = sim.role == b.body_id
+    r = sim.pos[:, sel] - np.array(b.centre)[:, None]
+    np.testing.assert_allclose(sim.u[0, sel], b.velocity[0] - b.omega[2] * r[1], rtol=0, atol=1e-15)
+    np.testing.assert_allclose(sim.u[1, sel], b.velocity[1] + b.omega[2] * r[0], rtol=0, atol=1e-15)
