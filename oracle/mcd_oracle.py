@@ -32,6 +32,7 @@ from __future__ import annotations
 
 import math
 from dataclasses import dataclass, field
+from typing import Optional
 
 import numpy as np
 import scipy.sparse as sp
@@ -115,19 +116,98 @@ class Mesh:
 
 
 @dataclass
+class SdfGrid:
+    """Discrete SDF of a rigid 2D body in its own frame (Sec. 2.5): psi at
+    the nodes origin + (i, j) h, values[j][i].  re_over_h and kind are the
+    MLS support radius (in units of h) and weight of the interpolation;
+    far is the radius about the body centre beyond which psi is taken as
+    |x - c| - R (the distance to the bounding disc of radius R)."""
+    values: np.ndarray
+    origin: tuple
+    h: float
+    re_over_h: float
+    kind: str
+    far: float
+
+
+def sdf_far_radius(radius, l0, band_over_l0):
+    """Reading: the interpolated SDF is used within R + (band + 2) l0 of the
+    body centre; farther points lie outside the band of the body and only
+    the sign of psi matters there, which the bounding disc gives."""
+    return radius + (band_over_l0 + 2.0) * l0
+
+
+@dataclass
 class BodyState:
-    """Circle/sphere at a given time: centre, radius R, R^2 (host value), id,
+    """Rigid body at a given time: centre, radius R, R^2 (host value), id,
     translational velocity and angular velocity omega (3-vector; in 2D only
-    its z component)."""
+    its z component).  With sdf = None the body is the circle/sphere of
+    radius R; otherwise it is the discrete SDF `sdf` placed at the centre
+    with posture angle theta (2D), and R is the radius of a disc about the
+    centre that contains it."""
     centre: tuple
     radius: float
     body_id: int
     velocity: tuple = ()
     omega: tuple = (0.0, 0.0, 0.0)
+    theta: float = 0.0
+    sdf: Optional[SdfGrid] = None
 
     @property
     def r2(self):
         return self.radius * self.radius
+
+
+def sdf_eval(b, x):
+    """psi and grad psi of a discrete-SDF body at the points x [2][K]
+    (Sec. 2.5 with the chi_c = 1 MLS of Sec. 3.2).
+
+    The point is taken to the body frame, xi = R(-theta)(x - c); the support
+    is the 3x3 block of SDF nodes around the node nearest to xi (kept one
+    node inside the grid); the quadratic fit through the centre node's value
+    (chi_c = 1) is the weighted least-squares solution for the derivative
+    coefficients Phi over the eight other nodes, with offsets and the
+    evaluation point in units of h and weights W(|X| h; r_e = re_over_h h);
+    psi = psi_s + p(s).Phi at s = (xi - xi_s)/h and grad psi is that
+    polynomial's gradient rotated back by theta.  Beyond sdf.far from the
+    centre: psi = |x - c| - R with gradient (x - c)/|x - c|.
+    """
+    g = b.sdf
+    d0 = x[0] - b.centre[0]
+    d1 = x[1] - b.centre[1]
+    r2 = d0 * d0 + d1 * d1
+    far = r2 >= g.far * g.far
+    ct, st = math.cos(b.theta), math.sin(b.theta)
+    xi0 = ct * d0 + st * d1
+    xi1 = ct * d1 - st * d0
+    q0 = (xi0 - g.origin[0]) / g.h
+    q1 = (xi1 - g.origin[1]) / g.h
+    ny, nx = g.values.shape
+    i = np.clip(np.floor(q0 + 0.5), 1, nx - 2).astype(np.int64)
+    j = np.clip(np.floor(q1 + 0.5), 1, ny - 2).astype(np.int64)
+    s0 = q0 - i
+    s1 = q1 - j
+    ps = g.values[j, i]
+    M = np.zeros((5, 5))
+    rhs = np.zeros((5, len(ps)))
+    for dj in (-1, 0, 1):
+        for di in (-1, 0, 1):
+            if di == 0 and dj == 0:
+                continue
+            w = float(weight(np.hypot(di, dj), g.re_over_h, g.kind))
+            p = np.array(basis([float(di), float(dj)]))
+            M += w * np.outer(p, p)
+            rhs += (w * p)[:, None] * (g.values[j + dj, i + di] - ps)[None, :]
+    Phi = np.linalg.solve(M, rhs)
+    psi = ps + np.einsum("bk,bk->k", np.array(basis([s0, s1])), Phi)
+    gx = (Phi[0] + s0 * Phi[2] + s1 * Phi[3]) / g.h
+    gy = (Phi[1] + s0 * Phi[3] + s1 * Phi[4]) / g.h
+    grad = [ct * gx - st * gy, st * gx + ct * gy]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        r = np.sqrt(r2)
+        psi = np.where(far, r - b.radius, psi)
+        grad = [np.where(far, d0 / r, grad[0]), np.where(far, d1 / r, grad[1])]
+    return psi, grad
 
 
 def _cross(w, r):
@@ -188,6 +268,9 @@ def roles(mesh, bodies, idx=None):
         vx = [mesh.origin[a] + (ijk[a] + corner[a]).astype(np.float64) * l0 for a in range(dim)]
         fluid = np.ones(K, dtype=bool)
         for b in bodies:
+            if b.sdf is not None:
+                fluid &= sdf_eval(b, np.array(vx))[0] >= 0.0
+                continue
             d2 = np.zeros(K)
             for a in range(dim):
                 da = vx[a] - b.centre[a]
@@ -203,11 +286,14 @@ def roles(mesh, bodies, idx=None):
         best = np.full(K, np.inf)
         best_id = np.zeros(K, dtype=np.int8)
         for b in sorted(bodies, key=lambda q: q.body_id):
-            d2 = np.zeros(K)
-            for a in range(dim):
-                da = cen[a] - b.centre[a]
-                d2 = d2 + da * da
-            apsi = np.abs(np.sqrt(d2) - b.radius)
+            if b.sdf is not None:
+                apsi = np.abs(sdf_eval(b, np.array(cen))[0])
+            else:
+                d2 = np.zeros(K)
+                for a in range(dim):
+                    da = cen[a] - b.centre[a]
+                    d2 = d2 + da * da
+                apsi = np.abs(np.sqrt(d2) - b.radius)
             better = apsi < best
             best = np.where(better, apsi, best)
             best_id = np.where(better, b.body_id, best_id).astype(np.int8)
@@ -235,6 +321,9 @@ def band_cells(mesh, bodies, role, band_l0):
     cen = [mesh.origin[a] + (ijk[a].astype(np.float64) + 0.5) * mesh.l0 for a in range(mesh.dim)]
     best = np.full(mesh.Nc, np.inf)
     for b in bodies:
+        if b.sdf is not None:
+            best = np.minimum(best, np.abs(sdf_eval(b, np.array(cen))[0]))
+            continue
         d2 = np.zeros(mesh.Nc)
         for a in range(mesh.dim):
             da = cen[a] - b.centre[a]
@@ -344,6 +433,14 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
             sel = rb == b.body_id
             if not sel.any():
                 continue
+            if b.sdf is not None:
+                # x** = x* - psi grad psi / |grad psi|
+                psi, gv = sdf_eval(b, np.array(xs))
+                gn = np.sqrt(gv[0] * gv[0] + gv[1] * gv[1])
+                t = psi / gn
+                for a in range(dim):
+                    xs[a] = np.where(sel, xs[a] - t * gv[a], xs[a])
+                continue
             dd = [xs[a] - b.centre[a] for a in range(dim)]
             r2 = dd[0] * dd[0]
             for a in range(1, dim):
@@ -357,12 +454,17 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
             inner = rb == INNER
             best = None
             for b in sorted(bodies, key=lambda q: q.body_id):
-                dd = [xs[a] - b.centre[a] for a in range(dim)]
-                r2 = dd[0] * dd[0]
-                for a in range(1, dim):
-                    r2 = r2 + dd[a] * dd[a]
-                r = np.sqrt(r2)
-                psi = r - b.radius
+                if b.sdf is not None:
+                    # direction grad psi with its norm in place of (x - c, |x - c|)
+                    psi, dd = sdf_eval(b, np.array(xs))
+                    r = np.sqrt(dd[0] * dd[0] + dd[1] * dd[1])
+                else:
+                    dd = [xs[a] - b.centre[a] for a in range(dim)]
+                    r2 = dd[0] * dd[0]
+                    for a in range(1, dim):
+                        r2 = r2 + dd[a] * dd[a]
+                    r = np.sqrt(r2)
+                    psi = r - b.radius
                 if best is None:
                     best = (psi, r, dd)
                 else:
@@ -389,7 +491,7 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
 def normals(mesh, bodies, role, pos):
     """Unit normal of boundary DPs pointing into the fluid (grad psi).
 
-    Body DPs: (x - c)/|x - c|.  Wall DPs: the axis normals of the walls the
+    Body DPs: (x - c)/|x - c| (grad psi / |grad psi| for a discrete SDF).  Wall DPs: the axis normals of the walls the
     cell touches, summed and normalised (corners get the diagonal).
     """
     dim = mesh.dim
@@ -397,6 +499,12 @@ def normals(mesh, bodies, role, pos):
     for b in bodies:
         sel = np.nonzero(role == b.body_id)[0]
         if len(sel) == 0:
+            continue
+        if b.sdf is not None:
+            _, gv = sdf_eval(b, pos[:, sel])
+            gn = np.sqrt(gv[0] * gv[0] + gv[1] * gv[1])
+            for a in range(dim):
+                nrm[a, sel] = gv[a] / gn
             continue
         dd = [pos[a, sel] - b.centre[a] for a in range(dim)]
         r2 = dd[0] * dd[0]
@@ -1105,8 +1213,9 @@ def remap_velocity(mesh, st_prev, u, pos_prev, pos_new, role_prev, role_new, bod
         rp = role_prev[idxs]
         for b in bodies_prev:
             sel = rp == b.body_id
+            gv = sdf_eval(b, pos_prev[:, idxs])[1] if b.sdf is not None else None
             for a in range(dim):
-                gcomp = pos_prev[a, idxs] - b.centre[a]
+                gcomp = gv[a] if gv is not None else pos_prev[a, idxs] - b.centre[a]
                 off[a] = np.where(sel, np.sign(gcomp).astype(np.int64), off[a])
         cp = np.zeros(len(idxs), dtype=np.int64)
         okc = np.ones(len(idxs), dtype=bool)

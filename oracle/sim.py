@@ -25,6 +25,21 @@ from . import mcd_oracle as O
 from paper_2404_17542_amd import inputs
 
 
+def oracle_bodies(case, t):
+    """Body states at time t; a body with a discrete SDF carries its grid
+    (the MLS weight and r_e / l0 of the case, in units of the grid step)."""
+    out = []
+    for b in case.rigid_bodies:
+        grid = None
+        g = b.sdf_grid(case.l0, case.band_over_l0)
+        if g is not None:
+            grid = O.SdfGrid(g[0], g[1], g[2], case.re_over_l0, case.weight,
+                             O.sdf_far_radius(b.radius, case.l0, case.band_over_l0))
+        out.append(O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t),
+                               (0.0, 0.0, b.motion.omega(t)), b.motion.theta(t), grid))
+    return out
+
+
 class OracleSim:
     def __init__(self, case, mixed=False):
         self.case = case
@@ -60,9 +75,7 @@ class OracleSim:
         self.st_vel = self._build(case.bc_velocity)
 
     def bodies_at(self, t):
-        return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t),
-                            (0.0, 0.0, b.motion.omega(t)))
-                for b in self.case.rigid_bodies]
+        return oracle_bodies(self.case, t)
 
     def _build(self, bc):
         return O.mls_build(self.mesh, self.pos, self.role, self.normal, bc, self.re, self.rs,

@@ -14,7 +14,7 @@ import numpy as np
 from dataclasses import dataclass, field, replace
 from typing import Optional
 
-from .inputs import Oscillation
+from .inputs import FlappingMotion, Oscillation, ellipse_sdf_grid
 
 WALL_ID = 1
 BODY_ID = 2
@@ -25,10 +25,24 @@ NEUMANN = 1
 
 @dataclass(frozen=True)
 class Body:
-    """A rigid circle (2D) or sphere (3D) with prescribed translation."""
+    """A rigid circle (2D) or sphere (3D) with prescribed motion; with
+    `ellipse` = (a, b), a >= b, a 2D ellipse given to the method as a
+    discrete SDF (Sec. 2.5) on its own grid of spacing sdf_h_over_l0 * l0,
+    major axis along the body-frame x axis, and `radius` = a bounds it."""
     radius: float
-    motion: Oscillation
+    motion: object
     body_id: int = BODY_ID
+    ellipse: Optional[tuple] = None
+    sdf_h_over_l0: float = 0.5
+
+    def sdf_grid(self, l0, band_over_l0):
+        """(values [ny][nx], origin, h) of the body's discrete SDF, covering the
+        disc of radius R + (band + 2) l0 with its inner nodes, or None."""
+        if self.ellipse is None:
+            return None
+        h = self.sdf_h_over_l0 * l0
+        reach = self.radius + (band_over_l0 + 2.0) * l0 + h
+        return ellipse_sdf_grid(self.ellipse[0], self.ellipse[1], h, reach)
 
 
 @dataclass(frozen=True)
@@ -117,6 +131,23 @@ def c2_rotating_cylinder(n=256, steps=50):
                    body=Body(radius=base.body.radius,
                              motion=Oscillation(mot.c0, mot.amplitude, mot.freq, 0, spin_amplitude=0.3,
                                                 spin_freq=1.0)))
+
+
+def c6_flapping_ellipse(n=512, steps=50):
+    """Hovering elliptic wing (Sec. 4, flapping wing): chord 1, aspect ratio 4
+    (semi-axes 0.5, 0.125), box [-10, 6]^2 (16 chords, 6 from the origin to
+    the upper and right walls), stroke plane at beta = pi/3 with
+    a(t) = a0/2 (1 + cos(2t/a0)), a0 = 2.5, posture theta(t) =
+    pi/4 (1 - sin(2t/a0)); no slip on the wing and the walls.  Re = 100 on
+    the peak translational speed 1 and the chord.  dt = pi/600 at 512^2
+    (scaled with the mesh).  The wing is a discrete SDF."""
+    l0 = 16.0 / n
+    wing = Body(radius=0.5, motion=FlappingMotion((0.0, 0.0), 2.5, math.pi / 3, math.pi / 4),
+                ellipse=(0.5, 0.125))
+    return Case(name=f"C6-flapping-ellipse-{n}", dim=2, n=(n, n), origin=(-10.0, -10.0), l0=l0,
+                periodic=(False, False), walls=True, jitter_seed=7, weight="cos2", body=wing,
+                nu=0.01, dt=(math.pi / 600.0) * (512.0 / n), steps=steps,
+                bc_pressure={1: DIRICHLET, 2: NEUMANN}, bc_velocity={1: DIRICHLET, 2: DIRICHLET})
 
 
 def c2_two_cylinders(n=256, steps=50):

@@ -49,8 +49,68 @@ struct mcd_ctx {
     // host constants of the arrangement (computed once, used identically by every call)
     double kl0 = 0, spring[4] = {0, 0, 0, 0}, eps_l0 = 0, band_l0 = 0, re = 0, rs = 0;
     FitDev fit{0.0, 0.0, 0.0};
+    double sdfC[5][8] = {};     // discrete-SDF MLS derivative weights (0: not computable)
+    bool sdf_ok = false;
     std::string err;
 };
+
+// chi_c = 1 quadratic MLS over the 3x3 nodes of a regular grid (offsets in
+// units of h, weight W(|X|; r_e / l0) of the context): C = M^-1 [w_k p_k]
+// with M = sum_k w_k p_k p_k^T, p = (X, Y, X^2/2, XY, Y^2/2).  Returns false
+// when M is singular (r_e too small to reach the diagonal nodes).
+static bool sdf_table(int wkind, double re, double C[5][8]) {
+    double P[8][5], w[8];
+    int k = 0;
+    for (int dj = -1; dj <= 1; ++dj)
+        for (int di = -1; di <= 1; ++di) {
+            if (di == 0 && dj == 0) continue;
+            const double X = di, Y = dj, r = sqrt(X * X + Y * Y);
+            double wk = 0.0;
+            if (r <= re) {
+                if (wkind == MCD_WEIGHT_COS2) {
+                    const double t = cos(M_PI * r / (2.0 * re));
+                    wk = t * t;
+                } else {
+                    wk = exp(-4.0 * r * r / (re * re));
+                }
+            }
+            w[k] = wk;
+            P[k][0] = X;
+            P[k][1] = Y;
+            P[k][2] = 0.5 * X * X;
+            P[k][3] = X * Y;
+            P[k][4] = 0.5 * Y * Y;
+            ++k;
+        }
+    // augmented system [M | w p^T] solved by Gauss-Jordan with partial pivoting
+    double A[5][13];
+    for (int a = 0; a < 5; ++a) {
+        for (int b = 0; b < 5; ++b) {
+            double m = 0.0;
+            for (int q = 0; q < 8; ++q) m += w[q] * P[q][a] * P[q][b];
+            A[a][b] = m;
+        }
+        for (int q = 0; q < 8; ++q) A[a][5 + q] = w[q] * P[q][a];
+    }
+    for (int col = 0; col < 5; ++col) {
+        int piv = col;
+        for (int r = col + 1; r < 5; ++r)
+            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
+        if (!(fabs(A[piv][col]) > 1e-12)) return false;
+        if (piv != col)
+            for (int q = 0; q < 13; ++q) std::swap(A[piv][q], A[col][q]);
+        const double inv = 1.0 / A[col][col];
+        for (int q = 0; q < 13; ++q) A[col][q] *= inv;
+        for (int r = 0; r < 5; ++r) {
+            if (r == col || A[r][col] == 0.0) continue;
+            const double f = A[r][col];
+            for (int q = 0; q < 13; ++q) A[r][q] -= f * A[col][q];
+        }
+    }
+    for (int a = 0; a < 5; ++a)
+        for (int q = 0; q < 8; ++q) C[a][q] = A[a][5 + q];
+    return true;
+}
 
 static mcd_status fail(mcd_ctx* c, mcd_status s, const char* fmt, const char* detail = "") {
     if (c) {
@@ -85,7 +145,29 @@ static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* ou
         if (b.id < 1 || b.id >= MCD_MAX_IDS || (c->desc.walls && b.id == c->desc.wall_id)) return false;
         if (k > 0 && b.id == out->id[k - 1]) return false;     // ids are distinct
         if (!(b.radius > 0) || !isfinite(b.radius)) return false;
-        if (b.sdf) return false;          // discrete-SDF bodies: not accepted by this build yet
+        out->sdf[k] = nullptr;
+        if (b.sdf) {
+            // discrete SDF (2D): a valid grid whose inner nodes cover the disc of
+            // the far radius, and a computable interpolation table
+            if (c->dim != 2 || !c->sdf_ok) return false;
+            if (b.sdf_n[0] < 3 || b.sdf_n[1] < 3 || !(b.sdf_h > 0) || !isfinite(b.sdf_h) || !isfinite(b.theta))
+                return false;
+            const double rho = b.radius + (c->prm.band_over_l0 + 2.0) * c->m.l0;
+            for (int a = 0; a < 2; ++a) {
+                if (!isfinite(b.sdf_origin[a])) return false;
+                if (!(b.sdf_origin[a] + b.sdf_h <= -rho) || !(b.sdf_origin[a] + (b.sdf_n[a] - 2) * b.sdf_h >= rho))
+                    return false;
+            }
+            out->sdf[k] = b.sdf;
+            out->sn[k][0] = b.sdf_n[0];
+            out->sn[k][1] = b.sdf_n[1];
+            out->so[k][0] = b.sdf_origin[0];
+            out->so[k][1] = b.sdf_origin[1];
+            out->sh[k] = b.sdf_h;
+            out->cth[k] = cos(b.theta);
+            out->sth[k] = sin(b.theta);
+            out->far2[k] = rho * rho;
+        }
         out->id[k] = b.id;
         for (int a = 0; a < 3; ++a) {
             if (!isfinite(b.centre[a]) || !isfinite(b.velocity[a]) || !isfinite(b.dvdt[a])) return false;
@@ -99,6 +181,7 @@ static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* ou
             if (b.omega[a] != 0.0 || b.domega_dt[a] != 0.0) out->rot[k] = 1;
         }
         out->any_rot |= out->rot[k];
+        memcpy(out->sdfC, c->sdfC, sizeof(out->sdfC));
         out->R[k] = b.radius;
         out->R2[k] = b.radius * b.radius;
     }
@@ -173,6 +256,7 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
         c->fit = FitDev{prm->fit_alpha * 0.5, re_fit, M_PI / re_fit};
     }
     c->re = prm->re_over_l0 * l0;
+    c->sdf_ok = sdf_table(prm->weight_kind, prm->re_over_l0, c->sdfC);
     c->rs = prm->rs_over_l0 * l0;
 
     auto alloc = [&](void** p, size_t bytes) {

@@ -181,11 +181,15 @@ __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const do
                 int off[3] = {0, 0, 0};
                 for (int b = 0; b < Bp.n; ++b) {
                     if (rp != Bp.id[b]) continue;
+                    // sign of grad psi at x^k: (x - c) for a circle/sphere
+                    double gv[DIM];
 #pragma unroll
-                    for (int a = 0; a < DIM; ++a) {
-                        const double g = pos_prev[a * Nc + c] - Bp.c[b][a];
-                        off[a] = g > 0.0 ? 1 : (g < 0.0 ? -1 : 0);
+                    for (int a = 0; a < DIM; ++a) gv[a] = pos_prev[a * Nc + c] - Bp.c[b][a];
+                    if constexpr (DIM == 2) {
+                        if (Bp.sdf[b]) sdf_psi(Bp, b, pos_prev[c], pos_prev[Nc + c], gv);
                     }
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) off[a] = gv[a] > 0.0 ? 1 : (gv[a] < 0.0 ? -1 : 0);
                 }
                 bool ok = true;
                 int cp = 0, stride = 1;

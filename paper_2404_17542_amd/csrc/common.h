@@ -35,7 +35,63 @@ struct BodiesDev {
     double dom[kMaxBodies][3];  // its backward difference over dt
     int rot[kMaxBodies];        // omega or domega non-zero
     int any_rot;
+    // discrete SDF bodies (2D, Sec. 2.5); sdf[k] == nullptr: circle/sphere
+    const double* sdf[kMaxBodies];
+    int sn[kMaxBodies][2];
+    double so[kMaxBodies][2];
+    double sh[kMaxBodies];
+    double cth[kMaxBodies], sth[kMaxBodies];
+    double far2[kMaxBodies];
+    // chi_c = 1 MLS derivative weights of the 3x3 SDF support: Phi_q =
+    // sum_k C[q][k] (psi_k - psi_centre), neighbours k in row order without
+    // the centre; one table for the context (the grid is regular)
+    double sdfC[5][8];
 };
+
+// psi and grad psi of discrete-SDF body b at the 2D point (x0, x1): the point
+// in the body frame, xi = R(-theta)(x - c); the 3x3 nodes around the nearest
+// node (kept one node inside the grid); psi = psi_s + p(s).Phi with s the
+// offset from that node in units of h; the gradient rotated back.  Beyond
+// the far radius: the bounding disc, psi = |x - c| - R.
+__device__ __forceinline__ double sdf_psi(const BodiesDev& B, int b, double x0, double x1, double* g) {
+    const double d0 = x0 - B.c[b][0], d1 = x1 - B.c[b][1];
+    const double r2 = d0 * d0 + d1 * d1;
+    if (r2 >= B.far2[b]) {
+        const double r = sqrt(r2);
+        g[0] = d0 / r;
+        g[1] = d1 / r;
+        return r - B.R[b];
+    }
+    const double ct = B.cth[b], st = B.sth[b], h = B.sh[b];
+    const double xi0 = ct * d0 + st * d1, xi1 = ct * d1 - st * d0;
+    const double q0 = (xi0 - B.so[b][0]) / h, q1 = (xi1 - B.so[b][1]) / h;
+    const int n0 = B.sn[b][0], n1 = B.sn[b][1];
+    int i = (int)floor(q0 + 0.5), j = (int)floor(q1 + 0.5);
+    i = i < 1 ? 1 : (i > n0 - 2 ? n0 - 2 : i);
+    j = j < 1 ? 1 : (j > n1 - 2 ? n1 - 2 : j);
+    const double s0 = q0 - (double)i, s1 = q1 - (double)j;
+    const double* __restrict__ S = B.sdf[b];
+    const double ps = S[(size_t)j * n0 + i];
+    double Phi[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    int k = 0;
+#pragma unroll
+    for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+        for (int di = -1; di <= 1; ++di) {
+            if (di == 0 && dj == 0) continue;
+            const double dv = S[(size_t)(j + dj) * n0 + (i + di)] - ps;
+#pragma unroll
+            for (int q = 0; q < 5; ++q) Phi[q] += B.sdfC[q][k] * dv;
+            ++k;
+        }
+    const double psi = ps + (s0 * Phi[0] + s1 * Phi[1] + 0.5 * s0 * s0 * Phi[2] + s0 * s1 * Phi[3] +
+                             0.5 * s1 * s1 * Phi[4]);
+    const double gx = (Phi[0] + s0 * Phi[2] + s1 * Phi[3]) / h;
+    const double gy = (Phi[1] + s0 * Phi[3] + s1 * Phi[4]) / h;
+    g[0] = ct * gx - st * gy;
+    g[1] = st * gx + ct * gy;
+    return psi;
+}
 
 // Velocity of a body point x (Eq. velocity_moving_boundary): V_trans + omega x r,
 // r = x - centre.  A body without rotation returns V_trans untouched.

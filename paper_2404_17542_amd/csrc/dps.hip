@@ -42,6 +42,13 @@ __global__ __launch_bounds__(kBlock) void k_roles(MeshDev m, BodiesDev B, double
             for (int a = 0; a < DIM; ++a) vx[a] = m.origin[a] + (double)(ijk[a] + ((v >> a) & 1)) * m.l0;
             bool fluid = true;
             for (int b = 0; b < B.n; ++b) {
+                if constexpr (DIM == 2) {
+                    if (B.sdf[b]) {
+                        double g[2];
+                        fluid = fluid && (sdf_psi(B, b, vx[0], vx[1], g) >= 0.0);
+                        continue;
+                    }
+                }
                 double d2 = 0.0;
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) {
@@ -62,13 +69,24 @@ __global__ __launch_bounds__(kBlock) void k_roles(MeshDev m, BodiesDev B, double
 #pragma unroll
             for (int a = 0; a < DIM; ++a) cen[a] = m.origin[a] + ((double)ijk[a] + 0.5) * m.l0;
             for (int b = 0; b < B.n; ++b) {
-                double d2 = 0.0;
-#pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    double da = cen[a] - B.c[b][a];
-                    d2 = d2 + da * da;
+                double apsi;
+                bool done = false;
+                if constexpr (DIM == 2) {
+                    if (B.sdf[b]) {
+                        double g[2];
+                        apsi = fabs(sdf_psi(B, b, cen[0], cen[1], g));
+                        done = true;
+                    }
                 }
-                double apsi = fabs(sqrt(d2) - B.R[b]);
+                if (!done) {
+                    double d2 = 0.0;
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) {
+                        double da = cen[a] - B.c[b][a];
+                        d2 = d2 + da * da;
+                    }
+                    apsi = fabs(sqrt(d2) - B.R[b]);
+                }
                 if (apsi < best) {
                     best = apsi;
                     best_id = B.id[b];
@@ -190,6 +208,18 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
         const int rc = role[c];
         for (int b = 0; b < B.n; ++b) {
             if (rc != B.id[b]) continue;
+            if constexpr (DIM == 2) {
+                if (B.sdf[b]) {
+                    // x** = x* - psi grad psi / |grad psi|
+                    double g[2];
+                    const double psi = sdf_psi(B, b, xs[0], xs[1], g);
+                    const double gn = sqrt(g[0] * g[0] + g[1] * g[1]);
+                    const double t = psi / gn;
+                    xs[0] = xs[0] - t * g[0];
+                    xs[1] = xs[1] - t * g[1];
+                    continue;
+                }
+            }
             double dd[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) dd[a] = xs[a] - B.c[b][a];
@@ -207,14 +237,25 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
             // are in ascending id order; ties keep the lower id)
             double best = 0.0, rb = 1.0, db[DIM];
             for (int b = 0; b < B.n; ++b) {
-                double dd[DIM];
+                // direction and its norm: (x - c, |x - c|), or (grad psi, |grad psi|)
+                double dd[DIM], r, psi;
+                bool done = false;
+                if constexpr (DIM == 2) {
+                    if (B.sdf[b]) {
+                        psi = sdf_psi(B, b, xs[0], xs[1], dd);
+                        r = sqrt(dd[0] * dd[0] + dd[1] * dd[1]);
+                        done = true;
+                    }
+                }
+                if (!done) {
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) dd[a] = xs[a] - B.c[b][a];
-                double r2 = dd[0] * dd[0];
+                    for (int a = 0; a < DIM; ++a) dd[a] = xs[a] - B.c[b][a];
+                    double r2 = dd[0] * dd[0];
 #pragma unroll
-                for (int a = 1; a < DIM; ++a) r2 = r2 + dd[a] * dd[a];
-                const double r = sqrt(r2);
-                const double psi = r - B.R[b];
+                    for (int a = 1; a < DIM; ++a) r2 = r2 + dd[a] * dd[a];
+                    r = sqrt(r2);
+                    psi = r - B.R[b];
+                }
                 if (b == 0 || psi < best) {
                     best = psi;
                     rb = r;
@@ -290,6 +331,16 @@ __global__ __launch_bounds__(kBlock) void k_normals(MeshDev m, BodiesDev B, cons
         } else if (r >= 1) {
             for (int b = 0; b < B.n; ++b) {
                 if (r != B.id[b]) continue;
+                if constexpr (DIM == 2) {
+                    if (B.sdf[b]) {
+                        double g[2];
+                        sdf_psi(B, b, pos[c], pos[Nc + c], g);
+                        const double gn = sqrt(g[0] * g[0] + g[1] * g[1]);
+                        nv[0] = g[0] / gn;
+                        nv[1] = g[1] / gn;
+                        continue;
+                    }
+                }
                 double dd[DIM];
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) dd[a] = pos[a * Nc + c] - B.c[b][a];

@@ -114,6 +114,84 @@ class Oscillation:
         return tuple(v)
 
 
+@dataclass(frozen=True)
+class FlappingMotion:
+    """Hovering-wing kinematics: the rotation centre moves along a stroke
+    plane of elevation beta, c(t) = c0 + a(t) (cos beta, sin beta) with
+    a(t) = a0/2 (1 + cos(2t/a0)), and the posture angle is
+    theta(t) = theta_offset + theta0 (1 - sin(2t/a0 + phi)) (Sec. 4, flapping
+    wing); velocity and omega are the time derivatives."""
+    c0: tuple
+    a0: float
+    beta: float
+    theta0: float
+    phi: float = 0.0
+    theta_offset: float = 0.0
+
+    def centre(self, t):
+        a = 0.5 * self.a0 * (1.0 + math.cos(2.0 * t / self.a0))
+        return (self.c0[0] + a * math.cos(self.beta), self.c0[1] + a * math.sin(self.beta))
+
+    def velocity(self, t):
+        da = -math.sin(2.0 * t / self.a0)
+        return (da * math.cos(self.beta), da * math.sin(self.beta))
+
+    def theta(self, t):
+        return self.theta_offset + self.theta0 * (1.0 - math.sin(2.0 * t / self.a0 + self.phi))
+
+    def omega(self, t):
+        return -self.theta0 * (2.0 / self.a0) * math.cos(2.0 * t / self.a0 + self.phi)
+
+
+def ellipse_distance(semi_a, semi_b, x, y):
+    """Signed distance (> 0 outside) from points (x, y) to the ellipse
+    x^2/a^2 + y^2/b^2 = 1, by Eberly's bisection on the closest-point
+    parameter ("Distance from a Point to an Ellipse, an Ellipsoid, or a
+    Hyperellipsoid", Geometric Tools), vectorised; a >= b."""
+    assert semi_a >= semi_b > 0
+    y0 = np.abs(np.asarray(x, dtype=np.float64))
+    y1 = np.abs(np.asarray(y, dtype=np.float64))
+    e0, e1 = float(semi_a), float(semi_b)
+    z0, z1 = y0 / e0, y1 / e1
+    g = z0 * z0 + z1 * z1 - 1.0
+    r0 = (e0 / e1) ** 2
+    # generic case y0 > 0, y1 > 0: root s of (r0 z0/(s + r0))^2 + (z1/(s + 1))^2 = 1
+    n0 = r0 * z0
+    lo = z1 - 1.0
+    hi = np.where(g < 0, 0.0, np.sqrt(n0 * n0 + z1 * z1) - 1.0)
+    for _ in range(160):
+        sm = 0.5 * (lo + hi)
+        with np.errstate(divide="ignore", invalid="ignore"):
+            gm = (n0 / (sm + r0)) ** 2 + (z1 / (sm + 1.0)) ** 2 - 1.0
+        lo = np.where(gm > 0, sm, lo)
+        hi = np.where(gm > 0, hi, sm)
+    sbar = 0.5 * (lo + hi)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        x0 = r0 * y0 / (sbar + r0)
+        x1 = y1 / (sbar + 1.0)
+    d_gen = np.sqrt((x0 - y0) ** 2 + (x1 - y1) ** 2)
+    # y1 = 0: on the major axis
+    num, den = e0 * y0, e0 * e0 - e1 * e1
+    xde = np.minimum(num / den, 1.0)
+    d_axis = np.where(num < den, np.sqrt((e0 * xde - y0) ** 2 + (e1 * np.sqrt(1.0 - xde * xde)) ** 2),
+                      np.abs(y0 - e0))
+    # y0 = 0, y1 > 0: on the minor axis
+    d_minor = np.abs(y1 - e1)
+    d = np.where(y1 > 0, np.where(y0 > 0, d_gen, d_minor), d_axis)
+    d = np.where((y1 > 0) & (y0 > 0) & (g == 0), 0.0, d)
+    return np.where(g < 0, -d, d)
+
+
+def ellipse_sdf_grid(semi_a, semi_b, h, half_extent):
+    """Discrete SDF of an ellipse centred at the origin of its frame, major
+    axis along x: nodes -L + (i, j) h with L = half_extent rounded up to a
+    multiple of h plus one node; returns (values [ny][nx], origin, h)."""
+    m = int(math.ceil(half_extent / h)) + 1
+    ax = -m * h + h * np.arange(2 * m + 1)
+    X, Y = np.meshgrid(ax, ax)
+    return ellipse_distance(semi_a, semi_b, X, Y), (-m * h, -m * h), h
+
+
 def he_normal_params(shapes, seed, taps=9):
     """Seeded initial network parameters: for each (cin, cout) convolution of
     `taps` taps (9 in 2D, 27 in 3D), weights N(0, 2 / (taps cin)) of shape

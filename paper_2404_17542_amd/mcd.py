@@ -173,7 +173,9 @@ def _vec3(v):
 
 def bodies_array(bodies):
     """bodies: list of dicts with id, centre, radius, velocity, dvdt and
-    optionally omega, domega_dt (3-vectors, or scalars about z in 2D)."""
+    optionally omega, domega_dt (3-vectors, or scalars about z in 2D) and,
+    for a discrete-SDF body, theta, sdf (device tensor [ny][nx]), sdf_origin,
+    sdf_h."""
     n = len(bodies)
     arr = (Body * max(n, 1))()
     for k, b in enumerate(bodies):
@@ -189,6 +191,17 @@ def bodies_array(bodies):
         for a in range(3):
             arr[k].omega[a] = w[a]
             arr[k].domega_dt[a] = dw[a]
+        arr[k].theta = float(b.get("theta", 0.0))
+        g = b.get("sdf")
+        if g is not None:
+            # a discrete SDF: a contiguous FP64 device tensor [ny][nx]
+            if not (isinstance(g, torch.Tensor) and g.is_cuda and g.dtype == torch.float64 and g.dim() == 2
+                    and g.is_contiguous()):
+                raise ValueError("sdf must be a contiguous 2D float64 device tensor")
+            arr[k].sdf = g.data_ptr()
+            arr[k].sdf_n[0], arr[k].sdf_n[1] = int(g.shape[1]), int(g.shape[0])
+            arr[k].sdf_origin[0], arr[k].sdf_origin[1] = (float(v) for v in b["sdf_origin"])
+            arr[k].sdf_h = float(b["sdf_h"])
     return arr, n
 
 

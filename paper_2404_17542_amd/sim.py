@@ -56,6 +56,12 @@ class GpuSim:
         self.t = 0.0
         self.log = []
         self.same_sets = case.bc_pressure == case.bc_velocity
+        # discrete SDFs of the bodies that have one, resident on the device
+        self.sdf = {}
+        for b in case.rigid_bodies:
+            g = b.sdf_grid(case.l0, case.band_over_l0)
+            if g is not None:
+                self.sdf[b.body_id] = (torch.tensor(g[0], **f64).contiguous(), g[1], g[2])
         self.bodies = self.bodies_at(0.0, prev=None)
         # initial masking (its transitions from the placeholder roles are not meaningful)
         self.ctx.update_dps(self.bodies, 0, self.pos, self.role, self.pos_prev, self.role_prev, self.trans,
@@ -97,8 +103,12 @@ class GpuSim:
             else:
                 dvdt = tuple((vn - vo) / self.case.dt for vn, vo in zip(vel, prev[i]["velocity"]))
                 dw = (w - prev[i]["omega"]) / self.case.dt
-            out.append({"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
-                        "dvdt": dvdt, "omega": w, "domega_dt": dw})
+            d = {"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
+                 "dvdt": dvdt, "omega": w, "domega_dt": dw, "theta": b.motion.theta(t)}
+            if b.body_id in self.sdf:
+                g, o, h = self.sdf[b.body_id]
+                d.update(sdf=g, sdf_origin=o, sdf_h=h)
+            out.append(d)
         return out
 
     def prepare(self):

@@ -9,16 +9,29 @@ def np_(t):
 
 
 def oracle_bodies(case, t):
-    return [O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t),
-                        (0.0, 0.0, b.motion.omega(t)))
-            for b in case.rigid_bodies]
+    from oracle.sim import oracle_bodies as ob
+    return ob(case, t)
+
+
+_SDF = {}
 
 
 def gpu_bodies(case, t, dvdt=None):
-    return [{"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius,
+    """Body dicts for the C ABI; discrete SDFs are uploaded once per case."""
+    import torch
+    out = []
+    for b in case.rigid_bodies:
+        d = {"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius,
              "velocity": b.motion.velocity(t), "dvdt": dvdt or (0.0,) * case.dim,
-             "omega": b.motion.omega(t)}
-            for b in case.rigid_bodies]
+             "omega": b.motion.omega(t), "theta": b.motion.theta(t)}
+        g = b.sdf_grid(case.l0, case.band_over_l0)
+        if g is not None:
+            key = (case.name, b.body_id)
+            if key not in _SDF:
+                _SDF[key] = torch.tensor(g[0], dtype=torch.float64, device="cuda").contiguous()
+            d.update(sdf=_SDF[key], sdf_origin=g[1], sdf_h=g[2])
+        out.append(d)
+    return out
 
 
 def bits_equal(a, b):

@@ -1,0 +1,159 @@
+"""Discrete-SDF bodies (Sec. 2.5) through the C ABI: a flapping ellipse whose
+SDF lives on its own grid and is read at the body's posture.  The GPU reads
+the SDF through a precomputed table of the 3x3 MLS weights and the oracle
+through a per-point weighted least-squares solve, so psi agrees to rounding,
+not bit for bit: roles and transition codes are compared exactly, positions,
+normals and fields to tolerances."""
+import math
+from dataclasses import replace
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle import mcd_oracle as O
+from oracle.sim import OracleSim
+from paper_2404_17542_amd import configs, inputs
+from gpu_helpers import gpu_bodies, np_, oracle_bodies
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_17542_amd import mcd
+    mcd.load()
+    return mcd
+
+
+def _dev(a, dtype=torch.float64):
+    return torch.tensor(np.ascontiguousarray(a), dtype=dtype, device="cuda")
+
+
+def _close_dps(g, o, l0, what):
+    pos, role, trans, nrm = g
+    assert np.array_equal(role, o.role), what
+    assert np.array_equal(trans, o.trans), what
+    dp = np.abs(pos - o.pos).max() / l0
+    dn = np.abs(nrm - o.normal).max()
+    assert dp < 1e-11 and dn < 1e-11, (what, dp, dn)
+    return dp, dn
+
+
+@pytest.mark.parametrize("fit_alpha", [0.0, 0.03])
+def test_flapping_ellipse_arrangement_matches_oracle(M, fit_alpha):
+    """256^2 flapping ellipse: initial arrangement (200 sweeps) and 40 steps
+    of the moving, turning wing: roles, transition codes, sweep counts and
+    band sizes equal; positions and normals within 1e-11 l0 / 1e-11 (measured:
+    about 1e-14)."""
+    case = replace(configs.c6_flapping_ellipse(n=256), fit_alpha=fit_alpha)
+    m = O.Mesh.from_case(case)
+    consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0, case.fit_alpha,
+                                case.fit_re_over_l0)
+    pos0 = inputs.jittered_positions(case.n, case.origin, case.l0, case.jitter_seed)
+    ob = oracle_bodies(case, 0.0)
+    up = O.update_dps(m, consts, ob, pos0, O.roles(m, ob), 200)
+    ctx = M.Context.from_case(case)
+    pos = _dev(pos0)
+    role = torch.full((m.Nc,), -1, dtype=torch.int8, device="cuda")
+    role_prev = torch.zeros_like(role)
+    trans = torch.zeros((m.Nc,), dtype=torch.uint8, device="cuda")
+    pos_prev = torch.zeros_like(pos)
+    normal = torch.zeros_like(pos)
+    gb = gpu_bodies(case, 0.0)
+    ctx.update_dps(gb, 0, pos, role, pos_prev, role_prev, trans, normal, info=False)
+    try:
+        ctx.sync()
+    except M.McdError:
+        pass
+    info = ctx.update_dps(gb, 200, pos, role, pos_prev, role_prev, trans, normal)
+    assert info["sweeps"] == up.sweeps
+    assert np.array_equal(np_(role), up.role)
+    worst = [0.0, 0.0]
+    total = np.zeros(9, dtype=np.int64)
+    ora_pos, ora_role = up.pos, up.role
+    for k in range(1, 41):
+        t = k * case.dt
+        up = O.update_dps(m, consts, oracle_bodies(case, t), ora_pos, ora_role, case.n_relax)
+        info = ctx.update_dps(gpu_bodies(case, t), case.n_relax, pos, role, pos_prev, role_prev, trans, normal)
+        ora_pos, ora_role = up.pos, up.role
+        assert info["sweeps"] == up.sweeps and info["band_cells"] == len(up.band), k
+        d = _close_dps((np_(pos), np_(role), np_(trans), np_(normal)), up, case.l0, k)
+        worst = [max(worst[0], d[0]), max(worst[1], d[1])]
+        total += np.bincount(up.trans, minlength=9)
+    print("max |dx|/l0, |dn|:", worst, "transitions:", total.tolist())
+    assert total[2] + total[6] + total[5] + total[7] > 0      # the wing changed roles on its way
+
+
+def test_flapping_ellipse_steps_match_oracle(M):
+    """Whole steps of the 256^2 flapping ellipse (rotating discrete-SDF wing,
+    no-slip walls): roles equal, positions within 1e-11 l0, velocity within
+    1e-6 and inner pressure within 1e-5 of the oracle; the force on the wing
+    equals the oracle's evaluated on the GPU's arrays."""
+    from paper_2404_17542_amd.sim import GpuSim
+    case = configs.c6_flapping_ellipse(n=256, steps=4)
+    g = GpuSim(case)
+    o = OracleSim(case)
+    assert np.array_equal(np_(g.role), o.role)
+    for _ in range(4):
+        rg = g.step()
+        ro = o.step()
+        assert rg["converged"] and rg["rel_res"] <= 1e-8
+        assert rg["trans"] == ro["trans"] and rg["sweeps"] == ro["sweeps"]
+        assert np.array_equal(np_(g.role), o.role)
+        assert np.abs(np_(g.pos) - o.pos).max() < 1e-11 * case.l0
+    ug = np_(g.u)
+    assert np.abs(ug - o.u).max() / np.abs(o.u).max() < 1e-6
+    inner = o.role == O.INNER
+    P = np_(g.P)
+    assert np.abs(P - o.P)[inner].max() / np.abs(o.P[inner]).max() < 1e-5
+    F, cnt = g.forces()
+    m = O.Mesh.from_case(case)
+    b = o.bodies[0]
+    re, rs = case.re_over_l0 * case.l0, case.rs_over_l0 * case.l0
+    Fo, co = O.fluid_force(m, np_(g.pos), np_(g.role), np_(g.normal), [b], case.bc_velocity, case.bc_pressure, ug,
+                           P, np_(g.fP), re, rs, case.nu, case.weight)
+    assert cnt[0] == co[0] and cnt[0][0] > 20
+    scale = np.abs(P[np_(g.role) == 2]).max() * 2 * math.pi * b.radius + 1e-30
+    assert np.abs(np.array(F[0]) - Fo[0]).max() <= 1e-10 * scale, (F[0], Fo[0])
+
+
+def test_sdf_body_argument_checks(M):
+    """A grid whose inner nodes do not span the far radius, a non-contiguous
+    or host grid, and a discrete SDF on a 3D mesh are rejected."""
+    case = configs.c6_flapping_ellipse(n=128)
+    ctx = M.Context.from_case(case)
+    N = case.n_cells
+    pos = _dev(inputs.jittered_positions(case.n, case.origin, case.l0, 1))
+    role = torch.full((N,), -1, dtype=torch.int8, device="cuda")
+    z = [torch.zeros_like(pos), torch.zeros_like(role), torch.zeros((N,), dtype=torch.uint8, device="cuda"),
+         torch.zeros_like(pos)]
+    good = gpu_bodies(case, 0.0)
+    small = dict(good[0], sdf=good[0]["sdf"][2:-2, 2:-2].contiguous(),
+                 sdf_origin=(good[0]["sdf_origin"][0] + 2 * good[0]["sdf_h"],
+                             good[0]["sdf_origin"][1] + 2 * good[0]["sdf_h"]))
+    with pytest.raises(M.McdError) as ei:
+        ctx.update_dps([small], 0, pos, role, z[0], z[1], z[2], z[3], info=False)
+    assert ei.value.status == 1
+    with pytest.raises(ValueError):
+        ctx.update_dps([dict(good[0], sdf=good[0]["sdf"].cpu())], 0, pos, role, z[0], z[1], z[2], z[3])
+    ctx.update_dps(good, 0, pos, role, z[0], z[1], z[2], z[3], info=False)      # the full grid is accepted
+    try:
+        ctx.sync()
+    except M.McdError:
+        pass
+    case3 = configs.c4_moving_sphere(n=16)
+    ctx3 = M.Context.from_case(case3)
+    N3 = case3.n_cells
+    pos3 = _dev(inputs.jittered_positions(case3.n, case3.origin, case3.l0, 1))
+    role3 = torch.full((N3,), -1, dtype=torch.int8, device="cuda")
+    z3 = [torch.zeros_like(pos3), torch.zeros_like(role3), torch.zeros((N3,), dtype=torch.uint8, device="cuda"),
+          torch.zeros_like(pos3)]
+    b3 = gpu_bodies(case3, 0.0)[0]
+    b3.update(sdf=good[0]["sdf"], sdf_origin=(-4.0, -4.0), sdf_h=0.5)
+    with pytest.raises(M.McdError) as ei:
+        ctx3.update_dps([b3], 0, pos3, role3, z3[0], z3[1], z3[2], z3[3], info=False)
+    assert ei.value.status == 1

@@ -1,0 +1,149 @@
+"""Pins of the discrete-SDF body (Sec. 2.5: an SDF sampled on its own grid,
+read through the chi_c = 1 MLS of Sec. 3.2 at the body's posture) and of
+the ellipse SDF generator used as its input."""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import mcd_oracle as O
+from paper_2404_17542_amd import inputs
+
+
+def _body(values, origin, h, centre=(0.0, 0.0), theta=0.0, radius=1.0, far=1e9, kind="cos2", re=2.5):
+    g = O.SdfGrid(np.asarray(values, dtype=np.float64), origin, h, re, kind, far)
+    return O.BodyState(centre, radius, 2, (0.0, 0.0), (0.0, 0.0, 0.0), theta, g)
+
+
+def _grid(n, h, f):
+    o = (-(n // 2) * h, -(n // 2) * h)
+    ax0 = o[0] + h * np.arange(n)
+    X, Y = np.meshgrid(ax0, ax0)
+    return f(X, Y), o
+
+
+@pytest.mark.parametrize("kind", ["cos2", "gauss"])
+def test_quadratics_are_reproduced_at_any_posture(kind):
+    """A quadratic sampled on the grid is reproduced exactly (psi and its
+    gradient) at any point and posture: the chi_c = 1 quadratic fit is exact
+    for quadratics."""
+    rng = np.random.default_rng(1)
+    cq = rng.standard_normal(6)
+
+    def q(X, Y):
+        return cq[0] + cq[1] * X + cq[2] * Y + cq[3] * X * X + cq[4] * X * Y + cq[5] * Y * Y
+
+    h = 0.05
+    vals, o = _grid(41, h, q)
+    c, th = (0.3, -0.7), 0.83
+    b = _body(vals, o, h, c, th, kind=kind)
+    K = 400
+    xi = rng.uniform(-0.8, 0.8, (2, K))
+    x = np.stack([c[0] + math.cos(th) * xi[0] - math.sin(th) * xi[1],
+                  c[1] + math.sin(th) * xi[0] + math.cos(th) * xi[1]])
+    psi, g = O.sdf_eval(b, x)
+    np.testing.assert_allclose(psi, q(xi[0], xi[1]), rtol=0, atol=1e-12)
+    gx = cq[1] + 2 * cq[3] * xi[0] + cq[4] * xi[1]
+    gy = cq[2] + cq[4] * xi[0] + 2 * cq[5] * xi[1]
+    np.testing.assert_allclose(g[0], math.cos(th) * gx - math.sin(th) * gy, rtol=0, atol=1e-10)
+    np.testing.assert_allclose(g[1], math.sin(th) * gx + math.cos(th) * gy, rtol=0, atol=1e-10)
+
+
+def test_discrete_circle_converges_at_third_order():
+    """A circle given as a sampled SDF: psi at random points approaches
+    |x - c| - R with an error that falls about 8x per halving of h (the
+    quadratic fit's third-order truncation), and grad psi is close to the
+    radial unit vector."""
+    R = 0.5
+    rng = np.random.default_rng(2)
+    ang = rng.uniform(0, 2 * math.pi, 500)
+    rad = rng.uniform(0.3, 0.8, 500)
+    c = (0.1, 0.2)
+    x = np.stack([c[0] + rad * np.cos(ang), c[1] + rad * np.sin(ang)])
+    errs = []
+    for h in (0.04, 0.02, 0.01):
+        n = int(round(2.0 / h)) + 1
+        vals, o = _grid(n, h, lambda X, Y: np.hypot(X, Y) - R)
+        b = _body(vals, o, h, c, theta=0.4)
+        psi, g = O.sdf_eval(b, x)
+        errs.append(np.abs(psi - (rad - R)).max())
+        assert np.abs(g[0] - np.cos(ang)).max() < 50 * h * h and np.abs(g[1] - np.sin(ang)).max() < 50 * h * h
+    assert errs[0] / errs[1] > 5.0 and errs[1] / errs[2] > 5.0, errs
+
+
+def test_far_points_take_the_bounding_disc():
+    vals, o = _grid(21, 0.1, lambda X, Y: np.hypot(X, Y) - 0.5)
+    b = _body(vals, o, 0.1, (1.0, 2.0), theta=1.0, radius=0.6, far=0.8)
+    x = np.array([[1.0 + 0.9, 1.0, 1.0 - 0.5], [2.0, 2.0 + 2.5, 2.0 - 0.7]])
+    psi, g = O.sdf_eval(b, x)
+    r = np.hypot(x[0] - 1.0, x[1] - 2.0)
+    np.testing.assert_array_equal(psi, r - 0.6)
+    np.testing.assert_allclose(g[0], (x[0] - 1.0) / r)
+
+
+def test_posture_rotates_the_shape():
+    """The ellipse's SDF grid at posture theta gives, at x, the ellipse
+    distance at R(-theta)(x - c) (within the interpolation error where the
+    distance is smooth: in the fluid and within 2h inside the surface; the
+    kink of the interior distance on the focal segment is not resolved); a quarter
+    turn swaps the axes."""
+    a, bb, h = 0.5, 0.125, 0.0125
+    vals, o, h = inputs.ellipse_sdf_grid(a, bb, h, 0.9)
+    c, th = (0.2, -0.1), 0.6
+    body = _body(vals, o, h, c, th, radius=a)
+    rng = np.random.default_rng(3)
+    xi = rng.uniform(-0.7, 0.7, (2, 2000))
+    x = np.stack([c[0] + math.cos(th) * xi[0] - math.sin(th) * xi[1],
+                  c[1] + math.sin(th) * xi[0] + math.cos(th) * xi[1]])
+    psi, _ = O.sdf_eval(body, x)
+    exact = inputs.ellipse_distance(a, bb, xi[0], xi[1])
+    fluid = exact >= 0.0
+    assert fluid.sum() > 1500
+    # largest near the tips, whose radius of curvature b^2/a is only 2.5 h
+    assert np.abs(psi - exact)[fluid].max() < 0.01 * h
+    near = (exact < 0.0) & (exact > -2 * h)
+    assert np.abs(psi - exact)[near].max() < 0.05 * h
+    q = _body(vals, o, h, (0.0, 0.0), 0.5 * math.pi, radius=a)
+    pts = np.array([[0.0, 0.0, 0.3], [0.6, -0.6, 0.0]])
+    psi_q, _ = O.sdf_eval(q, pts)
+    np.testing.assert_allclose(psi_q, [0.1, 0.1, 0.3 - bb], atol=1e-3 * h)
+
+
+def test_discrete_circle_roles_match_the_analytic_circle():
+    """Masks from a sampled circle SDF equal the analytic circle's except
+    where a vertex lies within the interpolation error of the surface."""
+    n, l0 = 64, 1.0 / 64
+    m = O.Mesh(2, (n, n), (0.0, 0.0), l0)
+    c, R = (0.5 + 0.3 * l0, 0.5 - 0.2 * l0), 10.3 * l0
+    h = 0.5 * l0
+    vals, o = _grid(161, h, lambda X, Y: np.hypot(X, Y) - R)
+    sb = _body(vals, o, h, c, theta=0.3, radius=R, far=O.sdf_far_radius(R, l0, 5.0))
+    ab = O.BodyState(c, R, 2)
+    rs, ra = O.roles(m, [sb]), O.roles(m, [ab])
+    diff = np.nonzero(rs != ra)[0]
+    ijk = m.ijk(np.arange(m.Nc))
+    near = np.zeros(m.Nc, dtype=bool)
+    for v in range(4):
+        vx = m.origin[0] + (ijk[0] + (v & 1)) * l0
+        vy = m.origin[1] + (ijk[1] + (v >> 1)) * l0
+        near |= np.abs(np.hypot(vx - c[0], vy - c[1]) - R) < 1e-3 * h
+    assert np.all(near[diff]), diff
+    assert (ra == 2).sum() > 40
+    np.testing.assert_array_equal(O.band_cells(m, [sb], rs, 5 * l0), O.band_cells(m, [ab], ra, 5 * l0))
+
+
+def test_ellipse_distance_closed_forms():
+    """On the axes the distance is closed-form; elsewhere it matches a
+    dense sampling of the boundary."""
+    a, b = 0.5, 0.125
+    d = inputs.ellipse_distance(a, b, np.array([0.7, 0.0, -0.9, 0.0]), np.array([0.0, 0.3, 0.0, -0.05]))
+    np.testing.assert_allclose(d, [0.2, 0.175, 0.4, -0.075], atol=1e-15)
+    rng = np.random.default_rng(4)
+    P = rng.uniform(-0.8, 0.8, (2, 200))
+    t = np.linspace(0, 2 * np.pi, 400001)
+    E = np.stack([a * np.cos(t), b * np.sin(t)])
+    bf = np.array([np.min(np.hypot(E[0] - p[0], E[1] - p[1])) for p in P.T])
+    d = inputs.ellipse_distance(a, b, P[0], P[1])
+    np.testing.assert_allclose(np.abs(d), bf, atol=5e-9)
+    inside = (P[0] / a) ** 2 + (P[1] / b) ** 2 < 1
+    assert np.all((d < 0) == inside)
