@@ -6,7 +6,8 @@ u* and the PPE right-hand side, Bi-CGSTAB to a true relative residual of
 1e-8 (FP64), projection.  Inputs are resident in HBM before the timed
 region starts.  Prints one JSON line.
 
-Other forms: --workload cylinder|sphere|manufactured (the last: the 32x32
+Other forms: --workload cylinder|sphere|flapping|manufactured (flapping: the
+512x512 hovering elliptic wing, a rotating discrete-SDF body; manufactured: the 32x32
 manufactured-solution Poisson problem, a step being the MLS build plus one
 PPE solve from zero, a latency figure), --precision mixed (FP32-stored
 matrix with FP64 residual replacement) or refine (FP32 Bi-CGSTAB inside
@@ -56,6 +57,9 @@ def workload_name(case, n_active, precision):
         what = "periodic Taylor-Green vortex"
     elif case.name.startswith("C2"):
         what = "oscillating cylinder (D=1, A=0.2D, moving DPs and roles)"
+    elif case.name.startswith("C6"):
+        what = ("flapping elliptic wing (chord 1, aspect 4, discrete SDF at posture theta(t), "
+                "translating and rotating, moving DPs and roles)")
     else:
         what = "moving sphere (D=0.25, A=0.2D, moving DPs and roles)"
     stencil = "3x3" if case.dim == 2 else "3x3x3"
@@ -198,9 +202,9 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=100)
     ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--workload", choices=["tgv", "cylinder", "sphere", "manufactured"], default="tgv",
+    ap.add_argument("--workload", choices=["tgv", "cylinder", "sphere", "flapping", "manufactured"], default="tgv",
                     help="tgv: 512^2 periodic Taylor-Green (default line); cylinder: 1024^2 oscillating "
-                         "cylinder; sphere: 128^3 moving sphere")
+                         "cylinder; sphere: 128^3 moving sphere; flapping: 512^2 hovering elliptic wing")
     ap.add_argument("--n", type=int, default=None)
     ap.add_argument("--precision", choices=sorted(PRECISIONS), default="fp64")
     ap.add_argument("--guess", choices=["warm", "zero", "learned"], default="warm",
@@ -235,6 +239,8 @@ def main():
         case = configs.c1_taylor_green(n=args.n or 512, steps=args.steps)
     elif args.workload == "cylinder":
         case = configs.c2_oscillating_cylinder(n=args.n or 1024, steps=args.steps)
+    elif args.workload == "flapping":
+        case = configs.c6_flapping_ellipse(n=args.n or 512, steps=args.steps)
     else:
         case = configs.c4_moving_sphere(n=args.n or 128, steps=args.steps)
     prec_name, mat_b, vec_b, dtype, prec_text = PRECISIONS[args.precision]
@@ -286,7 +292,7 @@ def main():
         bytes_per = stage_bytes(n_unknown, case.dim, mat_b, vec_b)
         avg_s = prof["s_ms"] / max(prof["s_n"], 1) * 1e-3
         achieved = bytes_per / avg_s / 1e9 if avg_s > 0 else None
-        flow = {"C1": "taylor_green", "C2": "cylinder", "C4": "sphere"}[case.name[:2]]
+        flow = {"C1": "taylor_green", "C2": "cylinder", "C4": "sphere", "C6": "flapping"}[case.name[:2]]
         traffic = measured_traffic(f"{flow}_{case.n[0]}_{args.precision}", case.dim)
         roofline = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                     "frac": achieved / HBM_PEAK_GBS if achieved else None, "traffic": traffic,
