@@ -202,6 +202,23 @@ def c4_moving_sphere(n=128, steps=20):
                 bc_pressure={1: DIRICHLET, 2: NEUMANN}, bc_velocity={1: NEUMANN, 2: DIRICHLET})
 
 
+def c4_two_spinning_spheres(n=32, steps=20):
+    """[0, 1]^3 with two spheres whose 5 l0 bands overlap on 32^3: R = 0.12
+    at (0.3, 0.5, 0.5), x(t) = 0.03 sin(2 pi t), spinning about y with
+    angle 0.4 sin(2 pi t) (id 2); R = 0.1 at (0.7, 0.5, 0.5), z(t) =
+    0.03 sin(2 pi t + pi/2), spinning about (1, 1, 1)/sqrt(3) with angle
+    0.6 sin(4 pi t) (id 3).  Walls and boundary conditions as in C4."""
+    base = c4_moving_sphere(n=n, steps=steps)
+    k = 1.0 / math.sqrt(3.0)
+    a = Body(radius=0.12, motion=Oscillation((0.3, 0.5, 0.5), 0.03, 1.0, 0, spin_amplitude=0.4, spin_freq=1.0,
+                                             spin_axis=(0.0, 1.0, 0.0)))
+    b = Body(radius=0.1, motion=Oscillation((0.7, 0.5, 0.5), 0.03, 1.0, 2, 0.5 * math.pi, spin_amplitude=0.6,
+                                            spin_freq=2.0, spin_axis=(k, k, k)), body_id=BODY_ID + 1)
+    return replace(base, name=f"C4-two-spinning-spheres-{n}", jitter_seed=8, body=a, more_bodies=(b,),
+                   bc_pressure={1: DIRICHLET, 2: NEUMANN, 3: NEUMANN},
+                   bc_velocity={1: NEUMANN, 2: DIRICHLET, 3: DIRICHLET})
+
+
 def c4_sphere_variant(seed, n=128, steps=60):
     """A C4-shaped trajectory for the 3D learned-guess data set: amplitude
     A ~ U[0.1, 0.4] D and frequency f ~ U[0.5, 2] drawn from PCG64(seed), as

@@ -86,8 +86,9 @@ def tgv_pressure(pos, t, nu):
 @dataclass(frozen=True)
 class Oscillation:
     """Body centre c(t) = c0 + A sin(2 pi f t + phase) e_axis; velocity is its
-    derivative.  Optional spin about z (2D): posture theta(t) = theta0 +
-    S sin(2 pi f_s t), angular velocity omega(t) = d theta / dt."""
+    derivative.  Optional spin about spin_axis (z in 2D): angle theta(t) =
+    theta0 + S sin(2 pi f_s t), angular velocity omega(t) = d theta / dt
+    (omega_vector: omega(t) spin_axis)."""
     c0: tuple
     amplitude: float
     freq: float
@@ -96,12 +97,17 @@ class Oscillation:
     spin_amplitude: float = 0.0
     spin_freq: float = 0.0
     theta0: float = 0.0
+    spin_axis: tuple = (0.0, 0.0, 1.0)    # unit axis of the spin (z in 2D)
 
     def theta(self, t):
         return self.theta0 + self.spin_amplitude * math.sin(2 * math.pi * self.spin_freq * t)
 
     def omega(self, t):
         return 2 * math.pi * self.spin_freq * self.spin_amplitude * math.cos(2 * math.pi * self.spin_freq * t)
+
+    def omega_vector(self, t):
+        w = self.omega(t)
+        return tuple(w * a for a in self.spin_axis)
 
     def centre(self, t):
         c = list(self.c0)
@@ -141,6 +147,9 @@ class FlappingMotion:
 
     def omega(self, t):
         return -self.theta0 * (2.0 / self.a0) * math.cos(2.0 * t / self.a0 + self.phi)
+
+    def omega_vector(self, t):
+        return (0.0, 0.0, self.omega(t))
 
 
 def ellipse_distance(semi_a, semi_b, x, y):

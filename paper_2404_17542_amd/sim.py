@@ -83,10 +83,10 @@ class GpuSim:
         for b in self.bodies:
             sel = role_h == b["id"]
             w = b["omega"]
-            r = [pos_h[a, sel] - b["centre"][a] for a in range(dim)]
-            rot = [-w * r[1], w * r[0]] + [0.0] * (dim - 2)      # omega about z
+            r = [pos_h[a, sel] - b["centre"][a] for a in range(dim)] + [0.0] * (3 - dim)
+            rot = (w[1] * r[2] - w[2] * r[1], w[2] * r[0] - w[0] * r[2], w[0] * r[1] - w[1] * r[0])   # omega x r
             for a in range(dim):
-                u0[a, sel] = b["velocity"][a] + rot[a] if w != 0.0 else b["velocity"][a]
+                u0[a, sel] = b["velocity"][a] + rot[a] if any(w) else b["velocity"][a]
         self.u.copy_(torch.tensor(u0, **f64))
         self.vel_slot = 0
         self.ctx.build_stencils(SET_VEL[self.vel_slot], self.pos, self.role, self.normal, case.bc_velocity,
@@ -97,12 +97,12 @@ class GpuSim:
         out = []
         for i, b in enumerate(self.case.rigid_bodies):
             vel = b.motion.velocity(t)
-            w = b.motion.omega(t)
+            w = b.motion.omega_vector(t)
             if prev is None:
-                dvdt, dw = (0.0,) * len(vel), 0.0
+                dvdt, dw = (0.0,) * len(vel), (0.0, 0.0, 0.0)
             else:
                 dvdt = tuple((vn - vo) / self.case.dt for vn, vo in zip(vel, prev[i]["velocity"]))
-                dw = (w - prev[i]["omega"]) / self.case.dt
+                dw = tuple((wn - wo) / self.case.dt for wn, wo in zip(w, prev[i]["omega"]))
             d = {"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
                  "dvdt": dvdt, "omega": w, "domega_dt": dw, "theta": b.motion.theta(t)}
             if b.body_id in self.sdf:
