@@ -121,6 +121,35 @@ def test_flapping_ellipse_steps_match_oracle(M):
     assert np.abs(np.array(F[0]) - Fo[0]).max() <= 1e-10 * scale, (F[0], Fo[0])
 
 
+def test_ellipse_and_cylinder_together_match_oracle(M):
+    """A discrete-SDF body and an analytic circle in one body list (ids 2
+    and 3, bands overlapping at the start): nearest-body decisions mix the
+    interpolated and the closed-form psi; roles, transitions and sweep
+    counts equal the oracle's, positions within 1e-11 l0, over the initial
+    arrangement and two whole steps."""
+    from paper_2404_17542_amd.inputs import Oscillation
+    from paper_2404_17542_amd.sim import GpuSim
+    base = configs.c6_flapping_ellipse(n=256, steps=2)
+    c0 = base.body.motion.centre(0.0)
+    cyl = configs.Body(radius=0.3, motion=Oscillation((c0[0] + 0.3, c0[1] - 0.75), 0.05, 1.0, 0),
+                       body_id=configs.BODY_ID + 1)
+    case = replace(base, name="C6-ellipse-and-cylinder-256", more_bodies=(cyl,),
+                   bc_pressure={1: configs.DIRICHLET, 2: configs.NEUMANN, 3: configs.NEUMANN},
+                   bc_velocity={1: configs.DIRICHLET, 2: configs.DIRICHLET, 3: configs.DIRICHLET})
+    g = GpuSim(case)
+    o = OracleSim(case)
+    assert np.array_equal(np_(g.role), o.role)
+    assert (o.role == 2).sum() > 10 and (o.role == 3).sum() > 10
+    assert np.abs(np_(g.pos) - o.pos).max() < 1e-11 * case.l0
+    for _ in range(2):
+        rg = g.step()
+        ro = o.step()
+        assert rg["converged"] and rg["trans"] == ro["trans"] and rg["sweeps"] == ro["sweeps"]
+        assert np.array_equal(np_(g.role), o.role)
+        assert np.abs(np_(g.pos) - o.pos).max() < 1e-11 * case.l0
+    assert np.abs(np_(g.u) - o.u).max() / np.abs(o.u).max() < 1e-6
+
+
 def test_sdf_body_argument_checks(M):
     """A grid whose inner nodes do not span the far radius, a non-contiguous
     or host grid, and a discrete SDF on a 3D mesh are rejected."""
