@@ -158,19 +158,38 @@ class BodyState:
         return self.radius * self.radius
 
 
+def sdf_weights(re_over_h, kind):
+    """Weights of the edge (|X| = 1) and corner (|X| = sqrt 2) nodes of the
+    3x3 SDF support, by the scalar library cos/exp (Sec. 3.2 weight)."""
+    def w(r):
+        if not r <= re_over_h:
+            return 0.0
+        if kind == "cos2":
+            a = math.cos(math.pi * r / (2.0 * re_over_h))
+            return a * a
+        return math.exp(-4.0 * r * r / (re_over_h * re_over_h))
+    return w(1.0), w(math.sqrt(2.0))
+
+
 def sdf_eval(b, x):
     """psi and grad psi of a discrete-SDF body at the points x [2][K]
     (Sec. 2.5 with the chi_c = 1 MLS of Sec. 3.2).
 
     The point is taken to the body frame, xi = R(-theta)(x - c); the support
     is the 3x3 block of SDF nodes around the node nearest to xi (kept one
-    node inside the grid); the quadratic fit through the centre node's value
-    (chi_c = 1) is the weighted least-squares solution for the derivative
-    coefficients Phi over the eight other nodes, with offsets and the
-    evaluation point in units of h and weights W(|X| h; r_e = re_over_h h);
-    psi = psi_s + p(s).Phi at s = (xi - xi_s)/h and grad psi is that
+    node inside the grid); the quadratic through the centre node's value
+    (chi_c = 1) has the derivative coefficients Phi of the weighted
+    least-squares fit to the eight other nodes (offsets X in units of h,
+    basis p = (X, Y, X^2/2, XY, Y^2/2), weights W(|X| h; r_e = re_over_h h)).
+    On this symmetric support the normal equations decouple; with the node
+    weights w1 (edges) and w2 (corners), g_q = sum_k w_k p_q(X_k) dpsi_k:
+      Phi_X = g_X / D1, Phi_Y = g_Y / D1, D1 = 2 w1 + 4 w2,
+      Phi_XY = g_XY / (4 w2),
+      [[A, B], [B, A]] (Phi_XX, Phi_YY) = (g_XX, g_YY), A = D1 / 4, B = w2.
+    psi = psi_s + p(s).Phi at s = (xi - xi_s)/h; grad psi is that
     polynomial's gradient rotated back by theta.  Beyond sdf.far from the
-    centre: psi = |x - c| - R with gradient (x - c)/|x - c|.
+    centre: psi = |x - c| - R with gradient (x - c)/|x - c|.  Each operation
+    is evaluated on its own in the order written.
     """
     g = b.sdf
     d0 = x[0] - b.centre[0]
@@ -188,20 +207,31 @@ def sdf_eval(b, x):
     s0 = q0 - i
     s1 = q1 - j
     ps = g.values[j, i]
-    M = np.zeros((5, 5))
-    rhs = np.zeros((5, len(ps)))
+    w1, w2 = sdf_weights(g.re_over_h, g.kind)
+    gq = [0.0] * 5
     for dj in (-1, 0, 1):
         for di in (-1, 0, 1):
             if di == 0 and dj == 0:
                 continue
-            w = float(weight(np.hypot(di, dj), g.re_over_h, g.kind))
-            p = np.array(basis([float(di), float(dj)]))
-            M += w * np.outer(p, p)
-            rhs += (w * p)[:, None] * (g.values[j + dj, i + di] - ps)[None, :]
-    Phi = np.linalg.solve(M, rhs)
-    psi = ps + np.einsum("bk,bk->k", np.array(basis([s0, s1])), Phi)
-    gx = (Phi[0] + s0 * Phi[2] + s1 * Phi[3]) / g.h
-    gy = (Phi[1] + s0 * Phi[3] + s1 * Phi[4]) / g.h
+            w = w2 if (di != 0 and dj != 0) else w1
+            X, Y = float(di), float(dj)
+            coef = (w * X, w * Y, w * (0.5 * X * X), w * (X * Y), w * (0.5 * Y * Y))
+            dv = g.values[j + dj, i + di] - ps
+            for q in range(5):
+                gq[q] = gq[q] + coef[q] * dv
+    D1 = 2.0 * w1 + 4.0 * w2
+    D3 = 4.0 * w2
+    A = D1 / 4.0
+    B = w2
+    det = A * A - B * B
+    P0 = gq[0] / D1
+    P1 = gq[1] / D1
+    P3 = gq[3] / D3
+    P2 = (A * gq[2] - B * gq[4]) / det
+    P4 = (A * gq[4] - B * gq[2]) / det
+    psi = ps + (s0 * P0 + s1 * P1 + 0.5 * s0 * s0 * P2 + s0 * s1 * P3 + 0.5 * s1 * s1 * P4)
+    gx = (P0 + s0 * P2 + s1 * P3) / g.h
+    gy = (P1 + s0 * P3 + s1 * P4) / g.h
     grad = [ct * gx - st * gy, st * gx + ct * gy]
     with np.errstate(invalid="ignore", divide="ignore"):
         r = np.sqrt(r2)

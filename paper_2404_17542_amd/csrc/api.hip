@@ -49,66 +49,49 @@ struct mcd_ctx {
     // host constants of the arrangement (computed once, used identically by every call)
     double kl0 = 0, spring[4] = {0, 0, 0, 0}, eps_l0 = 0, band_l0 = 0, re = 0, rs = 0;
     FitDev fit{0.0, 0.0, 0.0};
-    double sdfC[5][8] = {};     // discrete-SDF MLS derivative weights (0: not computable)
+    BodiesDev sdft{};           // discrete-SDF interpolation constants (sdfc, sdfD1 ...)
     bool sdf_ok = false;
     std::string err;
 };
 
-// chi_c = 1 quadratic MLS over the 3x3 nodes of a regular grid (offsets in
-// units of h, weight W(|X|; r_e / l0) of the context): C = M^-1 [w_k p_k]
-// with M = sum_k w_k p_k p_k^T, p = (X, Y, X^2/2, XY, Y^2/2).  Returns false
-// when M is singular (r_e too small to reach the diagonal nodes).
-static bool sdf_table(int wkind, double re, double C[5][8]) {
-    double P[8][5], w[8];
+// Closed form of the chi_c = 1 quadratic MLS over the 3x3 nodes of a regular
+// grid (offsets X, Y in units of h, weight W(|X|; r_e / l0) of the context,
+// basis p = (X, Y, X^2/2, XY, Y^2/2)).  By the symmetry of the support the
+// normal matrix is block diagonal: X and Y each with sum w X^2 =
+// 2 w1 + 4 w2 = D1, XY with sum w X^2 Y^2 = 4 w2 = D3, and the pair
+// (X^2/2, Y^2/2) with [[A, B], [B, A]], A = D1 / 4, B = w2 (w1, w2: the
+// weights of the edge and corner nodes).  The per-node factors w_k p_q(X_k)
+// are exact.  False when a weight vanishes (r_e not beyond sqrt 2).
+static bool sdf_table(int wkind, double re, BodiesDev* t) {
+#pragma clang fp contract(off)
+    auto wfun = [&](double r) {
+        if (!(r <= re)) return 0.0;
+        if (wkind == MCD_WEIGHT_COS2) {
+            const double a = cos(M_PI * r / (2.0 * re));
+            return a * a;
+        }
+        return exp(-4.0 * r * r / (re * re));
+    };
+    const double w1 = wfun(1.0), w2 = wfun(sqrt(2.0));
+    if (!(w1 > 0.0) || !(w2 > 0.0)) return false;
     int k = 0;
     for (int dj = -1; dj <= 1; ++dj)
         for (int di = -1; di <= 1; ++di) {
             if (di == 0 && dj == 0) continue;
-            const double X = di, Y = dj, r = sqrt(X * X + Y * Y);
-            double wk = 0.0;
-            if (r <= re) {
-                if (wkind == MCD_WEIGHT_COS2) {
-                    const double t = cos(M_PI * r / (2.0 * re));
-                    wk = t * t;
-                } else {
-                    wk = exp(-4.0 * r * r / (re * re));
-                }
-            }
-            w[k] = wk;
-            P[k][0] = X;
-            P[k][1] = Y;
-            P[k][2] = 0.5 * X * X;
-            P[k][3] = X * Y;
-            P[k][4] = 0.5 * Y * Y;
+            const double w = (di != 0 && dj != 0) ? w2 : w1;
+            const double X = di, Y = dj;
+            t->sdfc[0][k] = w * X;
+            t->sdfc[1][k] = w * Y;
+            t->sdfc[2][k] = w * (0.5 * X * X);
+            t->sdfc[3][k] = w * (X * Y);
+            t->sdfc[4][k] = w * (0.5 * Y * Y);
             ++k;
         }
-    // augmented system [M | w p^T] solved by Gauss-Jordan with partial pivoting
-    double A[5][13];
-    for (int a = 0; a < 5; ++a) {
-        for (int b = 0; b < 5; ++b) {
-            double m = 0.0;
-            for (int q = 0; q < 8; ++q) m += w[q] * P[q][a] * P[q][b];
-            A[a][b] = m;
-        }
-        for (int q = 0; q < 8; ++q) A[a][5 + q] = w[q] * P[q][a];
-    }
-    for (int col = 0; col < 5; ++col) {
-        int piv = col;
-        for (int r = col + 1; r < 5; ++r)
-            if (fabs(A[r][col]) > fabs(A[piv][col])) piv = r;
-        if (!(fabs(A[piv][col]) > 1e-12)) return false;
-        if (piv != col)
-            for (int q = 0; q < 13; ++q) std::swap(A[piv][q], A[col][q]);
-        const double inv = 1.0 / A[col][col];
-        for (int q = 0; q < 13; ++q) A[col][q] *= inv;
-        for (int r = 0; r < 5; ++r) {
-            if (r == col || A[r][col] == 0.0) continue;
-            const double f = A[r][col];
-            for (int q = 0; q < 13; ++q) A[r][q] -= f * A[col][q];
-        }
-    }
-    for (int a = 0; a < 5; ++a)
-        for (int q = 0; q < 8; ++q) C[a][q] = A[a][5 + q];
+    t->sdfD1 = 2.0 * w1 + 4.0 * w2;
+    t->sdfD3 = 4.0 * w2;
+    t->sdfA = t->sdfD1 / 4.0;
+    t->sdfB = w2;
+    t->sdfDet = t->sdfA * t->sdfA - t->sdfB * t->sdfB;
     return true;
 }
 
@@ -181,7 +164,12 @@ static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* ou
             if (b.omega[a] != 0.0 || b.domega_dt[a] != 0.0) out->rot[k] = 1;
         }
         out->any_rot |= out->rot[k];
-        memcpy(out->sdfC, c->sdfC, sizeof(out->sdfC));
+        memcpy(out->sdfc, c->sdft.sdfc, sizeof(out->sdfc));
+        out->sdfD1 = c->sdft.sdfD1;
+        out->sdfD3 = c->sdft.sdfD3;
+        out->sdfA = c->sdft.sdfA;
+        out->sdfB = c->sdft.sdfB;
+        out->sdfDet = c->sdft.sdfDet;
         out->R[k] = b.radius;
         out->R2[k] = b.radius * b.radius;
     }
@@ -256,7 +244,7 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
         c->fit = FitDev{prm->fit_alpha * 0.5, re_fit, M_PI / re_fit};
     }
     c->re = prm->re_over_l0 * l0;
-    c->sdf_ok = sdf_table(prm->weight_kind, prm->re_over_l0, c->sdfC);
+    c->sdf_ok = sdf_table(prm->weight_kind, prm->re_over_l0, &c->sdft);
     c->rs = prm->rs_over_l0 * l0;
 
     auto alloc = [&](void** p, size_t bytes) {

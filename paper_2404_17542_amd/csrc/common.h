@@ -42,18 +42,25 @@ struct BodiesDev {
     double sh[kMaxBodies];
     double cth[kMaxBodies], sth[kMaxBodies];
     double far2[kMaxBodies];
-    // chi_c = 1 MLS derivative weights of the 3x3 SDF support: Phi_q =
-    // sum_k C[q][k] (psi_k - psi_centre), neighbours k in row order without
-    // the centre; one table for the context (the grid is regular)
-    double sdfC[5][8];
+    // chi_c = 1 quadratic MLS over the 3x3 SDF nodes in closed form (the grid
+    // is regular and symmetric, so the normal equations decouple):
+    // g_q = sum_k sdfc[q][k] (psi_k - psi_centre) with sdfc = w_k p_q(X_k)
+    // (exact: X, Y in {-1, 0, 1}), then Phi_X = g_0 / D1, Phi_Y = g_1 / D1,
+    // Phi_XY = g_3 / D3 and the (X^2/2, Y^2/2) pair from its 2x2 block
+    // [[A, B], [B, A]]; neighbours k in row order without the centre
+    double sdfc[5][8];
+    double sdfD1, sdfD3, sdfA, sdfB, sdfDet;
 };
 
 // psi and grad psi of discrete-SDF body b at the 2D point (x0, x1): the point
 // in the body frame, xi = R(-theta)(x - c); the 3x3 nodes around the nearest
 // node (kept one node inside the grid); psi = psi_s + p(s).Phi with s the
 // offset from that node in units of h; the gradient rotated back.  Beyond
-// the far radius: the bounding disc, psi = |x - c| - R.
+// the far radius: the bounding disc, psi = |x - c| - R.  Every operation is
+// rounded on its own (no contraction), in a fixed order, so that the result
+// is reproducible bit for bit by a plain evaluation of the same formulas.
 __device__ __forceinline__ double sdf_psi(const BodiesDev& B, int b, double x0, double x1, double* g) {
+#pragma clang fp contract(off)
     const double d0 = x0 - B.c[b][0], d1 = x1 - B.c[b][1];
     const double r2 = d0 * d0 + d1 * d1;
     if (r2 >= B.far2[b]) {
@@ -72,7 +79,7 @@ __device__ __forceinline__ double sdf_psi(const BodiesDev& B, int b, double x0, 
     const double s0 = q0 - (double)i, s1 = q1 - (double)j;
     const double* __restrict__ S = B.sdf[b];
     const double ps = S[(size_t)j * n0 + i];
-    double Phi[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
+    double gq[5] = {0.0, 0.0, 0.0, 0.0, 0.0};
     int k = 0;
 #pragma unroll
     for (int dj = -1; dj <= 1; ++dj)
@@ -81,13 +88,15 @@ __device__ __forceinline__ double sdf_psi(const BodiesDev& B, int b, double x0, 
             if (di == 0 && dj == 0) continue;
             const double dv = S[(size_t)(j + dj) * n0 + (i + di)] - ps;
 #pragma unroll
-            for (int q = 0; q < 5; ++q) Phi[q] += B.sdfC[q][k] * dv;
+            for (int q = 0; q < 5; ++q) gq[q] = gq[q] + B.sdfc[q][k] * dv;
             ++k;
         }
-    const double psi = ps + (s0 * Phi[0] + s1 * Phi[1] + 0.5 * s0 * s0 * Phi[2] + s0 * s1 * Phi[3] +
-                             0.5 * s1 * s1 * Phi[4]);
-    const double gx = (Phi[0] + s0 * Phi[2] + s1 * Phi[3]) / h;
-    const double gy = (Phi[1] + s0 * Phi[3] + s1 * Phi[4]) / h;
+    const double P0 = gq[0] / B.sdfD1, P1 = gq[1] / B.sdfD1, P3 = gq[3] / B.sdfD3;
+    const double P2 = (B.sdfA * gq[2] - B.sdfB * gq[4]) / B.sdfDet;
+    const double P4 = (B.sdfA * gq[4] - B.sdfB * gq[2]) / B.sdfDet;
+    const double psi = ps + (s0 * P0 + s1 * P1 + 0.5 * s0 * s0 * P2 + s0 * s1 * P3 + 0.5 * s1 * s1 * P4);
+    const double gx = (P0 + s0 * P2 + s1 * P3) / h;
+    const double gy = (P1 + s0 * P3 + s1 * P4) / h;
     g[0] = ct * gx - st * gy;
     g[1] = st * gx + ct * gy;
     return psi;

@@ -147,3 +147,33 @@ def test_ellipse_distance_closed_forms():
     np.testing.assert_allclose(np.abs(d), bf, atol=5e-9)
     inside = (P[0] / a) ** 2 + (P[1] / b) ** 2 < 1
     assert np.all((d < 0) == inside)
+
+
+@pytest.mark.parametrize("kind,re", [("cos2", 2.5), ("gauss", 2.5), ("cos2", 1.6)])
+def test_closed_form_equals_the_weighted_least_squares_fit(kind, re):
+    """The closed-form Phi of the symmetric 3x3 support equals a direct
+    weighted least-squares solve (numpy lstsq of sqrt(w) p . Phi = sqrt(w)
+    dpsi over the eight nodes) for random node values."""
+    rng = np.random.default_rng(5)
+    vals = rng.standard_normal((7, 7))
+    h = 0.1
+    b = _body(vals, (-0.3, -0.3), h, kind=kind, re=re)
+    pts = np.stack([rng.uniform(-0.15, 0.15, 50), rng.uniform(-0.15, 0.15, 50)])
+    psi, g = O.sdf_eval(b, pts)
+    for k in range(pts.shape[1]):
+        q = (pts[:, k] - np.array([-0.3, -0.3])) / h
+        i, j = int(np.floor(q[0] + 0.5)), int(np.floor(q[1] + 0.5))
+        rows, rhs = [], []
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                if di == 0 and dj == 0:
+                    continue
+                w = float(O.weight(np.hypot(di, dj), re, kind))
+                rows.append(math.sqrt(w) * np.array([di, dj, 0.5 * di * di, di * dj, 0.5 * dj * dj]))
+                rhs.append(math.sqrt(w) * (vals[j + dj, i + di] - vals[j, i]))
+        phi = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)[0]
+        s = q - np.array([i, j])
+        ref = vals[j, i] + phi @ np.array([s[0], s[1], 0.5 * s[0] ** 2, s[0] * s[1], 0.5 * s[1] ** 2])
+        gref = np.array([phi[0] + s[0] * phi[2] + s[1] * phi[3], phi[1] + s[0] * phi[3] + s[1] * phi[4]]) / h
+        assert abs(psi[k] - ref) < 1e-12
+        assert abs(g[0][k] - gref[0]) < 1e-10 and abs(g[1][k] - gref[1]) < 1e-10
