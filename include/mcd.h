@@ -99,22 +99,24 @@ typedef struct {
  * In 2D only the z components omega[2], domega_dt[2] may be non-zero
  * (MCD_ERR_ARG otherwise).
  *
- * Discrete-SDF body (2D, Sec. 2.5), sdf != NULL: a device array
- * [sdf_n[1]][sdf_n[0]] (x fastest, caller-owned, read by the calls that
- * take the body in stream order) of psi at the body-frame nodes
- * xi_ij = sdf_origin + (i, j) sdf_h.  A point x maps to
- * xi = R(-theta)(x - centre); psi(x) and grad psi are the chi_c = 1
- * quadratic MLS reconstruction (Sec. 3.2, with the weight and r_e / l0 of
- * mcd_params taken in units of sdf_h) over the 3x3 nodes around the node
- * nearest to xi, rotated back by theta.  `radius` is then the radius of a
- * disc about `centre` that contains the body: beyond
+ * Discrete-SDF body (Sec. 2.5; 2D as in the paper, 3D by the same rule),
+ * sdf != NULL: a device array [sdf_n[1]][sdf_n[0]] (2D) or
+ * [sdf_n[2]][sdf_n[1]][sdf_n[0]] (3D), x fastest, caller-owned, read by the
+ * calls that take the body in stream order, of psi at the body-frame nodes
+ * xi = sdf_origin + (i, j[, k]) sdf_h.  A point x maps to
+ * xi = R^T (x - centre), R the posture: the rotation by theta about z (2D)
+ * or about the unit vector `axis` (3D).  psi(x) and grad psi are the
+ * chi_c = 1 quadratic MLS reconstruction (Sec. 3.2, with the weight and
+ * r_e / l0 of mcd_params taken in units of sdf_h) over the 3^d nodes around
+ * the node nearest to xi, rotated back by R.  `radius` is then the radius
+ * of a ball about `centre` that contains the body: beyond
  * rho = radius + (band_over_l0 + 2) l0 psi is |x - centre| - radius (those
  * points lie outside the body's band, where only the sign of psi is used).
  * The nodes 1 .. sdf_n[a] - 2 must span [-rho, rho] along each body axis
- * and sdf_n >= 3, sdf_h > 0 (MCD_ERR_ARG otherwise, also in 3D or when r_e
- * does not reach the diagonal nodes).  mcd_fluid_force orders a body's
- * boundary DPs by their polar angle about `centre`: the body must be
- * star-shaped about it. */
+ * and sdf_n >= 3, sdf_h > 0, |axis| = 1 in 3D (MCD_ERR_ARG otherwise, also
+ * when r_e does not reach the diagonal nodes).  mcd_fluid_force (2D) orders
+ * a body's boundary DPs by their polar angle about `centre`: the body must
+ * be star-shaped about it. */
 typedef struct {
     int id;              /* role id of its boundary DPs (1 .. 15), != wall_id, distinct
                             within one body list (MCD_ERR_ARG otherwise) */
@@ -124,10 +126,11 @@ typedef struct {
     double dvdt[3];      /* (V_trans^{k+1} - V_trans^k) / dt, Eq. (dvdt_moving_boundary) */
     double omega[3];     /* angular velocity omega^{k+1} */
     double domega_dt[3]; /* (omega^{k+1} - omega^k) / dt */
-    double theta;        /* posture angle of a discrete-SDF body's frame (2D, about z) */
+    double theta;        /* posture angle of a discrete-SDF body's frame */
+    double axis[3];      /* its rotation axis (3D; unit length); 2D: z, not read */
     const double* sdf;   /* NULL: the circle/sphere psi above; else a discrete SDF (above) */
-    int sdf_n[2];        /* nodes along the body-frame x and y axes */
-    double sdf_origin[2];/* body-frame position of node (0, 0) */
+    int sdf_n[3];        /* nodes along the body-frame axes (sdf_n[2] unused in 2D) */
+    double sdf_origin[3];/* body-frame position of node 0 */
     double sdf_h;        /* node spacing */
 } mcd_body;
 

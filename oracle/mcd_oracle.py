@@ -117,8 +117,8 @@ class Mesh:
 
 @dataclass
 class SdfGrid:
-    """Discrete SDF of a rigid 2D body in its own frame (Sec. 2.5): psi at
-    the nodes origin + (i, j) h, values[j][i].  re_over_h and kind are the
+    """Discrete SDF of a rigid body in its own frame (Sec. 2.5): psi at the
+    nodes origin + (i, j[, k]) h, values[j][i] (2D) or values[k][j][i] (3D).  re_over_h and kind are the
     MLS support radius (in units of h) and weight of the interpolation;
     far is the radius about the body centre beyond which psi is taken as
     |x - c| - R (the distance to the bounding disc of radius R)."""
@@ -143,8 +143,8 @@ class BodyState:
     translational velocity and angular velocity omega (3-vector; in 2D only
     its z component).  With sdf = None the body is the circle/sphere of
     radius R; otherwise it is the discrete SDF `sdf` placed at the centre
-    with posture angle theta (2D), and R is the radius of a disc about the
-    centre that contains it."""
+    with posture angle theta (about z in 2D, about the unit `axis` in 3D),
+    and R is the radius of a ball about the centre that contains it."""
     centre: tuple
     radius: float
     body_id: int
@@ -152,26 +152,123 @@ class BodyState:
     omega: tuple = (0.0, 0.0, 0.0)
     theta: float = 0.0
     sdf: Optional[SdfGrid] = None
+    axis: tuple = (0.0, 0.0, 1.0)
 
     @property
     def r2(self):
         return self.radius * self.radius
 
 
+def _sdf_weight(r, re_over_h, kind):
+    if not r <= re_over_h:
+        return 0.0
+    if kind == "cos2":
+        a = math.cos(math.pi * r / (2.0 * re_over_h))
+        return a * a
+    return math.exp(-4.0 * r * r / (re_over_h * re_over_h))
+
+
 def sdf_weights(re_over_h, kind):
     """Weights of the edge (|X| = 1) and corner (|X| = sqrt 2) nodes of the
     3x3 SDF support, by the scalar library cos/exp (Sec. 3.2 weight)."""
-    def w(r):
-        if not r <= re_over_h:
-            return 0.0
-        if kind == "cos2":
-            a = math.cos(math.pi * r / (2.0 * re_over_h))
-            return a * a
-        return math.exp(-4.0 * r * r / (re_over_h * re_over_h))
-    return w(1.0), w(math.sqrt(2.0))
+    return _sdf_weight(1.0, re_over_h, kind), _sdf_weight(math.sqrt(2.0), re_over_h, kind)
+
+
+def _sumsq(v):
+    """v_0^2 + v_1^2 (+ v_2^2), left to right."""
+    acc = v[0] * v[0]
+    for a in range(1, len(v)):
+        acc = acc + v[a] * v[a]
+    return acc
+
+
+def posture_matrix(theta, axis):
+    """Rotation by theta about the unit axis (Rodrigues: cos I + sin [a]x +
+    (1 - cos) a a^T), row-major; each entry in a fixed operation order."""
+    ct, st = math.cos(theta), math.sin(theta)
+    a0, a1, a2 = (float(v) for v in axis)
+    oc = 1.0 - ct
+    return (ct + oc * a0 * a0, oc * a0 * a1 - st * a2, oc * a0 * a2 + st * a1,
+            oc * a1 * a0 + st * a2, ct + oc * a1 * a1, oc * a1 * a2 - st * a0,
+            oc * a2 * a0 - st * a1, oc * a2 * a1 + st * a0, ct + oc * a2 * a2)
 
 
 def sdf_eval(b, x):
+    """psi and grad psi of a discrete-SDF body at the points x [dim][K]."""
+    if x.shape[0] == 3:
+        return sdf_eval3(b, x)
+    return sdf_eval2(b, x)
+
+
+def sdf_eval3(b, x):
+    """3D form of sdf_eval2: the 3x3x3 nodes around the nearest node of
+    xi = R^T (x - c), R the posture; basis (X, Y, Z, X^2/2, Y^2/2, Z^2/2, XY,
+    YZ, ZX).  On the symmetric support the linear terms have the
+    denominator D1 = sum w X^2 = 2 w1 + 8 w2 + 8 w3 (w1, w2, w3: face, edge
+    and corner weights), the mixed ones DX = sum w X^2 Y^2 = 4 w2 + 8 w3,
+    and the three squares solve ((A - B) I + B 11^T) Phi = g with A = D1/4,
+    B = DX/4: Phi_q = (g_q - B (g_XX + g_YY + g_ZZ) / (A + 2B)) / (A - B).
+    grad psi is R times the polynomial's gradient."""
+    g = b.sdf
+    d0 = x[0] - b.centre[0]
+    d1 = x[1] - b.centre[1]
+    d2 = x[2] - b.centre[2]
+    r2 = d0 * d0 + d1 * d1 + d2 * d2
+    far = r2 >= g.far * g.far
+    R = posture_matrix(b.theta, b.axis)
+    xi0 = R[0] * d0 + R[3] * d1 + R[6] * d2
+    xi1 = R[1] * d0 + R[4] * d1 + R[7] * d2
+    xi2 = R[2] * d0 + R[5] * d1 + R[8] * d2
+    q0 = (xi0 - g.origin[0]) / g.h
+    q1 = (xi1 - g.origin[1]) / g.h
+    q2 = (xi2 - g.origin[2]) / g.h
+    nz_, ny, nx = g.values.shape
+    i = np.clip(np.floor(q0 + 0.5), 1, nx - 2).astype(np.int64)
+    j = np.clip(np.floor(q1 + 0.5), 1, ny - 2).astype(np.int64)
+    l = np.clip(np.floor(q2 + 0.5), 1, nz_ - 2).astype(np.int64)
+    s0, s1, s2 = q0 - i, q1 - j, q2 - l
+    ps = g.values[l, j, i]
+    w1, w2 = sdf_weights(g.re_over_h, g.kind)
+    w3 = _sdf_weight(math.sqrt(3.0), g.re_over_h, g.kind)
+    wc = (w1, w2, w3)
+    gq = [0.0] * 9
+    for dk in (-1, 0, 1):
+        for dj in (-1, 0, 1):
+            for di in (-1, 0, 1):
+                nzc = (di != 0) + (dj != 0) + (dk != 0)
+                if nzc == 0:
+                    continue
+                w = wc[nzc - 1]
+                X, Y, Z = float(di), float(dj), float(dk)
+                coef = (w * X, w * Y, w * Z, w * (0.5 * X * X), w * (0.5 * Y * Y), w * (0.5 * Z * Z),
+                        w * (X * Y), w * (Y * Z), w * (Z * X))
+                dv = g.values[l + dk, j + dj, i + di] - ps
+                for q in range(9):
+                    gq[q] = gq[q] + coef[q] * dv
+    D1 = 2.0 * w1 + 8.0 * w2 + 8.0 * w3
+    DX = 4.0 * w2 + 8.0 * w3
+    A = D1 / 4.0
+    B = DX / 4.0
+    P0, P1, P2 = gq[0] / D1, gq[1] / D1, gq[2] / D1
+    tq = B * (gq[3] + gq[4] + gq[5]) / (A + 2.0 * B)
+    amb = A - B
+    P3, P4, P5 = (gq[3] - tq) / amb, (gq[4] - tq) / amb, (gq[5] - tq) / amb
+    P6, P7, P8 = gq[6] / DX, gq[7] / DX, gq[8] / DX
+    psi = ps + (s0 * P0 + s1 * P1 + s2 * P2 + 0.5 * s0 * s0 * P3 + 0.5 * s1 * s1 * P4 +
+                0.5 * s2 * s2 * P5 + s0 * s1 * P6 + s1 * s2 * P7 + s2 * s0 * P8)
+    gx = (P0 + s0 * P3 + s1 * P6 + s2 * P8) / g.h
+    gy = (P1 + s1 * P4 + s0 * P6 + s2 * P7) / g.h
+    gz = (P2 + s2 * P5 + s1 * P7 + s0 * P8) / g.h
+    grad = [R[0] * gx + R[1] * gy + R[2] * gz, R[3] * gx + R[4] * gy + R[5] * gz,
+            R[6] * gx + R[7] * gy + R[8] * gz]
+    with np.errstate(invalid="ignore", divide="ignore"):
+        r = np.sqrt(r2)
+        psi = np.where(far, r - b.radius, psi)
+        grad = [np.where(far, d / r, gc) for d, gc in zip((d0, d1, d2), grad)]
+    return psi, grad
+
+
+def sdf_eval2(b, x):
     """psi and grad psi of a discrete-SDF body at the points x [2][K]
     (Sec. 2.5 with the chi_c = 1 MLS of Sec. 3.2).
 
@@ -466,7 +563,7 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
             if b.sdf is not None:
                 # x** = x* - psi grad psi / |grad psi|
                 psi, gv = sdf_eval(b, np.array(xs))
-                gn = np.sqrt(gv[0] * gv[0] + gv[1] * gv[1])
+                gn = np.sqrt(_sumsq(gv))
                 t = psi / gn
                 for a in range(dim):
                     xs[a] = np.where(sel, xs[a] - t * gv[a], xs[a])
@@ -487,7 +584,7 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
                 if b.sdf is not None:
                     # direction grad psi with its norm in place of (x - c, |x - c|)
                     psi, dd = sdf_eval(b, np.array(xs))
-                    r = np.sqrt(dd[0] * dd[0] + dd[1] * dd[1])
+                    r = np.sqrt(_sumsq(dd))
                 else:
                     dd = [xs[a] - b.centre[a] for a in range(dim)]
                     r2 = dd[0] * dd[0]
@@ -532,7 +629,7 @@ def normals(mesh, bodies, role, pos):
             continue
         if b.sdf is not None:
             _, gv = sdf_eval(b, pos[:, sel])
-            gn = np.sqrt(gv[0] * gv[0] + gv[1] * gv[1])
+            gn = np.sqrt(_sumsq(gv))
             for a in range(dim):
                 nrm[a, sel] = gv[a] / gn
             continue

@@ -36,7 +36,7 @@ def oracle_bodies(case, t):
             grid = O.SdfGrid(g[0], g[1], g[2], case.re_over_l0, case.weight,
                              O.sdf_far_radius(b.radius, case.l0, case.band_over_l0))
         out.append(O.BodyState(b.motion.centre(t), b.radius, b.body_id, b.motion.velocity(t),
-                               b.motion.omega_vector(t), b.motion.theta(t), grid))
+                               b.motion.omega_vector(t), b.motion.theta(t), grid, b.posture_axis()))
     return out
 
 

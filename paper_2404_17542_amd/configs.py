@@ -14,7 +14,7 @@ import numpy as np
 from dataclasses import dataclass, field, replace
 from typing import Optional
 
-from .inputs import FlappingMotion, Oscillation, ellipse_sdf_grid
+from .inputs import FlappingMotion, Oscillation, capsule_sdf_grid, ellipse_sdf_grid
 
 WALL_ID = 1
 BODY_ID = 2
@@ -33,16 +33,22 @@ class Body:
     motion: object
     body_id: int = BODY_ID
     ellipse: Optional[tuple] = None
+    capsule: Optional[tuple] = None      # 3D: (half length, radius), axis along body-frame x
     sdf_h_over_l0: float = 0.5
 
     def sdf_grid(self, l0, band_over_l0):
-        """(values [ny][nx], origin, h) of the body's discrete SDF, covering the
-        disc of radius R + (band + 2) l0 with its inner nodes, or None."""
-        if self.ellipse is None:
+        """(values, origin, h) of the body's discrete SDF, covering the ball of
+        radius R + (band + 2) l0 with its inner nodes, or None."""
+        if self.ellipse is None and self.capsule is None:
             return None
         h = self.sdf_h_over_l0 * l0
         reach = self.radius + (band_over_l0 + 2.0) * l0 + h
+        if self.capsule is not None:
+            return capsule_sdf_grid(self.capsule[0], self.capsule[1], h, reach)
         return ellipse_sdf_grid(self.ellipse[0], self.ellipse[1], h, reach)
+
+    def posture_axis(self):
+        return tuple(getattr(self.motion, "spin_axis", (0.0, 0.0, 1.0)))
 
 
 @dataclass(frozen=True)
@@ -217,6 +223,18 @@ def c4_two_spinning_spheres(n=32, steps=20):
     return replace(base, name=f"C4-two-spinning-spheres-{n}", jitter_seed=8, body=a, more_bodies=(b,),
                    bc_pressure={1: DIRICHLET, 2: NEUMANN, 3: NEUMANN},
                    bc_velocity={1: NEUMANN, 2: DIRICHLET, 3: DIRICHLET})
+
+
+def c4_spinning_capsule(n=32, steps=20):
+    """[0, 1]^3 with a capsule (half length 0.12, radius 0.06; a discrete SDF
+    on a grid of spacing l0/2) at (0.5, 0.5, 0.5) + 0.03 sin(2 pi t) e_x,
+    turning about the axis (0, 0.6, 0.8) with angle 0.5 + 0.4 sin(2 pi t).
+    Walls and boundary conditions as in C4."""
+    base = c4_moving_sphere(n=n, steps=steps)
+    body = Body(radius=0.18, motion=Oscillation((0.5, 0.5, 0.5), 0.03, 1.0, 0, spin_amplitude=0.4, spin_freq=1.0,
+                                                theta0=0.5, spin_axis=(0.0, 0.6, 0.8)),
+                capsule=(0.12, 0.06))
+    return replace(base, name=f"C4-spinning-capsule-{n}", jitter_seed=9, body=body)
 
 
 def c4_sphere_variant(seed, n=128, steps=60):

@@ -61,7 +61,8 @@ struct mcd_ctx {
 // 2 w1 + 4 w2 = D1, XY with sum w X^2 Y^2 = 4 w2 = D3, and the pair
 // (X^2/2, Y^2/2) with [[A, B], [B, A]], A = D1 / 4, B = w2 (w1, w2: the
 // weights of the edge and corner nodes).  The per-node factors w_k p_q(X_k)
-// are exact.  False when a weight vanishes (r_e not beyond sqrt 2).
+// are exact.  False when a weight vanishes (r_e not beyond sqrt 2).  The 3D
+// constants (3x3x3 nodes) are set alongside.
 static bool sdf_table(int wkind, double re, BodiesDev* t) {
 #pragma clang fp contract(off)
     auto wfun = [&](double r) {
@@ -92,6 +93,15 @@ static bool sdf_table(int wkind, double re, BodiesDev* t) {
     t->sdfA = t->sdfD1 / 4.0;
     t->sdfB = w2;
     t->sdfDet = t->sdfA * t->sdfA - t->sdfB * t->sdfB;
+    // 3D: face, edge and corner node weights; D1 = sum w X^2, DX = sum w X^2 Y^2
+    const double w3 = wfun(sqrt(3.0));
+    t->s3w[0] = w1;
+    t->s3w[1] = w2;
+    t->s3w[2] = w3;
+    t->s3D1 = 2.0 * w1 + 8.0 * w2 + 8.0 * w3;
+    t->s3DX = 4.0 * w2 + 8.0 * w3;
+    t->s3A = t->s3D1 / 4.0;
+    t->s3B = t->s3DX / 4.0;
     return true;
 }
 
@@ -116,6 +126,7 @@ static mcd_status hipfail(mcd_ctx* c, hipError_t e, const char* where) {
     } while (0)
 
 static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* out) {
+#pragma clang fp contract(off)
     *out = BodiesDev{};
     if (n < 0 || n > MCD_MAX_BODIES || (n > 0 && !bodies)) return false;
     // ascending id order: ties of the nearest-body rule go to the lower id
@@ -130,25 +141,40 @@ static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* ou
         if (!(b.radius > 0) || !isfinite(b.radius)) return false;
         out->sdf[k] = nullptr;
         if (b.sdf) {
-            // discrete SDF (2D): a valid grid whose inner nodes cover the disc of
-            // the far radius, and a computable interpolation table
-            if (c->dim != 2 || !c->sdf_ok) return false;
-            if (b.sdf_n[0] < 3 || b.sdf_n[1] < 3 || !(b.sdf_h > 0) || !isfinite(b.sdf_h) || !isfinite(b.theta))
-                return false;
+            // discrete SDF: a valid grid whose inner nodes cover the ball of the far
+            // radius, a unit posture axis (3D), computable interpolation constants
+            const int d = c->dim;
+            if (!c->sdf_ok || !(b.sdf_h > 0) || !isfinite(b.sdf_h) || !isfinite(b.theta)) return false;
             const double rho = b.radius + (c->prm.band_over_l0 + 2.0) * c->m.l0;
-            for (int a = 0; a < 2; ++a) {
-                if (!isfinite(b.sdf_origin[a])) return false;
+            for (int a = 0; a < d; ++a) {
+                if (b.sdf_n[a] < 3 || !isfinite(b.sdf_origin[a])) return false;
                 if (!(b.sdf_origin[a] + b.sdf_h <= -rho) || !(b.sdf_origin[a] + (b.sdf_n[a] - 2) * b.sdf_h >= rho))
                     return false;
+                out->sn[k][a] = b.sdf_n[a];
+                out->so[k][a] = b.sdf_origin[a];
             }
             out->sdf[k] = b.sdf;
-            out->sn[k][0] = b.sdf_n[0];
-            out->sn[k][1] = b.sdf_n[1];
-            out->so[k][0] = b.sdf_origin[0];
-            out->so[k][1] = b.sdf_origin[1];
             out->sh[k] = b.sdf_h;
-            out->cth[k] = cos(b.theta);
-            out->sth[k] = sin(b.theta);
+            const double ct = cos(b.theta), st = sin(b.theta);
+            out->cth[k] = ct;
+            out->sth[k] = st;
+            if (d == 3) {
+                const double a0 = b.axis[0], a1 = b.axis[1], a2 = b.axis[2];
+                if (!isfinite(a0) || !isfinite(a1) || !isfinite(a2)) return false;
+                if (!(fabs(a0 * a0 + a1 * a1 + a2 * a2 - 1.0) <= 1e-12)) return false;
+                // Rodrigues: R = cos I + sin [a]x + (1 - cos) a a^T, row-major
+                const double oc = 1.0 - ct;
+                double* R = out->post[k];
+                R[0] = ct + oc * a0 * a0;
+                R[1] = oc * a0 * a1 - st * a2;
+                R[2] = oc * a0 * a2 + st * a1;
+                R[3] = oc * a1 * a0 + st * a2;
+                R[4] = ct + oc * a1 * a1;
+                R[5] = oc * a1 * a2 - st * a0;
+                R[6] = oc * a2 * a0 - st * a1;
+                R[7] = oc * a2 * a1 + st * a0;
+                R[8] = ct + oc * a2 * a2;
+            }
             out->far2[k] = rho * rho;
         }
         out->id[k] = b.id;
@@ -170,6 +196,11 @@ static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* ou
         out->sdfA = c->sdft.sdfA;
         out->sdfB = c->sdft.sdfB;
         out->sdfDet = c->sdft.sdfDet;
+        for (int q = 0; q < 3; ++q) out->s3w[q] = c->sdft.s3w[q];
+        out->s3D1 = c->sdft.s3D1;
+        out->s3DX = c->sdft.s3DX;
+        out->s3A = c->sdft.s3A;
+        out->s3B = c->sdft.s3B;
         out->R[k] = b.radius;
         out->R2[k] = b.radius * b.radius;
     }

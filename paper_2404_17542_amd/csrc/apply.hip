@@ -185,8 +185,11 @@ __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const do
                     double gv[DIM];
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) gv[a] = pos_prev[a * Nc + c] - Bp.c[b][a];
-                    if constexpr (DIM == 2) {
-                        if (Bp.sdf[b]) sdf_psi(Bp, b, pos_prev[c], pos_prev[Nc + c], gv);
+                    if (Bp.sdf[b]) {
+                        double xp[DIM];
+#pragma unroll
+                        for (int a = 0; a < DIM; ++a) xp[a] = pos_prev[a * Nc + c];
+                        sdf_eval<DIM>(Bp, b, xp, gv);
                     }
 #pragma unroll
                     for (int a = 0; a < DIM; ++a) off[a] = gv[a] > 0.0 ? 1 : (gv[a] < 0.0 ? -1 : 0);

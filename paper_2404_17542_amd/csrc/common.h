@@ -35,13 +35,19 @@ struct BodiesDev {
     double dom[kMaxBodies][3];  // its backward difference over dt
     int rot[kMaxBodies];        // omega or domega non-zero
     int any_rot;
-    // discrete SDF bodies (2D, Sec. 2.5); sdf[k] == nullptr: circle/sphere
+    // discrete SDF bodies (Sec. 2.5); sdf[k] == nullptr: circle/sphere
     const double* sdf[kMaxBodies];
-    int sn[kMaxBodies][2];
-    double so[kMaxBodies][2];
+    int sn[kMaxBodies][3];
+    double so[kMaxBodies][3];
     double sh[kMaxBodies];
-    double cth[kMaxBodies], sth[kMaxBodies];
+    double cth[kMaxBodies], sth[kMaxBodies];   // 2D posture
+    double post[kMaxBodies][9];                // 3D posture R (row-major): x = c + R xi
     double far2[kMaxBodies];
+    // 3D closed form over the 3x3x3 nodes: weights of face, edge and corner
+    // nodes; D1 = sum w X^2, DX = sum w X^2 Y^2; the diagonal quadratic block
+    // is (A - B) I + B 11^T with A = D1 / 4, B = DX / 4
+    double s3w[3];
+    double s3D1, s3DX, s3A, s3B;
     // chi_c = 1 quadratic MLS over the 3x3 SDF nodes in closed form (the grid
     // is regular and symmetric, so the normal equations decouple):
     // g_q = sum_k sdfc[q][k] (psi_k - psi_centre) with sdfc = w_k p_q(X_k)
@@ -100,6 +106,86 @@ __device__ __forceinline__ double sdf_psi(const BodiesDev& B, int b, double x0, 
     g[0] = ct * gx - st * gy;
     g[1] = st * gx + ct * gy;
     return psi;
+}
+
+// 3D: the same rule over the 3x3x3 nodes, basis (X, Y, Z, X^2/2, Y^2/2,
+// Z^2/2, XY, YZ, ZX); on the symmetric support the linear and mixed terms
+// decouple (denominators D1 and DX) and the three squares solve
+// ((A - B) I + B 11^T) Phi = g, i.e. Phi_q = (g_q - B (g_0 + g_1 + g_2) /
+// (A + 2B)) / (A - B).  Node factors w_k p_q(X_k) are exact.
+__device__ __forceinline__ double sdf_psi3(const BodiesDev& B, int b, const double* x, double* g) {
+#pragma clang fp contract(off)
+    const double d0 = x[0] - B.c[b][0], d1 = x[1] - B.c[b][1], d2 = x[2] - B.c[b][2];
+    const double r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    if (r2 >= B.far2[b]) {
+        const double r = sqrt(r2);
+        g[0] = d0 / r;
+        g[1] = d1 / r;
+        g[2] = d2 / r;
+        return r - B.R[b];
+    }
+    const double* R = B.post[b];
+    const double h = B.sh[b];
+    // xi = R^T d
+    const double xi0 = R[0] * d0 + R[3] * d1 + R[6] * d2;
+    const double xi1 = R[1] * d0 + R[4] * d1 + R[7] * d2;
+    const double xi2 = R[2] * d0 + R[5] * d1 + R[8] * d2;
+    const double q0 = (xi0 - B.so[b][0]) / h, q1 = (xi1 - B.so[b][1]) / h, q2 = (xi2 - B.so[b][2]) / h;
+    const int n0 = B.sn[b][0], n1 = B.sn[b][1], n2 = B.sn[b][2];
+    int i = (int)floor(q0 + 0.5), j = (int)floor(q1 + 0.5), l = (int)floor(q2 + 0.5);
+    i = i < 1 ? 1 : (i > n0 - 2 ? n0 - 2 : i);
+    j = j < 1 ? 1 : (j > n1 - 2 ? n1 - 2 : j);
+    l = l < 1 ? 1 : (l > n2 - 2 ? n2 - 2 : l);
+    const double s0 = q0 - (double)i, s1 = q1 - (double)j, s2 = q2 - (double)l;
+    const double* __restrict__ S = B.sdf[b];
+    const size_t n01 = (size_t)n0 * n1;
+    const double ps = S[(size_t)l * n01 + (size_t)j * n0 + i];
+    double gq[9] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int dk = -1; dk <= 1; ++dk)
+#pragma unroll
+        for (int dj = -1; dj <= 1; ++dj)
+#pragma unroll
+            for (int di = -1; di <= 1; ++di) {
+                const int nz = (di != 0) + (dj != 0) + (dk != 0);
+                if (nz == 0) continue;
+                const double w = B.s3w[nz - 1];
+                const double X = di, Y = dj, Z = dk;
+                const double dv = S[(size_t)(l + dk) * n01 + (size_t)(j + dj) * n0 + (i + di)] - ps;
+                gq[0] = gq[0] + (w * X) * dv;
+                gq[1] = gq[1] + (w * Y) * dv;
+                gq[2] = gq[2] + (w * Z) * dv;
+                gq[3] = gq[3] + (w * (0.5 * X * X)) * dv;
+                gq[4] = gq[4] + (w * (0.5 * Y * Y)) * dv;
+                gq[5] = gq[5] + (w * (0.5 * Z * Z)) * dv;
+                gq[6] = gq[6] + (w * (X * Y)) * dv;
+                gq[7] = gq[7] + (w * (Y * Z)) * dv;
+                gq[8] = gq[8] + (w * (Z * X)) * dv;
+            }
+    const double P0 = gq[0] / B.s3D1, P1 = gq[1] / B.s3D1, P2 = gq[2] / B.s3D1;
+    const double tq = B.s3B * (gq[3] + gq[4] + gq[5]) / (B.s3A + 2.0 * B.s3B);
+    const double amb = B.s3A - B.s3B;
+    const double P3 = (gq[3] - tq) / amb, P4 = (gq[4] - tq) / amb, P5 = (gq[5] - tq) / amb;
+    const double P6 = gq[6] / B.s3DX, P7 = gq[7] / B.s3DX, P8 = gq[8] / B.s3DX;
+    const double psi = ps + (s0 * P0 + s1 * P1 + s2 * P2 + 0.5 * s0 * s0 * P3 + 0.5 * s1 * s1 * P4 +
+                             0.5 * s2 * s2 * P5 + s0 * s1 * P6 + s1 * s2 * P7 + s2 * s0 * P8);
+    const double gx = (P0 + s0 * P3 + s1 * P6 + s2 * P8) / h;
+    const double gy = (P1 + s1 * P4 + s0 * P6 + s2 * P7) / h;
+    const double gz = (P2 + s2 * P5 + s1 * P7 + s0 * P8) / h;
+    // g = R g_xi
+    g[0] = R[0] * gx + R[1] * gy + R[2] * gz;
+    g[1] = R[3] * gx + R[4] * gy + R[5] * gz;
+    g[2] = R[6] * gx + R[7] * gy + R[8] * gz;
+    return psi;
+}
+
+// psi and grad psi of discrete-SDF body b at the point x of a DIM mesh
+template <int DIM>
+__device__ __forceinline__ double sdf_eval(const BodiesDev& B, int b, const double* x, double* g) {
+    if constexpr (DIM == 2)
+        return sdf_psi(B, b, x[0], x[1], g);
+    else
+        return sdf_psi3(B, b, x, g);
 }
 
 // Velocity of a body point x (Eq. velocity_moving_boundary): V_trans + omega x r,

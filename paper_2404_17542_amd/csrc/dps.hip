@@ -42,12 +42,10 @@ __global__ __launch_bounds__(kBlock) void k_roles(MeshDev m, BodiesDev B, double
             for (int a = 0; a < DIM; ++a) vx[a] = m.origin[a] + (double)(ijk[a] + ((v >> a) & 1)) * m.l0;
             bool fluid = true;
             for (int b = 0; b < B.n; ++b) {
-                if constexpr (DIM == 2) {
-                    if (B.sdf[b]) {
-                        double g[2];
-                        fluid = fluid && (sdf_psi(B, b, vx[0], vx[1], g) >= 0.0);
-                        continue;
-                    }
+                if (B.sdf[b]) {
+                    double g[DIM];
+                    fluid = fluid && (sdf_eval<DIM>(B, b, vx, g) >= 0.0);
+                    continue;
                 }
                 double d2 = 0.0;
 #pragma unroll
@@ -71,12 +69,10 @@ __global__ __launch_bounds__(kBlock) void k_roles(MeshDev m, BodiesDev B, double
             for (int b = 0; b < B.n; ++b) {
                 double apsi;
                 bool done = false;
-                if constexpr (DIM == 2) {
-                    if (B.sdf[b]) {
-                        double g[2];
-                        apsi = fabs(sdf_psi(B, b, cen[0], cen[1], g));
-                        done = true;
-                    }
+                if (B.sdf[b]) {
+                    double g[DIM];
+                    apsi = fabs(sdf_eval<DIM>(B, b, cen, g));
+                    done = true;
                 }
                 if (!done) {
                     double d2 = 0.0;
@@ -208,17 +204,17 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
         const int rc = role[c];
         for (int b = 0; b < B.n; ++b) {
             if (rc != B.id[b]) continue;
-            if constexpr (DIM == 2) {
-                if (B.sdf[b]) {
-                    // x** = x* - psi grad psi / |grad psi|
-                    double g[2];
-                    const double psi = sdf_psi(B, b, xs[0], xs[1], g);
-                    const double gn = sqrt(g[0] * g[0] + g[1] * g[1]);
-                    const double t = psi / gn;
-                    xs[0] = xs[0] - t * g[0];
-                    xs[1] = xs[1] - t * g[1];
-                    continue;
-                }
+            if (B.sdf[b]) {
+                // x** = x* - psi grad psi / |grad psi|
+                double g[DIM];
+                const double psi = sdf_eval<DIM>(B, b, xs, g);
+                double g2 = g[0] * g[0];
+#pragma unroll
+                for (int a = 1; a < DIM; ++a) g2 = g2 + g[a] * g[a];
+                const double t = psi / sqrt(g2);
+#pragma unroll
+                for (int a = 0; a < DIM; ++a) xs[a] = xs[a] - t * g[a];
+                continue;
             }
             double dd[DIM];
 #pragma unroll
@@ -240,12 +236,13 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
                 // direction and its norm: (x - c, |x - c|), or (grad psi, |grad psi|)
                 double dd[DIM], r, psi;
                 bool done = false;
-                if constexpr (DIM == 2) {
-                    if (B.sdf[b]) {
-                        psi = sdf_psi(B, b, xs[0], xs[1], dd);
-                        r = sqrt(dd[0] * dd[0] + dd[1] * dd[1]);
-                        done = true;
-                    }
+                if (B.sdf[b]) {
+                    psi = sdf_eval<DIM>(B, b, xs, dd);
+                    double g2 = dd[0] * dd[0];
+#pragma unroll
+                    for (int a = 1; a < DIM; ++a) g2 = g2 + dd[a] * dd[a];
+                    r = sqrt(g2);
+                    done = true;
                 }
                 if (!done) {
 #pragma unroll
@@ -331,15 +328,18 @@ __global__ __launch_bounds__(kBlock) void k_normals(MeshDev m, BodiesDev B, cons
         } else if (r >= 1) {
             for (int b = 0; b < B.n; ++b) {
                 if (r != B.id[b]) continue;
-                if constexpr (DIM == 2) {
-                    if (B.sdf[b]) {
-                        double g[2];
-                        sdf_psi(B, b, pos[c], pos[Nc + c], g);
-                        const double gn = sqrt(g[0] * g[0] + g[1] * g[1]);
-                        nv[0] = g[0] / gn;
-                        nv[1] = g[1] / gn;
-                        continue;
-                    }
+                if (B.sdf[b]) {
+                    double xp[DIM], g[DIM];
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) xp[a] = pos[a * Nc + c];
+                    sdf_eval<DIM>(B, b, xp, g);
+                    double g2 = g[0] * g[0];
+#pragma unroll
+                    for (int a = 1; a < DIM; ++a) g2 = g2 + g[a] * g[a];
+                    const double gn = sqrt(g2);
+#pragma unroll
+                    for (int a = 0; a < DIM; ++a) nv[a] = g[a] / gn;
+                    continue;
                 }
                 double dd[DIM];
 #pragma unroll

@@ -201,6 +201,20 @@ def ellipse_sdf_grid(semi_a, semi_b, h, half_extent):
     return ellipse_distance(semi_a, semi_b, X, Y), (-m * h, -m * h), h
 
 
+def capsule_sdf_grid(half_length, radius, h, half_extent):
+    """Discrete SDF of a capsule (the points within `radius` of the segment
+    from (-half_length, 0, 0) to (half_length, 0, 0)) in its own frame: the
+    exact distance |p - clamp(p_x, -L, L) e_x| - radius at the nodes
+    -M h + (i, j, k) h, M = ceil(half_extent / h) + 1; returns
+    (values [nz][ny][nx], origin, h)."""
+    m = int(math.ceil(half_extent / h)) + 1
+    ax = -m * h + h * np.arange(2 * m + 1)
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    cx = np.clip(X, -half_length, half_length)
+    vals = np.sqrt((X - cx) ** 2 + Y ** 2 + Z ** 2) - radius
+    return vals, (-m * h, -m * h, -m * h), h
+
+
 def he_normal_params(shapes, seed, taps=9):
     """Seeded initial network parameters: for each (cin, cout) convolution of
     `taps` taps (9 in 2D, 27 in 3D), weights N(0, 2 / (taps cin)) of shape

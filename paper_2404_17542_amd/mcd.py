@@ -53,8 +53,9 @@ class Params(C.Structure):
 class Body(C.Structure):
     _fields_ = [("id", C.c_int), ("centre", C.c_double * 3), ("radius", C.c_double),
                 ("velocity", C.c_double * 3), ("dvdt", C.c_double * 3), ("omega", C.c_double * 3),
-                ("domega_dt", C.c_double * 3), ("theta", C.c_double), ("sdf", C.c_void_p),
-                ("sdf_n", C.c_int * 2), ("sdf_origin", C.c_double * 2), ("sdf_h", C.c_double)]
+                ("domega_dt", C.c_double * 3), ("theta", C.c_double), ("axis", C.c_double * 3),
+                ("sdf", C.c_void_p), ("sdf_n", C.c_int * 3), ("sdf_origin", C.c_double * 3),
+                ("sdf_h", C.c_double)]
 
 
 class BcTable(C.Structure):
@@ -192,15 +193,20 @@ def bodies_array(bodies):
             arr[k].omega[a] = w[a]
             arr[k].domega_dt[a] = dw[a]
         arr[k].theta = float(b.get("theta", 0.0))
+        ax = b.get("axis", (0.0, 0.0, 1.0))
+        for a in range(3):
+            arr[k].axis[a] = float(ax[a])
         g = b.get("sdf")
         if g is not None:
-            # a discrete SDF: a contiguous FP64 device tensor [ny][nx]
-            if not (isinstance(g, torch.Tensor) and g.is_cuda and g.dtype == torch.float64 and g.dim() == 2
+            # a discrete SDF: a contiguous FP64 device tensor [ny][nx] or [nz][ny][nx]
+            if not (isinstance(g, torch.Tensor) and g.is_cuda and g.dtype == torch.float64 and g.dim() in (2, 3)
                     and g.is_contiguous()):
-                raise ValueError("sdf must be a contiguous 2D float64 device tensor")
+                raise ValueError("sdf must be a contiguous 2D or 3D float64 device tensor")
             arr[k].sdf = g.data_ptr()
-            arr[k].sdf_n[0], arr[k].sdf_n[1] = int(g.shape[1]), int(g.shape[0])
-            arr[k].sdf_origin[0], arr[k].sdf_origin[1] = (float(v) for v in b["sdf_origin"])
+            shape = tuple(reversed(g.shape))
+            for a in range(len(shape)):
+                arr[k].sdf_n[a] = int(shape[a])
+                arr[k].sdf_origin[a] = float(b["sdf_origin"][a])
             arr[k].sdf_h = float(b["sdf_h"])
     return arr, n
 

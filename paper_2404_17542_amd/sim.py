@@ -104,7 +104,8 @@ class GpuSim:
                 dvdt = tuple((vn - vo) / self.case.dt for vn, vo in zip(vel, prev[i]["velocity"]))
                 dw = tuple((wn - wo) / self.case.dt for wn, wo in zip(w, prev[i]["omega"]))
             d = {"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius, "velocity": vel,
-                 "dvdt": dvdt, "omega": w, "domega_dt": dw, "theta": b.motion.theta(t)}
+                 "dvdt": dvdt, "omega": w, "domega_dt": dw, "theta": b.motion.theta(t),
+                 "axis": b.posture_axis()}
             if b.body_id in self.sdf:
                 g, o, h = self.sdf[b.body_id]
                 d.update(sdf=g, sdf_origin=o, sdf_h=h)

@@ -23,7 +23,7 @@ def gpu_bodies(case, t, dvdt=None):
     for b in case.rigid_bodies:
         d = {"id": b.body_id, "centre": b.motion.centre(t), "radius": b.radius,
              "velocity": b.motion.velocity(t), "dvdt": dvdt or (0.0,) * case.dim,
-             "omega": b.motion.omega_vector(t), "theta": b.motion.theta(t)}
+             "omega": b.motion.omega_vector(t), "theta": b.motion.theta(t), "axis": b.posture_axis()}
         g = b.sdf_grid(case.l0, case.band_over_l0)
         if g is not None:
             key = (case.name, b.body_id)

@@ -146,8 +146,8 @@ def test_ellipse_and_cylinder_together_match_oracle(M):
 
 
 def test_sdf_body_argument_checks(M):
-    """A grid whose inner nodes do not span the far radius, a non-contiguous
-    or host grid, and a discrete SDF on a 3D mesh are rejected."""
+    """A grid whose inner nodes do not span the far radius, a host grid and,
+    in 3D, a posture axis of other than unit length are rejected."""
     case = configs.c6_flapping_ellipse(n=128)
     ctx = M.Context.from_case(case)
     N = case.n_cells
@@ -169,7 +169,8 @@ def test_sdf_body_argument_checks(M):
         ctx.sync()
     except M.McdError:
         pass
-    case3 = configs.c4_moving_sphere(n=16)
+    # 3D: a posture axis that is not a unit vector
+    case3 = configs.c4_spinning_capsule(n=16)
     ctx3 = M.Context.from_case(case3)
     N3 = case3.n_cells
     pos3 = _dev(inputs.jittered_positions(case3.n, case3.origin, case3.l0, 1))
@@ -177,7 +178,34 @@ def test_sdf_body_argument_checks(M):
     z3 = [torch.zeros_like(pos3), torch.zeros_like(role3), torch.zeros((N3,), dtype=torch.uint8, device="cuda"),
           torch.zeros_like(pos3)]
     b3 = gpu_bodies(case3, 0.0)[0]
-    b3.update(sdf=good[0]["sdf"], sdf_origin=(-4.0, -4.0), sdf_h=0.5)
     with pytest.raises(M.McdError) as ei:
-        ctx3.update_dps([b3], 0, pos3, role3, z3[0], z3[1], z3[2], z3[3], info=False)
+        ctx3.update_dps([dict(b3, axis=(0.0, 0.6, 0.81))], 0, pos3, role3, z3[0], z3[1], z3[2], z3[3], info=False)
     assert ei.value.status == 1
+    ctx3.update_dps([b3], 0, pos3, role3, z3[0], z3[1], z3[2], z3[3], info=False)
+    try:
+        ctx3.sync()
+    except M.McdError:
+        pass
+
+
+def test_spinning_capsule_3d_matches_oracle(M):
+    """3D discrete-SDF body (a capsule turning about an oblique axis, 32^3):
+    DP arrays bit-exact over the initial arrangement and three whole steps
+    (with role changes), velocity within 1e-6 of the oracle."""
+    from paper_2404_17542_amd.sim import GpuSim
+    case = configs.c4_spinning_capsule(n=32, steps=3)
+    g = GpuSim(case)
+    o = OracleSim(case)
+    assert np.array_equal(np_(g.role), o.role) and (o.role == 2).sum() > 100
+    assert bits_equal(np_(g.pos), o.pos) and bits_equal(np_(g.normal), o.normal)
+    moved = 0
+    for _ in range(3):
+        rg = g.step()
+        ro = o.step()
+        assert rg["converged"] and rg["rel_res"] <= 1e-8
+        assert rg["trans"] == ro["trans"] and rg["sweeps"] == ro["sweeps"]
+        assert np.array_equal(np_(g.role), o.role)
+        assert bits_equal(np_(g.pos), o.pos) and bits_equal(np_(g.normal), o.normal)
+        moved += ro["trans"][5] + ro["trans"][7]
+    assert moved > 0
+    assert np.abs(np_(g.u) - o.u).max() / np.abs(o.u).max() < 1e-6

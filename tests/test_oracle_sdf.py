@@ -177,3 +177,112 @@ def test_closed_form_equals_the_weighted_least_squares_fit(kind, re):
         gref = np.array([phi[0] + s[0] * phi[2] + s[1] * phi[3], phi[1] + s[0] * phi[3] + s[1] * phi[4]]) / h
         assert abs(psi[k] - ref) < 1e-12
         assert abs(g[0][k] - gref[0]) < 1e-10 and abs(g[1][k] - gref[1]) < 1e-10
+
+
+# ---------------------------------------------------------------------------
+# 3D (the same rule over the 3x3x3 nodes, posture about an axis)
+# ---------------------------------------------------------------------------
+
+def _body3(values, origin, h, centre=(0.0, 0.0, 0.0), theta=0.0, axis=(0.0, 0.0, 1.0), radius=1.0, far=1e9,
+           kind="cos2", re=2.5):
+    g = O.SdfGrid(np.asarray(values, dtype=np.float64), origin, h, re, kind, far)
+    return O.BodyState(centre, radius, 2, (0.0, 0.0, 0.0), (0.0, 0.0, 0.0), theta, g, axis)
+
+
+def _grid3(n, h, f):
+    o = (-(n // 2) * h,) * 3
+    ax = o[0] + h * np.arange(n)
+    Z, Y, X = np.meshgrid(ax, ax, ax, indexing="ij")
+    return f(X, Y, Z), o
+
+
+def test_posture_matrix_is_the_rotation_about_the_axis():
+    rng = np.random.default_rng(6)
+    a = rng.standard_normal(3)
+    a /= np.linalg.norm(a)
+    th = 0.77
+    R = np.array(O.posture_matrix(th, a)).reshape(3, 3)
+    np.testing.assert_allclose(R @ R.T, np.eye(3), atol=1e-15)
+    assert abs(np.linalg.det(R) - 1.0) < 1e-14
+    np.testing.assert_allclose(R @ a, a, atol=1e-15)
+    u = np.cross(a, [1.0, 0.0, 0.0])
+    u /= np.linalg.norm(u)
+    assert abs(float(u @ (R @ u)) - math.cos(th)) < 1e-14        # turns by theta in the plane normal to a
+    Rz = np.array(O.posture_matrix(th, (0.0, 0.0, 1.0))).reshape(3, 3)
+    np.testing.assert_allclose(Rz[:2, :2], [[math.cos(th), -math.sin(th)], [math.sin(th), math.cos(th)]], atol=0)
+
+
+@pytest.mark.parametrize("kind", ["cos2", "gauss"])
+def test_quadratics_are_reproduced_in_3d(kind):
+    rng = np.random.default_rng(7)
+    cq = rng.standard_normal(10)
+
+    def q(X, Y, Z):
+        return (cq[0] + cq[1] * X + cq[2] * Y + cq[3] * Z + cq[4] * X * X + cq[5] * Y * Y + cq[6] * Z * Z
+                + cq[7] * X * Y + cq[8] * Y * Z + cq[9] * Z * X)
+
+    h = 0.1
+    vals, o = _grid3(17, h, q)
+    a = np.array([0.3, -0.5, 0.8])
+    a /= np.linalg.norm(a)
+    c, th = (0.2, -0.1, 0.3), 1.1
+    b = _body3(vals, o, h, c, th, tuple(a), kind=kind)
+    R = np.array(O.posture_matrix(th, a)).reshape(3, 3)
+    xi = rng.uniform(-0.55, 0.55, (3, 300))
+    x = np.array(c)[:, None] + R @ xi
+    psi, g = O.sdf_eval(b, x)
+    np.testing.assert_allclose(psi, q(*xi), rtol=0, atol=1e-12)
+    gxi = np.stack([cq[1] + 2 * cq[4] * xi[0] + cq[7] * xi[1] + cq[9] * xi[2],
+                    cq[2] + 2 * cq[5] * xi[1] + cq[7] * xi[0] + cq[8] * xi[2],
+                    cq[3] + 2 * cq[6] * xi[2] + cq[8] * xi[1] + cq[9] * xi[0]])
+    np.testing.assert_allclose(np.array(g), R @ gxi, rtol=0, atol=1e-10)
+
+
+def test_3d_closed_form_equals_the_weighted_least_squares_fit():
+    rng = np.random.default_rng(8)
+    vals = rng.standard_normal((6, 6, 6))
+    h, re = 0.1, 2.5
+    b = _body3(vals, (-0.25, -0.25, -0.25), h, re=re)
+    pts = rng.uniform(-0.1, 0.1, (3, 30))
+    psi, g = O.sdf_eval(b, pts)
+    for k in range(pts.shape[1]):
+        q = (pts[:, k] + 0.25) / h
+        i, j, l = (int(np.floor(v + 0.5)) for v in q)
+        rows, rhs = [], []
+        for dk in (-1, 0, 1):
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    if di == dj == dk == 0:
+                        continue
+                    w = float(O.weight(math.sqrt(di * di + dj * dj + dk * dk), re, "cos2"))
+                    rows.append(math.sqrt(w) * np.array([di, dj, dk, 0.5 * di * di, 0.5 * dj * dj, 0.5 * dk * dk,
+                                                         di * dj, dj * dk, dk * di]))
+                    rhs.append(math.sqrt(w) * (vals[l + dk, j + dj, i + di] - vals[l, j, i]))
+        phi = np.linalg.lstsq(np.array(rows), np.array(rhs), rcond=None)[0]
+        s = q - np.array([i, j, l])
+        p = np.array([s[0], s[1], s[2], 0.5 * s[0] ** 2, 0.5 * s[1] ** 2, 0.5 * s[2] ** 2, s[0] * s[1], s[1] * s[2],
+                      s[2] * s[0]])
+        assert abs(psi[k] - (vals[l, j, i] + phi @ p)) < 1e-12
+
+
+def test_3d_sampled_sphere_converges_and_capsule_sdf_closed_forms():
+    R0 = 0.4
+    rng = np.random.default_rng(9)
+    d = rng.standard_normal((3, 300))
+    d /= np.linalg.norm(d, axis=0)
+    rad = rng.uniform(0.3, 0.6, 300)
+    x = d * rad
+    errs = []
+    for h in (0.05, 0.025):
+        n = int(round(1.6 / h)) + 1
+        vals, o = _grid3(n, h, lambda X, Y, Z: np.sqrt(X * X + Y * Y + Z * Z) - R0)
+        psi, _ = O.sdf_eval(_body3(vals, o, h, theta=0.3, axis=(0.0, 0.6, 0.8)), x)
+        errs.append(np.abs(psi - (rad - R0)).max())
+    assert errs[0] / errs[1] > 5.0, errs
+    vals, o, h = inputs.capsule_sdf_grid(0.12, 0.06, 0.01, 0.3)
+    ax = o[0] + h * np.arange(vals.shape[0])
+    i0 = int(np.argmin(np.abs(ax)))
+    assert abs(vals[i0, i0, i0] + 0.06) < 1e-15                       # centre: -radius
+    i1 = int(np.argmin(np.abs(ax - 0.2)))
+    assert abs(vals[i0, i0, i1] - (ax[i1] - 0.12 - 0.06)) < 1e-15      # beyond the cap along x
+    assert abs(vals[i1, i0, i0] - (ax[i1] - 0.06)) < 1e-15             # off the axis along z
