@@ -190,20 +190,21 @@ static bool make_bodies(mcd_ctx* c, const mcd_body* bodies, int n, BodiesDev* ou
             if (b.omega[a] != 0.0 || b.domega_dt[a] != 0.0) out->rot[k] = 1;
         }
         out->any_rot |= out->rot[k];
-        memcpy(out->sdfc, c->sdft.sdfc, sizeof(out->sdfc));
-        out->sdfD1 = c->sdft.sdfD1;
-        out->sdfD3 = c->sdft.sdfD3;
-        out->sdfA = c->sdft.sdfA;
-        out->sdfB = c->sdft.sdfB;
-        out->sdfDet = c->sdft.sdfDet;
-        for (int q = 0; q < 3; ++q) out->s3w[q] = c->sdft.s3w[q];
-        out->s3D1 = c->sdft.s3D1;
-        out->s3DX = c->sdft.s3DX;
-        out->s3A = c->sdft.s3A;
-        out->s3B = c->sdft.s3B;
         out->R[k] = b.radius;
         out->R2[k] = b.radius * b.radius;
     }
+    // the context's discrete-SDF interpolation constants
+    memcpy(out->sdfc, c->sdft.sdfc, sizeof(out->sdfc));
+    out->sdfD1 = c->sdft.sdfD1;
+    out->sdfD3 = c->sdft.sdfD3;
+    out->sdfA = c->sdft.sdfA;
+    out->sdfB = c->sdft.sdfB;
+    out->sdfDet = c->sdft.sdfDet;
+    for (int q = 0; q < 3; ++q) out->s3w[q] = c->sdft.s3w[q];
+    out->s3D1 = c->sdft.s3D1;
+    out->s3DX = c->sdft.s3DX;
+    out->s3A = c->sdft.s3A;
+    out->s3B = c->sdft.s3B;
     return true;
 }
 

@@ -33,7 +33,8 @@ __global__ __launch_bounds__(kBlock) void k_roles(MeshDev m, BodiesDev B, double
             x[a] = pos[a * Nc + c];
             pos_prev[a * Nc + c] = x[a];
         }
-        // vertices with psi >= 0 (outside every body): |v - c|^2 >= R^2
+        // vertices with psi >= 0 (outside every body): |v - c|^2 >= R^2 for a
+        // circle/sphere, the interpolated psi for a discrete SDF
         int count = 0;
 #pragma unroll
         for (int v = 0; v < (1 << DIM); ++v) {

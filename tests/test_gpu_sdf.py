@@ -209,3 +209,54 @@ def test_spinning_capsule_3d_matches_oracle(M):
         moved += ro["trans"][5] + ro["trans"][7]
     assert moved > 0
     assert np.abs(np_(g.u) - o.u).max() / np.abs(o.u).max() < 1e-6
+
+
+def test_sampled_circle_on_the_gpu_matches_the_analytic_circle(M):
+    """Full-size property: the 1024^2 cylinder given as a sampled SDF (h =
+    l0/2) and as the analytic circle give the same masks, except cells with
+    a vertex within the interpolation error of the circle, and boundary DPs
+    of both arrangements lie on the circle to within that error."""
+    case = configs.c2_oscillating_cylinder(n=1024)
+    l0 = case.l0
+    N = case.n_cells
+    R = case.body.radius
+    h = 0.5 * l0
+    rho = R + (case.band_over_l0 + 2.0) * l0
+    m_ = int(np.ceil((rho + h) / h)) + 1
+    ax = -m_ * h + h * np.arange(2 * m_ + 1)
+    X, Y = np.meshgrid(ax, ax)
+    grid = torch.tensor(np.hypot(X, Y) - R, dtype=torch.float64, device="cuda").contiguous()
+    pos0 = inputs.jittered_positions(case.n, case.origin, l0, case.jitter_seed)
+    out = {}
+    for kind in ("analytic", "sampled"):
+        ctx = M.Context.from_case(case)
+        pos = _dev(pos0)
+        role = torch.full((N,), -1, dtype=torch.int8, device="cuda")
+        z = [torch.zeros_like(pos), torch.zeros_like(role), torch.zeros((N,), dtype=torch.uint8, device="cuda"),
+             torch.zeros_like(pos)]
+        b = gpu_bodies(case, 0.0)
+        if kind == "sampled":
+            b[0].update(sdf=grid, sdf_origin=(-m_ * h, -m_ * h), sdf_h=h, theta=0.37)
+        ctx.update_dps(b, 0, pos, role, z[0], z[1], z[2], z[3], info=False)
+        try:
+            ctx.sync()
+        except M.McdError:
+            pass
+        ctx.update_dps(b, 100, pos, role, z[0], z[1], z[2], z[3])
+        out[kind] = (np_(role), np_(pos))
+    ra, rs = out["analytic"][0], out["sampled"][0]
+    c = np.array(case.body.motion.centre(0.0))
+    ii = np.arange(N)
+    vx = [case.origin[0] + (ii % case.n[0] + d) * l0 for d in (0, 1)]
+    vy = [case.origin[1] + (ii // case.n[0] + d) * l0 for d in (0, 1)]
+    near = np.zeros(N, dtype=bool)
+    for x in vx:
+        for y in vy:
+            near |= np.abs(np.hypot(x - c[0], y - c[1]) - R) < 1e-4 * l0
+    diff = ra != rs
+    assert np.all(near[diff]) and (ra == 2).sum() > 300
+    for kind in ("analytic", "sampled"):
+        role, pos = out[kind]
+        sel = role == 2
+        dist = np.hypot(pos[0, sel] - c[0], pos[1, sel] - c[1]) - R
+        assert np.abs(dist).max() < 0.1 * l0      # on the circle unless clamped to the cell
