@@ -212,6 +212,8 @@ def main():
     ap.add_argument("--weights", default=None, help="network weights for --guess learned")
     ap.add_argument("--precond", choices=["none", "jacobi"], default="none",
                     help="none: the plain method (default); jacobi: diagonal right preconditioning")
+    ap.add_argument("--no-step-graph", action="store_true",
+                    help="issue the calls around the PPE solve one by one instead of as recorded HIP graphs")
     ap.add_argument("--no-autotune", action="store_true",
                     help="keep the default stage-kernel shape instead of timing the candidates after warm-up")
     ap.add_argument("--cpu-steps", type=int, default=4)
@@ -247,7 +249,8 @@ def main():
     prec = getattr(mcd, prec_name)
     log(f"setting up {case.name}")
     sim = GpuSim(case, precision=prec, update_info=False,
-                 precond=mcd.PRECOND_JACOBI if args.precond == "jacobi" else mcd.PRECOND_NONE)
+                 precond=mcd.PRECOND_JACOBI if args.precond == "jacobi" else mcd.PRECOND_NONE,
+                 graph=not args.no_step_graph)
     if args.guess == "learned":
         if not args.weights:
             raise SystemExit("--guess learned needs --weights (written by paper_2404_17542_amd.learned)")
@@ -309,6 +312,7 @@ def main():
                       "dps": n_active, "precision": args.precision, "initial_guess": args.guess,
                       "preconditioner": args.precond,
                       "stage_shape": sim.ctx.get_shape(), "autotuned": tune is not None,
+                      "step_graphs": sim.graph,
                       "ppe_iters_per_step": sum(iters) / len(iters), "max_true_rel_res": worst},
            "roofline": roofline}
     if args.precision != "fp64" or args.guess != "warm" or args.precond != "none":

@@ -62,6 +62,7 @@ enum { MCD_PRECOND_NONE = 0, MCD_PRECOND_JACOBI = 1 };
 #define MCD_MAX_IDS 16      /* boundary ids 1 .. 15 */
 #define MCD_MAX_BODIES 8
 #define MCD_MAX_SETS 4      /* stencil-set slots held by a context */
+#define MCD_MAX_GRAPHS 4    /* captured-sequence slots held by a context */
 
 /* Background mesh (Sec. 2.2): uniform spacing l0, dim in {2, 3}. */
 typedef struct {
@@ -460,6 +461,33 @@ mcd_status mcd_profile(mcd_ctx* ctx, int enable);
  * launches since the last reset (all host pointers). */
 mcd_status mcd_profile_read(mcd_ctx* ctx, double* ms_p, long long* n_p, double* ms_s, long long* n_s,
                             int reset);
+
+/* ---------------------------------------------------------------------
+ * Captured call sequences (HIP graphs): the parts of a time step around
+ * the PPE solve as one graph launch each
+ * ------------------------------------------------------------------- */
+
+/* Starts recording into graph slot `slot` (0 .. MCD_MAX_GRAPHS-1): the
+ * calls on this context that follow are recorded on a private stream, not
+ * run, until mcd_graph_end.  Recordable are the calls that only enqueue
+ * device work: mcd_update_dps with info = NULL, mcd_build_stencils,
+ * mcd_get_stencils, mcd_apply, mcd_remap, mcd_advect_diffuse,
+ * mcd_neumann_pressure, mcd_project.  The others return MCD_ERR_ARG while a
+ * capture is open (mcd_sync, mcd_solve_ppe, mcd_ppe_residual,
+ * mcd_fluid_force, mcd_autotune, mcd_set_shape, mcd_profile*, the model
+ * calls, mcd_set_stream, mcd_update_dps with info).  Arrays passed to the
+ * recorded calls must stay valid until the graph has run.  Errors:
+ * MCD_ERR_ARG (bad slot, a capture already open), MCD_ERR_HIP. */
+mcd_status mcd_graph_begin(mcd_ctx* ctx, int slot);
+/* Ends the recording of `slot` and launches it on the context's stream.
+ * The first recording of a slot is instantiated; a later one with the same
+ * sequence of calls (arguments may differ) updates that executable graph in
+ * place, any other replaces it.  If a recorded call failed, nothing runs and
+ * MCD_ERR_ARG is returned (with that call's message).  Device-side results
+ * are those of the same calls made directly, bit for bit. */
+mcd_status mcd_graph_end(mcd_ctx* ctx, int slot);
+/* How often slot's graph was instantiated and updated in place (host ints). */
+mcd_status mcd_graph_stats(mcd_ctx* ctx, int slot, int* instantiated, int* updated);
 
 #ifdef __cplusplus
 }

@@ -51,6 +51,14 @@ struct mcd_ctx {
     FitDev fit{0.0, 0.0, 0.0};
     BodiesDev sdft{};           // discrete-SDF interpolation constants (sdfc, sdfD1 ...)
     bool sdf_ok = false;
+    // captured call sequences (mcd_graph_begin/end): the calls of a capture are
+    // recorded on a private stream and launched as one graph on `stream`
+    hipStream_t cap_st = nullptr;
+    hipStream_t user_st = nullptr;
+    int capturing = -1;
+    bool cap_failed = false;
+    hipGraphExec_t gexec[MCD_MAX_GRAPHS] = {};
+    int g_inst[MCD_MAX_GRAPHS] = {}, g_upd[MCD_MAX_GRAPHS] = {};
     std::string err;
 };
 
@@ -110,14 +118,24 @@ static mcd_status fail(mcd_ctx* c, mcd_status s, const char* fmt, const char* de
         char buf[512];
         snprintf(buf, sizeof(buf), fmt, detail);
         c->err = buf;
+        if (c->capturing >= 0) c->cap_failed = true;   // the recorded sequence is incomplete
     }
     return s;
 }
 
 static mcd_status hipfail(mcd_ctx* c, hipError_t e, const char* where) {
-    if (c) c->err = std::string(where) + ": " + hipGetErrorString(e);
+    if (c) {
+        c->err = std::string(where) + ": " + hipGetErrorString(e);
+        if (c->capturing >= 0) c->cap_failed = true;
+    }
     return MCD_ERR_HIP;
 }
+
+// calls that wait for the device (or read results back) cannot be recorded
+#define NO_CAPTURE(ctx, name)                                                              \
+    do {                                                                                   \
+        if ((ctx)->capturing >= 0) return fail(ctx, MCD_ERR_ARG, name ": not allowed while a graph is captured%s"); \
+    } while (0)
 
 #define HIPCHK(ctx, expr, where)                    \
     do {                                            \
@@ -316,7 +334,16 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
 
 void mcd_destroy(mcd_ctx* c) {
     if (!c) return;
+    if (c->capturing >= 0) {
+        hipGraph_t g = nullptr;
+        (void)hipStreamEndCapture(c->cap_st, &g);
+        if (g) (void)hipGraphDestroy(g);
+        c->stream = c->user_st;
+    }
     (void)hipStreamSynchronize(c->stream);
+    for (int k = 0; k < MCD_MAX_GRAPHS; ++k)
+        if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
     for (int s = 0; s < MCD_MAX_SETS; ++s) {
         SetDev& d = c->sets[s].dev;
         void* ptrs[6] = {d.phi, d.vmask, d.nmask, d.amat, d.amat32, d.unknown};
@@ -333,6 +360,7 @@ void mcd_destroy(mcd_ctx* c) {
 
 mcd_status mcd_set_stream(mcd_ctx* c, void* hip_stream) {
     if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_set_stream");
     c->stream = (hipStream_t)hip_stream;
     return MCD_OK;
 }
@@ -341,6 +369,7 @@ const char* mcd_last_error(const mcd_ctx* c) { return c ? c->err.c_str() : "null
 
 mcd_status mcd_sync(mcd_ctx* c) {
     if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_sync");
     HIPCHK(c, hipStreamSynchronize(c->stream), "mcd_sync");
     HIPCHK(c, hipMemcpy(c->cnt_host, c->cnt, CNT_N * sizeof(int), hipMemcpyDeviceToHost), "mcd_sync copy");
     const int role_err = c->cnt_host[CNT_LATCH_ROLE], sing = c->cnt_host[CNT_LATCH_SING];
@@ -367,6 +396,7 @@ mcd_status mcd_update_dps(mcd_ctx* c, const mcd_body* bodies, int n_bodies, int 
         return fail(c, MCD_ERR_ARG, "mcd_update_dps: null array%s");
     if (max_sweeps < 0 || max_sweeps > c->max_sweeps_alloc)
         return fail(c, MCD_ERR_ARG, "mcd_update_dps: max_sweeps out of range%s");
+    if (info) NO_CAPTURE(c, "mcd_update_dps with info");
     BodiesDev B;
     if (!make_bodies(c, bodies, n_bodies, &B)) return fail(c, MCD_ERR_ARG, "mcd_update_dps: invalid bodies%s");
     const MeshDev& m = c->m;
@@ -556,6 +586,7 @@ mcd_status mcd_fluid_force(mcd_ctx* c, int set_u, int set_p, const double* u, co
                            const double* neumann_f, const double* pos, const int8_t* role, const double* normal,
                            const mcd_body* bodies, int n_bodies, double mu, double* force, int* counts) {
     if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_fluid_force");
     if (c->dim != 2) return fail(c, MCD_ERR_ARG, "mcd_fluid_force: 2D meshes only%s");
     if (!valid_set(c, set_u, true) || !valid_set(c, set_p, true))
         return fail(c, MCD_ERR_ARG, "mcd_fluid_force: set not built%s");
@@ -591,6 +622,7 @@ mcd_status mcd_fluid_force(mcd_ctx* c, int set_u, int set_p, const double* u, co
 mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* neumann_f, double* p,
                          const mcd_solve_opts* opts, mcd_solve_info* info) {
     if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_solve_ppe");
     if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: set not built%s");
     if (!rhs || !p || !opts || !info) return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: null argument%s");
     if (!(opts->tol > 0) || opts->max_iter < 1 ||
@@ -627,6 +659,7 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
 mcd_status mcd_ppe_residual(mcd_ctx* c, int set, const double* rhs, const double* neumann_f, const double* p,
                             double* r, double* norms) {
     if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_ppe_residual");
     if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual: set not built%s");
     if (!rhs || !p || !r) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual: null argument%s");
     HIPCHK(c, launch_fill_i32(c->cnt + CNT_BAD, 1, 0, c->stream), "fill");
@@ -654,6 +687,7 @@ struct mcd_model {
 
 mcd_status mcd_model_create(mcd_ctx* c, int levels, const int* channels, int body_id, mcd_model** out) {
     if (!c || !channels || !out) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_model_create");
     *out = nullptr;
     if (levels < 2 || levels > 5) return fail(c, MCD_ERR_ARG, "mcd_model_create: levels must be 2..5%s");
     const int H = c->m.n[1], W = c->m.n[0], D = c->dim == 3 ? c->m.n[2] : 1;
@@ -685,6 +719,7 @@ size_t mcd_model_num_params(const mcd_model* md) { return md ? unet_nparams(*md-
 
 mcd_status mcd_model_set_params(mcd_model* md, const float* theta, size_t n) {
     if (!md || !theta || n != unet_nparams(*md->net)) return MCD_ERR_ARG;
+    NO_CAPTURE(md->ctx, "mcd_model_set_params");
     mcd_ctx* c = md->ctx;
     HIPCHK(c, hipMemcpyAsync(unet_theta(*md->net), theta, n * 4, hipMemcpyHostToDevice, c->stream), "set_params");
     HIPCHK(c, unet_weights_to_bf16(*md->net, c->stream), "set_params");
@@ -695,6 +730,7 @@ mcd_status mcd_model_set_params(mcd_model* md, const float* theta, size_t n) {
 
 mcd_status mcd_model_get_params(mcd_model* md, float* theta, size_t n) {
     if (!md || !theta || n != unet_nparams(*md->net)) return MCD_ERR_ARG;
+    NO_CAPTURE(md->ctx, "mcd_model_get_params");
     mcd_ctx* c = md->ctx;
     HIPCHK(c, hipStreamSynchronize(c->stream), "get_params");
     HIPCHK(c, hipMemcpy(theta, unet_theta(*md->net), n * 4, hipMemcpyDeviceToHost), "get_params");
@@ -703,6 +739,7 @@ mcd_status mcd_model_get_params(mcd_model* md, float* theta, size_t n) {
 
 mcd_status mcd_model_get_grads(mcd_model* md, float* grad, size_t n) {
     if (!md || !grad || n != unet_nparams(*md->net)) return MCD_ERR_ARG;
+    NO_CAPTURE(md->ctx, "mcd_model_get_grads");
     mcd_ctx* c = md->ctx;
     HIPCHK(c, hipStreamSynchronize(c->stream), "get_grads");
     HIPCHK(c, hipMemcpy(grad, unet_grad(*md->net), n * 4, hipMemcpyDeviceToHost), "get_grads");
@@ -711,6 +748,7 @@ mcd_status mcd_model_get_grads(mcd_model* md, float* grad, size_t n) {
 
 mcd_status mcd_model_output(mcd_model* md, float* h) {
     if (!md || !h) return MCD_ERR_ARG;
+    NO_CAPTURE(md->ctx, "mcd_model_output");
     mcd_ctx* c = md->ctx;
     HIPCHK(c, hipMemcpyAsync(h, unet_head_out(*md->net), c->Nc * 4, hipMemcpyDeviceToDevice, c->stream), "output");
     return MCD_OK;
@@ -718,6 +756,7 @@ mcd_status mcd_model_output(mcd_model* md, float* h) {
 
 mcd_status mcd_model_set_output_scale(mcd_model* md, double s) {
     if (!md) return MCD_ERR_ARG;
+    NO_CAPTURE(md->ctx, "mcd_model_set_output_scale");
     if (!(s > 0) || !isfinite(s)) return fail(md->ctx, MCD_ERR_ARG, "mcd_model_set_output_scale: s must be > 0%s");
     unet_set_output_scale(*md->net, s);
     return MCD_OK;
@@ -726,6 +765,7 @@ mcd_status mcd_model_set_output_scale(mcd_model* md, double s) {
 mcd_status mcd_model_infer(mcd_model* md, const double* rhs, const double* p_prev, const int8_t* role,
                            const mcd_bc_table* bc, double* p_out) {
     if (!md || !rhs || !p_prev || !role || !p_out) return MCD_ERR_ARG;
+    NO_CAPTURE(md->ctx, "mcd_model_infer");
     mcd_ctx* c = md->ctx;
     BcDev b;
     if (!make_bc(bc, &b)) return fail(c, MCD_ERR_ARG, "mcd_model_infer: invalid bc table%s");
@@ -736,6 +776,7 @@ mcd_status mcd_model_infer(mcd_model* md, const double* rhs, const double* p_pre
 mcd_status mcd_model_train_step(mcd_model* md, const double* rhs, const double* p_prev, const double* p_target,
                                 const int8_t* role, const mcd_bc_table* bc, double lr, double* loss) {
     if (!md || !rhs || !p_prev || !p_target || !role) return MCD_ERR_ARG;
+    NO_CAPTURE(md->ctx, "mcd_model_train_step");
     mcd_ctx* c = md->ctx;
     BcDev b;
     if (!make_bc(bc, &b)) return fail(c, MCD_ERR_ARG, "mcd_model_train_step: invalid bc table%s");
@@ -747,6 +788,7 @@ mcd_status mcd_model_train_step(mcd_model* md, const double* rhs, const double* 
 
 mcd_status mcd_autotune(mcd_ctx* c, int set, int iters, mcd_tuning* out) {
     if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_autotune");
     if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_autotune: set not built%s");
     if (!out || iters < 1 || iters > 100000) return fail(c, MCD_ERR_ARG, "mcd_autotune: invalid arguments%s");
     *out = mcd_tuning{};
@@ -760,6 +802,7 @@ mcd_status mcd_autotune(mcd_ctx* c, int set, int iters, mcd_tuning* out) {
 
 mcd_status mcd_set_shape(mcd_ctx* c, int grid, int depth) {
     if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_set_shape");
     const hipError_t e = krylov_set_shape(c->m, *c->kw, grid, depth);
     if (e == hipErrorInvalidValue) return fail(c, MCD_ERR_ARG, "mcd_set_shape: shape outside the limits%s");
     HIPCHK(c, e, "set_shape");
@@ -775,13 +818,81 @@ mcd_status mcd_get_shape(mcd_ctx* c, int* grid, int* depth, int* blocks) {
 
 mcd_status mcd_profile(mcd_ctx* c, int enable) {
     if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_profile");
     HIPCHK(c, krylov_profile(c->kw, enable ? 1 : 0), "mcd_profile");
     return MCD_OK;
 }
 
 mcd_status mcd_profile_read(mcd_ctx* c, double* ms_p, long long* n_p, double* ms_s, long long* n_s, int reset) {
     if (!c || !ms_p || !n_p || !ms_s || !n_s) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_profile_read");
     krylov_profile_read(c->kw, ms_p, n_p, ms_s, n_s, reset);
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_begin(mcd_ctx* c, int slot) {
+    if (!c) return MCD_ERR_ARG;
+    if (slot < 0 || slot >= MCD_MAX_GRAPHS) return fail(c, MCD_ERR_ARG, "mcd_graph_begin: slot out of range%s");
+    NO_CAPTURE(c, "mcd_graph_begin");
+    if (!c->cap_st) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking), "capture stream");
+    HIPCHK(c, hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal), "mcd_graph_begin");
+    c->user_st = c->stream;
+    c->stream = c->cap_st;
+    c->capturing = slot;
+    c->cap_failed = false;
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_end(mcd_ctx* c, int slot) {
+    if (!c) return MCD_ERR_ARG;
+    if (c->capturing < 0 || slot != c->capturing)
+        return fail(c, MCD_ERR_ARG, "mcd_graph_end: no capture of this slot is open%s");
+    hipGraph_t g = nullptr;
+    const hipError_t ec = hipStreamEndCapture(c->cap_st, &g);
+    c->stream = c->user_st;
+    c->capturing = -1;
+    if (ec != hipSuccess || c->cap_failed || !g) {
+        if (g) (void)hipGraphDestroy(g);
+        const bool failed = c->cap_failed;
+        c->cap_failed = false;
+        if (failed) {
+            c->err = "mcd_graph_end: a call failed while the graph was captured (" + c->err + "); nothing was run";
+            return MCD_ERR_ARG;
+        }
+        return hipfail(c, ec != hipSuccess ? ec : hipErrorInvalidValue, "mcd_graph_end");
+    }
+    hipError_t e = hipErrorInvalidValue;
+    if (c->gexec[slot]) {
+        // same sequence of calls as the slot's executable graph: update it in place
+        hipGraphNode_t bad = nullptr;
+        hipGraphExecUpdateResult res;
+        e = hipGraphExecUpdate(c->gexec[slot], g, &bad, &res);
+        if (e == hipSuccess && res == hipGraphExecUpdateSuccess) {
+            c->g_upd[slot]++;
+        } else {
+            (void)hipGetLastError();
+            (void)hipGraphExecDestroy(c->gexec[slot]);
+            c->gexec[slot] = nullptr;
+            e = hipErrorInvalidValue;
+        }
+    }
+    if (!c->gexec[slot]) {
+        e = hipGraphInstantiate(&c->gexec[slot], g, nullptr, nullptr, 0);
+        if (e != hipSuccess) c->gexec[slot] = nullptr;
+        else c->g_inst[slot]++;
+    }
+    (void)hipGraphDestroy(g);
+    HIPCHK(c, e, "mcd_graph_end instantiate");
+    HIPCHK(c, hipGraphLaunch(c->gexec[slot], c->stream), "mcd_graph_end launch");
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_stats(mcd_ctx* c, int slot, int* instantiated, int* updated) {
+    if (!c) return MCD_ERR_ARG;
+    if (slot < 0 || slot >= MCD_MAX_GRAPHS || !instantiated || !updated)
+        return fail(c, MCD_ERR_ARG, "mcd_graph_stats: bad argument%s");
+    *instantiated = c->g_inst[slot];
+    *updated = c->g_upd[slot];
     return MCD_OK;
 }
 

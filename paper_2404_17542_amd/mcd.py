@@ -36,7 +36,7 @@ EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last
             "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
             "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_set_output_scale",
             "mcd_model_infer",
-            "mcd_model_train_step")
+            "mcd_model_train_step", "mcd_graph_begin", "mcd_graph_end", "mcd_graph_stats")
 
 
 class MeshDesc(C.Structure):
@@ -121,6 +121,9 @@ def load():
         "mcd_solve_ppe": (i, [vp, i, vp, vp, vp, P(SolveOpts), P(SolveInfo)]),
         "mcd_ppe_residual": (i, [vp, i, vp, vp, vp, vp, P(d)]),
         "mcd_profile": (i, [vp, i]),
+        "mcd_graph_begin": (i, [vp, i]),
+        "mcd_graph_end": (i, [vp, i]),
+        "mcd_graph_stats": (i, [vp, i, P(i), P(i)]),
         "mcd_model_create": (i, [vp, i, P(i), i, P(vp)]),
         "mcd_model_destroy": (None, [vp]),
         "mcd_model_num_params": (C.c_size_t, [vp]),
@@ -416,6 +419,21 @@ class Context:
         g, dp, b = C.c_int(), C.c_int(), C.c_int()
         self._check(self.lib.mcd_get_shape(self.h, C.byref(g), C.byref(dp), C.byref(b)), "mcd_get_shape")
         return {"grid": g.value, "depth": dp.value, "blocks": b.value}
+
+    def graph_begin(self, slot):
+        """Start recording the following calls into graph slot `slot` (see
+        mcd_graph_begin); they run at graph_end."""
+        self._check(self.lib.mcd_graph_begin(self.h, int(slot)), "mcd_graph_begin")
+
+    def graph_end(self, slot):
+        """Stop recording and launch the slot's graph (instantiated the first
+        time, updated in place later)."""
+        self._check(self.lib.mcd_graph_end(self.h, int(slot)), "mcd_graph_end")
+
+    def graph_stats(self, slot):
+        a, b = C.c_int(), C.c_int()
+        self._check(self.lib.mcd_graph_stats(self.h, int(slot), C.byref(a), C.byref(b)), "mcd_graph_stats")
+        return {"instantiated": a.value, "updated": b.value}
 
     def profile(self, enable=True):
         self._check(self.lib.mcd_profile(self.h, int(bool(enable))), "mcd_profile")

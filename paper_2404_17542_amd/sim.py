@@ -26,8 +26,11 @@ SET_P = 2
 
 class GpuSim:
     def __init__(self, case, precision=M.PREC_FP64, device="cuda", check_every=16, update_info=True,
-                 guess="warm", model=None, precond=M.PRECOND_NONE):
+                 guess="warm", model=None, precond=M.PRECOND_NONE, graph=False):
+        if graph and update_info:
+            raise ValueError("graph mode records the DP update without its host-side info: pass update_info=False")
         self.case = case
+        self.graph = graph
         self.guess = guess
         self.precond = precond
         self.model = model
@@ -114,7 +117,23 @@ class GpuSim:
 
     def prepare(self):
         """First half of a step: DP update at t^{k+1}, remap, weights, u* and
-        the PPE data.  Leaves (pset, bodies_new, update info)."""
+        the PPE data.  Leaves (pset, bodies_new, update info).  In graph mode
+        these calls are recorded and launched as one graph (slot 0)."""
+        if not self.graph:
+            return self._prepare()
+        self.ctx.graph_begin(0)
+        try:
+            out = self._prepare()
+        except BaseException:
+            try:
+                self.ctx.graph_end(0)
+            except M.McdError:
+                pass
+            raise
+        self.ctx.graph_end(0)
+        return out
+
+    def _prepare(self):
         case, ctx = self.case, self.ctx
         tn = (self.k + 1) * case.dt
         bodies_new = self.bodies_at(tn, self.bodies) if self.bodies else []
@@ -172,7 +191,11 @@ class GpuSim:
 
     def finish(self, pset, bodies_new, info, upd):
         case = self.case
+        if self.graph:
+            self.ctx.graph_begin(1)
         self.ctx.project(pset, self.P, self.fP, self.ustar, case.dt, self.role, bodies_new, self.u, pos=self.pos)
+        if self.graph:
+            self.ctx.graph_end(1)
         self.vel_slot = 1 - self.vel_slot
         self.bodies = bodies_new
         self.k += 1

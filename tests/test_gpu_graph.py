@@ -1,0 +1,71 @@
+"""Recorded call sequences (mcd_graph_begin / mcd_graph_end): the parts of a
+time step around the PPE solve run as one HIP graph each.  Every replay is
+checked against the same step run call by call (bit for bit), with the
+eager work of the solve between replays; calls that wait for the device are
+refused while a graph is recorded and leave nothing half-run."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from paper_2404_17542_amd import configs
+from gpu_helpers import bits_equal, np_
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_17542_amd import mcd
+    mcd.load()
+    return mcd
+
+
+@pytest.mark.parametrize("which", ["cylinder", "taylor_green", "flapping"])
+def test_graph_steps_equal_direct_calls(M, which):
+    from paper_2404_17542_amd.sim import GpuSim
+    case = {"cylinder": lambda: configs.c2_oscillating_cylinder(n=128, steps=6),
+            "taylor_green": lambda: configs.c1_taylor_green(n=64, steps=6),
+            "flapping": lambda: configs.c6_flapping_ellipse(n=256, steps=6)}[which]()
+    eager = GpuSim(case, update_info=False)
+    graph = GpuSim(case, update_info=False, graph=True)
+    for k in range(6):
+        re_ = eager.step()
+        rg = graph.step()
+        torch.cuda.synchronize()
+        assert rg["iters"] == re_["iters"] and rg["converged"], k
+        for name in ("pos", "role", "normal", "u", "P", "fP"):
+            assert bits_equal(np_(getattr(graph, name)), np_(getattr(eager, name))), (k, name)
+    s0, s1 = graph.ctx.graph_stats(0), graph.ctx.graph_stats(1)
+    print(which, s0, s1)
+    assert s0["instantiated"] >= 1 and s0["instantiated"] + s0["updated"] == 6
+    assert s1["instantiated"] + s1["updated"] == 6
+
+
+def test_refused_calls_leave_nothing_half_run(M):
+    from paper_2404_17542_amd.sim import GpuSim
+    case = configs.c2_oscillating_cylinder(n=64, steps=2)
+    sim = GpuSim(case, update_info=False)
+    ctx = sim.ctx
+    u0 = np_(sim.u).copy()
+    ctx.graph_begin(2)
+    with pytest.raises(M.McdError):
+        ctx.graph_begin(2)                      # one capture at a time
+    ctx.project(0, sim.P, sim.fP, sim.ustar, case.dt, sim.role, sim.bodies, sim.u, pos=sim.pos)
+    with pytest.raises(M.McdError) as ei:
+        ctx.sync()                              # waits for the device: refused
+    assert ei.value.status == 1
+    with pytest.raises(M.McdError) as ei:
+        ctx.graph_end(2)                        # the recorded sequence is incomplete: nothing runs
+    assert ei.value.status == 1
+    torch.cuda.synchronize()
+    assert bits_equal(np_(sim.u), u0)
+    with pytest.raises(M.McdError):
+        ctx.graph_end(2)                        # no capture open
+    with pytest.raises(M.McdError):
+        ctx.graph_begin(M.MAX_GRAPHS if hasattr(M, "MAX_GRAPHS") else 4)
+    r = sim.step()                              # the context works as before
+    assert r["converged"]
+    assert ctx.graph_stats(2) == {"instantiated": 0, "updated": 0}
