@@ -479,13 +479,18 @@ mcd_status mcd_profile_read(mcd_ctx* ctx, double* ms_p, long long* n_p, double* 
  * recorded calls must stay valid until the graph has run.  Errors:
  * MCD_ERR_ARG (bad slot, a capture already open), MCD_ERR_HIP. */
 mcd_status mcd_graph_begin(mcd_ctx* ctx, int slot);
-/* Ends the recording of `slot` and launches it on the context's stream.
- * The first recording of a slot is instantiated; a later one with the same
- * sequence of calls (arguments may differ) updates that executable graph in
- * place, any other replaces it.  If a recorded call failed, nothing runs and
- * MCD_ERR_ARG is returned (with that call's message).  Device-side results
- * are those of the same calls made directly, bit for bit. */
-mcd_status mcd_graph_end(mcd_ctx* ctx, int slot);
+/* Ends the recording of `slot` and, with launch != 0, launches it on the
+ * context's stream.  The first recording of a slot is instantiated; a later
+ * one with the same sequence of calls (arguments may differ) updates that
+ * executable graph in place, any other replaces it; a slot must not be
+ * re-recorded while its previous launch may still be running (alternate
+ * slots for work recorded ahead).  If a recorded call failed, nothing runs
+ * and MCD_ERR_ARG is returned (with that call's message).  Device-side
+ * results are those of the same calls made directly, bit for bit. */
+mcd_status mcd_graph_end(mcd_ctx* ctx, int slot, int launch);
+/* Launches slot's executable graph (as last recorded) on the context's
+ * stream; MCD_ERR_ARG if the slot holds none. */
+mcd_status mcd_graph_launch(mcd_ctx* ctx, int slot);
 /* How often slot's graph was instantiated and updated in place (host ints). */
 mcd_status mcd_graph_stats(mcd_ctx* ctx, int slot, int* instantiated, int* updated);
 

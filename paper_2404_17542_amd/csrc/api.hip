@@ -843,7 +843,7 @@ mcd_status mcd_graph_begin(mcd_ctx* c, int slot) {
     return MCD_OK;
 }
 
-mcd_status mcd_graph_end(mcd_ctx* c, int slot) {
+mcd_status mcd_graph_end(mcd_ctx* c, int slot, int launch) {
     if (!c) return MCD_ERR_ARG;
     if (c->capturing < 0 || slot != c->capturing)
         return fail(c, MCD_ERR_ARG, "mcd_graph_end: no capture of this slot is open%s");
@@ -883,7 +883,16 @@ mcd_status mcd_graph_end(mcd_ctx* c, int slot) {
     }
     (void)hipGraphDestroy(g);
     HIPCHK(c, e, "mcd_graph_end instantiate");
-    HIPCHK(c, hipGraphLaunch(c->gexec[slot], c->stream), "mcd_graph_end launch");
+    if (launch) HIPCHK(c, hipGraphLaunch(c->gexec[slot], c->stream), "mcd_graph_end launch");
+    return MCD_OK;
+}
+
+mcd_status mcd_graph_launch(mcd_ctx* c, int slot) {
+    if (!c) return MCD_ERR_ARG;
+    if (slot < 0 || slot >= MCD_MAX_GRAPHS || !c->gexec[slot])
+        return fail(c, MCD_ERR_ARG, "mcd_graph_launch: slot holds no graph%s");
+    NO_CAPTURE(c, "mcd_graph_launch");
+    HIPCHK(c, hipGraphLaunch(c->gexec[slot], c->stream), "mcd_graph_launch");
     return MCD_OK;
 }
 

@@ -36,7 +36,8 @@ EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last
             "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
             "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_set_output_scale",
             "mcd_model_infer",
-            "mcd_model_train_step", "mcd_graph_begin", "mcd_graph_end", "mcd_graph_stats")
+            "mcd_model_train_step", "mcd_graph_begin", "mcd_graph_end", "mcd_graph_launch",
+            "mcd_graph_stats")
 
 
 class MeshDesc(C.Structure):
@@ -122,7 +123,8 @@ def load():
         "mcd_ppe_residual": (i, [vp, i, vp, vp, vp, vp, P(d)]),
         "mcd_profile": (i, [vp, i]),
         "mcd_graph_begin": (i, [vp, i]),
-        "mcd_graph_end": (i, [vp, i]),
+        "mcd_graph_end": (i, [vp, i, i]),
+        "mcd_graph_launch": (i, [vp, i]),
         "mcd_graph_stats": (i, [vp, i, P(i), P(i)]),
         "mcd_model_create": (i, [vp, i, P(i), i, P(vp)]),
         "mcd_model_destroy": (None, [vp]),
@@ -425,10 +427,13 @@ class Context:
         mcd_graph_begin); they run at graph_end."""
         self._check(self.lib.mcd_graph_begin(self.h, int(slot)), "mcd_graph_begin")
 
-    def graph_end(self, slot):
-        """Stop recording and launch the slot's graph (instantiated the first
-        time, updated in place later)."""
-        self._check(self.lib.mcd_graph_end(self.h, int(slot)), "mcd_graph_end")
+    def graph_end(self, slot, launch=True):
+        """Stop recording; the slot's graph is instantiated the first time and
+        updated in place later, and launched unless launch=False."""
+        self._check(self.lib.mcd_graph_end(self.h, int(slot), 1 if launch else 0), "mcd_graph_end")
+
+    def graph_launch(self, slot):
+        self._check(self.lib.mcd_graph_launch(self.h, int(slot)), "mcd_graph_launch")
 
     def graph_stats(self, slot):
         a, b = C.c_int(), C.c_int()

@@ -31,6 +31,7 @@ class GpuSim:
             raise ValueError("graph mode records the DP update without its host-side info: pass update_info=False")
         self.case = case
         self.graph = graph
+        self._ahead = None          # (k, slot, prepare results) recorded ahead in graph mode
         self.guess = guess
         self.precond = precond
         self.model = model
@@ -117,21 +118,10 @@ class GpuSim:
 
     def prepare(self):
         """First half of a step: DP update at t^{k+1}, remap, weights, u* and
-        the PPE data.  Leaves (pset, bodies_new, update info).  In graph mode
-        these calls are recorded and launched as one graph (slot 0)."""
-        if not self.graph:
-            return self._prepare()
-        self.ctx.graph_begin(0)
-        try:
-            out = self._prepare()
-        except BaseException:
-            try:
-                self.ctx.graph_end(0)
-            except M.McdError:
-                pass
-            raise
-        self.ctx.graph_end(0)
-        return out
+        the PPE data.  Leaves (pset, bodies_new, update info).  Direct calls
+        (step() in graph mode runs the same calls as recorded graphs)."""
+        self._ahead = None
+        return self._prepare()
 
     def _prepare(self):
         case, ctx = self.case, self.ctx
@@ -190,12 +180,15 @@ class GpuSim:
         return M.GUESS_CALLER
 
     def finish(self, pset, bodies_new, info, upd):
+        self._project(pset, bodies_new)
+        return self._advance(bodies_new, info, upd)
+
+    def _project(self, pset, bodies_new):
+        self.ctx.project(pset, self.P, self.fP, self.ustar, self.case.dt, self.role, bodies_new, self.u,
+                         pos=self.pos)
+
+    def _advance(self, bodies_new, info, upd):
         case = self.case
-        if self.graph:
-            self.ctx.graph_begin(1)
-        self.ctx.project(pset, self.P, self.fP, self.ustar, case.dt, self.role, bodies_new, self.u, pos=self.pos)
-        if self.graph:
-            self.ctx.graph_end(1)
         self.vel_slot = 1 - self.vel_slot
         self.bodies = bodies_new
         self.k += 1
@@ -214,9 +207,55 @@ class GpuSim:
                                   precond=self.precond if precond is None else precond)
 
     def step(self):
+        if self.graph:
+            return self._step_graphs()
         pset, bodies_new, upd = self.prepare()
         info = self.solve(pset, self.initial_guess(pset, self.guess))
         return self.finish(pset, bodies_new, info, upd)
+
+    def _record(self, slot, fn):
+        """Records the calls made by fn() into graph slot `slot` (not run)."""
+        self.ctx.graph_begin(slot)
+        try:
+            out = fn()
+        except BaseException:
+            try:
+                self.ctx.graph_end(slot, launch=False)
+            except M.McdError:
+                pass
+            raise
+        self.ctx.graph_end(slot, launch=False)
+        return out
+
+    def _step_graphs(self):
+        """One step as graphs: the preparation (recorded during the previous
+        step), the solve's chunk graphs, the projection.  While the GPU runs
+        this step, the host records its projection and the next step's
+        preparation, so no recording sits between GPU work.  Preparations use
+        slots 0 and 2, projections 1 and 3, alternating by step parity: a slot
+        is recorded again only after its previous launch has completed (the
+        solve of the step in between has returned)."""
+        pre = self._ahead
+        self._ahead = None
+        if pre is None or pre[0] != self.k:
+            slot = 2 * (self.k % 2)
+            pre = (self.k, slot, self._record(slot, self._prepare))
+        _, slot, (pset, bodies_new, upd) = pre
+        self.ctx.graph_launch(slot)
+        guess = self.initial_guess(pset, self.guess)
+        post = 1 + 2 * (self.k % 2)
+        self._record(post, lambda: self._project(pset, bodies_new))
+        saved = (self.k, self.vel_slot, self.bodies)
+        self.k, self.vel_slot, self.bodies = self.k + 1, 1 - self.vel_slot, bodies_new
+        try:
+            nslot = 2 * (self.k % 2)
+            nxt = (self.k, nslot, self._record(nslot, self._prepare))
+        finally:
+            self.k, self.vel_slot, self.bodies = saved
+        info = self.solve(pset, guess)
+        self.ctx.graph_launch(post)
+        self._ahead = nxt
+        return self._advance(bodies_new, info, upd)
 
     def ctx_unknown_count(self):
         """PPE unknowns of the current step (inner and Neumann DPs, minus a pin)."""

@@ -38,10 +38,13 @@ def test_graph_steps_equal_direct_calls(M, which):
         assert rg["iters"] == re_["iters"] and rg["converged"], k
         for name in ("pos", "role", "normal", "u", "P", "fP"):
             assert bits_equal(np_(getattr(graph, name)), np_(getattr(eager, name))), (k, name)
-    s0, s1 = graph.ctx.graph_stats(0), graph.ctx.graph_stats(1)
-    print(which, s0, s1)
-    assert s0["instantiated"] >= 1 and s0["instantiated"] + s0["updated"] == 6
-    assert s1["instantiated"] + s1["updated"] == 6
+    st = [graph.ctx.graph_stats(q) for q in range(4)]
+    print(which, st)
+    # preparations in slots 0 and 2 (six steps and the seventh recorded ahead),
+    # projections in 1 and 3; each slot instantiated once, then updated in place
+    assert all(q["instantiated"] == 1 for q in st)
+    assert sum(st[q]["instantiated"] + st[q]["updated"] for q in (0, 2)) == 7
+    assert sum(st[q]["instantiated"] + st[q]["updated"] for q in (1, 3)) == 6
 
 
 def test_refused_calls_leave_nothing_half_run(M):
@@ -53,6 +56,8 @@ def test_refused_calls_leave_nothing_half_run(M):
     ctx.graph_begin(2)
     with pytest.raises(M.McdError):
         ctx.graph_begin(2)                      # one capture at a time
+    with pytest.raises(M.McdError):
+        ctx.graph_launch(3)                     # refused while recording (and slot 3 holds nothing)
     ctx.project(0, sim.P, sim.fP, sim.ustar, case.dt, sim.role, sim.bodies, sim.u, pos=sim.pos)
     with pytest.raises(M.McdError) as ei:
         ctx.sync()                              # waits for the device: refused
@@ -64,6 +69,8 @@ def test_refused_calls_leave_nothing_half_run(M):
     assert bits_equal(np_(sim.u), u0)
     with pytest.raises(M.McdError):
         ctx.graph_end(2)                        # no capture open
+    with pytest.raises(M.McdError):
+        ctx.graph_launch(2)                     # the failed recording left no graph
     with pytest.raises(M.McdError):
         ctx.graph_begin(M.MAX_GRAPHS if hasattr(M, "MAX_GRAPHS") else 4)
     r = sim.step()                              # the context works as before
