@@ -260,3 +260,21 @@ def test_sampled_circle_on_the_gpu_matches_the_analytic_circle(M):
         sel = role == 2
         dist = np.hypot(pos[0, sel] - c[0], pos[1, sel] - c[1]) - R
         assert np.abs(dist).max() < 0.1 * l0      # on the circle unless clamped to the cell
+
+
+def test_flapping_ellipse_full_size_one_step(M):
+    """512^2 flapping ellipse at the benchmark configuration, with the step
+    graphs the benchmark uses: DP arrays bit-exact after the initial
+    arrangement (500 sweeps) and one step, velocity within 1e-6 of the oracle."""
+    from paper_2404_17542_amd.sim import GpuSim
+    case = configs.c6_flapping_ellipse(n=512, steps=1)
+    g = GpuSim(case, update_info=False, graph=True)
+    o = OracleSim(case)
+    assert np.array_equal(np_(g.role), o.role)
+    assert bits_equal(np_(g.pos), o.pos)
+    rg = g.step()
+    o.step()
+    assert rg["converged"] and rg["rel_res"] <= 1e-8
+    assert np.array_equal(np_(g.role), o.role)
+    assert bits_equal(np_(g.pos), o.pos) and bits_equal(np_(g.normal), o.normal)
+    assert np.abs(np_(g.u) - o.u).max() / np.abs(o.u).max() < 1e-6
