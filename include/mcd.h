@@ -475,8 +475,10 @@ mcd_status mcd_profile_read(mcd_ctx* ctx, double* ms_p, long long* n_p, double* 
  * mcd_neumann_pressure, mcd_project.  The others return MCD_ERR_ARG while a
  * capture is open (mcd_sync, mcd_solve_ppe, mcd_ppe_residual,
  * mcd_fluid_force, mcd_autotune, mcd_set_shape, mcd_profile*, the model
- * calls, mcd_set_stream, mcd_update_dps with info).  Arrays passed to the
- * recorded calls must stay valid until the graph has run.  Errors:
+ * calls, mcd_set_stream, mcd_update_dps with info).  Host arguments
+ * (bodies, boundary tables, scalars) are copied when a call is recorded;
+ * device arrays are referenced and must stay valid until the graph has run.
+ * A context records one slot at a time and is used from one thread.  Errors:
  * MCD_ERR_ARG (bad slot, a capture already open), MCD_ERR_HIP. */
 mcd_status mcd_graph_begin(mcd_ctx* ctx, int slot);
 /* Ends the recording of `slot` and, with launch != 0, launches it on the
