@@ -48,3 +48,26 @@ def test_two_cylinders_case():
     assert min(gaps) < 2 * c.band_over_l0 * c.l0
     assert configs.c2_oscillating_cylinder(n=128).rigid_bodies == (configs.c2_oscillating_cylinder(n=128).body,)
     assert configs.c1_taylor_green(n=64).rigid_bodies == ()
+
+
+def test_prescribed_motions_differentiate_consistently():
+    """velocity and omega are the time derivatives of centre and theta
+    (central differences), for the oscillation with spin and the flapping
+    wing; the wing's stroke runs along beta and its period is pi a0."""
+    from paper_2404_17542_amd.inputs import FlappingMotion, Oscillation
+    motions = [Oscillation((0.1, 0.2), 0.15, 1.3, 1, 0.4, spin_amplitude=0.3, spin_freq=0.7, theta0=0.2),
+               FlappingMotion((0.0, 0.0), 2.5, math.pi / 3, math.pi / 4, 0.3)]
+    h = 1e-6
+    for mo in motions:
+        for t in (0.0, 0.37, 1.9):
+            c1, c0 = mo.centre(t + h), mo.centre(t - h)
+            for a in range(2):
+                assert abs((c1[a] - c0[a]) / (2 * h) - mo.velocity(t)[a]) < 1e-7
+            assert abs((mo.theta(t + h) - mo.theta(t - h)) / (2 * h) - mo.omega(t)) < 1e-7
+            assert mo.omega_vector(t) == (0.0, 0.0, mo.omega(t))
+    wing = motions[1]
+    T = math.pi * wing.a0
+    for t in (0.0, 0.8, 2.1):
+        assert all(abs(u - v) < 1e-12 for u, v in zip(wing.centre(t), wing.centre(t + T)))
+        c = wing.centre(t)
+        assert abs(c[1] * math.cos(wing.beta) - c[0] * math.sin(wing.beta)) < 1e-12
