@@ -463,6 +463,44 @@ mcd_status mcd_profile_read(mcd_ctx* ctx, double* ms_p, long long* n_p, double* 
                             int reset);
 
 /* ---------------------------------------------------------------------
+ * PPE on a wider MLS support (comparison path, 2D)
+ * ------------------------------------------------------------------- */
+
+typedef struct {
+    int iterations;            /* Bi-CGSTAB iterations */
+    int converged;             /* true residual <= tol */
+    int singular;              /* unknown DPs whose fit was singular (weights zero) */
+    double true_rel_residual;  /* ||b - A x|| / ||b|| over unknown rows */
+    double build_ms;           /* GPU time of the weight build and assembly */
+    double solve_ms;           /* GPU time of the solve */
+} mcd_wide_info;
+
+/* Sec. 4 (flow past stationary cylinders) compares the 3x3 MLS support with
+ * an expanded 9x9 one (r_e = 3.5 l0).  This call builds the chi_c = 1
+ * quadratic fit of Sec. 3.2 over the (2 half + 1)^2 block of cells around
+ * every DP (half 1 .. 4; weight kind and r_s of the context, r_e =
+ * re_over_l0 l0), assembles its Laplacian weights into the PPE over the
+ * unknown DPs exactly as the sets of mcd_build_stencils do (Dirichlet values
+ * taken from p, Neumann data neumann_f, nullable), and solves it with a plain
+ * Bi-CGSTAB from p (unknown rows) to ||b - A x|| <= tol ||b||; p receives
+ * the solution at unknown rows.  One code path serves every half width (one
+ * thread per DP, host-formed scalars each iteration), so 3x3 and 9x9 are
+ * compared on equal terms; the production solve is mcd_solve_ppe.  2D only.
+ * Synchronises.  Errors: MCD_ERR_ARG, MCD_ERR_SINGULAR (a singular fit at an
+ * unknown DP; info still filled; known DPs such as wall corners may be
+ * singular and get zero weights), MCD_ERR_NOT_CONVERGED, MCD_ERR_OOM/HIP (the work arrays,
+ * (2 half + 1)^2 + 1 planes of Nc doubles and more, are allocated on first
+ * use and kept by the context). */
+mcd_status mcd_ppe_wide(mcd_ctx* ctx, int half, double re_over_l0, const double* pos, const int8_t* role,
+                        const double* normal, const mcd_bc_table* bc, const double* rhs, const double* neumann_f,
+                        double* p, double tol, int max_iter, mcd_wide_info* info);
+/* Copies the last assembled wide PPE matrix: (2 half + 1)^2 slot planes of
+ * Nc doubles (slot s = the cell at offset (s % W - half, s / W - half),
+ * W = 2 half + 1; the centre slot holds the diagonal; rows of known DPs are
+ * the identity) into the device array A.  Synchronises. */
+mcd_status mcd_ppe_wide_matrix(mcd_ctx* ctx, double* A);
+
+/* ---------------------------------------------------------------------
  * Captured call sequences (HIP graphs): the parts of a time step around
  * the PPE solve as one graph launch each
  * ------------------------------------------------------------------- */
@@ -475,7 +513,7 @@ mcd_status mcd_profile_read(mcd_ctx* ctx, double* ms_p, long long* n_p, double* 
  * mcd_neumann_pressure, mcd_project.  The others return MCD_ERR_ARG while a
  * capture is open (mcd_sync, mcd_solve_ppe, mcd_ppe_residual,
  * mcd_fluid_force, mcd_autotune, mcd_set_shape, mcd_profile*, the model
- * calls, mcd_set_stream, mcd_update_dps with info).  Host arguments
+ * calls, mcd_set_stream, mcd_update_dps with info, mcd_ppe_wide*).  Host arguments
  * (bodies, boundary tables, scalars) are copied when a call is recorded;
  * device arrays are referenced and must stay valid until the graph has run.
  * A context records one slot at a time and is used from one thread.  Errors:

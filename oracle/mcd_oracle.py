@@ -74,6 +74,28 @@ class Mesh:
         self.offsets = offs
         self.S = len(offs)
         self.centre = (self.S - 1) // 2
+        # the spring block of the arrangement is always the 3^dim block
+        self.spring_offsets = list(offs)
+        self.spring_centre = self.centre
+
+    def with_stencil_half(self, half):
+        """The same mesh with the MLS/PPE support widened to the (2 half + 1)^dim
+        block of cells (Sec. 4 compares 3x3 with 9x9); the arrangement keeps
+        its 3^dim spring block."""
+        import copy
+        m = copy.copy(self)
+        w = 2 * int(half) + 1
+        offs = []
+        for s in range(w ** self.dim):
+            o, r = [], s
+            for _ in range(self.dim):
+                o.append(r % w - int(half))
+                r //= w
+            offs.append(tuple(o))
+        m.offsets = offs
+        m.S = len(offs)
+        m.centre = (m.S - 1) // 2
+        return m
 
     @classmethod
     def from_case(cls, case):
@@ -537,8 +559,8 @@ def relax_sweep(mesh, consts, bodies, role, band, pos):
     x = pos[:, band]
     F = [np.zeros(len(band)) for _ in range(dim)]
     with np.errstate(divide="ignore", invalid="ignore"):
-        for s, off in enumerate(mesh.offsets):
-            if s == mesh.centre:
+        for s, off in enumerate(mesh.spring_offsets):
+            if s == mesh.spring_centre:
                 continue
             j, wrap = mesh.neighbour(ijk, off)
             ok = j >= 0

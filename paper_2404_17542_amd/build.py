@@ -23,6 +23,7 @@ SOURCES = {
     "apply.hip": [],
     "krylov.hip": [],
     "unet.hip": [],
+    "wide.hip": [],
     "api.hip": [],
 }
 

@@ -59,6 +59,7 @@ struct mcd_ctx {
     bool cap_failed = false;
     hipGraphExec_t gexec[MCD_MAX_GRAPHS] = {};
     int g_inst[MCD_MAX_GRAPHS] = {}, g_upd[MCD_MAX_GRAPHS] = {};
+    WideWork* ww = nullptr;     // wide-support PPE comparison path (allocated on first use)
     std::string err;
 };
 
@@ -343,6 +344,7 @@ void mcd_destroy(mcd_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < MCD_MAX_GRAPHS; ++k)
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
+    wide_free(c->ww);
     if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
     for (int s = 0; s < MCD_MAX_SETS; ++s) {
         SetDev& d = c->sets[s].dev;
@@ -827,6 +829,43 @@ mcd_status mcd_profile_read(mcd_ctx* c, double* ms_p, long long* n_p, double* ms
     if (!c || !ms_p || !n_p || !ms_s || !n_s) return MCD_ERR_ARG;
     NO_CAPTURE(c, "mcd_profile_read");
     krylov_profile_read(c->kw, ms_p, n_p, ms_s, n_s, reset);
+    return MCD_OK;
+}
+
+mcd_status mcd_ppe_wide(mcd_ctx* c, int half, double re_over_l0, const double* pos, const int8_t* role,
+                        const double* normal, const mcd_bc_table* bc, const double* rhs, const double* neumann_f,
+                        double* p, double tol, int max_iter, mcd_wide_info* info) {
+    if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_ppe_wide");
+    if (c->dim != 2) return fail(c, MCD_ERR_ARG, "mcd_ppe_wide: 2D meshes only%s");
+    if (half < 1 || half > 4 || c->m.n[0] < 2 * half + 1 || c->m.n[1] < 2 * half + 1)
+        return fail(c, MCD_ERR_ARG, "mcd_ppe_wide: half width outside 1 .. 4 or wider than the mesh%s");
+    if (!(re_over_l0 > 0) || !isfinite(re_over_l0) || !(tol > 0) || max_iter < 0)
+        return fail(c, MCD_ERR_ARG, "mcd_ppe_wide: bad r_e, tolerance or iteration limit%s");
+    if (!pos || !role || !normal || !rhs || !p || !info) return fail(c, MCD_ERR_ARG, "mcd_ppe_wide: null array%s");
+    BcDev B;
+    if (!make_bc(bc, &B)) return fail(c, MCD_ERR_ARG, "mcd_ppe_wide: invalid boundary table%s");
+    WideResult r;
+    HIPCHK(c, wide_ppe(c->m, &c->ww, half, re_over_l0 * c->m.l0, c->rs, c->prm.weight_kind, pos, role, normal, B, rhs,
+                       neumann_f, p, tol, max_iter, &r, c->stream),
+           "mcd_ppe_wide");
+    info->iterations = r.iterations;
+    info->converged = r.converged;
+    info->singular = r.singular;
+    info->true_rel_residual = r.true_rel_residual;
+    info->build_ms = r.build_ms;
+    info->solve_ms = r.solve_ms;
+    if (r.singular) return fail(c, MCD_ERR_SINGULAR, "mcd_ppe_wide: singular MLS fits%s");
+    if (!r.converged) return fail(c, MCD_ERR_NOT_CONVERGED, "mcd_ppe_wide: not converged%s");
+    return MCD_OK;
+}
+
+mcd_status mcd_ppe_wide_matrix(mcd_ctx* c, double* A) {
+    if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_ppe_wide_matrix");
+    if (!A || !c->ww) return fail(c, MCD_ERR_ARG, "mcd_ppe_wide_matrix: no wide PPE assembled yet%s");
+    HIPCHK(c, wide_lap_planes(c->ww, A, c->stream), "mcd_ppe_wide_matrix");
+    HIPCHK(c, hipStreamSynchronize(c->stream), "mcd_ppe_wide_matrix");
     return MCD_OK;
 }
 

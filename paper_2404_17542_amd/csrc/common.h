@@ -452,6 +452,22 @@ hipError_t launch_force(const MeshDev& m, const SetDev& su, const SetDev& sp, co
                         const double* fneu, const double* pos, const int8_t* role, const double* normal,
                         const BodiesDev& B, double mu, double* out, int* cnt, hipStream_t st);
 
+// PPE on a (2H+1)^2 MLS support (2D comparison path, wide.hip)
+struct WideWork;
+struct WideResult {
+    int iterations = 0;
+    int converged = 0;
+    int singular = 0;
+    double true_rel_residual = 0.0;
+    double build_ms = 0.0;
+    double solve_ms = 0.0;
+};
+hipError_t wide_ppe(const MeshDev& m, WideWork** slot, int H, double re, double rs, int wkind, const double* pos,
+                    const int8_t* role, const double* normal, const BcDev& bc, const double* rhs, const double* f,
+                    double* p, double tol, int max_iter, WideResult* res, hipStream_t st);
+hipError_t wide_lap_planes(const WideWork* w, double* out, hipStream_t st);
+void wide_free(WideWork* w);
+
 struct KrylovWork;
 struct SolveParams {
     double tol;

@@ -37,7 +37,7 @@ EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last
             "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_set_output_scale",
             "mcd_model_infer",
             "mcd_model_train_step", "mcd_graph_begin", "mcd_graph_end", "mcd_graph_launch",
-            "mcd_graph_stats")
+            "mcd_graph_stats", "mcd_ppe_wide", "mcd_ppe_wide_matrix")
 
 
 class MeshDesc(C.Structure):
@@ -57,6 +57,11 @@ class Body(C.Structure):
                 ("domega_dt", C.c_double * 3), ("theta", C.c_double), ("axis", C.c_double * 3),
                 ("sdf", C.c_void_p), ("sdf_n", C.c_int * 3), ("sdf_origin", C.c_double * 3),
                 ("sdf_h", C.c_double)]
+
+
+class WideInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int), ("converged", C.c_int), ("singular", C.c_int),
+                ("true_rel_residual", C.c_double), ("build_ms", C.c_double), ("solve_ms", C.c_double)]
 
 
 class BcTable(C.Structure):
@@ -122,6 +127,8 @@ def load():
         "mcd_solve_ppe": (i, [vp, i, vp, vp, vp, P(SolveOpts), P(SolveInfo)]),
         "mcd_ppe_residual": (i, [vp, i, vp, vp, vp, vp, P(d)]),
         "mcd_profile": (i, [vp, i]),
+        "mcd_ppe_wide": (i, [vp, i, d, vp, vp, vp, P(BcTable), vp, vp, vp, d, i, P(WideInfo)]),
+        "mcd_ppe_wide_matrix": (i, [vp, vp]),
         "mcd_graph_begin": (i, [vp, i]),
         "mcd_graph_end": (i, [vp, i, i]),
         "mcd_graph_launch": (i, [vp, i]),
@@ -421,6 +428,25 @@ class Context:
         g, dp, b = C.c_int(), C.c_int(), C.c_int()
         self._check(self.lib.mcd_get_shape(self.h, C.byref(g), C.byref(dp), C.byref(b)), "mcd_get_shape")
         return {"grid": g.value, "depth": dp.value, "blocks": b.value}
+
+    def ppe_wide(self, half, re_over_l0, pos, role, normal, bc, rhs, p, neumann_f=None, pin_first=False, tol=1e-8,
+                 max_iter=20000, raise_on_fail=True):
+        """PPE on the (2 half + 1)^2 support (see mcd_ppe_wide); returns its info."""
+        info = WideInfo()
+        D, N, V = self.dim * self.Nc, self.Nc, self._vec
+        t = bc_table(bc, pin_first)
+        st = self.lib.mcd_ppe_wide(self.h, int(half), float(re_over_l0), V(pos, D), _ptr(role, N, torch.int8),
+                                   V(normal, D), C.byref(t), V(rhs, N), V(neumann_f, N), V(p, N), float(tol),
+                                   int(max_iter), C.byref(info))
+        out = {"iterations": info.iterations, "converged": bool(info.converged), "singular": info.singular,
+               "true_rel_residual": info.true_rel_residual, "build_ms": info.build_ms, "solve_ms": info.solve_ms}
+        if raise_on_fail or st not in (0, 3):
+            self._check(st, "mcd_ppe_wide")
+        return out
+
+    def ppe_wide_matrix(self, half, out):
+        S = (2 * half + 1) ** 2
+        self._check(self.lib.mcd_ppe_wide_matrix(self.h, self._vec(out, S * self.Nc)), "mcd_ppe_wide_matrix")
 
     def graph_begin(self, slot):
         """Start recording the following calls into graph slot `slot` (see

@@ -170,3 +170,27 @@ def test_weights_match_independent_least_squares():
         np.testing.assert_allclose(Phi[:, k], sol, rtol=1e-9, atol=1e-9)
         checked += 1
     assert checked > 50
+
+
+@pytest.mark.parametrize("kind", ["cos2", "gauss"])
+def test_quadratic_reproduction_on_the_9x9_support(kind):
+    """The widened support (Sec. 4: 9x9 cells, r_e = 3.5 l0) still reproduces
+    quadratics exactly: gradient and Laplacian of a random quadratic at
+    interior DPs, weights summing to zero."""
+    n, l0 = 16, 0.1
+    m = O.Mesh(2, (n, n), (0.0, 0.0), l0, (False, False)).with_stencil_half(4)
+    assert m.S == 81 and m.offsets[m.centre] == (0, 0) and len(m.spring_offsets) == 9
+    pos = inputs.jittered_positions(m.n, m.origin, l0, seed=12)
+    role = np.full(m.Nc, O.INNER, np.int8)
+    ijk = m.ijk(np.arange(m.Nc))
+    idx = np.nonzero(np.all((ijk > 3) & (ijk < n - 4), axis=0))[0]
+    st = O.mls_build(m, pos, role, np.zeros_like(pos), {}, 3.5 * l0, l0, kind, idx=idx)
+    rng = np.random.default_rng(4)
+    f, grad, lap = _random_quadratic(rng, 2)
+    Phi = O.poly_coeffs(m, st, f(pos))
+    np.testing.assert_allclose(O.grad_from_phi(Phi, l0, 2), grad(pos[:, idx]), rtol=0, atol=1e-10)
+    np.testing.assert_allclose(O.lap_from_phi(Phi, l0, 2), lap(), rtol=0, atol=1e-8)
+    assert np.abs(st.phi[:, : m.S].sum(axis=1)).max() < 1e-10
+    # r_e = 3.5 l0 reaches about 37 of the 81 cells; the rest carry zero weight
+    nz = (np.abs(st.phi[2, : m.S]) + np.abs(st.phi[4, : m.S]) > 0).sum(axis=0)
+    assert 30 <= nz.min() and nz.max() <= 50
