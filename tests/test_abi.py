@@ -40,6 +40,7 @@ def test_struct_layouts_match_header_sizes():
     """Field order/size of the ctypes mirrors (checked against sizeof in C)."""
     from paper_2404_17542_amd import mcd
     assert ctypes.sizeof(mcd.MeshDesc) == 4 + 12 + 4 + 24 + 8 + 12 + 4 + 4
+    assert ctypes.sizeof(mcd.WideInfo) == 3 * 4 + 4 + 3 * 8             # padding before the doubles
     assert ctypes.sizeof(mcd.Body) == 8 + 24 + 8 + 4 * 24 + 8 + 24 + 8 + 16 + 24 + 8   # sdf_n[3] padded to 16
     assert ctypes.sizeof(mcd.BcTable) == 4 * 17
     assert ctypes.sizeof(mcd.Params) == 8 + 7 * 8          # weight_kind padded to 8, then 7 doubles
