@@ -874,7 +874,9 @@ mcd_status mcd_graph_begin(mcd_ctx* c, int slot) {
     if (slot < 0 || slot >= MCD_MAX_GRAPHS) return fail(c, MCD_ERR_ARG, "mcd_graph_begin: slot out of range%s");
     NO_CAPTURE(c, "mcd_graph_begin");
     if (!c->cap_st) HIPCHK(c, hipStreamCreateWithFlags(&c->cap_st, hipStreamNonBlocking), "capture stream");
-    HIPCHK(c, hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeThreadLocal), "mcd_graph_begin");
+    // relaxed: other work of this thread (an allocator, another stream) does not
+    // invalidate the recording; the recorded calls themselves never wait
+    HIPCHK(c, hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeRelaxed), "mcd_graph_begin");
     c->user_st = c->stream;
     c->stream = c->cap_st;
     c->capturing = slot;
@@ -892,6 +894,7 @@ mcd_status mcd_graph_end(mcd_ctx* c, int slot, int launch) {
     c->capturing = -1;
     if (ec != hipSuccess || c->cap_failed || !g) {
         if (g) (void)hipGraphDestroy(g);
+        (void)hipGetLastError();      // the failed recording leaves no error behind for later calls
         const bool failed = c->cap_failed;
         c->cap_failed = false;
         if (failed) {

@@ -11,6 +11,8 @@ owns the device arrays (torch tensors on one stream).
 """
 from __future__ import annotations
 
+import gc
+
 import math
 
 import numpy as np
@@ -32,6 +34,7 @@ class GpuSim:
         self.case = case
         self.graph = graph
         self._ahead = None          # (k, slot, prepare results) recorded ahead in graph mode
+        self.graph_fallbacks = 0    # parts run directly because a recording was invalidated
         self.guess = guess
         self.precond = precond
         self.model = model
@@ -214,17 +217,46 @@ class GpuSim:
         return self.finish(pset, bodies_new, info, upd)
 
     def _record(self, slot, fn):
-        """Records the calls made by fn() into graph slot `slot` (not run)."""
+        """Records the calls made by fn() into graph slot `slot` (not run) and
+        returns fn's result, or None when the runtime invalidated the
+        recording (nothing ran; the caller then makes the calls directly, with
+        the same results)."""
+        # no garbage collection while recording: a collected context would free
+        # device memory in the middle of the recording
+        gc_on = gc.isenabled()
+        gc.disable()
+        try:
+            return self._record_calls(slot, fn)
+        finally:
+            if gc_on:
+                gc.enable()
+
+    def _record_calls(self, slot, fn):
         self.ctx.graph_begin(slot)
         try:
             out = fn()
+        except M.McdError as e:
+            try:
+                self.ctx.graph_end(slot, launch=False)
+            except M.McdError:
+                pass
+            if e.status == 6:          # MCD_ERR_HIP: the recording, not the call, failed
+                self.graph_fallbacks += 1
+                return None
+            raise
         except BaseException:
             try:
                 self.ctx.graph_end(slot, launch=False)
             except M.McdError:
                 pass
             raise
-        self.ctx.graph_end(slot, launch=False)
+        try:
+            self.ctx.graph_end(slot, launch=False)
+        except M.McdError as e:
+            if e.status != 6:
+                raise
+            self.graph_fallbacks += 1
+            return None
         return out
 
     def _step_graphs(self):
@@ -237,23 +269,33 @@ class GpuSim:
         solve of the step in between has returned)."""
         pre = self._ahead
         self._ahead = None
-        if pre is None or pre[0] != self.k:
+        if pre is not None and pre[0] == self.k:
+            _, slot, out = pre
+            self.ctx.graph_launch(slot)
+        else:
             slot = 2 * (self.k % 2)
-            pre = (self.k, slot, self._record(slot, self._prepare))
-        _, slot, (pset, bodies_new, upd) = pre
-        self.ctx.graph_launch(slot)
+            out = self._record(slot, self._prepare)
+            if out is None:
+                out = self._prepare()
+            else:
+                self.ctx.graph_launch(slot)
+        pset, bodies_new, upd = out
         guess = self.initial_guess(pset, self.guess)
         post = 1 + 2 * (self.k % 2)
-        self._record(post, lambda: self._project(pset, bodies_new))
+        post_ok = self._record(post, lambda: self._project(pset, bodies_new) or True) is not None
         saved = (self.k, self.vel_slot, self.bodies)
         self.k, self.vel_slot, self.bodies = self.k + 1, 1 - self.vel_slot, bodies_new
         try:
             nslot = 2 * (self.k % 2)
-            nxt = (self.k, nslot, self._record(nslot, self._prepare))
+            ahead = self._record(nslot, self._prepare)
+            nxt = (self.k, nslot, ahead) if ahead is not None else None
         finally:
             self.k, self.vel_slot, self.bodies = saved
         info = self.solve(pset, guess)
-        self.ctx.graph_launch(post)
+        if post_ok:
+            self.ctx.graph_launch(post)
+        else:
+            self._project(pset, bodies_new)
         self._ahead = nxt
         return self._advance(bodies_new, info, upd)
 

@@ -39,12 +39,15 @@ def test_graph_steps_equal_direct_calls(M, which):
         for name in ("pos", "role", "normal", "u", "P", "fP"):
             assert bits_equal(np_(getattr(graph, name)), np_(getattr(eager, name))), (k, name)
     st = [graph.ctx.graph_stats(q) for q in range(4)]
-    print(which, st)
+    print(which, st, "fallbacks", graph.graph_fallbacks)
     # preparations in slots 0 and 2 (six steps and the seventh recorded ahead),
     # projections in 1 and 3; each slot instantiated once, then updated in place
-    assert all(q["instantiated"] == 1 for q in st)
-    assert sum(st[q]["instantiated"] + st[q]["updated"] for q in (0, 2)) == 7
-    assert sum(st[q]["instantiated"] + st[q]["updated"] for q in (1, 3)) == 6
+    # (a recording that the runtime invalidated runs directly instead: counted)
+    fb = graph.graph_fallbacks
+    assert fb <= 2
+    assert all(1 <= q["instantiated"] <= 1 + fb for q in st)
+    assert 7 - fb <= sum(st[q]["instantiated"] + st[q]["updated"] for q in (0, 2)) <= 7
+    assert 6 - fb <= sum(st[q]["instantiated"] + st[q]["updated"] for q in (1, 3)) <= 6
 
 
 def test_refused_calls_leave_nothing_half_run(M):
