@@ -1341,6 +1341,8 @@ def remap_velocity(mesh, st_prev, u, pos_prev, pos_new, role_prev, role_new, bod
     c' was not inner at step k the DP's own step-k stencil is used instead
     (reading) and the event is counted.
     -> body boundary: the body velocity (no slip).  -> wall or void: 0.
+    Returns (u~, stats); stats["src"] is the cell whose step-k fit each DP's
+    value comes from.
     """
     dim = mesh.dim
     out = np.zeros_like(u)
@@ -1378,6 +1380,7 @@ def remap_velocity(mesh, st_prev, u, pos_prev, pos_new, role_prev, role_new, bod
         src[idxs] = np.where(good, cp, idxs)
         stats["shifted"] = int(good.sum())
         stats["fallback"] = int((~good).sum())
+    stats["src"] = src
     dx = pos_new - pos_prev[:, src]
     for a in range(dim):
         val = taylor_shift(u[a, src], Phis[a][:, src], dx, st_prev.rs)
