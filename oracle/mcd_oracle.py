@@ -524,9 +524,9 @@ class RelaxConsts:
 
 def fit_cos(x):
     """cos x from its Taylor series through x^20, by Horner in x^2 with + and *
-    only (error below 1e-10 for |x| <= pi): a cosine that every
-    implementation evaluates to the same bits, for the weight beta of the
-    boundary-fitted arrangement."""
+    only (error below 1e-10 for |x| <= pi, below 1e-16 for |x| <= pi/2): a
+    cosine that every implementation evaluates to the same bits, for the
+    weight beta of the boundary-fitted arrangement and the MLS weight."""
     c = [(-1.0 if k % 2 else 1.0) / math.factorial(2 * k) for k in range(11)]
     x2 = x * x
     p = c[10]
@@ -738,14 +738,34 @@ def basis_normal(X, nv):
             nx * y + ny * x, ny * z + nz * y, nz * x + nx * z]
 
 
+def series_exp_neg(t):
+    """exp(-t) for 0 <= t <= 4 as (e^{-t/8})^8, e^{-u} from its Taylor series
+    through u^17 (truncation below 1e-21 for u <= 1/2) by Horner with + and *
+    only; relative error a few 1e-15 after the three squarings.  Like
+    fit_cos, every implementation evaluates it to the same bits."""
+    c = [1.0 / math.factorial(k) for k in range(18)]
+    u = -(t * 0.125)
+    p = c[17]
+    for k in range(16, -1, -1):
+        p = p * u + c[k]
+    p = p * p
+    p = p * p
+    return p * p
+
+
 def weight(r, re, kind):
     """cos^2(pi r / (2 re)) for r <= re, else 0 (Sec. 3.2).  'gauss' is the
-    truncated Gaussian exp(-4 r^2/re^2) used by the manufactured case."""
+    truncated Gaussian exp(-4 r^2/re^2) used by the manufactured case.
+
+    Reading (rounding): the cosine is fit_cos (its Taylor series; the
+    argument lies in [0, pi/2], where the series is exact to the last bit or
+    two) and the exponential series_exp_neg, so that the weights, and with
+    them the MLS fits, have the same bits wherever they are computed."""
     if kind == "cos2":
-        t = np.cos(np.pi * r / (2.0 * re))
+        t = fit_cos(np.pi * r / (2.0 * re))
         w = t * t
     elif kind == "gauss":
-        w = np.exp(-4.0 * r * r / (re * re))
+        w = series_exp_neg(4.0 * r * r / (re * re))
     else:
         raise ValueError(kind)
     return np.where(r <= re, w, 0.0)
@@ -846,8 +866,10 @@ def _mls_chunk(mesh, pos, role, normal, bc, re, rs, wkind, idx):
     for s, rk, w, a_row in rows:
         M += w[None, None, :] * a_row[:, None, :] * a_row[None, :, :]
         nrows += (rk > 0) & (w > 0.0)
-    # textbook Cholesky M = L L^T
+    # textbook Cholesky M = L L^T; each pivot's reciprocal 1 / L_jj is formed
+    # once and the eliminations and triangular solves multiply by it
     L = np.zeros_like(M)
+    Linv = np.zeros((m, K))
     tr = np.zeros(K)
     for i in range(m):
         tr = tr + M[i, i]
@@ -860,11 +882,12 @@ def _mls_chunk(mesh, pos, role, normal, bc, re, rs, wkind, idx):
         singular |= bad
         ljj = np.sqrt(np.where(bad, 1.0, dsum))
         L[jcol, jcol] = ljj
+        Linv[jcol] = 1.0 / ljj
         for i in range(jcol + 1, m):
             acc = M[i, jcol].copy()
             for k in range(jcol):
                 acc = acc - L[i, k] * L[jcol, k]
-            L[i, jcol] = acc / ljj
+            L[i, jcol] = acc * Linv[jcol]
     singular |= nrows < m        # fewer rows than basis terms: M has no full rank
     singular &= active
 
@@ -874,13 +897,13 @@ def _mls_chunk(mesh, pos, role, normal, bc, re, rs, wkind, idx):
             acc = rhs[i].copy()
             for k in range(i):
                 acc = acc - L[i, k] * z[k]
-            z[i] = acc / L[i, i]
+            z[i] = acc * Linv[i]
         y = np.zeros_like(rhs)
         for i in reversed(range(m)):
             acc = z[i].copy()
             for k in range(i + 1, m):
                 acc = acc - L[k, i] * y[k]
-            y[i] = acc / L[i, i]
+            y[i] = acc * Linv[i]
         return y
 
     phi = np.zeros((m, S + 1, K))

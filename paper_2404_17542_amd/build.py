@@ -1,8 +1,8 @@
 """Builds libmcd.so (gfx950) in-tree with hipcc.
 
-Each HIP source is compiled separately (the DP-arrangement source also with
--ffp-contract=off for its bit-exact contract) and linked into a shared
-library next to this file.
+Each HIP source is compiled separately (the DP-arrangement and MLS-build
+sources also with -ffp-contract=off for their bit-exact contracts) and
+linked into a shared library next to this file.
 """
 from __future__ import annotations
 
@@ -19,7 +19,7 @@ HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 SOURCES = {
     "dps.hip": ["-ffp-contract=off"],
-    "mls.hip": [],
+    "mls.hip": ["-ffp-contract=off"],
     "apply.hip": [],
     "krylov.hip": [],
     "unet.hip": [],

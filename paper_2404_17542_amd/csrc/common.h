@@ -297,6 +297,50 @@ __device__ __forceinline__ int slot_nonzeros(int s) {
     return nz;
 }
 
+// cos x from its Taylor series through x^20 (error below 1e-10 for
+// |x| <= pi, below 1e-16 for |x| <= pi/2), by Horner in x^2 with + and *
+// only, so that it gives the same bits wherever it is evaluated: the weight
+// beta of the boundary-fitted arrangement (bit-exact DP positions) and the
+// cos^2 MLS weight (bit-exact stencil weights).  Coefficients (-1)^k / (2k)!,
+// the factorials exact in FP64 up to 20!.
+__device__ __forceinline__ double series_cos(double x) {
+#pragma clang fp contract(off)
+    double c[11];
+    double f = 1.0;
+#pragma unroll
+    for (int k = 0; k <= 10; ++k) {
+        if (k > 0) f = f * (double)(2 * k - 1) * (double)(2 * k);
+        c[k] = (k % 2 ? -1.0 : 1.0) / f;
+    }
+    const double x2 = x * x;
+    double p = c[10];
+#pragma unroll
+    for (int k = 9; k >= 0; --k) p = p * x2 + c[k];
+    return p;
+}
+
+// exp(-t) for 0 <= t <= 4 as (e^{-t/8})^8, with e^{-u} from its Taylor
+// series through u^17 by Horner (+ and * only; coefficients 1/k!, exact
+// factorials), then three squarings: the Gaussian MLS weight with the same
+// bits wherever it is evaluated (relative error a few 1e-15).
+__device__ __forceinline__ double series_exp_neg(double t) {
+#pragma clang fp contract(off)
+    double c[18];
+    double f = 1.0;
+#pragma unroll
+    for (int k = 0; k < 18; ++k) {
+        if (k > 0) f = f * (double)k;
+        c[k] = 1.0 / f;
+    }
+    const double u = -(t * 0.125);
+    double p = c[17];
+#pragma unroll
+    for (int k = 16; k >= 0; --k) p = p * u + c[k];
+    p = p * p;
+    p = p * p;
+    return p * p;
+}
+
 // 0: no row, 1: value row (inner or Dirichlet id), 2: Neumann row.
 __device__ __forceinline__ int row_kind(int rj, const BcDev& bc) {
     if (rj == MCD_ROLE_INNER) return 1;

@@ -126,26 +126,6 @@ __global__ __launch_bounds__(kBlock) void k_roles(MeshDev m, BodiesDev B, double
 // state[0]: converged flag, state[1]: sweeps executed.
 // ---------------------------------------------------------------------------
 
-// cos x from its Taylor series through x^20 (error below 1e-10 for
-// |x| <= pi), by Horner in x^2 with + and * only, so that it gives the same
-// bits wherever it is evaluated (the weight beta of the boundary-fitted
-// arrangement enters the bit-exact DP positions).  Coefficients
-// (-1)^k / (2k)!, the factorials exact in FP64 up to 20!.
-__device__ __forceinline__ double fit_cos(double x) {
-    double c[11];
-    double f = 1.0;
-#pragma unroll
-    for (int k = 0; k <= 10; ++k) {
-        if (k > 0) f = f * (double)(2 * k - 1) * (double)(2 * k);
-        c[k] = (k % 2 ? -1.0 : 1.0) / f;
-    }
-    const double x2 = x * x;
-    double p = c[10];
-#pragma unroll
-    for (int k = 9; k >= 0; --k) p = p * x2 + c[k];
-    return p;
-}
-
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double kl0, double sp1, double sp2,
                                                   double sp3, double eps_l0, FitDev fit,
@@ -262,7 +242,7 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
                 }
             }
             if (best < fit.re) {
-                const double beta = fit.half_alpha * (1.0 + fit_cos(best * fit.pi_over_re));
+                const double beta = fit.half_alpha * (1.0 + series_cos(best * fit.pi_over_re));
                 const double t = (beta * best) / rb;
 #pragma unroll
                 for (int a = 0; a < DIM; ++a) xs[a] = xs[a] - t * db[a];

@@ -8,17 +8,24 @@
 // re-gathers each row and writes W_j = M^-1 (w_j a_j) into the slot planes
 // (coalesced: consecutive threads write consecutive cells of a plane), plus
 // the PPE Laplacian matrix over unknown rows/columns in FP64 and FP32.
+//
+// Rounding: built without contraction (no FMA), with the series weight
+// functions and one reciprocal per Cholesky pivot, and every sum taken in
+// slot and basis order, the weights have the same bits as a plain
+// evaluation of the same formulas in that order (IEEE + - * / sqrt).
 #include "common.h"
 
 namespace mcd {
 
+// cos^2(pi r / (2 r_e)) (Sec. 3.2) or the truncated Gaussian, with the
+// series cosine / exponential of common.h.
 __device__ __forceinline__ double mls_weight(double r, double re, int kind) {
     if (r > re) return 0.0;
     if (kind == MCD_WEIGHT_COS2) {
-        const double t = cos(M_PI * r / (2.0 * re));
+        const double t = series_cos(M_PI * r / (2.0 * re));
         return t * t;
     }
-    return exp(-4.0 * r * r / (re * re));
+    return series_exp_neg(4.0 * r * r / (re * re));
 }
 
 // Tiles of the build: 64 x 4 cells (2D) or 32 x 4 x 2 (3D), one cell per

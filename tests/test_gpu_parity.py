@@ -1,9 +1,9 @@
 """HIP path vs the FP64 oracle, element by element, through the C ABI.
 
 Bars: DP arrays (positions, roles, transition codes, normals, sweep counts)
-bit-exact; FP64 MLS weights within 1e-12 relative per DP and per basis
-component; PPE true relative residual <= 1e-8 on the GPU's operator and,
-re-checked, on the oracle's operator.
+bit-exact; FP64 MLS weights equal to the oracle's (well inside the 1e-12
+relative contract) for every DP class; PPE true relative residual <= 1e-8 on
+the GPU's operator and, re-checked, on the oracle's operator.
 """
 import math
 
@@ -181,11 +181,17 @@ def _arranged(case, sweeps=100):
     return m, up.pos, up.role, up.normal
 
 
-def _weights_parity(M, case, bc, idx=None, tol=1e-12):
-    """Inner DPs: <= 1e-12 relative per basis component.  Boundary DPs whose
-    moment matrix is ill-conditioned (wall DPs with exactly 5 rows reach
-    cond(M) ~ 1e11) are held to the forward-error bound of a Cholesky solve,
-    max(1e-12, 1e-14 cond(M)) (about n^2 u cond(M) with n = 5..9)."""
+def _weights_parity(M, case, bc, idx=None):
+    """Every DP's weights equal the oracle's exactly (value equality, so the
+    sign of a zero aside, the same bits): both sides evaluate the same
+    formulas in the same order without contraction, with the series weight
+    functions and one reciprocal per Cholesky pivot.  This holds for every
+    DP class, also for the wall DPs whose moment matrix is nearly singular
+    (cond(M) up to ~1e11 with exactly five rows), so the contract (1e-12
+    relative) is met with room for every weight an operator reads (inner
+    DPs and body DPs in both sets).  Singular flags and row masks agree.
+    Prints per class: DPs, singular DPs, largest cond(M) (boundary classes)
+    and the largest relative difference."""
     m, pos, role, nrm = _arranged(case)
     ctx = M.Context.from_case(case)
     ctx.build_stencils(0, _dev(pos), _dev(role, torch.int8), _dev(nrm), bc, case.pin_first)
@@ -203,27 +209,26 @@ def _weights_parity(M, case, bc, idx=None, tol=1e-12):
     re, rs = case.re_over_l0 * case.l0, case.rs_over_l0 * case.l0
     st = O.mls_build(m, pos, role, nrm, bc, re, rs, case.weight, idx=idx)
     sel = st.idx
-    # the same DPs are singular on both sides (GPU: all masks zero); a
-    # pivot within rounding of the threshold may flip only for cond(M) > 1e11
     gpu_sing = (masks[0, sel] == 0) & (masks[1, sel] == 0) & (role[sel] != O.VOID)
-    flip = np.nonzero(gpu_sing != st.singular)[0]
-    if len(flip):
-        cond = O.moment_cond(m, pos, role, nrm, bc, re, rs, case.weight, sel[flip])
-        assert np.all(cond > 1e11), (sel[flip], cond)
-    ok = ~(st.singular | gpu_sing)
+    assert np.array_equal(gpu_sing, st.singular), sel[gpu_sing != st.singular]
+    ok = ~st.singular
     vm, nm = masks_from_kind(st, m.S, m.centre)
     assert np.array_equal(masks[0, sel][ok], vm[ok])
     assert np.array_equal(masks[1, sel][ok], nm[ok])
-    rel = weights_rel_err(phi[:, :, sel], st.phi).max(axis=0)
-    rel = np.where(ok, rel, 0.0)
-    inner = role[sel] == O.INNER
-    assert rel[inner].max(initial=0.0) <= tol, ("inner", sel[inner][rel[inner].argmax()], rel[inner].max())
-    over = np.nonzero(rel > tol)[0]
-    if len(over):
-        cond = O.moment_cond(m, pos, role, nrm, bc, re, rs, case.weight, sel[over])
-        bound = np.maximum(tol, 1e-14 * cond)
-        worst = np.argmax(rel[over] / bound)
-        assert np.all(rel[over] <= bound), ("boundary", sel[over][worst], rel[over][worst], cond[worst])
+    g = phi[:, :, sel]
+    rel = weights_rel_err(g, st.phi).max(axis=0)
+    wall = m.is_wall_cell(m.ijk(sel))
+    rsel = role[sel]
+    classes = {"inner": rsel == O.INNER, "body": (rsel >= 1) & ~wall, "wall": wall & (rsel != O.VOID)}
+    for name, c in classes.items():
+        cond = 0.0
+        if name != "inner" and c.any() and c.sum() <= 20000:
+            cidx = sel[c & ok]
+            cond = float(O.moment_cond(m, pos, role, nrm, bc, re, rs, case.weight, cidx).max()) if len(cidx) else 0.0
+        print(f"{case.name} weights {name}: {int(c.sum())} DPs, {int((c & ~ok).sum())} singular, "
+              f"max cond(M) {cond:.2e}, max rel diff {rel[c].max(initial=0.0):.1e}")
+    bad = np.nonzero(np.any(g != st.phi, axis=(0, 1)))[0]
+    assert len(bad) == 0, ("weights differ", sel[bad[:8]], rel[bad[:8]], rsel[bad[:8]])
     return m, st, phi, amat, pos, role, nrm, ctx
 
 
@@ -253,8 +258,9 @@ def test_weights_sphere_3d(M, which):
 
 
 def test_weights_full_size_sampled(M):
-    """512^2 periodic and 1024^2 cylinder: 4096 sampled DPs each (plus every
-    body-boundary DP of the cylinder)."""
+    """512^2 periodic and 1024^2 cylinder: 4096 sampled DPs each, plus every
+    body-boundary DP, its right neighbour and every wall DP of the cylinder,
+    in the pressure and the velocity set."""
     rng = np.random.default_rng(0)
     case = configs.c1_taylor_green(n=512)
     idx = np.sort(rng.choice(case.n_cells, 4096, replace=False))
@@ -264,20 +270,26 @@ def test_weights_full_size_sampled(M):
     r0 = O.roles(m, oracle_bodies(case, 0.0))
     idx = np.union1d(rng.choice(case.n_cells, 4096, replace=False), np.nonzero(r0 == 2)[0])
     idx = np.union1d(idx, np.nonzero(r0 == 2)[0] + 1)
+    idx = np.union1d(idx, np.nonzero(m.is_wall_cell(m.ijk(np.arange(m.Nc))))[0])      # every wall DP
     _weights_parity(M, case, case.bc_pressure, idx=idx)
+    _weights_parity(M, case, case.bc_velocity, idx=idx)
 
 
 def test_sphere_full_size_arrangement_and_weights(M):
     """128^3 moving sphere at the benchmark size: the initial arrangement
     (500 sweeps) and 2 steps bit-exact, then the weights of 3000 sampled DPs
-    plus every sphere-boundary DP within 1e-12 (LDS-tiled build, 3D)."""
+    plus every sphere-boundary DP equal to the oracle's (LDS-tiled build,
+    3D)."""
     case = configs.c4_moving_sphere(n=128)
     _dps_parity(M, case, steps=2, init_sweeps=case.n_relax_init)
     m = O.Mesh.from_case(case)
     r0 = O.roles(m, oracle_bodies(case, 0.0))
     rng = np.random.default_rng(4)
     idx = np.union1d(rng.choice(case.n_cells, 3000, replace=False), np.nonzero(r0 == 2)[0])
+    walls = np.nonzero(m.is_wall_cell(m.ijk(np.arange(m.Nc))))[0]
+    idx = np.union1d(idx, rng.choice(walls, 4000, replace=False))
     _weights_parity(M, case, case.bc_pressure, idx=idx)
+    _weights_parity(M, case, case.bc_velocity, idx=idx)
 
 
 def test_weights_deterministic(M):

@@ -194,3 +194,22 @@ def test_quadratic_reproduction_on_the_9x9_support(kind):
     # r_e = 3.5 l0 reaches about 37 of the 81 cells; the rest carry zero weight
     nz = (np.abs(st.phi[2, : m.S]) + np.abs(st.phi[4, : m.S]) > 0).sum(axis=0)
     assert 30 <= nz.min() and nz.max() <= 50
+
+
+def test_series_weight_functions_match_the_library():
+    """The MLS weight's cosine and exponential are series evaluations (same
+    bits everywhere); on their ranges they agree with the C library: cos to
+    2.5e-16 absolute (about one ulp of 1) on [0, pi/2], exp(-t) to 2e-15
+    relative on [0, 4]."""
+    import math
+    x = np.linspace(0.0, math.pi / 2, 20001)
+    got = O.fit_cos(x)
+    want = np.array([math.cos(v) for v in x])
+    assert np.max(np.abs(got - want)) <= 2.5e-16
+    t = np.linspace(0.0, 4.0, 20001)
+    got = O.series_exp_neg(t)
+    want = np.array([math.exp(-v) for v in t])
+    assert np.max(np.abs(got / want - 1.0)) <= 2e-15
+    # the weight itself: cos^2 vanishes at r = re, is 1 at r = 0 and 1/2 at re/2
+    w = O.weight(np.array([0.0, 1.25, 2.5, 2.6]), 2.5, "cos2")
+    assert w[0] == 1.0 and abs(w[1] - 0.5) <= 2.5e-16 and abs(w[2]) <= 1e-31 and w[3] == 0.0
