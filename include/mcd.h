@@ -461,6 +461,12 @@ mcd_status mcd_profile(mcd_ctx* ctx, int enable);
  * launches since the last reset (all host pointers). */
 mcd_status mcd_profile_read(mcd_ctx* ctx, double* ms_p, long long* n_p, double* ms_s, long long* n_s,
                             int reset);
+/* The same split by the matrix copy the launches read, so that their bytes
+ * can be counted from the matrix they actually read: ms[4] and n[4] (host)
+ * receive, in this order, P-stage and S-stage launches on the FP64 matrix,
+ * then P-stage and S-stage launches on the FP32 matrix (FP32_MATRIX and
+ * FP32_REFINE solves). */
+mcd_status mcd_profile_read_split(mcd_ctx* ctx, double* ms, long long* n, int reset);
 
 /* ---------------------------------------------------------------------
  * PPE on a wider MLS support (comparison path, 2D)

@@ -828,7 +828,26 @@ mcd_status mcd_profile(mcd_ctx* c, int enable) {
 mcd_status mcd_profile_read(mcd_ctx* c, double* ms_p, long long* n_p, double* ms_s, long long* n_s, int reset) {
     if (!c || !ms_p || !n_p || !ms_s || !n_s) return MCD_ERR_ARG;
     NO_CAPTURE(c, "mcd_profile_read");
-    krylov_profile_read(c->kw, ms_p, n_p, ms_s, n_s, reset);
+    krylov_profile_read(c->kw, ms_p, n_p, ms_s, n_s, nullptr, nullptr, reset);
+    return MCD_OK;
+}
+
+mcd_status mcd_profile_read_split(mcd_ctx* c, double* ms, long long* n, int reset) {
+    if (!c || !ms || !n) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_profile_read_split");
+    double p, s;
+    long long np_, ns_;
+    double m32[2];
+    long long c32[2];
+    krylov_profile_read(c->kw, &p, &np_, &s, &ns_, m32, c32, reset);
+    ms[0] = p - m32[0];
+    ms[1] = s - m32[1];
+    ms[2] = m32[0];
+    ms[3] = m32[1];
+    n[0] = np_ - c32[0];
+    n[1] = ns_ - c32[1];
+    n[2] = c32[0];
+    n[3] = c32[1];
     return MCD_OK;
 }
 

@@ -536,7 +536,8 @@ hipError_t krylov_set_shape(const MeshDev& m, KrylovWork& w, int grid, int depth
 void krylov_get_shape(const KrylovWork& w, int* grid, int* depth, int* blocks);
 hipError_t krylov_autotune(const MeshDev& m, const SetDev& set, KrylovWork& w, int iters, int max_cand,
                            int* n_out, int* grid_out, int* depth_out, double* us_out, int* chosen);
-void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms_s, long long* n_s, int reset);
+void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms_s, long long* n_s, double* ms32,
+                         long long* n32, int reset);
 hipError_t solve_ppe_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
                           double* p, const SolveParams& sp, SolveOut* out, int* bad, hipStream_t st);
 hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,

@@ -1200,9 +1200,12 @@ struct KrylovWork {
     static constexpr int kProf = 4096;
     hipEvent_t pev[kProf][4];
     int pidx[kProf];       // global iteration index of the recorded launch pair
+    int pa32[kProf];       // 1 when the recorded pair read the FP32 copy of the matrix
     int np = 0;
     double ms[2] = {0.0, 0.0};   // accumulated P, S milliseconds of working launches
     long long cnt[2] = {0, 0};
+    double ms32[2] = {0.0, 0.0};   // the part of them that read the FP32 matrix
+    long long cnt32[2] = {0, 0};
 };
 
 // Enqueues one Bi-CGSTAB iteration (P-stage in `mode`, then S-stage) with
@@ -1295,7 +1298,10 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, 
             for (int q = 0; q < n; ++q) {
                 const bool rec = timing && w.np < KrylovWork::kProf;
                 hipEvent_t* ev = rec ? w.pev[w.np] : nullptr;
-                if (rec) w.pidx[w.np] = iter0 + launched;
+                if (rec) {
+                    w.pidx[w.np] = iter0 + launched;
+                    w.pa32[w.np] = sizeof(TA) < sizeof(double) ? 1 : 0;
+                }
                 enqueue_iteration<DIM, T, TA>(m, V, K, par, first ? mode0 : P_NORMAL, st, ev ? ev[0] : nullptr,
                                           ev ? ev[1] : nullptr,
                                           ev ? ev[2] : nullptr, ev ? ev[3] : nullptr);
@@ -1348,6 +1354,12 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, 
             w.ms[1] += b;
             w.cnt[0] += 1;
             w.cnt[1] += 1;
+            if (w.pa32[k]) {
+                w.ms32[0] += a;
+                w.ms32[1] += b;
+                w.cnt32[0] += 1;
+                w.cnt32[1] += 1;
+            }
         }
     }
     w.np = 0;
@@ -1939,14 +1951,23 @@ hipError_t krylov_profile(KrylovWork* w, int enable) {
     return hipSuccess;
 }
 
-void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms_s, long long* n_s, int reset) {
+void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms_s, long long* n_s, double* ms32,
+                         long long* n32, int reset) {
     *ms_p = w->ms[0];
     *n_p = w->cnt[0];
     *ms_s = w->ms[1];
     *n_s = w->cnt[1];
+    if (ms32 && n32) {
+        ms32[0] = w->ms32[0];
+        ms32[1] = w->ms32[1];
+        n32[0] = w->cnt32[0];
+        n32[1] = w->cnt32[1];
+    }
     if (reset) {
         w->ms[0] = w->ms[1] = 0.0;
         w->cnt[0] = w->cnt[1] = 0;
+        w->ms32[0] = w->ms32[1] = 0.0;
+        w->cnt32[0] = w->cnt32[1] = 0;
     }
 }
 

@@ -32,7 +32,7 @@ MAX_SETS = 4
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
             "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
             "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_ppe_residual", "mcd_profile",
-            "mcd_profile_read", "mcd_autotune", "mcd_set_shape", "mcd_get_shape", "mcd_fluid_force",
+            "mcd_profile_read", "mcd_profile_read_split", "mcd_autotune", "mcd_set_shape", "mcd_get_shape", "mcd_fluid_force",
             "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
             "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_set_output_scale",
             "mcd_model_infer",
@@ -144,6 +144,7 @@ def load():
         "mcd_model_infer": (i, [vp, vp, vp, vp, P(BcTable), vp]),
         "mcd_model_train_step": (i, [vp, vp, vp, vp, vp, P(BcTable), d, P(d)]),
         "mcd_profile_read": (i, [vp, P(d), P(C.c_longlong), P(d), P(C.c_longlong), i]),
+        "mcd_profile_read_split": (i, [vp, P(d), P(C.c_longlong), i]),
         "mcd_autotune": (i, [vp, i, i, P(Tuning)]),
         "mcd_fluid_force": (i, [vp, i, i, vp, vp, vp, vp, vp, vp, P(Body), i, d, P(d), P(i)]),
         "mcd_set_shape": (i, [vp, i, i]),
@@ -475,6 +476,15 @@ class Context:
         self._check(self.lib.mcd_profile_read(self.h, C.byref(mp), C.byref(npp), C.byref(ms), C.byref(ns),
                                               int(bool(reset))), "mcd_profile_read")
         return {"p_ms": mp.value, "p_n": npp.value, "s_ms": ms.value, "s_n": ns.value}
+
+    def profile_read_split(self, reset=True):
+        """Stage timings split by the matrix copy the launches read:
+        {'fp64': {p_ms, p_n, s_ms, s_n}, 'fp32': {...}}."""
+        ms = (C.c_double * 4)()
+        n = (C.c_longlong * 4)()
+        self._check(self.lib.mcd_profile_read_split(self.h, ms, n, int(bool(reset))), "mcd_profile_read_split")
+        return {"fp64": {"p_ms": ms[0], "p_n": n[0], "s_ms": ms[1], "s_n": n[1]},
+                "fp32": {"p_ms": ms[2], "p_n": n[2], "s_ms": ms[3], "s_n": n[3]}}
 
 
 class Model:

@@ -21,5 +21,7 @@ def test_stage_bytes():
     assert bench.stage_bytes(1000, 2, 8, 8) == 112_000
     assert bench.stage_bytes(1000, 2, 4, 8) == 76_000
     assert bench.stage_bytes(1000, 3, 8, 8) == 256_000
-    from paper_2404_17542_amd.stage_sweep import stage_bytes
-    assert stage_bytes(1000, 8, 8) == (112_000, 152_000)
+    # P-stage: 9 planes + 10 vector streams (s, t, p, v, x, rhat read; r, p', x, v' written)
+    assert bench.stage_bytes(1000, 2, 8, 8, "P") == 152_000
+    assert bench.stage_bytes(1000, 3, 8, 8, "P") == 296_000
+    assert bench.stage_bytes(1000, 3, 4, 8, "P") == 188_000
