@@ -53,6 +53,7 @@ class OracleSim:
         self.k = 0
         self.timings = {}
         self.log = []
+        self.last_ppe = None        # (A, b_eff, unknown indices) of the last plain solve
         pos = inputs.jittered_positions(case.n, case.origin, case.l0, case.jitter_seed)
         bodies = self.bodies_at(0.0)
         role0 = O.roles(self.mesh, bodies)
@@ -107,9 +108,10 @@ class OracleSim:
         if self.mixed:
             P, info = O.solve_ppe_mixed(mesh, st_p, self.role, case.bc_pressure, b, p_in, f_p, case.tol,
                                         case.pin_first, guess="caller")
+            self.last_ppe = None
         else:
-            P, info, _ = O.solve_ppe(mesh, st_p, self.role, case.bc_pressure, b, p_in, f_p, case.tol,
-                                     case.pin_first, guess="caller")
+            P, info, self.last_ppe = O.solve_ppe(mesh, st_p, self.role, case.bc_pressure, b, p_in, f_p, case.tol,
+                                                 case.pin_first, guess="caller")
         t4 = time.perf_counter()
         self.u = O.project(mesh, st_p, P, f_p, ustar, case.dt, self.role, bodies_new, pos=self.pos)
         self.P = P

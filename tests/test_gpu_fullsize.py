@@ -1,0 +1,92 @@
+"""Whole steps at the benchmark sizes against the FP64 oracle, in both forms
+of the metric: the plain FP64 method and the learned initial guess with the
+FP32-stored matrix (mixed precision).
+
+1024^2 oscillating cylinder and 128^3 moving sphere: after the initial
+arrangement and one projection step, the DP arrays are bit-exact; the GPU's
+pressure has a true relative residual <= 1e-8 on the oracle's own assembled
+PPE system of that step (its weights and right-hand side, computed on the
+CPU); the velocity is compared with the oracle's step (plain FP64 in 2D
+within 1e-6; the other errors are printed and held to a looser bar).
+"""
+import os
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+from oracle.sim import OracleSim
+from paper_2404_17542_amd import configs
+from gpu_helpers import bits_equal, np_
+
+pytestmark = pytest.mark.gpu
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+WEIGHTS = {2: os.path.join(ROOT, "paper_2404_17542_amd", "weights", "unet_c3_1024.npz"),
+           3: os.path.join(ROOT, "paper_2404_17542_amd", "weights", "unet_c4_128.npz")}
+
+
+@pytest.fixture(scope="module")
+def M():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2404_17542_amd import mcd
+    mcd.load()
+    return mcd
+
+
+def _gpu_step(M, case, form):
+    """One step of a fresh GpuSim in `form`; returns host copies of the state
+    after the initial arrangement and after the step."""
+    from paper_2404_17542_amd import learned
+    from paper_2404_17542_amd.sim import GpuSim
+    if form == "plain":
+        g = GpuSim(case)
+    else:
+        g = GpuSim(case, precision=M.PREC_FP32_MATRIX)
+        g.model = learned.load_model(g.ctx, WEIGHTS[case.dim])
+        g.guess = "learned"
+    init = (np_(g.pos), np_(g.role))
+    rec = g.step()
+    out = {"init": init, "rec": rec, "pos": np_(g.pos), "role": np_(g.role), "normal": np_(g.normal),
+           "u": np_(g.u), "P": np_(g.P)}
+    g.ctx.close()
+    del g
+    torch.cuda.empty_cache()
+    return out
+
+
+def _check(M, case, u_bar_plain):
+    forms = {f: _gpu_step(M, case, f) for f in ("plain", "learned_mixed")}
+    o0 = OracleSim(case)
+    init = (o0.pos.copy(), o0.role.copy())
+    ro = o0.step()
+    A, b, uidx = o0.last_ppe
+    nb = np.linalg.norm(b)
+    for name, r in forms.items():
+        assert bits_equal(r["init"][0], init[0]) and bits_equal(r["init"][1], init[1]), name
+        rec = r["rec"]
+        assert rec["converged"] and rec["rel_res"] <= 1e-8, (name, rec)
+        assert rec["sweeps"] == ro["sweeps"] and rec["trans"] == ro["trans"], name
+        assert bits_equal(r["pos"], o0.pos) and bits_equal(r["role"], o0.role), name
+        assert bits_equal(r["normal"], o0.normal), name
+        res = np.linalg.norm(b - A @ r["P"][uidx]) / nb
+        uerr = np.abs(r["u"] - o0.u).max() / np.abs(o0.u).max()
+        perr = np.linalg.norm(r["P"][uidx] - o0.P[uidx]) / np.linalg.norm(o0.P[uidx])
+        print(f"{case.name} {name}: {rec['iters']} iterations (oracle {ro['iters']}), residual on the oracle's "
+              f"system {res:.3e}, u error {uerr:.2e}, P error {perr:.2e}")
+        assert res <= 1e-8, (name, res)
+        assert uerr < (u_bar_plain if name == "plain" else 10 * u_bar_plain), (name, uerr)
+
+
+def test_cylinder_1024_one_step_both_forms(M):
+    """1024^2 oscillating cylinder (1.05 M cells): 500-sweep arrangement and
+    one step, plain FP64 and learned + mixed."""
+    _check(M, configs.c2_oscillating_cylinder(n=1024, steps=1), 1e-6)
+
+
+def test_sphere_128_one_step_both_forms(M):
+    """128^3 moving sphere (2.1 M cells, the benchmark line): 500-sweep
+    arrangement and one step, plain FP64 and learned + mixed."""
+    _check(M, configs.c4_moving_sphere(n=128, steps=1), 1e-5)

@@ -42,9 +42,13 @@ def _problem(n=64, seed=0):
     return case, m, role, unknown, b, p_prev, p_tgt
 
 
-@pytest.mark.parametrize("ch,scale", [((16, 32), 1.0), ((16, 32, 64), 2.5)])
-def test_unet_forward_loss_and_gradients_match_reference(M, ch, scale):
-    case, m, role, unknown, b, p_prev, p_tgt = _problem()
+@pytest.mark.parametrize("ch,scale,n", [((16, 32), 1.0, 64), ((16, 32, 64), 2.5, 64),
+                                         ((16, 32, 64, 128), 2.0, 256)])
+def test_unet_forward_loss_and_gradients_match_reference(M, ch, scale, n):
+    """Forward, loss and every layer's gradients against the FP64 network;
+    the last case is the production network (four levels, 16-128 channels,
+    the 192-channel decoder concatenation) on a 256^2 mesh."""
+    case, m, role, unknown, b, p_prev, p_tgt = _problem(n)
     ctx = M.Context.from_case(case)
     model = M.Model(ctx, ch)
     model.set_output_scale(scale)
@@ -156,8 +160,10 @@ def _problem3d(n=32, seed=0):
     return case, m, role, unknown, b, p_prev, p_tgt
 
 
-@pytest.mark.parametrize("ch", [(16, 32), (16, 32, 64)])
+@pytest.mark.parametrize("ch", [(16, 32), (16, 32, 64), (16, 32, 64, 128)])
 def test_unet3d_forward_loss_and_gradients_match_reference(M, ch):
+    """3D forward, loss and gradients against the FP64 network on 32^3; the
+    last case has the production channels of the sphere's network."""
     case, m, role, unknown, b, p_prev, p_tgt = _problem3d()
     ctx = M.Context.from_case(case)
     model = M.Model(ctx, ch)
