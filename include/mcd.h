@@ -362,6 +362,22 @@ mcd_status mcd_solve_ppe(mcd_ctx* ctx, int set, const double* rhs, const double*
 mcd_status mcd_ppe_residual(mcd_ctx* ctx, int set, const double* rhs, const double* neumann_f, const double* p,
                             double* r, double* norms);
 
+/* For callers that cannot allocate device memory at call time (a tight
+ * serving loop, a harness that forbids hipMalloc): mcd_ppe_residual with the
+ * same arguments, results and errors (r and norms equal to its own, bit for
+ * bit), that allocates nothing and touches no workspace of ctx.  Its scratch
+ * (per-block partial sums, the two norms, a counter) is a fixed device array
+ * of mcd_noalloc_scratch_bytes() bytes (about 16 KB) per device, held from
+ * the first mcd_create on that device until the process ends; it does not
+ * grow with the mesh (the residual runs at most 1024 blocks), so no mesh
+ * size is beyond it.  Every call on a device shares that array: calls that
+ * overlap on one device (other threads, other streams) race and must be
+ * serialised by the caller.  Synchronises the context's stream. */
+mcd_status mcd_ppe_residual_noalloc(mcd_ctx* ctx, int set, const double* rhs, const double* neumann_f,
+                                    const double* p, double* r, double* norms);
+/* Size in bytes of the per-device scratch of mcd_ppe_residual_noalloc. */
+size_t mcd_noalloc_scratch_bytes(void);
+
 /* ---------------------------------------------------------------------
  * Learned PPE initial guess (2D and 3D): a U-Net on the background mesh.
  * Not part of the MCD method: a network that corrects the warm start of the

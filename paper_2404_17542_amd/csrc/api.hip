@@ -60,6 +60,7 @@ struct mcd_ctx {
     hipGraphExec_t gexec[MCD_MAX_GRAPHS] = {};
     int g_inst[MCD_MAX_GRAPHS] = {}, g_upd[MCD_MAX_GRAPHS] = {};
     WideWork* ww = nullptr;     // wide-support PPE comparison path (allocated on first use)
+    int device = -1;            // device current at mcd_create
     std::string err;
 };
 
@@ -324,6 +325,8 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
     if (e == hipSuccess) e = alloc((void**)&c->fbuf, 4 * MCD_MAX_BODIES * sizeof(double));
     if (e == hipSuccess) e = hipHostMalloc((void**)&c->cnt_host, CNT_N * sizeof(int), hipHostMallocDefault);
     if (e == hipSuccess) e = krylov_alloc(c->m, &c->kw);
+    if (e == hipSuccess) e = hipGetDevice(&c->device);
+    if (e == hipSuccess) e = noalloc_setup(c->device);     // scratch address of this device, once per device
     if (e == hipSuccess) e = hipDeviceSynchronize();
     if (e != hipSuccess) {
         mcd_destroy(c);
@@ -677,6 +680,27 @@ mcd_status mcd_ppe_residual(mcd_ctx* c, int set, const double* rhs, const double
     }
     return MCD_OK;
 }
+
+mcd_status mcd_ppe_residual_noalloc(mcd_ctx* c, int set, const double* rhs, const double* neumann_f,
+                                    const double* p, double* r, double* norms) {
+    if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_ppe_residual_noalloc");
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual_noalloc: set not built%s");
+    if (!rhs || !p || !r) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual_noalloc: null argument%s");
+    double nr[2] = {0.0, 0.0};
+    int bad = 0;
+    HIPCHK(c, ppe_residual_noalloc_impl(c->device, c->m, c->sets[set].dev, rhs, neumann_f, p, r, nr, &bad,
+                                        c->stream),
+           "residual (no allocation)");
+    if (bad) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual_noalloc: non-finite right-hand side%s");
+    if (norms) {
+        norms[0] = nr[0];
+        norms[1] = nr[1];
+    }
+    return MCD_OK;
+}
+
+size_t mcd_noalloc_scratch_bytes(void) { return noalloc_scratch_bytes(); }
 
 // ---------------------------------------------------------------------------
 // Learned initial guess

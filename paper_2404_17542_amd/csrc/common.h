@@ -540,6 +540,11 @@ void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms
                          long long* n32, int reset);
 hipError_t solve_ppe_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
                           double* p, const SolveParams& sp, SolveOut* out, int* bad, hipStream_t st);
+hipError_t noalloc_setup(int device);
+size_t noalloc_scratch_bytes();
+hipError_t ppe_residual_noalloc_impl(int device, const MeshDev& m, const SetDev& set, const double* rhs,
+                                     const double* fneu, const double* p, double* r, double norms[2], int* bad_out,
+                                     hipStream_t st);
 hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
                              const double* p, double* r, double norms[2], int* bad, hipStream_t st);
 

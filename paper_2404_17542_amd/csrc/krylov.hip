@@ -20,6 +20,7 @@
 #include <hip/hip_ext.h>
 
 #include <cmath>
+#include <mutex>
 
 #include "common.h"
 
@@ -948,14 +949,46 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
     }
 }
 
+// b_eff of unknown row c: rhs - (Dirichlet columns) g - (Neumann rows) f.
+template <int DIM>
+__device__ __forceinline__ double beff_row(const MeshDev& m, const SetDev& st, int c, const double* __restrict__ rhs,
+                                           const double* __restrict__ g, const double* __restrict__ fneu,
+                                           double irs2) {
+    constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
+    const size_t Nc = (size_t)m.Nc;
+    int ijk[3];
+    cell_ijk(m, c, ijk);
+    double acc = rhs[c];
+    const uint32_t vm = st.vmask[c], nm = st.nmask[c];
+    for (int s = 0; s < S; ++s) {
+        if (s == CEN) continue;
+        const bool v = (vm >> s) & 1u, n = fneu && ((nm >> s) & 1u);
+        if (!v && !n) continue;
+        int j;
+        double sh[3];
+        neighbour<DIM>(m, ijk, s, j, sh);
+        double ph[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) ph[q] = st.phi[((size_t)q * (S + 1) + s) * Nc + c];
+        const double lc = diag2<DIM>(ph) * irs2;
+        if (v && !st.unknown[j]) acc -= lc * g[j];
+        if (n) acc -= lc * fneu[j];
+    }
+    if (fneu && ((nm >> S) & 1u)) {
+        double ph[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) ph[q] = st.phi[((size_t)q * (S + 1) + S) * Nc + c];
+        acc -= diag2<DIM>(ph) * irs2 * fneu[c];
+    }
+    return acc;
+}
+
 // b_eff = rhs - (Dirichlet columns) g - (Neumann rows) f at unknown rows; x0.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_ppe_rhs(MeshDev m, SetDev st, const double* __restrict__ rhs,
                                                     const double* __restrict__ g, const double* __restrict__ fneu,
                                                     int caller_guess, double* __restrict__ beff,
                                                     double* __restrict__ x0, int* bad) {
-    constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
-    const size_t Nc = (size_t)m.Nc;
     const double irs2 = 1.0 / (st.rs * st.rs);
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
         if (!st.unknown[c]) {
@@ -963,30 +996,7 @@ __global__ __launch_bounds__(kBlock) void k_ppe_rhs(MeshDev m, SetDev st, const 
             x0[c] = 0.0;
             continue;
         }
-        int ijk[3];
-        cell_ijk(m, c, ijk);
-        double acc = rhs[c];
-        const uint32_t vm = st.vmask[c], nm = st.nmask[c];
-        for (int s = 0; s < S; ++s) {
-            if (s == CEN) continue;
-            const bool v = (vm >> s) & 1u, n = fneu && ((nm >> s) & 1u);
-            if (!v && !n) continue;
-            int j;
-            double sh[3];
-            neighbour<DIM>(m, ijk, s, j, sh);
-            double ph[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) ph[q] = st.phi[((size_t)q * (S + 1) + s) * Nc + c];
-            const double lc = diag2<DIM>(ph) * irs2;
-            if (v && !st.unknown[j]) acc -= lc * g[j];
-            if (n) acc -= lc * fneu[j];
-        }
-        if (fneu && ((nm >> S) & 1u)) {
-            double ph[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) ph[q] = st.phi[((size_t)q * (S + 1) + S) * Nc + c];
-            acc -= diag2<DIM>(ph) * irs2 * fneu[c];
-        }
+        const double acc = beff_row<DIM>(m, st, c, rhs, g, fneu, irs2);
         if (!isfinite(acc)) atomicAdd(bad, 1);
         beff[c] = acc;
         x0[c] = caller_guess ? g[c] : 0.0;
@@ -1032,6 +1042,42 @@ __global__ void k_resid_finish(const double* __restrict__ part, int nblk, double
         out[0] = sqrt(q[0]);
         out[1] = sqrt(q[1]);
     }
+}
+
+// r = b_eff - A p at unknown rows (0 elsewhere) in one pass, b_eff formed per
+// row instead of staged: the same arithmetic, grid and per-thread order as
+// k_ppe_rhs followed by k_ppe_resid (so the same bits), with the partials,
+// the counter of non-finite rows and nothing else in the caller's scratch.
+template <int DIM>
+__global__ __launch_bounds__(kBlock) void k_ppe_resid_fused(MeshDev m, SetDev st, const double* __restrict__ rhs,
+                                                            const double* __restrict__ p,
+                                                            const double* __restrict__ fneu, double* __restrict__ r,
+                                                            double* __restrict__ part, int* bad) {
+    __shared__ double lds[2][kBlock / 64];
+    const double irs2 = 1.0 / (st.rs * st.rs);
+    double rr = 0.0, bb = 0.0;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
+        double v = 0.0;
+        if (st.unknown[c]) {
+            const double be = beff_row<DIM>(m, st, c, rhs, p, fneu, irs2);
+            if (!isfinite(be)) atomicAdd(bad, 1);
+            v = be - spmv_row<DIM, double, double>(m, st.amat, c,
+                                                   [&](int j) { return st.unknown[j] ? p[j] : 0.0; });
+            rr += v * v;
+            bb += be * be;
+        }
+        r[c] = v;
+    }
+    double q[2] = {rr, bb};
+    block_sum<2>(q, lds);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = q[0];
+        part[2 * blockIdx.x + 1] = q[1];
+    }
+}
+
+__global__ void k_zero_int(int* p) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0;
 }
 
 // Residual replacement (FP32-stored matrix, FP64 vectors): r = b_eff - A64 x
@@ -1746,6 +1792,64 @@ hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w,
     if ((e = hipMemcpyAsync(w.host, fin, 2 * sizeof(double), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     const double* h = reinterpret_cast<const double*>(w.host);
+    norms[0] = h[0];
+    norms[1] = h[1];
+    return hipSuccess;
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free residual: its scratch is a file-scope device array (one copy
+// per device, kept until the process ends).  The residual's grid is at most
+// 2 kKGrid blocks at any mesh size, so the scratch size does not depend on
+// the mesh.  Host code uses the per-device address from hipGetSymbolAddress,
+// never the array's name.
+// ---------------------------------------------------------------------------
+
+constexpr int kNoAllocBlocks = 2 * kKGrid;
+struct NoAllocScratch {
+    double part[2 * kNoAllocBlocks];   // per-block partial sums of r.r and b.b
+    double fin[2];                     // ||r||, ||b_eff||
+    int bad;                           // non-finite b_eff rows
+};
+static __device__ __align__(256) NoAllocScratch scratch;
+
+constexpr int kMaxDevices = 64;
+static NoAllocScratch* g_scratch_ptr[kMaxDevices] = {};
+static std::mutex g_scratch_mu;
+
+size_t noalloc_scratch_bytes() { return sizeof(NoAllocScratch); }
+
+hipError_t noalloc_setup(int device) {
+    if (device < 0 || device >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (g_scratch_ptr[device]) return hipSuccess;
+    void* ptr = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+    if (e != hipSuccess) return e;
+    g_scratch_ptr[device] = static_cast<NoAllocScratch*>(ptr);
+    return hipSuccess;
+}
+
+hipError_t ppe_residual_noalloc_impl(int device, const MeshDev& m, const SetDev& set, const double* rhs,
+                                     const double* fneu, const double* p, double* r, double norms[2], int* bad_out,
+                                     hipStream_t st) {
+    if (device < 0 || device >= kMaxDevices || !g_scratch_ptr[device]) return hipErrorNotInitialized;
+    NoAllocScratch* ptr = g_scratch_ptr[device];
+    const int gr = (m.Nc + kBlock - 1) / kBlock > kNoAllocBlocks ? kNoAllocBlocks : (m.Nc + kBlock - 1) / kBlock;
+    hipLaunchKernelGGL(k_zero_int, dim3(1), dim3(64), 0, st, &ptr->bad);
+    if (m.dim == 2)
+        hipLaunchKernelGGL(k_ppe_resid_fused<2>, dim3(gr), dim3(kBlock), 0, st, m, set, rhs, p, fneu, r, ptr->part,
+                           &ptr->bad);
+    else
+        hipLaunchKernelGGL(k_ppe_resid_fused<3>, dim3(gr), dim3(kBlock), 0, st, m, set, rhs, p, fneu, r, ptr->part,
+                           &ptr->bad);
+    hipLaunchKernelGGL(k_resid_finish, dim3(1), dim3(kBlock), 0, st, ptr->part, gr, ptr->fin);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    double h[2];
+    if ((e = hipMemcpyAsync(h, ptr->fin, sizeof(h), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(bad_out, &ptr->bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     norms[0] = h[0];
     norms[1] = h[1];
     return hipSuccess;

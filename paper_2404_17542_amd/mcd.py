@@ -31,7 +31,8 @@ MAX_SETS = 4
 
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
             "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
-            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_ppe_residual", "mcd_profile",
+            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_ppe_residual", "mcd_ppe_residual_noalloc",
+            "mcd_noalloc_scratch_bytes", "mcd_profile",
             "mcd_profile_read", "mcd_profile_read_split", "mcd_autotune", "mcd_set_shape", "mcd_get_shape", "mcd_fluid_force",
             "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
             "mcd_model_get_params", "mcd_model_get_grads", "mcd_model_output", "mcd_model_set_output_scale",
@@ -126,6 +127,8 @@ def load():
         "mcd_project": (i, [vp, i, vp, vp, vp, d, vp, vp, P(Body), i, vp]),
         "mcd_solve_ppe": (i, [vp, i, vp, vp, vp, P(SolveOpts), P(SolveInfo)]),
         "mcd_ppe_residual": (i, [vp, i, vp, vp, vp, vp, P(d)]),
+        "mcd_ppe_residual_noalloc": (i, [vp, i, vp, vp, vp, vp, P(d)]),
+        "mcd_noalloc_scratch_bytes": (C.c_size_t, []),
         "mcd_profile": (i, [vp, i]),
         "mcd_ppe_wide": (i, [vp, i, d, vp, vp, vp, P(BcTable), vp, vp, vp, d, i, P(WideInfo)]),
         "mcd_ppe_wide_matrix": (i, [vp, vp]),
@@ -398,6 +401,15 @@ class Context:
         N, V = self.Nc, self._vec
         self._check(self.lib.mcd_ppe_residual(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), V(r, N),
                                               norms), "mcd_ppe_residual")
+        return norms[0], norms[1]
+
+    def ppe_residual_noalloc(self, set_id, rhs, p, r, neumann_f=None):
+        """mcd_ppe_residual_noalloc: the same residual with the library's fixed
+        per-device scratch (no allocation); returns (||r||, ||b_eff||)."""
+        norms = (C.c_double * 2)()
+        N, V = self.Nc, self._vec
+        self._check(self.lib.mcd_ppe_residual_noalloc(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N),
+                                                      V(r, N), norms), "mcd_ppe_residual_noalloc")
         return norms[0], norms[1]
 
     def fluid_force(self, set_u, set_p, u, p, pos, role, normal, bodies, mu, neumann_f=None):
