@@ -283,6 +283,7 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
     }
     m.walls = mesh->walls ? 1 : 0;
     m.wall_id = mesh->wall_id;
+    m.mps = padded_plane_stride((size_t)Nc);
     const double l0 = mesh->l0;
     c->kl0 = prm->kappa * l0;
     c->spring[0] = 0.0;
@@ -312,8 +313,8 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
         e = alloc((void**)&d.phi, (size_t)c->NB * (c->S + 1) * N * sizeof(double));
         if (e == hipSuccess) e = alloc((void**)&d.vmask, N * sizeof(uint32_t));
         if (e == hipSuccess) e = alloc((void**)&d.nmask, N * sizeof(uint32_t));
-        if (e == hipSuccess) e = alloc((void**)&d.amat, (size_t)c->S * N * sizeof(double));
-        if (e == hipSuccess) e = alloc((void**)&d.amat32, (size_t)c->S * N * sizeof(float));
+        if (e == hipSuccess) e = alloc((void**)&d.amat, (size_t)c->S * m.mps * sizeof(double));
+        if (e == hipSuccess) e = alloc((void**)&d.amat32, (size_t)c->S * m.mps * sizeof(float));
         if (e == hipSuccess) e = alloc((void**)&d.unknown, N);
     }
     c->max_sweeps_alloc = 4096;
@@ -498,7 +499,9 @@ mcd_status mcd_get_stencils(mcd_ctx* c, int set, double* phi, uint32_t* masks, d
         HIPCHK(c, hipMemcpyAsync(masks + N, d.nmask, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy");
     }
     if (amat)
-        HIPCHK(c, hipMemcpyAsync(amat, d.amat, (size_t)c->S * N * sizeof(double), hipMemcpyDeviceToDevice, st), "copy");
+        HIPCHK(c, hipMemcpy2DAsync(amat, N * sizeof(double), d.amat, c->m.mps * sizeof(double), N * sizeof(double),
+                                   (size_t)c->S, hipMemcpyDeviceToDevice, st),
+               "copy");
     return MCD_OK;
 }
 

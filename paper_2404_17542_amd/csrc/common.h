@@ -21,7 +21,23 @@ struct MeshDev {
     double length[3];   // n[a] * l0
     int walls;
     int wall_id;
+    // Element stride between the slot planes of the PPE matrix (and between
+    // the Krylov vectors of one precision): Nc rounded up to 64 plus 576, so
+    // that planes do not start a power of two apart, which puts the same cell
+    // of every plane on the same HBM channel.
+    size_t mps;
 };
+
+// Stride of the padded planes for a mesh of Nc cells (see MeshDev::mps).
+inline size_t padded_plane_stride(size_t Nc) { return (Nc + 63) / 64 * 64 + 576; }
+
+// Load of a matrix entry that is read once per stage launch: non-temporal, so
+// that the streamed matrix does not evict the vectors whose tile halos other
+// blocks re-read from cache.
+template <typename TA>
+__device__ __forceinline__ TA ld_stream(const TA* p) {
+    return __builtin_nontemporal_load(p);
+}
 
 struct BodiesDev {
     int n;
@@ -239,8 +255,8 @@ struct SetDev {
     double* phi;        // [nb][S+1][Nc]
     uint32_t* vmask;    // [Nc] bit s: slot s is a value row
     uint32_t* nmask;    // [Nc] bit s: slot s is a Neumann row; bit S: own Neumann row
-    double* amat;       // [S][Nc] PPE matrix (unknown rows/cols)
-    float* amat32;      // [S][Nc]
+    double* amat;       // [S][mps] PPE matrix (unknown rows/cols), plane stride MeshDev::mps
+    float* amat32;      // [S][mps]
     uint8_t* unknown;   // [Nc]
     double rs;
 };

@@ -93,7 +93,7 @@ __device__ __forceinline__ T spmv_row(const MeshDev& m, const TA* __restrict__ A
 #pragma unroll
         for (int s = 0; s < S; ++s) {
             const int off = (s % 3 - 1) + (DIM > 1 ? ((s / 3) % 3 - 1) * n0 : 0) + (DIM > 2 ? (s / 9 - 1) * n01 : 0);
-            const T a = (T)A[(size_t)s * Nc + c];
+            const T a = (T)A[(size_t)s * m.mps + c];
             if (DIFF)
                 acc += s == CEN ? a * xc : a * (val(c + off) - xc);
             else
@@ -103,7 +103,7 @@ __device__ __forceinline__ T spmv_row(const MeshDev& m, const TA* __restrict__ A
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const T a = (T)A[(size_t)s * Nc + c];
+        const T a = (T)A[(size_t)s * m.mps + c];
         int j;
         double sh[3];
         if (!neighbour<DIM>(m, ijk, s, j, sh)) continue;
@@ -244,19 +244,19 @@ __device__ __forceinline__ int halo_cell(const MeshDev& m, int gx, int gy) {
 }
 
 template <typename T, typename TA>
-__device__ __forceinline__ T stencil_lds(const TA* __restrict__ A, size_t Nc, int c, const T* lds, int lx, int ly) {
+__device__ __forceinline__ T stencil_lds(const TA* __restrict__ A, size_t mps, int c, const T* lds, int lx, int ly) {
     T acc = 0;
     if constexpr (sizeof(TA) < sizeof(double)) {
         // FP32-stored matrix in difference form (centre slot = row sum)
         const T xc = lds[(ly + 1) * HX + lx + 1];
 #pragma unroll
         for (int s = 0; s < 9; ++s) {
-            const T a = (T)A[(size_t)s * Nc + c];
+            const T a = (T)ld_stream(A + (size_t)s * mps + c);
             acc += s == 4 ? a * xc : a * (lds[(ly + s / 3) * HX + (lx + s % 3)] - xc);
         }
     } else {
 #pragma unroll
-        for (int s = 0; s < 9; ++s) acc += (T)A[(size_t)s * Nc + c] * lds[(ly + s / 3) * HX + (lx + s % 3)];
+        for (int s = 0; s < 9; ++s) acc += (T)ld_stream(A + (size_t)s * mps + c) * lds[(ly + s / 3) * HX + (lx + s % 3)];
     }
     return acc;
 }
@@ -303,7 +303,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T, TA> V, K
         const int gx = tx0 + lx, gy = ty0 + ly;
         if (gx < m.n[0] && gy < m.n[1]) {
             const int c = gx + m.n[0] * gy;
-            const T ax = stencil_lds<T, TA>(A, (size_t)m.Nc, c, xl, lx, ly);
+            const T ax = stencil_lds<T, TA>(A, m.mps, c, xl, lx, ly);
             const T bc = bp[c];
             const T r = bc - ax;
             sp[c] = r;
@@ -460,7 +460,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
             c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
             if (c >= 0) {
 #pragma unroll
-                for (int s = 0; s < 9; ++s) a[s] = A[(size_t)s * Nc + c];
+                for (int s = 0; s < 9; ++s) a[s] = ld_stream(A + (size_t)s * m.mps + c);
                 rhc = rh[c];
             }
         }
@@ -563,7 +563,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
         c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
         if (c >= 0) {
 #pragma unroll
-            for (int s = 0; s < 9; ++s) a[s] = A[(size_t)s * Nc + c];
+            for (int s = 0; s < 9; ++s) a[s] = ld_stream(A + (size_t)s * m.mps + c);
             rhc = rh[c];
         }
     }
@@ -597,7 +597,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
             c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
             if (c >= 0) {
 #pragma unroll
-                for (int s = 0; s < 9; ++s) a[s] = A[(size_t)s * Nc + c];
+                for (int s = 0; s < 9; ++s) a[s] = ld_stream(A + (size_t)s * m.mps + c);
                 rhc = rh[c];
             }
         }
@@ -698,9 +698,9 @@ __device__ __forceinline__ void brick_origin(const KBufs& K, int brick, int& tx0
 
 // Matrix row of cell c (27 slot planes) into registers.
 template <typename TA>
-__device__ __forceinline__ void load_row27(const TA* __restrict__ A, size_t Nc, int c, TA (&a)[27]) {
+__device__ __forceinline__ void load_row27(const TA* __restrict__ A, size_t mps, int c, TA (&a)[27]) {
 #pragma unroll
-    for (int s = 0; s < 27; ++s) a[s] = A[(size_t)s * Nc + c];
+    for (int s = 0; s < 27; ++s) a[s] = ld_stream(A + (size_t)s * mps + c);
 }
 
 // 27-point product of a preloaded row with the ring planes (slots of planes
@@ -773,7 +773,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
             }
         },
         [&](int c) {
-            load_row27<TA>(A, (size_t)m.Nc, c, a);
+            load_row27<TA>(A, m.mps, c, a);
             bcv = bp[c];
         },
         [&](int c, int s0, int s1, int s2) {
@@ -851,7 +851,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
             }
         },
         [&](int c) {
-            load_row27<TA>(A, (size_t)m.Nc, c, a);
+            load_row27<TA>(A, m.mps, c, a);
             rhc = rh[c];
         },
         [&](int c, int s0, int s1, int s2) {
@@ -924,7 +924,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
             }
         },
         [&](int c) {
-            load_row27<TA>(A, (size_t)m.Nc, c, a);
+            load_row27<TA>(A, m.mps, c, a);
             rhc = rh[c];
         },
         [&](int c, int s0, int s1, int s2) {
@@ -1162,7 +1162,7 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(MeshDev m, const double*
                                                         double* __restrict__ dinv, double* __restrict__ x) {
     constexpr int CEN = Dims<DIM>::CEN;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
-        const double d = unknown[c] ? A[(size_t)CEN * m.Nc + c] : 0.0;
+        const double d = unknown[c] ? A[(size_t)CEN * m.mps + c] : 0.0;
         const bool ok = d != 0.0 && isfinite(d);
         dinv[c] = ok ? 1.0 / d : 1.0;
         if (ok) x[c] = x[c] * d;
@@ -1176,26 +1176,26 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_matrix(MeshDev m, const doubl
                                                           const double* __restrict__ dinv, double* __restrict__ J,
                                                           float* __restrict__ J32) {
     constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
-    const size_t Nc = (size_t)m.Nc;
+    const size_t P = m.mps;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
         int ijk[3];
         cell_ijk(m, c, ijk);
         double off_sum = 0.0, diag = 0.0;
         for (int s = 0; s < S; ++s) {
-            const double a = A[(size_t)s * Nc + c];
+            const double a = A[(size_t)s * P + c];
             double v = 0.0;
             int j;
             double sh[3];
             if (a != 0.0 && neighbour<DIM>(m, ijk, s, j, sh)) v = a * dinv[j];
-            J[(size_t)s * Nc + c] = v;
+            J[(size_t)s * P + c] = v;
             if (s == CEN) {
                 diag = v;
             } else {
-                J32[(size_t)s * Nc + c] = (float)v;
+                J32[(size_t)s * P + c] = (float)v;
                 off_sum += v;
             }
         }
-        J32[(size_t)CEN * Nc + c] = (float)(diag + off_sum);
+        J32[(size_t)CEN * P + c] = (float)(diag + off_sum);
     }
 }
 
@@ -1229,8 +1229,8 @@ struct KrylovWork {
     float* b32;
     double* xsave;         // iterate before a refinement step
     double* dinv;          // [Nc] inverse diagonal (Jacobi)
-    double* jac64;         // [S][Nc] column-scaled matrix A D^-1 (Jacobi)
-    float* jac32;          // [S][Nc] its FP32 copy in difference form
+    double* jac64;         // [S][mps] column-scaled matrix A D^-1 (Jacobi)
+    float* jac32;          // [S][mps] its FP32 copy in difference form
     int* bad_host;         // pinned
     // replayed chunks of kGraphIters iterations (per operator and precision)
     static constexpr int kGraphIters = 16;
@@ -1748,14 +1748,20 @@ hipError_t solve_ppe_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, co
     return e != hipSuccess ? e : e2;
 }
 
+// The nine vectors of one precision in one allocation, mps elements apart
+// (padded, so that the same cell of different vectors is not on one HBM
+// channel); x is the allocation's base.
 template <typename T>
-static hipError_t alloc_vec(KVec<T>& V, size_t Nc) {
-    T** ptrs[9] = {&V.x, &V.r, &V.rhat, &V.s, &V.t, &V.p[0], &V.p[1], &V.v[0], &V.v[1]};
-    for (T** q : ptrs) {
-        hipError_t e = hipMalloc((void**)q, Nc * sizeof(T));
-        if (e != hipSuccess) return e;
-        if ((e = hipMemset(*q, 0, Nc * sizeof(T))) != hipSuccess) return e;
+static hipError_t alloc_vec(KVec<T>& V, size_t mps) {
+    T* base = nullptr;
+    hipError_t e = hipMalloc((void**)&base, 9 * mps * sizeof(T));
+    if (e != hipSuccess) return e;
+    if ((e = hipMemset(base, 0, 9 * mps * sizeof(T))) != hipSuccess) {
+        (void)hipFree(base);
+        return e;
     }
+    T** ptrs[9] = {&V.x, &V.r, &V.rhat, &V.s, &V.t, &V.p[0], &V.p[1], &V.v[0], &V.v[1]};
+    for (int k = 0; k < 9; ++k) *ptrs[k] = base + k * mps;
     V.A = nullptr;
     V.b = nullptr;
     return hipSuccess;
@@ -1763,9 +1769,7 @@ static hipError_t alloc_vec(KVec<T>& V, size_t Nc) {
 
 template <typename T>
 static void free_vec(KVec<T>& V) {
-    T* ptrs[9] = {V.x, V.r, V.rhat, V.s, V.t, V.p[0], V.p[1], V.v[0], V.v[1]};
-    for (T* q : ptrs)
-        if (q) (void)hipFree(q);
+    if (V.x) (void)hipFree(V.x);
 }
 
 // Residual of the PPE at p: r = (rhs - Dirichlet and Neumann columns) - A p
@@ -2025,15 +2029,15 @@ hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     if ((e = hipHostMalloc((void**)&w->host, 2 * sizeof(KState), hipHostMallocDefault)) != hipSuccess) return e;
     for (int i = 0; i < 2; ++i)
         if ((e = hipEventCreateWithFlags(&w->ev[i], hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = alloc_vec(w->v64, Nc)) != hipSuccess) return e;
-    if ((e = alloc_vec(w->v32, Nc)) != hipSuccess) return e;
+    if ((e = alloc_vec(w->v64, m.mps)) != hipSuccess) return e;
+    if ((e = alloc_vec(w->v32, m.mps)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->beff, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->b32, (size_t)Nc * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->xsave, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
     const size_t S = m.dim == 3 ? 27 : 9;
     if ((e = hipMalloc((void**)&w->dinv, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&w->jac64, S * Nc * sizeof(double))) != hipSuccess) return e;
-    if ((e = hipMalloc((void**)&w->jac32, S * Nc * sizeof(float))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&w->jac64, S * m.mps * sizeof(double))) != hipSuccess) return e;
+    if ((e = hipMalloc((void**)&w->jac32, S * m.mps * sizeof(float))) != hipSuccess) return e;
     w->v32.b = w->b32;
     if ((e = hipHostMalloc((void**)&w->bad_host, sizeof(int), hipHostMallocDefault)) != hipSuccess) return e;
     if ((e = hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking)) != hipSuccess) return e;

@@ -273,8 +273,8 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                         if (!is_unknown(H.r[e], H.j[e], bc)) lap = 0.0;
                     }
                     if (st.amat) {
-                        st.amat[(size_t)s * Nc + c] = lap;
-                        st.amat32[(size_t)s * Nc + c] = (float)lap;
+                        st.amat[(size_t)s * m.mps + c] = lap;
+                        st.amat32[(size_t)s * m.mps + c] = (float)lap;
                         off_sum += lap;
                     }
                 } else {
@@ -290,8 +290,8 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                 // sum a_j (x_j - x_c) + rowsum x_c and keep the exact
                 // cancellation of the stencil on smooth fields
                 const double dg = unk_c ? -diag_sum : 0.0;
-                st.amat[(size_t)CEN * Nc + c] = dg;
-                st.amat32[(size_t)CEN * Nc + c] = (float)(dg + off_sum);
+                st.amat[(size_t)CEN * m.mps + c] = dg;
+                st.amat32[(size_t)CEN * m.mps + c] = (float)(dg + off_sum);
             }
         }
         __syncthreads();
