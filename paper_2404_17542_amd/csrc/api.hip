@@ -310,7 +310,7 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
     for (int s = 0; s < MCD_MAX_SETS && e == hipSuccess; ++s) {
         SetDev& d = c->sets[s].dev;
         d.rs = c->rs;
-        e = alloc((void**)&d.phi, (size_t)c->NB * (c->S + 1) * N * sizeof(double));
+        e = alloc((void**)&d.phi, (size_t)c->NB * (c->S + 1) * m.mps * sizeof(double));
         if (e == hipSuccess) e = alloc((void**)&d.vmask, N * sizeof(uint32_t));
         if (e == hipSuccess) e = alloc((void**)&d.nmask, N * sizeof(uint32_t));
         if (e == hipSuccess) e = alloc((void**)&d.amat, (size_t)c->S * m.mps * sizeof(double));
@@ -492,7 +492,8 @@ mcd_status mcd_get_stencils(mcd_ctx* c, int set, double* phi, uint32_t* masks, d
     const SetDev& d = c->sets[set].dev;
     hipStream_t st = c->stream;
     if (phi)
-        HIPCHK(c, hipMemcpyAsync(phi, d.phi, (size_t)c->NB * (c->S + 1) * N * sizeof(double), hipMemcpyDeviceToDevice, st),
+        HIPCHK(c, hipMemcpy2DAsync(phi, N * sizeof(double), d.phi, c->m.mps * sizeof(double), N * sizeof(double),
+                                   (size_t)c->NB * (c->S + 1), hipMemcpyDeviceToDevice, st),
                "copy");
     if (masks) {
         HIPCHK(c, hipMemcpyAsync(masks, d.vmask, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy");

@@ -43,7 +43,7 @@ __device__ __forceinline__ void poly_multi(const MeshDev& m, const SetDev& st, i
         for (int k = 0; k < NC; ++k) d[k] = v ? fld[k * Nc + j] - fc[k] : fneu[k * Nc + j];
 #pragma unroll
         for (int q = 0; q < Q1; ++q) {
-            const double w = st.phi[((size_t)q * (S + 1) + s) * Nc + c];
+            const double w = ld_stream(st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
 #pragma unroll
             for (int k = 0; k < NC; ++k) Phi[k][q] += w * d[k];
         }
@@ -51,7 +51,7 @@ __device__ __forceinline__ void poly_multi(const MeshDev& m, const SetDev& st, i
     if (fneu && ((nm >> S) & 1u)) {
 #pragma unroll
         for (int q = 0; q < Q1; ++q) {
-            const double w = st.phi[((size_t)q * (S + 1) + S) * Nc + c];
+            const double w = ld_stream(st.phi + ((size_t)q * (S + 1) + S) * m.mps + c);
 #pragma unroll
             for (int k = 0; k < NC; ++k) Phi[k][q] += w * fneu[k * Nc + c];
         }
@@ -79,12 +79,12 @@ __device__ __forceinline__ void poly_at(const MeshDev& m, const SetDev& st, int 
         neighbour<DIM>(m, ijk, s, j, sh);
         const double d = v ? fld[j] - fc : fneu[j];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) Phi[q] += st.phi[((size_t)q * (S + 1) + s) * Nc + c] * d;
+        for (int q = 0; q < NB; ++q) Phi[q] += ld_stream(st.phi + ((size_t)q * (S + 1) + s) * m.mps + c) * d;
     }
     if (fneu && ((nm >> S) & 1u)) {
         const double fcn = fneu[c];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) Phi[q] += st.phi[((size_t)q * (S + 1) + S) * Nc + c] * fcn;
+        for (int q = 0; q < NB; ++q) Phi[q] += ld_stream(st.phi + ((size_t)q * (S + 1) + S) * m.mps + c) * fcn;
     }
 }
 

@@ -250,9 +250,10 @@ struct BcDev {
     int pin_first;
 };
 
-// Storage of one stencil set (all planes are [.][Nc]).
+// Storage of one stencil set (weight and matrix planes at the padded plane
+// stride MeshDev::mps; per-cell arrays [Nc]).
 struct SetDev {
-    double* phi;        // [nb][S+1][Nc]
+    double* phi;        // [nb][S+1][mps]
     uint32_t* vmask;    // [Nc] bit s: slot s is a value row
     uint32_t* nmask;    // [Nc] bit s: slot s is a Neumann row; bit S: own Neumann row
     double* amat;       // [S][mps] PPE matrix (unknown rows/cols), plane stride MeshDev::mps

@@ -263,9 +263,13 @@ __device__ __forceinline__ T stencil_lds(const TA* __restrict__ A, size_t mps, i
 
 // Tiles of a block: a contiguous run [first, first + count) of the row-major
 // tile order, so consecutive tiles of a block share halo rows and the blocks
-// an XCD receives cover one contiguous band of the mesh.
+// an XCD receives cover one contiguous band of the mesh.  Each block walks
+// its run from a different starting tile (rotated by 13 tiles per block):
+// when runs are whole rows of tiles, blocks that all started at the same
+// column would read addresses a power of two apart at the same time, which
+// the HBM channel interleave maps onto the same channels.
 struct TileRun {
-    int first, count;
+    int first, count, rot;
 };
 
 __device__ __forceinline__ TileRun tiles_of(const KBufs& K) {
@@ -273,7 +277,13 @@ __device__ __forceinline__ TileRun tiles_of(const KBufs& K) {
     const int first = lb * K.tpb;
     int count = K.ntiles - first;
     count = count < 0 ? 0 : (count > K.tpb ? K.tpb : count);
-    return TileRun{first, count};
+    return TileRun{first, count, count > 1 ? (lb * 13) % count : 0};
+}
+
+// The k-th tile a block processes (0 <= k < count).
+__device__ __forceinline__ int run_tile(const TileRun& r, int k) {
+    const int q = k + r.rot;
+    return r.first + (q >= r.count ? q - r.count : q);
 }
 
 __device__ __forceinline__ void tile_origin(const KBufs& K, int tile, int& tx0, int& ty0) {
@@ -294,7 +304,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T, TA> V, K
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     for (int k = 0; k < run.count; ++k) {
         int tx0, ty0;
-        tile_origin(K, run.first + k, tx0, ty0);
+        tile_origin(K, run_tile(run, k), tx0, ty0);
         for (int e = threadIdx.x; e < NH; e += kKBlock) {
             const int j = halo_cell(m, tx0 + e % HX - 1, ty0 + e / HX - 1);
             xl[e] = j >= 0 ? xp[j] : T(0);
@@ -422,7 +432,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
     TA a[9];
     T rhc = 0;
     if (run.count > 0) {
-        tile_origin(K, run.first, tx0n, ty0n);
+        tile_origin(K, run_tile(run, 0), tx0n, ty0n);
         load_halo_p<T, MODE>(m, tx0n, ty0n, e0, sp, tp, po, vo, rp, xp, h0);
         if (has1) load_halo_p<T, MODE>(m, tx0n, ty0n, e1, sp, tp, po, vo, rp, xp, h1);
     }
@@ -492,7 +502,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
             pl[e] = pv;
         }
         if (k + 1 < run.count) {
-            tile_origin(K, run.first + k + 1, tx0n, ty0n);
+            tile_origin(K, run_tile(run, k + 1), tx0n, ty0n);
             load_halo_p<T, MODE>(m, tx0n, ty0n, e0, sp, tp, po, vo, rp, xp, h0);
             if (has1) load_halo_p<T, MODE>(m, tx0n, ty0n, e1, sp, tp, po, vo, rp, xp, h1);
         }
@@ -546,7 +556,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
     T r0 = 0, v0 = 0, r1 = 0, v1 = 0, rhc = 0;
     TA a[9];
     if (run.count > 0) {
-        tile_origin(K, run.first, tx0n, ty0n);
+        tile_origin(K, run_tile(run, 0), tx0n, ty0n);
         j0 = halo_cell(m, tx0n + e0 % HX - 1, ty0n + e0 / HX - 1);
         if (j0 >= 0) {
             r0 = rp[j0];
@@ -620,7 +630,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
             sl[e1] = sv;
         }
         if (k + 1 < run.count) {
-            tile_origin(K, run.first + k + 1, tx0n, ty0n);
+            tile_origin(K, run_tile(run, k + 1), tx0n, ty0n);
             j0 = halo_cell(m, tx0n + e0 % HX - 1, ty0n + e0 / HX - 1);
             if (j0 >= 0) {
                 r0 = rp[j0];
@@ -735,7 +745,7 @@ __device__ __forceinline__ void march_bricks(const MeshDev& m, const KBufs& K, F
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     for (int k = 0; k < run.count; ++k) {
         int tx0, ty0, tz0;
-        brick_origin(K, run.first + k, tx0, ty0, tz0);
+        brick_origin(K, run_tile(run, k), tx0, ty0, tz0);
         const int tz1 = min(tz0 + K.tz, m.n[2]);
         const int gx = tx0 + lx, gy = ty0 + ly;
         const bool inside = gx < m.n[0] && gy < m.n[1];
@@ -969,7 +979,7 @@ __device__ __forceinline__ double beff_row(const MeshDev& m, const SetDev& st, i
         neighbour<DIM>(m, ijk, s, j, sh);
         double ph[NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) ph[q] = st.phi[((size_t)q * (S + 1) + s) * Nc + c];
+        for (int q = 0; q < NB; ++q) ph[q] = ld_stream(st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
         const double lc = diag2<DIM>(ph) * irs2;
         if (v && !st.unknown[j]) acc -= lc * g[j];
         if (n) acc -= lc * fneu[j];
@@ -977,7 +987,7 @@ __device__ __forceinline__ double beff_row(const MeshDev& m, const SetDev& st, i
     if (fneu && ((nm >> S) & 1u)) {
         double ph[NB];
 #pragma unroll
-        for (int q = 0; q < NB; ++q) ph[q] = st.phi[((size_t)q * (S + 1) + S) * Nc + c];
+        for (int q = 0; q < NB; ++q) ph[q] = ld_stream(st.phi + ((size_t)q * (S + 1) + S) * m.mps + c);
         acc -= diag2<DIM>(ph) * irs2 * fneu[c];
     }
     return acc;

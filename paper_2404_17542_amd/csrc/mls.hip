@@ -6,8 +6,10 @@
 // Pass 1 gathers the 3x3(x3) block and accumulates M (packed lower
 // triangle, registers); M is Cholesky-factored in registers; pass 2
 // re-gathers each row and writes W_j = M^-1 (w_j a_j) into the slot planes
-// (coalesced: consecutive threads write consecutive cells of a plane), plus
-// the PPE Laplacian matrix over unknown rows/columns in FP64 and FP32.
+// (coalesced: consecutive threads write consecutive cells of a plane; the
+// planes are written once and read by later kernels only, so the stores are
+// non-temporal), plus the PPE Laplacian matrix over unknown rows/columns in
+// FP64 and FP32.
 //
 // Rounding: built without contraction (no FMA), with the series weight
 // functions and one reciprocal per Cholesky pivot, and every sum taken in
@@ -32,8 +34,7 @@ __device__ __forceinline__ double mls_weight(double r, double re, int kind) {
 // thread of a 256-thread block; the tile plus a one-cell halo is staged in
 // LDS (positions already shifted to the periodic image seen from the tile,
 // normals, roles, cell indices), so the 2 x 27 neighbour reads per DP of the
-// two passes are LDS reads.  Pass 1 keeps each row's weight w_j in LDS for
-// pass 2.
+// two passes are LDS reads.
 template <int DIM> struct MlsTile;
 template <> struct MlsTile<2> { static constexpr int X = 64, Y = 4, Z = 1; };
 template <> struct MlsTile<3> { static constexpr int X = 32, Y = 4, Z = 2; };
@@ -100,7 +101,11 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
     using HT = MlsHalo<DIM>;
     static_assert(T::X * T::Y * T::Z == kBlock, "one tile cell per thread");
     __shared__ HT H;
-    __shared__ double wc[S][kBlock];
+    // 2D keeps each row's weight in LDS between the passes; 3D recomputes it
+    // in pass 2 (same bits), which leaves 43 KB of LDS per block instead of
+    // 98 KB, so that two blocks fit on a CU
+    constexpr bool kCacheW = DIM == 2;
+    __shared__ double wc[kCacheW ? S : 1][kBlock];
     const size_t Nc = (size_t)m.Nc;
     const int ntx = (m.n[0] + T::X - 1) / T::X, nty = (m.n[1] + T::Y - 1) / T::Y;
     const int ntz = DIM == 3 ? (m.n[2] + T::Z - 1) / T::Z : 1;
@@ -164,7 +169,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                     double w = 0.0, a[NB];
                     const int kind = row_lds<DIM>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs, wkind,
                                                   true, w, a);
-                    wc[s][threadIdx.x] = w;
+                    if (kCacheW) wc[s][threadIdx.x] = w;
                     if (!kind) continue;
                     if (kind == 1)
                         vm |= 1u << s;
@@ -236,8 +241,8 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
 #pragma unroll
                 for (int q = 0; q < NB; ++q) y[q] = 0.0;
                 if (isv || isn) {
-                    double w = wc[s][threadIdx.x], a[NB];
-                    row_lds<DIM>(H, bc, e, s == CEN, xc, re, rs, wkind, false, w, a);
+                    double w = kCacheW ? wc[s][threadIdx.x] : 0.0, a[NB];
+                    row_lds<DIM>(H, bc, e, s == CEN, xc, re, rs, wkind, !kCacheW, w, a);
 #pragma unroll
                     for (int q = 0; q < NB; ++q) y[q] = w * a[q];
                     // forward L z = y, backward L^T y = z
@@ -265,7 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                 }
                 if (s != CEN) {
 #pragma unroll
-                    for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + s) * Nc + c] = y[q];
+                    for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(y[q], st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
                     double lap = 0.0;
                     if (isv && unk_c) {
                         lap = diag2<DIM>(y) / (rs * rs);
@@ -273,25 +278,25 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                         if (!is_unknown(H.r[e], H.j[e], bc)) lap = 0.0;
                     }
                     if (st.amat) {
-                        st.amat[(size_t)s * m.mps + c] = lap;
-                        st.amat32[(size_t)s * m.mps + c] = (float)lap;
+                        __builtin_nontemporal_store(lap, st.amat + (size_t)s * m.mps + c);
+                        __builtin_nontemporal_store((float)lap, st.amat32 + (size_t)s * m.mps + c);
                         off_sum += lap;
                     }
                 } else {
 #pragma unroll
-                    for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + S) * Nc + c] = y[q];
+                    for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(y[q], st.phi + ((size_t)q * (S + 1) + S) * m.mps + c);
                 }
             }
 #pragma unroll
-            for (int q = 0; q < NB; ++q) st.phi[((size_t)q * (S + 1) + CEN) * Nc + c] = -cacc[q];
+            for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(-cacc[q], st.phi + ((size_t)q * (S + 1) + CEN) * m.mps + c);
             if (st.amat) {
                 // FP32 copy in difference form: its centre slot holds the row sum
                 // (zero for rows without known neighbours), so that products
                 // sum a_j (x_j - x_c) + rowsum x_c and keep the exact
                 // cancellation of the stencil on smooth fields
                 const double dg = unk_c ? -diag_sum : 0.0;
-                st.amat[(size_t)CEN * m.mps + c] = dg;
-                st.amat32[(size_t)CEN * m.mps + c] = (float)(dg + off_sum);
+                __builtin_nontemporal_store(dg, st.amat + (size_t)CEN * m.mps + c);
+                __builtin_nontemporal_store((float)(dg + off_sum), st.amat32 + (size_t)CEN * m.mps + c);
             }
         }
         __syncthreads();
