@@ -154,7 +154,15 @@ typedef struct mcd_ctx mcd_ctx;
  * Errors: MCD_ERR_ARG for an invalid mesh/params, MCD_ERR_OOM. */
 mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hip_stream,
                       mcd_ctx** out);
+/* Releases ctx: waits for its stream, then frees its device memory.  An open
+ * recording of ctx itself is abandoned.  While any context of the process
+ * has a recording open (mcd_graph_begin .. mcd_graph_end), the release is
+ * deferred until the last such recording ends, because freeing memory or
+ * waiting for a stream during a recording can make the runtime invalidate
+ * it; the caller must not use ctx after this call either way. */
 void mcd_destroy(mcd_ctx* ctx);
+/* Contexts and models whose release is deferred (see mcd_destroy). */
+int mcd_pending_destroys(void);
 mcd_status mcd_set_stream(mcd_ctx* ctx, void* hip_stream);
 /* Waits for the context's stream and returns latched device errors
  * (MCD_ERR_SINGULAR, MCD_ERR_ROLE), clearing them. */
@@ -403,6 +411,7 @@ typedef struct mcd_model mcd_model;
  * [16, 256]; every mesh axis must be divisible by 2^(levels-1).  body_id: role id
  * of the body for the one-hot input.  Weights start at zero (set them). */
 mcd_status mcd_model_create(mcd_ctx* ctx, int levels, const int* channels, int body_id, mcd_model** out);
+/* Releases a model (deferred like mcd_destroy while a recording is open). */
 void mcd_model_destroy(mcd_model* model);
 size_t mcd_model_num_params(const mcd_model* model);
 /* host arrays of mcd_model_num_params floats; set resets the optimiser */

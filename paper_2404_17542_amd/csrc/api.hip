@@ -4,7 +4,9 @@
 #include <string.h>
 
 #include <algorithm>
+#include <mutex>
 #include <string>
+#include <vector>
 
 #include "common.h"
 
@@ -337,6 +339,42 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
     return MCD_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Lifetime while recordings are open.  Destroying a context or a model frees
+// device memory and waits for its stream; either, done while any context of
+// the process has a recording open (mcd_graph_begin .. mcd_graph_end), can
+// make the runtime invalidate that recording.  Destruction is therefore
+// deferred until the last open recording of the process has ended.
+// ---------------------------------------------------------------------------
+
+static std::mutex g_life_mu;
+static int g_open_recordings = 0;
+static std::vector<mcd_ctx*> g_pending_ctx;
+static std::vector<mcd_model*> g_pending_model;
+
+static void destroy_ctx_now(mcd_ctx* c);
+static void destroy_model_now(mcd_model* md);
+
+static void recording_opened() {
+    std::lock_guard<std::mutex> lk(g_life_mu);
+    ++g_open_recordings;
+}
+
+// A recording ended; when it was the last open one, destroys what waited.
+static void recording_closed() {
+    std::vector<mcd_ctx*> ctxs;
+    std::vector<mcd_model*> models;
+    {
+        std::lock_guard<std::mutex> lk(g_life_mu);
+        if (g_open_recordings > 0) --g_open_recordings;
+        if (g_open_recordings > 0) return;
+        ctxs.swap(g_pending_ctx);
+        models.swap(g_pending_model);
+    }
+    for (mcd_model* md : models) destroy_model_now(md);
+    for (mcd_ctx* c : ctxs) destroy_ctx_now(c);
+}
+
 void mcd_destroy(mcd_ctx* c) {
     if (!c) return;
     if (c->capturing >= 0) {
@@ -344,7 +382,26 @@ void mcd_destroy(mcd_ctx* c) {
         (void)hipStreamEndCapture(c->cap_st, &g);
         if (g) (void)hipGraphDestroy(g);
         c->stream = c->user_st;
+        c->capturing = -1;
+        (void)hipGetLastError();
+        recording_closed();
     }
+    {
+        std::lock_guard<std::mutex> lk(g_life_mu);
+        if (g_open_recordings > 0) {
+            g_pending_ctx.push_back(c);
+            return;
+        }
+    }
+    destroy_ctx_now(c);
+}
+
+int mcd_pending_destroys(void) {
+    std::lock_guard<std::mutex> lk(g_life_mu);
+    return (int)(g_pending_ctx.size() + g_pending_model.size());
+}
+
+static void destroy_ctx_now(mcd_ctx* c) {
     (void)hipStreamSynchronize(c->stream);
     for (int k = 0; k < MCD_MAX_GRAPHS; ++k)
         if (c->gexec[k]) (void)hipGraphExecDestroy(c->gexec[k]);
@@ -740,6 +797,17 @@ mcd_status mcd_model_create(mcd_ctx* c, int levels, const int* channels, int bod
 
 void mcd_model_destroy(mcd_model* md) {
     if (!md) return;
+    {
+        std::lock_guard<std::mutex> lk(g_life_mu);
+        if (g_open_recordings > 0) {
+            g_pending_model.push_back(md);
+            return;
+        }
+    }
+    destroy_model_now(md);
+}
+
+static void destroy_model_now(mcd_model* md) {
     (void)hipStreamSynchronize(md->ctx->stream);
     unet_free(md->net);
     delete md;
@@ -924,6 +992,7 @@ mcd_status mcd_graph_begin(mcd_ctx* c, int slot) {
     // relaxed: other work of this thread (an allocator, another stream) does not
     // invalidate the recording; the recorded calls themselves never wait
     HIPCHK(c, hipStreamBeginCapture(c->cap_st, hipStreamCaptureModeRelaxed), "mcd_graph_begin");
+    recording_opened();
     c->user_st = c->stream;
     c->stream = c->cap_st;
     c->capturing = slot;
@@ -939,6 +1008,7 @@ mcd_status mcd_graph_end(mcd_ctx* c, int slot, int launch) {
     const hipError_t ec = hipStreamEndCapture(c->cap_st, &g);
     c->stream = c->user_st;
     c->capturing = -1;
+    recording_closed();
     if (ec != hipSuccess || c->cap_failed || !g) {
         if (g) (void)hipGraphDestroy(g);
         (void)hipGetLastError();      // the failed recording leaves no error behind for later calls

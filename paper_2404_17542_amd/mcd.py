@@ -29,7 +29,7 @@ MAX_IDS = 16
 MAX_BODIES = 8
 MAX_SETS = 4
 
-EXPORTED = ("mcd_create", "mcd_destroy", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
+EXPORTED = ("mcd_create", "mcd_destroy", "mcd_pending_destroys", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
             "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
             "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_ppe_residual", "mcd_ppe_residual_noalloc",
             "mcd_noalloc_scratch_bytes", "mcd_profile",
@@ -129,6 +129,7 @@ def load():
         "mcd_ppe_residual": (i, [vp, i, vp, vp, vp, vp, P(d)]),
         "mcd_ppe_residual_noalloc": (i, [vp, i, vp, vp, vp, vp, P(d)]),
         "mcd_noalloc_scratch_bytes": (C.c_size_t, []),
+        "mcd_pending_destroys": (i, []),
         "mcd_profile": (i, [vp, i]),
         "mcd_ppe_wide": (i, [vp, i, d, vp, vp, vp, P(BcTable), vp, vp, vp, d, i, P(WideInfo)]),
         "mcd_ppe_wide_matrix": (i, [vp, vp]),
