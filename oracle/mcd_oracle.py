@@ -1075,8 +1075,9 @@ def bicgstab(A, b, x0, tol, max_iter=20000, breakdown=1e-30, minv=None):
     """Bi-CGSTAB (van der Vorst, 1992), as named in Sec. 3.3; unpreconditioned
     unless minv is given.
 
-    minv: the inverse of a diagonal right preconditioner M, as a vector
-    (Jacobi: 1/diag(A)).  Right preconditioning applies M^-1 to the search
+    minv: the inverse of a right preconditioner M, as a vector for a
+    diagonal M (Jacobi: 1/diag(A)) or as a function q -> M^-1 q (the
+    multigrid V-cycle).  Right preconditioning applies M^-1 to the search
     directions before each product with A (v = A M^-1 p, t = A M^-1 s) and
     updates x with the preconditioned directions, so r stays b - A x.
 
@@ -1085,7 +1086,12 @@ def bicgstab(A, b, x0, tol, max_iter=20000, breakdown=1e-30, minv=None):
     A restart with r_hat = r also follows a (near-)breakdown of rho or
     r_hat.v.
     """
-    prec = (lambda q: q) if minv is None else (lambda q: minv * q)
+    if minv is None:
+        prec = lambda q: q          # noqa: E731
+    elif callable(minv):
+        prec = minv
+    else:
+        prec = lambda q: minv * q   # noqa: E731
     info = SolveInfo()
     x = x0.astype(np.float64).copy()
     nb = float(np.linalg.norm(b))
@@ -1152,17 +1158,165 @@ def jacobi_inverse_diagonal(A):
 def solve_ppe(mesh, st, role, bc, rhs, p_in, f_neu, tol, pin_first=False, guess="zero", max_iter=20000,
               precond="none"):
     """Solve the PPE; p_in carries Dirichlet values (and the guess for 'caller').
-    precond: 'none' (the plain method) or 'jacobi' (right preconditioning with
-    the diagonal of the PPE matrix)."""
+    precond: 'none' (the plain method), 'jacobi' (right preconditioning with
+    the diagonal of the PPE matrix) or 'mg' (right preconditioning with one
+    multigrid V-cycle, mg_levels / mg_vcycle)."""
     A, beff, uidx = ppe_system(mesh, st, role, bc, rhs, p_in, f_neu, pin_first)
     x0 = p_in[uidx] if guess == "caller" else np.zeros(len(uidx))
-    if precond not in ("none", "jacobi"):
+    if precond not in ("none", "jacobi", "mg"):
         raise ValueError(f"unknown preconditioner {precond!r}")
-    minv = jacobi_inverse_diagonal(A) if precond == "jacobi" else None
+    minv = None
+    if precond == "jacobi":
+        minv = jacobi_inverse_diagonal(A)
+    elif precond == "mg":
+        levels = mg_levels(mesh, A, uidx)
+
+        def minv(q):
+            full = np.zeros(mesh.Nc)
+            full[uidx] = q
+            return mg_vcycle(levels, full)[uidx]
     x, info = bicgstab(A, beff, x0, tol, max_iter, minv=minv)
     p = p_in.copy()
     p[uidx] = x
     return p, info, (A, beff, uidx)
+
+
+# ---------------------------------------------------------------------------
+# Multigrid preconditioner (not from the paper: the preconditioner of the
+# mixed-precision form).  Geometric coarsening of the background mesh by 2
+# per axis, cell-centred multilinear prolongation, averaging restriction and
+# Galerkin coarse operators, so the coarse levels inherit the fine operator's
+# boundary rows (Neumann body DPs, Dirichlet walls, the periodic pin) without
+# geometric reasoning; one damped-Jacobi sweep before and after the coarse
+# correction; a dense solve on the coarsest level.
+# ---------------------------------------------------------------------------
+
+MG_OMEGA = 0.8          # Jacobi damping
+MG_MAX_COARSE = 64      # cells of the coarsest level
+
+
+@dataclass
+class MgLevel:
+    n: tuple                 # cells per axis
+    periodic: tuple
+    unknown: np.ndarray      # bool [N]
+    A: object                # sparse [N, N], zero rows and columns at non-unknown cells
+    dinv: np.ndarray         # 1 / diag(A) at unknown cells, 0 elsewhere
+    P: object = None         # prolongation [N, N_coarse]
+    R: object = None         # restriction [N_coarse, N]
+    inv: np.ndarray = None   # dense inverse on the coarsest level
+
+
+def _cells_ijk(n):
+    N = int(np.prod(n))
+    rem = np.arange(N)
+    out = []
+    for a in range(len(n)):
+        out.append(rem % n[a])
+        rem = rem // n[a]
+    return out
+
+
+def _mg_coarse_dims(n, periodic):
+    """Cells per axis of the next level, or None when the level is the
+    coarsest: every axis halves (rounded up), periodic axes must be even,
+    and no axis may fall below 3 cells."""
+    nc = tuple((v + 1) // 2 for v in n)
+    if any(p and v % 2 for v, p in zip(n, periodic)) or min(nc) < 3:
+        return None
+    return nc
+
+
+def mg_transfer(n, periodic, unknown_f, unknown_c, nc):
+    """Prolongation P (fine cell j: weights 3/4 towards its own parent cell
+    and 1/4 towards the parent's neighbour on j's side, per axis; coarse
+    cells outside the mesh or not unknown are dropped and the row is
+    renormalised; zero rows at non-unknown fine cells) and restriction R
+    (the mean of the 2^dim children, R = C^T / 2^dim)."""
+    dim = len(n)
+    ijk = _cells_ijk(n)
+    N, Ncn = int(np.prod(n)), int(np.prod(nc))
+    rows, cols, vals = [], [], []
+    for corner in range(2 ** dim):
+        w = np.ones(N)
+        idx = np.zeros(N, dtype=np.int64)
+        ok = unknown_f.copy()
+        stride = 1
+        for a in range(dim):
+            far = (corner >> a) & 1
+            side = np.where(ijk[a] % 2 == 0, -1, 1)
+            J = ijk[a] // 2 + side * far
+            if periodic[a]:
+                J = J % nc[a]
+            ok &= (J >= 0) & (J < nc[a])
+            w = w * (0.25 if far else 0.75)
+            idx += np.clip(J, 0, nc[a] - 1) * stride
+            stride *= nc[a]
+        ok &= unknown_c[idx]
+        rows.append(np.nonzero(ok)[0])
+        cols.append(idx[ok])
+        vals.append(w[ok])
+    P = sp.csr_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, Ncn))
+    tot = np.asarray(P.sum(axis=1)).ravel()
+    P = (sp.diags(np.where(tot > 0, 1.0 / np.where(tot > 0, tot, 1.0), 0.0)) @ P).tocsr()
+    par = np.zeros(N, dtype=np.int64)
+    stride = 1
+    for a in range(dim):
+        par += (ijk[a] // 2) * stride
+        stride *= nc[a]
+    C = sp.csr_matrix((np.ones(N), (np.arange(N), par)), shape=(N, Ncn))
+    R = (C.T / float(2 ** dim)).tocsr()
+    return P, R, par
+
+
+def mg_levels(mesh, A, uidx, max_coarse=MG_MAX_COARSE):
+    """Level hierarchy of the PPE matrix A (over the unknowns uidx of the
+    mesh): level 0 is A on all cells; level l+1 has unknown cells where any
+    child is unknown and A_(l+1) = R_l A_l P_l."""
+    n, periodic = tuple(mesh.n), tuple(mesh.periodic)
+    N = mesh.Nc
+    E = sp.csr_matrix((np.ones(len(uidx)), (uidx, np.arange(len(uidx)))), shape=(N, len(uidx)))
+    Al = (E @ A @ E.T).tocsr()
+    unk = np.zeros(N, dtype=bool)
+    unk[uidx] = True
+    levels = []
+    while True:
+        d = Al.diagonal()
+        dinv = np.where(unk, 1.0 / np.where(unk, d, 1.0), 0.0)
+        lev = MgLevel(n, periodic, unk, Al, dinv)
+        levels.append(lev)
+        nc = _mg_coarse_dims(n, periodic)
+        if nc is None or int(np.prod(n)) <= max_coarse:
+            dense = Al.toarray()
+            dense[~unk, :] = 0.0
+            dense[:, ~unk] = 0.0
+            dense[~unk, ~unk] = 1.0
+            lev.inv = np.linalg.inv(dense)
+            return levels
+        ijk = _cells_ijk(n)
+        par = np.zeros(int(np.prod(n)), dtype=np.int64)
+        stride = 1
+        for a in range(len(n)):
+            par += (ijk[a] // 2) * stride
+            stride *= nc[a]
+        unk_c = np.zeros(int(np.prod(nc)), dtype=bool)
+        unk_c[par[unk]] = True
+        lev.P, lev.R, _ = mg_transfer(n, periodic, unk, unk_c, nc)
+        Al = (lev.R @ Al @ lev.P).tocsr()
+        n, unk = nc, unk_c
+
+
+def mg_vcycle(levels, b, level=0, omega=MG_OMEGA):
+    """One V-cycle x ~ A^-1 b on level `level` (b over the level's cells):
+    x = w D^-1 b; coarse right-hand side R (b - A x); x += P (V-cycle of
+    it); x += w D^-1 (b - A x).  The coarsest level is solved densely."""
+    lev = levels[level]
+    if lev.inv is not None:
+        return lev.inv @ b
+    x = omega * lev.dinv * b
+    bc = lev.R @ (b - lev.A @ x)
+    x = x + lev.P @ mg_vcycle(levels, bc, level + 1, omega)
+    return x + omega * lev.dinv * (b - lev.A @ x)
 
 
 def fp32_operator(A, vec_dtype):
