@@ -57,7 +57,7 @@ enum { MCD_WEIGHT_COS2 = 0, MCD_WEIGHT_GAUSS = 1 };
  *                FP64 matrix and replaced (Krylov space kept). */
 enum { MCD_PREC_FP64 = 0, MCD_PREC_FP32_REFINE = 1, MCD_PREC_FP32_MATRIX = 2 };
 enum { MCD_GUESS_ZERO = 0, MCD_GUESS_CALLER = 1 };
-enum { MCD_PRECOND_NONE = 0, MCD_PRECOND_JACOBI = 1 };
+enum { MCD_PRECOND_NONE = 0, MCD_PRECOND_JACOBI = 1, MCD_PRECOND_MG = 2 };
 
 #define MCD_MAX_IDS 16      /* boundary ids 1 .. 15 */
 #define MCD_MAX_BODIES 8
@@ -336,7 +336,15 @@ typedef struct {
                             for the FP32 modes), the residual and the stopping rule stay those
                             of A x = b, and the tolerance is confirmed on A (a miss is finished
                             by unpreconditioned FP64 Bi-CGSTAB within max_iter).  Columns with
-                            a zero or non-finite diagonal are not scaled. */
+                            a zero or non-finite diagonal are not scaled.
+                            MCD_PRECOND_MG (precision must be FP64): Bi-CGSTAB in FP64 on the
+                            FP64 matrix, right-preconditioned by one multigrid V-cycle in FP32
+                            (geometric coarsening by 2 per axis down to at most 64 cells,
+                            multilinear prolongation, averaging restriction, Galerkin coarse
+                            operators R A P built for every solve, one damped-Jacobi sweep
+                            (0.8) before and after each coarse correction, dense solve on the
+                            coarsest level); MCD_ERR_ARG when the mesh cannot be coarsened
+                            that far (an odd periodic axis or an axis below 6 cells). */
 } mcd_solve_opts;
 
 typedef struct {
@@ -359,6 +367,14 @@ typedef struct {
  * memory.  Returns MCD_ERR_NOT_CONVERGED if the tolerance was not met. */
 mcd_status mcd_solve_ppe(mcd_ctx* ctx, int set, const double* rhs, const double* neumann_f,
                          double* p, const mcd_solve_opts* opts, mcd_solve_info* info);
+
+/* One V-cycle of the multigrid preconditioner (MCD_PRECOND_MG) of set's PPE
+ * matrix: out ~ A^-1 in, with the hierarchy built from the set (not from
+ * the paper: the preconditioner of the mixed form).  in: [Nc] f64 device,
+ * read at unknown cells; out: [Nc] f64 device, zero at other cells;
+ * levels: host int, the number of levels.  Synchronises.  MCD_ERR_ARG for
+ * an unbuilt set or a mesh that cannot be coarsened to 64 cells. */
+mcd_status mcd_mg_apply(mcd_ctx* ctx, int set, const double* in, double* out, int* levels);
 
 /* Residual of the PPE of set `set` at p (Sec. 3.3, the pressure Poisson
  * equation as assembled for mcd_solve_ppe): r = b_eff - A p on unknown rows,

@@ -24,6 +24,7 @@ SOURCES = {
     "krylov.hip": [],
     "unet.hip": [],
     "wide.hip": [],
+    "mg.hip": [],
     "api.hip": [],
 }
 

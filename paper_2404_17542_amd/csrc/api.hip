@@ -695,8 +695,13 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
         (opts->precision != MCD_PREC_FP64 && opts->precision != MCD_PREC_FP32_REFINE &&
          opts->precision != MCD_PREC_FP32_MATRIX) ||
         (opts->guess != MCD_GUESS_ZERO && opts->guess != MCD_GUESS_CALLER) ||
-        (opts->precond != MCD_PRECOND_NONE && opts->precond != MCD_PRECOND_JACOBI))
+        (opts->precond != MCD_PRECOND_NONE && opts->precond != MCD_PRECOND_JACOBI &&
+         opts->precond != MCD_PRECOND_MG))
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid options%s");
+    if (opts->precond == MCD_PRECOND_MG && opts->precision != MCD_PREC_FP64)
+        return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: the multigrid preconditioner takes precision FP64 (its cycle runs in FP32)%s");
+    if (opts->precond == MCD_PRECOND_MG && !krylov_mg_usable(c->kw))
+        return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: this mesh cannot be coarsened to 64 cells (multigrid)%s");
     if (opts->precision != MCD_PREC_FP64 &&
         (!(opts->inner_tol > 0) || !(opts->inner_tol < 1) || opts->max_outer < 1 || opts->max_inner < 0 ||
          !(opts->fp64_below >= 0) || !(opts->fp64_below < 1)))
@@ -719,6 +724,17 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
     info->rhs_norm = o.bnorm;
     if (bad) return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: non-finite right-hand side%s");
     if (!o.converged) return fail(c, MCD_ERR_NOT_CONVERGED, "mcd_solve_ppe: tolerance not reached%s");
+    return MCD_OK;
+}
+
+mcd_status mcd_mg_apply(mcd_ctx* c, int set, const double* in, double* out, int* levels) {
+    if (!c) return MCD_ERR_ARG;
+    NO_CAPTURE(c, "mcd_mg_apply");
+    if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_mg_apply: set not built%s");
+    if (!in || !out || !levels) return fail(c, MCD_ERR_ARG, "mcd_mg_apply: null argument%s");
+    if (!krylov_mg_usable(c->kw))
+        return fail(c, MCD_ERR_ARG, "mcd_mg_apply: this mesh cannot be coarsened to 64 cells%s");
+    HIPCHK(c, krylov_mg_apply(c->m, *c->kw, c->sets[set].dev, in, out, levels, c->stream), "mcd_mg_apply");
     return MCD_OK;
 }
 

@@ -549,6 +549,9 @@ struct SolveOut {
 hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out);
 void krylov_free(KrylovWork* w);
 hipError_t krylov_profile(KrylovWork* w, int enable);
+bool krylov_mg_usable(const KrylovWork* w);
+hipError_t krylov_mg_apply(const MeshDev& m, KrylovWork& w, const SetDev& set, const double* in, double* out,
+                           int* levels, hipStream_t st);
 hipError_t krylov_set_shape(const MeshDev& m, KrylovWork& w, int grid, int depth);
 void krylov_get_shape(const KrylovWork& w, int* grid, int* depth, int* blocks);
 hipError_t krylov_autotune(const MeshDev& m, const SetDev& set, KrylovWork& w, int iters, int max_cand,
@@ -557,6 +560,25 @@ void krylov_profile_read(KrylovWork* w, double* ms_p, long long* n_p, double* ms
                          long long* n32, int reset);
 hipError_t solve_ppe_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
                           double* p, const SolveParams& sp, SolveOut* out, int* bad, hipStream_t st);
+// Multigrid preconditioner and the Bi-CGSTAB that uses it (mg.hip).
+struct MgWork;
+struct MgVecs {
+    double *x, *r, *rhat, *p, *v, *s, *t, *ph, *sh;   // [Nc] FP64
+    const double* b;                                  // effective right-hand side
+};
+struct MgResult {
+    int iterations = 0, restarts = 0, converged = 0, coarse_singular = 0;
+    double rel = 0.0, bnorm = 0.0;
+};
+hipError_t mg_alloc(const MeshDev& m, MgWork** out);
+void mg_free(MgWork* w);
+bool mg_usable(const MgWork* w);
+hipError_t mg_setup(const MeshDev& m, MgWork& w, const SetDev& set, hipStream_t st);
+hipError_t mg_bicgstab(const MeshDev& m, MgWork& w, const SetDev& set, const MgVecs& V, double tol, int max_iter,
+                       hipStream_t st, MgResult* out);
+hipError_t mg_apply(const MeshDev& m, MgWork& w, const SetDev& set, const double* in, double* out, int* levels,
+                    hipStream_t st);
+
 hipError_t noalloc_setup(int device);
 size_t noalloc_scratch_bytes();
 hipError_t ppe_residual_noalloc_impl(int device, const MeshDev& m, const SetDev& set, const double* rhs,

@@ -1262,6 +1262,7 @@ struct KrylovWork {
     long long cnt[2] = {0, 0};
     double ms32[2] = {0.0, 0.0};   // the part of them that read the FP32 matrix
     long long cnt32[2] = {0, 0};
+    MgWork* mg = nullptr;          // multigrid hierarchy (MCD_PRECOND_MG)
 };
 
 // Enqueues one Bi-CGSTAB iteration (P-stage in `mode`, then S-stage) with
@@ -1512,6 +1513,21 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     // the operator the Krylov iterations see: A, or A D^-1 with Jacobi
     const double* A64 = set.amat;
     const float* A32 = set.amat32;
+    if (sp.precond == MCD_PRECOND_MG) {
+        // FP64 Bi-CGSTAB right-preconditioned by one FP32 V-cycle; p[1] and
+        // v[1] hold the preconditioned directions
+        const MgVecs mv{w.v64.x, w.v64.r, w.v64.rhat, w.v64.p[0], w.v64.v[0], w.v64.s, w.v64.t, w.v64.p[1],
+                        w.v64.v[1], w.beff};
+        MgResult res;
+        if ((e = mg_bicgstab(m, *w.mg, set, mv, sp.tol, sp.max_iter, st, &res)) != hipSuccess) return e;
+        out->iterations = res.iterations;
+        out->restarts = res.restarts;
+        out->converged = res.converged;
+        out->rel = res.rel;
+        out->bnorm = res.bnorm;
+        hipLaunchKernelGGL(k_writeback, dim3(g), dim3(kBlock), 0, st, m.Nc, set.unknown, w.v64.x, p);
+        return hipGetLastError();
+    }
     const bool jacobi = sp.precond == MCD_PRECOND_JACOBI;
     if (jacobi) {
         hipLaunchKernelGGL(k_jacobi_diag<DIM>, dim3(g), dim3(kBlock), 0, st, m, set.amat, set.unknown, w.dinv,
@@ -2039,6 +2055,7 @@ hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     if ((e = hipHostMalloc((void**)&w->host, 2 * sizeof(KState), hipHostMallocDefault)) != hipSuccess) return e;
     for (int i = 0; i < 2; ++i)
         if ((e = hipEventCreateWithFlags(&w->ev[i], hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = mg_alloc(m, &w->mg)) != hipSuccess) return e;
     if ((e = alloc_vec(w->v64, m.mps)) != hipSuccess) return e;
     if ((e = alloc_vec(w->v32, m.mps)) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->beff, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
@@ -2053,6 +2070,15 @@ hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     if ((e = hipStreamCreateWithFlags(&w->st, hipStreamNonBlocking)) != hipSuccess) return e;
     if ((e = hipEventCreateWithFlags(&w->join, hipEventDisableTiming)) != hipSuccess) return e;
     return hipSuccess;
+}
+
+bool krylov_mg_usable(const KrylovWork* w) { return mg_usable(w->mg); }
+
+hipError_t krylov_mg_apply(const MeshDev& m, KrylovWork& w, const SetDev& set, const double* in, double* out,
+                           int* levels, hipStream_t st) {
+    hipError_t e = mg_apply(m, *w.mg, set, in, out, levels, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    return e;
 }
 
 hipError_t krylov_profile(KrylovWork* w, int enable) {
@@ -2101,6 +2127,7 @@ void krylov_free(KrylovWork* w) {
         if (w->ev[i]) (void)hipEventDestroy(w->ev[i]);
     free_vec(w->v64);
     free_vec(w->v32);
+    mg_free(w->mg);
     if (w->beff) (void)hipFree(w->beff);
     if (w->b32) (void)hipFree(w->b32);
     if (w->xsave) (void)hipFree(w->xsave);

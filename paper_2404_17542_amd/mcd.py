@@ -23,7 +23,7 @@ BC_DIRICHLET, BC_NEUMANN = 0, 1
 WEIGHT_COS2, WEIGHT_GAUSS = 0, 1
 PREC_FP64, PREC_FP32_REFINE, PREC_FP32_MATRIX = 0, 1, 2
 GUESS_ZERO, GUESS_CALLER = 0, 1
-PRECOND_NONE, PRECOND_JACOBI = 0, 1
+PRECOND_NONE, PRECOND_JACOBI, PRECOND_MG = 0, 1, 2
 OP_PHI, OP_GRAD, OP_LAP, OP_DIV, OP_SHIFT = 0, 1, 2, 3, 4
 MAX_IDS = 16
 MAX_BODIES = 8
@@ -31,7 +31,8 @@ MAX_SETS = 4
 
 EXPORTED = ("mcd_create", "mcd_destroy", "mcd_pending_destroys", "mcd_set_stream", "mcd_sync", "mcd_last_error", "mcd_update_dps",
             "mcd_build_stencils", "mcd_get_stencils", "mcd_apply", "mcd_remap", "mcd_advect_diffuse",
-            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_ppe_residual", "mcd_ppe_residual_noalloc",
+            "mcd_neumann_pressure", "mcd_project", "mcd_solve_ppe", "mcd_mg_apply", "mcd_ppe_residual",
+            "mcd_ppe_residual_noalloc",
             "mcd_noalloc_scratch_bytes", "mcd_profile",
             "mcd_profile_read", "mcd_profile_read_split", "mcd_autotune", "mcd_set_shape", "mcd_get_shape", "mcd_fluid_force",
             "mcd_model_create", "mcd_model_destroy", "mcd_model_num_params", "mcd_model_set_params",
@@ -128,6 +129,7 @@ def load():
         "mcd_solve_ppe": (i, [vp, i, vp, vp, vp, P(SolveOpts), P(SolveInfo)]),
         "mcd_ppe_residual": (i, [vp, i, vp, vp, vp, vp, P(d)]),
         "mcd_ppe_residual_noalloc": (i, [vp, i, vp, vp, vp, vp, P(d)]),
+        "mcd_mg_apply": (i, [vp, i, vp, vp, P(i)]),
         "mcd_noalloc_scratch_bytes": (C.c_size_t, []),
         "mcd_pending_destroys": (i, []),
         "mcd_profile": (i, [vp, i]),
@@ -403,6 +405,14 @@ class Context:
         self._check(self.lib.mcd_ppe_residual(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), V(r, N),
                                               norms), "mcd_ppe_residual")
         return norms[0], norms[1]
+
+    def mg_apply(self, set_id, inp, out):
+        """One V-cycle of the set's multigrid preconditioner (mcd_mg_apply);
+        returns the number of levels."""
+        lv = C.c_int()
+        N, V = self.Nc, self._vec
+        self._check(self.lib.mcd_mg_apply(self.h, int(set_id), V(inp, N), V(out, N), C.byref(lv)), "mcd_mg_apply")
+        return lv.value
 
     def ppe_residual_noalloc(self, set_id, rhs, p, r, neumann_f=None):
         """mcd_ppe_residual_noalloc: the same residual with the library's fixed
