@@ -1,6 +1,7 @@
 """Whole steps at the benchmark sizes against the FP64 oracle, in both forms
 of the metric: the plain FP64 method and the learned initial guess with the
-FP32-stored matrix (mixed precision).
+FP32 multigrid-preconditioned solve (mixed precision), and also the learned
+guess with the FP32-stored matrix.
 
 1024^2 oscillating cylinder and 128^3 moving sphere: after the initial
 arrangement and one projection step, the DP arrays are bit-exact; the GPU's
@@ -43,7 +44,11 @@ def _gpu_step(M, case, form):
     from paper_2404_17542_amd.sim import GpuSim
     if form == "plain":
         g = GpuSim(case)
-    else:
+    elif form == "learned_mixed":
+        g = GpuSim(case, precond=M.PRECOND_MG)
+        g.model = learned.load_model(g.ctx, WEIGHTS[case.dim])
+        g.guess = "learned"
+    else:                                   # the FP32-stored matrix without a preconditioner
         g = GpuSim(case, precision=M.PREC_FP32_MATRIX)
         g.model = learned.load_model(g.ctx, WEIGHTS[case.dim])
         g.guess = "learned"
@@ -58,7 +63,7 @@ def _gpu_step(M, case, form):
 
 
 def _check(M, case, u_bar_plain):
-    forms = {f: _gpu_step(M, case, f) for f in ("plain", "learned_mixed")}
+    forms = {f: _gpu_step(M, case, f) for f in ("plain", "learned_mixed", "learned_fp32_matrix")}
     o0 = OracleSim(case)
     init = (o0.pos.copy(), o0.role.copy())
     ro = o0.step()
