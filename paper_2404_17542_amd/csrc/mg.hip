@@ -40,6 +40,7 @@ struct MgLevel {
     float* x = nullptr;          // [N] work
     float* y = nullptr;          // [N] the level's cycle result
     float* b = nullptr;          // [N] the level's right-hand side
+    float* pn = nullptr;         // [N] 1 / row sum of the raw prolongation weights into the next level
 };
 
 struct MgWork {
@@ -58,7 +59,7 @@ struct MgWork {
 // Level geometry
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ int mg_cell(const MeshDev& m, const int ijk[3]) {
+__device__ __forceinline__ int mg_cell(const MeshDev& m, const int* ijk) {
     return ijk[0] + m.n[0] * (ijk[1] + m.n[1] * ijk[2]);
 }
 
@@ -71,12 +72,11 @@ __device__ __forceinline__ bool mg_coord(const MeshDev& mc, int a, int& v) {
     return true;
 }
 
-// Prolongation weights of fine cell j (coordinates jf): up to 2^DIM unknown
-// coarse cells (coordinates kc) and their renormalised weights.
+// Sum of the raw prolongation weights of fine cell j (coordinates jf) over
+// its valid coarse cells (inside the mesh or wrapped, unknown): the
+// normalisation of P's row j.
 template <int DIM>
-__device__ __forceinline__ int mg_pweights(const MeshDev& mc, const uint8_t* __restrict__ unk_c, const int jf[3],
-                                           int kc[][3], float* w) {
-    int n = 0;
+__device__ __forceinline__ float mg_pweight_sum(const MeshDev& mc, const uint8_t* __restrict__ unk_c, const int jf[3]) {
     float tot = 0.0f;
 #pragma unroll
     for (int corner = 0; corner < (1 << DIM); ++corner) {
@@ -92,21 +92,36 @@ __device__ __forceinline__ int mg_pweights(const MeshDev& mc, const uint8_t* __r
             k[a] = v;
             wt *= far ? 0.25f : 0.75f;
         }
-        if (!ok || !unk_c[mg_cell(mc, k)]) continue;
-        kc[n][0] = k[0];
-        kc[n][1] = k[1];
-        kc[n][2] = k[2];
-        w[n] = wt;
-        tot += wt;
-        ++n;
+        if (ok && unk_c[mg_cell(mc, k)]) tot += wt;
     }
-    for (int q = 0; q < n; ++q) w[q] /= tot;
-    return n;
+    return tot;
+}
+
+// Calls f(K, w) for every valid coarse cell K of fine cell j with its raw
+// weight w (3/4 or 1/4 per axis; divide by mg_pweight_sum for P).
+template <int DIM, typename F>
+__device__ __forceinline__ void mg_pvisit(const MeshDev& mc, const uint8_t* __restrict__ unk_c, const int jf[3], F f) {
+#pragma unroll
+    for (int corner = 0; corner < (1 << DIM); ++corner) {
+        int k[3] = {0, 0, 0};
+        float wt = 1.0f;
+        bool ok = true;
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            const int far = (corner >> a) & 1;
+            const int side = (jf[a] % 2 == 0) ? -1 : 1;
+            int v = jf[a] / 2 + side * far;
+            ok = ok && mg_coord(mc, a, v);
+            k[a] = v;
+            wt *= far ? 0.25f : 0.75f;
+        }
+        if (ok && unk_c[mg_cell(mc, k)]) f(k, wt);
+    }
 }
 
 // Slot of the coarse offset K - I (periodic axes wrapped into -1..1).
 template <int DIM>
-__device__ __forceinline__ int mg_slot(const MeshDev& mc, const int K[3], const int I[3]) {
+__device__ __forceinline__ int mg_slot(const MeshDev& mc, const int* K, const int* I) {
     int s = 0, mul = 1;
 #pragma unroll
     for (int a = 0; a < DIM; ++a) {
@@ -121,8 +136,22 @@ __device__ __forceinline__ int mg_slot(const MeshDev& mc, const int K[3], const 
     return s;
 }
 
+// Element offset of stencil slot s for a cell away from the mesh edges.
+template <int DIM>
+__device__ __forceinline__ int mg_off(const MeshDev& m, int s) {
+    return (s % 3 - 1) + (DIM > 1 ? ((s / 3) % 3 - 1) * m.n[0] : 0) + (DIM > 2 ? (s / 9 - 1) * m.n[0] * m.n[1] : 0);
+}
+
+template <int DIM>
+__device__ __forceinline__ bool mg_interior(const MeshDev& m, const int ijk[3]) {
+    bool in = ijk[0] > 0 && ijk[0] < m.n[0] - 1 && ijk[1] > 0 && ijk[1] < m.n[1] - 1;
+    if (DIM == 3) in = in && ijk[2] > 0 && ijk[2] < m.n[2] - 1;
+    return in;
+}
+
 // (A x)_c of a level operator: FP32 difference form (level 0: sum a_j (x_j -
-// x_c) + rowsum x_c) or plain form (coarse levels).
+// x_c) + rowsum x_c) or plain form (coarse levels).  Cells away from the
+// mesh edges use constant slot offsets.
 template <int DIM, bool DIFF>
 __device__ __forceinline__ float mg_spmv(const MeshDev& m, const float* __restrict__ A, int c,
                                          const float* __restrict__ x) {
@@ -131,6 +160,17 @@ __device__ __forceinline__ float mg_spmv(const MeshDev& m, const float* __restri
     cell_ijk(m, c, ijk);
     const float xc = x[c];
     float acc = 0.0f;
+    if (mg_interior<DIM>(m, ijk)) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            const float a = ld_stream(A + (size_t)s * m.mps + c);
+            if (s == CEN)
+                acc += a * xc;
+            else
+                acc += DIFF ? a * (x[c + mg_off<DIM>(m, s)] - xc) : a * x[c + mg_off<DIM>(m, s)];
+        }
+        return acc;
+    }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const float a = ld_stream(A + (size_t)s * m.mps + c);
@@ -153,6 +193,11 @@ __device__ __forceinline__ double mg_spmv64(const MeshDev& m, const double* __re
     int ijk[3];
     cell_ijk(m, c, ijk);
     double acc = 0.0;
+    if (mg_interior<DIM>(m, ijk)) {
+#pragma unroll
+        for (int s = 0; s < S; ++s) acc += ld_stream(A + (size_t)s * m.mps + c) * val(c + mg_off<DIM>(m, s));
+        return acc;
+    }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
         const double a = ld_stream(A + (size_t)s * m.mps + c);
@@ -198,29 +243,58 @@ __global__ void k_mg_flags(MeshDev mf, const uint8_t* __restrict__ unk_f, MeshDe
     }
 }
 
-// A_c = R A_f P for every coarse row I (FP64 accumulation), and its 1/diag.
+// 1 / (sum of the raw prolongation weights) of every unknown fine cell (0 at
+// other cells): P[j][K] = w(j, K) * pn[j].
+template <int DIM>
+__global__ void k_mg_pnorm(MeshDev mf, const uint8_t* __restrict__ unk_f, MeshDev mc, const uint8_t* __restrict__ unk_c,
+                           float* __restrict__ pn) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < mf.Nc; j += gridDim.x * blockDim.x) {
+        float v = 0.0f;
+        if (unk_f[j]) {
+            int fj[3];
+            cell_ijk(mf, j, fj);
+            const float t = mg_pweight_sum<DIM>(mc, unk_c, fj);
+            v = t > 0.0f ? 1.0f / t : 0.0f;
+        }
+        pn[j] = v;
+    }
+}
+
+// A_c = R A_f P.  A block takes kMgGalCells coarse cells; each of its
+// threads takes one child i of one of them and adds a_s(i) P[j(i, s)][K] to
+// its own row of LDS accumulators at the slot of K - I (FP64); the 2^DIM
+// children's rows are then summed in child order per slot.
+template <int DIM> struct MgGal;
+template <> struct MgGal<2> { static constexpr int CELLS = 64; };
+template <> struct MgGal<3> { static constexpr int CELLS = 32; };
+
 template <int DIM, typename TA>
-__global__ void k_mg_galerkin(MeshDev mf, const TA* __restrict__ Af, const uint8_t* __restrict__ unk_f, MeshDev mc,
-                              const uint8_t* __restrict__ unk_c, float* __restrict__ Ac, float* __restrict__ dinv_c) {
-    constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
-    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < mc.Nc; I += gridDim.x * blockDim.x) {
-        double acc[S];
+__global__ __launch_bounds__(kBlock) void k_mg_galerkin(MeshDev mf, const TA* __restrict__ Af,
+                                                        const uint8_t* __restrict__ unk_f,
+                                                        const float* __restrict__ pn, MeshDev mc,
+                                                        const uint8_t* __restrict__ unk_c, float* __restrict__ Ac,
+                                                        float* __restrict__ dinv_c) {
+    constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN, CH = 1 << DIM, CELLS = MgGal<DIM>::CELLS;
+    static_assert(CELLS * CH == kBlock, "one child per thread");
+    __shared__ double acc[CELLS][CH][S];
+    const int cl = threadIdx.x / CH, ch = threadIdx.x % CH;
+    for (int base = blockIdx.x * CELLS; base < mc.Nc; base += gridDim.x * CELLS) {
+        const int I = base + cl;
+        double* row = acc[cl][ch];
 #pragma unroll
-        for (int s = 0; s < S; ++s) acc[s] = 0.0;
-        int ic[3];
-        cell_ijk(mc, I, ic);
-        if (unk_c[I]) {
-            for (int ch = 0; ch < (1 << DIM); ++ch) {
-                int fi[3] = {0, 0, 0};
-                bool in = true;
+        for (int t = 0; t < S; ++t) row[t] = 0.0;
+        if (I < mc.Nc && unk_c[I]) {
+            int ic[3];
+            cell_ijk(mc, I, ic);
+            int fi[3] = {0, 0, 0};
+            bool in = true;
 #pragma unroll
-                for (int a = 0; a < DIM; ++a) {
-                    fi[a] = 2 * ic[a] + ((ch >> a) & 1);
-                    in = in && fi[a] < mf.n[a];
-                }
-                if (!in) continue;
-                const int i = mg_cell(mf, fi);
-                if (!unk_f[i]) continue;
+            for (int a = 0; a < DIM; ++a) {
+                fi[a] = 2 * ic[a] + ((ch >> a) & 1);
+                in = in && fi[a] < mf.n[a];
+            }
+            const int i = in ? mg_cell(mf, fi) : 0;
+            if (in && unk_f[i]) {
                 for (int s = 0; s < S; ++s) {
                     const double a = (double)Af[(size_t)s * mf.mps + i];
                     if (a == 0.0) continue;
@@ -229,18 +303,26 @@ __global__ void k_mg_galerkin(MeshDev mf, const TA* __restrict__ Af, const uint8
                     if (!neighbour<DIM>(mf, fi, s, j, sh)) continue;
                     int fj[3];
                     cell_ijk(mf, j, fj);
-                    int kc[1 << DIM][3];
-                    float w[1 << DIM];
-                    const int nk = mg_pweights<DIM>(mc, unk_c, fj, kc, w);
-                    for (int q = 0; q < nk; ++q) acc[mg_slot<DIM>(mc, kc[q], ic)] += a * (double)w[q];
+                    const double aw = a * (double)pn[j];
+                    mg_pvisit<DIM>(mc, unk_c, fj, [&](const int* K, float w) {
+                        row[mg_slot<DIM>(mc, K, ic)] += aw * (double)w;
+                    });
                 }
             }
         }
-        const double scale = 1.0 / (double)(1 << DIM);
+        __syncthreads();
+        if (I < mc.Nc) {
+            const double scale = 1.0 / (double)CH;
+            for (int t = ch; t < S; t += CH) {
+                double v = 0.0;
 #pragma unroll
-        for (int s = 0; s < S; ++s) Ac[(size_t)s * mc.mps + I] = (float)(acc[s] * scale);
-        const double d = acc[CEN] * scale;
-        dinv_c[I] = (unk_c[I] && d != 0.0 && isfinite(d)) ? (float)(1.0 / d) : 0.0f;
+                for (int c = 0; c < CH; ++c) v += acc[cl][c][t];
+                v *= scale;
+                Ac[(size_t)t * mc.mps + I] = (float)v;
+                if (t == CEN) dinv_c[I] = (unk_c[I] && v != 0.0 && isfinite(v)) ? (float)(1.0 / v) : 0.0f;
+            }
+        }
+        __syncthreads();
     }
 }
 
@@ -324,10 +406,17 @@ __global__ void k_mg_scale(int N, const float* __restrict__ dinv, const float* _
         x[c] = kMgOmega * dinv[c] * b[c];
 }
 
+// r = b - A x at unknown cells (0 elsewhere).
 template <int DIM, bool DIFF>
-__global__ void k_mg_restrict(MeshDev mf, const float* __restrict__ Af, const uint8_t* __restrict__ unk_f,
-                              const float* __restrict__ xf, const float* __restrict__ bf, MeshDev mc,
-                              float* __restrict__ bc) {
+__global__ void k_mg_resid(MeshDev m, const float* __restrict__ A, const uint8_t* __restrict__ unk,
+                           const float* __restrict__ x, const float* __restrict__ b, float* __restrict__ r) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x)
+        r[c] = unk[c] ? b[c] - mg_spmv<DIM, DIFF>(m, A, c, x) : 0.0f;
+}
+
+// Coarse right-hand side: the mean of the children's residuals (R).
+template <int DIM>
+__global__ void k_mg_average(MeshDev mf, const float* __restrict__ rf, MeshDev mc, float* __restrict__ bc) {
     for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < mc.Nc; I += gridDim.x * blockDim.x) {
         int ic[3];
         cell_ijk(mc, I, ic);
@@ -341,27 +430,23 @@ __global__ void k_mg_restrict(MeshDev mf, const float* __restrict__ Af, const ui
                 f[a] = 2 * ic[a] + ((ch >> a) & 1);
                 in = in && f[a] < mf.n[a];
             }
-            if (!in) continue;
-            const int i = mg_cell(mf, f);
-            if (unk_f[i]) sum += bf[i] - mg_spmv<DIM, DIFF>(mf, Af, i, xf);
+            if (in) sum += rf[mg_cell(mf, f)];
         }
         bc[I] = sum * (1.0f / (float)(1 << DIM));
     }
 }
 
 template <int DIM>
-__global__ void k_mg_prolong(MeshDev mf, const uint8_t* __restrict__ unk_f, float* __restrict__ xf, MeshDev mc,
-                             const uint8_t* __restrict__ unk_c, const float* __restrict__ yc) {
+__global__ void k_mg_prolong(MeshDev mf, const uint8_t* __restrict__ unk_f, const float* __restrict__ pn,
+                             float* __restrict__ xf, MeshDev mc, const uint8_t* __restrict__ unk_c,
+                             const float* __restrict__ yc) {
     for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < mf.Nc; j += gridDim.x * blockDim.x) {
         if (!unk_f[j]) continue;
         int fj[3];
         cell_ijk(mf, j, fj);
-        int kc[1 << DIM][3];
-        float w[1 << DIM];
-        const int nk = mg_pweights<DIM>(mc, unk_c, fj, kc, w);
         float add = 0.0f;
-        for (int q = 0; q < nk; ++q) add += w[q] * yc[mg_cell(mc, kc[q])];
-        xf[j] += add;
+        mg_pvisit<DIM>(mc, unk_c, fj, [&](const int* K, float w) { add += w * yc[mg_cell(mc, K)]; });
+        xf[j] += add * pn[j];
     }
 }
 
@@ -414,6 +499,7 @@ hipError_t mg_alloc(const MeshDev& m, MgWork** out) {
         falloc(&L.x, (size_t)cur.Nc);
         falloc(&L.y, (size_t)cur.Nc);
         falloc(&L.b, (size_t)cur.Nc);
+        falloc(&L.pn, (size_t)cur.Nc);
         w->L = l + 1;
         // the next level, unless this one is the coarsest
         MeshDev nx = cur;
@@ -452,7 +538,7 @@ void mg_free(MgWork* w) {
     for (int l = 0; l < w->L; ++l) {
         MgLevel& L = w->lev[l];
         // level 0 borrows the set's matrix and flags while a solve runs
-        float* f[5] = {l > 0 ? L.A : nullptr, L.dinv, L.x, L.y, L.b};
+        float* f[6] = {l > 0 ? L.A : nullptr, L.dinv, L.x, L.y, L.b, L.pn};
         for (float* p : f)
             if (p) (void)hipFree(p);
         if (l > 0 && L.unk) (void)hipFree(L.unk);
@@ -484,12 +570,15 @@ static hipError_t mg_setup_dim(MgWork& w, const SetDev& set, hipStream_t st) {
         MgLevel& F = w.lev[l];
         MgLevel& C = w.lev[l + 1];
         hipLaunchKernelGGL(k_mg_flags<DIM>, dim3(grid_for(C.m.Nc)), dim3(kBlock), 0, st, F.m, F.unk, C.m, C.unk);
+        hipLaunchKernelGGL(k_mg_pnorm<DIM>, dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.unk, C.m, C.unk, F.pn);
+        const int gb = (C.m.Nc + MgGal<DIM>::CELLS - 1) / MgGal<DIM>::CELLS;
+        const dim3 gg(gb > 8192 ? 8192 : gb);
         if (l == 0)
-            hipLaunchKernelGGL((k_mg_galerkin<DIM, double>), dim3(grid_for(C.m.Nc)), dim3(kBlock), 0, st, F.m,
-                               set.amat, F.unk, C.m, C.unk, C.A, C.dinv);
+            hipLaunchKernelGGL((k_mg_galerkin<DIM, double>), gg, dim3(kBlock), 0, st, F.m, set.amat, F.unk, F.pn, C.m,
+                               C.unk, C.A, C.dinv);
         else
-            hipLaunchKernelGGL((k_mg_galerkin<DIM, float>), dim3(grid_for(C.m.Nc)), dim3(kBlock), 0, st, F.m, F.A,
-                               F.unk, C.m, C.unk, C.A, C.dinv);
+            hipLaunchKernelGGL((k_mg_galerkin<DIM, float>), gg, dim3(kBlock), 0, st, F.m, F.A, F.unk, F.pn, C.m, C.unk,
+                               C.A, C.dinv);
     }
     const MgLevel& Lc = w.lev[w.L - 1];
     hipLaunchKernelGGL(k_mg_zero_flag, dim3(1), dim3(64), 0, st, w.flag);
@@ -513,20 +602,22 @@ static void mg_cycle_dim(MgWork& w, hipStream_t st) {
         MgLevel& F = w.lev[l];
         MgLevel& C = w.lev[l + 1];
         hipLaunchKernelGGL(k_mg_scale, dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m.Nc, F.dinv, F.b, F.x);
+        // the level's residual goes to y (its cycle result is written only later)
         if (l == 0)
-            hipLaunchKernelGGL((k_mg_restrict<DIM, true>), dim3(grid_for(C.m.Nc)), dim3(kBlock), 0, st, F.m, F.A,
-                               F.unk, F.x, F.b, C.m, C.b);
+            hipLaunchKernelGGL((k_mg_resid<DIM, true>), dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.A, F.unk,
+                               F.x, F.b, F.y);
         else
-            hipLaunchKernelGGL((k_mg_restrict<DIM, false>), dim3(grid_for(C.m.Nc)), dim3(kBlock), 0, st, F.m, F.A,
-                               F.unk, F.x, F.b, C.m, C.b);
+            hipLaunchKernelGGL((k_mg_resid<DIM, false>), dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.A, F.unk,
+                               F.x, F.b, F.y);
+        hipLaunchKernelGGL(k_mg_average<DIM>, dim3(grid_for(C.m.Nc)), dim3(kBlock), 0, st, F.m, F.y, C.m, C.b);
     }
     const MgLevel& Lc = w.lev[w.L - 1];
     hipLaunchKernelGGL(k_mg_coarse_solve, dim3(1), dim3(256), 0, st, w.inv, Lc.m.Nc, Lc.unk, Lc.b, Lc.y);
     for (int l = w.L - 2; l >= 0; --l) {
         MgLevel& F = w.lev[l];
         MgLevel& C = w.lev[l + 1];
-        hipLaunchKernelGGL(k_mg_prolong<DIM>, dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.unk, F.x, C.m,
-                           C.unk, C.y);
+        hipLaunchKernelGGL(k_mg_prolong<DIM>, dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.unk, F.pn, F.x,
+                           C.m, C.unk, C.y);
         if (l == 0)
             hipLaunchKernelGGL((k_mg_smooth<DIM, true>), dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.A, F.unk,
                                F.dinv, F.b, F.x, F.y);
