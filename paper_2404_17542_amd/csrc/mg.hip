@@ -268,6 +268,104 @@ template <int DIM> struct MgGal;
 template <> struct MgGal<2> { static constexpr int CELLS = 64; };
 template <> struct MgGal<3> { static constexpr int CELLS = 32; };
 
+// Per-axis prolongation weight, away from the mesh edges and unknown-cell
+// boundaries: a fine cell at offset o from child c of coarse cell I (q = c +
+// o + 1 in 0..3) lies in coarse cell I + floor((c + o) / 2) (weight 3/4) and
+// takes 1/4 from that cell's neighbour on its side; e in 0..2 is the coarse
+// offset + 1.
+__device__ __forceinline__ double mg_w1(int q, int e) {
+    const int big = (q + 1) >> 1;
+    const int small = big + ((q & 1) ? -1 : 1);
+    return e == big ? 0.75 : (e == small ? 0.25 : 0.0);
+}
+
+// Interior rows of R A P for one child (parity c[]), whose every coarse
+// neighbour is inside the mesh and unknown (so P's rows are the full
+// multilinear stencils with unit sum): the 3^d fine row contracts with the
+// per-axis weights one axis at a time.
+template <int DIM, typename TA>
+__device__ __forceinline__ void mg_gal_interior(const MeshDev& mf, const TA* __restrict__ Af, int i, const int* c,
+                                                double* row) {
+    constexpr int S = Dims<DIM>::S;
+    double a[S];
+#pragma unroll
+    for (int s = 0; s < S; ++s) a[s] = (double)Af[(size_t)s * mf.mps + i];
+    if (DIM == 2) {
+        double t1[3][3];   // [oy][ex]
+#pragma unroll
+        for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+            for (int ex = 0; ex < 3; ++ex) {
+                double v = 0.0;
+#pragma unroll
+                for (int ox = 0; ox < 3; ++ox) v += a[ox + 3 * oy] * mg_w1(c[0] + ox, ex);
+                t1[oy][ex] = v;
+            }
+#pragma unroll
+        for (int ey = 0; ey < 3; ++ey)
+#pragma unroll
+            for (int ex = 0; ex < 3; ++ex) {
+                double v = 0.0;
+#pragma unroll
+                for (int oy = 0; oy < 3; ++oy) v += t1[oy][ex] * mg_w1(c[1] + oy, ey);
+                row[ex + 3 * ey] = v;
+            }
+    } else {
+        double t1[3][3][3];   // [oz][oy][ex]
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+            for (int oy = 0; oy < 3; ++oy)
+#pragma unroll
+                for (int ex = 0; ex < 3; ++ex) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int ox = 0; ox < 3; ++ox) v += a[ox + 3 * oy + 9 * oz] * mg_w1(c[0] + ox, ex);
+                    t1[oz][oy][ex] = v;
+                }
+        double t2[3][3][3];   // [oz][ey][ex]
+#pragma unroll
+        for (int oz = 0; oz < 3; ++oz)
+#pragma unroll
+            for (int ey = 0; ey < 3; ++ey)
+#pragma unroll
+                for (int ex = 0; ex < 3; ++ex) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int oy = 0; oy < 3; ++oy) v += t1[oz][oy][ex] * mg_w1(c[1] + oy, ey);
+                    t2[oz][ey][ex] = v;
+                }
+#pragma unroll
+        for (int ez = 0; ez < 3; ++ez)
+#pragma unroll
+            for (int ey = 0; ey < 3; ++ey)
+#pragma unroll
+                for (int ex = 0; ex < 3; ++ex) {
+                    double v = 0.0;
+#pragma unroll
+                    for (int oz = 0; oz < 3; ++oz) v += t2[oz][ey][ex] * mg_w1(c[2] + oz, ez);
+                    row[ex + 3 * ey + 9 * ez] = v;
+                }
+    }
+}
+
+// True when every coarse cell of the 3^d block around I is inside the mesh
+// (no wrap) and unknown.
+template <int DIM>
+__device__ __forceinline__ bool mg_full_block(const MeshDev& mc, const uint8_t* __restrict__ unk_c, const int* ic) {
+    constexpr int S = Dims<DIM>::S;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a)
+        if (ic[a] < 1 || ic[a] > mc.n[a] - 2) return false;
+    bool all = true;
+#pragma unroll
+    for (int s = 0; s < S; ++s) {
+        const int k[3] = {ic[0] + s % 3 - 1, ic[1] + (s / 3) % 3 - 1, DIM == 3 ? ic[2] + s / 9 - 1 : 0};
+        all = all && unk_c[mg_cell(mc, k)];
+    }
+    return all;
+}
+
 template <int DIM, typename TA>
 __global__ __launch_bounds__(kBlock) void k_mg_galerkin(MeshDev mf, const TA* __restrict__ Af,
                                                         const uint8_t* __restrict__ unk_f,
@@ -294,7 +392,10 @@ __global__ __launch_bounds__(kBlock) void k_mg_galerkin(MeshDev mf, const TA* __
                 in = in && fi[a] < mf.n[a];
             }
             const int i = in ? mg_cell(mf, fi) : 0;
-            if (in && unk_f[i]) {
+            const int par[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
+            if (in && unk_f[i] && mg_full_block<DIM>(mc, unk_c, ic)) {
+                mg_gal_interior<DIM, TA>(mf, Af, i, par, row);
+            } else if (in && unk_f[i]) {
                 for (int s = 0; s < S; ++s) {
                     const double a = (double)Af[(size_t)s * mf.mps + i];
                     if (a == 0.0) continue;
