@@ -249,9 +249,9 @@ def cpu_baseline_full_steps(case, steps):
                       f"{platform.processor() or platform.machine()}, {os.cpu_count()} logical CPUs"}
 
 
-def cpu_baseline_sampled(case, iters_per_step, n_sample=1 << 16, n_iters=8):
+def _sampled_step(case, iters_per_step, n_sample, n_iters, threads):
     """The oracle's cost of one step of the full-size workload from bounded
-    samples (one thread), for workloads whose oracle step takes minutes:
+    samples, with the BLAS thread pools limited to `threads`:
       DP update   the oracle's update_dps on the whole mesh (from the seeded
                   positions and the t = 0 masks, one step's sweeps);
       weights     mls_build of the velocity and the pressure set on n_sample
@@ -262,7 +262,7 @@ def cpu_baseline_sampled(case, iters_per_step, n_sample=1 << 16, n_iters=8):
       PPE         n_iters of the oracle's Bi-CGSTAB on an operator with the
                   workload's size and 3^dim sparsity, per iteration times the
                   plain form's measured iterations per step.
-    Returns the DP-steps/s of the sum."""
+    Returns (active DPs, seconds per step, phase seconds, sample text)."""
     import numpy as np
     import scipy.sparse as sp
     from threadpoolctl import threadpool_limits
@@ -272,7 +272,7 @@ def cpu_baseline_sampled(case, iters_per_step, n_sample=1 << 16, n_iters=8):
     from paper_2404_17542_amd import inputs
 
     t_start = time.perf_counter()
-    with threadpool_limits(limits=1):
+    with threadpool_limits(limits=threads):
         m = O.Mesh.from_case(case)
         consts = O.RelaxConsts.make(case.l0, case.kappa, case.eps_relax, case.band_over_l0, case.fit_alpha,
                                     case.fit_re_over_l0)
@@ -325,18 +325,40 @@ def cpu_baseline_sampled(case, iters_per_step, n_sample=1 << 16, n_iters=8):
     scale = n_active / len(idx)
     t_step = t_update + (t_build + t_ops) * scale + t_iter * iters_per_step
     grid = "x".join(str(v) for v in case.n)
-    return {"value": n_active / t_step, "unit": "DP-steps/s", "cores": 1, "kind": "oracle",
-            "sample": (f"one step of the same {grid} workload assembled from bounded samples of the oracle "
-                       f"(numpy/scipy FP64, 1 thread): DP update on the whole mesh {t_update:.1f} s; MLS "
-                       f"weights of both sets on {len(idx)} random DPs {t_build:.1f} s and their field "
-                       f"operations {t_ops:.1f} s, both scaled by {scale:.1f} to every active DP; "
-                       f"{info.iterations} Bi-CGSTAB iterations on an operator of the workload's size and "
-                       f"sparsity, {t_iter:.3f} s each, times the plain form's {iters_per_step:.0f} "
-                       f"iterations per step; estimated step {t_step:.0f} s, measured in "
-                       f"{time.perf_counter() - t_start:.0f} s; host "
-                       f"{platform.processor() or platform.machine()}, {os.cpu_count()} logical CPUs"),
-            "phases_s": {"update": t_update, "weights": t_build * scale, "field_ops": t_ops * scale,
-                         "ppe": t_iter * iters_per_step}}
+    sample = (f"one step of the same {grid} workload assembled from bounded samples of the oracle "
+              f"(numpy/scipy FP64, BLAS limited to {threads} thread(s)): DP update on the whole mesh "
+              f"{t_update:.1f} s; MLS weights of both sets on {len(idx)} random DPs {t_build:.1f} s and their "
+              f"field operations {t_ops:.1f} s, both scaled by {scale:.1f} to every active DP; "
+              f"{info.iterations} Bi-CGSTAB iterations on an operator of the workload's size and sparsity, "
+              f"{t_iter:.3f} s each, times the plain form's {iters_per_step:.0f} iterations per step; "
+              f"estimated step {t_step:.0f} s, measured in {time.perf_counter() - t_start:.0f} s")
+    phases = {"update": t_update, "weights": t_build * scale, "field_ops": t_ops * scale,
+              "ppe": t_iter * iters_per_step}
+    return n_active, t_step, phases, sample
+
+
+def host_cores():
+    """Logical CPUs this process may run on."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count()
+
+
+def cpu_baseline_sampled(case, iters_per_step, n_sample=1 << 18, n_iters=48):
+    """The oracle's cost of one step of the full-size workload, measured on
+    bounded samples (`_sampled_step`), once with one thread (the reported
+    `value`) and once with every host core available to the BLAS pools (the
+    oracle's elementwise numpy work and scipy's sparse products run on one
+    thread either way)."""
+    host = f"host {platform.processor() or platform.machine()}, {host_cores()} logical CPUs available"
+    n_active, t1, ph1, s1 = _sampled_step(case, iters_per_step, n_sample, n_iters, 1)
+    nc = host_cores()
+    _, tn, phn, _ = _sampled_step(case, iters_per_step, n_sample, n_iters, nc)
+    return {"value": n_active / t1, "unit": "DP-steps/s", "cores": 1, "kind": "oracle",
+            "sample": f"{s1}; {host}", "phases_s": ph1,
+            "all_cores": {"value": n_active / tn, "cores": nc, "phases_s": phn,
+                          "sample": "the same sample with the BLAS thread pools at every available core"}}
 
 
 # ---------------------------------------------------------------------------
