@@ -16,6 +16,10 @@
 // x += P (cycle); x += w D^-1 (b - A x); the coarsest level is solved with
 // its dense inverse.  The cycle runs in FP32 (level 0 reads the FP32 copy of
 // the matrix, in difference form); the Galerkin products accumulate in FP64.
+// Launches per cycle: one per level on the way down (pre-smoothing from zero,
+// residual and restriction fused), two per level on the way up
+// (prolongation, smoothing), and one workgroup for the levels of at most
+// kMgTailCells cells, where separate launches would cost more than the work.
 //
 // Outer solver: Bi-CGSTAB in FP64 with the FP64 matrix, right-preconditioned
 // (v = A M^-1 p, t = A M^-1 s, x += alpha M^-1 p + omega M^-1 s), inner
@@ -31,6 +35,9 @@ constexpr int kMgMaxLevels = 16;
 constexpr int kMgMaxCoarse = 64;
 constexpr float kMgOmega = 0.8f;
 constexpr int kMgParts = 1024;          // outer-solver blocks (partial sums)
+constexpr int kMgTailCells = 512;       // levels this small run inside one workgroup
+constexpr int kMgMaxTail = 8;           // at most this many levels in that workgroup
+constexpr int kMgTailBlock = 1024;
 
 struct MgLevel {
     MeshDev m{};                 // dims, periodic; m.mps = plane stride of A
@@ -45,6 +52,7 @@ struct MgLevel {
 
 struct MgWork {
     int L = 0;
+    int tail = 0;                // first level of the one-workgroup tail of the cycle
     bool usable = false;         // the coarsest level has at most kMgMaxCoarse cells
     MgLevel lev[kMgMaxLevels];
     double* dense = nullptr;     // [Nc][Nc] coarsest matrix (FP64)
@@ -97,45 +105,6 @@ __device__ __forceinline__ float mg_pweight_sum(const MeshDev& mc, const uint8_t
     return tot;
 }
 
-// Calls f(K, w) for every valid coarse cell K of fine cell j with its raw
-// weight w (3/4 or 1/4 per axis; divide by mg_pweight_sum for P).
-template <int DIM, typename F>
-__device__ __forceinline__ void mg_pvisit(const MeshDev& mc, const uint8_t* __restrict__ unk_c, const int jf[3], F f) {
-#pragma unroll
-    for (int corner = 0; corner < (1 << DIM); ++corner) {
-        int k[3] = {0, 0, 0};
-        float wt = 1.0f;
-        bool ok = true;
-#pragma unroll
-        for (int a = 0; a < DIM; ++a) {
-            const int far = (corner >> a) & 1;
-            const int side = (jf[a] % 2 == 0) ? -1 : 1;
-            int v = jf[a] / 2 + side * far;
-            ok = ok && mg_coord(mc, a, v);
-            k[a] = v;
-            wt *= far ? 0.25f : 0.75f;
-        }
-        if (ok && unk_c[mg_cell(mc, k)]) f(k, wt);
-    }
-}
-
-// Slot of the coarse offset K - I (periodic axes wrapped into -1..1).
-template <int DIM>
-__device__ __forceinline__ int mg_slot(const MeshDev& mc, const int* K, const int* I) {
-    int s = 0, mul = 1;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a) {
-        int d = K[a] - I[a];
-        if (mc.periodic[a]) {
-            if (d > 1) d -= mc.n[a];
-            if (d < -1) d += mc.n[a];
-        }
-        s += (d + 1) * mul;
-        mul *= 3;
-    }
-    return s;
-}
-
 // Element offset of stencil slot s for a cell away from the mesh edges.
 template <int DIM>
 __device__ __forceinline__ int mg_off(const MeshDev& m, int s) {
@@ -149,39 +118,92 @@ __device__ __forceinline__ bool mg_interior(const MeshDev& m, const int ijk[3]) 
     return in;
 }
 
-// (A x)_c of a level operator: FP32 difference form (level 0: sum a_j (x_j -
-// x_c) + rowsum x_c) or plain form (coarse levels).  Cells away from the
-// mesh edges use constant slot offsets.
-template <int DIM, bool DIFF>
-__device__ __forceinline__ float mg_spmv(const MeshDev& m, const float* __restrict__ A, int c,
-                                         const float* __restrict__ x) {
+// One level as the cycle kernels see it.
+struct MgLv {
+    int n[3];
+    int per[3];
+    int Nc;
+    int diff;                    // level 0: FP32 copy of the PPE matrix in difference form
+    size_t mps;                  // plane stride of A
+    const float* A;
+    const uint8_t* unk;
+    const float* dinv;
+    const float* pn;
+    float* x;
+    float* y;
+    float* b;
+};
+
+__device__ __forceinline__ void mg_ijk(const int* n, int c, int ijk[3]) {
+    ijk[0] = c % n[0];
+    const int r = c / n[0];
+    ijk[1] = r % n[1];
+    ijk[2] = r / n[1];
+}
+
+__device__ __forceinline__ int mg_at(const int* n, const int* ijk) { return ijk[0] + n[0] * (ijk[1] + n[1] * ijk[2]); }
+
+// Cell j at stencil slot s of cell ijk (periodic axes wrapped), without
+// branches: j is always a valid index (self when the slot lies outside a
+// non-periodic mesh) and the return value says whether the slot is a
+// neighbour, so that every load of a row can be issued at once.
+template <int DIM>
+__device__ __forceinline__ bool mg_nbs(const int* n, const int* per, const int* ijk, int s, int self, int& j) {
+    int idx = 0, stride = 1;
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        int v = ijk[a] + (a == 0 ? s % 3 : (a == 1 ? (s / 3) % 3 : s / 9)) - 1;
+        const bool lo = v < 0, hi = v >= n[a];
+        v = lo ? v + n[a] : (hi ? v - n[a] : v);
+        ok = ok && (!(lo || hi) || per[a] != 0);
+        idx += v * stride;
+        stride *= n[a];
+    }
+    j = ok ? idx : self;
+    return ok;
+}
+
+// (A v)_c of a level operator, v given by val(j) and vc = v_c: the plain form
+// sum_s a_s v_j, or on level 0 the difference form sum_(s != centre) a_s
+// (v_j - v_c) + a_centre v_c (the centre slot holds the row sum).  STREAM:
+// non-temporal matrix loads (level 0, read once per pass from HBM); coarse
+// levels stay in cache between the passes of a cycle.
+template <int DIM, bool STREAM, typename V>
+__device__ __forceinline__ float mg_av(const MgLv& L, int c, const int* ijk, float vc, V val) {
     constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
-    int ijk[3];
-    cell_ijk(m, c, ijk);
-    const float xc = x[c];
+    const bool diff = L.diff != 0;
+    bool inner = ijk[0] > 0 && ijk[0] < L.n[0] - 1 && ijk[1] > 0 && ijk[1] < L.n[1] - 1;
+    if (DIM == 3) inner = inner && ijk[2] > 0 && ijk[2] < L.n[2] - 1;
     float acc = 0.0f;
-    if (mg_interior<DIM>(m, ijk)) {
+    if (inner) {       // constant offsets: every load of the row can be issued at once
+        const int sy = L.n[0], sz = L.n[0] * L.n[1];
 #pragma unroll
         for (int s = 0; s < S; ++s) {
-            const float a = ld_stream(A + (size_t)s * m.mps + c);
-            if (s == CEN)
-                acc += a * xc;
-            else
-                acc += DIFF ? a * (x[c + mg_off<DIM>(m, s)] - xc) : a * x[c + mg_off<DIM>(m, s)];
+            const float* pa = L.A + (size_t)s * L.mps + c;
+            const float a = STREAM ? ld_stream(pa) : *pa;
+            if (s == CEN) {
+                acc += a * vc;
+            } else {
+                const float v = val(c + (s % 3 - 1) + ((s / 3) % 3 - 1) * sy + (DIM == 3 ? (s / 9 - 1) * sz : 0));
+                acc += diff ? a * (v - vc) : a * v;
+            }
         }
         return acc;
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const float a = ld_stream(A + (size_t)s * m.mps + c);
+        const float* pa = L.A + (size_t)s * L.mps + c;
+        const float a = STREAM ? ld_stream(pa) : *pa;
         if (s == CEN) {
-            acc += a * xc;
+            acc += a * vc;
             continue;
         }
         int j;
-        double sh[3];
-        if (!neighbour<DIM>(m, ijk, s, j, sh)) continue;
-        acc += DIFF ? a * (x[j] - xc) : a * x[j];
+        const bool ok = mg_nbs<DIM>(L.n, L.per, ijk, s, c, j);
+        const float v = val(j);
+        const float term = diff ? a * (v - vc) : a * v;
+        acc += ok ? term : 0.0f;
     }
     return acc;
 }
@@ -260,36 +282,21 @@ __global__ void k_mg_pnorm(MeshDev mf, const uint8_t* __restrict__ unk_f, MeshDe
     }
 }
 
-// A_c = R A_f P.  A block takes kMgGalCells coarse cells; each of its
-// threads takes one child i of one of them and adds a_s(i) P[j(i, s)][K] to
-// its own row of LDS accumulators at the slot of K - I (FP64); the 2^DIM
-// children's rows are then summed in child order per slot.
-template <int DIM> struct MgGal;
-template <> struct MgGal<2> { static constexpr int CELLS = 64; };
-template <> struct MgGal<3> { static constexpr int CELLS = 32; };
-
-// Per-axis prolongation weight, away from the mesh edges and unknown-cell
-// boundaries: a fine cell at offset o from child c of coarse cell I (q = c +
-// o + 1 in 0..3) lies in coarse cell I + floor((c + o) / 2) (weight 3/4) and
-// takes 1/4 from that cell's neighbour on its side; e in 0..2 is the coarse
-// offset + 1.
+// Per-axis prolongation weight: a fine cell at offset o from child c of
+// coarse cell I (q = c + o + 1 in 0..3) lies in coarse cell I +
+// floor((c + o) / 2) (weight 3/4) and takes 1/4 from that cell's neighbour
+// on its side; e in 0..2 is the coarse offset + 1.
 __device__ __forceinline__ double mg_w1(int q, int e) {
     const int big = (q + 1) >> 1;
     const int small = big + ((q & 1) ? -1 : 1);
     return e == big ? 0.75 : (e == small ? 0.25 : 0.0);
 }
 
-// Interior rows of R A P for one child (parity c[]), whose every coarse
-// neighbour is inside the mesh and unknown (so P's rows are the full
-// multilinear stencils with unit sum): the 3^d fine row contracts with the
-// per-axis weights one axis at a time.
-template <int DIM, typename TA>
-__device__ __forceinline__ void mg_gal_interior(const MeshDev& mf, const TA* __restrict__ Af, int i, const int* c,
-                                                double* row) {
-    constexpr int S = Dims<DIM>::S;
-    double a[S];
-#pragma unroll
-    for (int s = 0; s < S; ++s) a[s] = (double)Af[(size_t)s * mf.mps + i];
+// row[e] = sum_s a[s] prod_a w(c_a + o_a(s) + 1, e_a): the 3^d row of a
+// child (parity c[]) contracted with the per-axis prolongation weights one
+// axis at a time.
+template <int DIM>
+__device__ __forceinline__ void mg_contract(const double* a, const int* c, double* row) {
     if (DIM == 2) {
         double t1[3][3];   // [oy][ex]
 #pragma unroll
@@ -349,81 +356,80 @@ __device__ __forceinline__ void mg_gal_interior(const MeshDev& mf, const TA* __r
     }
 }
 
-// True when every coarse cell of the 3^d block around I is inside the mesh
-// (no wrap) and unknown.
-template <int DIM>
-__device__ __forceinline__ bool mg_full_block(const MeshDev& mc, const uint8_t* __restrict__ unk_c, const int* ic) {
-    constexpr int S = Dims<DIM>::S;
-#pragma unroll
-    for (int a = 0; a < DIM; ++a)
-        if (ic[a] < 1 || ic[a] > mc.n[a] - 2) return false;
-    bool all = true;
-#pragma unroll
-    for (int s = 0; s < S; ++s) {
-        const int k[3] = {ic[0] + s % 3 - 1, ic[1] + (s / 3) % 3 - 1, DIM == 3 ? ic[2] + s / 9 - 1 : 0};
-        all = all && unk_c[mg_cell(mc, k)];
-    }
-    return all;
-}
-
+// A_c = R A_f P, accumulated in FP64.  One thread per child i of a coarse
+// cell I, the 2^d children of I in consecutive lanes.  Row i of A_f P is
+// sum_s a_s(i) P[j_s] with P[j][K] = pn[j] w(j, K) over the coarse cells K
+// of j that lie inside the mesh and are unknown; all of them lie in the 3^d
+// block around I.  Since pn[j] = 0 at fine cells that are not unknown, the
+// child contracts a'_s = a_s(i) pn[j_s] (0 for a slot outside the mesh) with
+// the separable weights w, and the coarse cells outside the mesh or not
+// unknown are dropped from the sum afterwards (a factor of K alone).  The
+// children's rows are added across their lanes and scaled by 2^-d (R).
 template <int DIM, typename TA>
 __global__ __launch_bounds__(kBlock) void k_mg_galerkin(MeshDev mf, const TA* __restrict__ Af,
                                                         const uint8_t* __restrict__ unk_f,
                                                         const float* __restrict__ pn, MeshDev mc,
                                                         const uint8_t* __restrict__ unk_c, float* __restrict__ Ac,
                                                         float* __restrict__ dinv_c) {
-    constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN, CH = 1 << DIM, CELLS = MgGal<DIM>::CELLS;
-    static_assert(CELLS * CH == kBlock, "one child per thread");
-    __shared__ double acc[CELLS][CH][S];
-    const int cl = threadIdx.x / CH, ch = threadIdx.x % CH;
-    for (int base = blockIdx.x * CELLS; base < mc.Nc; base += gridDim.x * CELLS) {
-        const int I = base + cl;
-        double* row = acc[cl][ch];
+    constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN, CH = 1 << DIM;
+    const int total = mc.Nc * CH;        // the grid is a multiple of CH threads: a cell's lanes share a pass
+    for (int t = blockIdx.x * blockDim.x + threadIdx.x; t < total; t += gridDim.x * blockDim.x) {
+        const int I = t / CH, ch = t % CH;
+        int ic[3] = {0, 0, 0};
+        mg_ijk(mc.n, I, ic);
+        int f[3] = {0, 0, 0};
+        bool in = true;
 #pragma unroll
-        for (int t = 0; t < S; ++t) row[t] = 0.0;
-        if (I < mc.Nc && unk_c[I]) {
-            int ic[3];
-            cell_ijk(mc, I, ic);
-            int fi[3] = {0, 0, 0};
-            bool in = true;
+        for (int a = 0; a < DIM; ++a) {
+            f[a] = 2 * ic[a] + ((ch >> a) & 1);
+            in = in && f[a] < mf.n[a];
+        }
+        const bool cu = unk_c[I] != 0;
+        double row[S];
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                fi[a] = 2 * ic[a] + ((ch >> a) & 1);
-                in = in && fi[a] < mf.n[a];
-            }
-            const int i = in ? mg_cell(mf, fi) : 0;
-            const int par[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
-            if (in && unk_f[i] && mg_full_block<DIM>(mc, unk_c, ic)) {
-                mg_gal_interior<DIM, TA>(mf, Af, i, par, row);
-            } else if (in && unk_f[i]) {
-                for (int s = 0; s < S; ++s) {
-                    const double a = (double)Af[(size_t)s * mf.mps + i];
-                    if (a == 0.0) continue;
-                    int j;
-                    double sh[3];
-                    if (!neighbour<DIM>(mf, fi, s, j, sh)) continue;
-                    int fj[3];
-                    cell_ijk(mf, j, fj);
-                    const double aw = a * (double)pn[j];
-                    mg_pvisit<DIM>(mc, unk_c, fj, [&](const int* K, float w) {
-                        row[mg_slot<DIM>(mc, K, ic)] += aw * (double)w;
-                    });
+        for (int s = 0; s < S; ++s) row[s] = 0.0;
+        if (cu && in) {
+            const int i = mg_at(mf.n, f);
+            if (unk_f[i]) {
+                double a[S];
+                bool inner = f[0] > 0 && f[0] < mf.n[0] - 1 && f[1] > 0 && f[1] < mf.n[1] - 1;
+                if (DIM == 3) inner = inner && f[2] > 0 && f[2] < mf.n[2] - 1;
+                if (inner) {
+                    const int sy = mf.n[0], sz = mf.n[0] * mf.n[1];
+#pragma unroll
+                    for (int s = 0; s < S; ++s)
+                        a[s] = (double)Af[(size_t)s * mf.mps + i] *
+                               (double)pn[i + (s % 3 - 1) + ((s / 3) % 3 - 1) * sy + (DIM == 3 ? (s / 9 - 1) * sz : 0)];
+                } else {
+#pragma unroll
+                    for (int s = 0; s < S; ++s) {
+                        int j;
+                        const bool ok = mg_nbs<DIM>(mf.n, mf.periodic, f, s, i, j);
+                        const double v = (double)Af[(size_t)s * mf.mps + i] * (double)pn[j];
+                        a[s] = ok ? v : 0.0;
+                    }
                 }
+                const int par[3] = {ch & 1, (ch >> 1) & 1, (ch >> 2) & 1};
+                mg_contract<DIM>(a, par, row);
             }
         }
-        __syncthreads();
-        if (I < mc.Nc) {
-            const double scale = 1.0 / (double)CH;
-            for (int t = ch; t < S; t += CH) {
-                double v = 0.0;
 #pragma unroll
-                for (int c = 0; c < CH; ++c) v += acc[cl][c][t];
-                v *= scale;
-                Ac[(size_t)t * mc.mps + I] = (float)v;
-                if (t == CEN) dinv_c[I] = (unk_c[I] && v != 0.0 && isfinite(v)) ? (float)(1.0 / v) : 0.0f;
-            }
+        for (int s = 0; s < S; ++s) {
+            row[s] += __shfl_xor(row[s], 1);
+            row[s] += __shfl_xor(row[s], 2);
+            if (DIM == 3) row[s] += __shfl_xor(row[s], 4);
         }
-        __syncthreads();
+        // lane ch writes the slots s = ch (mod 2^d)
+#pragma unroll
+        for (int s = 0; s < S; ++s) {
+            if (s % CH != ch) continue;
+            int K;
+            const bool okn = mg_nbs<DIM>(mc.n, mc.periodic, ic, s, I, K);
+            const bool ok = cu && okn && unk_c[K] != 0;
+            const double v = ok ? row[s] * (1.0 / (double)CH) : 0.0;
+            Ac[(size_t)s * mc.mps + I] = (float)v;
+            if (s == CEN) dinv_c[I] = (cu && v != 0.0 && isfinite(v)) ? (float)(1.0 / v) : 0.0f;
+        }
     }
 }
 
@@ -454,118 +460,235 @@ __global__ void k_mg_dense(MeshDev mc, const TA* __restrict__ Ac, const uint8_t*
 }
 
 // Gauss-Jordan inversion with partial pivoting of the N x N (N <= 64)
-// coarsest matrix, one block, in LDS.  flag = 1 when a pivot vanishes.
-__global__ __launch_bounds__(256) void k_mg_invert(const double* __restrict__ D, int N, float* __restrict__ inv,
-                                                   int* flag) {
-    __shared__ double M[kMgMaxCoarse][2 * kMgMaxCoarse];
-    __shared__ double fac[kMgMaxCoarse];
+// coarsest matrix, one block of kMgTailBlock threads, in LDS.  Per column k:
+// wave 0 finds the pivot row (largest |M[r][k]|, r >= k, the lowest r on
+// ties) by a butterfly; the pivot row p, divided by the pivot, becomes row k
+// and the old row k moves to p; then every other row r subtracts M[r][k]
+// times the new row k.  flag = 1 when a pivot vanishes.
+__global__ __launch_bounds__(kMgTailBlock) void k_mg_invert(const double* __restrict__ D, int N,
+                                                            float* __restrict__ inv, int* flag) {
+    constexpr int RG = kMgTailBlock / (2 * kMgMaxCoarse);     // row groups
+    __shared__ double M[kMgMaxCoarse][2 * kMgMaxCoarse + 1];
+    __shared__ double prow[2 * kMgMaxCoarse], orow[2 * kMgMaxCoarse], fac[kMgMaxCoarse];
     __shared__ int piv;
-    const int W = 2 * N;
-    for (int e = threadIdx.x; e < N * W; e += blockDim.x) {
-        const int r = e / W, c = e % W;
-        M[r][c] = c < N ? D[r * N + c] : (c - N == r ? 1.0 : 0.0);
-    }
+    const int W = 2 * N, tid = threadIdx.x;
+    const int col = tid % (2 * kMgMaxCoarse), r0 = tid / (2 * kMgMaxCoarse);
+    if (col < W)
+        for (int r = r0; r < N; r += RG) M[r][col] = col < N ? D[r * N + col] : (col - N == r ? 1.0 : 0.0);
     __syncthreads();
     for (int k = 0; k < N; ++k) {
-        if (threadIdx.x == 0) {
-            int best = k;
-            for (int r = k + 1; r < N; ++r)
-                if (fabs(M[r][k]) > fabs(M[best][k])) best = r;
-            piv = best;
-            if (!(fabs(M[best][k]) > 0.0)) *flag = 1;
+        if (tid < 64) {
+            double v = (tid >= k && tid < N) ? fabs(M[tid][k]) : -1.0;
+            int idx = tid;
+#pragma unroll
+            for (int o = 32; o >= 1; o >>= 1) {
+                const double ov = __shfl_xor(v, o);
+                const int oi = __shfl_xor(idx, o);
+                if (ov > v || (ov == v && oi < idx)) {
+                    v = ov;
+                    idx = oi;
+                }
+            }
+            if (tid == 0) {
+                piv = idx;
+                if (!(v > 0.0)) *flag = 1;
+            }
         }
         __syncthreads();
         const int p = piv;
-        if (p != k)
-            for (int c = threadIdx.x; c < W; c += blockDim.x) {
-                const double t = M[k][c];
-                M[k][c] = M[p][c];
-                M[p][c] = t;
-            }
-        __syncthreads();
-        const double d = M[k][k];
+        const double d = M[p][k];
         const double id = d != 0.0 ? 1.0 / d : 0.0;
-        __syncthreads();
-        for (int c = threadIdx.x; c < W; c += blockDim.x) M[k][c] *= id;
-        for (int r = threadIdx.x; r < N; r += blockDim.x) fac[r] = r == k ? 0.0 : M[r][k];
-        __syncthreads();
-        for (int e = threadIdx.x; e < N * W; e += blockDim.x) {
-            const int r = e / W, c = e % W;
-            if (r != k) M[r][c] -= fac[r] * M[k][c];
+        if (tid < W) {
+            prow[tid] = M[p][tid] * id;
+            orow[tid] = M[k][tid];
+        } else if (tid >= 2 * kMgMaxCoarse && tid < 2 * kMgMaxCoarse + N) {
+            const int r = tid - 2 * kMgMaxCoarse;
+            fac[r] = r == k ? 0.0 : (r == p ? M[k][k] : M[r][k]);
         }
         __syncthreads();
+        if (col < W)
+            for (int r = r0; r < N; r += RG) {
+                if (r == k)
+                    M[r][col] = prow[col];
+                else
+                    M[r][col] = (r == p ? orow[col] : M[r][col]) - fac[r] * prow[col];
+            }
+        __syncthreads();
     }
-    for (int e = threadIdx.x; e < N * N; e += blockDim.x) inv[e] = (float)M[e / N][N + e % N];
+    for (int e = tid; e < N * N; e += blockDim.x) inv[e] = (float)M[e / N][N + e % N];
 }
 
 // ---------------------------------------------------------------------------
 // Cycle kernels (FP32)
 // ---------------------------------------------------------------------------
 
-__global__ void k_mg_scale(int N, const float* __restrict__ dinv, const float* __restrict__ b, float* __restrict__ x) {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x)
-        x[c] = kMgOmega * dinv[c] * b[c];
+// Down-leg of level F: x = w D^-1 b, r = b - A x at unknown cells (0
+// elsewhere), coarse right-hand side = the mean of the children's r.  Item t
+// is child t % 2^d of coarse cell t / 2^d; the children of one coarse cell
+// sit in consecutive lanes and add their residuals across them.  x_j of the
+// neighbours is formed from b and D^-1 on the fly, so the level needs no
+// separate pre-smoothing pass.
+template <int DIM, bool STREAM>
+__device__ __forceinline__ void mg_down_at(const MgLv& F, const MgLv& C, int t) {
+    constexpr int CH = 1 << DIM;
+    const int I = t / CH, ch = t % CH;
+    int ic[3] = {0, 0, 0};
+    mg_ijk(C.n, I, ic);
+    int f[3] = {0, 0, 0};
+    bool in = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        f[a] = 2 * ic[a] + ((ch >> a) & 1);
+        in = in && f[a] < F.n[a];
+    }
+    float r = 0.0f;
+    if (in) {
+        const int c = mg_at(F.n, f);
+        const float bc = F.b[c];
+        const float xc = kMgOmega * F.dinv[c] * bc;
+        F.x[c] = xc;
+        if (F.unk[c])
+            r = bc - mg_av<DIM, STREAM>(F, c, f, xc, [&](int j) { return kMgOmega * F.dinv[j] * F.b[j]; });
+    }
+    r += __shfl_xor(r, 1);
+    r += __shfl_xor(r, 2);
+    if (DIM == 3) r += __shfl_xor(r, 4);
+    if (ch == 0) C.b[I] = r * (1.0f / (float)CH);
 }
 
-// r = b - A x at unknown cells (0 elsewhere).
-template <int DIM, bool DIFF>
-__global__ void k_mg_resid(MeshDev m, const float* __restrict__ A, const uint8_t* __restrict__ unk,
-                           const float* __restrict__ x, const float* __restrict__ b, float* __restrict__ r) {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x)
-        r[c] = unk[c] ? b[c] - mg_spmv<DIM, DIFF>(m, A, c, x) : 0.0f;
-}
-
-// Coarse right-hand side: the mean of the children's residuals (R).
+// Up-leg, first half: x_j += P y_c at unknown fine cells (y_c is 0 at coarse
+// cells that are not unknown, so only the mesh edges need a test).
 template <int DIM>
-__global__ void k_mg_average(MeshDev mf, const float* __restrict__ rf, MeshDev mc, float* __restrict__ bc) {
-    for (int I = blockIdx.x * blockDim.x + threadIdx.x; I < mc.Nc; I += gridDim.x * blockDim.x) {
-        int ic[3];
-        cell_ijk(mc, I, ic);
-        float sum = 0.0f;
+__device__ __forceinline__ void mg_prolong_at(const MgLv& F, const MgLv& C, int j) {
+    if (!F.unk[j]) return;
+    int fj[3] = {0, 0, 0};
+    mg_ijk(F.n, j, fj);
+    float add = 0.0f;
 #pragma unroll
-        for (int ch = 0; ch < (1 << DIM); ++ch) {
-            int f[3] = {0, 0, 0};
-            bool in = true;
+    for (int corner = 0; corner < (1 << DIM); ++corner) {
+        int k[3] = {0, 0, 0};
+        float wt = 1.0f;
+        bool ok = true;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                f[a] = 2 * ic[a] + ((ch >> a) & 1);
-                in = in && f[a] < mf.n[a];
-            }
-            if (in) sum += rf[mg_cell(mf, f)];
+        for (int a = 0; a < DIM; ++a) {
+            const int far = (corner >> a) & 1;
+            int v = (fj[a] >> 1) + (far ? ((fj[a] & 1) ? 1 : -1) : 0);
+            const bool lo = v < 0, hi = v >= C.n[a];
+            ok = ok && (!(lo || hi) || C.per[a] != 0);
+            k[a] = lo ? v + C.n[a] : (hi ? v - C.n[a] : v);      // in range either way
+            wt *= far ? 0.25f : 0.75f;
         }
-        bc[I] = sum * (1.0f / (float)(1 << DIM));
+        const float yk = C.y[mg_at(C.n, k)];
+        add += ok ? wt * yk : 0.0f;
+    }
+    F.x[j] += add * F.pn[j];
+}
+
+// Up-leg, second half: y = x + w D^-1 (b - A x) at unknown cells, 0 elsewhere.
+template <int DIM, bool STREAM>
+__device__ __forceinline__ void mg_smooth_at(const MgLv& F, int c) {
+    float y = 0.0f;
+    if (F.unk[c]) {
+        int ijk[3] = {0, 0, 0};
+        mg_ijk(F.n, c, ijk);
+        const float xc = F.x[c];
+        const float* x = F.x;
+        y = xc + kMgOmega * F.dinv[c] * (F.b[c] - mg_av<DIM, STREAM>(F, c, ijk, xc, [&](int j) { return x[j]; }));
+    }
+    F.y[c] = y;
+}
+
+// Down-leg over bricks of 64 x 2 x 2 (3D) or 64 x 4 (2D) fine cells, one
+// per block (grid: bricks along x, y, z), one cell per thread so that the
+// matrix planes stream in whole rows; the residuals meet in LDS and the
+// brick's coarse cells add their children there, in child order.
+template <int DIM>
+struct MgBrick {
+    static constexpr int BX = 64, BY = DIM == 3 ? 2 : 4, BZ = DIM == 3 ? 2 : 1;
+};
+
+template <int DIM, bool STREAM>
+__global__ __launch_bounds__(kBlock) void k_mg_down(MgLv F, MgLv C) {
+    constexpr int BX = MgBrick<DIM>::BX, BY = MgBrick<DIM>::BY, BZ = MgBrick<DIM>::BZ, CH = 1 << DIM;
+    static_assert(BX * BY * BZ == kBlock, "one fine cell per thread");
+    __shared__ float rs[BZ][BY][BX];
+    const int tx = threadIdx.x % BX, ty = (threadIdx.x / BX) % BY, tz = threadIdx.x / (BX * BY);
+    const int f[3] = {(int)blockIdx.x * BX + tx, (int)blockIdx.y * BY + ty, DIM == 3 ? (int)blockIdx.z * BZ + tz : 0};
+    const bool in = f[0] < F.n[0] && f[1] < F.n[1] && (DIM == 2 || f[2] < F.n[2]);
+    float r = 0.0f;
+    if (in) {
+        const int c = mg_at(F.n, f);
+        const float bc = F.b[c];
+        const float xc = kMgOmega * F.dinv[c] * bc;
+        F.x[c] = xc;
+        if (F.unk[c])
+            r = bc - mg_av<DIM, STREAM>(F, c, f, xc, [&](int j) { return kMgOmega * F.dinv[j] * F.b[j]; });
+    }
+    rs[tz][ty][tx] = r;
+    __syncthreads();
+    constexpr int CX = BX / 2, CY = BY / 2, CZ = DIM == 3 ? BZ / 2 : 1;
+    if (threadIdx.x < CX * CY * CZ) {
+        const int cx = threadIdx.x % CX, cy = (threadIdx.x / CX) % CY, cz = threadIdx.x / (CX * CY);
+        const int I[3] = {(int)blockIdx.x * CX + cx, (int)blockIdx.y * CY + cy, DIM == 3 ? (int)blockIdx.z * CZ + cz : 0};
+        if (I[0] < C.n[0] && I[1] < C.n[1] && (DIM == 2 || I[2] < C.n[2])) {
+            float sum = 0.0f;
+#pragma unroll
+            for (int ch = 0; ch < CH; ++ch)
+                sum += rs[DIM == 3 ? 2 * cz + ((ch >> 2) & 1) : 0][2 * cy + ((ch >> 1) & 1)][2 * cx + (ch & 1)];
+            C.b[mg_at(C.n, I)] = sum * (1.0f / (float)CH);
+        }
     }
 }
 
 template <int DIM>
-__global__ void k_mg_prolong(MeshDev mf, const uint8_t* __restrict__ unk_f, const float* __restrict__ pn,
-                             float* __restrict__ xf, MeshDev mc, const uint8_t* __restrict__ unk_c,
-                             const float* __restrict__ yc) {
-    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < mf.Nc; j += gridDim.x * blockDim.x) {
-        if (!unk_f[j]) continue;
-        int fj[3];
-        cell_ijk(mf, j, fj);
-        float add = 0.0f;
-        mg_pvisit<DIM>(mc, unk_c, fj, [&](const int* K, float w) { add += w * yc[mg_cell(mc, K)]; });
-        xf[j] += add * pn[j];
+__global__ __launch_bounds__(kBlock) void k_mg_prolong(MgLv F, MgLv C) {
+    for (int j = blockIdx.x * blockDim.x + threadIdx.x; j < F.Nc; j += gridDim.x * blockDim.x)
+        mg_prolong_at<DIM>(F, C, j);
+}
+
+template <int DIM, bool STREAM>
+__global__ __launch_bounds__(kBlock) void k_mg_smooth(MgLv F) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < F.Nc; c += gridDim.x * blockDim.x)
+        mg_smooth_at<DIM, STREAM>(F, c);
+}
+
+// The coarse end of the cycle in one workgroup: down-legs of levels
+// l[0] .. l[nl - 2], the coarsest level l[nl - 1] solved with its dense
+// inverse (y = inv b, 0 at cells that are not unknown), then the up-legs back
+// to l[0].  Every phase ends at a barrier of the workgroup, which orders its
+// global stores before the next phase's loads.
+struct MgTail {
+    int nl;
+    const float* inv;
+    MgLv l[kMgMaxTail];
+};
+
+template <int DIM>
+__global__ __launch_bounds__(kMgTailBlock) void k_mg_tail(MgTail T) {
+    constexpr int CH = 1 << DIM;
+    const int tid = threadIdx.x, nt = blockDim.x;
+    for (int l = 0; l + 1 < T.nl; ++l) {
+        const int total = T.l[l + 1].Nc * CH;
+        for (int t = tid; t < total; t += nt) mg_down_at<DIM, false>(T.l[l], T.l[l + 1], t);
+        __syncthreads();
     }
-}
-
-template <int DIM, bool DIFF>
-__global__ void k_mg_smooth(MeshDev m, const float* __restrict__ A, const uint8_t* __restrict__ unk,
-                            const float* __restrict__ dinv, const float* __restrict__ b, const float* __restrict__ x,
-                            float* __restrict__ y) {
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x)
-        y[c] = unk[c] ? x[c] + kMgOmega * dinv[c] * (b[c] - mg_spmv<DIM, DIFF>(m, A, c, x)) : 0.0f;
-}
-
-__global__ __launch_bounds__(256) void k_mg_coarse_solve(const float* __restrict__ inv, int N,
-                                                         const uint8_t* __restrict__ unk,
-                                                         const float* __restrict__ b, float* __restrict__ y) {
-    for (int r = threadIdx.x; r < N; r += blockDim.x) {
+    {
+        const MgLv& Lc = T.l[T.nl - 1];
+        const int N = Lc.Nc;                 // <= kMgMaxCoarse: 16 lanes per row
+        const int r = tid >> 4, q = tid & 15;
         float acc = 0.0f;
-        for (int k = 0; k < N; ++k) acc += inv[r * N + k] * b[k];
-        y[r] = unk[r] ? acc : 0.0f;
+        if (r < N)
+            for (int k = q; k < N; k += 16) acc += T.inv[r * N + k] * Lc.b[k];
+#pragma unroll
+        for (int o = 1; o < 16; o <<= 1) acc += __shfl_xor(acc, o);
+        if (r < N && q == 0) Lc.y[r] = Lc.unk[r] ? acc : 0.0f;
+    }
+    __syncthreads();
+    for (int l = T.nl - 2; l >= 0; --l) {
+        for (int j = tid; j < T.l[l].Nc; j += nt) mg_prolong_at<DIM>(T.l[l], T.l[l + 1], j);
+        __syncthreads();
+        for (int c = tid; c < T.l[l].Nc; c += nt) mg_smooth_at<DIM, false>(T.l[l], c);
+        __syncthreads();
     }
 }
 
@@ -622,6 +745,9 @@ hipError_t mg_alloc(const MeshDev& m, MgWork** out) {
         nx.mps = padded_plane_stride((size_t)N);
         cur = nx;
     }
+    // the tail: the smallest levels, at most kMgMaxTail of them
+    w->tail = w->L - 1;
+    while (w->tail > 0 && w->lev[w->tail - 1].m.Nc <= kMgTailCells && w->L - (w->tail - 1) <= kMgMaxTail) --w->tail;
     const int Nc = w->usable ? w->lev[w->L - 1].m.Nc : 1;
     if (e == hipSuccess) e = hipMalloc((void**)&w->dense, (size_t)Nc * Nc * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&w->inv, (size_t)Nc * Nc * sizeof(float));
@@ -672,7 +798,7 @@ static hipError_t mg_setup_dim(MgWork& w, const SetDev& set, hipStream_t st) {
         MgLevel& C = w.lev[l + 1];
         hipLaunchKernelGGL(k_mg_flags<DIM>, dim3(grid_for(C.m.Nc)), dim3(kBlock), 0, st, F.m, F.unk, C.m, C.unk);
         hipLaunchKernelGGL(k_mg_pnorm<DIM>, dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.unk, C.m, C.unk, F.pn);
-        const int gb = (C.m.Nc + MgGal<DIM>::CELLS - 1) / MgGal<DIM>::CELLS;
+        const int gb = ((C.m.Nc << DIM) + kBlock - 1) / kBlock;
         const dim3 gg(gb > 8192 ? 8192 : gb);
         if (l == 0)
             hipLaunchKernelGGL((k_mg_galerkin<DIM, double>), gg, dim3(kBlock), 0, st, F.m, set.amat, F.unk, F.pn, C.m,
@@ -687,7 +813,7 @@ static hipError_t mg_setup_dim(MgWork& w, const SetDev& set, hipStream_t st) {
         hipLaunchKernelGGL((k_mg_dense<DIM, double>), dim3(1), dim3(256), 0, st, Lc.m, set.amat, Lc.unk, w.dense);
     else
         hipLaunchKernelGGL((k_mg_dense<DIM, float>), dim3(1), dim3(256), 0, st, Lc.m, Lc.A, Lc.unk, w.dense);
-    hipLaunchKernelGGL(k_mg_invert, dim3(1), dim3(256), 0, st, w.dense, Lc.m.Nc, w.inv, w.flag);
+    hipLaunchKernelGGL(k_mg_invert, dim3(1), dim3(kMgTailBlock), 0, st, w.dense, Lc.m.Nc, w.inv, w.flag);
     return hipGetLastError();
 }
 
@@ -696,35 +822,53 @@ hipError_t mg_setup(const MeshDev& m, MgWork& w, const SetDev& set, hipStream_t 
     return m.dim == 2 ? mg_setup_dim<2>(w, set, st) : mg_setup_dim<3>(w, set, st);
 }
 
-// One V-cycle on level 0: rhs lev[0].b, result lev[0].y.
+static MgLv mg_lv(const MgLevel& L, int level) {
+    MgLv v{};
+    for (int a = 0; a < 3; ++a) {
+        v.n[a] = a < L.m.dim ? L.m.n[a] : 1;
+        v.per[a] = a < L.m.dim ? L.m.periodic[a] : 0;
+    }
+    v.Nc = L.m.Nc;
+    v.diff = level == 0 ? 1 : 0;
+    v.mps = L.m.mps;
+    v.A = L.A;
+    v.unk = L.unk;
+    v.dinv = L.dinv;
+    v.pn = L.pn;
+    v.x = L.x;
+    v.y = L.y;
+    v.b = L.b;
+    return v;
+}
+
+// One V-cycle on level 0: rhs lev[0].b, result lev[0].y.  Levels above the
+// tail take one down-leg launch each and two up-leg launches (prolongation,
+// smoothing); the tail runs in one launch.
 template <int DIM>
 static void mg_cycle_dim(MgWork& w, hipStream_t st) {
-    for (int l = 0; l + 1 < w.L; ++l) {
-        MgLevel& F = w.lev[l];
-        MgLevel& C = w.lev[l + 1];
-        hipLaunchKernelGGL(k_mg_scale, dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m.Nc, F.dinv, F.b, F.x);
-        // the level's residual goes to y (its cycle result is written only later)
+    const int ts = w.tail;
+    for (int l = 0; l < ts; ++l) {
+        const MgLv F = mg_lv(w.lev[l], l), C = mg_lv(w.lev[l + 1], l + 1);
+        const dim3 g((F.n[0] + MgBrick<DIM>::BX - 1) / MgBrick<DIM>::BX, (F.n[1] + MgBrick<DIM>::BY - 1) / MgBrick<DIM>::BY,
+                     (F.n[2] + MgBrick<DIM>::BZ - 1) / MgBrick<DIM>::BZ);
         if (l == 0)
-            hipLaunchKernelGGL((k_mg_resid<DIM, true>), dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.A, F.unk,
-                               F.x, F.b, F.y);
+            hipLaunchKernelGGL((k_mg_down<DIM, true>), g, dim3(kBlock), 0, st, F, C);
         else
-            hipLaunchKernelGGL((k_mg_resid<DIM, false>), dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.A, F.unk,
-                               F.x, F.b, F.y);
-        hipLaunchKernelGGL(k_mg_average<DIM>, dim3(grid_for(C.m.Nc)), dim3(kBlock), 0, st, F.m, F.y, C.m, C.b);
+            hipLaunchKernelGGL((k_mg_down<DIM, false>), g, dim3(kBlock), 0, st, F, C);
     }
-    const MgLevel& Lc = w.lev[w.L - 1];
-    hipLaunchKernelGGL(k_mg_coarse_solve, dim3(1), dim3(256), 0, st, w.inv, Lc.m.Nc, Lc.unk, Lc.b, Lc.y);
-    for (int l = w.L - 2; l >= 0; --l) {
-        MgLevel& F = w.lev[l];
-        MgLevel& C = w.lev[l + 1];
-        hipLaunchKernelGGL(k_mg_prolong<DIM>, dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.unk, F.pn, F.x,
-                           C.m, C.unk, C.y);
+    MgTail T{};
+    T.nl = w.L - ts;
+    T.inv = w.inv;
+    for (int k = 0; k < T.nl; ++k) T.l[k] = mg_lv(w.lev[ts + k], ts + k);
+    hipLaunchKernelGGL(k_mg_tail<DIM>, dim3(1), dim3(kMgTailBlock), 0, st, T);
+    for (int l = ts - 1; l >= 0; --l) {
+        const MgLv F = mg_lv(w.lev[l], l), C = mg_lv(w.lev[l + 1], l + 1);
+        const dim3 g(grid_for(F.Nc));
+        hipLaunchKernelGGL(k_mg_prolong<DIM>, g, dim3(kBlock), 0, st, F, C);
         if (l == 0)
-            hipLaunchKernelGGL((k_mg_smooth<DIM, true>), dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.A, F.unk,
-                               F.dinv, F.b, F.x, F.y);
+            hipLaunchKernelGGL((k_mg_smooth<DIM, true>), g, dim3(kBlock), 0, st, F);
         else
-            hipLaunchKernelGGL((k_mg_smooth<DIM, false>), dim3(grid_for(F.m.Nc)), dim3(kBlock), 0, st, F.m, F.A,
-                               F.unk, F.dinv, F.b, F.x, F.y);
+            hipLaunchKernelGGL((k_mg_smooth<DIM, false>), g, dim3(kBlock), 0, st, F);
     }
 }
 

@@ -17,6 +17,8 @@
 // evaluation of the same formulas in that order (IEEE + - * / sqrt).
 #include "common.h"
 
+#include <cmath>
+
 namespace mcd {
 
 // cos^2(pi r / (2 r_e)) (Sec. 3.2) or the truncated Gaussian, with the
@@ -61,10 +63,10 @@ __device__ __forceinline__ int halo_slot(int lx, int ly, int lz, int s) {
 // Row of neighbour slot e: kind (0 none, 1 value, 2 Neumann), its basis
 // vector a (value or normal-derivative row, Eq. obj_func) and, when
 // want_w, its weight.
-template <int DIM>
+template <int DIM, bool POW2>
 __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, int e, bool centre,
-                                       const double* xc, double re, double rs, int wkind, bool want_w, double& w,
-                                       double* a) {
+                                       const double* xc, double re, double rs, double rs_inv, int wkind, bool want_w,
+                                       double& w, double* a) {
     if (H.j[e] < 0) return 0;
     const int kind = row_kind(H.r[e], bc);
     if (centre && kind != 2) return 0;     // the DP itself: only its Neumann row
@@ -75,7 +77,7 @@ __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, i
     for (int q = 0; q < DIM; ++q) {
         d[q] = H.p[q][e] - xc[q];
         r2 += d[q] * d[q];
-        X[q] = d[q] / rs;
+        X[q] = POW2 ? d[q] * rs_inv : d[q] / rs;
     }
     if (want_w) w = mls_weight(sqrt(r2), re, wkind);
     if (kind == 1) {
@@ -89,7 +91,10 @@ __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, i
     return kind;
 }
 
-template <int DIM>
+// POW2: r_s is a power of two, so x / r_s and x * (1 / r_s) are the same
+// real number and round to the same double; the kernel then multiplies (the
+// divisions by r_s and r_s^2 are most of its division work).
+template <int DIM, bool POW2>
 __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* __restrict__ pos,
                                                       const int8_t* __restrict__ role,
                                                       const double* __restrict__ normal, BcDev bc, double re,
@@ -107,6 +112,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
     constexpr bool kCacheW = DIM == 2;
     __shared__ double wc[kCacheW ? S : 1][kBlock];
     const size_t Nc = (size_t)m.Nc;
+    const double rs_inv = 1.0 / rs, rr_inv = 1.0 / (rs * rs);     // exact when POW2
     const int ntx = (m.n[0] + T::X - 1) / T::X, nty = (m.n[1] + T::Y - 1) / T::Y;
     const int ntz = DIM == 3 ? (m.n[2] + T::Z - 1) / T::Z : 1;
     const int ntiles = ntx * nty * ntz;
@@ -167,7 +173,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
             if (rc != MCD_ROLE_VOID) {
                 for (int s = 0; s < S; ++s) {
                     double w = 0.0, a[NB];
-                    const int kind = row_lds<DIM>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs, wkind,
+                    const int kind = row_lds<DIM, POW2>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs, rs_inv, wkind,
                                                   true, w, a);
                     if (kCacheW) wc[s][threadIdx.x] = w;
                     if (!kind) continue;
@@ -242,7 +248,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                 for (int q = 0; q < NB; ++q) y[q] = 0.0;
                 if (isv || isn) {
                     double w = kCacheW ? wc[s][threadIdx.x] : 0.0, a[NB];
-                    row_lds<DIM>(H, bc, e, s == CEN, xc, re, rs, wkind, !kCacheW, w, a);
+                    row_lds<DIM, POW2>(H, bc, e, s == CEN, xc, re, rs, rs_inv, wkind, !kCacheW, w, a);
 #pragma unroll
                     for (int q = 0; q < NB; ++q) y[q] = w * a[q];
                     // forward L z = y, backward L^T y = z
@@ -273,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                     for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(y[q], st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
                     double lap = 0.0;
                     if (isv && unk_c) {
-                        lap = diag2<DIM>(y) / (rs * rs);
+                        lap = POW2 ? diag2<DIM>(y) * rr_inv : diag2<DIM>(y) / (rs * rs);
                         diag_sum += lap;
                         if (!is_unknown(H.r[e], H.j[e], bc)) lap = 0.0;
                     }
@@ -310,12 +316,25 @@ hipError_t launch_mls_build(const MeshDev& m, const double* pos, const int8_t* r
     long long g = m.dim == 2 ? (long long)((m.n[0] + 63) / 64) * ((m.n[1] + 3) / 4)
                              : (long long)((m.n[0] + 31) / 32) * ((m.n[1] + 3) / 4) * ((m.n[2] + 1) / 2);
     if (g > 4096) g = 4096;
-    if (m.dim == 2)
-        hipLaunchKernelGGL(k_mls_build<2>, dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re, rs, wkind,
-                           set, counters, latch);
-    else
-        hipLaunchKernelGGL(k_mls_build<3>, dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re, rs, wkind,
-                           set, counters, latch);
+    // r_s and r_s^2 powers of two, within the normal range
+    int e1 = 0, e2 = 0;
+    const bool pow2 = std::isnormal(rs) && std::isnormal(rs * rs) && std::frexp(rs, &e1) == 0.5 &&
+                      std::frexp(rs * rs, &e2) == 0.5 && std::isnormal(1.0 / (rs * rs));
+    if (m.dim == 2) {
+        if (pow2)
+            hipLaunchKernelGGL((k_mls_build<2, true>), dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re,
+                               rs, wkind, set, counters, latch);
+        else
+            hipLaunchKernelGGL((k_mls_build<2, false>), dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re,
+                               rs, wkind, set, counters, latch);
+    } else {
+        if (pow2)
+            hipLaunchKernelGGL((k_mls_build<3, true>), dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re,
+                               rs, wkind, set, counters, latch);
+        else
+            hipLaunchKernelGGL((k_mls_build<3, false>), dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re,
+                               rs, wkind, set, counters, latch);
+    }
     return hipGetLastError();
 }
 
