@@ -101,8 +101,10 @@ __device__ __forceinline__ double taylor(double fc, const double* Phi, const dou
     return acc;
 }
 
-template <int DIM>
-__global__ __launch_bounds__(kBlock) void k_apply(MeshDev m, SetDev st, int op, const double* __restrict__ in,
+// One kernel per operator (OP = MCD_OP_*), so that each keeps only its own
+// registers.
+template <int DIM, int OP>
+__global__ __launch_bounds__(kBlock) void k_apply(MeshDev m, SetDev st, const double* __restrict__ in,
                                                   int ncomp, const double* __restrict__ fneu,
                                                   const double* __restrict__ shift, double* __restrict__ out,
                                                   double scale) {
@@ -113,23 +115,23 @@ __global__ __launch_bounds__(kBlock) void k_apply(MeshDev m, SetDev st, int op, 
         int ijk[3];
         cell_ijk(m, c, ijk);
         double Phi[NB];
-        if (op == MCD_OP_PHI) {
+        if constexpr (OP == MCD_OP_PHI) {
             poly_at<DIM>(m, st, c, ijk, in, fneu, Phi);
 #pragma unroll
             for (int q = 0; q < NB; ++q) out[q * Nc + c] = Phi[q] * scale;
-        } else if (op == MCD_OP_GRAD) {
+        } else if constexpr (OP == MCD_OP_GRAD) {
             double P1[1][NB];
             poly_multi<DIM, 1, DIM>(m, st, c, ijk, in, fneu, P1);
 #pragma unroll
             for (int a = 0; a < DIM; ++a) out[a * Nc + c] = P1[0][a] / rs * scale;
-        } else if (op == MCD_OP_DIV) {
+        } else if constexpr (OP == MCD_OP_DIV) {
             double P3[DIM][NB];
             poly_multi<DIM, DIM, DIM>(m, st, c, ijk, in, fneu, P3);
             double acc = 0.0;
 #pragma unroll
             for (int a = 0; a < DIM; ++a) acc += P3[a][a] / rs;
             out[c] = acc * scale;
-        } else if (op == MCD_OP_LAP) {
+        } else if constexpr (OP == MCD_OP_LAP) {
             if (ncomp == DIM) {
                 double P3[DIM][NB];
                 poly_multi<DIM, DIM>(m, st, c, ijk, in, fneu, P3);
@@ -511,9 +513,25 @@ static inline int grid_cells(int n) {
             hipLaunchKernelGGL(KERNEL<3>, dim3(grid_cells(m.Nc)), dim3(kBlock), 0, st, __VA_ARGS__);    \
     } while (0)
 
+template <int OP>
+static void launch_apply_op(const MeshDev& m, const SetDev& set, const double* in, int ncomp, const double* fneu,
+                            const double* shift, double* out, double scale, hipStream_t st) {
+    const dim3 g(grid_cells(m.Nc));
+    if (m.dim == 2)
+        hipLaunchKernelGGL((k_apply<2, OP>), g, dim3(kBlock), 0, st, m, set, in, ncomp, fneu, shift, out, scale);
+    else
+        hipLaunchKernelGGL((k_apply<3, OP>), g, dim3(kBlock), 0, st, m, set, in, ncomp, fneu, shift, out, scale);
+}
+
 hipError_t launch_apply(const MeshDev& m, const SetDev& set, int op, const double* in, int ncomp,
                         const double* fneu, const double* shift, double* out, double scale, hipStream_t st) {
-    MCD_DISPATCH(k_apply, m, set, op, in, ncomp, fneu, shift, out, scale);
+    switch (op) {
+        case MCD_OP_PHI: launch_apply_op<MCD_OP_PHI>(m, set, in, ncomp, fneu, shift, out, scale, st); break;
+        case MCD_OP_GRAD: launch_apply_op<MCD_OP_GRAD>(m, set, in, ncomp, fneu, shift, out, scale, st); break;
+        case MCD_OP_DIV: launch_apply_op<MCD_OP_DIV>(m, set, in, ncomp, fneu, shift, out, scale, st); break;
+        case MCD_OP_LAP: launch_apply_op<MCD_OP_LAP>(m, set, in, ncomp, fneu, shift, out, scale, st); break;
+        default: launch_apply_op<MCD_OP_SHIFT>(m, set, in, ncomp, fneu, shift, out, scale, st); break;
+    }
     return hipGetLastError();
 }
 

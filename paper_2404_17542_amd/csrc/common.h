@@ -305,8 +305,33 @@ __device__ __forceinline__ bool neighbour(const MeshDev& m, const int ijk[3], in
     return true;
 }
 
+// The same without branches: when the neighbour lies outside a
+// non-periodic mesh, j = self and shift = 0 (and false is returned), so that
+// j is always a valid index.
 template <int DIM>
-__device__ __forceinline__ int slot_nonzeros(int s) {
+__device__ __forceinline__ bool neighbour_or_self(const MeshDev& m, const int ijk[3], int s, int self, int& j,
+                                                  double shift[3]) {
+    const int o[3] = {s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1};
+    int idx = 0, stride = 1;
+    bool ok = true;
+#pragma unroll
+    for (int a = 0; a < DIM; ++a) {
+        int ii = ijk[a] + o[a];
+        const bool lo = ii < 0, hi = ii >= m.n[a];
+        ii = lo ? ii + m.n[a] : (hi ? ii - m.n[a] : ii);
+        ok = ok && (!(lo || hi) || m.periodic[a] != 0);
+        shift[a] = (double)(lo ? -1 : (hi ? 1 : 0)) * m.length[a];
+        idx += ii * stride;
+        stride *= m.n[a];
+    }
+    j = ok ? idx : self;
+    if (!ok)
+        for (int a = 0; a < DIM; ++a) shift[a] = 0.0;
+    return ok;
+}
+
+template <int DIM>
+__device__ __forceinline__ constexpr int slot_nonzeros(int s) {
     int o[3] = {s % 3 - 1, (s / 3) % 3 - 1, s / 9 - 1};
     int nz = 0;
 #pragma unroll

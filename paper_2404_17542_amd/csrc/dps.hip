@@ -159,12 +159,20 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
 #pragma unroll
         for (int a = 0; a < DIM; ++a) F[a] = 0.0;
         constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
-        for (int s = 0; s < S; ++s) {
+        // every slot without branches, so that the square roots and divisions
+        // of different neighbours overlap; a slot that is no spring (outside
+        // the mesh, a void neighbour, a coincident one) adds an exact zero,
+        // which leaves the sum's bits unchanged (F is never -0)
+#pragma unroll 1
+        for (int s0 = 0; s0 < S; s0 += 9) {      // one plane of 3 x 3 slots at a time
+#pragma unroll
+          for (int t = 0; t < 9; ++t) {
+            const int s = s0 + t;
             if (s == CEN) continue;
             int j;
             double sh[3];
-            if (!neighbour<DIM>(m, ijk, s, j, sh)) continue;
-            if (role[j] == MCD_ROLE_VOID) continue;
+            const bool inm = neighbour_or_self<DIM>(m, ijk, s, c, j, sh);
+            const bool live = inm && role[j] != MCD_ROLE_VOID;
             double d[DIM];
 #pragma unroll
             for (int a = 0; a < DIM; ++a) d[a] = (pin[a * Nc + j] + sh[a]) - x[a];
@@ -172,12 +180,16 @@ __global__ __launch_bounds__(kBlock) void k_relax(MeshDev m, BodiesDev B, double
 #pragma unroll
             for (int a = 1; a < DIM; ++a) d2 = d2 + d[a] * d[a];
             const double dist = sqrt(d2);
-            if (!(dist > 0.0)) continue;   // a coincident neighbour has no direction
+            const bool ok = live && dist > 0.0;   // a coincident neighbour has no direction
             const int nz = slot_nonzeros<DIM>(s);
             const double L = nz == 1 ? sp1 : (nz == 2 ? sp2 : sp3);
             const double g = 1.0 - dist / L;
 #pragma unroll
-            for (int a = 0; a < DIM; ++a) F[a] = F[a] + g * (d[a] / dist);
+            for (int a = 0; a < DIM; ++a) {
+                const double term = g * (d[a] / dist);
+                F[a] = F[a] + (ok ? term : 0.0);
+            }
+          }
         }
         double xs[DIM];
 #pragma unroll

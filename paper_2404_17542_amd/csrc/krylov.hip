@@ -977,11 +977,15 @@ __device__ __forceinline__ double beff_row(const MeshDev& m, const SetDev& st, i
         int j;
         double sh[3];
         neighbour<DIM>(m, ijk, s, j, sh);
+        // only known value neighbours and Neumann rows move to the right-hand
+        // side: the weights of the other slots are not read
+        const bool known = v && !st.unknown[j];
+        if (!known && !n) continue;
         double ph[NB];
 #pragma unroll
         for (int q = 0; q < NB; ++q) ph[q] = ld_stream(st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
         const double lc = diag2<DIM>(ph) * irs2;
-        if (v && !st.unknown[j]) acc -= lc * g[j];
+        if (known) acc -= lc * g[j];
         if (n) acc -= lc * fneu[j];
     }
     if (fneu && ((nm >> S) & 1u)) {
