@@ -162,8 +162,12 @@ __global__ __launch_bounds__(kBlock) void k_apply(MeshDev m, SetDev st, const do
     }
 }
 
-// Appendix A remap: u~ = u^k(x^{k+1}) with the step-k weights.
-template <int DIM>
+// Appendix A remap: u~ = u^k(x^{k+1}) with the step-k weights.  Two
+// launches over the cells: TRANS = false takes every cell except the inner
+// DPs that were not inner at step k, TRANS = true takes exactly those (the
+// shifted support of Eq. A.2); the rare second case kept out of the first
+// launch leaves it the registers and schedule of a plain weight application.
+template <int DIM, bool TRANS>
 __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const double* __restrict__ u,
                                                   const double* __restrict__ pos_prev,
                                                   const double* __restrict__ pos,
@@ -174,10 +178,12 @@ __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const do
     const size_t Nc = (size_t)m.Nc;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
         const int rn = role[c];
+        const bool moved_in = rn == MCD_ROLE_INNER && role_prev[c] != MCD_ROLE_INNER;
+        if (moved_in != TRANS) continue;
         if (rn == MCD_ROLE_INNER) {
             int src = c;
             const int rp = role_prev[c];
-            if (rp != MCD_ROLE_INNER) {
+            if constexpr (TRANS) {
                 int ijk[3];
                 cell_ijk(m, c, ijk);
                 int off[3] = {0, 0, 0};
@@ -207,7 +213,8 @@ __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const do
                 }
                 const bool good = ok && role_prev[cp] == MCD_ROLE_INNER;
                 src = good ? cp : c;
-                atomicAdd(&counters[good ? 0 : 1], 1);
+                wave_count_add(&counters[0], good);
+                wave_count_add(&counters[1], !good);
             }
             int sijk[3];
             cell_ijk(m, src, sijk);
@@ -538,7 +545,18 @@ hipError_t launch_apply(const MeshDev& m, const SetDev& set, int op, const doubl
 hipError_t launch_remap(const MeshDev& m, const SetDev& set_prev, const double* u, const double* pos_prev,
                         const double* pos, const int8_t* role_prev, const int8_t* role, const BodiesDev& Bprev,
                         const BodiesDev& Bnew, double* out, int* counters, hipStream_t st) {
-    MCD_DISPATCH(k_remap, m, set_prev, u, pos_prev, pos, role_prev, role, Bprev, Bnew, out, counters);
+    const dim3 g(grid_cells(m.Nc));
+    if (m.dim == 2) {
+        hipLaunchKernelGGL((k_remap<2, false>), g, dim3(kBlock), 0, st, m, set_prev, u, pos_prev, pos, role_prev, role,
+                           Bprev, Bnew, out, counters);
+        hipLaunchKernelGGL((k_remap<2, true>), g, dim3(kBlock), 0, st, m, set_prev, u, pos_prev, pos, role_prev, role,
+                           Bprev, Bnew, out, counters);
+    } else {
+        hipLaunchKernelGGL((k_remap<3, false>), g, dim3(kBlock), 0, st, m, set_prev, u, pos_prev, pos, role_prev, role,
+                           Bprev, Bnew, out, counters);
+        hipLaunchKernelGGL((k_remap<3, true>), g, dim3(kBlock), 0, st, m, set_prev, u, pos_prev, pos, role_prev, role,
+                           Bprev, Bnew, out, counters);
+    }
     return hipGetLastError();
 }
 

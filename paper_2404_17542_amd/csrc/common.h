@@ -451,6 +451,15 @@ template <> __device__ __forceinline__ double diag2<3>(const double* P) { return
 // Reductions (wave64 shuffles, then LDS across the 4 waves of a block)
 // ---------------------------------------------------------------------------
 
+// Adds to *ctr the number of active lanes of the wave whose flag is set,
+// with one atomic per wave instead of one per lane (many lanes adding to one
+// counter serialise at the cache).
+__device__ __forceinline__ void wave_count_add(int* ctr, bool flag) {
+    const unsigned long long act = __ballot(1);
+    const unsigned long long fm = __ballot(flag);
+    if ((int)__lane_id() == __ffsll((unsigned long long)act) - 1 && fm != 0ull) atomicAdd(ctr, (int)__popcll(fm));
+}
+
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);

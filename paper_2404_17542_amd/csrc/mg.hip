@@ -58,8 +58,10 @@ struct MgWork {
     double* dense = nullptr;     // [Nc][Nc] coarsest matrix (FP64)
     float* inv = nullptr;        // [Nc][Nc] its inverse
     double* part = nullptr;      // [4][kMgParts] partial sums of the outer solver
-    double* tot = nullptr;       // [4] totals
-    double* host = nullptr;      // [4] pinned copy of the totals
+    double* host = nullptr;      // [4] totals, pinned host memory written by the reducing kernel
+    double* host_dev = nullptr;  // the same memory as the device sees it
+    hipEvent_t ev = nullptr;     // completion of the reducing kernel
+    struct MgScal* scal = nullptr;  // scalars of the outer iteration (device)
     int* flag = nullptr;         // [1] singular coarsest matrix
 };
 
@@ -752,9 +754,11 @@ hipError_t mg_alloc(const MeshDev& m, MgWork** out) {
     if (e == hipSuccess) e = hipMalloc((void**)&w->dense, (size_t)Nc * Nc * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&w->inv, (size_t)Nc * Nc * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void**)&w->part, 4 * kMgParts * sizeof(double));
-    if (e == hipSuccess) e = hipMalloc((void**)&w->tot, 4 * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&w->flag, sizeof(int));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&w->host, 4 * sizeof(double), hipHostMallocDefault);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&w->host, 4 * sizeof(double), hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&w->host_dev, w->host, 0);
+    if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipMalloc((void**)&w->scal, 64);
     return e;
 }
 
@@ -773,9 +777,11 @@ void mg_free(MgWork* w) {
     if (w->dense) (void)hipFree(w->dense);
     if (w->inv) (void)hipFree(w->inv);
     if (w->part) (void)hipFree(w->part);
-    if (w->tot) (void)hipFree(w->tot);
+
     if (w->flag) (void)hipFree(w->flag);
     if (w->host) (void)hipHostFree(w->host);
+    if (w->ev) (void)hipEventDestroy(w->ev);
+    if (w->scal) (void)hipFree(w->scal);
     delete w;
 }
 
@@ -908,9 +914,31 @@ __global__ void k_mgo_resid(MeshDev m, const double* __restrict__ A, const uint8
     mg_parts(q, 3, part);
 }
 
-// p = r + beta (p - omega v); the cycle's FP32 right-hand side b0 = p
+// Scalars of the outer iteration, kept on the device so that an iteration
+// needs one host synchronisation (after its last reduction) instead of three;
+// each is formed by the same IEEE operations the host would use.
+struct MgScal {
+    double rho, alpha, omega, rho_new;
+    int flag;                    // rhat.v vanished or is not finite: x and r were left as they were
+};
+
+__global__ void k_mgo_restart(MgScal* sc) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc->rho = 1.0;
+        sc->alpha = 1.0;
+        sc->omega = 1.0;
+        sc->flag = 0;
+    }
+}
+
+// p = r + beta (p - omega v), beta = (rho_new / rho) (alpha / omega) (0 on
+// the first iteration after a (re)start, with omega 0); the cycle's FP32
+// right-hand side b0 = p
 __global__ void k_mgo_p(int N, const uint8_t* __restrict__ unk, const double* __restrict__ r, double* __restrict__ p,
-                        const double* __restrict__ v, double beta, double omega, float* __restrict__ b0) {
+                        const double* __restrict__ v, const MgScal* __restrict__ sc, int first,
+                        float* __restrict__ b0) {
+    const double beta = first ? 0.0 : (sc->rho_new / sc->rho) * (sc->alpha / sc->omega);
+    const double omega = first ? 0.0 : sc->omega;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
         const double pv = unk[c] ? r[c] + beta * (p[c] - omega * v[c]) : 0.0;
         p[c] = pv;
@@ -941,8 +969,9 @@ __global__ void k_mgo_apply(MeshDev m, const double* __restrict__ A, const uint8
 }
 
 // s = r - alpha v; b0 = s
-__global__ void k_mgo_s(int N, const double* __restrict__ r, const double* __restrict__ v, double alpha,
-                        double* __restrict__ s, float* __restrict__ b0) {
+__global__ void k_mgo_s(int N, const double* __restrict__ r, const double* __restrict__ v,
+                        const MgScal* __restrict__ sc, double* __restrict__ s, float* __restrict__ b0) {
+    const double alpha = sc->alpha;
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
         const double sv = r[c] - alpha * v[c];
         s[c] = sv;
@@ -950,38 +979,79 @@ __global__ void k_mgo_s(int N, const double* __restrict__ r, const double* __res
     }
 }
 
-// x += alpha ph + omega sh; r = s - omega t; partials r.r, rhat.r
+// x += alpha ph + omega sh; r = s - omega t; partials r.r, rhat.r (nothing
+// changes when the iteration broke down)
 __global__ void k_mgo_xr(int N, double* __restrict__ x, const double* __restrict__ ph, const double* __restrict__ sh,
-                         const double* __restrict__ s, const double* __restrict__ t, double alpha, double omega,
+                         const double* __restrict__ s, const double* __restrict__ t, const MgScal* __restrict__ sc,
                          double* __restrict__ r, const double* __restrict__ rhat, double* part) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
-    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
-        x[c] = x[c] + alpha * ph[c] + omega * sh[c];
-        const double rv = s[c] - omega * t[c];
-        r[c] = rv;
-        q[0] += rv * rv;
-        q[1] += rhat[c] * rv;
-    }
+    const double alpha = sc->alpha, omega = sc->omega;
+    if (!sc->flag)
+        for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < N; c += gridDim.x * blockDim.x) {
+            x[c] = x[c] + alpha * ph[c] + omega * sh[c];
+            const double rv = s[c] - omega * t[c];
+            r[c] = rv;
+            q[0] += rv * rv;
+            q[1] += rhat[c] * rv;
+        }
     mg_parts(q, 2, part);
 }
 
-// totals of nq partial rows over nblk blocks, in block order
-__global__ void k_mgo_reduce(const double* __restrict__ part, int nblk, int nq, double* __restrict__ tot) {
+// Totals of nq partial rows over nblk blocks, in block order, and what the
+// iteration makes of them:
+//   kResid  r.r, b.b, rhat.r -> rho_new = rhat.r; host {r.r, b.b, rhat.r}
+//   kAlpha  rhat.v -> alpha = rho_new / rhat.v (flag when 0 or not finite)
+//   kOmega  t.s, t.t -> omega = t.s / t.t (0 when t.t = 0)
+//   kNext   r.r, rhat.r -> rho = rho_new, rho_new = rhat.r;
+//           host {r.r, rho_new, omega, flag}
+enum { kResid = 0, kAlpha = 1, kOmega = 2, kNext = 3 };
+
+__global__ void k_mgo_reduce(const double* __restrict__ part, int nblk, int nq, int mode, MgScal* sc,
+                             double* __restrict__ host) {
     __shared__ double lds[4][kBlock / 64];
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < nq; ++k)
         for (int b = threadIdx.x; b < nblk; b += blockDim.x) q[k] += part[k * kMgParts + b];
     block_sum<4>(q, lds);
-    if (threadIdx.x == 0)
-        for (int k = 0; k < 4; ++k) tot[k] = q[k];
+    if (threadIdx.x != 0) return;
+    if (mode == kResid) {
+        sc->rho_new = q[2];
+        host[0] = q[0];
+        host[1] = q[1];
+        host[2] = q[2];
+    } else if (mode == kAlpha) {
+        const double rv = q[0];
+        const bool bad = !(fabs(rv) > 0.0) || !isfinite(rv);
+        sc->flag = bad ? 1 : 0;
+        sc->alpha = bad ? 0.0 : sc->rho_new / rv;
+    } else if (mode == kOmega) {
+        sc->omega = q[1] > 0.0 ? q[0] / q[1] : 0.0;
+    } else {
+        if (!sc->flag) {
+            sc->rho = sc->rho_new;
+            sc->rho_new = q[1];
+        }
+        host[0] = q[0];
+        host[1] = sc->rho_new;
+        host[2] = sc->omega;
+        host[3] = (double)sc->flag;
+    }
 }
 
-static hipError_t totals(MgWork& w, int nblk, int nq, hipStream_t st, double* out) {
-    hipLaunchKernelGGL(k_mgo_reduce, dim3(1), dim3(kBlock), 0, st, w.part, nblk, nq, w.tot);
-    hipError_t e = hipMemcpyAsync(w.host, w.tot, 4 * sizeof(double), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipStreamSynchronize(st);
+// Reduction in mode `mode`; with `wait`, the host waits for it (polling an
+// event, which wakes it sooner than a blocking stream synchronisation) and
+// reads the four values its mode leaves in pinned host memory.
+static hipError_t totals(MgWork& w, int nblk, int nq, int mode, hipStream_t st, bool wait, double* out) {
+    hipLaunchKernelGGL(k_mgo_reduce, dim3(1), dim3(kBlock), 0, st, w.part, nblk, nq, mode, w.scal, w.host_dev);
+    if (!wait) return hipGetLastError();
+    hipError_t e = hipEventRecord(w.ev, st);
     if (e == hipSuccess)
-        for (int k = 0; k < 4; ++k) out[k] = w.host[k];
+        while ((e = hipEventQuery(w.ev)) == hipErrorNotReady) {
+        }
+    if (e == hipSuccess) {
+        const volatile double* h = w.host;
+        for (int k = 0; k < 4; ++k) out[k] = h[k];
+    }
     return e;
 }
 
@@ -1003,7 +1073,7 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
     int flag = 0;
     if ((e = hipMemcpyAsync(&flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_mgo_resid<DIM>, dim3(g), dim3(kBlock), 0, st, m, A, unk, V.b, V.x, V.r, V.rhat, 1, w.part);
-    if ((e = totals(w, g, 3, st, t4)) != hipSuccess) return e;
+    if ((e = totals(w, g, 3, kResid, st, true, t4)) != hipSuccess) return e;
     *out = MgResult{};
     out->coarse_singular = flag;
     const double bb = t4[1];
@@ -1013,45 +1083,39 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
         return hipSuccess;
     }
     const double tol2 = tol * tol * bb;
-    double rr = t4[0];
+    double rr = t4[0], rho_new = t4[2];
     int iters = 0, restarts = 0;
     while (rr > tol2 && iters < max_iter) {
         // (re)start: rhat = r (set by the residual kernel), rho = alpha = omega = 1, p = v = 0
-        double rho = 1.0, alpha = 1.0, omega = 1.0, rho_new = t4[2];
-        hipLaunchKernelGGL(k_mgo_p, dim3(g), dim3(kBlock), 0, st, N, unk, V.r, V.p, V.v, 0.0, 0.0, b0);
+        hipLaunchKernelGGL(k_mgo_restart, dim3(1), dim3(64), 0, st, w.scal);
         bool first = true, restart = false;
         while (iters < max_iter) {
-            if (!first) {
-                if (!(fabs(rho_new) > 1e-300)) {
-                    restart = true;
-                    break;
-                }
-                const double beta = (rho_new / rho) * (alpha / omega);
-                hipLaunchKernelGGL(k_mgo_p, dim3(g), dim3(kBlock), 0, st, N, unk, V.r, V.p, V.v, beta, omega, b0);
+            if (!first && !(fabs(rho_new) > 1e-300)) {
+                restart = true;
+                break;
             }
+            hipLaunchKernelGGL(k_mgo_p, dim3(g), dim3(kBlock), 0, st, N, unk, V.r, V.p, V.v, w.scal, first ? 1 : 0,
+                               b0);
             first = false;
             mg_cycle(m, w, st);
             hipLaunchKernelGGL(k_mgo_apply<DIM>, dim3(g), dim3(kBlock), 0, st, m, A, unk, y0, V.ph, V.v, V.rhat,
                                (const double*)nullptr, w.part);
-            if ((e = totals(w, g, 1, st, t4)) != hipSuccess) return e;
-            const double rv = t4[0];
-            if (!(fabs(rv) > 0.0) || !std::isfinite(rv)) {
-                restart = true;
-                break;
-            }
-            alpha = rho_new / rv;
-            hipLaunchKernelGGL(k_mgo_s, dim3(g), dim3(kBlock), 0, st, N, V.r, V.v, alpha, V.s, b0);
+            if ((e = totals(w, g, 1, kAlpha, st, false, nullptr)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_mgo_s, dim3(g), dim3(kBlock), 0, st, N, V.r, V.v, w.scal, V.s, b0);
             mg_cycle(m, w, st);
             hipLaunchKernelGGL(k_mgo_apply<DIM>, dim3(g), dim3(kBlock), 0, st, m, A, unk, y0, V.sh, V.t, V.rhat,
                                V.s, w.part);
-            if ((e = totals(w, g, 2, st, t4)) != hipSuccess) return e;
-            omega = t4[1] > 0.0 ? t4[0] / t4[1] : 0.0;
-            hipLaunchKernelGGL(k_mgo_xr, dim3(g), dim3(kBlock), 0, st, N, V.x, V.ph, V.sh, V.s, V.t, alpha, omega,
-                               V.r, V.rhat, w.part);
-            if ((e = totals(w, g, 2, st, t4)) != hipSuccess) return e;
-            rho = rho_new;
+            if ((e = totals(w, g, 2, kOmega, st, false, nullptr)) != hipSuccess) return e;
+            hipLaunchKernelGGL(k_mgo_xr, dim3(g), dim3(kBlock), 0, st, N, V.x, V.ph, V.sh, V.s, V.t, w.scal, V.r,
+                               V.rhat, w.part);
+            if ((e = totals(w, g, 2, kNext, st, true, t4)) != hipSuccess) return e;
+            if (t4[3] != 0.0) {          // rhat.v broke down: x unchanged, restart from its residual
+                restart = true;
+                break;
+            }
             rr = t4[0];
             rho_new = t4[1];
+            const double omega = t4[2];
             ++iters;
             if (rr <= tol2) break;
             if (omega == 0.0 || !std::isfinite(rr)) {
@@ -1062,8 +1126,9 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
         // confirm with the true residual (and restart from it if needed)
         hipLaunchKernelGGL(k_mgo_resid<DIM>, dim3(g), dim3(kBlock), 0, st, m, A, unk, V.b, V.x, V.r, V.rhat, 1,
                            w.part);
-        if ((e = totals(w, g, 3, st, t4)) != hipSuccess) return e;
+        if ((e = totals(w, g, 3, kResid, st, true, t4)) != hipSuccess) return e;
         rr = t4[0];
+        rho_new = t4[2];
         if (restart || rr > tol2) ++restarts;
         if (restart && restarts > 50) break;
     }

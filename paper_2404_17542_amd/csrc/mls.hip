@@ -221,12 +221,11 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                         M[i * (i + 1) / 2 + jc] = acc * inv;
                     }
                 }
-                if (sing) {
-                    atomicAdd(&counters[rc == MCD_ROLE_INNER ? 0 : 1], 1);
-                    if (rc == MCD_ROLE_INNER) {
-                        atomicMin(&counters[2], c);
-                        atomicAdd(latch, 1);
-                    }
+                wave_count_add(&counters[0], sing && rc == MCD_ROLE_INNER);
+                wave_count_add(&counters[1], sing && rc != MCD_ROLE_INNER);
+                if (sing && rc == MCD_ROLE_INNER) {
+                    atomicMin(&counters[2], c);
+                    atomicAdd(latch, 1);
                 }
             }
             if (sing) {
