@@ -15,7 +15,7 @@ namespace mcd {
 // Only basis components q < Q1 are formed (Q1 = DIM: the gradient), the
 // others are left 0, so a first-derivative operator reads DIM of the NB
 // weight planes.
-template <int DIM, int NC, int Q1 = Dims<DIM>::NB>
+template <int DIM, int NC, int Q1 = Dims<DIM>::NB, bool FLAT = false>
 __device__ __forceinline__ void poly_multi(const MeshDev& m, const SetDev& st, int c, const int ijk[3],
                                            const double* __restrict__ fld, const double* __restrict__ fneu,
                                            double (&Phi)[NC][Dims<DIM>::NB]) {
@@ -30,6 +30,38 @@ __device__ __forceinline__ void poly_multi(const MeshDev& m, const SetDev& st, i
     double fc[NC];
 #pragma unroll
     for (int k = 0; k < NC; ++k) fc[k] = fld[k * Nc + c];
+    if constexpr (FLAT) {
+        // for a few scattered cells (latency, not throughput, bounds them):
+        // every slot without branches, a plane of slots at a time, so that
+        // their loads overlap; a slot that is no row of the fit has zero
+        // weights (the build writes them) and a zero difference
+#pragma unroll 1
+        for (int s0 = 0; s0 < S; s0 += 9) {
+#pragma unroll
+            for (int t = 0; t < 9; ++t) {
+                const int s = s0 + t;
+                if (s == CEN) continue;
+                const bool v = (vm >> s) & 1u;
+                const bool n = fneu != nullptr && ((nm >> s) & 1u);
+                int j;
+                double sh[3];
+                neighbour_or_self<DIM>(m, ijk, s, c, j, sh);
+                double d[NC];
+#pragma unroll
+                for (int k = 0; k < NC; ++k) {
+                    const double fj = fld[k * Nc + j];
+                    const double gj = fneu != nullptr ? fneu[k * Nc + j] : 0.0;
+                    d[k] = v ? fj - fc[k] : (n ? gj : 0.0);
+                }
+#pragma unroll
+                for (int q = 0; q < Q1; ++q) {
+                    const double w = ld_stream(st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
+#pragma unroll
+                    for (int k = 0; k < NC; ++k) Phi[k][q] += w * d[k];
+                }
+            }
+        }
+    } else
     for (int s = 0; s < S; ++s) {
         if (s == CEN) continue;
         const bool v = (vm >> s) & 1u;
@@ -222,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_remap(MeshDev m, SetDev sp, const do
 #pragma unroll
             for (int a = 0; a < DIM; ++a) dx[a] = pos[a * Nc + c] - pos_prev[a * Nc + src];
             double P3[DIM][NB];
-            poly_multi<DIM, DIM>(m, sp, src, sijk, u, nullptr, P3);
+            poly_multi<DIM, DIM, Dims<DIM>::NB, TRANS>(m, sp, src, sijk, u, nullptr, P3);
 #pragma unroll
             for (int a = 0; a < DIM; ++a) out[a * Nc + c] = taylor<DIM>(u[a * Nc + src], P3[a], dx, sp.rs);
         } else {

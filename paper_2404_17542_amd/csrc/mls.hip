@@ -18,14 +18,16 @@
 #include "common.h"
 
 #include <cmath>
+#include <type_traits>
 
 namespace mcd {
 
 // cos^2(pi r / (2 r_e)) (Sec. 3.2) or the truncated Gaussian, with the
 // series cosine / exponential of common.h.
-__device__ __forceinline__ double mls_weight(double r, double re, int kind) {
+template <int WK>
+__device__ __forceinline__ double mls_weight(double r, double re) {
     if (r > re) return 0.0;
-    if (kind == MCD_WEIGHT_COS2) {
+    if (WK == MCD_WEIGHT_COS2) {
         const double t = series_cos(M_PI * r / (2.0 * re));
         return t * t;
     }
@@ -63,9 +65,9 @@ __device__ __forceinline__ int halo_slot(int lx, int ly, int lz, int s) {
 // Row of neighbour slot e: kind (0 none, 1 value, 2 Neumann), its basis
 // vector a (value or normal-derivative row, Eq. obj_func) and, when
 // want_w, its weight.
-template <int DIM, bool POW2>
+template <int DIM, bool POW2, int WK>
 __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, int e, bool centre,
-                                       const double* xc, double re, double rs, double rs_inv, int wkind, bool want_w,
+                                       const double* xc, double re, double rs, double rs_inv, bool want_w,
                                        double& w, double* a) {
     if (H.j[e] < 0) return 0;
     const int kind = row_kind(H.r[e], bc);
@@ -79,7 +81,7 @@ __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, i
         r2 += d[q] * d[q];
         X[q] = POW2 ? d[q] * rs_inv : d[q] / rs;
     }
-    if (want_w) w = mls_weight(sqrt(r2), re, wkind);
+    if (want_w) w = mls_weight<WK>(sqrt(r2), re);
     if (kind == 1) {
         basis<DIM>(X, a);
     } else {
@@ -93,12 +95,14 @@ __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, i
 
 // POW2: r_s is a power of two, so x / r_s and x * (1 / r_s) are the same
 // real number and round to the same double; the kernel then multiplies (the
-// divisions by r_s and r_s^2 are most of its division work).
-template <int DIM, bool POW2>
+// divisions by r_s and r_s^2 are most of its division work).  WK: the weight
+// function (one instantiation each, so that only its series constants
+// occupy scalar registers).
+template <int DIM, bool POW2, int WK>
 __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* __restrict__ pos,
                                                       const int8_t* __restrict__ role,
                                                       const double* __restrict__ normal, BcDev bc, double re,
-                                                      double rs, int wkind, SetDev st, int* counters,
+                                                      double rs, SetDev st, int* counters,
                                                       int* latch) {
     constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
     constexpr int NP = NB * (NB + 1) / 2;
@@ -173,7 +177,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
             if (rc != MCD_ROLE_VOID) {
                 for (int s = 0; s < S; ++s) {
                     double w = 0.0, a[NB];
-                    const int kind = row_lds<DIM, POW2>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs, rs_inv, wkind,
+                    const int kind = row_lds<DIM, POW2, WK>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs, rs_inv,
                                                   true, w, a);
                     if (kCacheW) wc[s][threadIdx.x] = w;
                     if (!kind) continue;
@@ -247,7 +251,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                 for (int q = 0; q < NB; ++q) y[q] = 0.0;
                 if (isv || isn) {
                     double w = kCacheW ? wc[s][threadIdx.x] : 0.0, a[NB];
-                    row_lds<DIM, POW2>(H, bc, e, s == CEN, xc, re, rs, rs_inv, wkind, !kCacheW, w, a);
+                    row_lds<DIM, POW2, WK>(H, bc, e, s == CEN, xc, re, rs, rs_inv, !kCacheW, w, a);
 #pragma unroll
                     for (int q = 0; q < NB; ++q) y[q] = w * a[q];
                     // forward L z = y, backward L^T y = z
@@ -319,20 +323,31 @@ hipError_t launch_mls_build(const MeshDev& m, const double* pos, const int8_t* r
     int e1 = 0, e2 = 0;
     const bool pow2 = std::isnormal(rs) && std::isnormal(rs * rs) && std::frexp(rs, &e1) == 0.5 &&
                       std::frexp(rs * rs, &e2) == 0.5 && std::isnormal(1.0 / (rs * rs));
+    const dim3 gd((int)g), bd(kBlock);
+    auto go = [&](auto dim_c, auto pow2_c, auto wk_c) {
+        constexpr int D = decltype(dim_c)::value;
+        constexpr bool P2 = decltype(pow2_c)::value;
+        constexpr int WK = decltype(wk_c)::value;
+        hipLaunchKernelGGL((k_mls_build<D, P2, WK>), gd, bd, 0, st, m, pos, role, normal, bc, re, rs, set, counters,
+                           latch);
+    };
+    using C2 = std::integral_constant<int, 2>;
+    using C3 = std::integral_constant<int, 3>;
+    using T = std::true_type;
+    using F = std::false_type;
+    using WC = std::integral_constant<int, MCD_WEIGHT_COS2>;
+    using WG = std::integral_constant<int, MCD_WEIGHT_GAUSS>;
+    const bool cos2 = wkind == MCD_WEIGHT_COS2;
     if (m.dim == 2) {
         if (pow2)
-            hipLaunchKernelGGL((k_mls_build<2, true>), dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re,
-                               rs, wkind, set, counters, latch);
+            cos2 ? go(C2{}, T{}, WC{}) : go(C2{}, T{}, WG{});
         else
-            hipLaunchKernelGGL((k_mls_build<2, false>), dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re,
-                               rs, wkind, set, counters, latch);
+            cos2 ? go(C2{}, F{}, WC{}) : go(C2{}, F{}, WG{});
     } else {
         if (pow2)
-            hipLaunchKernelGGL((k_mls_build<3, true>), dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re,
-                               rs, wkind, set, counters, latch);
+            cos2 ? go(C3{}, T{}, WC{}) : go(C3{}, T{}, WG{});
         else
-            hipLaunchKernelGGL((k_mls_build<3, false>), dim3((int)g), dim3(kBlock), 0, st, m, pos, role, normal, bc, re,
-                               rs, wkind, set, counters, latch);
+            cos2 ? go(C3{}, F{}, WC{}) : go(C3{}, F{}, WG{});
     }
     return hipGetLastError();
 }

@@ -94,16 +94,44 @@ struct Taps {
 // cout must be a multiple of 16.
 constexpr int kCR = 4, kCC = 32, kHR = kCR + 2, kHC = kCC + 2, kHalo = kHR * kHC;
 
+// Epilogue of a 32-pixel x 32-channel accumulator tile of wave `wave`: bias,
+// ReLU and BF16 through the wave's 32 x 32 LDS tile sw (rows kSW apart, so
+// that the two halves of the wave write different banks), so that every lane
+// stores 16 contiguous bytes of output plane z.
+constexpr int kSW = 40;
+__device__ __forceinline__ void conv_epilogue(const f32x16& acc, __bf16* sw, const ConvIn& in, int l, int wave,
+                                              int tx0, int ty0, int z, int nt, const float* __restrict__ bias,
+                                              int cout, int relu, __bf16* __restrict__ Y) {
+    const int row = l >> 1, col0 = 16 * (l & 1);
+    const int y = ty0 + wave, x = tx0 + row;
+    const int n = nt * 32 + (l & 31);
+    const float bn = (bias && n < cout) ? bias[n] : 0.0f;
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        float v = acc[i] + bn;
+        if (relu) v = fmaxf(v, 0.0f);
+        sw[(8 * (i >> 2) + 4 * (l >> 5) + (i & 3)) * kSW + (l & 31)] = (__bf16)v;
+    }
+    __syncthreads();
+    const int nc = nt * 32 + col0;
+    if (y < in.H && x < in.W && nc < cout) {
+        const bf16x8* src = (const bf16x8*)(sw + row * kSW + col0);
+        bf16x8* dst = (bf16x8*)(Y + fine_px(in, z, y, x) * cout + nc);
+        dst[0] = src[0];
+        dst[1] = src[1];
+    }
+}
+
 // Grid: x = column tiles, y = row tiles x planes, z = 32-column tiles of
 // output channels (so that small coarse-level images still spread over the
-// whole chip).
+// whole chip).  Used for 2D; 3D convolutions go through k_conv3_march.
 template <int DIM>
 __global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __restrict__ Wk, int np,
                                                    const float* __restrict__ bias, int cout, int relu,
                                                    __bf16* __restrict__ Y) {
     using TP = Taps<DIM>;
     __shared__ __attribute__((aligned(16))) __bf16 tile[TP::HZ * kHalo * 16];
-    __shared__ __attribute__((aligned(16))) __bf16 stage[4][32 * 32];
+    __shared__ __attribute__((aligned(16))) __bf16 stage[4][32 * kSW];
     const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
     const int nty = (in.H + kCR - 1) / kCR;
     const int tx0 = blockIdx.x * kCC, ty0 = (blockIdx.y % nty) * kCR, z = blockIdx.y / nty, nt = blockIdx.z;
@@ -132,24 +160,121 @@ __global__ __launch_bounds__(256) void k_conv_mfma(ConvIn in, const __bf16* __re
         }
         __syncthreads();
     }
-    __bf16* sw = stage[wave];
-    const int row = l >> 1, col0 = 16 * (l & 1);
-    const int y = ty0 + wave, x = tx0 + row;
-    const int n = nt * 32 + (l & 31);
-    const float bn = (bias && n < cout) ? bias[n] : 0.0f;
+    conv_epilogue(acc, stage[wave], in, l, wave, tx0, ty0, z, nt, bias, cout, relu, Y);
+}
+
+// 3D convolution marching along z.  A block owns a 4 x 32 tile of one
+// column of up to zb consecutive output planes and one 32-wide tile of
+// output channels (grid: x = column tiles, y = row tiles x plane groups,
+// z = channel tiles).  Work proceeds in stages (input plane p, 16-channel
+// chunk): the stage's 6 x 34 halo tile and the 27 taps' B fragments of the
+// chunk are staged in LDS (the B fragments once per block when K is one
+// chunk), and the next stage's loads are issued into registers before the
+// matrix-core work of the current one.  Plane p contributes to the outputs
+// p + 1, p and p - 1 (taps with dz = -1, 0, +1), kept in three rolling
+// accumulators; the A fragment of a (dy, dx) offset is read once for the
+// three of them.  After plane p the output p - 1 is complete and goes
+// through conv_epilogue.  Each input plane is read once per block instead of
+// three times.
+constexpr int kTap3 = 27, kWVec = kTap3 * 32 * 2;      // B vectors (8 bf16) of a chunk
+constexpr int kAReg = (2 * kHalo + 255) / 256, kBReg = (kWVec + 255) / 256;
+// LDS stride of a pixel's 16 input channels (A): 48 bytes, so that the
+// 16-byte fragment reads of consecutive lanes fall in different banks
+constexpr int kPX = 24;
+
+__global__ __launch_bounds__(256, 3) void k_conv3_march(ConvIn in, const __bf16* __restrict__ Wk, int np,
+                                                     const float* __restrict__ bias, int cout, int relu, int zb,
+                                                     __bf16* __restrict__ Y) {
+    __shared__ __attribute__((aligned(16))) __bf16 tile[kHalo * kPX];
+    __shared__ __attribute__((aligned(16))) __bf16 wt[kTap3 * 32 * 16];
+    __shared__ __attribute__((aligned(16))) __bf16 stage[4][32 * kSW];
+    const int wave = threadIdx.x >> 6, l = threadIdx.x & 63;
+    const int nty = (in.H + kCR - 1) / kCR;
+    const int tx0 = blockIdx.x * kCC, ty0 = (blockIdx.y % nty) * kCR, z0 = (blockIdx.y / nty) * zb;
+    const int nt = blockIdx.z;
+    const int z1 = z0 + zb < in.D ? z0 + zb : in.D;      // outputs [z0, z1)
+    const int K = in.c0 + in.c1;
+    const int nch = K / 16;
+    const int half = 8 * (l >> 5);
+    const int pf = z0 - 1 > 0 ? z0 - 1 : 0, pl = z1 < in.D - 1 ? z1 : in.D - 1;
+    const int nst = (pl - pf + 1) * nch;                 // stages (plane, chunk), planes [pf, pl]
+    bf16x8 ra[kAReg], rb[kBReg];
+    auto fetch = [&](int si) {
+        const int p = pf + si / nch, k0 = (si % nch) * 16;
+#pragma unroll
+        for (int j = 0; j < kAReg; ++j) {
+            const int v = threadIdx.x + 256 * j;
+            if (v < 2 * kHalo) {
+                const int px = v >> 1, hv = v & 1;
+                ra[j] = load8(in, p, ty0 - 1 + px / kHC, tx0 - 1 + px % kHC, k0 + 8 * hv);
+            }
+        }
+        if (nch > 1 || si == 0) {
+#pragma unroll
+            for (int j = 0; j < kBReg; ++j) {
+                const int v = threadIdx.x + 256 * j;
+                if (v < kWVec) {
+                    const int t = v >> 6, n = (v >> 1) & 31, hv = v & 1;
+                    rb[j] = *(const bf16x8*)(Wk + ((size_t)t * np + nt * 32 + n) * K + k0 + 8 * hv);
+                }
+            }
+        }
+    };
+    auto publish = [&](int si) {
+#pragma unroll
+        for (int j = 0; j < kAReg; ++j) {
+            const int v = threadIdx.x + 256 * j;
+            if (v < 2 * kHalo) *(bf16x8*)(tile + (v >> 1) * kPX + 8 * (v & 1)) = ra[j];
+        }
+        if (nch > 1 || si == 0) {
+#pragma unroll
+            for (int j = 0; j < kBReg; ++j) {
+                const int v = threadIdx.x + 256 * j;
+                if (v < kWVec) *(bf16x8*)(wt + ((v >> 6) * 32 + ((v >> 1) & 31)) * 16 + 8 * (v & 1)) = rb[j];
+            }
+        }
+    };
+    f32x16 a0, a1, a2;                                   // outputs p - 1, p, p + 1
 #pragma unroll
     for (int i = 0; i < 16; ++i) {
-        float v = acc[i] + bn;
-        if (relu) v = fmaxf(v, 0.0f);
-        sw[(8 * (i >> 2) + 4 * (l >> 5) + (i & 3)) * 32 + (l & 31)] = (__bf16)v;
+        a0[i] = 0.0f;
+        a1[i] = 0.0f;
+        a2[i] = 0.0f;
     }
-    __syncthreads();
-    const int nc = nt * 32 + col0;
-    if (y < in.H && x < in.W && nc < cout) {
-        const bf16x8* src = (const bf16x8*)(sw + row * 32 + col0);
-        bf16x8* dst = (bf16x8*)(Y + fine_px(in, z, y, x) * cout + nc);
-        dst[0] = src[0];
-        dst[1] = src[1];
+    int si = 0;
+    if (nst > 0) fetch(0);
+    for (int p = z0 - 1; p <= z1; ++p) {
+        if (p >= 0 && p < in.D) {
+            const bool o0 = p - 1 >= z0 && p - 1 < z1, o1 = p >= z0 && p < z1, o2 = p + 1 >= z0 && p + 1 < z1;
+            for (int c = 0; c < nch; ++c, ++si) {
+                publish(si);
+                __syncthreads();
+                if (si + 1 < nst) fetch(si + 1);
+                const __bf16* wl = wt + (l & 31) * 16 + half;
+#pragma unroll
+                for (int hy = 0; hy < 3; ++hy)
+#pragma unroll
+                    for (int hx = 0; hx < 3; ++hx) {
+                        const int t2 = hy * 3 + hx;           // tap within a plane
+                        const bf16x8 a = *(const bf16x8*)(tile + ((wave + hy) * kHC + (l & 31) + hx) * kPX + half);
+                        // output p - 1 reads plane p with dz = +1 (taps 18..26), output p with dz = 0
+                        // (taps 9..17), output p + 1 with dz = -1 (taps 0..8)
+                        if (o0) a0 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    a, *(const bf16x8*)(wl + (18 + t2) * 32 * 16), a0, 0, 0, 0);
+                        if (o1) a1 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    a, *(const bf16x8*)(wl + (9 + t2) * 32 * 16), a1, 0, 0, 0);
+                        if (o2) a2 = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                                    a, *(const bf16x8*)(wl + t2 * 32 * 16), a2, 0, 0, 0);
+                    }
+                __syncthreads();
+            }
+        }
+        if (p - 1 >= z0 && p - 1 < z1)
+            conv_epilogue(a0, stage[wave], in, l, wave, tx0, ty0, p - 1, nt, bias, cout, relu, Y);
+        a0 = a1;
+        a1 = a2;
+#pragma unroll
+        for (int i = 0; i < 16; ++i) a2[i] = 0.0f;
     }
 }
 
@@ -623,11 +748,17 @@ static inline int grid_of(size_t n, int block = 256) {
 static hipError_t launch_conv(const ConvIn& in, const __bf16* Wk, int np, const float* bias, int cout, int relu,
                               __bf16* Y, hipStream_t st) {
     if (np % 32) return hipErrorInvalidValue;
-    const dim3 g((in.W + kCC - 1) / kCC, (in.H + kCR - 1) / kCR * in.D, np / 32), b(256);
-    if (in.zs)
-        hipLaunchKernelGGL(k_conv_mfma<3>, g, b, 0, st, in, Wk, np, bias, cout, relu, Y);
-    else
+    const int gx = (in.W + kCC - 1) / kCC, gy = (in.H + kCR - 1) / kCR;
+    if (in.zs) {
+        // planes per block: the most (up to 8) that still leave at least 1024 blocks
+        int zb = 8;
+        while (zb > 1 && (long long)gx * gy * ((in.D + zb - 1) / zb) * (np / 32) < 1024) zb >>= 1;
+        const dim3 g(gx, gy * ((in.D + zb - 1) / zb), np / 32), b(256);
+        hipLaunchKernelGGL(k_conv3_march, g, b, 0, st, in, Wk, np, bias, cout, relu, zb, Y);
+    } else {
+        const dim3 g(gx, gy * in.D, np / 32), b(256);
         hipLaunchKernelGGL(k_conv_mfma<2>, g, b, 0, st, in, Wk, np, bias, cout, relu, Y);
+    }
     return hipGetLastError();
 }
 
