@@ -39,6 +39,23 @@ __device__ __forceinline__ TA ld_stream(const TA* p) {
     return __builtin_nontemporal_load(p);
 }
 
+// Load of a matrix entry that iterative solvers read once per iteration:
+// non-temporal (NT) when the matrix and vectors of an iteration exceed the
+// last-level cache, so that the streamed matrix does not evict the vectors;
+// plain otherwise, so that the matrix stays in cache from one iteration to
+// the next.
+template <bool NT, typename TA>
+__device__ __forceinline__ TA ld_mat(const TA* p) {
+    if constexpr (NT)
+        return __builtin_nontemporal_load(p);
+    else
+        return *p;
+}
+
+// The last-level cache (256 MB on the MI355X) holds an iteration's data when
+// they stay below this.
+constexpr size_t kCacheFitBytes = 192u << 20;
+
 struct BodiesDev {
     int n;
     int id[kMaxBodies];

@@ -71,7 +71,9 @@ struct KBufs {
     int ntiles;          // tiles (2D) or bricks (3D) of the mesh
     int tpb;             // tiles or bricks per block
     int tz;              // planes per brick (3D)
+    int nt;              // matrix loads non-temporal (the iteration's data exceed the last-level cache)
 };
+
 
 // Sum of A[s][c] * val(j) over the stencil slots of cell c.  Interior cells
 // use constant slot offsets; cells on the mesh edge take the general path.
@@ -243,7 +245,7 @@ __device__ __forceinline__ int halo_cell(const MeshDev& m, int gx, int gy) {
     return gx + m.n[0] * gy;
 }
 
-template <typename T, typename TA>
+template <bool NT, typename T, typename TA>
 __device__ __forceinline__ T stencil_lds(const TA* __restrict__ A, size_t mps, int c, const T* lds, int lx, int ly) {
     T acc = 0;
     if constexpr (sizeof(TA) < sizeof(double)) {
@@ -251,12 +253,12 @@ __device__ __forceinline__ T stencil_lds(const TA* __restrict__ A, size_t mps, i
         const T xc = lds[(ly + 1) * HX + lx + 1];
 #pragma unroll
         for (int s = 0; s < 9; ++s) {
-            const T a = (T)ld_stream(A + (size_t)s * mps + c);
+            const T a = (T)ld_mat<NT>(A + (size_t)s * mps + c);
             acc += s == 4 ? a * xc : a * (lds[(ly + s / 3) * HX + (lx + s % 3)] - xc);
         }
     } else {
 #pragma unroll
-        for (int s = 0; s < 9; ++s) acc += (T)ld_stream(A + (size_t)s * mps + c) * lds[(ly + s / 3) * HX + (lx + s % 3)];
+        for (int s = 0; s < 9; ++s) acc += (T)ld_mat<NT>(A + (size_t)s * mps + c) * lds[(ly + s / 3) * HX + (lx + s % 3)];
     }
     return acc;
 }
@@ -291,7 +293,7 @@ __device__ __forceinline__ void tile_origin(const KBufs& K, int tile, int& tx0, 
     ty0 = (tile / K.ntx) * TY;
 }
 
-template <typename T, typename TA>
+template <typename T, typename TA, bool NT>
 __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T, TA> V, KBufs K) {
     __shared__ T xl[NH];
     const T* __restrict__ xp = V.x;
@@ -313,7 +315,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T, TA> V, K
         const int gx = tx0 + lx, gy = ty0 + ly;
         if (gx < m.n[0] && gy < m.n[1]) {
             const int c = gx + m.n[0] * gy;
-            const T ax = stencil_lds<T, TA>(A, m.mps, c, xl, lx, ly);
+            const T ax = stencil_lds<NT, T, TA>(A, m.mps, c, xl, lx, ly);
             const T bc = bp[c];
             const T r = bc - ax;
             sp[c] = r;
@@ -405,7 +407,7 @@ __device__ __forceinline__ void load_halo_p(const MeshDev& m, int tx0, int ty0, 
 // partials, the halo operands, the matrix row, rhat) is issued before the
 // block reduction, and the next tile's halo operands while the current tile
 // is formed, so that the memory latencies overlap.
-template <typename T, typename TA, int MODE>
+template <typename T, typename TA, int MODE, bool NT>
 __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T pl[NH];
     const KState* __restrict__ in = K.st[2];
@@ -470,7 +472,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
             c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
             if (c >= 0) {
 #pragma unroll
-                for (int s = 0; s < 9; ++s) a[s] = ld_stream(A + (size_t)s * m.mps + c);
+                for (int s = 0; s < 9; ++s) a[s] = ld_mat<NT>(A + (size_t)s * m.mps + c);
                 rhc = rh[c];
             }
         }
@@ -534,7 +536,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
 }
 
 // S-stage (2D), load-first like the P-stage.
-template <typename T, typename TA>
+template <typename T, typename TA, bool NT>
 __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T sl[NH];
     const KState* __restrict__ in = K.st[1];
@@ -573,7 +575,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
         c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
         if (c >= 0) {
 #pragma unroll
-            for (int s = 0; s < 9; ++s) a[s] = ld_stream(A + (size_t)s * m.mps + c);
+            for (int s = 0; s < 9; ++s) a[s] = ld_mat<NT>(A + (size_t)s * m.mps + c);
             rhc = rh[c];
         }
     }
@@ -607,7 +609,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
             c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
             if (c >= 0) {
 #pragma unroll
-                for (int s = 0; s < 9; ++s) a[s] = ld_stream(A + (size_t)s * m.mps + c);
+                for (int s = 0; s < 9; ++s) a[s] = ld_mat<NT>(A + (size_t)s * m.mps + c);
                 rhc = rh[c];
             }
         }
@@ -707,10 +709,10 @@ __device__ __forceinline__ void brick_origin(const KBufs& K, int brick, int& tx0
 }
 
 // Matrix row of cell c (27 slot planes) into registers.
-template <typename TA>
+template <bool NT, typename TA>
 __device__ __forceinline__ void load_row27(const TA* __restrict__ A, size_t mps, int c, TA (&a)[27]) {
 #pragma unroll
-    for (int s = 0; s < 27; ++s) a[s] = ld_stream(A + (size_t)s * mps + c);
+    for (int s = 0; s < 27; ++s) a[s] = ld_mat<NT>(A + (size_t)s * mps + c);
 }
 
 // 27-point product of a preloaded row with the ring planes (slots of planes
@@ -762,7 +764,7 @@ __device__ __forceinline__ void march_bricks(const MeshDev& m, const KBufs& K, F
     }
 }
 
-template <typename T, typename TA>
+template <typename T, typename TA, bool NT>
 __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, KBufs K) {
     __shared__ T ring[3][NH];
     const T* __restrict__ xp = V.x;
@@ -783,7 +785,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
             }
         },
         [&](int c) {
-            load_row27<TA>(A, m.mps, c, a);
+            load_row27<NT, TA>(A, m.mps, c, a);
             bcv = bp[c];
         },
         [&](int c, int s0, int s1, int s2) {
@@ -799,7 +801,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
     write_partials<2>(v, K.part[0], K);
 }
 
-template <typename T, typename TA, int MODE>
+template <typename T, typename TA, int MODE, bool NT>
 __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T ring[3][NH];
     const KState* __restrict__ in = K.st[2];
@@ -861,7 +863,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
             }
         },
         [&](int c) {
-            load_row27<TA>(A, m.mps, c, a);
+            load_row27<NT, TA>(A, m.mps, c, a);
             rhc = rh[c];
         },
         [&](int c, int s0, int s1, int s2) {
@@ -879,7 +881,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
     }
 }
 
-template <typename T, typename TA>
+template <typename T, typename TA, bool NT>
 __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T ring[3][NH];
     const KState* __restrict__ in = K.st[1];
@@ -934,7 +936,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
             }
         },
         [&](int c) {
-            load_row27<TA>(A, m.mps, c, a);
+            load_row27<NT, TA>(A, m.mps, c, a);
             rhc = rh[c];
         },
         [&](int c, int s0, int s1, int s2) {
@@ -1271,27 +1273,36 @@ struct KrylovWork {
 
 // Enqueues one Bi-CGSTAB iteration (P-stage in `mode`, then S-stage) with
 // operand parity par.
-template <int DIM, typename T, typename TA>
-static void enqueue_iteration(const MeshDev& m, const KVec<T, TA>& V, const KBufs& K, int par, int mode,
-                              hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, hipEvent_t e3) {
+template <int DIM, typename T, typename TA, bool NT>
+static void enqueue_iteration_nt(const MeshDev& m, const KVec<T, TA>& V, const KBufs& K, int par, int mode,
+                                 hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, hipEvent_t e3) {
     const dim3 G(K.nblk), B(kKBlock);
     if (m.dim == 2) {
         if (mode == P_FIRST)
-            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_FIRST>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_FIRST, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
         else if (mode == P_RESUME)
-            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_RESUME>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_RESUME, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
         else
-            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_NORMAL>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        hipExtLaunchKernelGGL((k_t2_S<T, TA>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_NORMAL, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_t2_S<T, TA, NT>), G, B, 0, st, e2, e3, 0, m, V, par, K);
     } else {
         if (mode == P_FIRST)
-            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_FIRST>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_FIRST, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
         else if (mode == P_RESUME)
-            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_RESUME>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_RESUME, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
         else
-            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_NORMAL>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        hipExtLaunchKernelGGL((k_t3_S<T, TA>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_NORMAL, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_t3_S<T, TA, NT>), G, B, 0, st, e2, e3, 0, m, V, par, K);
     }
+}
+
+template <int DIM, typename T, typename TA>
+static void enqueue_iteration(const MeshDev& m, const KVec<T, TA>& V, const KBufs& K, int par, int mode,
+                              hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, hipEvent_t e3) {
+    if (K.nt)
+        enqueue_iteration_nt<DIM, T, TA, true>(m, V, K, par, mode, st, e0, e1, e2, e3);
+    else
+        enqueue_iteration_nt<DIM, T, TA, false>(m, V, K, par, mode, st, e0, e1, e2, e3);
 }
 
 // Graph of kGraphIters non-first iterations starting at parity 1 (an even
@@ -1432,10 +1443,17 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, 
 template <int DIM, typename T, typename TA>
 static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K, int with_bb, double tol2,
                         hipStream_t st, KState* out, double delta2 = 0.0, double tol2_next = -1.0) {
-    if (m.dim == 2)
-        hipLaunchKernelGGL((k_t2_init<T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
-    else
-        hipLaunchKernelGGL((k_t3_init<T, TA>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+    if (m.dim == 2) {
+        if (K.nt)
+            hipLaunchKernelGGL((k_t2_init<T, TA, true>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+        else
+            hipLaunchKernelGGL((k_t2_init<T, TA, false>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+    } else {
+        if (K.nt)
+            hipLaunchKernelGGL((k_t3_init<T, TA, true>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+        else
+            hipLaunchKernelGGL((k_t3_init<T, TA, false>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+    }
     hipLaunchKernelGGL(k_kfinish, dim3(1), dim3(kKBlock), 0, st, K, with_bb, tol2, with_bb ? 0 : 1, delta2,
                        tol2_next < 0.0 ? tol2 : tol2_next);
     hipError_t e = hipGetLastError();
@@ -2046,9 +2064,14 @@ hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     (void)shape_of(m, kKGrid, m.dim == 3 ? kDefaultDepth : 1, K0);
     w->grid_req = kKGrid;
     const int cap = kKGrid;
+    // the matrix stays in the last-level cache between iterations when it fits
+    // there with the Krylov vectors; larger systems stream it
+    const size_t S = m.dim == 3 ? 27 : 9;
     for (KBufs* K : {&w->kb64, &w->kb32}) {
         *K = K0;
         K->cap = cap;
+        const size_t mat = S * (size_t)Nc * (K == &w->kb64 ? sizeof(double) : sizeof(float));
+        K->nt = mat + 10 * (size_t)Nc * sizeof(double) > kCacheFitBytes ? 1 : 0;
         for (int q = 0; q < 3; ++q) {
             if ((e = hipMalloc((void**)&K->part[q], 4 * (size_t)cap * sizeof(double))) != hipSuccess) return e;
             if ((e = hipMemset(K->part[q], 0, 4 * (size_t)cap * sizeof(double))) != hipSuccess) return e;
@@ -2065,7 +2088,6 @@ hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out) {
     if ((e = hipMalloc((void**)&w->beff, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->b32, (size_t)Nc * sizeof(float))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->xsave, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
-    const size_t S = m.dim == 3 ? 27 : 9;
     if ((e = hipMalloc((void**)&w->dinv, (size_t)Nc * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->jac64, S * m.mps * sizeof(double))) != hipSuccess) return e;
     if ((e = hipMalloc((void**)&w->jac32, S * m.mps * sizeof(float))) != hipSuccess) return e;

@@ -53,6 +53,7 @@ struct MgLevel {
 struct MgWork {
     int L = 0;
     int tail = 0;                // first level of the one-workgroup tail of the cycle
+    bool nt = true;              // level-0 and outer matrices streamed (they exceed the last-level cache)
     bool usable = false;         // the coarsest level has at most kMgMaxCoarse cells
     MgLevel lev[kMgMaxLevels];
     double* dense = nullptr;     // [Nc][Nc] coarsest matrix (FP64)
@@ -211,7 +212,7 @@ __device__ __forceinline__ float mg_av(const MgLv& L, int c, const int* ijk, flo
 }
 
 // (A x)_c of the FP64 PPE matrix (plain form, planes at stride m.mps).
-template <int DIM, typename F>
+template <int DIM, bool NT, typename F>
 __device__ __forceinline__ double mg_spmv64(const MeshDev& m, const double* __restrict__ A, int c, F val) {
     constexpr int S = Dims<DIM>::S;
     int ijk[3];
@@ -219,12 +220,12 @@ __device__ __forceinline__ double mg_spmv64(const MeshDev& m, const double* __re
     double acc = 0.0;
     if (mg_interior<DIM>(m, ijk)) {
 #pragma unroll
-        for (int s = 0; s < S; ++s) acc += ld_stream(A + (size_t)s * m.mps + c) * val(c + mg_off<DIM>(m, s));
+        for (int s = 0; s < S; ++s) acc += ld_mat<NT>(A + (size_t)s * m.mps + c) * val(c + mg_off<DIM>(m, s));
         return acc;
     }
 #pragma unroll
     for (int s = 0; s < S; ++s) {
-        const double a = ld_stream(A + (size_t)s * m.mps + c);
+        const double a = ld_mat<NT>(A + (size_t)s * m.mps + c);
         int j;
         double sh[3];
         if (!neighbour<DIM>(m, ijk, s, j, sh)) continue;
@@ -747,6 +748,9 @@ hipError_t mg_alloc(const MeshDev& m, MgWork** out) {
         nx.mps = padded_plane_stride((size_t)N);
         cur = nx;
     }
+    // the FP64 and FP32 matrices of level 0 stay in the last-level cache when
+    // they fit there with room for the vectors; larger ones are streamed
+    w->nt = (size_t)S * m.Nc * (sizeof(double) + sizeof(float)) > (kCacheFitBytes * 5) / 6;
     // the tail: the smallest levels, at most kMgMaxTail of them
     w->tail = w->L - 1;
     while (w->tail > 0 && w->lev[w->tail - 1].m.Nc <= kMgTailCells && w->L - (w->tail - 1) <= kMgMaxTail) --w->tail;
@@ -857,7 +861,7 @@ static void mg_cycle_dim(MgWork& w, hipStream_t st) {
         const MgLv F = mg_lv(w.lev[l], l), C = mg_lv(w.lev[l + 1], l + 1);
         const dim3 g((F.n[0] + MgBrick<DIM>::BX - 1) / MgBrick<DIM>::BX, (F.n[1] + MgBrick<DIM>::BY - 1) / MgBrick<DIM>::BY,
                      (F.n[2] + MgBrick<DIM>::BZ - 1) / MgBrick<DIM>::BZ);
-        if (l == 0)
+        if (l == 0 && w.nt)
             hipLaunchKernelGGL((k_mg_down<DIM, true>), g, dim3(kBlock), 0, st, F, C);
         else
             hipLaunchKernelGGL((k_mg_down<DIM, false>), g, dim3(kBlock), 0, st, F, C);
@@ -871,7 +875,7 @@ static void mg_cycle_dim(MgWork& w, hipStream_t st) {
         const MgLv F = mg_lv(w.lev[l], l), C = mg_lv(w.lev[l + 1], l + 1);
         const dim3 g(grid_for(F.Nc));
         hipLaunchKernelGGL(k_mg_prolong<DIM>, g, dim3(kBlock), 0, st, F, C);
-        if (l == 0)
+        if (l == 0 && w.nt)
             hipLaunchKernelGGL((k_mg_smooth<DIM, true>), g, dim3(kBlock), 0, st, F);
         else
             hipLaunchKernelGGL((k_mg_smooth<DIM, false>), g, dim3(kBlock), 0, st, F);
@@ -897,14 +901,14 @@ __device__ __forceinline__ void mg_parts(double (&q)[4], int nq, double* part) {
 }
 
 // r = b - A x, rhat = r (restart = 0 keeps rhat); partials r.r, b.b, rhat.r
-template <int DIM>
+template <int DIM, bool NT>
 __global__ void k_mgo_resid(MeshDev m, const double* __restrict__ A, const uint8_t* __restrict__ unk,
                             const double* __restrict__ b, const double* __restrict__ x, double* __restrict__ r,
                             double* __restrict__ rhat, int set_rhat, double* part) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
         double v = 0.0;
-        if (unk[c]) v = b[c] - mg_spmv64<DIM>(m, A, c, [&](int j) { return x[j]; });
+        if (unk[c]) v = b[c] - mg_spmv64<DIM, NT>(m, A, c, [&](int j) { return x[j]; });
         r[c] = v;
         if (set_rhat) rhat[c] = v;
         q[0] += v * v;
@@ -948,14 +952,14 @@ __global__ void k_mgo_p(int N, const uint8_t* __restrict__ unk, const double* __
 
 // z = (double) y0 (the preconditioned direction), w = A z; partials rhat.w
 // (or t.s, t.t with s given)
-template <int DIM>
+template <int DIM, bool NT>
 __global__ void k_mgo_apply(MeshDev m, const double* __restrict__ A, const uint8_t* __restrict__ unk,
                             const float* __restrict__ y0, double* __restrict__ z, double* __restrict__ wv,
                             const double* __restrict__ rhat, const double* __restrict__ s, double* part) {
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
         double v = 0.0;
-        if (unk[c]) v = mg_spmv64<DIM>(m, A, c, [&](int j) { return (double)y0[j]; });
+        if (unk[c]) v = mg_spmv64<DIM, NT>(m, A, c, [&](int j) { return (double)y0[j]; });
         z[c] = (double)y0[c];
         wv[c] = v;
         if (s) {
@@ -1068,11 +1072,27 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
     const float* y0 = w.lev[0].y;
     double t4[4];
     if (!w.usable) return hipErrorNotSupported;
+    auto resid = [&]() {
+        if (w.nt)
+            hipLaunchKernelGGL((k_mgo_resid<DIM, true>), dim3(g), dim3(kBlock), 0, st, m, A, unk, V.b, V.x, V.r,
+                               V.rhat, 1, w.part);
+        else
+            hipLaunchKernelGGL((k_mgo_resid<DIM, false>), dim3(g), dim3(kBlock), 0, st, m, A, unk, V.b, V.x, V.r,
+                               V.rhat, 1, w.part);
+    };
+    auto apply = [&](double* z, double* wv, const double* sv) {
+        if (w.nt)
+            hipLaunchKernelGGL((k_mgo_apply<DIM, true>), dim3(g), dim3(kBlock), 0, st, m, A, unk, y0, z, wv, V.rhat,
+                               sv, w.part);
+        else
+            hipLaunchKernelGGL((k_mgo_apply<DIM, false>), dim3(g), dim3(kBlock), 0, st, m, A, unk, y0, z, wv, V.rhat,
+                               sv, w.part);
+    };
     hipError_t e = mg_setup_dim<DIM>(w, set, st);
     if (e != hipSuccess) return e;
     int flag = 0;
     if ((e = hipMemcpyAsync(&flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_mgo_resid<DIM>, dim3(g), dim3(kBlock), 0, st, m, A, unk, V.b, V.x, V.r, V.rhat, 1, w.part);
+    resid();
     if ((e = totals(w, g, 3, kResid, st, true, t4)) != hipSuccess) return e;
     *out = MgResult{};
     out->coarse_singular = flag;
@@ -1098,13 +1118,11 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
                                b0);
             first = false;
             mg_cycle(m, w, st);
-            hipLaunchKernelGGL(k_mgo_apply<DIM>, dim3(g), dim3(kBlock), 0, st, m, A, unk, y0, V.ph, V.v, V.rhat,
-                               (const double*)nullptr, w.part);
+            apply(V.ph, V.v, nullptr);
             if ((e = totals(w, g, 1, kAlpha, st, false, nullptr)) != hipSuccess) return e;
             hipLaunchKernelGGL(k_mgo_s, dim3(g), dim3(kBlock), 0, st, N, V.r, V.v, w.scal, V.s, b0);
             mg_cycle(m, w, st);
-            hipLaunchKernelGGL(k_mgo_apply<DIM>, dim3(g), dim3(kBlock), 0, st, m, A, unk, y0, V.sh, V.t, V.rhat,
-                               V.s, w.part);
+            apply(V.sh, V.t, V.s);
             if ((e = totals(w, g, 2, kOmega, st, false, nullptr)) != hipSuccess) return e;
             hipLaunchKernelGGL(k_mgo_xr, dim3(g), dim3(kBlock), 0, st, N, V.x, V.ph, V.sh, V.s, V.t, w.scal, V.r,
                                V.rhat, w.part);
@@ -1124,8 +1142,7 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
             }
         }
         // confirm with the true residual (and restart from it if needed)
-        hipLaunchKernelGGL(k_mgo_resid<DIM>, dim3(g), dim3(kBlock), 0, st, m, A, unk, V.b, V.x, V.r, V.rhat, 1,
-                           w.part);
+        resid();
         if ((e = totals(w, g, 3, kResid, st, true, t4)) != hipSuccess) return e;
         rr = t4[0];
         rho_new = t4[2];
