@@ -337,14 +337,20 @@ typedef struct {
                             of A x = b, and the tolerance is confirmed on A (a miss is finished
                             by unpreconditioned FP64 Bi-CGSTAB within max_iter).  Columns with
                             a zero or non-finite diagonal are not scaled.
-                            MCD_PRECOND_MG (precision must be FP64): Bi-CGSTAB in FP64 on the
-                            FP64 matrix, right-preconditioned by one multigrid V-cycle in FP32
+                            MCD_PRECOND_MG (precision FP64 or FP32_MATRIX; FP32_REFINE is
+                            refused with MCD_ERR_ARG): Bi-CGSTAB with FP64 vectors and inner
+                            products, its matrix products with the FP64 matrix (FP64) or with
+                            the FP32 copy in difference form (FP32_MATRIX; fp64_below and the
+                            inner options are not used), right-preconditioned by one
+                            multigrid V-cycle in FP32
                             (geometric coarsening by 2 per axis down to at most 64 cells,
                             multilinear prolongation, averaging restriction, Galerkin coarse
                             operators R A P built for every solve, one damped-Jacobi sweep
                             (0.8) before and after each coarse correction, dense solve on the
-                            coarsest level); MCD_ERR_ARG when the mesh cannot be coarsened
-                            that far (an odd periodic axis or an axis below 6 cells). */
+                            coarsest level); the tolerance is confirmed with the FP64 matrix,
+                            and a run that misses it restarts from that residual; MCD_ERR_ARG
+                            when the mesh cannot be coarsened that far (an odd periodic axis or
+                            an axis below 6 cells). */
 } mcd_solve_opts;
 
 typedef struct {

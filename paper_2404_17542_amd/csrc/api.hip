@@ -698,8 +698,9 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
         (opts->precond != MCD_PRECOND_NONE && opts->precond != MCD_PRECOND_JACOBI &&
          opts->precond != MCD_PRECOND_MG))
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: invalid options%s");
-    if (opts->precond == MCD_PRECOND_MG && opts->precision != MCD_PREC_FP64)
-        return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: the multigrid preconditioner takes precision FP64 (its cycle runs in FP32)%s");
+    if (opts->precond == MCD_PRECOND_MG && opts->precision == MCD_PREC_FP32_REFINE)
+        return fail(c, MCD_ERR_ARG,
+                    "mcd_solve_ppe: the multigrid preconditioner takes precision FP64 or FP32_MATRIX (its cycle runs in FP32)%s");
     if (opts->precond == MCD_PRECOND_MG && !krylov_mg_usable(c->kw))
         return fail(c, MCD_ERR_ARG, "mcd_solve_ppe: this mesh cannot be coarsened to 64 cells (multigrid)%s");
     if (opts->precision != MCD_PREC_FP64 &&

@@ -626,7 +626,7 @@ void mg_free(MgWork* w);
 bool mg_usable(const MgWork* w);
 hipError_t mg_setup(const MeshDev& m, MgWork& w, const SetDev& set, hipStream_t st);
 hipError_t mg_bicgstab(const MeshDev& m, MgWork& w, const SetDev& set, const MgVecs& V, double tol, int max_iter,
-                       hipStream_t st, MgResult* out);
+                       bool f32_products, hipStream_t st, MgResult* out);
 hipError_t mg_apply(const MeshDev& m, MgWork& w, const SetDev& set, const double* in, double* out, int* levels,
                     hipStream_t st);
 

@@ -1536,12 +1536,15 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     const double* A64 = set.amat;
     const float* A32 = set.amat32;
     if (sp.precond == MCD_PRECOND_MG) {
-        // FP64 Bi-CGSTAB right-preconditioned by one FP32 V-cycle; p[1] and
-        // v[1] hold the preconditioned directions
+        // Bi-CGSTAB with FP64 vectors right-preconditioned by one FP32 V-cycle,
+        // products with the FP64 matrix or (FP32_MATRIX) its FP32 copy; p[1]
+        // and v[1] hold the preconditioned directions
         const MgVecs mv{w.v64.x, w.v64.r, w.v64.rhat, w.v64.p[0], w.v64.v[0], w.v64.s, w.v64.t, w.v64.p[1],
                         w.v64.v[1], w.beff};
         MgResult res;
-        if ((e = mg_bicgstab(m, *w.mg, set, mv, sp.tol, sp.max_iter, st, &res)) != hipSuccess) return e;
+        if ((e = mg_bicgstab(m, *w.mg, set, mv, sp.tol, sp.max_iter, sp.precision == MCD_PREC_FP32_MATRIX, st,
+                             &res)) != hipSuccess)
+            return e;
         out->iterations = res.iterations;
         out->restarts = res.restarts;
         out->converged = res.converged;

@@ -21,10 +21,12 @@
 // (prolongation, smoothing), and one workgroup for the levels of at most
 // kMgTailCells cells, where separate launches would cost more than the work.
 //
-// Outer solver: Bi-CGSTAB in FP64 with the FP64 matrix, right-preconditioned
-// (v = A M^-1 p, t = A M^-1 s, x += alpha M^-1 p + omega M^-1 s), inner
-// products from per-block partial sums added in a fixed order, scalars on
-// the host; stopping on ||r|| <= tol ||b|| confirmed by the true residual.
+// Outer solver: Bi-CGSTAB with FP64 vectors, right-preconditioned (v = A
+// M^-1 p, t = A M^-1 s, x += alpha M^-1 p + omega M^-1 s), its products with
+// the FP64 matrix or (mixed precision) with the FP32 copy in difference form;
+// inner products from per-block partial sums added in a fixed order; stopping
+// on ||r|| <= tol ||b|| confirmed by the true residual with the FP64 matrix,
+// from which a run that has not met the tolerance restarts (refinement).
 #include "common.h"
 
 #include <cmath>
@@ -951,16 +953,47 @@ __global__ void k_mgo_p(int N, const uint8_t* __restrict__ unk, const double* __
 }
 
 // z = (double) y0 (the preconditioned direction), w = A z; partials rhat.w
-// (or t.s, t.t with s given)
-template <int DIM, bool NT>
-__global__ void k_mgo_apply(MeshDev m, const double* __restrict__ A, const uint8_t* __restrict__ unk,
-                            const float* __restrict__ y0, double* __restrict__ z, double* __restrict__ wv,
-                            const double* __restrict__ rhat, const double* __restrict__ s, double* part) {
+// (or t.s, t.t with s given).  F32: A z from the FP32 copy of the matrix in
+// difference form, sum a_j (z_j - z_c) + rowsum z_c, formed in FP64.
+template <int DIM, bool NT, bool F32>
+__global__ void k_mgo_apply(MeshDev m, const double* __restrict__ A, const float* __restrict__ A32,
+                            const uint8_t* __restrict__ unk, const float* __restrict__ y0, double* __restrict__ z,
+                            double* __restrict__ wv, const double* __restrict__ rhat, const double* __restrict__ s,
+                            double* part) {
+    constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < m.Nc; c += gridDim.x * blockDim.x) {
         double v = 0.0;
-        if (unk[c]) v = mg_spmv64<DIM, NT>(m, A, c, [&](int j) { return (double)y0[j]; });
-        z[c] = (double)y0[c];
+        const double zc = (double)y0[c];
+        if (unk[c]) {
+            if constexpr (F32) {
+                int ijk[3];
+                cell_ijk(m, c, ijk);
+                if (mg_interior<DIM>(m, ijk)) {
+#pragma unroll
+                    for (int sl = 0; sl < S; ++sl) {
+                        const double a = (double)ld_mat<NT>(A32 + (size_t)sl * m.mps + c);
+                        v += sl == CEN ? a * zc : a * ((double)y0[c + mg_off<DIM>(m, sl)] - zc);
+                    }
+                } else {
+#pragma unroll
+                    for (int sl = 0; sl < S; ++sl) {
+                        const double a = (double)ld_mat<NT>(A32 + (size_t)sl * m.mps + c);
+                        if (sl == CEN) {
+                            v += a * zc;
+                            continue;
+                        }
+                        int j;
+                        double sh[3];
+                        if (!neighbour<DIM>(m, ijk, sl, j, sh)) continue;
+                        v += a * ((double)y0[j] - zc);
+                    }
+                }
+            } else {
+                v = mg_spmv64<DIM, NT>(m, A, c, [&](int j) { return (double)y0[j]; });
+            }
+        }
+        z[c] = zc;
         wv[c] = v;
         if (s) {
             q[0] += v * s[c];
@@ -1063,7 +1096,7 @@ static hipError_t totals(MgWork& w, int nblk, int nq, int mode, hipStream_t st, 
 // vectors of the workspace); b: effective right-hand side.
 template <int DIM>
 static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set, const MgVecs& V, double tol,
-                                  int max_iter, hipStream_t st, MgResult* out) {
+                                  int max_iter, bool f32_products, hipStream_t st, MgResult* out) {
     const int N = m.Nc;
     const int g = (N + kBlock - 1) / kBlock > kMgParts ? kMgParts : (N + kBlock - 1) / kBlock;
     const double* A = set.amat;
@@ -1080,13 +1113,22 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
             hipLaunchKernelGGL((k_mgo_resid<DIM, false>), dim3(g), dim3(kBlock), 0, st, m, A, unk, V.b, V.x, V.r,
                                V.rhat, 1, w.part);
     };
+    const float* A32 = set.amat32;
     auto apply = [&](double* z, double* wv, const double* sv) {
-        if (w.nt)
-            hipLaunchKernelGGL((k_mgo_apply<DIM, true>), dim3(g), dim3(kBlock), 0, st, m, A, unk, y0, z, wv, V.rhat,
-                               sv, w.part);
-        else
-            hipLaunchKernelGGL((k_mgo_apply<DIM, false>), dim3(g), dim3(kBlock), 0, st, m, A, unk, y0, z, wv, V.rhat,
-                               sv, w.part);
+        if (f32_products) {
+            if (w.nt)
+                hipLaunchKernelGGL((k_mgo_apply<DIM, true, true>), dim3(g), dim3(kBlock), 0, st, m, A, A32, unk, y0, z,
+                                   wv, V.rhat, sv, w.part);
+            else
+                hipLaunchKernelGGL((k_mgo_apply<DIM, false, true>), dim3(g), dim3(kBlock), 0, st, m, A, A32, unk, y0,
+                                   z, wv, V.rhat, sv, w.part);
+        } else if (w.nt) {
+            hipLaunchKernelGGL((k_mgo_apply<DIM, true, false>), dim3(g), dim3(kBlock), 0, st, m, A, A32, unk, y0, z,
+                               wv, V.rhat, sv, w.part);
+        } else {
+            hipLaunchKernelGGL((k_mgo_apply<DIM, false, false>), dim3(g), dim3(kBlock), 0, st, m, A, A32, unk, y0, z,
+                               wv, V.rhat, sv, w.part);
+        }
     };
     hipError_t e = mg_setup_dim<DIM>(w, set, st);
     if (e != hipSuccess) return e;
@@ -1157,9 +1199,9 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
 }
 
 hipError_t mg_bicgstab(const MeshDev& m, MgWork& w, const SetDev& set, const MgVecs& V, double tol, int max_iter,
-                       hipStream_t st, MgResult* out) {
-    return m.dim == 2 ? mg_bicgstab_dim<2>(m, w, set, V, tol, max_iter, st, out)
-                      : mg_bicgstab_dim<3>(m, w, set, V, tol, max_iter, st, out);
+                       bool f32_products, hipStream_t st, MgResult* out) {
+    return m.dim == 2 ? mg_bicgstab_dim<2>(m, w, set, V, tol, max_iter, f32_products, st, out)
+                      : mg_bicgstab_dim<3>(m, w, set, V, tol, max_iter, f32_products, st, out);
 }
 
 // One V-cycle of the set's preconditioner on in (FP64 [Nc], read at unknown

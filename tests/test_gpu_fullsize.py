@@ -1,7 +1,8 @@
 """Whole steps at the benchmark sizes against the FP64 oracle, in both forms
 of the metric: the plain FP64 method and the learned initial guess with the
-FP32 multigrid-preconditioned solve (mixed precision), and also the learned
-guess with the FP32-stored matrix.
+FP32 multigrid-preconditioned solve whose products read the FP32 matrix
+(mixed precision), and also the learned guess with the FP32-stored matrix
+without a preconditioner.
 
 1024^2 oscillating cylinder and 128^3 moving sphere: after the initial
 arrangement and one projection step, the DP arrays are bit-exact; the GPU's
@@ -45,7 +46,7 @@ def _gpu_step(M, case, form):
     if form == "plain":
         g = GpuSim(case)
     elif form == "learned_mixed":
-        g = GpuSim(case, precond=M.PRECOND_MG)
+        g = GpuSim(case, precision=M.PREC_FP32_MATRIX, precond=M.PRECOND_MG)
         g.model = learned.load_model(g.ctx, WEIGHTS[case.dim])
         g.guess = "learned"
     else:                                   # the FP32-stored matrix without a preconditioner

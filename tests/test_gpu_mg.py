@@ -98,10 +98,26 @@ def test_preconditioned_solve_reaches_the_tolerance(M, name):
     assert info["iterations"] <= 12 and info["iterations"] < plain["iterations"]
 
 
+@pytest.mark.parametrize("name", sorted(CASES))
+def test_fp32_products_reach_the_tolerance(M, name):
+    """The mixed form: products with the FP32 difference-form matrix, FP64
+    vectors, the FP32 V-cycle; the tolerance holds on the oracle's FP64
+    operator."""
+    case, m, ctx, A, b, uidx, rhs, f, g = _problem(M, name)
+    p = _dev(g)
+    info = ctx.solve_ppe(2, _dev(rhs), p, _dev(f), precision=M.PREC_FP32_MATRIX, precond=M.PRECOND_MG)
+    res = np.linalg.norm(b - A @ np_(p)[uidx]) / np.linalg.norm(b)
+    print(f"{name}: MG with FP32 products {info['iterations']} iterations, {info['restarts']} restarts, "
+          f"oracle-operator residual {res:.2e}")
+    assert info["converged"] and info["true_rel_residual"] <= 1e-8
+    assert res <= 1e-8
+    assert info["iterations"] <= 16
+
+
 def test_unusable_mesh_and_precision_are_refused(M):
     case, m, ctx, A, b, uidx, rhs, f, g = _problem(M, "cylinder128")
     with pytest.raises(M.McdError) as e:
-        ctx.solve_ppe(2, _dev(rhs), _dev(g), _dev(f), precision=M.PREC_FP32_MATRIX, precond=M.PRECOND_MG)
+        ctx.solve_ppe(2, _dev(rhs), _dev(g), _dev(f), precision=M.PREC_FP32_REFINE, precond=M.PRECOND_MG)
     assert e.value.status == 1
     odd = configs.c1_taylor_green(n=62)          # periodic 62 -> 31 (odd): no coarse level
     c2 = M.Context.from_case(odd)
