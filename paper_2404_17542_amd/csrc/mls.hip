@@ -47,8 +47,11 @@ template <int DIM>
 struct MlsHalo {
     static constexpr int X = MlsTile<DIM>::X + 2, Y = MlsTile<DIM>::Y + 2, Z = DIM == 3 ? MlsTile<DIM>::Z + 2 : 1;
     static constexpr int N = X * Y * Z;
+    // 3D reads the normals of its (rare) Neumann rows from global memory, so
+    // that the LDS left over holds every row's weight between the passes
+    static constexpr bool NV = DIM == 2;
     double p[DIM][N];      // neighbour position (periodic image)
-    double nv[DIM][N];     // neighbour normal
+    double nv[NV ? DIM : 1][NV ? N : 1];   // neighbour normal (2D)
     int j[N];              // cell index, -1 outside a non-periodic mesh
     int8_t r[N];           // role
 };
@@ -68,7 +71,7 @@ __device__ __forceinline__ int halo_slot(int lx, int ly, int lz, int s) {
 template <int DIM, bool POW2, int WK>
 __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, int e, bool centre,
                                        const double* xc, double re, double rs, double rs_inv, bool want_w,
-                                       double& w, double* a) {
+                                       const double* __restrict__ normal, size_t Nc, double& w, double* a) {
     if (H.j[e] < 0) return 0;
     const int kind = row_kind(H.r[e], bc);
     if (centre && kind != 2) return 0;     // the DP itself: only its Neumann row
@@ -87,7 +90,7 @@ __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, i
     } else {
         double nv[DIM];
 #pragma unroll
-        for (int q = 0; q < DIM; ++q) nv[q] = H.nv[q][e];
+        for (int q = 0; q < DIM; ++q) nv[q] = MlsHalo<DIM>::NV ? H.nv[q][e] : normal[q * Nc + H.j[e]];
         basis_normal<DIM>(X, nv, a);
     }
     return kind;
@@ -110,10 +113,10 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
     using HT = MlsHalo<DIM>;
     static_assert(T::X * T::Y * T::Z == kBlock, "one tile cell per thread");
     __shared__ HT H;
-    // 2D keeps each row's weight in LDS between the passes; 3D recomputes it
-    // in pass 2 (same bits), which leaves 43 KB of LDS per block instead of
-    // 98 KB, so that two blocks fit on a CU
-    constexpr bool kCacheW = DIM == 2;
+    // each row's weight stays in LDS between the passes (same bits as
+    // recomputing it; in 3D the halo holds no normals, so that two blocks
+    // still fit on a CU)
+    constexpr bool kCacheW = true;
     __shared__ double wc[kCacheW ? S : 1][kBlock];
     const size_t Nc = (size_t)m.Nc;
     const double rs_inv = 1.0 / rs, rr_inv = 1.0 / (rs * rs);     // exact when POW2
@@ -154,7 +157,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
 #pragma unroll
             for (int q = 0; q < DIM; ++q) {
                 H.p[q][e] = in ? pos[q * Nc + idx] + sh[q] : 0.0;
-                H.nv[q][e] = in ? normal[q * Nc + idx] : 0.0;
+                if (HT::NV) H.nv[q][e] = in ? normal[q * Nc + idx] : 0.0;
             }
         }
         __syncthreads();
@@ -177,8 +180,8 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
             if (rc != MCD_ROLE_VOID) {
                 for (int s = 0; s < S; ++s) {
                     double w = 0.0, a[NB];
-                    const int kind = row_lds<DIM, POW2, WK>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs, rs_inv,
-                                                  true, w, a);
+                    const int kind = row_lds<DIM, POW2, WK>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs,
+                                                            rs_inv, true, normal, Nc, w, a);
                     if (kCacheW) wc[s][threadIdx.x] = w;
                     if (!kind) continue;
                     if (kind == 1)
@@ -251,7 +254,7 @@ __global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* _
                 for (int q = 0; q < NB; ++q) y[q] = 0.0;
                 if (isv || isn) {
                     double w = kCacheW ? wc[s][threadIdx.x] : 0.0, a[NB];
-                    row_lds<DIM, POW2, WK>(H, bc, e, s == CEN, xc, re, rs, rs_inv, !kCacheW, w, a);
+                    row_lds<DIM, POW2, WK>(H, bc, e, s == CEN, xc, re, rs, rs_inv, !kCacheW, normal, Nc, w, a);
 #pragma unroll
                     for (int q = 0; q < NB; ++q) y[q] = w * a[q];
                     // forward L z = y, backward L^T y = z
