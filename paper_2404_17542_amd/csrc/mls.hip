@@ -54,6 +54,7 @@ struct MlsHalo {
     double nv[NV ? DIM : 1][NV ? N : 1];   // neighbour normal (2D)
     int j[N];              // cell index, -1 outside a non-periodic mesh
     int8_t r[N];           // role
+    int8_t kd[N];          // row kind (0 none, 1 value row, 2 Neumann row)
 };
 
 // halo slot of the neighbour at stencil slot s of tile cell (lx, ly, lz)
@@ -69,11 +70,11 @@ __device__ __forceinline__ int halo_slot(int lx, int ly, int lz, int s) {
 // vector a (value or normal-derivative row, Eq. obj_func) and, when
 // want_w, its weight.
 template <int DIM, bool POW2, int WK>
-__device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, int e, bool centre,
+__device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, int e, bool centre,
                                        const double* xc, double re, double rs, double rs_inv, bool want_w,
                                        const double* __restrict__ normal, size_t Nc, double& w, double* a) {
     if (H.j[e] < 0) return 0;
-    const int kind = row_kind(H.r[e], bc);
+    const int kind = H.kd[e];
     if (centre && kind != 2) return 0;     // the DP itself: only its Neumann row
     if (kind == 0) return 0;
     double d[DIM], X[DIM];
@@ -96,221 +97,255 @@ __device__ __forceinline__ int row_lds(const MlsHalo<DIM>& H, const BcDev& bc, i
     return kind;
 }
 
+// Unknown of a PPE (inner, or a boundary DP whose row is a Neumann row, minus
+// the pinned DP), from the staged role r and row kind.
+__device__ __forceinline__ bool mls_unknown(int r, int kind, int j, bool pin) {
+    if (pin && j == 0) return false;
+    return r == MCD_ROLE_INNER || (r > 0 && kind == 2);
+}
+
+template <int DIM>
+__device__ __forceinline__ void mls_tile_origin(const MeshDev& m, int tile, int o[3]) {
+    using T = MlsTile<DIM>;
+    const int ntx = (m.n[0] + T::X - 1) / T::X, nty = (m.n[1] + T::Y - 1) / T::Y;
+    o[0] = (tile % ntx) * T::X;
+    o[1] = ((tile / ntx) % nty) * T::Y;
+    o[2] = (tile / (ntx * nty)) * T::Z;
+}
+
+// Stages the tile at origin o and its halo into H: positions shifted to the
+// periodic image seen from the tile, roles, row kinds, cell indices, 2D
+// normals.  No barrier.
+template <int DIM>
+__device__ __forceinline__ void mls_stage(const MeshDev& m, MlsHalo<DIM>& H, const int o[3],
+                                          const double* __restrict__ pos, const int8_t* __restrict__ role,
+                                          const double* __restrict__ normal, const BcDev& bc) {
+    using HT = MlsHalo<DIM>;
+    const size_t Nc = (size_t)m.Nc;
+    for (int e = threadIdx.x; e < HT::N; e += kBlock) {
+        const int h[3] = {e % HT::X, (e / HT::X) % HT::Y, e / (HT::X * HT::Y)};
+        int idx = 0, stride = 1;
+        bool in = true;
+        double sh[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+        for (int a = 0; a < DIM; ++a) {
+            int ii = o[a] - 1 + h[a];
+            // beyond every active cell's neighbourhood (a tile wider than
+            // the mesh): not a neighbour of anything, left outside
+            if (ii < -1 || ii > m.n[a]) in = false;
+            if (ii < 0) {
+                in = in && m.periodic[a];
+                ii += m.n[a];
+                sh[a] = -m.length[a];
+            } else if (ii >= m.n[a]) {
+                in = in && m.periodic[a];
+                ii -= m.n[a];
+                sh[a] = m.length[a];
+            }
+            idx += ii * stride;
+            stride *= m.n[a];
+        }
+        const int8_t rr = in ? role[idx] : (int8_t)0;
+        H.j[e] = in ? idx : -1;
+        H.r[e] = rr;
+        H.kd[e] = (int8_t)(in ? row_kind(rr, bc) : 0);
+#pragma unroll
+        for (int q = 0; q < DIM; ++q) {
+            H.p[q][e] = in ? pos[q * Nc + idx] + sh[q] : 0.0;
+            if (HT::NV) H.nv[q][e] = in ? normal[q * Nc + idx] : 0.0;
+        }
+    }
+}
+
+// The fit of the DP at tile cell (lx, ly, lz), cell c, written to the set st.
+// wc: this thread's weight cache between the passes (each row's weight, the
+// same bits as recomputing it).
+template <int DIM, bool POW2, int WK>
+__device__ __forceinline__ void mls_fit(const MeshDev& m, const MlsHalo<DIM>& H, double* wc, int lx, int ly, int lz,
+                                        int c, bool pin, const SetDev& st, const double* __restrict__ normal,
+                                        double re, double rs, int* counters, int* latch) {
+    constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
+    constexpr int NP = NB * (NB + 1) / 2;
+    const size_t Nc = (size_t)m.Nc;
+    const double rs_inv = 1.0 / rs, rr_inv = 1.0 / (rs * rs);     // exact when POW2
+    const int ecen = halo_slot<DIM>(lx, ly, lz, CEN);
+    const int rc = H.r[ecen];
+    double xc[DIM];
+#pragma unroll
+    for (int q = 0; q < DIM; ++q) xc[q] = H.p[q][ecen];
+    const bool unk_c = mls_unknown(rc, H.kd[ecen], c, pin);
+    st.unknown[c] = unk_c ? 1 : 0;
+    double M[NP];
+#pragma unroll
+    for (int q = 0; q < NP; ++q) M[q] = 0.0;
+    uint32_t vm = 0, nm = 0;
+    int nrows = 0;
+    if (rc != MCD_ROLE_VOID) {
+        for (int s = 0; s < S; ++s) {
+            double w = 0.0, a[NB];
+            const int kind = row_lds<DIM, POW2, WK>(H, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs, rs_inv,
+                                                    true, normal, Nc, w, a);
+            wc[s * kBlock] = w;
+            if (!kind) continue;
+            if (kind == 1)
+                vm |= 1u << s;
+            else
+                nm |= 1u << (s == CEN ? S : s);
+            nrows += (w > 0.0) ? 1 : 0;
+            int q = 0;
+#pragma unroll
+            for (int r = 0; r < NB; ++r) {
+                const double wa = w * a[r];
+#pragma unroll
+                for (int k = 0; k <= r; ++k) M[q++] += wa * a[k];
+            }
+        }
+    }
+    // Cholesky M = L L^T in place (packed lower triangle); the diagonal
+    // slots keep 1 / L_jj, so that the triangular solves of pass 2
+    // multiply instead of divide
+    double tr = 0.0;
+#pragma unroll
+    for (int r = 0; r < NB; ++r) tr += M[r * (r + 1) / 2 + r];
+    bool sing = (rc == MCD_ROLE_VOID);
+    if (!sing) {
+        // fewer rows of positive weight than basis terms: M is rank-deficient
+        if (nrows < NB) sing = true;
+#pragma unroll
+        for (int jc = 0; jc < NB; ++jc) {
+            double dsum = M[jc * (jc + 1) / 2 + jc];
+#pragma unroll
+            for (int k = 0; k < jc; ++k) dsum -= M[jc * (jc + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
+            if (!(dsum > 1e-12 * tr / NB)) {
+                sing = true;
+                dsum = 1.0;
+            }
+            const double ljj = sqrt(dsum);
+            const double inv = 1.0 / ljj;
+            M[jc * (jc + 1) / 2 + jc] = inv;
+#pragma unroll
+            for (int i = jc + 1; i < NB; ++i) {
+                double acc = M[i * (i + 1) / 2 + jc];
+#pragma unroll
+                for (int k = 0; k < jc; ++k) acc -= M[i * (i + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
+                M[i * (i + 1) / 2 + jc] = acc * inv;
+            }
+        }
+        wave_count_add(&counters[0], sing && rc == MCD_ROLE_INNER);
+        wave_count_add(&counters[1], sing && rc != MCD_ROLE_INNER);
+        if (sing && rc == MCD_ROLE_INNER) {
+            atomicMin(&counters[2], c);
+            atomicAdd(latch, 1);
+        }
+    }
+    if (sing) {
+        vm = 0;
+        nm = 0;
+    }
+    st.vmask[c] = vm;
+    st.nmask[c] = nm;
+    double cacc[NB];
+#pragma unroll
+    for (int q = 0; q < NB; ++q) cacc[q] = 0.0;
+    double diag_sum = 0.0, off_sum = 0.0;
+    for (int s = 0; s < S; ++s) {
+        const int slot = (s == CEN) ? S : s;
+        const bool isv = (vm >> s) & 1u, isn = (nm >> slot) & 1u;
+        const int e = halo_slot<DIM>(lx, ly, lz, s);
+        double y[NB];
+#pragma unroll
+        for (int q = 0; q < NB; ++q) y[q] = 0.0;
+        if (isv || isn) {
+            double w = wc[s * kBlock], a[NB];
+            row_lds<DIM, POW2, WK>(H, e, s == CEN, xc, re, rs, rs_inv, false, normal, Nc, w, a);
+#pragma unroll
+            for (int q = 0; q < NB; ++q) y[q] = w * a[q];
+            // forward L z = y, backward L^T y = z
+#pragma unroll
+            for (int i = 0; i < NB; ++i) {
+                double acc = y[i];
+#pragma unroll
+                for (int k = 0; k < i; ++k) acc -= M[i * (i + 1) / 2 + k] * y[k];
+                y[i] = acc * M[i * (i + 1) / 2 + i];
+            }
+#pragma unroll
+            for (int i = NB - 1; i >= 0; --i) {
+                double acc = y[i];
+#pragma unroll
+                for (int k = i + 1; k < NB; ++k) acc -= M[k * (k + 1) / 2 + i] * y[k];
+                y[i] = acc * M[i * (i + 1) / 2 + i];
+            }
+            if (isn) {
+#pragma unroll
+                for (int q = 0; q < NB; ++q) y[q] *= rs;
+            } else {
+#pragma unroll
+                for (int q = 0; q < NB; ++q) cacc[q] += y[q];
+            }
+        }
+        if (s != CEN) {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(y[q], st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
+            double lap = 0.0;
+            if (isv && unk_c) {
+                lap = POW2 ? diag2<DIM>(y) * rr_inv : diag2<DIM>(y) / (rs * rs);
+                diag_sum += lap;
+                if (!mls_unknown(H.r[e], H.kd[e], H.j[e], pin)) lap = 0.0;
+            }
+            if (st.amat) {
+                __builtin_nontemporal_store(lap, st.amat + (size_t)s * m.mps + c);
+                __builtin_nontemporal_store((float)lap, st.amat32 + (size_t)s * m.mps + c);
+                off_sum += lap;
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(y[q], st.phi + ((size_t)q * (S + 1) + S) * m.mps + c);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(-cacc[q], st.phi + ((size_t)q * (S + 1) + CEN) * m.mps + c);
+    if (st.amat) {
+        // FP32 copy in difference form: its centre slot holds the row sum (zero
+        // for rows without known neighbours), so that products sum
+        // a_j (x_j - x_c) + rowsum x_c and keep the exact cancellation of the
+        // stencil on smooth fields
+        const double dg = unk_c ? -diag_sum : 0.0;
+        __builtin_nontemporal_store(dg, st.amat + (size_t)CEN * m.mps + c);
+        __builtin_nontemporal_store((float)(dg + off_sum), st.amat32 + (size_t)CEN * m.mps + c);
+    }
+}
+
 // POW2: r_s is a power of two, so x / r_s and x * (1 / r_s) are the same
 // real number and round to the same double; the kernel then multiplies (the
 // divisions by r_s and r_s^2 are most of its division work).  WK: the weight
 // function (one instantiation each, so that only its series constants
-// occupy scalar registers).
+// occupy scalar registers).  Two blocks per CU (the register budget of two
+// waves per SIMD).
 template <int DIM, bool POW2, int WK>
-__global__ __launch_bounds__(kBlock) void k_mls_build(MeshDev m, const double* __restrict__ pos,
+__global__ __launch_bounds__(kBlock, 2) void k_mls_build(MeshDev m, const double* __restrict__ pos,
                                                       const int8_t* __restrict__ role,
                                                       const double* __restrict__ normal, BcDev bc, double re,
-                                                      double rs, SetDev st, int* counters,
-                                                      int* latch) {
-    constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
-    constexpr int NP = NB * (NB + 1) / 2;
+                                                      double rs, SetDev st, int* counters, int* latch) {
     using T = MlsTile<DIM>;
-    using HT = MlsHalo<DIM>;
     static_assert(T::X * T::Y * T::Z == kBlock, "one tile cell per thread");
-    __shared__ HT H;
-    // each row's weight stays in LDS between the passes (same bits as
-    // recomputing it; in 3D the halo holds no normals, so that two blocks
-    // still fit on a CU)
-    constexpr bool kCacheW = true;
-    __shared__ double wc[kCacheW ? S : 1][kBlock];
-    const size_t Nc = (size_t)m.Nc;
-    const double rs_inv = 1.0 / rs, rr_inv = 1.0 / (rs * rs);     // exact when POW2
-    const int ntx = (m.n[0] + T::X - 1) / T::X, nty = (m.n[1] + T::Y - 1) / T::Y;
-    const int ntz = DIM == 3 ? (m.n[2] + T::Z - 1) / T::Z : 1;
-    const int ntiles = ntx * nty * ntz;
+    __shared__ MlsHalo<DIM> H;
+    // each row's weight stays in LDS between the passes (in 3D the halo holds
+    // no normals, so that two blocks still fit on a CU)
+    __shared__ double wc[Dims<DIM>::S][kBlock];
+    const int ntiles = ((m.n[0] + T::X - 1) / T::X) * ((m.n[1] + T::Y - 1) / T::Y) *
+                       (DIM == 3 ? (m.n[2] + T::Z - 1) / T::Z : 1);
     const int lx = threadIdx.x % T::X, ly = (threadIdx.x / T::X) % T::Y, lz = threadIdx.x / (T::X * T::Y);
     const int nblk = gridDim.x;
     const int lb = xcd_block(blockIdx.x, nblk);
     for (int tile = lb; tile < ntiles; tile += nblk) {
-        const int o[3] = {(tile % ntx) * T::X, ((tile / ntx) % nty) * T::Y, (tile / (ntx * nty)) * T::Z};
-        // stage the tile and its halo
-        for (int e = threadIdx.x; e < HT::N; e += kBlock) {
-            const int h[3] = {e % HT::X, (e / HT::X) % HT::Y, e / (HT::X * HT::Y)};
-            int idx = 0, stride = 1;
-            bool in = true;
-            double sh[3] = {0.0, 0.0, 0.0};
-#pragma unroll
-            for (int a = 0; a < DIM; ++a) {
-                int ii = o[a] - 1 + h[a];
-                // beyond every active cell's neighbourhood (a tile wider than
-                // the mesh): not a neighbour of anything, left outside
-                if (ii < -1 || ii > m.n[a]) in = false;
-                if (ii < 0) {
-                    in = in && m.periodic[a];
-                    ii += m.n[a];
-                    sh[a] = -m.length[a];
-                } else if (ii >= m.n[a]) {
-                    in = in && m.periodic[a];
-                    ii -= m.n[a];
-                    sh[a] = m.length[a];
-                }
-                idx += ii * stride;
-                stride *= m.n[a];
-            }
-            H.j[e] = in ? idx : -1;
-            H.r[e] = in ? role[idx] : (int8_t)0;
-#pragma unroll
-            for (int q = 0; q < DIM; ++q) {
-                H.p[q][e] = in ? pos[q * Nc + idx] + sh[q] : 0.0;
-                if (HT::NV) H.nv[q][e] = in ? normal[q * Nc + idx] : 0.0;
-            }
-        }
+        int o[3];
+        mls_tile_origin<DIM>(m, tile, o);
+        mls_stage<DIM>(m, H, o, pos, role, normal, bc);
         __syncthreads();
         const int gx = o[0] + lx, gy = o[1] + ly, gz = DIM == 3 ? o[2] + lz : 0;
-        const bool active = gx < m.n[0] && gy < m.n[1] && (DIM == 2 || gz < m.n[2]);
-        if (active) {
-            const int c = gx + m.n[0] * (gy + m.n[1] * gz);
-            const int ecen = halo_slot<DIM>(lx, ly, lz, CEN);
-            const int rc = H.r[ecen];
-            double xc[DIM];
-#pragma unroll
-            for (int q = 0; q < DIM; ++q) xc[q] = H.p[q][ecen];
-            const bool unk_c = is_unknown(rc, c, bc);
-            st.unknown[c] = unk_c ? 1 : 0;
-            double M[NP];
-#pragma unroll
-            for (int q = 0; q < NP; ++q) M[q] = 0.0;
-            uint32_t vm = 0, nm = 0;
-            int nrows = 0;
-            if (rc != MCD_ROLE_VOID) {
-                for (int s = 0; s < S; ++s) {
-                    double w = 0.0, a[NB];
-                    const int kind = row_lds<DIM, POW2, WK>(H, bc, halo_slot<DIM>(lx, ly, lz, s), s == CEN, xc, re, rs,
-                                                            rs_inv, true, normal, Nc, w, a);
-                    if (kCacheW) wc[s][threadIdx.x] = w;
-                    if (!kind) continue;
-                    if (kind == 1)
-                        vm |= 1u << s;
-                    else
-                        nm |= 1u << (s == CEN ? S : s);
-                    nrows += (w > 0.0) ? 1 : 0;
-                    int q = 0;
-#pragma unroll
-                    for (int r = 0; r < NB; ++r) {
-                        const double wa = w * a[r];
-#pragma unroll
-                        for (int k = 0; k <= r; ++k) M[q++] += wa * a[k];
-                    }
-                }
-            }
-            // Cholesky M = L L^T in place (packed lower triangle); the diagonal
-            // slots keep 1 / L_jj, so that the triangular solves of pass 2
-            // multiply instead of divide
-            double tr = 0.0;
-#pragma unroll
-            for (int r = 0; r < NB; ++r) tr += M[r * (r + 1) / 2 + r];
-            bool sing = (rc == MCD_ROLE_VOID);
-            if (!sing) {
-                // fewer rows of positive weight than basis terms: M is rank-deficient
-                if (nrows < NB) sing = true;
-#pragma unroll
-                for (int jc = 0; jc < NB; ++jc) {
-                    double dsum = M[jc * (jc + 1) / 2 + jc];
-#pragma unroll
-                    for (int k = 0; k < jc; ++k) dsum -= M[jc * (jc + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
-                    if (!(dsum > 1e-12 * tr / NB)) {
-                        sing = true;
-                        dsum = 1.0;
-                    }
-                    const double ljj = sqrt(dsum);
-                    const double inv = 1.0 / ljj;
-                    M[jc * (jc + 1) / 2 + jc] = inv;
-#pragma unroll
-                    for (int i = jc + 1; i < NB; ++i) {
-                        double acc = M[i * (i + 1) / 2 + jc];
-#pragma unroll
-                        for (int k = 0; k < jc; ++k) acc -= M[i * (i + 1) / 2 + k] * M[jc * (jc + 1) / 2 + k];
-                        M[i * (i + 1) / 2 + jc] = acc * inv;
-                    }
-                }
-                wave_count_add(&counters[0], sing && rc == MCD_ROLE_INNER);
-                wave_count_add(&counters[1], sing && rc != MCD_ROLE_INNER);
-                if (sing && rc == MCD_ROLE_INNER) {
-                    atomicMin(&counters[2], c);
-                    atomicAdd(latch, 1);
-                }
-            }
-            if (sing) {
-                vm = 0;
-                nm = 0;
-            }
-            st.vmask[c] = vm;
-            st.nmask[c] = nm;
-            double cacc[NB];
-#pragma unroll
-            for (int q = 0; q < NB; ++q) cacc[q] = 0.0;
-            double diag_sum = 0.0, off_sum = 0.0;
-            for (int s = 0; s < S; ++s) {
-                const int slot = (s == CEN) ? S : s;
-                const bool isv = (vm >> s) & 1u, isn = (nm >> slot) & 1u;
-                const int e = halo_slot<DIM>(lx, ly, lz, s);
-                double y[NB];
-#pragma unroll
-                for (int q = 0; q < NB; ++q) y[q] = 0.0;
-                if (isv || isn) {
-                    double w = kCacheW ? wc[s][threadIdx.x] : 0.0, a[NB];
-                    row_lds<DIM, POW2, WK>(H, bc, e, s == CEN, xc, re, rs, rs_inv, !kCacheW, normal, Nc, w, a);
-#pragma unroll
-                    for (int q = 0; q < NB; ++q) y[q] = w * a[q];
-                    // forward L z = y, backward L^T y = z
-#pragma unroll
-                    for (int i = 0; i < NB; ++i) {
-                        double acc = y[i];
-#pragma unroll
-                        for (int k = 0; k < i; ++k) acc -= M[i * (i + 1) / 2 + k] * y[k];
-                        y[i] = acc * M[i * (i + 1) / 2 + i];
-                    }
-#pragma unroll
-                    for (int i = NB - 1; i >= 0; --i) {
-                        double acc = y[i];
-#pragma unroll
-                        for (int k = i + 1; k < NB; ++k) acc -= M[k * (k + 1) / 2 + i] * y[k];
-                        y[i] = acc * M[i * (i + 1) / 2 + i];
-                    }
-                    if (isn) {
-#pragma unroll
-                        for (int q = 0; q < NB; ++q) y[q] *= rs;
-                    } else {
-#pragma unroll
-                        for (int q = 0; q < NB; ++q) cacc[q] += y[q];
-                    }
-                }
-                if (s != CEN) {
-#pragma unroll
-                    for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(y[q], st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
-                    double lap = 0.0;
-                    if (isv && unk_c) {
-                        lap = POW2 ? diag2<DIM>(y) * rr_inv : diag2<DIM>(y) / (rs * rs);
-                        diag_sum += lap;
-                        if (!is_unknown(H.r[e], H.j[e], bc)) lap = 0.0;
-                    }
-                    if (st.amat) {
-                        __builtin_nontemporal_store(lap, st.amat + (size_t)s * m.mps + c);
-                        __builtin_nontemporal_store((float)lap, st.amat32 + (size_t)s * m.mps + c);
-                        off_sum += lap;
-                    }
-                } else {
-#pragma unroll
-                    for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(y[q], st.phi + ((size_t)q * (S + 1) + S) * m.mps + c);
-                }
-            }
-#pragma unroll
-            for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(-cacc[q], st.phi + ((size_t)q * (S + 1) + CEN) * m.mps + c);
-            if (st.amat) {
-                // FP32 copy in difference form: its centre slot holds the row sum
-                // (zero for rows without known neighbours), so that products
-                // sum a_j (x_j - x_c) + rowsum x_c and keep the exact
-                // cancellation of the stencil on smooth fields
-                const double dg = unk_c ? -diag_sum : 0.0;
-                __builtin_nontemporal_store(dg, st.amat + (size_t)CEN * m.mps + c);
-                __builtin_nontemporal_store((float)(dg + off_sum), st.amat32 + (size_t)CEN * m.mps + c);
-            }
-        }
+        if (gx < m.n[0] && gy < m.n[1] && (DIM == 2 || gz < m.n[2]))
+            mls_fit<DIM, POW2, WK>(m, H, &wc[0][threadIdx.x], lx, ly, lz, gx + m.n[0] * (gy + m.n[1] * gz),
+                                   bc.pin_first, st, normal, re, rs, counters, latch);
         __syncthreads();
     }
 }
