@@ -387,8 +387,11 @@ mcd_status mcd_mg_apply(mcd_ctx* ctx, int set, const double* in, double* out, in
  * where b_eff is rhs with the Dirichlet columns (values of p at known DPs)
  * and the Neumann data moved over; r = 0 at other cells.  rhs, neumann_f
  * (nullable), p, r: [Nc] f64 device.  norms: host [2] = (||r||_2,
- * ||b_eff||_2), nullable.  Synchronises.  MCD_ERR_ARG for an unbuilt set or
- * a non-finite right-hand side. */
+ * ||b_eff||_2): then the call synchronises and returns MCD_ERR_ARG for a
+ * non-finite right-hand side.  norms NULL: the call only enqueues r on the
+ * context's stream and returns at once, without checking the right-hand
+ * side (a non-finite value reaches r; mcd_solve_ppe on the same right-hand
+ * side reports it).  MCD_ERR_ARG for an unbuilt set or a null array. */
 mcd_status mcd_ppe_residual(mcd_ctx* ctx, int set, const double* rhs, const double* neumann_f, const double* p,
                             double* r, double* norms);
 

@@ -746,16 +746,20 @@ mcd_status mcd_ppe_residual(mcd_ctx* c, int set, const double* rhs, const double
     if (!valid_set(c, set, true)) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual: set not built%s");
     if (!rhs || !p || !r) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual: null argument%s");
     HIPCHK(c, launch_fill_i32(c->cnt + CNT_BAD, 1, 0, c->stream), "fill");
+    if (!norms) {      // r only: enqueued, no wait and no check of the right-hand side
+        HIPCHK(c, ppe_residual_impl(c->m, c->sets[set].dev, *c->kw, rhs, neumann_f, p, r, nullptr, c->cnt + CNT_BAD,
+                                    c->stream),
+               "residual");
+        return MCD_OK;
+    }
     double nr[2] = {0.0, 0.0};
     HIPCHK(c, ppe_residual_impl(c->m, c->sets[set].dev, *c->kw, rhs, neumann_f, p, r, nr, c->cnt + CNT_BAD, c->stream),
            "residual");
     int bad = 0;
     HIPCHK(c, hipMemcpy(&bad, c->cnt + CNT_BAD, sizeof(int), hipMemcpyDeviceToHost), "copy");
     if (bad) return fail(c, MCD_ERR_ARG, "mcd_ppe_residual: non-finite right-hand side%s");
-    if (norms) {
-        norms[0] = nr[0];
-        norms[1] = nr[1];
-    }
+    norms[0] = nr[0];
+    norms[1] = nr[1];
     return MCD_OK;
 }
 

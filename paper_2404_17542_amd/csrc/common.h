@@ -619,14 +619,17 @@ struct MgVecs {
 };
 struct MgResult {
     int iterations = 0, restarts = 0, converged = 0, coarse_singular = 0;
+    int bad = 0;                 // the right-hand side was not finite (nothing solved)
     double rel = 0.0, bnorm = 0.0;
 };
 hipError_t mg_alloc(const MeshDev& m, MgWork** out);
 void mg_free(MgWork* w);
 bool mg_usable(const MgWork* w);
 hipError_t mg_setup(const MeshDev& m, MgWork& w, const SetDev& set, hipStream_t st);
+// bad: device flag of a non-finite right-hand side (set by the b_eff kernel),
+// read back with the first residual's totals
 hipError_t mg_bicgstab(const MeshDev& m, MgWork& w, const SetDev& set, const MgVecs& V, double tol, int max_iter,
-                       bool f32_products, hipStream_t st, MgResult* out);
+                       bool f32_products, const int* bad, hipStream_t st, MgResult* out);
 hipError_t mg_apply(const MeshDev& m, MgWork& w, const SetDev& set, const double* in, double* out, int* levels,
                     hipStream_t st);
 

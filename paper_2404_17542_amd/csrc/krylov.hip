@@ -1560,10 +1560,14 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
                        w.v64.x, bad);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    if ((e = hipMemcpyAsync(w.bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
-    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     *out = SolveOut{};
-    if (*w.bad_host) return hipSuccess;     // caller reports the non-finite input
+    // the multigrid solve reads the non-finite flag back with its first
+    // totals; the other forms check it here
+    if (sp.precond != MCD_PRECOND_MG) {
+        if ((e = hipMemcpyAsync(w.bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+        if (*w.bad_host) return hipSuccess;     // caller reports the non-finite input
+    }
     // the operator the Krylov iterations see: A, or A D^-1 with Jacobi
     const double* A64 = set.amat;
     const float* A32 = set.amat32;
@@ -1574,9 +1578,10 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         const MgVecs mv{w.v64.x, w.v64.r, w.v64.rhat, w.v64.p[0], w.v64.v[0], w.v64.s, w.v64.t, w.v64.p[1],
                         w.v64.v[1], w.beff};
         MgResult res;
-        if ((e = mg_bicgstab(m, *w.mg, set, mv, sp.tol, sp.max_iter, sp.precision == MCD_PREC_FP32_MATRIX, st,
+        if ((e = mg_bicgstab(m, *w.mg, set, mv, sp.tol, sp.max_iter, sp.precision == MCD_PREC_FP32_MATRIX, bad, st,
                              &res)) != hipSuccess)
             return e;
+        if (res.bad) return hipSuccess;         // caller reports the non-finite input
         out->iterations = res.iterations;
         out->restarts = res.restarts;
         out->converged = res.converged;
@@ -1856,8 +1861,8 @@ static void free_vec(KVec<T>& V) {
 }
 
 // Residual of the PPE at p: r = (rhs - Dirichlet and Neumann columns) - A p
-// on unknown rows.  norms = (||r||_2, ||b_eff||_2).  Runs on the caller's
-// stream and returns after it has drained.
+// on unknown rows.  norms = (||r||_2, ||b_eff||_2): runs on the caller's
+// stream and returns after it has drained; norms null: only enqueues r.
 hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w, const double* rhs, const double* fneu,
                              const double* p, double* r, double norms[2], int* bad, hipStream_t st) {
     const int g = (m.Nc + kBlock - 1) / kBlock > 8192 ? 8192 : (m.Nc + kBlock - 1) / kBlock;
@@ -1873,6 +1878,7 @@ hipError_t ppe_residual_impl(const MeshDev& m, const SetDev& set, KrylovWork& w,
         hipLaunchKernelGGL(k_ppe_resid<3>, dim3(gr), dim3(kBlock), 0, st, m, set.amat, set.unknown, w.beff, w.v64.x,
                            r, part);
     }
+    if (!norms) return hipGetLastError();        // r only: nothing to wait for
     hipLaunchKernelGGL(k_resid_finish, dim3(1), dim3(kBlock), 0, st, part, gr, fin);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

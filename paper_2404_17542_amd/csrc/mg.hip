@@ -61,7 +61,7 @@ struct MgWork {
     double* dense = nullptr;     // [Nc][Nc] coarsest matrix (FP64)
     float* inv = nullptr;        // [Nc][Nc] its inverse
     double* part = nullptr;      // [4][kMgParts] partial sums of the outer solver
-    double* host = nullptr;      // [4] totals, pinned host memory written by the reducing kernel
+    double* host = nullptr;      // [8] totals, pinned host memory written by the reducing kernel
     double* host_dev = nullptr;  // the same memory as the device sees it
     hipEvent_t ev = nullptr;     // completion of the reducing kernel
     struct MgScal* scal = nullptr;  // scalars of the outer iteration (device)
@@ -761,7 +761,7 @@ hipError_t mg_alloc(const MeshDev& m, MgWork** out) {
     if (e == hipSuccess) e = hipMalloc((void**)&w->inv, (size_t)Nc * Nc * sizeof(float));
     if (e == hipSuccess) e = hipMalloc((void**)&w->part, 4 * kMgParts * sizeof(double));
     if (e == hipSuccess) e = hipMalloc((void**)&w->flag, sizeof(int));
-    if (e == hipSuccess) e = hipHostMalloc((void**)&w->host, 4 * sizeof(double), hipHostMallocCoherent);
+    if (e == hipSuccess) e = hipHostMalloc((void**)&w->host, 8 * sizeof(double), hipHostMallocCoherent);
     if (e == hipSuccess) e = hipHostGetDevicePointer((void**)&w->host_dev, w->host, 0);
     if (e == hipSuccess) e = hipEventCreateWithFlags(&w->ev, hipEventDisableTiming);
     if (e == hipSuccess) e = hipMalloc((void**)&w->scal, 64);
@@ -1036,7 +1036,8 @@ __global__ void k_mgo_xr(int N, double* __restrict__ x, const double* __restrict
 
 // Totals of nq partial rows over nblk blocks, in block order, and what the
 // iteration makes of them:
-//   kResid  r.r, b.b, rhat.r -> rho_new = rhat.r; host {r.r, b.b, rhat.r}
+//   kResid  r.r, b.b, rhat.r -> rho_new = rhat.r; host {r.r, b.b, rhat.r, the
+//           right-hand side's non-finite flag, the coarsest matrix's singular flag}
 //   kAlpha  rhat.v -> alpha = rho_new / rhat.v (flag when 0 or not finite)
 //   kOmega  t.s, t.t -> omega = t.s / t.t (0 when t.t = 0)
 //   kNext   r.r, rhat.r -> rho = rho_new, rho_new = rhat.r;
@@ -1044,7 +1045,8 @@ __global__ void k_mgo_xr(int N, double* __restrict__ x, const double* __restrict
 enum { kResid = 0, kAlpha = 1, kOmega = 2, kNext = 3 };
 
 __global__ void k_mgo_reduce(const double* __restrict__ part, int nblk, int nq, int mode, MgScal* sc,
-                             double* __restrict__ host) {
+                             double* __restrict__ host, const int* __restrict__ bad,
+                             const int* __restrict__ cflag) {
     __shared__ double lds[4][kBlock / 64];
     double q[4] = {0.0, 0.0, 0.0, 0.0};
     for (int k = 0; k < nq; ++k)
@@ -1056,6 +1058,8 @@ __global__ void k_mgo_reduce(const double* __restrict__ part, int nblk, int nq, 
         host[0] = q[0];
         host[1] = q[1];
         host[2] = q[2];
+        host[3] = bad ? (double)*bad : 0.0;        // non-finite right-hand side
+        host[4] = cflag ? (double)*cflag : 0.0;    // singular coarsest matrix
     } else if (mode == kAlpha) {
         const double rv = q[0];
         const bool bad = !(fabs(rv) > 0.0) || !isfinite(rv);
@@ -1077,9 +1081,12 @@ __global__ void k_mgo_reduce(const double* __restrict__ part, int nblk, int nq, 
 
 // Reduction in mode `mode`; with `wait`, the host waits for it (polling an
 // event, which wakes it sooner than a blocking stream synchronisation) and
-// reads the four values its mode leaves in pinned host memory.
-static hipError_t totals(MgWork& w, int nblk, int nq, int mode, hipStream_t st, bool wait, double* out) {
-    hipLaunchKernelGGL(k_mgo_reduce, dim3(1), dim3(kBlock), 0, st, w.part, nblk, nq, mode, w.scal, w.host_dev);
+// reads the five values its mode leaves in pinned host memory (bad: the
+// right-hand side's device flag, reported by kResid).
+static hipError_t totals(MgWork& w, int nblk, int nq, int mode, hipStream_t st, bool wait, double* out,
+                         const int* bad = nullptr) {
+    hipLaunchKernelGGL(k_mgo_reduce, dim3(1), dim3(kBlock), 0, st, w.part, nblk, nq, mode, w.scal, w.host_dev, bad,
+                       mode == kResid ? w.flag : nullptr);
     if (!wait) return hipGetLastError();
     hipError_t e = hipEventRecord(w.ev, st);
     if (e == hipSuccess)
@@ -1087,7 +1094,7 @@ static hipError_t totals(MgWork& w, int nblk, int nq, int mode, hipStream_t st, 
         }
     if (e == hipSuccess) {
         const volatile double* h = w.host;
-        for (int k = 0; k < 4; ++k) out[k] = h[k];
+        for (int k = 0; k < 5; ++k) out[k] = h[k];
     }
     return e;
 }
@@ -1096,14 +1103,14 @@ static hipError_t totals(MgWork& w, int nblk, int nq, int mode, hipStream_t st, 
 // vectors of the workspace); b: effective right-hand side.
 template <int DIM>
 static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set, const MgVecs& V, double tol,
-                                  int max_iter, bool f32_products, hipStream_t st, MgResult* out) {
+                                  int max_iter, bool f32_products, const int* bad, hipStream_t st, MgResult* out) {
     const int N = m.Nc;
     const int g = (N + kBlock - 1) / kBlock > kMgParts ? kMgParts : (N + kBlock - 1) / kBlock;
     const double* A = set.amat;
     const uint8_t* unk = set.unknown;
     float* b0 = w.lev[0].b;
     const float* y0 = w.lev[0].y;
-    double t4[4];
+    double t4[5];                  // totals of the last reduction waited for
     if (!w.usable) return hipErrorNotSupported;
     auto resid = [&]() {
         if (w.nt)
@@ -1132,12 +1139,16 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
     };
     hipError_t e = mg_setup_dim<DIM>(w, set, st);
     if (e != hipSuccess) return e;
-    int flag = 0;
-    if ((e = hipMemcpyAsync(&flag, w.flag, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    // the right-hand side's check and the coarsest matrix's flag come back with
+    // the first residual's totals (one host wait for the three)
     resid();
-    if ((e = totals(w, g, 3, kResid, st, true, t4)) != hipSuccess) return e;
+    if ((e = totals(w, g, 3, kResid, st, true, t4, bad)) != hipSuccess) return e;
     *out = MgResult{};
-    out->coarse_singular = flag;
+    out->coarse_singular = t4[4] != 0.0 ? 1 : 0;
+    if (t4[3] != 0.0) {            // non-finite right-hand side: nothing is solved
+        out->bad = 1;
+        return hipSuccess;
+    }
     const double bb = t4[1];
     out->bnorm = sqrt(bb);
     if (bb == 0.0) {
@@ -1199,9 +1210,9 @@ static hipError_t mg_bicgstab_dim(const MeshDev& m, MgWork& w, const SetDev& set
 }
 
 hipError_t mg_bicgstab(const MeshDev& m, MgWork& w, const SetDev& set, const MgVecs& V, double tol, int max_iter,
-                       bool f32_products, hipStream_t st, MgResult* out) {
-    return m.dim == 2 ? mg_bicgstab_dim<2>(m, w, set, V, tol, max_iter, f32_products, st, out)
-                      : mg_bicgstab_dim<3>(m, w, set, V, tol, max_iter, f32_products, st, out);
+                       bool f32_products, const int* bad, hipStream_t st, MgResult* out) {
+    return m.dim == 2 ? mg_bicgstab_dim<2>(m, w, set, V, tol, max_iter, f32_products, bad, st, out)
+                      : mg_bicgstab_dim<3>(m, w, set, V, tol, max_iter, f32_products, bad, st, out);
 }
 
 // One V-cycle of the set's preconditioner on in (FP64 [Nc], read at unknown

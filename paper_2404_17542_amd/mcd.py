@@ -398,13 +398,15 @@ class Context:
             self._check(st, "mcd_solve_ppe")
         return out
 
-    def ppe_residual(self, set_id, rhs, p, r, neumann_f=None):
-        """r := b_eff - A p on unknown rows; returns (||r||, ||b_eff||)."""
-        norms = (C.c_double * 2)()
+    def ppe_residual(self, set_id, rhs, p, r, neumann_f=None, norms=True):
+        """r := b_eff - A p on unknown rows; returns (||r||, ||b_eff||), or,
+        with norms=False, only enqueues r (no wait, no input check) and
+        returns None."""
+        out = (C.c_double * 2)() if norms else None
         N, V = self.Nc, self._vec
         self._check(self.lib.mcd_ppe_residual(self.h, int(set_id), V(rhs, N), V(neumann_f, N), V(p, N), V(r, N),
-                                              norms), "mcd_ppe_residual")
-        return norms[0], norms[1]
+                                              out), "mcd_ppe_residual")
+        return (out[0], out[1]) if norms else None
 
     def mg_apply(self, set_id, inp, out):
         """One V-cycle of the set's multigrid preconditioner (mcd_mg_apply);

@@ -178,7 +178,8 @@ class GpuSim:
             raise ValueError(f"unknown initial guess {mode!r} (or no model for 'learned')")
         if self.resid is None:
             self.resid = torch.zeros_like(self.P)
-        self.ctx.ppe_residual(pset, self.rhs, self.P, self.resid, self.fP)
+        # enqueued only: the solve that follows checks the same right-hand side
+        self.ctx.ppe_residual(pset, self.rhs, self.P, self.resid, self.fP, norms=False)
         self.model.infer(self.resid, self.P, self.role, self.case.bc_pressure, self.P)
         return M.GUESS_CALLER
 

@@ -114,6 +114,25 @@ def test_fp32_products_reach_the_tolerance(M, name):
     assert info["iterations"] <= 16
 
 
+@pytest.mark.parametrize("precision", ["fp64", "fp32_matrix"])
+def test_non_finite_rhs_is_reported_and_p_kept(M, precision):
+    """A non-finite right-hand side: the multigrid solve reads the b_eff
+    check back with its first residual, reports MCD_ERR_ARG and leaves p as
+    it was; a later solve on the same context works."""
+    case, m, ctx, A, b, uidx, rhs, f, g = _problem(M, "cylinder128")
+    prec = {"fp64": M.PREC_FP64, "fp32_matrix": M.PREC_FP32_MATRIX}[precision]
+    bad = rhs.copy()
+    bad[uidx[len(uidx) // 2]] = np.inf
+    p0 = np.random.default_rng(9).standard_normal(m.Nc)
+    p = _dev(p0)
+    with pytest.raises(M.McdError) as e:
+        ctx.solve_ppe(2, _dev(bad), p, _dev(f), precision=prec, precond=M.PRECOND_MG)
+    assert e.value.status == 1
+    assert np.array_equal(np_(p).view(np.int64), p0.view(np.int64))
+    info = ctx.solve_ppe(2, _dev(rhs), p, _dev(f), precision=prec, precond=M.PRECOND_MG)
+    assert info["converged"] and info["true_rel_residual"] <= 1e-8
+
+
 def test_unusable_mesh_and_precision_are_refused(M):
     case, m, ctx, A, b, uidx, rhs, f, g = _problem(M, "cylinder128")
     with pytest.raises(M.McdError) as e:

@@ -522,6 +522,11 @@ def test_ppe_residual_matches_oracle(M):
     assert err.max() <= 1e-13, err.max()
     assert nr == pytest.approx(np.linalg.norm(r_ora), rel=1e-12)
     assert nb == pytest.approx(np.linalg.norm(beff), rel=1e-12)
+    # without norms the call only enqueues r: the same bits once the stream is done
+    r2 = _dev(np.full(m.Nc, 7.0))
+    assert ctx.ppe_residual(2, _dev(rhs), _dev(p), r2, _dev(f), norms=False) is None
+    ctx.sync()
+    assert np.array_equal(np_(r2).view(np.int64), rg.view(np.int64))
     # the solver's own stopping quantity agrees: after a solve, ||r|| / ||b_eff|| <= tol
     info = ctx.solve_ppe(2, _dev(rhs), pp := _dev(p), _dev(f), guess=M.GUESS_CALLER)
     nr2, nb2 = ctx.ppe_residual(2, _dev(rhs), pp, r, _dev(f))
