@@ -712,11 +712,11 @@ mcd_status mcd_solve_ppe(mcd_ctx* c, int set, const double* rhs, const double* n
                    opts->fp64_below, opts->precond};
     HIPCHK(c, launch_fill_i32(c->cnt + CNT_BAD, 1, 0, c->stream), "fill");
     SolveOut o;
+    // the solve returns after its own stream (ordered after this one) is idle,
+    // with the right-hand side's check in o.bad
     HIPCHK(c, solve_ppe_impl(c->m, c->sets[set].dev, *c->kw, rhs, neumann_f, p, sp, &o, c->cnt + CNT_BAD, c->stream),
            "solve");
-    HIPCHK(c, hipStreamSynchronize(c->stream), "solve");
-    int bad = 0;
-    HIPCHK(c, hipMemcpy(&bad, c->cnt + CNT_BAD, sizeof(int), hipMemcpyDeviceToHost), "copy");
+    const int bad = o.bad;
     info->iterations = o.iterations;
     info->restarts = o.restarts;
     info->refinements = o.refinements;

@@ -595,6 +595,7 @@ struct SolveParams {
 };
 struct SolveOut {
     int iterations, restarts, refinements, converged;
+    int bad;                     // the right-hand side was not finite (nothing solved)
     double rel, bnorm;
 };
 hipError_t krylov_alloc(const MeshDev& m, KrylovWork** out);

@@ -83,7 +83,6 @@ __device__ __forceinline__ T spmv_row(const MeshDev& m, const TA* __restrict__ A
     // sum_j a_j (x_j - x_c) + rowsum x_c.  FP64 matrices use the plain form.
     constexpr bool DIFF = sizeof(TA) < sizeof(double);
     constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
-    const size_t Nc = (size_t)m.Nc;
     int ijk[3];
     cell_ijk(m, c, ijk);
     bool interior = ijk[0] > 0 && ijk[0] < m.n[0] - 1 && ijk[1] > 0 && ijk[1] < m.n[1] - 1;
@@ -424,7 +423,6 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
     T* __restrict__ xp = V.x;
     const TileRun run = tiles_of(K);
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const size_t Nc = (size_t)m.Nc;
     const int e0 = threadIdx.x, e1 = threadIdx.x + kKBlock;
     const bool has1 = e1 < NH;
     double q[4] = {0.0, 0.0, 0.0, 0.0};
@@ -549,7 +547,6 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
     T* __restrict__ tp = V.t;
     const TileRun run = tiles_of(K);
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
-    const size_t Nc = (size_t)m.Nc;
     const int e0 = threadIdx.x, e1 = threadIdx.x + kKBlock;
     const bool has1 = e1 < NH;
     double tot[2];
@@ -1566,7 +1563,10 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     if (sp.precond != MCD_PRECOND_MG) {
         if ((e = hipMemcpyAsync(w.bad_host, bad, sizeof(int), hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
-        if (*w.bad_host) return hipSuccess;     // caller reports the non-finite input
+        if (*w.bad_host) {                      // caller reports the non-finite input
+            out->bad = 1;
+            return hipSuccess;
+        }
     }
     // the operator the Krylov iterations see: A, or A D^-1 with Jacobi
     const double* A64 = set.amat;
@@ -1581,7 +1581,10 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         if ((e = mg_bicgstab(m, *w.mg, set, mv, sp.tol, sp.max_iter, sp.precision == MCD_PREC_FP32_MATRIX, bad, st,
                              &res)) != hipSuccess)
             return e;
-        if (res.bad) return hipSuccess;         // caller reports the non-finite input
+        if (res.bad) {                          // caller reports the non-finite input
+            out->bad = 1;
+            return hipSuccess;
+        }
         out->iterations = res.iterations;
         out->restarts = res.restarts;
         out->converged = res.converged;
