@@ -315,6 +315,7 @@ mcd_status mcd_create(const mcd_mesh_desc* mesh, const mcd_params* prm, void* hi
         e = alloc((void**)&d.phi, (size_t)c->NB * (c->S + 1) * m.mps * sizeof(double));
         if (e == hipSuccess) e = alloc((void**)&d.vmask, N * sizeof(uint32_t));
         if (e == hipSuccess) e = alloc((void**)&d.nmask, N * sizeof(uint32_t));
+        if (e == hipSuccess) e = alloc((void**)&d.kmask, N * sizeof(uint32_t));
         if (e == hipSuccess) e = alloc((void**)&d.amat, (size_t)c->S * m.mps * sizeof(double));
         if (e == hipSuccess) e = alloc((void**)&d.amat32, (size_t)c->S * m.mps * sizeof(float));
         if (e == hipSuccess) e = alloc((void**)&d.unknown, N);
@@ -409,7 +410,7 @@ static void destroy_ctx_now(mcd_ctx* c) {
     if (c->cap_st) (void)hipStreamDestroy(c->cap_st);
     for (int s = 0; s < MCD_MAX_SETS; ++s) {
         SetDev& d = c->sets[s].dev;
-        void* ptrs[6] = {d.phi, d.vmask, d.nmask, d.amat, d.amat32, d.unknown};
+        void* ptrs[7] = {d.phi, d.vmask, d.nmask, d.kmask, d.amat, d.amat32, d.unknown};
         for (void* p : ptrs)
             if (p) (void)hipFree(p);
     }

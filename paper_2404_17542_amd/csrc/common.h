@@ -273,6 +273,8 @@ struct SetDev {
     double* phi;        // [nb][S+1][mps]
     uint32_t* vmask;    // [Nc] bit s: slot s is a value row
     uint32_t* nmask;    // [Nc] bit s: slot s is a Neumann row; bit S: own Neumann row
+    uint32_t* kmask;    // [Nc] unknown rows: bit s: slot s is a value row whose DP is not an unknown
+                        // (its value moves to the PPE's right-hand side); 0 at other rows
     double* amat;       // [S][mps] PPE matrix (unknown rows/cols), plane stride MeshDev::mps
     float* amat32;      // [S][mps]
     uint8_t* unknown;   // [Nc]

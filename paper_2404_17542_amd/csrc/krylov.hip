@@ -959,65 +959,34 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
 }
 
 // b_eff of unknown row c: rhs - (Dirichlet columns) g - (Neumann rows) f.
-// The unknown flags of all value neighbours are loaded together (branch-free
-// neighbour indices) before any decides, so that a row costs one memory
-// latency instead of one per slot; the few known or Neumann slots are then
-// visited in slot order.
+// Only known value neighbours (the row's kmask, from the weight build) and
+// Neumann rows move to the right-hand side; they are visited in slot order,
+// and the weights of the other slots are not read.
 template <int DIM>
 __device__ __forceinline__ double beff_row(const MeshDev& m, const SetDev& st, int c, const double* __restrict__ rhs,
                                            const double* __restrict__ g, const double* __restrict__ fneu,
                                            double irs2) {
     constexpr int NB = Dims<DIM>::NB, S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
-    int ijk[3];
-    cell_ijk(m, c, ijk);
     double acc = rhs[c];
-    const uint32_t vm = st.vmask[c] & ~(1u << CEN), nm = st.nmask[c];
-    // only known value neighbours and Neumann rows move to the right-hand
-    // side: the weights of the other slots are not read
-    uint32_t todo = fneu ? nm & ((1u << S) - 1u) & ~(1u << CEN) : 0u;
-    if (vm) {
-        // per axis, the index contribution and validity of offsets -1, 0, +1
-        // (periodic wrap; outside a non-periodic mesh the slot reads the cell
-        // itself, as neighbour_or_self does), so a slot costs two additions
-        int cx[3][3];
-        bool ok[3][3];
-        int stride = 1;
+    const uint32_t km = st.kmask[c], nm = st.nmask[c];
+    uint32_t todo = km | (fneu ? nm & ((1u << S) - 1u) & ~(1u << CEN) : 0u);
+    if (todo) {
+        int ijk[3];
+        cell_ijk(m, c, ijk);
+        while (todo) {
+            const int s = __ffs(todo) - 1;
+            todo &= todo - 1u;
+            const bool known = ((km >> s) & 1u) != 0, n = fneu && ((nm >> s) & 1u);
+            int j;
+            double sh[3];
+            neighbour_or_self<DIM>(m, ijk, s, c, j, sh);
+            double ph[NB];
 #pragma unroll
-        for (int a = 0; a < 3; ++a) {
-#pragma unroll
-            for (int o = 0; o < 3; ++o) {
-                int ii = a < DIM ? ijk[a] + o - 1 : 0;
-                const bool lo = ii < 0, hi = a < DIM && ii >= m.n[a];
-                ii = lo ? ii + m.n[a] : (hi ? ii - m.n[a] : ii);
-                ok[a][o] = a >= DIM || !(lo || hi) || m.periodic[a] != 0;
-                cx[a][o] = ii * stride;
-            }
-            if (a < DIM) stride *= m.n[a];
+            for (int q = 0; q < NB; ++q) ph[q] = ld_stream(st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
+            const double lc = diag2<DIM>(ph) * irs2;
+            if (known) acc -= lc * g[j];
+            if (n) acc -= lc * fneu[j];
         }
-        uint8_t u[S];
-#pragma unroll
-        for (int s = 0; s < S; ++s) {
-            const int ox = s % 3, oy = (s / 3) % 3, oz = DIM == 3 ? s / 9 : 1;
-            const bool in = ok[0][ox] && ok[1][oy] && ok[2][oz];
-            u[s] = st.unknown[in ? cx[0][ox] + cx[1][oy] + cx[2][oz] : c];
-        }
-#pragma unroll
-        for (int s = 0; s < S; ++s)
-            if (((vm >> s) & 1u) && !u[s]) todo |= 1u << s;
-    }
-    while (todo) {
-        const int s = __ffs(todo) - 1;
-        todo &= todo - 1u;
-        const bool known = ((vm >> s) & 1u) != 0, n = fneu && ((nm >> s) & 1u);
-        int j;
-        double sh[3];
-        neighbour_or_self<DIM>(m, ijk, s, c, j, sh);
-        double ph[NB];
-#pragma unroll
-        for (int q = 0; q < NB; ++q) ph[q] = ld_stream(st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
-        const double lc = diag2<DIM>(ph) * irs2;
-        if (known) acc -= lc * g[j];
-        if (n) acc -= lc * fneu[j];
     }
     if (fneu && ((nm >> S) & 1u)) {
         double ph[NB];

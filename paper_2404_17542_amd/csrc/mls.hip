@@ -248,6 +248,7 @@ __device__ __forceinline__ void mls_fit(const MeshDev& m, const MlsHalo<DIM>& H,
 #pragma unroll
     for (int q = 0; q < NB; ++q) cacc[q] = 0.0;
     double diag_sum = 0.0, off_sum = 0.0;
+    uint32_t km = 0;
     for (int s = 0; s < S; ++s) {
         const int slot = (s == CEN) ? S : s;
         const bool isv = (vm >> s) & 1u, isn = (nm >> slot) & 1u;
@@ -290,7 +291,10 @@ __device__ __forceinline__ void mls_fit(const MeshDev& m, const MlsHalo<DIM>& H,
             if (isv && unk_c) {
                 lap = POW2 ? diag2<DIM>(y) * rr_inv : diag2<DIM>(y) / (rs * rs);
                 diag_sum += lap;
-                if (!mls_unknown(H.r[e], H.kd[e], H.j[e], pin)) lap = 0.0;
+                if (!mls_unknown(H.r[e], H.kd[e], H.j[e], pin)) {
+                    lap = 0.0;
+                    km |= 1u << s;
+                }
             }
             if (st.amat) {
                 __builtin_nontemporal_store(lap, st.amat + (size_t)s * m.mps + c);
@@ -304,6 +308,7 @@ __device__ __forceinline__ void mls_fit(const MeshDev& m, const MlsHalo<DIM>& H,
     }
 #pragma unroll
     for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(-cacc[q], st.phi + ((size_t)q * (S + 1) + CEN) * m.mps + c);
+    st.kmask[c] = km;
     if (st.amat) {
         // FP32 copy in difference form: its centre slot holds the row sum (zero
         // for rows without known neighbours), so that products sum
