@@ -712,6 +712,32 @@ __device__ __forceinline__ void load_row27(const TA* __restrict__ A, size_t mps,
     for (int s = 0; s < 27; ++s) a[s] = ld_mat<NT>(A + (size_t)s * mps + c);
 }
 
+// FP64 matrices (the set's operator and its Jacobi-scaled copy) hold rows
+// of cells that are not unknown as 27 zeros (+0.0), while the centre of an
+// unknown row is never +0.0: it is -sum of the row's value weights, a sum
+// that starts at +0.0 and so is never -0.0; a Jacobi-scaled centre is that
+// times its reciprocal (about 1), times 1 (not finite), or the -0.0 kept.  A row whose centre has the bits of +0.0 is therefore all
+// zeros and its other 26 planes are not read: the rows of walls and of
+// cells inside a body cost no matrix traffic.  The centre of the next plane
+// is fetched one plane ahead, so the test adds no latency.  FP32 matrices
+// (difference form: the centre holds the row sum, zero for most rows) read
+// every plane.
+template <typename TA>
+struct RowSkip {
+    static constexpr bool on = sizeof(TA) == sizeof(double);
+};
+
+template <bool NT, typename TA>
+__device__ __forceinline__ void load_row27_skip(const TA* __restrict__ A, size_t mps, int c, TA cen, TA (&a)[27]) {
+    if (__double_as_longlong((double)cen) == 0) {
+#pragma unroll
+        for (int s = 0; s < 27; ++s) a[s] = TA(0);
+        return;
+    }
+#pragma unroll
+    for (int s = 0; s < 27; ++s) a[s] = s == 13 ? cen : ld_mat<NT>(A + (size_t)s * mps + c);
+}
+
 // 27-point product of a preloaded row with the ring planes (slots of planes
 // z-1, z, z+1).
 template <typename T, typename TA>
@@ -735,24 +761,28 @@ __device__ __forceinline__ T stencil3_lds(const TA (&a)[27], const T (*ring)[NH]
 
 // Marches the bricks of this block: form(gz, slot, own_plane) fills a ring
 // slot with the operand of plane gz (doing the owners' updates when
-// own_plane); pre(c) issues the loads of output cell c (matrix row) before
-// the next plane is formed, so that they overlap; out(c, s0, s1, s2)
-// consumes the product at cell c.  Barriers are LDS-only.
+// own_plane); pre(c, cn) issues the loads of output cell c (matrix row)
+// before the next plane is formed, so that they overlap, and those that the
+// row of cell cn (the next plane of the brick, -1 after the last) depends
+// on; pre(-1, c) at the start of a brick fetches them for its first plane;
+// out(c, s0, s1, s2) consumes the product at cell c.  Barriers are LDS-only.
 template <typename T, typename FORM, typename PRE, typename OUT>
 __device__ __forceinline__ void march_bricks(const MeshDev& m, const KBufs& K, FORM form, PRE pre, OUT out) {
     const TileRun run = tiles_of(K);
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
+    const int n01 = m.n[0] * m.n[1];
     for (int k = 0; k < run.count; ++k) {
         int tx0, ty0, tz0;
         brick_origin(K, run_tile(run, k), tx0, ty0, tz0);
         const int tz1 = min(tz0 + K.tz, m.n[2]);
         const int gx = tx0 + lx, gy = ty0 + ly;
         const bool inside = gx < m.n[0] && gy < m.n[1];
+        if (inside) pre(-1, gx + m.n[0] * (gy + m.n[1] * tz0));
         form(tx0, ty0, tz0 - 1, 0, false);
         form(tx0, ty0, tz0, 1, true);
         for (int z = tz0; z < tz1; ++z) {
             const int c = gx + m.n[0] * (gy + m.n[1] * z);
-            if (inside) pre(c);
+            if (inside) pre(c, z + 1 < tz1 ? c + n01 : -1);
             form(tx0, ty0, z + 1, (z - tz0 + 2) % 3, z + 1 < tz1);
             sync_lds();
             if (inside) out(c, (z - tz0) % 3, (z - tz0 + 1) % 3, (z - tz0 + 2) % 3);
@@ -772,6 +802,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0;
     TA a[27];
+    TA cen = 0;      // centre of the row pre() loads next
     T bcv = 0;
     march_bricks<T>(
         m, K,
@@ -781,9 +812,15 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
                 ring[slot][e] = j >= 0 ? xp[j] : T(0);
             }
         },
-        [&](int c) {
-            load_row27<NT, TA>(A, m.mps, c, a);
-            bcv = bp[c];
+        [&](int c, int cn) {
+            if (c >= 0) {
+                if constexpr (RowSkip<TA>::on)
+                    load_row27_skip<NT, TA>(A, m.mps, c, cen, a);
+                else
+                    load_row27<NT, TA>(A, m.mps, c, a);
+                bcv = bp[c];
+            }
+            if (RowSkip<TA>::on && cn >= 0) cen = ld_mat<NT>(A + (size_t)13 * m.mps + cn);
         },
         [&](int c, int s0, int s1, int s2) {
             const T ax = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
@@ -823,6 +860,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0;
     TA a[27];
+    TA cen = 0;      // centre of the row pre() loads next
     T rhc = 0;
     march_bricks<T>(
         m, K,
@@ -859,9 +897,18 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
                 ring[slot][e] = pv;
             }
         },
-        [&](int c) {
-            load_row27<NT, TA>(A, m.mps, c, a);
-            rhc = rh[c];
+        [&](int c, int cn) {
+            if (c >= 0) {
+                if constexpr (RowSkip<TA>::on) {
+                    load_row27_skip<NT, TA>(A, m.mps, c, cen, a);
+                    // r-hat is +0.0 wherever the row is
+                    rhc = __double_as_longlong((double)cen) == 0 ? T(0) : rh[c];
+                } else {
+                    load_row27<NT, TA>(A, m.mps, c, a);
+                    rhc = rh[c];
+                }
+            }
+            if (RowSkip<TA>::on && cn >= 0) cen = ld_mat<NT>(A + (size_t)13 * m.mps + cn);
         },
         [&](int c, int s0, int s1, int s2) {
             const T av = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
@@ -915,6 +962,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     TA a[27];
+    TA cen = 0;      // centre of the row pre() loads next
     T rhc = 0;
     march_bricks<T>(
         m, K,
@@ -932,9 +980,18 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
                 ring[slot][e] = sv;
             }
         },
-        [&](int c) {
-            load_row27<NT, TA>(A, m.mps, c, a);
-            rhc = rh[c];
+        [&](int c, int cn) {
+            if (c >= 0) {
+                if constexpr (RowSkip<TA>::on) {
+                    load_row27_skip<NT, TA>(A, m.mps, c, cen, a);
+                    // r-hat is +0.0 wherever the row is
+                    rhc = __double_as_longlong((double)cen) == 0 ? T(0) : rh[c];
+                } else {
+                    load_row27<NT, TA>(A, m.mps, c, a);
+                    rhc = rh[c];
+                }
+            }
+            if (RowSkip<TA>::on && cn >= 0) cen = ld_mat<NT>(A + (size_t)13 * m.mps + cn);
         },
         [&](int c, int s0, int s1, int s2) {
             const T tcv = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
@@ -1197,7 +1254,9 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_matrix(MeshDev m, const doubl
         double off_sum = 0.0, diag = 0.0;
         for (int s = 0; s < S; ++s) {
             const double a = A[(size_t)s * P + c];
-            double v = 0.0;
+            // a zero keeps its sign: the centre of an unknown row is never
+            // +0.0, here as in A (the stage kernels skip rows whose centre is)
+            double v = a == 0.0 ? a : 0.0;
             int j;
             double sh[3];
             if (a != 0.0 && neighbour<DIM>(m, ijk, s, j, sh)) v = a * dinv[j];
