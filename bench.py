@@ -49,14 +49,22 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def stage_bytes(n_unknown, dim, matrix_bytes, vector_bytes, stage="S"):
+def stage_bytes(n_unknown, dim, matrix_bytes, vector_bytes, stage="S", centre_formed=False):
     """Algorithmic bytes of one stage launch over n_unknown rows: the 3^dim
     matrix planes plus, S-stage (s = r - alpha v; t = A s), r, v, rhat read
     and s, t written (5 vector streams); P-stage (r, x, p updates; v = A p),
-    s, t, p, v, x, rhat read and r, p', x, v' written (10 streams)."""
+    s, t, p, v, x, rhat read and r, p', x, v' written (10 streams).
+    centre_formed (the stages on the set's own FP64 operator): the 3^dim - 1
+    off-centre planes, the kernel forming the centre from them, and in 3D the
+    row's 1-byte unknown flag (rows of cells that are not unknown are not
+    read)."""
     slots = 3 ** dim
     streams = 5 if stage == "S" else 10
-    return n_unknown * (slots * matrix_bytes + streams * vector_bytes)
+    if centre_formed:
+        per_row = (slots - 1) * matrix_bytes + (1 if dim == 3 else 0)
+    else:
+        per_row = slots * matrix_bytes
+    return n_unknown * (per_row + streams * vector_bytes)
 
 
 PRECISIONS = {"fp64": ("PREC_FP64", 8, 8, "f64", "FP64"),
@@ -181,7 +189,9 @@ def run_form(case, args, precision, guess, precond, weights, label):
                 k = stage.lower()
                 ms += prof[mat][f"{k}_ms"]
                 n += prof[mat][f"{k}_n"]
-                nbytes += prof[mat][f"{k}_n"] * stage_bytes(n_unk, case.dim, mb, vec_b, stage)
+                # the Jacobi-scaled copy stores its centre; the set's operator does not need it
+                cf = mb == 8 and precond != "jacobi"
+                nbytes += prof[mat][f"{k}_n"] * stage_bytes(n_unk, case.dim, mb, vec_b, stage, cf)
             if n:
                 avg_s = ms / n * 1e-3
                 stages[stage] = {"kernel": f"k_t{case.dim}_{stage}", "launches": int(n), "total_ms": ms,
@@ -564,7 +574,7 @@ def sweep_size(n, iters, precision):
     prof = ctx.profile_read(reset=True)
     ctx.profile(False)
     n_unk = case.n_cells - 1
-    sb, pb = stage_bytes(n_unk, 2, mb, 8, "S"), stage_bytes(n_unk, 2, mb, 8, "P")
+    sb, pb = stage_bytes(n_unk, 2, mb, 8, "S", mb == 8), stage_bytes(n_unk, 2, mb, 8, "P", mb == 8)
     s_us = prof["s_ms"] / max(prof["s_n"], 1) * 1e3
     p_us = prof["p_ms"] / max(prof["p_n"], 1) * 1e3
     out = {"n": n, "unknowns": n_unk, "precision": precision, "iterations": info["iterations"],

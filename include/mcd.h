@@ -224,7 +224,9 @@ mcd_status mcd_build_stencils(mcd_ctx* ctx, int set, const double* pos, const in
  * lexicographic order (x fastest), slot (S-1)/2 = -sum of value weights,
  * slot S = the DP's own Neumann row; masks [2][Nc] u32 (bit s of masks[0]:
  * slot s is a value row; bit s of masks[1]: slot s is a Neumann row, bit S:
- * own Neumann row); amat [S][Nc] f64 PPE matrix (nullable). */
+ * own Neumann row); amat [S][Nc] f64 PPE matrix over the unknown rows and
+ * columns (nullable; the library's own copy also keeps the weights of known
+ * value neighbours, which the export sets to 0). */
 mcd_status mcd_get_stencils(mcd_ctx* ctx, int set, double* phi, uint32_t* masks, double* amat);
 
 typedef enum {

@@ -29,6 +29,20 @@ struct SetStore {
     int built = 0;
 };
 
+// The stored FP64 matrix keeps, in the slots of an unknown row, the weights
+// of its known value neighbours (bits of kmask); the exported copy [S][Nc]
+// is the matrix itself, with those columns zero.
+__global__ void k_export_matrix(int Nc, const uint32_t* __restrict__ kmask, double* __restrict__ a) {
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < Nc; c += gridDim.x * blockDim.x) {
+        uint32_t km = kmask[c];
+        while (km) {
+            const int s = __builtin_ctz(km);
+            km &= km - 1u;
+            a[(size_t)s * Nc + c] = 0.0;
+        }
+    }
+}
+
 }  // namespace
 
 struct mcd_ctx {
@@ -557,10 +571,14 @@ mcd_status mcd_get_stencils(mcd_ctx* c, int set, double* phi, uint32_t* masks, d
         HIPCHK(c, hipMemcpyAsync(masks, d.vmask, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy");
         HIPCHK(c, hipMemcpyAsync(masks + N, d.nmask, N * sizeof(uint32_t), hipMemcpyDeviceToDevice, st), "copy");
     }
-    if (amat)
+    if (amat) {
         HIPCHK(c, hipMemcpy2DAsync(amat, N * sizeof(double), d.amat, c->m.mps * sizeof(double), N * sizeof(double),
                                    (size_t)c->S, hipMemcpyDeviceToDevice, st),
                "copy");
+        const int g = (int)std::min<size_t>((N + kBlock - 1) / kBlock, 4096);
+        hipLaunchKernelGGL(k_export_matrix, dim3(g), dim3(kBlock), 0, st, (int)N, d.kmask, amat);
+        HIPCHK(c, hipGetLastError(), "export");
+    }
     return MCD_OK;
 }
 

@@ -275,8 +275,9 @@ struct SetDev {
     uint32_t* nmask;    // [Nc] bit s: slot s is a Neumann row; bit S: own Neumann row
     uint32_t* kmask;    // [Nc] unknown rows: bit s: slot s is a value row whose DP is not an unknown
                         // (its value moves to the PPE's right-hand side); 0 at other rows
-    double* amat;       // [S][mps] PPE matrix (unknown rows/cols), plane stride MeshDev::mps
-    float* amat32;      // [S][mps]
+    double* amat;       // [S][mps] PPE matrix of the unknown rows, plane stride MeshDev::mps; the slots of
+                        // known value neighbours (kmask) keep their weights, centre = -sum of the others
+    float* amat32;      // [S][mps] unknown rows and columns, difference form (centre = row sum)
     uint8_t* unknown;   // [Nc]
     double rs;
 };

@@ -21,6 +21,7 @@
 
 #include <cmath>
 #include <mutex>
+#include <type_traits>
 
 #include "common.h"
 
@@ -59,6 +60,9 @@ struct KVec {
     T *x, *r, *rhat, *s, *t, *p[2], *v[2];
     const TA* A;     // [S][Nc]; TA = float for an FP32-stored matrix with FP64 vectors
     const T* b;
+    // set for the set's own FP64 operator: its unknown flags; the stage
+    // kernels then form the centre from the row's other slots
+    const uint8_t* unk = nullptr;
 };
 
 struct KBufs {
@@ -244,10 +248,38 @@ __device__ __forceinline__ int halo_cell(const MeshDev& m, int gx, int gy) {
     return gx + m.n[0] * gy;
 }
 
-template <bool NT, typename T, typename TA>
+// Row of cell c (2D): the 9 planes, or (CF: the set's own FP64 operator,
+// whose slots keep the weights of known value neighbours, the operands being
+// zero there) the 8 off-centre planes, complete_row9 then forming the centre
+// as minus their sum in slot order (the sum the weight build forms).
+template <bool NT, bool CF, typename TA>
+__device__ __forceinline__ void load_row9(const TA* __restrict__ A, size_t mps, int c, TA (&a)[9]) {
+    static_assert(!CF || sizeof(TA) == sizeof(double), "centre formed for FP64 matrices only");
+#pragma unroll
+    for (int s = 0; s < 9; ++s) a[s] = (CF && s == 4) ? TA(0) : ld_mat<NT>(A + (size_t)s * mps + c);
+}
+
+template <bool CF, typename TA>
+__device__ __forceinline__ void complete_row9(TA (&a)[9]) {
+    if constexpr (CF) {
+        TA sum = 0;
+#pragma unroll
+        for (int s = 0; s < 9; ++s)
+            if (s != 4) sum += a[s];
+        a[4] = -sum;
+    }
+}
+
+template <bool NT, bool CF, typename T, typename TA>
 __device__ __forceinline__ T stencil_lds(const TA* __restrict__ A, size_t mps, int c, const T* lds, int lx, int ly) {
     T acc = 0;
-    if constexpr (sizeof(TA) < sizeof(double)) {
+    if constexpr (CF) {
+        TA a[9];
+        load_row9<NT, true>(A, mps, c, a);
+        complete_row9<true>(a);
+#pragma unroll
+        for (int s = 0; s < 9; ++s) acc += (T)a[s] * lds[(ly + s / 3) * HX + (lx + s % 3)];
+    } else if constexpr (sizeof(TA) < sizeof(double)) {
         // FP32-stored matrix in difference form (centre slot = row sum)
         const T xc = lds[(ly + 1) * HX + lx + 1];
 #pragma unroll
@@ -292,7 +324,7 @@ __device__ __forceinline__ void tile_origin(const KBufs& K, int tile, int& tx0, 
     ty0 = (tile / K.ntx) * TY;
 }
 
-template <typename T, typename TA, bool NT>
+template <typename T, typename TA, bool NT, bool CF>
 __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T, TA> V, KBufs K) {
     __shared__ T xl[NH];
     const T* __restrict__ xp = V.x;
@@ -314,7 +346,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_init(MeshDev m, KVec<T, TA> V, K
         const int gx = tx0 + lx, gy = ty0 + ly;
         if (gx < m.n[0] && gy < m.n[1]) {
             const int c = gx + m.n[0] * gy;
-            const T ax = stencil_lds<NT, T, TA>(A, m.mps, c, xl, lx, ly);
+            const T ax = stencil_lds<NT, CF, T, TA>(A, m.mps, c, xl, lx, ly);
             const T bc = bp[c];
             const T r = bc - ax;
             sp[c] = r;
@@ -406,7 +438,7 @@ __device__ __forceinline__ void load_halo_p(const MeshDev& m, int tx0, int ty0, 
 // partials, the halo operands, the matrix row, rhat) is issued before the
 // block reduction, and the next tile's halo operands while the current tile
 // is formed, so that the memory latencies overlap.
-template <typename T, typename TA, int MODE, bool NT>
+template <typename T, typename TA, int MODE, bool NT, bool CF>
 __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T pl[NH];
     const KState* __restrict__ in = K.st[2];
@@ -469,8 +501,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
             const int gxo = tx0 + lx, gyo = ty0 + ly;
             c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
             if (c >= 0) {
-#pragma unroll
-                for (int s = 0; s < 9; ++s) a[s] = ld_mat<NT>(A + (size_t)s * m.mps + c);
+                load_row9<NT, CF>(A, m.mps, c, a);
                 rhc = rh[c];
             }
         }
@@ -509,6 +540,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
         sync_lds();
         if (c >= 0) {
             T av = 0;
+            complete_row9<CF>(a);
             if constexpr (sizeof(TA) < sizeof(double)) {
                 const T xc = pl[(ly + 1) * HX + lx + 1];
 #pragma unroll
@@ -534,7 +566,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_P(MeshDev m, KVec<T, TA> V, int 
 }
 
 // S-stage (2D), load-first like the P-stage.
-template <typename T, typename TA, bool NT>
+template <typename T, typename TA, bool NT, bool CF>
 __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T sl[NH];
     const KState* __restrict__ in = K.st[1];
@@ -571,8 +603,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
         const int gxo = tx0n + lx, gyo = ty0n + ly;
         c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
         if (c >= 0) {
-#pragma unroll
-            for (int s = 0; s < 9; ++s) a[s] = ld_mat<NT>(A + (size_t)s * m.mps + c);
+            load_row9<NT, CF>(A, m.mps, c, a);
             rhc = rh[c];
         }
     }
@@ -605,8 +636,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
             const int gxo = tx0 + lx, gyo = ty0 + ly;
             c = (gxo < m.n[0] && gyo < m.n[1]) ? gxo + m.n[0] * gyo : -1;
             if (c >= 0) {
-#pragma unroll
-                for (int s = 0; s < 9; ++s) a[s] = ld_mat<NT>(A + (size_t)s * m.mps + c);
+                load_row9<NT, CF>(A, m.mps, c, a);
                 rhc = rh[c];
             }
         }
@@ -646,6 +676,7 @@ __global__ __launch_bounds__(kKBlock) void k_t2_S(MeshDev m, KVec<T, TA> V, int 
         sync_lds();
         if (c >= 0) {
             T tcv = 0;
+            complete_row9<CF>(a);
             if constexpr (sizeof(TA) < sizeof(double)) {
                 const T xc = sl[(ly + 1) * HX + lx + 1];
 #pragma unroll
@@ -705,38 +736,74 @@ __device__ __forceinline__ void brick_origin(const KBufs& K, int brick, int& tx0
     tz0 = (brick / (K.ntx * K.nty)) * K.tz;
 }
 
-// Matrix row of cell c (27 slot planes) into registers.
-template <bool NT, typename TA>
-__device__ __forceinline__ void load_row27(const TA* __restrict__ A, size_t mps, int c, TA (&a)[27]) {
-#pragma unroll
-    for (int s = 0; s < 27; ++s) a[s] = ld_mat<NT>(A + (size_t)s * mps + c);
-}
-
-// FP64 matrices (the set's operator and its Jacobi-scaled copy) hold rows
-// of cells that are not unknown as 27 zeros (+0.0), while the centre of an
-// unknown row is never +0.0: it is -sum of the row's value weights, a sum
-// that starts at +0.0 and so is never -0.0; a Jacobi-scaled centre is that
-// times its reciprocal (about 1), times 1 (not finite), or the -0.0 kept.  A row whose centre has the bits of +0.0 is therefore all
-// zeros and its other 26 planes are not read: the rows of walls and of
-// cells inside a body cost no matrix traffic.  The centre of the next plane
-// is fetched one plane ahead, so the test adds no latency.  FP32 matrices
-// (difference form: the centre holds the row sum, zero for most rows) read
-// every plane.
+// Matrix rows of the 3D stage kernels.  Rows of cells that are not unknown
+// are 27 zeros (+0.0) in every FP64 matrix, and their 26 off-centre planes
+// are not read; what tells them apart is fetched one plane ahead, so the
+// test adds no latency:
+// - CF (the set's own FP64 operator): the cell's unknown flag.  The row's
+//   slots also keep the weights of its known value neighbours (operands are
+//   zero there), so the centre is minus the sum of the other 26 slots, in
+//   slot order (the sum the weight build forms and stores), and the centre
+//   plane is not read either.
+// - other FP64 matrices (the Jacobi-scaled copy): the centre.  The centre of
+//   an unknown row is never +0.0: it is -sum of the row's value weights, a
+//   sum that starts at +0.0 and so is never -0.0, times its reciprocal
+//   (about 1), times 1 (not finite), or the -0.0 kept.
+// - FP32 matrices (difference form: the centre holds the row sum, zero for
+//   most rows): every plane is read.
 template <typename TA>
 struct RowSkip {
     static constexpr bool on = sizeof(TA) == sizeof(double);
 };
 
-template <bool NT, typename TA>
-__device__ __forceinline__ void load_row27_skip(const TA* __restrict__ A, size_t mps, int c, TA cen, TA (&a)[27]) {
-    if (__double_as_longlong((double)cen) == 0) {
+template <typename TA, bool NT, bool CF>
+struct RowLoad {
+    static_assert(!CF || sizeof(TA) == sizeof(double), "centre formed for FP64 matrices only");
+    const TA* __restrict__ A;
+    size_t mps;
+    const uint8_t* __restrict__ unk;
+    TA cen;          // centre of the next row (FP64, not CF)
+    uint8_t u;       // unknown flag of the next row (CF)
+
+    // row of cell c into a; false for a row of zeros
+    __device__ __forceinline__ bool load(int c, TA (&a)[27]) {
+        bool nz = true;
+        if constexpr (CF)
+            nz = u != 0;
+        else if constexpr (RowSkip<TA>::on)
+            nz = __double_as_longlong((double)cen) != 0;
+        if (!nz) {
 #pragma unroll
-        for (int s = 0; s < 27; ++s) a[s] = TA(0);
-        return;
+            for (int s = 0; s < 27; ++s) a[s] = TA(0);
+            return false;
+        }
+#pragma unroll
+        for (int s = 0; s < 27; ++s) {
+            if (s == 13)
+                a[s] = CF ? TA(0) : (RowSkip<TA>::on ? cen : ld_mat<NT>(A + (size_t)s * mps + c));
+            else
+                a[s] = ld_mat<NT>(A + (size_t)s * mps + c);
+        }
+        return true;
     }
+    // fetches what the row of cell cn is told apart by
+    __device__ __forceinline__ void ahead(int cn) {
+        if constexpr (CF)
+            u = unk[cn];
+        else if constexpr (RowSkip<TA>::on)
+            cen = ld_mat<NT>(A + (size_t)13 * mps + cn);
+    }
+    // completes a loaded row before its product
+    __device__ __forceinline__ void complete(TA (&a)[27]) {
+        if constexpr (CF) {
+            TA sum = 0;
 #pragma unroll
-    for (int s = 0; s < 27; ++s) a[s] = s == 13 ? cen : ld_mat<NT>(A + (size_t)s * mps + c);
-}
+            for (int s = 0; s < 27; ++s)
+                if (s != 13) sum += a[s];
+            a[13] = -sum;
+        }
+    }
+};
 
 // 27-point product of a preloaded row with the ring planes (slots of planes
 // z-1, z, z+1).
@@ -791,7 +858,7 @@ __device__ __forceinline__ void march_bricks(const MeshDev& m, const KBufs& K, F
     }
 }
 
-template <typename T, typename TA, bool NT>
+template <typename T, typename TA, bool NT, bool CF>
 __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, KBufs K) {
     __shared__ T ring[3][NH];
     const T* __restrict__ xp = V.x;
@@ -802,7 +869,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0;
     TA a[27];
-    TA cen = 0;      // centre of the row pre() loads next
+    RowLoad<TA, NT, CF> rows{A, m.mps, V.unk, TA(0), 0};
     T bcv = 0;
     march_bricks<T>(
         m, K,
@@ -814,15 +881,13 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
         },
         [&](int c, int cn) {
             if (c >= 0) {
-                if constexpr (RowSkip<TA>::on)
-                    load_row27_skip<NT, TA>(A, m.mps, c, cen, a);
-                else
-                    load_row27<NT, TA>(A, m.mps, c, a);
+                rows.load(c, a);
                 bcv = bp[c];
             }
-            if (RowSkip<TA>::on && cn >= 0) cen = ld_mat<NT>(A + (size_t)13 * m.mps + cn);
+            if (cn >= 0) rows.ahead(cn);
         },
         [&](int c, int s0, int s1, int s2) {
+            rows.complete(a);
             const T ax = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
             const T bc = bcv;
             const T r = bc - ax;
@@ -835,7 +900,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_init(MeshDev m, KVec<T, TA> V, K
     write_partials<2>(v, K.part[0], K);
 }
 
-template <typename T, typename TA, int MODE, bool NT>
+template <typename T, typename TA, int MODE, bool NT, bool CF>
 __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T ring[3][NH];
     const KState* __restrict__ in = K.st[2];
@@ -860,7 +925,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0;
     TA a[27];
-    TA cen = 0;      // centre of the row pre() loads next
+    RowLoad<TA, NT, CF> rows{A, m.mps, V.unk, TA(0), 0};
     T rhc = 0;
     march_bricks<T>(
         m, K,
@@ -899,18 +964,13 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
         },
         [&](int c, int cn) {
             if (c >= 0) {
-                if constexpr (RowSkip<TA>::on) {
-                    load_row27_skip<NT, TA>(A, m.mps, c, cen, a);
-                    // r-hat is +0.0 wherever the row is
-                    rhc = __double_as_longlong((double)cen) == 0 ? T(0) : rh[c];
-                } else {
-                    load_row27<NT, TA>(A, m.mps, c, a);
-                    rhc = rh[c];
-                }
+                // r-hat is +0.0 wherever the row is zero
+                rhc = rows.load(c, a) ? rh[c] : T(0);
             }
-            if (RowSkip<TA>::on && cn >= 0) cen = ld_mat<NT>(A + (size_t)13 * m.mps + cn);
+            if (cn >= 0) rows.ahead(cn);
         },
         [&](int c, int s0, int s1, int s2) {
+            rows.complete(a);
             const T av = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
             vn[c] = av;
             a0 += (double)rhc * (double)av;
@@ -925,7 +985,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_P(MeshDev m, KVec<T, TA> V, int 
     }
 }
 
-template <typename T, typename TA, bool NT>
+template <typename T, typename TA, bool NT, bool CF>
 __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int par, KBufs K) {
     __shared__ T ring[3][NH];
     const KState* __restrict__ in = K.st[1];
@@ -962,7 +1022,7 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
     const int lx = threadIdx.x % TX, ly = threadIdx.x / TX;
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     TA a[27];
-    TA cen = 0;      // centre of the row pre() loads next
+    RowLoad<TA, NT, CF> rows{A, m.mps, V.unk, TA(0), 0};
     T rhc = 0;
     march_bricks<T>(
         m, K,
@@ -982,18 +1042,13 @@ __global__ __launch_bounds__(kKBlock) void k_t3_S(MeshDev m, KVec<T, TA> V, int 
         },
         [&](int c, int cn) {
             if (c >= 0) {
-                if constexpr (RowSkip<TA>::on) {
-                    load_row27_skip<NT, TA>(A, m.mps, c, cen, a);
-                    // r-hat is +0.0 wherever the row is
-                    rhc = __double_as_longlong((double)cen) == 0 ? T(0) : rh[c];
-                } else {
-                    load_row27<NT, TA>(A, m.mps, c, a);
-                    rhc = rh[c];
-                }
+                // r-hat is +0.0 wherever the row is zero
+                rhc = rows.load(c, a) ? rh[c] : T(0);
             }
-            if (RowSkip<TA>::on && cn >= 0) cen = ld_mat<NT>(A + (size_t)13 * m.mps + cn);
+            if (cn >= 0) rows.ahead(cn);
         },
         [&](int c, int s0, int s1, int s2) {
+            rows.complete(a);
             const T tcv = stencil3_lds<T, TA>(a, ring, s0, s1, s2, lx, ly);
             const T sc = ring[s1][(ly + 1) * HX + lx + 1];
             tp[c] = tcv;
@@ -1240,10 +1295,13 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_diag(MeshDev m, const double*
     }
 }
 
-// J[s][c] = A[s][c] dinv[j(c, s)] (FP64), and its FP32 copy in difference form
-// (centre slot = row sum of the scaled row), as the MLS build stores A.
+// J[s][c] = A[s][c] dinv[j(c, s)] (FP64; like A, it keeps the weights of
+// known value neighbours, scaled by 1), and its FP32 copy over the unknown
+// columns in difference form (centre slot = row sum of the scaled row), as
+// the MLS build stores A.
 template <int DIM>
 __global__ __launch_bounds__(kBlock) void k_jacobi_matrix(MeshDev m, const double* __restrict__ A,
+                                                          const uint8_t* __restrict__ unknown,
                                                           const double* __restrict__ dinv, double* __restrict__ J,
                                                           float* __restrict__ J32) {
     constexpr int S = Dims<DIM>::S, CEN = Dims<DIM>::CEN;
@@ -1257,15 +1315,20 @@ __global__ __launch_bounds__(kBlock) void k_jacobi_matrix(MeshDev m, const doubl
             // a zero keeps its sign: the centre of an unknown row is never
             // +0.0, here as in A (the stage kernels skip rows whose centre is)
             double v = a == 0.0 ? a : 0.0;
+            bool col = false;      // an unknown column
             int j;
             double sh[3];
-            if (a != 0.0 && neighbour<DIM>(m, ijk, s, j, sh)) v = a * dinv[j];
+            if (a != 0.0 && neighbour<DIM>(m, ijk, s, j, sh)) {
+                v = a * dinv[j];
+                col = unknown[j] != 0;
+            }
             J[(size_t)s * P + c] = v;
             if (s == CEN) {
                 diag = v;
             } else {
-                J32[(size_t)s * P + c] = (float)v;
-                off_sum += v;
+                const double v32 = col ? v : 0.0;
+                J32[(size_t)s * P + c] = (float)v32;
+                off_sum += v32;
             }
         }
         J32[(size_t)CEN * P + c] = (float)(diag + off_sum);
@@ -1328,29 +1391,41 @@ struct KrylovWork {
     MgWork* mg = nullptr;          // multigrid hierarchy (MCD_PRECOND_MG)
 };
 
+template <int DIM, typename T, typename TA, bool NT, bool CF>
+static void enqueue_stages(const MeshDev& m, const KVec<T, TA>& V, const KBufs& K, int par, int mode, hipStream_t st,
+                           hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, hipEvent_t e3) {
+    const dim3 G(K.nblk), B(kKBlock);
+    if constexpr (DIM == 2) {
+        if (mode == P_FIRST)
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_FIRST, NT, CF>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        else if (mode == P_RESUME)
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_RESUME, NT, CF>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        else
+            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_NORMAL, NT, CF>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_t2_S<T, TA, NT, CF>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+    } else {
+        if (mode == P_FIRST)
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_FIRST, NT, CF>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        else if (mode == P_RESUME)
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_RESUME, NT, CF>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        else
+            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_NORMAL, NT, CF>), G, B, 0, st, e0, e1, 0, m, V, par, K);
+        hipExtLaunchKernelGGL((k_t3_S<T, TA, NT, CF>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+    }
+}
+
 // Enqueues one Bi-CGSTAB iteration (P-stage in `mode`, then S-stage) with
 // operand parity par.
 template <int DIM, typename T, typename TA, bool NT>
 static void enqueue_iteration_nt(const MeshDev& m, const KVec<T, TA>& V, const KBufs& K, int par, int mode,
                                  hipStream_t st, hipEvent_t e0, hipEvent_t e1, hipEvent_t e2, hipEvent_t e3) {
-    const dim3 G(K.nblk), B(kKBlock);
-    if (m.dim == 2) {
-        if (mode == P_FIRST)
-            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_FIRST, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        else if (mode == P_RESUME)
-            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_RESUME, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        else
-            hipExtLaunchKernelGGL((k_t2_P<T, TA, P_NORMAL, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        hipExtLaunchKernelGGL((k_t2_S<T, TA, NT>), G, B, 0, st, e2, e3, 0, m, V, par, K);
-    } else {
-        if (mode == P_FIRST)
-            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_FIRST, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        else if (mode == P_RESUME)
-            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_RESUME, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        else
-            hipExtLaunchKernelGGL((k_t3_P<T, TA, P_NORMAL, NT>), G, B, 0, st, e0, e1, 0, m, V, par, K);
-        hipExtLaunchKernelGGL((k_t3_S<T, TA, NT>), G, B, 0, st, e2, e3, 0, m, V, par, K);
+    if constexpr (sizeof(TA) == sizeof(double)) {
+        if (V.unk) {
+            enqueue_stages<DIM, T, TA, NT, true>(m, V, K, par, mode, st, e0, e1, e2, e3);
+            return;
+        }
     }
+    enqueue_stages<DIM, T, TA, NT, false>(m, V, K, par, mode, st, e0, e1, e2, e3);
 }
 
 template <int DIM, typename T, typename TA>
@@ -1367,7 +1442,8 @@ static void enqueue_iteration(const MeshDev& m, const KVec<T, TA>& V, const KBuf
 template <int DIM, typename T, typename TA>
 static hipError_t chunk_graph(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K,
                               hipGraphExec_t* out) {
-    const int fp32 = sizeof(T) == 4;
+    // key: the matrix, the precision and whether the centre is formed
+    const int fp32 = (sizeof(T) == 4 ? 1 : 0) | (V.unk ? 2 : 0);
     for (int i = 0; i < w.ngraphs; ++i)
         if (w.graphs[i].A == (const void*)V.A && w.graphs[i].fp32 == fp32) {
             *out = w.graphs[i].exec;
@@ -1500,16 +1576,25 @@ static hipError_t run_iterations(const MeshDev& m, KrylovWork& w, const KVec<T, 
 template <int DIM, typename T, typename TA>
 static hipError_t kinit(const MeshDev& m, KrylovWork& w, const KVec<T, TA>& V, const KBufs& K, int with_bb, double tol2,
                         hipStream_t st, KState* out, double delta2 = 0.0, double tol2_next = -1.0) {
-    if (m.dim == 2) {
-        if (K.nt)
-            hipLaunchKernelGGL((k_t2_init<T, TA, true>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
-        else
-            hipLaunchKernelGGL((k_t2_init<T, TA, false>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
-    } else {
-        if (K.nt)
-            hipLaunchKernelGGL((k_t3_init<T, TA, true>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
-        else
-            hipLaunchKernelGGL((k_t3_init<T, TA, false>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+    {
+        auto go = [&](auto nt_c, auto cf_c) {
+            constexpr bool NT = decltype(nt_c)::value, CF = decltype(cf_c)::value;
+            if constexpr (DIM == 2)
+                hipLaunchKernelGGL((k_t2_init<T, TA, NT, CF>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+            else
+                hipLaunchKernelGGL((k_t3_init<T, TA, NT, CF>), dim3(K.nblk), dim3(kKBlock), 0, st, m, V, K);
+        };
+        using Tr = std::true_type;
+        using Fa = std::false_type;
+        if constexpr (sizeof(TA) == sizeof(double)) {
+            const bool cf = V.unk != nullptr;
+            if (K.nt)
+                cf ? go(Tr{}, Tr{}) : go(Tr{}, Fa{});
+            else
+                cf ? go(Fa{}, Tr{}) : go(Fa{}, Fa{});
+        } else {
+            K.nt ? go(Tr{}, Fa{}) : go(Fa{}, Fa{});
+        }
     }
     hipLaunchKernelGGL(k_kfinish, dim3(1), dim3(kKBlock), 0, st, K, with_bb, tol2, with_bb ? 0 : 1, delta2,
                        tol2_next < 0.0 ? tol2 : tol2_next);
@@ -1625,7 +1710,8 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     if (jacobi) {
         hipLaunchKernelGGL(k_jacobi_diag<DIM>, dim3(g), dim3(kBlock), 0, st, m, set.amat, set.unknown, w.dinv,
                            w.v64.x);
-        hipLaunchKernelGGL(k_jacobi_matrix<DIM>, dim3(g), dim3(kBlock), 0, st, m, set.amat, w.dinv, w.jac64, w.jac32);
+        hipLaunchKernelGGL(k_jacobi_matrix<DIM>, dim3(g), dim3(kBlock), 0, st, m, set.amat, set.unknown, w.dinv,
+                           w.jac64, w.jac32);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         A64 = w.jac64;
         A32 = w.jac32;
@@ -1633,6 +1719,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
     KVec<double> V = w.v64;
     V.A = A64;
     V.b = w.beff;
+    if (!jacobi) V.unk = set.unknown;
     const int check = sp.check_every > 0 ? sp.check_every : 8;
     if (sp.precision == MCD_PREC_FP64) {
         int it = 0, rst = 0, conv = 0;
@@ -1832,6 +1919,7 @@ static hipError_t solve_dim(const MeshDev& m, const SetDev& set, KrylovWork& w, 
         hipLaunchKernelGGL(k_jacobi_unscale, dim3(g), dim3(kBlock), 0, st, m.Nc, set.unknown, w.dinv, V.x);
         KVec<double> V0 = V;
         V0.A = set.amat;
+        V0.unk = set.unknown;
         if (out->bnorm > 0.0) {
             KState h;
             if ((e = kinit<DIM, double, double>(m, w, V0, w.kb64, 1, sp.tol * sp.tol, st, &h)) != hipSuccess) return e;
@@ -2043,6 +2131,7 @@ static hipError_t time_shape(const MeshDev& m, const SetDev& set, KrylovWork& w,
     KVec<double> V = w.v64;
     V.A = set.amat;
     V.b = w.beff;
+    V.unk = set.unknown;
     const int g = (m.Nc + kBlock - 1) / kBlock > 8192 ? 8192 : (m.Nc + kBlock - 1) / kBlock;
     hipLaunchKernelGGL(k_tune_problem, dim3(g), dim3(kBlock), 0, st, m.Nc, set.unknown, w.beff, V.x);
     KState h;

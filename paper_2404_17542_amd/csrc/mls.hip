@@ -8,8 +8,12 @@
 // re-gathers each row and writes W_j = M^-1 (w_j a_j) into the slot planes
 // (coalesced: consecutive threads write consecutive cells of a plane; the
 // planes are written once and read by later kernels only, so the stores are
-// non-temporal), plus the PPE Laplacian matrix over unknown rows/columns in
-// FP64 and FP32.
+// non-temporal), plus the PPE Laplacian matrix of the unknown rows in FP64
+// and FP32.  Its FP32 copy holds only the unknown columns; the FP64 slots
+// of an unknown row also keep the weights of its known value neighbours
+// (the operands of every product with it are zero there), so that the
+// centre is minus the sum of the row's other slots in slot order, the sum
+// the build forms, and need not be read.
 //
 // Rounding: built without contraction (no FMA), with the series weight
 // functions and one reciprocal per Cholesky pivot, and every sum taken in
@@ -287,17 +291,21 @@ __device__ __forceinline__ void mls_fit(const MeshDev& m, const MlsHalo<DIM>& H,
         if (s != CEN) {
 #pragma unroll
             for (int q = 0; q < NB; ++q) __builtin_nontemporal_store(y[q], st.phi + ((size_t)q * (S + 1) + s) * m.mps + c);
-            double lap = 0.0;
+            // lap: the matrix entry (0 in the columns of known value
+            // neighbours); lapk: the FP64 slot, which keeps those weights
+            // too, so that the centre is minus the sum of the row's slots
+            double lap = 0.0, lapk = 0.0;
             if (isv && unk_c) {
                 lap = POW2 ? diag2<DIM>(y) * rr_inv : diag2<DIM>(y) / (rs * rs);
                 diag_sum += lap;
+                lapk = lap;
                 if (!mls_unknown(H.r[e], H.kd[e], H.j[e], pin)) {
                     lap = 0.0;
                     km |= 1u << s;
                 }
             }
             if (st.amat) {
-                __builtin_nontemporal_store(lap, st.amat + (size_t)s * m.mps + c);
+                __builtin_nontemporal_store(lapk, st.amat + (size_t)s * m.mps + c);
                 __builtin_nontemporal_store((float)lap, st.amat32 + (size_t)s * m.mps + c);
                 off_sum += lap;
             }

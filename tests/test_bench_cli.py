@@ -25,3 +25,8 @@ def test_stage_bytes():
     assert bench.stage_bytes(1000, 2, 8, 8, "P") == 152_000
     assert bench.stage_bytes(1000, 3, 8, 8, "P") == 296_000
     assert bench.stage_bytes(1000, 3, 4, 8, "P") == 188_000
+    # the set's own FP64 operator: the off-centre planes (2D: 8) and, in 3D, the 1-byte unknown flag
+    assert bench.stage_bytes(1000, 2, 8, 8, "S", True) == 104_000
+    assert bench.stage_bytes(1000, 2, 8, 8, "P", True) == 144_000
+    assert bench.stage_bytes(1000, 3, 8, 8, "S", True) == 249_000
+    assert bench.stage_bytes(1000, 3, 8, 8, "P", True) == 289_000
