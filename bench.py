@@ -153,14 +153,22 @@ def run_form(case, args, precision, guess, precond, weights, label):
         log(f"{label}: autotuned stage-kernel shape {tune['shape']} from "
             + ", ".join(f"{c['grid']}x{c['depth']}: {c['us_per_iter']:.2f} us" for c in tune["candidates"]))
     n_active = sim.n_active()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for k in range(args.steps):
-        sim.step()
-        if (k + 1) % 10 == 0:
-            log(f"{label}: step {k + 1}/{args.steps}")
-    torch.cuda.synchronize()
-    elapsed = time.perf_counter() - t0
+    # Python's cyclic garbage collector stays off over the timed steps (a
+    # collection can pause the host for tens of milliseconds between two
+    # launches); every step's device work runs as without it
+    gc.collect()
+    gc.disable()
+    try:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for k in range(args.steps):
+            sim.step()
+            if (k + 1) % 10 == 0:
+                log(f"{label}: step {k + 1}/{args.steps}")
+        torch.cuda.synchronize()
+        elapsed = time.perf_counter() - t0
+    finally:
+        gc.enable()
     timed = sim.log[-args.steps:]
     assert all(r["converged"] for r in timed), "a PPE solve did not converge"
     iters = [r["iters"] for r in timed]
